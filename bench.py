@@ -1,0 +1,167 @@
+"""Benchmark: band-H psi/s of the folded-spectrum CG on the 256-atom wire cell.
+
+One step = one folded-spectrum PCG iteration on the whole block: gradient and
+preconditioner, conjugation and projection, the two H applications
+Y = (H - E)P and A P = (H - E) Y, the per-band line minimisation and the
+Gram/Cholesky re-orthonormalisation.  K steps run as one solve of K
+iterations (its set-up, one residual check and the final Rayleigh-Ritz are
+inside the timed region too).  value = band-H psi applications per second.
+
+Workload (synthetic stand-in for the paper's copper nanowire): 20 x 20 x 80 bohr
+cell, 48 x 48 x 192 grid, Ecut 10 Ha (48,369 plane waves), 256-atom fcc wire
+with Gaussian wells and 4 Kleinman-Bylander projectors per atom, 128 bands
+nearest E_ref = 0.3 Ha, complex128.
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
+--no-cpu (skip the CPU oracle leg) --precision {fp64,mixed}.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+BF16_PEAK_TFS = 2500.0
+
+
+def stage_work(ctx, nb, dtype_bytes, nproj):
+    """Algorithmic bytes or flops of one launch of each H psi stage for a batch
+    of nb bands: (bound, amount, unit)."""
+    n0, n1, n2 = ctx.grid
+    colgrid = ctx.ncols * n2 * dtype_bytes          # one band's column grid
+    sphere = ctx.npw * dtype_bytes
+    return {
+        "z_inverse": ("hbm", nb * (sphere + colgrid), "B"),
+        "xy_fft_v": ("hbm", nb * 2 * colgrid + n0 * n1 * n2 * (8 if dtype_bytes == 16 else 4), "B"),
+        "z_forward_kinetic": ("hbm", nb * (colgrid + 2 * sphere), "B"),
+        "projection": ("mfma", 8.0 * nproj * ctx.npw * nb, "flop"),
+        "back_projection": ("mfma", 8.0 * nproj * ctx.npw * nb, "flop"),
+    }
+
+
+def cpu_baseline(prob, nb_sample=16, iters=1):
+    """The FP64 oracle's folded CG (numpy FFT H psi) on a bounded sample of the
+    same cell: nb_sample bands, `iters` iterations."""
+    import numpy as np
+    from oracle.hamiltonian import Operator
+    from oracle.fsm_cg import fsm_cg
+    from paper_1907_06821_amd import synth
+    op = Operator.from_problem(prob)
+    psi0 = synth.start_vectors(2, nb_sample, op.npw)
+    t0 = time.perf_counter()
+    r = fsm_cg(op.apply, prob.e_ref, psi0, op.kin, tol=1e-30, maxit=iters, check_every=iters)
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": r["n_hpsi"] / dt, "unit": "band-Hpsi/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": f"{prob.name}: {nb_sample} bands, {iters} folded-CG iteration(s) incl. set-up and final "
+                      f"Rayleigh-Ritz, {r['n_hpsi']} band-Hpsi in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--cpu-bands", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver shards no work across GPUs in this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+
+    torch.cuda.set_device(0)
+    prob = synth.config(2)
+    mixed = args.precision == "mixed"
+    flags = pw.PW_PREP_C128 | (pw.PW_PREP_C64 if mixed else 0)
+    ctx = pw.Context.from_problem(prob, max_bands=prob.nbands, flags=flags)
+    nb = prob.nbands
+    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
+    opts = dict(tol=1e-30, check_every=10 ** 6, precision=1 if mixed else 0)
+
+    # warm-up (also allocates the solver workspace)
+    psi = psi0.clone()
+    pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=max(1, args.warmup), raise_on_noconv=False, **opts)
+    torch.cuda.synchronize()
+
+    psi = psi0.clone()
+    pw.profile_begin(ctx, 200000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=args.steps, raise_on_noconv=False, **opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = pw.profile_end(ctx)
+    dt = t1 - t0
+    value = st["n_hpsi"] / dt
+
+    # dominant stage and its roofline
+    work = stage_work(ctx, nb, 8 if mixed else 16, ctx.nproj)
+    stages = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        bound, amount, unit = work[k]
+        avg_s = ms / n / 1e3
+        if bound == "hbm":
+            ach = amount / avg_s / 1e9
+            peak, u = HBM_PEAK_GBS, "GB/s"
+        else:
+            ach = amount / avg_s / 1e12
+            peak, u = (BF16_PEAK_TFS if mixed else FP64_PEAK_TFS), "TFLOP/s"
+        stages[k] = {"bound": bound, "avg_ms": ms / n, "launches": n, "achieved": ach, "peak": peak, "unit": u,
+                     "frac": ach / peak, "share": ms / (dt * 1e3)}
+    dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches"])
+    d = stages[dom]
+    roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
+                "frac": round(d["frac"], 4), "traffic": None, "kernel": dom}
+
+    line = {
+        "metric": "band-Hψ/sec and folded-CG time to residual 1e-6 (mixed+learned vs FP64)",
+        "value": round(value, 1),
+        "unit": "band-Hpsi/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+bf16" if mixed else "c128",
+        "data": "synthetic",
+        "config": {"workload": "wire256: 20x20x80 bohr, 48x48x192 grid, Ecut 10 Ha, npw 48369, 256 atoms x 4 KB "
+                               "projectors, 128 bands near E_ref 0.3 Ha, folded-spectrum PCG iteration",
+                   "npw": ctx.npw, "bands": nb, "nproj": ctx.nproj, "grid": list(ctx.grid),
+                   "precision": args.precision},
+        "roofline": roofline,
+        "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                   for k, v in stages.items()},
+        "n_hpsi": st["n_hpsi"],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

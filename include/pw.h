@@ -1,0 +1,193 @@
+/*
+ * pw.h -- C ABI of libpw: folded-spectrum plane-wave eigensolver for gfx950.
+ *
+ * The library finds the Kohn-Sham states of a plane-wave Hamiltonian nearest a
+ * reference energy E by minimising <psi|(H - E)^2|psi> with preconditioned
+ * conjugate gradients.  The folded operator (H - E)^2 and its positivity are
+ * the paper's folded equation (Sec. II.B); the few-states-near-E use is the
+ * folded-spectrum method the paper names in Sec. II.B; the G-diagonal
+ * preconditioner M(G) and the eigen-residual Delta_i = ||H phi_i - eps_i phi_i||
+ * are defined under the paper's M' equation (Sec. II.B).
+ *
+ * Conventions shared by every entry point
+ *   - Cell: orthorhombic, lengths L = (L0, L1, L2) bohr, axis 2 is z.
+ *     Reciprocal vectors G = 2 pi (n0/L0, n1/L1, n2/L2), Miller triple n.
+ *   - Basis: every n with (1/2)|G + k|^2 <= ecut (Ha).  Coefficient order is
+ *     lexicographic in the signed triple (n0, n1, n2); pw_basis_miller returns
+ *     it.  Every n must land on a distinct grid point: 2 max|n_i| + 1 <= N_i.
+ *   - Wave-function blocks are band-major: band b, plane wave g at
+ *     psi[b * ld + g], interleaved complex (re, im), complex128 or complex64.
+ *   - Real space: grid point r_j = (j0 L0/N0, j1 L1/N1, j2 L2/N2), arrays
+ *     [N0][N1][N2] C order.  G -> r is the unnormalised sum
+ *     f(r_j) = sum_G c(G) exp(+i G.r_j); r -> G is
+ *     c(G) = (1/N) sum_j f(r_j) exp(-i G.r_j), N = N0 N1 N2.  With V given by
+ *     its grid samples this makes the FFT application of V equal to the
+ *     plane-wave matrix element Vt(G - G') exactly.
+ *   - Nonlocal term: Kleinman-Bylander sum_p |beta_p> D_p <beta_p|, 4 per atom
+ *     (s, px, py, pz) with q = G + k:
+ *       beta_{a,j}(G) = sqrt(8 pi^1.5 s^3) Y_j(q) exp(-|q|^2 s^2/2) exp(-i q.R_a) / sqrt(Omega),
+ *       Y_s = 1, Y_{p,m} = sqrt(3) q_m/|q| (0 at q = 0).
+ *   - Pointers marked "device" are HIP device memory owned by the caller; the
+ *     library never frees them.  Pointers marked "host" are read (or written)
+ *     before the call returns.  `stream` is a hipStream_t (NULL = default).
+ *   - Errors: every call returns a pw_status and never aborts; the text of the
+ *     last error on the calling thread is pw_last_error().  On PW_ENOCONV the
+ *     outputs hold the best iterate; on any other error outputs are
+ *     unspecified.
+ */
+#ifndef PW_H
+#define PW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PW_OK = 0,
+    PW_EINVAL = -1,       /* bad argument (size, stride, null pointer, grid too small) */
+    PW_ENOMEM = -2,       /* device allocation failed */
+    PW_EHIP = -3,         /* a HIP runtime call failed */
+    PW_ENOTPD = -4,       /* Gram matrix not positive definite (dependent bands) */
+    PW_ENOCONV = -5,      /* solver hit maxit before tol */
+    PW_ENAN = -6,         /* NaN/Inf met in an input or a convergence scalar */
+    PW_EUNSUPPORTED = -7  /* combination not built (e.g. dtype without its tables) */
+} pw_status;
+
+typedef enum {
+    PW_C128 = 0,          /* complex128 everywhere */
+    PW_C64 = 1            /* complex64 FFT/pointwise, BF16 x BF16 -> FP32 projector GEMMs */
+} pw_dtype;
+
+typedef struct pw_ctx pw_ctx;
+
+/* Cell, grid and cutoff of one plane-wave problem. */
+typedef struct {
+    int32_t n[3];         /* FFT grid N0, N1, N2; each a product of 2, 3, 5, at most 1024 */
+    double cell[3];       /* L0, L1, L2 (bohr) */
+    double kpt[3];        /* Bloch vector k, Cartesian (1/bohr) */
+    double ecut;          /* kinetic cutoff (Ha) */
+} pw_cell;
+
+/* Potential: local part sampled on the grid plus KB projectors.
+ * v_r    device, float64 [N0][N1][N2], Ha; copied into the context.
+ * natom  number of projector centres (0 = local only)
+ * pos    host [natom][3] bohr
+ * nl     projectors per atom: 0, 1 (s) or 4 (s, px, py, pz)
+ * sigma  projector Gaussian width (bohr)
+ * d      host [natom * nl] KB strengths D_p (Ha), order per atom s, px, py, pz */
+typedef struct {
+    const double *v_r;
+    int32_t natom;
+    const double *pos;
+    int32_t nl;
+    double sigma;
+    const double *d;
+} pw_potential;
+
+/* Context flags: which precisions to prepare tables for. */
+#define PW_PREP_C128 1    /* complex128 projector table [nproj][npw] */
+#define PW_PREP_C64  2    /* BF16 projector table and complex64 potential */
+
+typedef struct {
+    int32_t npw;          /* plane waves in the sphere */
+    int32_t ncols;        /* (n0, n1) columns that touch the sphere */
+    int32_t nshell;       /* distinct |G + k| shells */
+    int32_t nproj;        /* natom * nl */
+    int32_t grid[3];
+    int32_t max_bands;
+    int64_t device_bytes; /* workspace + tables owned by the context */
+} pw_ctx_info;
+
+/* Number of plane waves in the sphere (host only, no GPU). */
+pw_status pw_basis_size(const pw_cell *cell, int32_t *npw);
+
+/* Miller triples of the basis in coefficient order: host int32 [npw][3]. */
+pw_status pw_basis_miller(const pw_cell *cell, int32_t *miller, int32_t npw);
+
+/* Build a context on the current device: basis, z-column tables, kinetic
+ * energies, shells, V (z-major copy), projector tables per `flags`, and a
+ * workspace for hpsi on up to `max_bands` bands.  All device memory is
+ * allocated here (and by the first folded-CG solve); hot calls allocate
+ * nothing.  Returns PW_EINVAL if the sphere does not fit the grid. */
+pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t max_bands,
+                        int32_t flags, void *stream, pw_ctx **out);
+pw_status pw_ctx_destroy(pw_ctx *ctx);
+pw_status pw_ctx_get_info(const pw_ctx *ctx, pw_ctx_info *info);
+
+/* Host copies of per-plane-wave tables: kinetic energy (1/2)|G+k|^2 (float64
+ * [npw]) and shell index (int32 [npw], shells ascending in energy). */
+pw_status pw_ctx_kinetic(const pw_ctx *ctx, double *kin_host);
+pw_status pw_ctx_shells(const pw_ctx *ctx, int32_t *shell_host, double *shell_t_host);
+
+/* hpsi = (H - shift) psi for nb bands.  psi, hpsi: device, [nb][ld] / [nb][ldh]
+ * of the dtype's complex type, ld, ldh >= npw, no overlap.  Any nb >= 0 (the
+ * call loops over chunks of max_bands).  PW_C64 needs a context built with
+ * PW_PREP_C64.  Asynchronous on `stream`. */
+pw_status pw_hpsi(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *psi, int64_t ld,
+                  void *hpsi, int64_t ldh, double shift, void *stream);
+
+/* Wave <-> grid transforms of the hpsi path (no potential).
+ * to_grid:   out[b][j] = sum_G c_b(G) exp(+i G.r_j)        (device [nb][N])
+ * from_grid: c_b(G) = (1/N) sum_j f_b(r_j) exp(-i G.r_j)   (device [nb][ld])
+ * Grid arrays are [nb][N0][N1][N2] contiguous complex of the dtype. */
+pw_status pw_wave_to_grid(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *psi, int64_t ld,
+                          void *grid, void *stream);
+pw_status pw_grid_to_wave(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *grid,
+                          void *psi, int64_t ld, void *stream);
+
+/* Orthonormalise a complex128 block in place: S = Psi^H Psi, S = L L^H,
+ * Psi <- Psi L^{-H} (the Gram/Cholesky step of the solver).  Returns
+ * PW_ENOTPD (synchronising) if a Cholesky pivot is not positive. */
+pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void *stream);
+
+/* Solver options. */
+typedef struct {
+    double tol;           /* stop when max_i Delta_i <= tol (Ha); paper's accuracy 1e-6 */
+    int32_t maxit;        /* CG iterations cap */
+    int32_t precond;      /* 0 folded Teter-Payne-Allan, 1 paper M(G), 2 learned (network set) */
+    double delta_e;       /* dE of M(G) (Ha) */
+    int32_t precision;    /* 0 FP64 throughout; 1 mixed (complex64 H psi, FP64 block algebra) */
+    int32_t check_every;  /* iterations between exact residual checks */
+    int32_t verbose;      /* print the residual at each check to stderr */
+} pw_cg_opts;
+
+typedef struct {
+    int32_t iters;        /* CG iterations done */
+    int32_t converged;    /* 1 if max Delta <= tol */
+    int64_t n_hpsi;       /* band-H psi applications */
+    double max_resid;     /* final max_i Delta_i, from an FP64 H psi */
+    double seconds;       /* wall time of the solve */
+    int32_t n_hist;       /* in: capacity of hist; out: entries written */
+    double *hist;         /* host, optional: [n_hist][2] = (iteration, max Delta) */
+} pw_cg_stats;
+
+void pw_cg_opts_default(pw_cg_opts *opts);
+
+/* Folded-spectrum PCG for the nb states nearest e_ref.
+ * psi   device complex128 [nb][ld]: in, start block (any full-rank block);
+ *       out, Ritz vectors of H ascending in energy, orthonormal.
+ * eig   host [nb]: Ritz values theta_i (Ha), ascending.
+ * resid host [nb]: Delta_i = ||H psi_i - theta_i psi_i|| from an FP64 H psi.
+ * The solver synchronises `stream` once per check_every iterations. */
+pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld,
+                             double *eig, double *resid, const pw_cg_opts *opts,
+                             pw_cg_stats *stats, void *stream);
+
+/* Per-stage timing with HIP events recorded on the stream each stage is
+ * launched on.  pw_profile_begin allocates room for max_records stage launches
+ * (allocation happens here, not in the timed calls); pw_profile_end waits for
+ * the recorded events and returns, per stage kind, the summed milliseconds and
+ * the launch count.  Kinds: 0 z pass inverse, 1 xy pass (2D FFTs and V),
+ * 2 z pass forward + kinetic, 3 projection <beta|psi>, 4 back-projection. */
+#define PW_PROF_NKINDS 8
+pw_status pw_profile_begin(pw_ctx *ctx, int32_t max_records);
+pw_status pw_profile_end(pw_ctx *ctx, double *ms, int64_t *launches);
+
+const char *pw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PW_H */

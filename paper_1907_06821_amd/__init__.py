@@ -1,0 +1,308 @@
+"""paper_1907_06821_amd: folded-spectrum plane-wave eigensolver for MI355X (gfx950).
+
+Thin ctypes binding over libpw.so (include/pw.h).  Every function here only
+marshals arguments; all arithmetic runs in the library's HIP kernels.  torch is
+used for device memory and streams.  If libpw.so is missing or cannot be
+loaded, importing the compute entry points raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIBPATH = _HERE / "libpw.so"
+
+PW_OK, PW_EINVAL, PW_ENOMEM, PW_EHIP, PW_ENOTPD, PW_ENOCONV, PW_ENAN, PW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+PW_C128, PW_C64 = 0, 1
+PW_PREP_C128, PW_PREP_C64 = 1, 2
+
+_STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EHIP", -4: "PW_ENOTPD",
+                 -5: "PW_ENOCONV", -6: "PW_ENAN", -7: "PW_EUNSUPPORTED"}
+
+# names declared in include/pw.h (checked by the test-suite against the library's exports)
+EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy", "pw_ctx_get_info",
+           "pw_ctx_kinetic", "pw_ctx_shells", "pw_hpsi", "pw_wave_to_grid", "pw_grid_to_wave",
+           "pw_orthonormalize", "pw_cg_opts_default", "pw_folded_cg_solve", "pw_profile_begin",
+           "pw_profile_end", "pw_last_error")
+PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
+PW_PROF_NKINDS = 8
+
+
+class PwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pw_cell(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("cell", C.c_double * 3), ("kpt", C.c_double * 3), ("ecut", C.c_double)]
+
+
+class pw_potential(C.Structure):
+    _fields_ = [("v_r", C.c_void_p), ("natom", C.c_int32), ("pos", C.POINTER(C.c_double)), ("nl", C.c_int32),
+                ("sigma", C.c_double), ("d", C.POINTER(C.c_double))]
+
+
+class pw_ctx_info(C.Structure):
+    _fields_ = [("npw", C.c_int32), ("ncols", C.c_int32), ("nshell", C.c_int32), ("nproj", C.c_int32),
+                ("grid", C.c_int32 * 3), ("max_bands", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class pw_cg_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precond", C.c_int32), ("delta_e", C.c_double),
+                ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32)]
+
+
+class pw_cg_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_hpsi", C.c_int64), ("max_resid", C.c_double),
+                ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpw.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not LIBPATH.exists():
+            raise ImportError(f"{LIBPATH} is not built; run __graft_entry__.build() or "
+                              "python -m paper_1907_06821_amd.csrc.build")
+        L = C.CDLL(str(LIBPATH))
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "pw_basis_size": [C.POINTER(pw_cell), C.POINTER(i32)],
+            "pw_basis_miller": [C.POINTER(pw_cell), C.POINTER(i32), i32],
+            "pw_ctx_create": [C.POINTER(pw_cell), C.POINTER(pw_potential), i32, i32, vp, C.POINTER(vp)],
+            "pw_ctx_destroy": [vp],
+            "pw_ctx_get_info": [vp, C.POINTER(pw_ctx_info)],
+            "pw_ctx_kinetic": [vp, C.POINTER(dbl)],
+            "pw_ctx_shells": [vp, C.POINTER(i32), C.POINTER(dbl)],
+            "pw_hpsi": [vp, i32, i32, vp, i64, vp, i64, dbl, vp],
+            "pw_wave_to_grid": [vp, i32, i32, vp, i64, vp, vp],
+            "pw_grid_to_wave": [vp, i32, i32, vp, vp, i64, vp],
+            "pw_orthonormalize": [vp, i32, vp, i64, vp],
+            "pw_folded_cg_solve": [vp, dbl, i32, vp, i64, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(pw_cg_opts),
+                                   C.POINTER(pw_cg_stats), vp],
+            "pw_profile_begin": [vp, i32],
+            "pw_profile_end": [vp, C.POINTER(dbl), C.POINTER(i64)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.pw_cg_opts_default.argtypes = [C.POINTER(pw_cg_opts)]
+        L.pw_cg_opts_default.restype = None
+        L.pw_last_error.argtypes = []
+        L.pw_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != PW_OK:
+        raise PwError(status, lib().pw_last_error().decode(errors="replace"))
+
+
+def make_cell(grid, cell, ecut, kpt=(0.0, 0.0, 0.0)):
+    c = pw_cell()
+    for a in range(3):
+        c.n[a] = int(grid[a])
+        c.cell[a] = float(cell[a])
+        c.kpt[a] = float(kpt[a])
+    c.ecut = float(ecut)
+    return c
+
+
+def basis_miller(grid, cell, ecut, kpt=(0.0, 0.0, 0.0)):
+    """Miller triples of the basis in coefficient order (host computation in the library)."""
+    c = make_cell(grid, cell, ecut, kpt)
+    n = C.c_int32()
+    _check(lib().pw_basis_size(C.byref(c), C.byref(n)))
+    out = np.empty((n.value, 3), dtype=np.int32)
+    _check(lib().pw_basis_miller(C.byref(c), out.ctypes.data_as(C.POINTER(C.c_int32)), n.value))
+    return out
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return PW_C128
+    if t.dtype == torch.complex64:
+        return PW_C64
+    raise TypeError(f"expected complex128 or complex64, got {t.dtype}")
+
+
+def _check_block(t, npw):
+    if not t.is_cuda:
+        raise ValueError("blocks must live on the GPU")
+    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < npw or t.shape[1] != npw:
+        raise ValueError(f"expected a [nb, {npw}] row-contiguous block, got shape {tuple(t.shape)} "
+                         f"stride {t.stride()}")
+
+
+class Context:
+    """A pw_ctx: basis, tables and workspace of one problem on the current GPU.
+
+    vgrid: float64 [N0, N1, N2] local potential samples (numpy or torch).
+    pos, dproj: atom centres [natom, 3] (bohr) and KB strengths [natom * nl] (Ha).
+    flags: PW_PREP_C128 and/or PW_PREP_C64."""
+
+    def __init__(self, grid, cell, ecut, vgrid, pos=None, nl=0, sigma=0.8, dproj=None, kpt=(0.0, 0.0, 0.0),
+                 max_bands=128, flags=PW_PREP_C128, stream=None):
+        import torch
+        self._lib = lib()
+        self.handle = C.c_void_p()
+        self.cellc = make_cell(grid, cell, ecut, kpt)
+        v = torch.as_tensor(np.ascontiguousarray(vgrid, dtype=np.float64)).to("cuda")
+        if tuple(v.shape) != tuple(int(x) for x in grid):
+            raise ValueError("vgrid shape does not match the grid")
+        pot = pw_potential()
+        pot.v_r = v.data_ptr()
+        pos_np = np.ascontiguousarray(np.zeros((0, 3)) if pos is None else pos, dtype=np.float64)
+        d_np = np.ascontiguousarray(np.zeros(0) if dproj is None else dproj, dtype=np.float64)
+        pot.natom = int(pos_np.shape[0]) if nl else 0
+        pot.pos = pos_np.ctypes.data_as(C.POINTER(C.c_double))
+        pot.nl = int(nl)
+        pot.sigma = float(sigma)
+        pot.d = d_np.ctypes.data_as(C.POINTER(C.c_double))
+        st = _stream_ptr(stream)
+        _check(self._lib.pw_ctx_create(C.byref(self.cellc), C.byref(pot), int(max_bands), int(flags), st,
+                                       C.byref(self.handle)))
+        torch.cuda.current_stream().synchronize()
+        info = pw_ctx_info()
+        _check(self._lib.pw_ctx_get_info(self.handle, C.byref(info)))
+        self.npw, self.ncols, self.nshell, self.nproj = info.npw, info.ncols, info.nshell, info.nproj
+        self.grid = tuple(int(x) for x in grid)
+        self.max_bands = int(max_bands)
+
+    @classmethod
+    def from_problem(cls, prob, max_bands=None, flags=PW_PREP_C128, vgrid=None):
+        return cls(prob.grid, prob.cell, prob.ecut, prob.vgrid() if vgrid is None else vgrid,
+                   pos=prob.pos, nl=prob.nl, sigma=prob.sigma, dproj=prob.dproj, kpt=prob.kpt,
+                   max_bands=max_bands or prob.nbands, flags=flags)
+
+    def info(self):
+        info = pw_ctx_info()
+        _check(self._lib.pw_ctx_get_info(self.handle, C.byref(info)))
+        return {f: getattr(info, f) if f != "grid" else tuple(info.grid) for f, _ in pw_ctx_info._fields_}
+
+    def kinetic(self):
+        out = np.empty(self.npw)
+        _check(self._lib.pw_ctx_kinetic(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def shells(self):
+        sid = np.empty(self.npw, dtype=np.int32)
+        st = np.empty(self.nshell)
+        _check(self._lib.pw_ctx_shells(self.handle, sid.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       st.ctypes.data_as(C.POINTER(C.c_double))))
+        return sid, st
+
+    def close(self):
+        if self.handle:
+            _check(self._lib.pw_ctx_destroy(self.handle))
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hpsi(ctx, psi, shift=0.0, out=None, stream=None):
+    """out = (H - shift) psi; complex128 -> FP64 path, complex64 -> mixed path."""
+    import torch
+    _check_block(psi, ctx.npw)
+    if out is None:
+        out = torch.empty_like(psi)
+    _check_block(out, ctx.npw)
+    _check(ctx._lib.pw_hpsi(ctx.handle, _dtype_code(psi), psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                            C.c_void_p(out.data_ptr()), out.stride(0), float(shift), _stream_ptr(stream)))
+    return out
+
+
+def wave_to_grid(ctx, psi, stream=None):
+    import torch
+    _check_block(psi, ctx.npw)
+    out = torch.empty((psi.shape[0],) + ctx.grid, dtype=psi.dtype, device=psi.device)
+    _check(ctx._lib.pw_wave_to_grid(ctx.handle, _dtype_code(psi), psi.shape[0], C.c_void_p(psi.data_ptr()),
+                                    psi.stride(0), C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def grid_to_wave(ctx, grid, stream=None):
+    import torch
+    if tuple(grid.shape[1:]) != ctx.grid or not grid.is_contiguous():
+        raise ValueError("grid must be a contiguous [nb, N0, N1, N2] tensor")
+    out = torch.empty((grid.shape[0], ctx.npw), dtype=grid.dtype, device=grid.device)
+    _check(ctx._lib.pw_grid_to_wave(ctx.handle, _dtype_code(grid), grid.shape[0], C.c_void_p(grid.data_ptr()),
+                                    C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
+    return out
+
+
+def orthonormalize(ctx, psi, stream=None):
+    """In-place Gram/Cholesky orthonormalisation of a complex128 block."""
+    _check_block(psi, ctx.npw)
+    _check(ctx._lib.pw_orthonormalize(ctx.handle, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                      _stream_ptr(stream)))
+    return psi
+
+
+def profile_begin(ctx, max_records=100000):
+    _check(ctx._lib.pw_profile_begin(ctx.handle, int(max_records)))
+
+
+def profile_end(ctx):
+    """{stage kind: (total ms, launches)} for the launches since profile_begin."""
+    ms = np.zeros(PW_PROF_NKINDS)
+    n = np.zeros(PW_PROF_NKINDS, dtype=np.int64)
+    _check(ctx._lib.pw_profile_end(ctx.handle, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                   n.ctypes.data_as(C.POINTER(C.c_int64))))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(PROF_KINDS)}
+
+
+def cg_opts(**kw):
+    o = pw_cg_opts()
+    lib().pw_cg_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_on_noconv=True, **kw):
+    """Folded-spectrum PCG on the complex128 block psi (in: start, out: Ritz vectors).
+
+    Returns (eig [nb] ascending, resid [nb], stats dict)."""
+    _check_block(psi, ctx.npw)
+    nb = psi.shape[0]
+    o = opts if opts is not None else cg_opts(**kw)
+    eig = np.zeros(nb)
+    res = np.zeros(nb)
+    st = pw_cg_stats()
+    hist = np.zeros((max(hist_len, 0), 2))
+    st.n_hist = int(hist_len)
+    st.hist = hist.ctypes.data_as(C.POINTER(C.c_double)) if hist_len else C.POINTER(C.c_double)()
+    status = ctx._lib.pw_folded_cg_solve(ctx.handle, float(e_ref), nb, C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                         eig.ctypes.data_as(C.POINTER(C.c_double)),
+                                         res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o), C.byref(st),
+                                         _stream_ptr(stream))
+    stats = dict(iters=st.iters, converged=bool(st.converged), n_hpsi=st.n_hpsi, max_resid=st.max_resid,
+                 seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status)
+    if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
+        _check(status)
+    return eig, res, stats

@@ -1,0 +1,430 @@
+// C ABI of libpw: contexts, H psi, wave <-> grid transforms, orthonormalisation.
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "kernels.h"
+
+namespace pw {
+const char *last_error();
+void build_projectors(int npw, int natom, int nl, const int32_t *d_miller, const pw_cell &c, const double *d_pos,
+                      double sigma, void *beta, hipStream_t st);
+void build_vz(int n0, int n1, int n2, const double *v, double *vz64, float *vz32, hipStream_t st);
+void beta_to_bf16(int rows, int npw, int64_t ldp, const void *src, void *re, void *im, hipStream_t st);
+void solver_destroy(Solver *s);
+
+void DevBuf::alloc(size_t b) {
+    free_();
+    if (b == 0) return;
+    b = (b + 255) & ~size_t(255);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        p = nullptr;
+        set_error("hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+        throw Fail{PW_ENOMEM};
+    }
+    bytes = b;
+}
+
+void DevBuf::free_() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+template <typename T> static void upload(DevBuf &d, const std::vector<T> &h, int64_t &acct) {
+    d.alloc(h.size() * sizeof(T));
+    acct += (int64_t)d.bytes;
+    if (!h.empty()) PW_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+static void twiddles(int n, std::vector<double> &t64, std::vector<float> &t32) {
+    t64.resize(2 * n);
+    t32.resize(2 * n);
+    for (int t = 0; t < n; ++t) {
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)n;
+        const double c = (double)cosl(ang), s = (double)-sinl(ang);
+        t64[2 * t] = c;
+        t64[2 * t + 1] = s;
+        t32[2 * t] = (float)cosl(ang);
+        t32[2 * t + 1] = (float)-sinl(ang);
+    }
+}
+
+// Largest split-K scratch any call can need: the split count grows as the output
+// shrinks, so take the maximum over every band count up to max_bands.
+size_t hpsi_partial_bytes(const pw_ctx *ctx) {
+    size_t b = 0;
+    const int npw = ctx->basis.npw;
+    for (int n = 1; n <= ctx->max_bands; ++n) {
+        if (ctx->nproj) {
+            b = std::max(b, nt_partial_bytes(ctx->nproj, n, npw));
+            b = std::max(b, cnt_partial_bytes(ctx->nproj, n, npw));
+        }
+        b = std::max(b, nt_partial_bytes(n, n, npw));
+    }
+    return b;
+}
+
+// (H - shift) psi for one chunk of at most max_bands bands, complex128
+static void hpsi_c128(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
+                      hipStream_t st) {
+    const int npw = ctx->basis.npw;
+    const double scale = 1.0 / ((double)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2]);
+    { ProfScope p(ctx, 0, st); launch_zinv<double>(ctx, nb, psi, ld, ctx->d_cols.p, st); }
+    { ProfScope p(ctx, 1, st); launch_xy<double, 0>(ctx, nb, ctx->d_cols.p, nullptr, st); }
+    {
+        ProfScope p(ctx, 2, st);
+        launch_zfwd<double>(ctx, nb, ctx->d_cols.p, psi, ld, ctx->d_kin.as<double>(), shift, scale, out, ldo, st);
+    }
+    if (ctx->nproj) {
+        // projT[b][p] = D_p <beta_p | psi_b>, then out += projT . beta
+        {
+            ProfScope p(ctx, 3, st);
+            zgemm_nt(ctx->nproj, nb, npw, true, ctx->d_beta64.p, npw, psi, ld, 1.0, ctx->d_dproj.as<double>(), 0.0,
+                     ctx->d_proj.p, ctx->nproj, true, ctx->d_partial.p, st);
+        }
+        ProfScope p(ctx, 4, st);
+        zgemm_nn_launch(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->nproj, ctx->d_beta64.p, npw, 1.0, 1.0, out, ldo, st);
+    }
+}
+
+static void hpsi_c64(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
+                     hipStream_t st) {
+    const int npw = ctx->basis.npw;
+    const double scale = 1.0 / ((double)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2]);
+    { ProfScope p(ctx, 0, st); launch_zinv<float>(ctx, nb, psi, ld, ctx->d_cols.p, st); }
+    { ProfScope p(ctx, 1, st); launch_xy<float, 0>(ctx, nb, ctx->d_cols.p, nullptr, st); }
+    {
+        ProfScope p(ctx, 2, st);
+        launch_zfwd<float>(ctx, nb, ctx->d_cols.p, psi, ld, ctx->d_kin.as<double>(), shift, scale, out, ldo, st);
+    }
+    if (ctx->nproj) {
+        {
+            ProfScope p(ctx, 3, st);
+            proj_bf16(ctx->nproj, nb, npw, ctx->d_beta_bf16.p, psi, ld, ctx->d_dproj32.as<float>(), ctx->d_proj.p,
+                      ctx->d_partial.p, st);
+        }
+        ProfScope p(ctx, 4, st);
+        backproj_bf16(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->d_beta_bf16.p, out, ldo, st);
+    }
+}
+
+void hpsi_any(pw_ctx *ctx, pw_dtype dt, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
+              hipStream_t st) {
+    const size_t es = dt == PW_C128 ? 16 : 8;
+    for (int b0 = 0; b0 < nb; b0 += ctx->max_bands) {
+        const int nbc = std::min(ctx->max_bands, nb - b0);
+        const char *pi = (const char *)psi + (size_t)b0 * ld * es;
+        char *po = (char *)out + (size_t)b0 * ldo * es;
+        if (dt == PW_C128) hpsi_c128(ctx, nbc, pi, ld, po, ldo, shift, st);
+        else hpsi_c64(ctx, nbc, pi, ld, po, ldo, shift, st);
+    }
+}
+
+// Psi <- Psi L^{-H} for a complex128 block, using ws (>= nb*npw complex128) as scratch
+void orthonormalize_c128(pw_ctx *ctx, int nb, void *psi, int64_t ld, void *ws, void *small, int *d_status,
+                         hipStream_t st) {
+    const int npw = ctx->basis.npw;
+    double2 *S = (double2 *)small;
+    double2 *W = S + (size_t)nb * nb;
+    double2 *T = W + (size_t)nb * nb;
+    zgemm_nt(nb, nb, npw, true, psi, ld, psi, ld, 1.0, nullptr, 0.0, S, nb, false, ctx->d_partial.p, st);
+    chol_inv(nb, S, nb, W, T, d_status, st);
+    zgemm_nn_launch(nb, npw, nb, T, nb, psi, ld, 1.0, 0.0, ws, npw, st);
+    copy_block(nb, npw, ws, npw, psi, ld, st);
+}
+
+}  // namespace pw
+
+using namespace pw;
+
+#define PW_API_BEGIN try {
+#define PW_API_END                                                       \
+    }                                                                    \
+    catch (const Fail &f) { return f.st; }                               \
+    catch (const std::bad_alloc &) { set_error("host allocation failed"); return PW_ENOMEM; } \
+    catch (...) { set_error("unexpected exception"); return PW_EINVAL; } \
+    return PW_OK;
+
+extern "C" {
+
+const char *pw_last_error(void) { return pw::last_error(); }
+
+pw_status pw_basis_size(const pw_cell *cell, int32_t *npw) {
+    PW_API_BEGIN
+    PW_CHECK(cell && npw, PW_EINVAL, "null argument");
+    std::vector<int32_t> m;
+    enumerate_miller(*cell, m);
+    *npw = (int32_t)(m.size() / 3);
+    PW_API_END
+}
+
+pw_status pw_basis_miller(const pw_cell *cell, int32_t *miller, int32_t npw) {
+    PW_API_BEGIN
+    PW_CHECK(cell && miller, PW_EINVAL, "null argument");
+    std::vector<int32_t> m;
+    enumerate_miller(*cell, m);
+    PW_CHECK((int64_t)m.size() == 3 * (int64_t)npw, PW_EINVAL, "npw %d does not match the basis (%zu)", npw,
+             m.size() / 3);
+    std::memcpy(miller, m.data(), m.size() * sizeof(int32_t));
+    PW_API_END
+}
+
+pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t max_bands, int32_t flags, void *stream,
+                        pw_ctx **out) {
+    PW_API_BEGIN
+    PW_CHECK(cell && pot && out, PW_EINVAL, "null argument");
+    PW_CHECK(max_bands >= 1 && max_bands <= 8192, PW_EINVAL, "max_bands %d out of range", max_bands);
+    PW_CHECK(pot->v_r, PW_EINVAL, "v_r is null");
+    PW_CHECK(pot->natom >= 0 && (pot->natom == 0 || (pot->pos && pot->d)), PW_EINVAL, "bad atom arrays");
+    PW_CHECK(pot->nl == 0 || pot->nl == 1 || pot->nl == 4, PW_EINVAL, "nl must be 0, 1 or 4");
+    if (!(flags & (PW_PREP_C128 | PW_PREP_C64))) flags |= PW_PREP_C128;
+    *out = nullptr;
+    std::unique_ptr<pw_ctx> c(new pw_ctx());
+    hipStream_t st = (hipStream_t)stream;
+    c->cell = *cell;
+    for (int a = 0; a < 3; ++a) c->plan[a] = make_plan(cell->n[a]);
+    c->basis = build_basis(*cell);
+    c->max_bands = max_bands;
+    c->flags = flags;
+    c->natom = pot->nl ? pot->natom : 0;
+    c->nl = pot->nl;
+    c->nproj = c->natom * c->nl;
+    PW_HIP(hipGetDevice(&c->device));
+    const Basis &b = c->basis;
+    const int n0 = cell->n[0], n1 = cell->n[1], n2 = cell->n[2];
+    int64_t acct = 0;
+    upload(c->d_kin, b.kin, acct);
+    upload(c->d_colstart, b.col_start, acct);
+    std::vector<int32_t> zmap(b.npw), colpos(b.ncols);
+    for (int col = 0; col < b.ncols; ++col) {
+        colpos[col] = b.col_i0[col] * (n1 + 1) + b.col_i1[col];
+        for (int g = b.col_start[col]; g < b.col_start[col + 1]; ++g) {
+            const int n2v = b.miller[3 * g + 2];
+            zmap[g] = (col % c->cb) * (n2 + 1) + ((n2v % n2) + n2) % n2;
+        }
+    }
+    upload(c->d_zmap, zmap, acct);
+    upload(c->d_colpos, colpos, acct);
+    upload(c->d_shell, b.shell, acct);
+    for (int a = 0; a < 3; ++a) {
+        std::vector<double> t64;
+        std::vector<float> t32;
+        twiddles(cell->n[a], t64, t32);
+        upload(c->d_tw64[a], t64, acct);
+        upload(c->d_tw32[a], t32, acct);
+    }
+    const int64_t ngrid = (int64_t)n0 * n1 * n2;
+    c->d_vz64.alloc(ngrid * 8);
+    if (flags & PW_PREP_C64) c->d_vz32.alloc(ngrid * 4);
+    acct += c->d_vz64.bytes + c->d_vz32.bytes;
+    build_vz(n0, n1, n2, pot->v_r, c->d_vz64.as<double>(), c->d_vz32.as<float>(), st);
+    if (c->nproj) {
+        c->dproj.assign(pot->d, pot->d + c->nproj);
+        for (double d : c->dproj) PW_CHECK(std::isfinite(d), PW_ENAN, "non-finite KB strength");
+        upload(c->d_dproj, c->dproj, acct);
+        std::vector<float> d32(c->dproj.begin(), c->dproj.end());
+        upload(c->d_dproj32, d32, acct);
+        std::vector<int32_t> mil(b.miller);
+        DevBuf d_mil, d_pos;
+        int64_t tmp = 0;
+        upload(d_mil, mil, tmp);
+        std::vector<double> pos(pot->pos, pot->pos + 3 * c->natom);
+        upload(d_pos, pos, tmp);
+        c->d_beta64.alloc((size_t)c->nproj * b.npw * 16);
+        build_projectors(b.npw, c->natom, c->nl, d_mil.as<int32_t>(), *cell, d_pos.as<double>(), pot->sigma,
+                         c->d_beta64.p, st);
+        if (flags & PW_PREP_C64) {
+            c->ldb16 = ((b.npw + 63) / 64) * 64;
+            c->d_beta_bf16.alloc((size_t)2 * c->nproj * c->ldb16 * 2);
+            beta_to_bf16(c->nproj, b.npw, c->ldb16, c->d_beta64.p, c->d_beta_bf16.p,
+                         (char *)c->d_beta_bf16.p + (size_t)c->nproj * c->ldb16 * 2, st);
+            acct += c->d_beta_bf16.bytes;
+            if (!(flags & PW_PREP_C128)) c->d_beta64.free_();
+        }
+        acct += c->d_beta64.bytes;
+        PW_HIP(hipStreamSynchronize(st));   // d_mil, d_pos die here
+    }
+    c->d_cols.alloc((size_t)max_bands * n2 * b.ncols * 16);
+    c->d_proj.alloc((size_t)max_bands * std::max(1, c->nproj) * 16);
+    c->d_partial.alloc(hpsi_partial_bytes(c.get()));
+    c->d_ortho_ws.alloc((size_t)max_bands * b.npw * 16);
+    c->d_ortho_small.alloc((size_t)3 * max_bands * max_bands * 16 + 256);
+    acct += c->d_cols.bytes + c->d_proj.bytes + c->d_partial.bytes + c->d_ortho_ws.bytes + c->d_ortho_small.bytes;
+    c->device_bytes = acct;
+    PW_HIP(hipStreamSynchronize(st));
+    *out = c.release();
+    PW_API_END
+}
+
+pw_status pw_ctx_destroy(pw_ctx *ctx) {
+    PW_API_BEGIN
+    if (!ctx) return PW_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->solver) solver_destroy(ctx->solver);
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+    ctx->prof_pool.clear();
+    DevBuf *bufs[] = {&ctx->d_kin, &ctx->d_zmap, &ctx->d_colpos, &ctx->d_colstart, &ctx->d_vz64, &ctx->d_vz32,
+                      &ctx->d_tw64[0], &ctx->d_tw64[1], &ctx->d_tw64[2], &ctx->d_tw32[0], &ctx->d_tw32[1],
+                      &ctx->d_tw32[2], &ctx->d_beta64, &ctx->d_beta_bf16, &ctx->d_dproj, &ctx->d_dproj32,
+                      &ctx->d_shell, &ctx->d_cols, &ctx->d_proj, &ctx->d_partial, &ctx->d_ortho_ws,
+                      &ctx->d_ortho_small};
+    for (DevBuf *d : bufs) d->free_();
+    (void)hipSetDevice(cur);
+    delete ctx;
+    PW_API_END
+}
+
+pw_status pw_ctx_get_info(const pw_ctx *ctx, pw_ctx_info *info) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && info, PW_EINVAL, "null argument");
+    info->npw = ctx->basis.npw;
+    info->ncols = ctx->basis.ncols;
+    info->nshell = (int32_t)ctx->basis.shell_t.size();
+    info->nproj = ctx->nproj;
+    for (int a = 0; a < 3; ++a) info->grid[a] = ctx->cell.n[a];
+    info->max_bands = ctx->max_bands;
+    info->device_bytes = ctx->device_bytes;
+    PW_API_END
+}
+
+pw_status pw_ctx_kinetic(const pw_ctx *ctx, double *kin) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && kin, PW_EINVAL, "null argument");
+    std::memcpy(kin, ctx->basis.kin.data(), sizeof(double) * ctx->basis.npw);
+    PW_API_END
+}
+
+pw_status pw_ctx_shells(const pw_ctx *ctx, int32_t *shell, double *shell_t) {
+    PW_API_BEGIN
+    PW_CHECK(ctx, PW_EINVAL, "null argument");
+    if (shell) std::memcpy(shell, ctx->basis.shell.data(), sizeof(int32_t) * ctx->basis.npw);
+    if (shell_t) std::memcpy(shell_t, ctx->basis.shell_t.data(), sizeof(double) * ctx->basis.shell_t.size());
+    PW_API_END
+}
+
+static void check_block_args(const pw_ctx *ctx, pw_dtype dt, int nb, const void *a, int64_t lda) {
+    PW_CHECK(ctx, PW_EINVAL, "null context");
+    PW_CHECK(dt == PW_C128 || dt == PW_C64, PW_EINVAL, "unknown dtype %d", (int)dt);
+    PW_CHECK(nb >= 0, PW_EINVAL, "negative band count");
+    PW_CHECK(nb == 0 || a, PW_EINVAL, "null block");
+    PW_CHECK(lda >= ctx->basis.npw, PW_EINVAL, "leading dimension %lld < npw %d", (long long)lda, ctx->basis.npw);
+    if (dt == PW_C64) PW_CHECK(ctx->flags & PW_PREP_C64, PW_EUNSUPPORTED, "context built without PW_PREP_C64");
+    if (dt == PW_C128) PW_CHECK(ctx->flags & PW_PREP_C128, PW_EUNSUPPORTED, "context built without PW_PREP_C128");
+}
+
+pw_status pw_hpsi(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *psi, int64_t ld, void *hpsi, int64_t ldh,
+                  double shift, void *stream) {
+    PW_API_BEGIN
+    check_block_args(ctx, dtype, nb, psi, ld);
+    check_block_args(ctx, dtype, nb, hpsi, ldh);
+    PW_CHECK(nb == 0 || psi != hpsi, PW_EINVAL, "psi and hpsi must not alias");
+    PW_CHECK(std::isfinite(shift), PW_ENAN, "non-finite shift");
+    if (nb == 0) return PW_OK;
+    hpsi_any(ctx, dtype, nb, psi, ld, hpsi, ldh, shift, (hipStream_t)stream);
+    PW_API_END
+}
+
+pw_status pw_wave_to_grid(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *psi, int64_t ld, void *grid,
+                          void *stream) {
+    PW_API_BEGIN
+    check_block_args(ctx, dtype, nb, psi, ld);
+    PW_CHECK(nb == 0 || grid, PW_EINVAL, "null grid");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = dtype == PW_C128 ? 16 : 8;
+    const size_t ng = (size_t)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2];
+    for (int b0 = 0; b0 < nb; b0 += ctx->max_bands) {
+        const int nbc = std::min(ctx->max_bands, nb - b0);
+        const char *pi = (const char *)psi + (size_t)b0 * ld * es;
+        char *go = (char *)grid + (size_t)b0 * ng * es;
+        if (dtype == PW_C128) {
+            launch_zinv<double>(ctx, nbc, pi, ld, ctx->d_cols.p, st);
+            launch_xy<double, 1>(ctx, nbc, ctx->d_cols.p, go, st);
+        } else {
+            launch_zinv<float>(ctx, nbc, pi, ld, ctx->d_cols.p, st);
+            launch_xy<float, 1>(ctx, nbc, ctx->d_cols.p, go, st);
+        }
+    }
+    PW_API_END
+}
+
+pw_status pw_grid_to_wave(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *grid, void *psi, int64_t ld,
+                          void *stream) {
+    PW_API_BEGIN
+    check_block_args(ctx, dtype, nb, psi, ld);
+    PW_CHECK(nb == 0 || grid, PW_EINVAL, "null grid");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = dtype == PW_C128 ? 16 : 8;
+    const size_t ng = (size_t)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2];
+    const double scale = 1.0 / (double)ng;
+    for (int b0 = 0; b0 < nb; b0 += ctx->max_bands) {
+        const int nbc = std::min(ctx->max_bands, nb - b0);
+        char *po = (char *)psi + (size_t)b0 * ld * es;
+        const char *gi = (const char *)grid + (size_t)b0 * ng * es;
+        if (dtype == PW_C128) {
+            launch_xy<double, 2>(ctx, nbc, ctx->d_cols.p, (void *)gi, st);
+            launch_zfwd<double>(ctx, nbc, ctx->d_cols.p, nullptr, 0, nullptr, 0.0, scale, po, ld, st);
+        } else {
+            launch_xy<float, 2>(ctx, nbc, ctx->d_cols.p, (void *)gi, st);
+            launch_zfwd<float>(ctx, nbc, ctx->d_cols.p, nullptr, 0, nullptr, 0.0, scale, po, ld, st);
+        }
+    }
+    PW_API_END
+}
+
+pw_status pw_profile_begin(pw_ctx *ctx, int32_t max_records) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && max_records >= 1 && max_records <= (1 << 22), PW_EINVAL, "bad profile arguments");
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+    ctx->prof_pool.clear();
+    ctx->prof_rec.clear();
+    ctx->prof_rec.reserve(max_records);
+    ctx->prof_pool.resize(2 * (size_t)max_records, nullptr);
+    for (auto &e : ctx->prof_pool) PW_HIP(hipEventCreate(&e));
+    ctx->prof_next = 0;
+    ctx->prof_on = true;
+    PW_API_END
+}
+
+pw_status pw_profile_end(pw_ctx *ctx, double *ms, int64_t *launches) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && ms && launches, PW_EINVAL, "null argument");
+    for (int k = 0; k < PW_PROF_NKINDS; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    for (const ProfRec &r : ctx->prof_rec) {
+        PW_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        PW_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        if (r.kind >= 0 && r.kind < PW_PROF_NKINDS) {
+            ms[r.kind] += t;
+            launches[r.kind] += 1;
+        }
+    }
+    ctx->prof_on = false;
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+    ctx->prof_pool.clear();
+    ctx->prof_rec.clear();
+    ctx->prof_next = 0;
+    PW_API_END
+}
+
+pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void *stream) {
+    PW_API_BEGIN
+    check_block_args(ctx, PW_C128, nb, psi, ld);
+    PW_CHECK(nb <= ctx->max_bands, PW_EINVAL, "nb %d > max_bands %d", nb, ctx->max_bands);
+    if (nb == 0) return PW_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int *d_status = (int *)((char *)ctx->d_ortho_small.p + (size_t)3 * ctx->max_bands * ctx->max_bands * 16);
+    fill_zero(d_status, 16, st);
+    orthonormalize_c128(ctx, nb, psi, ld, ctx->d_ortho_ws.p, ctx->d_ortho_small.p, d_status, st);
+    int status = 0;
+    PW_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    PW_CHECK(status == 0, PW_ENOTPD, "Gram matrix not positive definite at pivot %d", status - 1);
+    PW_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,364 @@
+// Band-wise vector kernels of the folded-spectrum CG: fused gradient and
+// preconditioner, conjugation, line-search inner products, per-band updates and
+// residual norms.  All blocks are band-major complex128 [nb][ld]; every
+// reduction is two-stage (per-workgroup partials, then a fixed-order sum), so
+// results do not depend on scheduling.
+#include "kernels.h"
+
+namespace pw {
+
+constexpr int RT = 256;          // threads per reduction workgroup
+constexpr int RCHUNK = RT * 8;   // plane waves per reduction workgroup
+
+int band_splits(int npw) { return (npw + RCHUNK - 1) / RCHUNK; }
+
+__device__ inline double tpa_k(double x) {
+    // Teter-Payne-Allan kinetic preconditioner
+    const double num = 27.0 + x * (18.0 + x * (12.0 + 8.0 * x));
+    return num / (num + 16.0 * x * x * x * x);
+}
+
+__device__ inline double prec_weight(const PrecArgs &pa, int b, int g) {
+    const double t = pa.kin[g];
+    if (pa.kind == 1) {
+        const double d = t - pa.e_ref;
+        return 1.0 / (d * d + pa.de2);
+    }
+    const double k = tpa_k(t / pa.tband[b]);
+    double w = k * k;
+    if (pa.kind == 2) w *= exp((double)pa.ftab[(int64_t)pa.shell[g] * pa.nb + b]);
+    return w;
+}
+
+template <int NQ>
+__device__ inline void block_store(double (&acc)[NQ], double *partial, int nb, int nsplit, int b, int split) {
+    __shared__ double red[NQ][RT];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) partial[((int64_t)q * nb + b) * nsplit + split] = red[q][0];
+    }
+}
+
+// out[q * nb + b] = sum_split partial[q][b][split]
+__global__ void finish_red(int nq, int nb, int nsplit, const double *__restrict__ partial, double *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq * nb) return;
+    double s = 0;
+    for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)i * nsplit + k];
+    out[i] = s;
+}
+
+static void finish(int nq, int nb, const BandRed &r, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(finish_red, dim3((nq * nb + 255) / 256), dim3(256), 0, st, nq, nb, r.nsplit, r.partial, out);
+    PW_LAUNCH_CHECK();
+}
+
+#define BAND_LOOP(npw)                                                     \
+    const int b = blockIdx.y, split = blockIdx.x;                          \
+    const int g0 = split * RCHUNK;                                         \
+    const int g1 = min(npw, g0 + RCHUNK);                                  \
+    for (int g = g0 + threadIdx.x; g < g1; g += RT)
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RT) void k_mu_tband(int nb, int npw, const double2 *__restrict__ Y,
+                                                 const double2 *__restrict__ X, int64_t ld,
+                                                 const double *__restrict__ kin, double *partial, int nsplit) {
+    double acc[2] = {0, 0};
+    BAND_LOOP(npw) {
+        const double2 y = Y[(int64_t)b * ld + g], x = X[(int64_t)b * ld + g];
+        acc[0] += y.x * y.x + y.y * y.y;
+        acc[1] += kin[g] * (x.x * x.x + x.y * x.y);
+    }
+    block_store<2>(acc, partial, nb, nsplit, b, split);
+}
+
+void red_mu_tband(int nb, int npw, const void *Y, const void *X, int64_t ld, const double *kin, double *mu,
+                  double *tband, BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_mu_tband, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)Y,
+                       (const double2 *)X, ld, kin, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    // mu -> out[0:nb], tband -> out[nb:2nb] requires contiguous outputs
+    PW_CHECK(tband == mu + nb, PW_EINVAL, "mu and tband must be adjacent");
+    finish(2, nb, r, mu, st);
+}
+
+// G = AX - mu X ; Z = K o G ; gz = Re<G, Z> ; gzo = Re<Gold, Z> ; Gold <- G
+__global__ __launch_bounds__(RT) void k_grad(int nb, int npw, const double2 *__restrict__ X,
+                                             const double2 *__restrict__ AX, double2 *__restrict__ Gold,
+                                             double2 *__restrict__ Z, int64_t ld, const double *__restrict__ mu,
+                                             PrecArgs pa, double *partial, int nsplit) {
+    double acc[2] = {0, 0};
+    BAND_LOOP(npw) {
+        const int64_t i = (int64_t)b * ld + g;
+        const double m = mu[b];
+        const double2 x = X[i], ax = AX[i], go = Gold[i];
+        const double2 gr = make_double2(ax.x - m * x.x, ax.y - m * x.y);
+        const double w = prec_weight(pa, b, g);
+        const double2 z = make_double2(w * gr.x, w * gr.y);
+        acc[0] += gr.x * z.x + gr.y * z.y;
+        acc[1] += go.x * z.x + go.y * z.y;
+        Gold[i] = gr;
+        Z[i] = z;
+    }
+    block_store<2>(acc, partial, nb, nsplit, b, split);
+}
+
+void red_grad(int nb, int npw, const void *X, const void *AX, void *Gold, void *Z, int64_t ld, const double *mu,
+              PrecArgs pa, double *gz, double *gzo, BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)X,
+                       (const double2 *)AX, (double2 *)Gold, (double2 *)Z, ld, mu, pa, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    PW_CHECK(gzo == gz + nb, PW_EINVAL, "gz and gzo must be adjacent");
+    finish(2, nb, r, gz, st);
+}
+
+__global__ __launch_bounds__(RT) void k_gzold(int nb, int npw, const double2 *__restrict__ G, int64_t ld,
+                                              PrecArgs pa, double *partial, int nsplit) {
+    double acc[1] = {0};
+    BAND_LOOP(npw) {
+        const double2 v = G[(int64_t)b * ld + g];
+        acc[0] += prec_weight(pa, b, g) * (v.x * v.x + v.y * v.y);
+    }
+    block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+void red_gzold(int nb, int npw, const void *G, int64_t ld, PrecArgs pa, double *gz_old, BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_gzold, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)G, ld, pa,
+                       r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    finish(1, nb, r, gz_old, st);
+}
+
+// P = -Z + beta P with Polak-Ribiere beta = max(0, (gz - gzo) / gz_old); the
+// first workgroup of each band also stores gz as the next gz_old.
+__global__ void k_pupdate(int nb, int npw, const double2 *__restrict__ Z, double2 *__restrict__ P, int64_t ld,
+                          const double *__restrict__ gz, const double *__restrict__ gzo, double *__restrict__ gz_old) {
+    const int b = blockIdx.y;
+    const double den = gz_old[b];
+    double beta = den > 0.0 ? (gz[b] - gzo[b]) / den : 0.0;
+    if (!(beta > 0.0)) beta = 0.0;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < npw) {
+        const int64_t i = (int64_t)b * ld + g;
+        const double2 z = Z[i], p = P[i];
+        P[i] = make_double2(-z.x + beta * p.x, -z.y + beta * p.y);
+    }
+}
+
+__global__ void k_store_gzold(int nb, const double *gz, double *gz_old) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) gz_old[b] = gz[b];
+}
+
+void pupdate(int nb, int npw, const void *Z, void *P, int64_t ld, const double *gz, const double *gzo,
+             double *gz_old, hipStream_t st) {
+    hipLaunchKernelGGL(k_pupdate, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (const double2 *)Z,
+                       (double2 *)P, ld, gz, gzo, gz_old);
+    PW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_store_gzold, dim3((nb + 255) / 256), dim3(256), 0, st, nb, gz, gz_old);
+    PW_LAUNCH_CHECK();
+}
+
+// <Y, YP> (re, im), ||YP||^2, ||P||^2
+__global__ __launch_bounds__(RT) void k_line(int nb, int npw, const double2 *__restrict__ Y,
+                                             const double2 *__restrict__ YP, const double2 *__restrict__ P,
+                                             int64_t ld, double *partial, int nsplit) {
+    double acc[4] = {0, 0, 0, 0};
+    BAND_LOOP(npw) {
+        const int64_t i = (int64_t)b * ld + g;
+        const double2 y = Y[i], yp = YP[i], p = P[i];
+        acc[0] += y.x * yp.x + y.y * yp.y;
+        acc[1] += y.x * yp.y - y.y * yp.x;
+        acc[2] += yp.x * yp.x + yp.y * yp.y;
+        acc[3] += p.x * p.x + p.y * p.y;
+    }
+    block_store<4>(acc, partial, nb, nsplit, b, split);
+}
+
+void red_line(int nb, int npw, const void *Y, const void *YP, const void *P, int64_t ld, double *out4, BandRed r,
+              hipStream_t st) {
+    hipLaunchKernelGGL(k_line, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)Y,
+                       (const double2 *)YP, (const double2 *)P, ld, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    finish(4, nb, r, out4, st);
+}
+
+// Exact minimum of the Rayleigh quotient of A on span{psi, p} (p orthogonal to
+// psi): lowest eigenvector of [[a11, a12], [conj a12, a22]] in the basis
+// {psi, p/|p|}, computed without cancellation.  coef[b] = (alpha re, alpha im,
+// beta re, beta im) with psi' = alpha psi + beta p.
+__global__ void k_line_coef(int nb, const double *__restrict__ mu, const double *__restrict__ l4,
+                            double *__restrict__ coef) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double pn2 = l4[3 * nb + b];
+    double ar = 1, ai = 0, br = 0, bi = 0;
+    if (pn2 > 0.0) {
+        const double pn = sqrt(pn2);
+        const double a11 = mu[b];
+        const double cr = l4[b] / pn, ci = l4[nb + b] / pn;   // a12 = <Y, YP>/|p|
+        const double a22 = l4[2 * nb + b] / pn2;
+        const double d = 0.5 * (a22 - a11);
+        const double r = sqrt(d * d + cr * cr + ci * ci);
+        if (r > 0.0) {
+            if (d >= 0) { ar = d + r; ai = 0; br = -cr; bi = ci; }          // (d + r, -conj a12)
+            else { ar = cr; ai = ci; br = d - r; bi = 0; }                  // (a12, d - r)
+            const double nrm = sqrt(ar * ar + ai * ai + br * br + bi * bi);
+            ar /= nrm; ai /= nrm; br /= nrm * pn; bi /= nrm * pn;
+        }
+    }
+    coef[4 * b + 0] = ar;
+    coef[4 * b + 1] = ai;
+    coef[4 * b + 2] = br;
+    coef[4 * b + 3] = bi;
+}
+
+void line_coef(int nb, const double *mu, const double *l4, double *coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_line_coef, dim3((nb + 255) / 256), dim3(256), 0, st, nb, mu, l4, coef);
+    PW_LAUNCH_CHECK();
+}
+
+__device__ inline double2 lin2(double2 a, double2 x, double2 b, double2 y) {
+    return make_double2(a.x * x.x - a.y * x.y + b.x * y.x - b.y * y.y, a.x * x.y + a.y * x.x + b.x * y.y + b.y * y.x);
+}
+
+__global__ void k_combine3(int nb, int npw, double2 *__restrict__ X, double2 *__restrict__ Y, double2 *__restrict__ AX,
+                           const double2 *__restrict__ P, const double2 *__restrict__ YP,
+                           const double2 *__restrict__ AP, int64_t ld, const double *__restrict__ coef) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const double2 al = make_double2(coef[4 * b], coef[4 * b + 1]);
+    const double2 be = make_double2(coef[4 * b + 2], coef[4 * b + 3]);
+    const int64_t i = (int64_t)b * ld + g;
+    X[i] = lin2(al, X[i], be, P[i]);
+    Y[i] = lin2(al, Y[i], be, YP[i]);
+    AX[i] = lin2(al, AX[i], be, AP[i]);
+}
+
+void combine3(int nb, int npw, void *X, void *Y, void *AX, const void *P, const void *YP, const void *AP,
+              int64_t ld, const double *coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine3, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (double2 *)X,
+                       (double2 *)Y, (double2 *)AX, (const double2 *)P, (const double2 *)YP, (const double2 *)AP,
+                       ld, coef);
+    PW_LAUNCH_CHECK();
+}
+
+// res[b] = || Y_b - w_b X_b ||
+__global__ __launch_bounds__(RT) void k_resid(int nb, int npw, const double2 *__restrict__ Y,
+                                              const double2 *__restrict__ X, int64_t ld, const double *__restrict__ w,
+                                              double *partial, int nsplit) {
+    double acc[1] = {0};
+    BAND_LOOP(npw) {
+        const int64_t i = (int64_t)b * ld + g;
+        const double2 y = Y[i], x = X[i];
+        const double wb = w[b];
+        const double rx = y.x - wb * x.x, ry = y.y - wb * x.y;
+        acc[0] += rx * rx + ry * ry;
+    }
+    block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+__global__ void k_sqrt(int n, double *x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = sqrt(x[i]);
+}
+
+void red_resid(int nb, int npw, const void *Y, const void *X, int64_t ld, const double *w, double *res, BandRed r,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_resid, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)Y,
+                       (const double2 *)X, ld, w, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    finish(1, nb, r, res, st);
+    hipLaunchKernelGGL(k_sqrt, dim3((nb + 255) / 256), dim3(256), 0, st, nb, res);
+    PW_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(RT) void k_norm2(int nb, int npw, const double2 *__restrict__ X, int64_t ld,
+                                              double *partial, int nsplit) {
+    double acc[1] = {0};
+    BAND_LOOP(npw) {
+        const double2 x = X[(int64_t)b * ld + g];
+        acc[0] += x.x * x.x + x.y * x.y;
+    }
+    block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+void band_norms(int nb, int npw, const void *X, int64_t ld, double *out, BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm2, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)X, ld, r.partial,
+                       r.nsplit);
+    PW_LAUNCH_CHECK();
+    finish(1, nb, r, out, st);
+    hipLaunchKernelGGL(k_sqrt, dim3((nb + 255) / 256), dim3(256), 0, st, nb, out);
+    PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill_zero(uint4 *p, size_t n16) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+void fill_zero(void *p, size_t bytes, hipStream_t st) {
+    PW_CHECK(bytes % 16 == 0 && ((uintptr_t)p % 16) == 0, PW_EINVAL, "fill_zero needs 16-byte aligned sizes");
+    const size_t n16 = bytes / 16;
+    if (!n16) return;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, st, (uint4 *)p, n16);
+    PW_LAUNCH_CHECK();
+}
+
+template <typename S, typename D>
+__global__ void k_convert(int npw, const S *__restrict__ src, int64_t lds, D *__restrict__ dst, int64_t ldd) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const S v = src[(int64_t)b * lds + g];
+    D o;
+    o.x = v.x;
+    o.y = v.y;
+    dst[(int64_t)b * ldd + g] = o;
+}
+
+void copy_block(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t st) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL((k_convert<double2, double2>), dim3((npw + 255) / 256, nb), dim3(256), 0, st, npw,
+                       (const double2 *)src, lds, (double2 *)dst, ldd);
+    PW_LAUNCH_CHECK();
+}
+
+void c64_to_c128(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t st) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL((k_convert<float2, double2>), dim3((npw + 255) / 256, nb), dim3(256), 0, st, npw,
+                       (const float2 *)src, lds, (double2 *)dst, ldd);
+    PW_LAUNCH_CHECK();
+}
+
+void c128_to_c64(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t st) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL((k_convert<double2, float2>), dim3((npw + 255) / 256, nb), dim3(256), 0, st, npw,
+                       (const double2 *)src, lds, (float2 *)dst, ldd);
+    PW_LAUNCH_CHECK();
+}
+
+__global__ void k_nan_check(size_t n, const double *x, int *flag) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(x[i])) flag[0] = 1;
+}
+
+void nan_check(size_t n, const double *x, int *flag, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_nan_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, flag);
+    PW_LAUNCH_CHECK();
+}
+
+}  // namespace pw

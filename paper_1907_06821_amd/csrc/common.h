@@ -1,0 +1,172 @@
+// Shared definitions of libpw: complex types, error plumbing, context layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/pw.h"
+
+namespace pw {
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on HIP vector types (interleaved re, im)
+// ---------------------------------------------------------------------------
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename T> using cplx = typename cvec<T>::type;
+
+template <typename T> __host__ __device__ inline cplx<T> cmake(T re, T im) {
+    cplx<T> z; z.x = re; z.y = im; return z;
+}
+template <typename T> __host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) {
+    return cmake<T>(a.x + b.x, a.y + b.y);
+}
+template <typename T> __host__ __device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) {
+    return cmake<T>(a.x - b.x, a.y - b.y);
+}
+template <typename T> __host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return cmake<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T> __host__ __device__ inline cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+    return cmake<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T> __host__ __device__ inline cplx<T> cscale(cplx<T> a, T s) {
+    return cmake<T>(a.x * s, a.y * s);
+}
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+struct Fail {
+    pw_status st;
+};
+
+#define PW_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::pw::set_error("%s:%d: %s -> %s", __FILE__, __LINE__, #call,                  \
+                            hipGetErrorString(e_));                                       \
+            throw ::pw::Fail{PW_EHIP};                                                    \
+        }                                                                                 \
+    } while (0)
+
+#define PW_CHECK(cond, status, ...)                                                       \
+    do {                                                                                  \
+        if (!(cond)) {                                                                    \
+            ::pw::set_error(__VA_ARGS__);                                                 \
+            throw ::pw::Fail{status};                                                     \
+        }                                                                                 \
+    } while (0)
+
+#define PW_LAUNCH_CHECK() PW_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// FFT plans
+// ---------------------------------------------------------------------------
+constexpr int kMaxStages = 12;
+struct FftPlan {
+    int n;
+    int nstages;
+    int radix[kMaxStages];
+};
+FftPlan make_plan(int n);   // factor n into radices 8, 4, 2, 3, 5
+
+// ---------------------------------------------------------------------------
+// basis (host)
+// ---------------------------------------------------------------------------
+struct Basis {
+    int npw = 0;
+    std::vector<int32_t> miller;     // [npw][3]
+    std::vector<double> kin;         // [npw]
+    // z-columns: runs of consecutive n2 at fixed (n0, n1), in coefficient order
+    int ncols = 0;
+    std::vector<int32_t> col_start;  // [ncols + 1]
+    std::vector<int32_t> col_i0;     // n0 mod N0
+    std::vector<int32_t> col_i1;     // n1 mod N1
+    std::vector<int32_t> col_n2lo;   // first n2 of the run
+    std::vector<int32_t> shell;      // [npw]
+    std::vector<double> shell_t;     // [nshell]
+    int n0min = 0, n0max = 0;
+};
+void enumerate_miller(const pw_cell &c, std::vector<int32_t> &miller);
+Basis build_basis(const pw_cell &c);
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { free_(); }
+    void alloc(size_t b);
+    void free_();
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+struct Solver;   // folded-CG workspace (solver.cpp)
+
+// optional per-stage timing with HIP events on the launch stream
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace pw
+
+struct pw_ctx {
+    pw_cell cell;
+    pw::Basis basis;
+    int max_bands = 0;
+    int flags = 0;
+    int natom = 0, nl = 0, nproj = 0;
+    std::vector<double> dproj;       // host copy [nproj]
+    int device = 0;
+    int64_t device_bytes = 0;
+    pw::FftPlan plan[3];
+    int cb = 16;                     // z-columns per workgroup in the z passes
+    // device tables
+    pw::DevBuf d_kin, d_zmap, d_colpos, d_colstart, d_vz64, d_vz32, d_tw64[3], d_tw32[3];
+    pw::DevBuf d_beta64, d_beta_bf16, d_dproj, d_dproj32, d_shell;
+    int64_t ldb16 = 0;               // row length of the BF16 projector planes
+    // hpsi workspace
+    pw::DevBuf d_cols;               // [max_bands][N2][ncols] complex128 (reused for c64)
+    pw::DevBuf d_proj;               // projections [nproj][max_bands] complex128
+    pw::DevBuf d_partial;            // split-K partial sums
+    pw::DevBuf d_ortho_ws, d_ortho_small;   // pw_orthonormalize scratch
+    pw::Solver *solver = nullptr;
+    // profiling (pw_profile_begin / pw_profile_end)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<pw::ProfRec> prof_rec;
+    size_t prof_next = 0;
+};
+
+namespace pw {
+// Records a pair of events around a launch sequence when profiling is on.
+struct ProfScope {
+    pw_ctx *c;
+    hipStream_t st;
+    hipEvent_t b = nullptr;
+    ProfScope(pw_ctx *ctx, int kind, hipStream_t s) : c(ctx), st(s) {
+        if (c->prof_on && c->prof_next + 2 <= c->prof_pool.size() && c->prof_rec.size() < c->prof_rec.capacity()) {
+            hipEvent_t a = c->prof_pool[c->prof_next++];
+            b = c->prof_pool[c->prof_next++];
+            c->prof_rec.push_back(ProfRec{kind, a, b});
+            (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (b) (void)hipEventRecord(b, st);
+    }
+};
+}  // namespace pw

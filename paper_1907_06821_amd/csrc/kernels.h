@@ -1,0 +1,73 @@
+// Host-side launchers of the libpw kernels (declarations).
+#pragma once
+#include "common.h"
+
+namespace pw {
+
+// fft.hip
+template <typename T> void launch_zinv(pw_ctx *, int nb, const void *psi, int64_t ld, void *cols, hipStream_t);
+template <typename T>
+void launch_zfwd(pw_ctx *, int nb, const void *cols, const void *psi, int64_t ld, const double *kin, double shift,
+                 double scale, void *out, int64_t ldo, hipStream_t);
+template <typename T, int MODE> void launch_xy(pw_ctx *, int nb, void *cols, void *grid, hipStream_t);
+
+// gemm.hip (complex128)
+int nt_splits(int M, int N, int K);
+size_t nt_partial_bytes(int M, int N, int K);
+void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
+              double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
+              hipStream_t);
+void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
+                     double beta, void *Out, int64_t ldo, hipStream_t);
+
+// gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
+size_t cnt_partial_bytes(int M, int N, int K);
+void proj_bf16(int nproj, int nb, int npw, const void *beta_bf16, const void *psi, int64_t ld, const float *d,
+               void *projT, void *partial, hipStream_t);
+void backproj_bf16(int nb, int npw, int nproj, const void *projT, const void *beta_bf16, void *out, int64_t ldo,
+                   hipStream_t);
+
+// dense.hip
+void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t);
+void jacobi_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
+                 double ref, int *info, hipStream_t);
+
+// blas1.hip -------------------------------------------------------------------
+struct PrecArgs {
+    int kind;                 // 0 TPA^2, 1 paper M(G), 2 TPA^2 * exp(f[shell][band])
+    const double *kin;        // [npw]
+    const double *tband;      // [nb] band kinetic energies (TPA)
+    double e_ref, de2;        // M(G)
+    const float *ftab;        // [nshell][nb] learned log-scaling
+    const int32_t *shell;     // [npw]
+    int nb;
+};
+
+struct BandRed {              // scratch for two-stage band reductions
+    double *partial;          // [nq][nb][nsplit]
+    int nsplit;
+};
+int band_splits(int npw);
+
+void fill_zero(void *p, size_t bytes, hipStream_t);
+void copy_block(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t);
+void red_mu_tband(int nb, int npw, const void *Y, const void *X, int64_t ld, const double *kin, double *mu,
+                  double *tband, BandRed, hipStream_t);
+void red_grad(int nb, int npw, const void *X, const void *AX, void *Gold, void *Z, int64_t ld, const double *mu,
+              PrecArgs pa, double *gz, double *gzo, BandRed, hipStream_t);
+void red_gzold(int nb, int npw, const void *G, int64_t ld, PrecArgs pa, double *gz_old, BandRed, hipStream_t);
+void pupdate(int nb, int npw, const void *Z, void *P, int64_t ld, const double *gz, const double *gzo,
+             double *gz_old, hipStream_t);
+void red_line(int nb, int npw, const void *Y, const void *YP, const void *P, int64_t ld, double *out4,
+              BandRed, hipStream_t);
+void line_coef(int nb, const double *mu, const double *line4, double *coef, hipStream_t);
+void combine3(int nb, int npw, void *X, void *Y, void *AX, const void *P, const void *YP, const void *AP,
+              int64_t ld, const double *coef, hipStream_t);
+void red_resid(int nb, int npw, const void *Y, const void *X, int64_t ld, const double *w, double *res,
+               BandRed, hipStream_t);
+void band_norms(int nb, int npw, const void *X, int64_t ld, double *out, BandRed, hipStream_t);
+void c64_to_c128(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t);
+void c128_to_c64(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t);
+void nan_check(size_t n, const double *x, int *flag, hipStream_t);
+
+}  // namespace pw

@@ -1,0 +1,312 @@
+// Folded-spectrum preconditioned CG driver (host control, all arithmetic on the GPU).
+//
+// Finds the nb eigenpairs of H nearest E by minimising tr(Psi^H A Psi), A = (H - E)^2,
+// over orthonormal Psi: the folded operator and its positivity are the paper's folded
+// equation (Sec. II.B), the CG functional is the paper's F with the eigenvector in place
+// of the scattering source (Sec. II.B), the G-diagonal preconditioner is M(G) of Sec.
+// II.B (or the folded Teter-Payne-Allan form), and convergence is the eigen-residual
+// Delta_i = ||H psi_i - theta_i psi_i|| of Sec. II.B.
+//
+// One iteration (band-major blocks [nb][npw], Y = (H - E) X, AX = (H - E) Y):
+//   mu = ||Y||^2, T_i            -> G = AX - mu X, Z = K o G, Polak-Ribiere P
+//   P -= X (X^H P)               -> YP = (H - E) P, AP = (H - E) YP   (two H psi)
+//   per-band exact 2x2 minimum   -> X, Y, AX updated together
+//   S = X^H X = L L^H            -> X, Y, AX <- conj(L^-1) . (X, Y, AX)
+// Every check_every iterations: Y and AX recomputed from X, Rayleigh-Ritz in A
+// (bands ordered by folded value, directions turned with them), and the residuals
+// Delta_i of a Rayleigh-Ritz in H taken on copies; the host syncs only here.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <utility>
+
+#include "kernels.h"
+
+namespace pw {
+
+void hpsi_any(pw_ctx *ctx, pw_dtype dt, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
+              hipStream_t st);
+
+struct Solver {
+    int nbmax = 0, npw = 0;
+    DevBuf X, Y, AX, P, YP, AP, G, Z, T1, T2, T3;
+    DevBuf P32, Q32, R32;          // complex64 staging for mixed-precision H psi
+    DevBuf small;                  // N x N work matrices
+    DevBuf vec;                    // per-band vectors
+    DevBuf red;                    // reduction partials
+    DevBuf status;                 // ints
+    int nsplit = 0;
+};
+
+void solver_destroy(Solver *s) { delete s; }
+
+static Solver *solver_get(pw_ctx *ctx, int nb, bool mixed) {
+    Solver *s = ctx->solver;
+    const int npw = ctx->basis.npw;
+    if (!s || s->nbmax < nb) {
+        delete s;
+        ctx->solver = nullptr;
+        s = new Solver();
+        s->nbmax = ctx->max_bands;
+        s->npw = npw;
+        const size_t blk = (size_t)s->nbmax * npw * 16;
+        DevBuf *blocks[] = {&s->X, &s->Y, &s->AX, &s->P, &s->YP, &s->AP, &s->G, &s->Z, &s->T1, &s->T2, &s->T3};
+        for (DevBuf *d : blocks) d->alloc(blk);
+        const size_t nn = (size_t)s->nbmax * s->nbmax * 16;
+        s->small.alloc(6 * nn);
+        s->vec.alloc((size_t)s->nbmax * 8 * 24);
+        s->nsplit = band_splits(npw);
+        s->red.alloc((size_t)4 * s->nbmax * s->nsplit * 8);
+        s->status.alloc(256);
+        ctx->solver = s;
+        ctx->device_bytes += (int64_t)(11 * blk + 6 * nn + s->vec.bytes + s->red.bytes + 256);
+    }
+    if (mixed && !s->P32.p) {
+        const size_t blk32 = (size_t)s->nbmax * npw * 8;
+        s->P32.alloc(blk32);
+        s->Q32.alloc(blk32);
+        s->R32.alloc(blk32);
+        ctx->device_bytes += (int64_t)(3 * blk32);
+    }
+    return s;
+}
+
+pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double *eig, double *resid,
+                    const pw_cg_opts &o, pw_cg_stats *stats, hipStream_t st) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int npw = ctx->basis.npw;
+    const bool mixed = o.precision == 1;
+    Solver *s = solver_get(ctx, nb, mixed);
+    const int64_t L = npw;   // internal leading dimension
+    void *X = s->X.p, *Y = s->Y.p, *AX = s->AX.p, *P = s->P.p, *YP = s->YP.p, *AP = s->AP.p;
+    void *G = s->G.p, *Z = s->Z.p, *T1 = s->T1.p, *T2 = s->T2.p, *T3 = s->T3.p;
+    const size_t nn = (size_t)nb * nb;
+    double2 *Sm = (double2 *)s->small.p, *Wm = Sm + nn, *Tm = Wm + nn, *Rm = Tm + nn, *Aw = Rm + nn, *Vw = Aw + nn;
+    double *v = (double *)s->vec.p;
+    double *mu = v, *tband = v + nb, *gz = v + 2 * nb, *gzo = v + 3 * nb, *gz_old = v + 4 * nb;
+    double *line4 = v + 5 * nb, *coef = v + 9 * nb, *lam = v + 13 * nb, *res = v + 14 * nb;
+    int *d_status = (int *)s->status.p;
+    BandRed br{(double *)s->red.p, s->nsplit};
+    int64_t n_hpsi = 0;
+    bool use_mixed = mixed;
+
+    PrecArgs pa{};
+    pa.kind = o.precond == 1 ? 1 : 0;
+    pa.kin = ctx->d_kin.as<double>();
+    pa.tband = tband;
+    pa.e_ref = E;
+    pa.de2 = o.delta_e * o.delta_e;
+    pa.shell = ctx->d_shell.as<int32_t>();
+    pa.nb = nb;
+
+    auto fold = [&](void *in, void *y, void *ay, bool low) {
+        if (low) {
+            c128_to_c64(nb, npw, in, L, s->P32.p, L, st);
+            hpsi_any(ctx, PW_C64, nb, s->P32.p, L, s->Q32.p, L, E, st);
+            hpsi_any(ctx, PW_C64, nb, s->Q32.p, L, s->R32.p, L, E, st);
+            c64_to_c128(nb, npw, s->Q32.p, L, y, L, st);
+            c64_to_c128(nb, npw, s->R32.p, L, ay, L, st);
+        } else {
+            hpsi_any(ctx, PW_C128, nb, in, L, y, L, E, st);
+            hpsi_any(ctx, PW_C128, nb, y, L, ay, L, E, st);
+        }
+        n_hpsi += 2 * nb;
+    };
+    auto rotate = [&](const double2 *M, void *&blk, void *&tmp) {
+        zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st);
+        std::swap(blk, tmp);
+    };
+    auto orth = [&]() {
+        zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
+        rotate(Tm, X, T1);
+        rotate(Tm, Y, T2);
+        rotate(Tm, AX, T3);
+    };
+    // Rayleigh-Ritz in A = (H - E)^2 on the iterate (Y, AX exact): Ritz values of
+    // Y^H Y ascending; the search directions and gradients turn with the bands.
+    auto a_rr = [&](bool rotate_dirs) {
+        zgemm_nt(nb, nb, npw, true, Y, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        jacobi_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
+        rotate(Rm, X, T1);
+        rotate(Rm, Y, T2);
+        rotate(Rm, AX, T3);
+        if (rotate_dirs) {
+            rotate(Rm, P, T1);
+            rotate(Rm, G, T2);
+        }
+    };
+    // Rayleigh-Ritz in H on copies of the block: lam = theta - E ascending and the
+    // residuals Delta_i of the H-Ritz vectors (the iterate itself is left alone)
+    auto h_resid = [&]() {
+        zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        jacobi_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
+        zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st);
+        zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st);
+        red_resid(nb, npw, T2, T1, L, lam, res, br, st);
+    };
+
+    fill_zero(s->status.p, 256, st);
+    copy_block(nb, npw, psi, ld, X, L, st);
+    fill_zero(P, (size_t)nb * npw * 16, st);
+    fill_zero(G, (size_t)nb * npw * 16, st);
+    fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
+    // initial orthonormalisation (Y, AX are garbage here but get overwritten)
+    zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+    chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
+    rotate(Tm, X, T1);
+    fold(X, Y, AX, false);
+    a_rr(false);
+    fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
+
+    std::vector<double> h_lam(nb), h_res(nb);
+    int h_status[8];
+    int it = 0;
+    bool converged = false;
+    double best = INFINITY;
+    int stall = 0;
+    int nhist = 0;
+    const int check = std::max(1, o.check_every);
+    pw_status result = PW_OK;
+    for (it = 1; it <= o.maxit; ++it) {
+        red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
+        red_grad(nb, npw, X, AX, G, Z, L, mu, pa, gz, gzo, br, st);
+        pupdate(nb, npw, Z, P, L, gz, gzo, gz_old, st);
+        // P -= X (X^H P): W[b][j] = -<x_j|p_b>
+        zgemm_nt(nb, nb, npw, true, X, L, P, L, -1.0, nullptr, 0.0, Wm, nb, true, ctx->d_partial.p, st);
+        zgemm_nn_launch(nb, npw, nb, Wm, nb, X, L, 1.0, 1.0, P, L, st);
+        fold(P, YP, AP, use_mixed);
+        red_line(nb, npw, Y, YP, P, L, line4, br, st);
+        line_coef(nb, mu, line4, coef, st);
+        combine3(nb, npw, X, Y, AX, P, YP, AP, L, coef, st);
+        orth();
+        if (it % check == 0 || it == o.maxit) {
+            fold(X, Y, AX, false);
+            a_rr(true);
+            h_resid();
+            // PR denominator for the rotated gradients
+            red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
+            red_gzold(nb, npw, G, L, pa, gz_old, br, st);
+            PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
+            PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
+            PW_HIP(hipMemcpyAsync(h_status, d_status, sizeof h_status, hipMemcpyDeviceToHost, st));
+            PW_HIP(hipStreamSynchronize(st));
+            if (h_status[0]) {
+                set_error("Gram matrix lost positive definiteness (pivot %d) before iteration %d", h_status[0] - 1, it);
+                result = PW_ENOTPD;
+                break;
+            }
+            double mx = 0.0;
+            bool finite = true;
+            for (int b = 0; b < nb; ++b) {
+                if (!std::isfinite(h_res[b]) || !std::isfinite(h_lam[b])) finite = false;
+                mx = std::max(mx, h_res[b]);
+            }
+            if (!finite) {
+                set_error("non-finite residual at iteration %d", it);
+                result = PW_ENAN;
+                break;
+            }
+            if (stats && stats->hist && nhist < stats->n_hist) {
+                stats->hist[2 * nhist] = it;
+                stats->hist[2 * nhist + 1] = mx;
+                ++nhist;
+            }
+            if (o.verbose) fprintf(stderr, "[pw] it %6d  max resid %.3e%s\n", it, mx, use_mixed ? "  (mixed)" : "");
+            if (mx <= o.tol) {
+                converged = true;
+                break;
+            }
+            // precision ladder: leave the low-precision operator once it stops helping
+            if (use_mixed) {
+                if (mx < 0.7 * best) { best = mx; stall = 0; }
+                else if (++stall >= 2) use_mixed = false;
+                if (mx < 1e-4) use_mixed = false;
+            }
+        }
+    }
+    if (it > o.maxit) it = o.maxit;
+    // final Rayleigh-Ritz in H, ascending energies, FP64 residuals
+    if (result == PW_OK || result == PW_ENOCONV) {
+        hpsi_any(ctx, PW_C128, nb, X, L, Y, L, E, st);
+        n_hpsi += nb;
+        zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        jacobi_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
+        rotate(Rm, X, T1);
+        rotate(Rm, Y, T2);
+        red_resid(nb, npw, Y, X, L, lam, res, br, st);
+        copy_block(nb, npw, X, L, psi, ld, st);
+        PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
+        PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
+        PW_HIP(hipStreamSynchronize(st));
+        double mx = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            if (eig) eig[b] = h_lam[b] + E;
+            if (resid) resid[b] = h_res[b];
+            mx = std::max(mx, h_res[b]);
+        }
+        if (!converged) {
+            converged = mx <= o.tol;
+            if (!converged) {
+                set_error("folded CG did not reach tol %.3e in %d iterations (max residual %.3e)", o.tol, o.maxit, mx);
+                result = PW_ENOCONV;
+            }
+        }
+        if (stats) stats->max_resid = mx;
+    }
+    // the solver's scratch blocks may have been swapped: keep them in the struct
+    s->X.p = X; s->Y.p = Y; s->AX.p = AX; s->P.p = P; s->YP.p = YP; s->AP.p = AP;
+    s->G.p = G; s->Z.p = Z; s->T1.p = T1; s->T2.p = T2; s->T3.p = T3;
+    if (stats) {
+        stats->iters = it;
+        stats->converged = converged ? 1 : 0;
+        stats->n_hpsi = n_hpsi;
+        stats->n_hist = nhist;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return result;
+}
+
+}  // namespace pw
+
+extern "C" {
+
+void pw_cg_opts_default(pw_cg_opts *o) {
+    if (!o) return;
+    o->tol = 1e-6;
+    o->maxit = 20000;
+    o->precond = 0;
+    o->delta_e = 1.0;
+    o->precision = 0;
+    o->check_every = 20;
+    o->verbose = 0;
+}
+
+pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld, double *eig,
+                             double *resid, const pw_cg_opts *opts, pw_cg_stats *stats, void *stream) {
+    try {
+        PW_CHECK(ctx && psi, PW_EINVAL, "null argument");
+        PW_CHECK(ctx->flags & PW_PREP_C128, PW_EUNSUPPORTED, "the solver needs a complex128 context");
+        PW_CHECK(nb >= 1 && nb <= ctx->max_bands && nb <= 1024, PW_EINVAL, "nb %d must be in [1, min(max_bands, 1024)]",
+                 nb);
+        PW_CHECK(nb <= ctx->basis.npw, PW_EINVAL, "more bands than plane waves");
+        PW_CHECK(ld >= ctx->basis.npw, PW_EINVAL, "ld < npw");
+        PW_CHECK(std::isfinite(e_ref), PW_ENAN, "non-finite e_ref");
+        pw_cg_opts o;
+        pw_cg_opts_default(&o);
+        if (opts) o = *opts;
+        PW_CHECK(o.tol > 0 && o.maxit >= 1 && o.check_every >= 1, PW_EINVAL, "bad solver options");
+        PW_CHECK(o.precond == 0 || o.precond == 1, PW_EUNSUPPORTED, "preconditioner %d not available", o.precond);
+        PW_CHECK(o.precision == 0 || o.precision == 1, PW_EINVAL, "precision must be 0 or 1");
+        if (o.precision == 1)
+            PW_CHECK(ctx->flags & PW_PREP_C64, PW_EUNSUPPORTED, "mixed precision needs PW_PREP_C64");
+        return pw::folded_cg(ctx, e_ref, nb, psi, ld, eig, resid, o, stats, (hipStream_t)stream);
+    } catch (const pw::Fail &f) {
+        return f.st;
+    } catch (...) {
+        pw::set_error("unexpected exception in pw_folded_cg_solve");
+        return PW_EINVAL;
+    }
+}
+
+}  // extern "C"
