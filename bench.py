@@ -95,7 +95,7 @@ def main():
     ctx = pw.Context.from_problem(prob, max_bands=prob.nbands, flags=flags)
     nb = prob.nbands
     psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
-    opts = dict(tol=1e-30, check_every=10 ** 6, precision=1 if mixed else 0)
+    opts = dict(tol=1e-30, check_every=20, precision=1 if mixed else 0)
 
     # warm-up (also allocates the solver workspace)
     psi = psi0.clone()

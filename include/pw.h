@@ -142,6 +142,22 @@ pw_status pw_grid_to_wave(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *g
  * PW_ENOTPD (synchronising) if a Cholesky pivot is not positive. */
 pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void *stream);
 
+/* Small dense FP64 kernels of the block algebra, exposed for direct use and
+ * testing (one workgroup each, n <= 1024; device pointers, complex128, row-major).
+ *
+ * pw_dense_eigh: eigen-decomposition of the Hermitian part of A (n x n, ld lda)
+ *   by cyclic Jacobi: w (device, n) eigenvalues ordered by key (0: ascending,
+ *   1: ascending |w - ref|), R (device, n x n) with row b the eigenvector of w[b]
+ *   in the input basis (so a band-major block rotates as Psi' = R . Psi).
+ *   sweeps (host, optional) receives the number of Jacobi sweeps.  Synchronises.
+ * pw_dense_chol_inv: S = L L^H for Hermitian positive definite S (n x n, lds),
+ *   T = conj(L^{-1}) (n x n) so that Psi' = T . Psi has Psi'^H Psi' = I when
+ *   S = Psi^H Psi.  Returns PW_ENOTPD if a pivot is not positive.  Synchronises.
+ * Both are the Rayleigh-Ritz and Gram/Cholesky steps of the solver. */
+pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *R, int32_t key, double ref,
+                        int32_t *sweeps, void *stream);
+pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void *stream);
+
 /* Solver options. */
 typedef struct {
     double tol;           /* stop when max_i Delta_i <= tol (Ha); paper's accuracy 1e-6 */

@@ -26,7 +26,8 @@ _STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EHIP", -4
 # names declared in include/pw.h (checked by the test-suite against the library's exports)
 EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy", "pw_ctx_get_info",
            "pw_ctx_kinetic", "pw_ctx_shells", "pw_hpsi", "pw_wave_to_grid", "pw_grid_to_wave",
-           "pw_orthonormalize", "pw_cg_opts_default", "pw_folded_cg_solve", "pw_profile_begin",
+           "pw_orthonormalize", "pw_cg_opts_default", "pw_folded_cg_solve", "pw_dense_eigh",
+           "pw_dense_chol_inv", "pw_profile_begin",
            "pw_profile_end", "pw_last_error")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
 PW_PROF_NKINDS = 8
@@ -88,6 +89,8 @@ def lib():
             "pw_orthonormalize": [vp, i32, vp, i64, vp],
             "pw_folded_cg_solve": [vp, dbl, i32, vp, i64, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(pw_cg_opts),
                                    C.POINTER(pw_cg_stats), vp],
+            "pw_dense_eigh": [i32, vp, i64, vp, vp, i32, dbl, C.POINTER(i32), vp],
+            "pw_dense_chol_inv": [i32, vp, i64, vp, vp],
             "pw_profile_begin": [vp, i32],
             "pw_profile_end": [vp, C.POINTER(dbl), C.POINTER(i64)],
         }
@@ -259,6 +262,33 @@ def orthonormalize(ctx, psi, stream=None):
     _check(ctx._lib.pw_orthonormalize(ctx.handle, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
                                       _stream_ptr(stream)))
     return psi
+
+
+def dense_eigh(a, key=0, ref=0.0, stream=None):
+    """Hermitian eigensolver on a [n, n] complex128 device matrix: (w, R, sweeps),
+    rows of R are eigenvectors (w ordered by key: 0 ascending, 1 by |w - ref|)."""
+    import torch
+    n = a.shape[0]
+    if a.dtype != torch.complex128 or not a.is_cuda or a.shape != (n, n) or a.stride(1) != 1:
+        raise ValueError("expected a row-contiguous [n, n] complex128 CUDA tensor")
+    w = torch.empty(n, dtype=torch.float64, device=a.device)
+    r = torch.empty((n, n), dtype=torch.complex128, device=a.device)
+    sw = C.c_int32()
+    _check(lib().pw_dense_eigh(n, C.c_void_p(a.data_ptr()), a.stride(0), C.c_void_p(w.data_ptr()),
+                               C.c_void_p(r.data_ptr()), int(key), float(ref), C.byref(sw), _stream_ptr(stream)))
+    return w, r, sw.value
+
+
+def dense_chol_inv(s, stream=None):
+    """T = conj(L^{-1}) with s = L L^H (complex128 device matrix)."""
+    import torch
+    n = s.shape[0]
+    if s.dtype != torch.complex128 or not s.is_cuda or s.shape != (n, n) or s.stride(1) != 1:
+        raise ValueError("expected a row-contiguous [n, n] complex128 CUDA tensor")
+    t = torch.empty((n, n), dtype=torch.complex128, device=s.device)
+    _check(lib().pw_dense_chol_inv(n, C.c_void_p(s.data_ptr()), s.stride(0), C.c_void_p(t.data_ptr()),
+                                   _stream_ptr(stream)))
+    return t
 
 
 def profile_begin(ctx, max_records=100000):

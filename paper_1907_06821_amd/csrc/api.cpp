@@ -376,6 +376,39 @@ pw_status pw_grid_to_wave(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *g
     PW_API_END
 }
 
+pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *R, int32_t key, double ref,
+                        int32_t *sweeps, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(n >= 1 && n <= 1024 && lda >= n && A && w && R, PW_EINVAL, "bad pw_dense_eigh arguments");
+    PW_CHECK(key == 0 || key == 1, PW_EINVAL, "key must be 0 or 1");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf work;
+    work.alloc((size_t)2 * n * n * 16 + 256);
+    int *info = (int *)((char *)work.p + (size_t)2 * n * n * 16);
+    jacobi_eigh(n, A, lda, work.p, (char *)work.p + (size_t)n * n * 16, w, R, key, ref, info, st);
+    int h = 0;
+    PW_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    if (sweeps) *sweeps = h;
+    PW_API_END
+}
+
+pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(n >= 1 && n <= 1024 && lds >= n && S && T, PW_EINVAL, "bad pw_dense_chol_inv arguments");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf work;
+    work.alloc((size_t)n * n * 16 + 256);
+    int *status = (int *)((char *)work.p + (size_t)n * n * 16);
+    fill_zero(status, 16, st);
+    chol_inv(n, S, lds, work.p, T, status, st);
+    int h = 0;
+    PW_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    PW_CHECK(h == 0, PW_ENOTPD, "matrix not positive definite at pivot %d", h - 1);
+    PW_API_END
+}
+
 pw_status pw_profile_begin(pw_ctx *ctx, int32_t max_records) {
     PW_API_BEGIN
     PW_CHECK(ctx && max_records >= 1 && max_records <= (1 << 22), PW_EINVAL, "bad profile arguments");

@@ -1,205 +1,20 @@
-// Sphere <-> grid 3D FFT of the H psi path, staged in LDS, for gfx950.
-//
-// The local potential is applied as FFT^-1 (V(r) . FFT psi): coefficients on the
-// cutoff sphere go to real space with exp(+iG.r), are multiplied by V(r_j) and
-// come back with (1/N) exp(-iG.r).  The transform is split in two kinds of pass so
-// that only the z-columns that touch the sphere are ever moved through HBM:
+// Sphere <-> grid 3D FFT passes of the H psi path (gfx950).
 //
 //   z pass (inverse):  sphere coefficients of CB columns -> LDS -> length-N2 FFTs
 //                      -> column grid cols[b][z][c]          (c over touched columns)
 //   xy pass:           one (band, z) plane: scatter its columns into an N0 x N1 LDS
-//                      plane, 2D inverse FFT, multiply by V(., ., z), 2D forward FFT,
-//                      gather the columns back (in place)
-//   z pass (forward):  column grid -> LDS -> FFTs -> (1/N) . gather onto the sphere,
-//                      fused with the kinetic term (T_G - shift) c(G)
-//
-// Every 1D transform is a mixed-radix (8, 4, 2, 3, 5) Stockham FFT on LDS data: a
-// thread loads its butterflies' inputs into registers, all threads synchronise,
-// then write the outputs, so one LDS buffer suffices.  Twiddles exp(-2 pi i t/n)
-// come from a table computed on the host in extended precision.
-#include "common.h"
+//                      plane, 2D inverse FFT (y only on the x rows the sphere
+//                      touches), multiply by V(., ., z), 2D forward FFT, gather
+//                      the columns back in place
+//   z pass (forward):  column grid -> LDS -> FFTs -> (1/N) . gather onto the
+//                      sphere, fused with the kinetic term (T_G - shift) c(G)
+// Only the z-columns that touch the sphere travel through HBM.  Common grid
+// lengths are compiled with their radices built in (CtLen); other lengths use the
+// run-time plan (RtLen).
+#include "fft_core.h"
 
 namespace pw {
 
-// ---------------------------------------------------------------------------
-// small DFTs on registers; sign = -1 forward, +1 inverse
-// ---------------------------------------------------------------------------
-template <typename T> __device__ inline cplx<T> mul_si(cplx<T> a, int sign) {
-    // a * (sign * i)
-    return sign > 0 ? cmake<T>(-a.y, a.x) : cmake<T>(a.y, -a.x);
-}
-
-template <typename T, int R> struct Dft;
-
-template <typename T> struct Dft<T, 2> {
-    __device__ static inline void run(cplx<T> *v, int) {
-        cplx<T> a = v[0], b = v[1];
-        v[0] = cadd<T>(a, b);
-        v[1] = csub<T>(a, b);
-    }
-};
-
-template <typename T> struct Dft<T, 4> {
-    __device__ static inline void run(cplx<T> *v, int s) {
-        cplx<T> t0 = cadd<T>(v[0], v[2]), t1 = csub<T>(v[0], v[2]);
-        cplx<T> t2 = cadd<T>(v[1], v[3]), t3 = mul_si<T>(csub<T>(v[1], v[3]), s);
-        v[0] = cadd<T>(t0, t2);
-        v[2] = csub<T>(t0, t2);
-        v[1] = cadd<T>(t1, t3);
-        v[3] = csub<T>(t1, t3);
-    }
-};
-
-template <typename T> struct Dft<T, 8> {
-    __device__ static inline void run(cplx<T> *v, int s) {
-        const T h = (T)0.70710678118654752440084436210485;
-        cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
-        cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<T, 4>::run(e, s);
-        Dft<T, 4>::run(o, s);
-        // w8^k = exp(s * 2 pi i k / 8)
-        cplx<T> w1 = cmake<T>(h, s * h), w3 = cmake<T>(-h, s * h);
-        cplx<T> o1 = cmul<T>(o[1], w1), o2 = mul_si<T>(o[2], s), o3 = cmul<T>(o[3], w3);
-        v[0] = cadd<T>(e[0], o[0]);
-        v[4] = csub<T>(e[0], o[0]);
-        v[1] = cadd<T>(e[1], o1);
-        v[5] = csub<T>(e[1], o1);
-        v[2] = cadd<T>(e[2], o2);
-        v[6] = csub<T>(e[2], o2);
-        v[3] = cadd<T>(e[3], o3);
-        v[7] = csub<T>(e[3], o3);
-    }
-};
-
-template <typename T> struct Dft<T, 3> {
-    __device__ static inline void run(cplx<T> *v, int s) {
-        const T c = (T)-0.5, sn = (T)0.86602540378443864676372317075294;
-        cplx<T> t = cadd<T>(v[1], v[2]);
-        cplx<T> d = mul_si<T>(cscale<T>(csub<T>(v[1], v[2]), sn), s);
-        cplx<T> m = cadd<T>(v[0], cscale<T>(t, c));
-        v[0] = cadd<T>(v[0], t);
-        v[1] = cadd<T>(m, d);
-        v[2] = csub<T>(m, d);
-    }
-};
-
-template <typename T> struct Dft<T, 5> {
-    __device__ static inline void run(cplx<T> *v, int s) {
-        const T c1 = (T)0.30901699437494742410229341718282;    // cos(2 pi/5)
-        const T c2 = (T)-0.80901699437494742410229341718282;   // cos(4 pi/5)
-        const T s1 = (T)0.95105651629515357211643933337938;    // sin(2 pi/5)
-        const T s2 = (T)0.58778525229247312916870595463907;    // sin(4 pi/5)
-        cplx<T> t1 = cadd<T>(v[1], v[4]), t2 = cadd<T>(v[2], v[3]);
-        cplx<T> t3 = csub<T>(v[1], v[4]), t4 = csub<T>(v[2], v[3]);
-        cplx<T> a = cadd<T>(v[0], cadd<T>(cscale<T>(t1, c1), cscale<T>(t2, c2)));
-        cplx<T> b = cadd<T>(v[0], cadd<T>(cscale<T>(t1, c2), cscale<T>(t2, c1)));
-        cplx<T> p = mul_si<T>(cadd<T>(cscale<T>(t3, s1), cscale<T>(t4, s2)), s);
-        cplx<T> q = mul_si<T>(csub<T>(cscale<T>(t3, s2), cscale<T>(t4, s1)), s);
-        v[0] = cadd<T>(v[0], cadd<T>(t1, t2));
-        v[1] = cadd<T>(a, p);
-        v[4] = csub<T>(a, p);
-        v[2] = cadd<T>(b, q);
-        v[3] = csub<T>(b, q);
-    }
-};
-
-// ---------------------------------------------------------------------------
-// one Stockham stage on LDS data.
-// howmany transforms of length n; element e of transform f sits at
-// buf[((f + f0) % fmod) * ds + e * es].  Ns = product of earlier radices.
-// ---------------------------------------------------------------------------
-struct FftGeom {
-    int n, howmany, es, ds, f0, fmod;
-};
-
-template <typename T, int R, int NIT, int NTHR>
-__device__ inline void fft_stage(cplx<T> *buf, const FftGeom &g, int Ns, const cplx<T> *tw, int sign) {
-    const int nbf = g.n / R;
-    const int total = g.howmany * nbf;
-    const int tws = g.n / (Ns * R);
-    const int tid = threadIdx.x;
-    cplx<T> v[NIT][R];
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int idx = tid + it * NTHR;
-        if (idx < total) {
-            int f, j;
-            if (g.es == 1) { f = idx / nbf; j = idx - f * nbf; }
-            else { j = idx / g.howmany; f = idx - j * g.howmany; }
-            int row = f + g.f0;
-            if (row >= g.fmod) row -= g.fmod;
-            const cplx<T> *src = buf + row * g.ds;
-            const int k = j % Ns;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = src[(j + r * nbf) * g.es];
-            if (Ns > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cplx<T> w = tw[k * r * tws];
-                    if (sign > 0) w.y = -w.y;
-                    v[it][r] = cmul<T>(v[it][r], w);
-                }
-            }
-            Dft<T, R>::run(v[it], sign);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int idx = tid + it * NTHR;
-        if (idx < total) {
-            int f, j;
-            if (g.es == 1) { f = idx / nbf; j = idx - f * nbf; }
-            else { j = idx / g.howmany; f = idx - j * g.howmany; }
-            int row = f + g.f0;
-            if (row >= g.fmod) row -= g.fmod;
-            cplx<T> *dst = buf + row * g.ds;
-            const int k = j % Ns;
-            const int o = (j / Ns) * Ns * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) dst[(o + r * Ns) * g.es] = v[it][r];
-        }
-    }
-    __syncthreads();
-}
-
-// registers per thread per stage: MAXV complex values
-template <typename T> struct FftRegs { static constexpr int MAXV = 16; };
-template <> struct FftRegs<float> { static constexpr int MAXV = 24; };
-
-template <typename T, int NTHR>
-__device__ void lds_fft(cplx<T> *buf, const FftPlan &plan, const FftGeom &g, const cplx<T> *tw, int sign) {
-    constexpr int MAXV = FftRegs<T>::MAXV;
-    int Ns = 1;
-    for (int s = 0; s < plan.nstages; ++s) {
-        const int R = plan.radix[s];
-        switch (R) {
-            case 8: fft_stage<T, 8, MAXV / 8, NTHR>(buf, g, Ns, tw, sign); break;
-            case 4: fft_stage<T, 4, MAXV / 4, NTHR>(buf, g, Ns, tw, sign); break;
-            case 2: fft_stage<T, 2, MAXV / 2, NTHR>(buf, g, Ns, tw, sign); break;
-            case 3: fft_stage<T, 3, MAXV / 3, NTHR>(buf, g, Ns, tw, sign); break;
-            case 5: fft_stage<T, 5, MAXV / 5, NTHR>(buf, g, Ns, tw, sign); break;
-            default: break;
-        }
-        Ns *= R;
-    }
-}
-
-// host check that every stage fits the per-thread register budget
-template <typename T> static bool fft_fits(const FftPlan &plan, int howmany, int nthr) {
-    constexpr int MAXV = FftRegs<T>::MAXV;
-    for (int s = 0; s < plan.nstages; ++s) {
-        const int R = plan.radix[s];
-        const long total = (long)howmany * (plan.n / R);
-        const long nit = (total + nthr - 1) / nthr;
-        if (nit > MAXV / R) return false;
-    }
-    return true;
-}
-
-// ---------------------------------------------------------------------------
-// kernel parameters
-// ---------------------------------------------------------------------------
 struct ZArgs {
     FftPlan plan;             // length N2
     int n2, ncols, cb, nb;
@@ -224,28 +39,29 @@ template <typename T> __device__ inline void load_tw(cplx<T> *dst, const cplx<T>
 // ---------------------------------------------------------------------------
 // z pass, inverse: sphere -> column grid
 // ---------------------------------------------------------------------------
-template <typename T, int NTHR>
+template <typename T, int NTHR, typename LZ>
 __global__ __launch_bounds__(NTHR) void zpass_inv(ZArgs a, const cplx<T> *__restrict__ psi, int64_t ld,
                                                   cplx<T> *__restrict__ cols) {
     extern __shared__ unsigned char smem_raw[];
+    const int n2 = LZ::N > 0 ? LZ::N : a.n2;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *buf = tw + a.n2;
+    cplx<T> *buf = tw + n2;
     const int cb = blockIdx.x, b = blockIdx.y;
     const int c0 = cb * a.cb;
     const int c1 = min(c0 + a.cb, a.ncols);
     const int nc = c1 - c0;
-    const int rs = a.n2 + 1;
-    load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw), a.n2);
+    const int rs = n2 + 1;
+    load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw), n2);
     for (int i = threadIdx.x; i < nc * rs; i += NTHR) buf[i] = cmake<T>(0, 0);
     __syncthreads();
     const int g0 = a.colstart[c0], g1 = a.colstart[c1];
     const cplx<T> *src = psi + (int64_t)b * ld;
     for (int g = g0 + threadIdx.x; g < g1; g += NTHR) buf[a.zmap[g]] = src[g];
     __syncthreads();
-    FftGeom geo{a.n2, nc, 1, rs, 0, nc};
-    lds_fft<T, NTHR>(buf, a.plan, geo, tw, +1);
-    cplx<T> *dst = cols + (int64_t)b * a.n2 * a.ncols + c0;
-    for (int e = threadIdx.x; e < nc * a.n2; e += NTHR) {
+    FftGeom geo{n2, nc, 1, rs, 0, nc};
+    LZ::template fft<T, NTHR, 0>(buf, a.plan, geo, tw, +1);
+    cplx<T> *dst = cols + (int64_t)b * n2 * a.ncols + c0;
+    for (int e = threadIdx.x; e < nc * n2; e += NTHR) {
         const int z = e / nc, ci = e - z * nc;
         dst[(int64_t)z * a.ncols + ci] = buf[ci * rs + z];
     }
@@ -255,28 +71,29 @@ __global__ __launch_bounds__(NTHR) void zpass_inv(ZArgs a, const cplx<T> *__rest
 // z pass, forward: column grid -> sphere, with (1/N) and the kinetic epilogue
 //   out[g] = scale * FFT(cols)[g] + (kin[g] - shift) * psi[g]   (kin may be null)
 // ---------------------------------------------------------------------------
-template <typename T, int NTHR>
+template <typename T, int NTHR, typename LZ>
 __global__ __launch_bounds__(NTHR) void zpass_fwd(ZArgs a, const cplx<T> *__restrict__ cols,
                                                   const cplx<T> *__restrict__ psi, int64_t ld,
                                                   const double *__restrict__ kin, double shift, double scale,
                                                   cplx<T> *__restrict__ out, int64_t ldo) {
     extern __shared__ unsigned char smem_raw[];
+    const int n2 = LZ::N > 0 ? LZ::N : a.n2;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *buf = tw + a.n2;
+    cplx<T> *buf = tw + n2;
     const int cb = blockIdx.x, b = blockIdx.y;
     const int c0 = cb * a.cb;
     const int c1 = min(c0 + a.cb, a.ncols);
     const int nc = c1 - c0;
-    const int rs = a.n2 + 1;
-    load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw), a.n2);
-    const cplx<T> *src = cols + (int64_t)b * a.n2 * a.ncols + c0;
-    for (int e = threadIdx.x; e < nc * a.n2; e += NTHR) {
+    const int rs = n2 + 1;
+    load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw), n2);
+    const cplx<T> *src = cols + (int64_t)b * n2 * a.ncols + c0;
+    for (int e = threadIdx.x; e < nc * n2; e += NTHR) {
         const int z = e / nc, ci = e - z * nc;
         buf[ci * rs + z] = src[(int64_t)z * a.ncols + ci];
     }
     __syncthreads();
-    FftGeom geo{a.n2, nc, 1, rs, 0, nc};
-    lds_fft<T, NTHR>(buf, a.plan, geo, tw, -1);
+    FftGeom geo{n2, nc, 1, rs, 0, nc};
+    LZ::template fft<T, NTHR, 0>(buf, a.plan, geo, tw, -1);
     const int g0 = a.colstart[c0], g1 = a.colstart[c1];
     cplx<T> *o = out + (int64_t)b * ldo;
     const T sc = (T)scale;
@@ -298,32 +115,33 @@ __global__ __launch_bounds__(NTHR) void zpass_fwd(ZArgs a, const cplx<T> *__rest
 //           MODE 1: columns -> plane -> grid out [b][x][y][z]
 //           MODE 2: grid in [b][x][y][z] -> plane -> columns
 // ---------------------------------------------------------------------------
-template <typename T, int NTHR, int MODE>
+template <typename T, int NTHR, int MODE, typename L0, typename L1>
 __global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ cols, cplx<T> *__restrict__ grid) {
     extern __shared__ unsigned char smem_raw[];
+    const int n0 = L0::N > 0 ? L0::N : a.n0;
+    const int n1 = L1::N > 0 ? L1::N : a.n1;
     cplx<T> *tw0 = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *tw1 = tw0 + a.n0;
-    cplx<T> *pl = tw1 + a.n1;
+    cplx<T> *tw1 = tw0 + n0;
+    cplx<T> *pl = tw1 + n1;
     const int z = blockIdx.x, b = blockIdx.y;
-    const int rs = a.n1 + 1;
-    const int64_t npl = (int64_t)a.n0 * a.n1;
-    load_tw<T>(tw0, reinterpret_cast<const cplx<T> *>(a.tw0), a.n0);
-    load_tw<T>(tw1, reinterpret_cast<const cplx<T> *>(a.tw1), a.n1);
+    const int rs = n1 + 1;
+    const int npl = n0 * n1;
+    load_tw<T>(tw0, reinterpret_cast<const cplx<T> *>(a.tw0), n0);
+    load_tw<T>(tw1, reinterpret_cast<const cplx<T> *>(a.tw1), n1);
     cplx<T> *crow = cols + ((int64_t)b * a.n2 + z) * a.ncols;
+    const FftGeom gy{n1, a.nrows, 1, rs, a.rowlo, n0};    // y transforms on the touched x rows
+    const FftGeom gx{n0, n1, rs, 1, 0, n1};                // x transforms on every y
     if (MODE != 2) {
-        for (int i = threadIdx.x; i < a.n0 * rs; i += NTHR) pl[i] = cmake<T>(0, 0);
+        for (int i = threadIdx.x; i < n0 * rs; i += NTHR) pl[i] = cmake<T>(0, 0);
         __syncthreads();
         for (int c = threadIdx.x; c < a.ncols; c += NTHR) pl[a.colpos[c]] = crow[c];
         __syncthreads();
-        // inverse along y on the rows that hold columns, then along x everywhere
-        FftGeom gy{a.n1, a.nrows, 1, rs, a.rowlo, a.n0};
-        lds_fft<T, NTHR>(pl, a.plan1, gy, tw1, +1);
-        FftGeom gx{a.n0, a.n1, rs, 1, 0, a.n1};
-        lds_fft<T, NTHR>(pl, a.plan0, gx, tw0, +1);
+        L1::template fft<T, NTHR, 0>(pl, a.plan1, gy, tw1, +1);
+        L0::template fft<T, NTHR, L1::N>(pl, a.plan0, gx, tw0, +1);
     } else {
         const cplx<T> *gin = grid + (int64_t)b * npl * a.n2;
         for (int i = threadIdx.x; i < npl; i += NTHR) {
-            const int x = i / a.n1, y = i - x * a.n1;
+            const int x = i / n1, y = i - x * n1;
             pl[x * rs + y] = gin[(int64_t)i * a.n2 + z];
         }
         __syncthreads();
@@ -331,31 +149,26 @@ __global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ 
     if (MODE == 1) {
         cplx<T> *gout = grid + (int64_t)b * npl * a.n2;
         for (int i = threadIdx.x; i < npl; i += NTHR) {
-            const int x = i / a.n1, y = i - x * a.n1;
+            const int x = i / n1, y = i - x * n1;
             gout[(int64_t)i * a.n2 + z] = pl[x * rs + y];
         }
         return;
     }
     if (MODE == 0) {
-        const double *vz = reinterpret_cast<const double *>(a.vz);
         const T *vzt = reinterpret_cast<const T *>(a.vz) + (int64_t)z * npl;
         for (int i = threadIdx.x; i < npl; i += NTHR) {
-            const int x = i / a.n1, y = i - x * a.n1;
+            const int x = i / n1, y = i - x * n1;
             pl[x * rs + y] = cscale<T>(pl[x * rs + y], vzt[i]);
         }
-        (void)vz;
         __syncthreads();
     }
-    // forward along x everywhere, then along y on the rows that hold columns
-    FftGeom gx{a.n0, a.n1, rs, 1, 0, a.n1};
-    lds_fft<T, NTHR>(pl, a.plan0, gx, tw0, -1);
-    FftGeom gy{a.n1, a.nrows, 1, rs, a.rowlo, a.n0};
-    lds_fft<T, NTHR>(pl, a.plan1, gy, tw1, -1);
+    L0::template fft<T, NTHR, L1::N>(pl, a.plan0, gx, tw0, -1);
+    L1::template fft<T, NTHR, 0>(pl, a.plan1, gy, tw1, -1);
     for (int c = threadIdx.x; c < a.ncols; c += NTHR) crow[c] = pl[a.colpos[c]];
 }
 
 // ---------------------------------------------------------------------------
-// host launchers
+// host side
 // ---------------------------------------------------------------------------
 template <typename T> static int pick_threads(const FftPlan &p, int howmany) {
     for (int t : {256, 512, 1024})
@@ -403,54 +216,121 @@ template <typename F> static void allow_lds(F *kernel, size_t lds) {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
 }
 
-#define PW_LAUNCH_BY_THREADS(nthr, KERNEL, T, grid, lds, stream, ...)                           \
-    do {                                                                                       \
-        switch (nthr) {                                                                        \
-            case 256: allow_lds(KERNEL<T, 256>, lds); hipLaunchKernelGGL((KERNEL<T, 256>), grid, dim3(256), lds, stream, __VA_ARGS__); break; \
-            case 512: allow_lds(KERNEL<T, 512>, lds); hipLaunchKernelGGL((KERNEL<T, 512>), grid, dim3(512), lds, stream, __VA_ARGS__); break; \
-            case 1024: allow_lds(KERNEL<T, 1024>, lds); hipLaunchKernelGGL((KERNEL<T, 1024>), grid, dim3(1024), lds, stream, __VA_ARGS__); break; \
-            default: PW_CHECK(false, PW_EUNSUPPORTED, "FFT does not fit the register budget"); \
-        }                                                                                      \
-        PW_LAUNCH_CHECK();                                                                     \
-    } while (0)
+// z passes: launch with a compile-time length when one is built for n2
+template <typename T, typename LZ, int NTHR>
+static void zinv_go(const ZArgs &a, int ncb, int nb, size_t lds, hipStream_t s, const void *psi, int64_t ld,
+                    void *cols) {
+    allow_lds(zpass_inv<T, NTHR, LZ>, lds);
+    hipLaunchKernelGGL((zpass_inv<T, NTHR, LZ>), dim3(ncb, nb), dim3(NTHR), lds, s, a,
+                       reinterpret_cast<const cplx<T> *>(psi), ld, reinterpret_cast<cplx<T> *>(cols));
+}
+
+template <typename T, typename LZ, int NTHR>
+static void zfwd_go(const ZArgs &a, int ncb, int nb, size_t lds, hipStream_t s, const void *cols, const void *psi,
+                    int64_t ld, const double *kin, double shift, double scale, void *out, int64_t ldo) {
+    allow_lds(zpass_fwd<T, NTHR, LZ>, lds);
+    hipLaunchKernelGGL((zpass_fwd<T, NTHR, LZ>), dim3(ncb, nb), dim3(NTHR), lds, s, a,
+                       reinterpret_cast<const cplx<T> *>(cols), reinterpret_cast<const cplx<T> *>(psi), ld, kin,
+                       shift, scale, reinterpret_cast<cplx<T> *>(out), ldo);
+}
+
+constexpr int kZcb = 16;   // columns per z-pass workgroup (pw_ctx::cb)
+
+// dispatch a functor on (length policy, threads) for a z-pass length
+template <typename T, typename F> static void with_zlen(int n2, int nthr_rt, F &&f) {
+#define PW_ZCASE(L)                                                                   \
+    case L: {                                                                         \
+        constexpr int t = ct_threads<T>(L, kZcb);                                     \
+        static_assert(t > 0, "z length does not fit");                              \
+        f.template operator()<CtLen<L>, t>();                                         \
+        return;                                                                       \
+    }
+    switch (n2) {
+        PW_ZCASE(16) PW_ZCASE(20) PW_ZCASE(32) PW_ZCASE(40) PW_ZCASE(48) PW_ZCASE(64) PW_ZCASE(96)
+        PW_ZCASE(128) PW_ZCASE(192) PW_ZCASE(384) PW_ZCASE(512)
+        default: break;
+    }
+#undef PW_ZCASE
+    switch (nthr_rt) {
+        case 256: f.template operator()<RtLen, 256>(); return;
+        case 512: f.template operator()<RtLen, 512>(); return;
+        case 1024: f.template operator()<RtLen, 1024>(); return;
+        default: PW_CHECK(false, PW_EUNSUPPORTED, "FFT length %d does not fit the register budget", n2);
+    }
+}
+
+template <typename T> struct ZinvGo {
+    const ZArgs &a; int ncb, nb; size_t lds; hipStream_t s; const void *psi; int64_t ld; void *cols;
+    template <typename LZ, int NT> void operator()() { zinv_go<T, LZ, NT>(a, ncb, nb, lds, s, psi, ld, cols); }
+};
+
+template <typename T> struct ZfwdGo {
+    const ZArgs &a; int ncb, nb; size_t lds; hipStream_t s; const void *cols, *psi; int64_t ld;
+    const double *kin; double shift, scale; void *out; int64_t ldo;
+    template <typename LZ, int NT> void operator()() {
+        zfwd_go<T, LZ, NT>(a, ncb, nb, lds, s, cols, psi, ld, kin, shift, scale, out, ldo);
+    }
+};
 
 template <typename T>
 void launch_zinv(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *cols, hipStream_t s) {
     ZArgs a = zargs<T>(ctx, nb);
+    PW_CHECK(a.cb == kZcb, PW_EINVAL, "column block mismatch");
     const int ncb = (a.ncols + a.cb - 1) / a.cb;
-    const int nthr = pick_threads<T>(a.plan, a.cb);
     const size_t lds = sizeof(cplx<T>) * (a.n2 + (size_t)a.cb * (a.n2 + 1));
-    PW_LAUNCH_BY_THREADS(nthr, zpass_inv, T, dim3(ncb, nb), lds, s, a,
-                         reinterpret_cast<const cplx<T> *>(psi), ld, reinterpret_cast<cplx<T> *>(cols));
+    ZinvGo<T> go{a, ncb, nb, lds, s, psi, ld, cols};
+    with_zlen<T>(a.n2, pick_threads<T>(a.plan, a.cb), go);
+    PW_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_zfwd(pw_ctx *ctx, int nb, const void *cols, const void *psi, int64_t ld, const double *kin,
                  double shift, double scale, void *out, int64_t ldo, hipStream_t s) {
     ZArgs a = zargs<T>(ctx, nb);
+    PW_CHECK(a.cb == kZcb, PW_EINVAL, "column block mismatch");
     const int ncb = (a.ncols + a.cb - 1) / a.cb;
-    const int nthr = pick_threads<T>(a.plan, a.cb);
     const size_t lds = sizeof(cplx<T>) * (a.n2 + (size_t)a.cb * (a.n2 + 1));
-    PW_LAUNCH_BY_THREADS(nthr, zpass_fwd, T, dim3(ncb, nb), lds, s, a,
-                         reinterpret_cast<const cplx<T> *>(cols), reinterpret_cast<const cplx<T> *>(psi), ld,
-                         kin, shift, scale, reinterpret_cast<cplx<T> *>(out), ldo);
+    ZfwdGo<T> go{a, ncb, nb, lds, s, cols, psi, ld, kin, shift, scale, out, ldo};
+    with_zlen<T>(a.n2, pick_threads<T>(a.plan, a.cb), go);
+    PW_LAUNCH_CHECK();
+}
+
+template <typename T, int MODE, typename L0, typename L1, int NTHR>
+static void xy_go(const XYArgs &a, int nb, size_t lds, hipStream_t s, void *cols, void *grid) {
+    allow_lds(xy_pass<T, NTHR, MODE, L0, L1>, lds);
+    hipLaunchKernelGGL((xy_pass<T, NTHR, MODE, L0, L1>), dim3(a.n2, nb), dim3(NTHR), lds, s, a,
+                       reinterpret_cast<cplx<T> *>(cols), reinterpret_cast<cplx<T> *>(grid));
 }
 
 template <typename T, int MODE>
 void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
     XYArgs a = xyargs<T>(ctx);
+    const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
+    PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
+    if (a.n0 == a.n1) {
+#define PW_XYCASE(L)                                                                        \
+    case L: {                                                                               \
+        constexpr int t1 = ct_threads<T>(L, L), t = t1;                                    \
+        if constexpr (t > 0) {                                                              \
+            xy_go<T, MODE, CtLen<L>, CtLen<L>, t>(a, nb, lds, s, cols, grid);                \
+            PW_LAUNCH_CHECK();                                                              \
+            return;                                                                         \
+        }                                                                                   \
+        break;                                                                              \
+    }
+        switch (a.n0) {
+            PW_XYCASE(16) PW_XYCASE(32) PW_XYCASE(40) PW_XYCASE(48) PW_XYCASE(64) PW_XYCASE(96) PW_XYCASE(128)
+            default: break;
+        }
+#undef PW_XYCASE
+    }
     int nthr = 0;
     for (int t : {256, 512, 1024})
         if (fft_fits<T>(a.plan1, a.n0, t) && fft_fits<T>(a.plan0, a.n1, t)) { nthr = t; break; }
-    const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
-    PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
-    cplx<T> *c = reinterpret_cast<cplx<T> *>(cols);
-    cplx<T> *g = reinterpret_cast<cplx<T> *>(grid);
-    dim3 gr(a.n2, nb);
     switch (nthr) {
-        case 256: allow_lds(xy_pass<T, 256, MODE>, lds); hipLaunchKernelGGL((xy_pass<T, 256, MODE>), gr, dim3(256), lds, s, a, c, g); break;
-        case 512: allow_lds(xy_pass<T, 512, MODE>, lds); hipLaunchKernelGGL((xy_pass<T, 512, MODE>), gr, dim3(512), lds, s, a, c, g); break;
-        case 1024: allow_lds(xy_pass<T, 1024, MODE>, lds); hipLaunchKernelGGL((xy_pass<T, 1024, MODE>), gr, dim3(1024), lds, s, a, c, g); break;
+        case 256: xy_go<T, MODE, RtLen, RtLen, 256>(a, nb, lds, s, cols, grid); break;
+        case 512: xy_go<T, MODE, RtLen, RtLen, 512>(a, nb, lds, s, cols, grid); break;
+        case 1024: xy_go<T, MODE, RtLen, RtLen, 1024>(a, nb, lds, s, cols, grid); break;
         default: PW_CHECK(false, PW_EUNSUPPORTED, "xy FFT does not fit the register budget");
     }
     PW_LAUNCH_CHECK();

@@ -4,90 +4,119 @@
 //   NT (split-K):  C[m][n] = sum_k op(A[m][k]) B[n][k],   K = npw (huge), M, N small
 //                  -> projections <beta_p|psi_b>, Gram Psi^H Psi, Psi^H Y, Psi^H P
 //   NN:            Out[m][j] = alpha sum_k W[m][k] X[k][j] + beta Out[m][j],  j over npw
-//                  -> back-projection sum_p beta_p D_p c_pb, block rotations Psi Q
+//                  -> back-projection sum_p beta_p D_p c_pb, block rotations Q . Psi
 // Complex products are four real MFMAs into separate real/imaginary accumulators.
-// Operand tiles are staged in LDS (rows padded by one element against bank
-// conflicts); split-K partial sums are reduced by a second deterministic kernel,
-// so results are bitwise reproducible (no floating-point atomics).
+// Operand tiles are staged in LDS (rows padded against bank conflicts); the next
+// k-stage is fetched into registers while the current one is multiplied.
+// Split-K partial sums are reduced by a second kernel in a fixed order, so
+// results are bitwise reproducible (no floating-point atomics).
 #include "kernels.h"
 
 namespace pw {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Lane layout of v_mfma_f64_16x16x4f64 (wave64):
+// Lane layout of v_mfma_f64_16x16x4f64 (wave64), checked on gfx950:
 //   A operand: lane l holds A[i = l % 16][k = l / 16]
 //   B operand: lane l holds B[k = l / 16][j = l % 16]
-//   D:         lane l, item v holds D[i = l / 16 + 4 v][j = l % 16]  (checked on gfx950)
+//   D:         lane l, item v holds D[i = l / 16 + 4 v][j = l % 16]
 __device__ inline v4d mfma16(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 constexpr int KT = 16;       // k-depth of one LDS stage (complex elements)
 
+// acc_r += Re(a b), acc_i += Im(a b)
+__device__ inline void cmfma(const double2 a, const double2 b, v4d &ar, v4d &ai) {
+    ar = mfma16(a.x, b.x, ar);
+    ar = mfma16(-a.y, b.y, ar);
+    ai = mfma16(a.x, b.y, ai);
+    ai = mfma16(a.y, b.x, ai);
+}
+
 // ---------------------------------------------------------------------------
 // NT split-K partials: partial[s][m][n] = sum_{k in chunk s} op(A[m][k]) * B[n][k]
-// op = conj when CONJA.  Tile 64 x 64, 4 waves each 32 x 32.
+// op = conj when CONJA.  Waves WM x WN, each BM x BN blocks of 16 x 16.
 // ---------------------------------------------------------------------------
-template <bool CONJA>
-__global__ __launch_bounds__(256) void zgemm_nt_partial(int M, int N, int K, const double2 *__restrict__ A,
-                                                        int64_t lda, const double2 *__restrict__ B, int64_t ldb,
-                                                        int kchunk, double2 *__restrict__ partial) {
-    __shared__ double2 As[64][KT + 1];
-    __shared__ double2 Bs[64][KT + 1];
-    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64, s = blockIdx.z;
+template <int WM, int WN, int BM, int BN, bool CONJA>
+__global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, int K, const double2 *__restrict__ A,
+                                                                 int64_t lda, const double2 *__restrict__ B,
+                                                                 int64_t ldb, int kchunk,
+                                                                 double2 *__restrict__ partial) {
+    constexpr int NT = WM * WN * 64;
+    constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
+    constexpr int LA = TM * KT / NT, LB = TN * KT / NT;     // complex loads per thread per stage
+    static_assert(TM * KT % NT == 0 && TN * KT % NT == 0, "tile/thread mismatch");
+    __shared__ double2 As[TM][KT + 1];
+    __shared__ double2 Bs[TN][KT + 1];
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN, s = blockIdx.z;
     const int kbeg = s * kchunk;
     const int kend = min(K, kbeg + kchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    v4d accr[2][2], acci[2][2];
+    const int wm = wave % WM, wn = wave / WM;
+    v4d accr[BM][BN], acci[BM][BN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) { accr[i][j] = v4d{0, 0, 0, 0}; acci[i][j] = v4d{0, 0, 0, 0}; }
-    for (int k0 = kbeg; k0 < kend; k0 += KT) {
+        for (int j = 0; j < BN; ++j) { accr[i][j] = v4d{0, 0, 0, 0}; acci[i][j] = v4d{0, 0, 0, 0}; }
+    double2 ra[LA], rb[LB];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int e = tid + it * 256;
-            const int r = e / KT, kk = e % KT;
-            const int gk = k0 + kk;
-            const int gm = m0 + r, gn = n0 + r;
-            As[r][kk] = (gm < M && gk < kend) ? A[(int64_t)gm * lda + gk] : make_double2(0.0, 0.0);
-            Bs[r][kk] = (gn < N && gk < kend) ? B[(int64_t)gn * ldb + gk] : make_double2(0.0, 0.0);
+        for (int it = 0; it < LA; ++it) {
+            const int e = tid + it * NT, r = e / KT, kk = e % KT, gk = k0 + kk, gm = m0 + r;
+            ra[it] = (gm < M && gk < kend) ? A[(int64_t)gm * lda + gk] : make_double2(0.0, 0.0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < LB; ++it) {
+            const int e = tid + it * NT, r = e / KT, kk = e % KT, gk = k0 + kk, gn = n0 + r;
+            rb[it] = (gn < N && gk < kend) ? B[(int64_t)gn * ldb + gk] : make_double2(0.0, 0.0);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int it = 0; it < LA; ++it) { const int e = tid + it * NT; As[e / KT][e % KT] = ra[it]; }
+#pragma unroll
+        for (int it = 0; it < LB; ++it) { const int e = tid + it * NT; Bs[e / KT][e % KT] = rb[it]; }
+    };
+    if (kbeg < kend) {
+        fetch(kbeg);
+        stash();
+    }
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += KT) {
+        const bool more = k0 + KT < kend;
+        if (more) fetch(k0 + KT);
 #pragma unroll
         for (int kq = 0; kq < KT / 4; ++kq) {
             const int k = kq * 4 + (lane >> 4);
-            double2 a[2], b[2];
+            double2 a[BM], b[BN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                a[i] = As[wm * 32 + i * 16 + (lane & 15)][k];
+            for (int i = 0; i < BM; ++i) {
+                a[i] = As[(wm * BM + i) * 16 + (lane & 15)][k];
                 if (CONJA) a[i].y = -a[i].y;
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[wn * 32 + j * 16 + (lane & 15)][k];
+            for (int j = 0; j < BN; ++j) b[j] = Bs[(wn * BN + j) * 16 + (lane & 15)][k];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = mfma16(a[i].x, b[j].x, accr[i][j]);
-                    accr[i][j] = mfma16(-a[i].y, b[j].y, accr[i][j]);
-                    acci[i][j] = mfma16(a[i].x, b[j].y, acci[i][j]);
-                    acci[i][j] = mfma16(a[i].y, b[j].x, acci[i][j]);
-                }
+                for (int j = 0; j < BN; ++j) cmfma(a[i], b[j], accr[i][j], acci[i][j]);
         }
         __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
     double2 *P = partial + (int64_t)s * M * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BN; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
-                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                const int row = m0 + (wm * BM + i) * 16 + (lane >> 4) + 4 * v;
+                const int col = n0 + (wn * BN + j) * 16 + (lane & 15);
                 if (row < M && col < N) P[(int64_t)row * N + col] = make_double2(accr[i][j][v], acci[i][j][v]);
             }
 }
@@ -116,66 +145,89 @@ __global__ void reduce_partial(int M, int N, int nsplit, const double2 *__restri
 }
 
 // ---------------------------------------------------------------------------
-// NN: Out[m][j] = alpha * sum_k W[m][k] X[k][j] + beta * Out[m][j]
-// Tile 64 (m) x 64 (j), 4 waves each 32 x 32.
+// NN: Out_z[m][j] = alpha * sum_k W[m][k] X_z[k][j] + beta * Out_z[m][j]
+// for up to 4 (X_z, Out_z) pairs sharing W (blockIdx.z).  Waves WM x WJ, each
+// BM x BJ blocks of 16 x 16.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void zgemm_nn(int M, int J, int K, const double2 *__restrict__ W, int64_t ldw,
-                                                const double2 *__restrict__ X, int64_t ldx, double alpha,
-                                                double beta, double2 *__restrict__ Out, int64_t ldo) {
-    __shared__ double2 Ws[64][KT + 1];
-    __shared__ double2 Xs[KT][64 + 1];
-    const int j0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+struct NNBatch {
+    const double2 *X[4];
+    double2 *Out[4];
+};
+
+template <int WM, int WJ, int BM, int BJ>
+__global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, int K, const double2 *__restrict__ W,
+                                                                int64_t ldw, NNBatch bt, int64_t ldx, double alpha,
+                                                                double beta, int64_t ldo) {
+    constexpr int NT = WM * WJ * 64;
+    constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
+    constexpr int LW = TM * KT / NT, LX = KT * TJ / NT;
+    static_assert(TM * KT % NT == 0 && KT * TJ % NT == 0, "tile/thread mismatch");
+    __shared__ double2 Ws[TM][KT + 1];
+    __shared__ double2 Xs[KT][TJ + 1];
+    const double2 *__restrict__ X = bt.X[blockIdx.z];
+    double2 *__restrict__ Out = bt.Out[blockIdx.z];
+    const int j0 = blockIdx.x * TJ, m0 = blockIdx.y * TM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wj = wave >> 1;
-    v4d accr[2][2], acci[2][2];
+    const int wm = wave % WM, wj = wave / WM;
+    v4d accr[BM][BJ], acci[BM][BJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) { accr[i][j] = v4d{0, 0, 0, 0}; acci[i][j] = v4d{0, 0, 0, 0}; }
-    for (int k0 = 0; k0 < K; k0 += KT) {
+        for (int j = 0; j < BJ; ++j) { accr[i][j] = v4d{0, 0, 0, 0}; acci[i][j] = v4d{0, 0, 0, 0}; }
+    double2 rw[LW], rx[LX];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int e = tid + it * 256;
-            {   // W tile 64 x KT
-                const int r = e / KT, kk = e % KT;
-                const int gm = m0 + r, gk = k0 + kk;
-                Ws[r][kk] = (gm < M && gk < K) ? W[(int64_t)gm * ldw + gk] : make_double2(0.0, 0.0);
-            }
-            {   // X tile KT x 64
-                const int kk = e / 64, c = e % 64;
-                const int gk = k0 + kk, gj = j0 + c;
-                Xs[kk][c] = (gk < K && gj < J) ? X[(int64_t)gk * ldx + gj] : make_double2(0.0, 0.0);
-            }
+        for (int it = 0; it < LW; ++it) {
+            const int e = tid + it * NT, r = e / KT, kk = e % KT, gm = m0 + r, gk = k0 + kk;
+            rw[it] = (gm < M && gk < K) ? W[(int64_t)gm * ldw + gk] : make_double2(0.0, 0.0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < LX; ++it) {
+            const int e = tid + it * NT, kk = e / TJ, c = e % TJ, gk = k0 + kk, gj = j0 + c;
+            rx[it] = (gk < K && gj < J) ? X[(int64_t)gk * ldx + gj] : make_double2(0.0, 0.0);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int it = 0; it < LW; ++it) { const int e = tid + it * NT; Ws[e / KT][e % KT] = rw[it]; }
+#pragma unroll
+        for (int it = 0; it < LX; ++it) { const int e = tid + it * NT; Xs[e / TJ][e % TJ] = rx[it]; }
+    };
+    if (K > 0) {
+        fetch(0);
+        stash();
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += KT) {
+        const bool more = k0 + KT < K;
+        if (more) fetch(k0 + KT);
 #pragma unroll
         for (int kq = 0; kq < KT / 4; ++kq) {
             const int k = kq * 4 + (lane >> 4);
-            double2 a[2], b[2];
+            double2 a[BM], b[BJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = Ws[wm * 32 + i * 16 + (lane & 15)][k];
+            for (int i = 0; i < BM; ++i) a[i] = Ws[(wm * BM + i) * 16 + (lane & 15)][k];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Xs[k][wj * 32 + j * 16 + (lane & 15)];
+            for (int j = 0; j < BJ; ++j) b[j] = Xs[k][(wj * BJ + j) * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = mfma16(a[i].x, b[j].x, accr[i][j]);
-                    accr[i][j] = mfma16(-a[i].y, b[j].y, accr[i][j]);
-                    acci[i][j] = mfma16(a[i].x, b[j].y, acci[i][j]);
-                    acci[i][j] = mfma16(a[i].y, b[j].x, acci[i][j]);
-                }
+                for (int j = 0; j < BJ; ++j) cmfma(a[i], b[j], accr[i][j], acci[i][j]);
         }
         __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
-                const int col = j0 + wj * 32 + j * 16 + (lane & 15);
+                const int row = m0 + (wm * BM + i) * 16 + (lane >> 4) + 4 * v;
+                const int col = j0 + (wj * BJ + j) * 16 + (lane & 15);
                 if (row < M && col < J) {
                     double2 *o = Out + (int64_t)row * ldo + col;
                     double re = alpha * accr[i][j][v], im = alpha * acci[i][j][v];
@@ -188,13 +240,18 @@ __global__ __launch_bounds__(256) void zgemm_nn(int M, int J, int K, const doubl
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
-// Number of K-splits so that the grid holds >= ~1024 workgroups and each chunk
-// keeps at least a few LDS stages.
+// NT tile 64 x 128 (4 waves of 32 x 64)
+constexpr int NT_TM = 64, NT_TN = 128;
+
+// K-splits: enough workgroups to cover the chip (~512) while keeping at least
+// four LDS stages per chunk and the partial sums under 64 MiB.
 int nt_splits(int M, int N, int K) {
-    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-    int s = (1024 + tiles - 1) / tiles;
+    const int tiles = ((M + NT_TM - 1) / NT_TM) * ((N + NT_TN - 1) / NT_TN);
+    int s = (512 + tiles - 1) / tiles;
     const int maxs = (K + 4 * KT - 1) / (4 * KT);
     if (s > maxs) s = maxs;
+    const int64_t cap = (int64_t)(64 << 20) / ((int64_t)M * N * (int64_t)sizeof(double2));
+    if (s > cap) s = (int)cap;
     if (s < 1) s = 1;
     return s;
 }
@@ -211,38 +268,58 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     const int ns = nt_splits(M, N, K);
     int kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + KT - 1) / KT) * KT;
-    const int nsplit = (K + kchunk - 1) / kchunk;
-    dim3 grid((M + 63) / 64, (N + 63) / 64, nsplit > 0 ? nsplit : 1);
+    const int nsplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
+    dim3 grid((M + NT_TM - 1) / NT_TM, (N + NT_TN - 1) / NT_TN, nsplit);
     if (K <= 0) {
         fill_zero(partial, (size_t)M * N * sizeof(double2), st);
     } else if (conja) {
-        hipLaunchKernelGGL((zgemm_nt_partial<true>), grid, dim3(256), 0, st, M, N, K,
+        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, true>), grid, dim3(256), 0, st, M, N, K,
                            (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
     } else {
-        hipLaunchKernelGGL((zgemm_nt_partial<false>), grid, dim3(256), 0, st, M, N, K,
+        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, false>), grid, dim3(256), 0, st, M, N, K,
                            (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
     }
     PW_LAUNCH_CHECK();
     const int64_t tot = (int64_t)M * N;
     const int nblk = (int)((tot + 255) / 256);
-    const int ns_eff = K <= 0 ? 1 : nsplit;
     if (trans)
-        hipLaunchKernelGGL((reduce_partial<true>), dim3(nblk), dim3(256), 0, st, M, N, ns_eff,
+        hipLaunchKernelGGL((reduce_partial<true>), dim3(nblk), dim3(256), 0, st, M, N, nsplit,
                            (const double2 *)partial, alpha, rowscale, beta, (double2 *)C, ldc);
     else
-        hipLaunchKernelGGL((reduce_partial<false>), dim3(nblk), dim3(256), 0, st, M, N, ns_eff,
+        hipLaunchKernelGGL((reduce_partial<false>), dim3(nblk), dim3(256), 0, st, M, N, nsplit,
                            (const double2 *)partial, alpha, rowscale, beta, (double2 *)C, ldc);
     PW_LAUNCH_CHECK();
 }
 
-// Out (M x J, ldo) = alpha * W (M x K, ldw) . X (K x J, ldx) + beta * Out
+// Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
+void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st) {
+    if (M <= 0 || J <= 0 || nz <= 0) return;
+    PW_CHECK(nz <= 4, PW_EINVAL, "at most 4 blocks per batched rotation");
+    NNBatch bt{};
+    for (int z = 0; z < nz; ++z) {
+        bt.X[z] = (const double2 *)X[z];
+        bt.Out[z] = (double2 *)Out[z];
+    }
+    if (M > 64) {
+        // 128 x 64 tiles: 4 waves stacked in M, each 32 x 64
+        dim3 grid((J + 63) / 64, (M + 127) / 128, nz);
+        hipLaunchKernelGGL((zgemm_nn_kernel<4, 1, 2, 4>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
+                           bt, ldx, alpha, beta, ldo);
+    } else {
+        // 64 x 64 tiles: 2 x 2 waves, each 32 x 32
+        dim3 grid((J + 63) / 64, (M + 63) / 64, nz);
+        hipLaunchKernelGGL((zgemm_nn_kernel<2, 2, 2, 2>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
+                           bt, ldx, alpha, beta, ldo);
+    }
+    PW_LAUNCH_CHECK();
+}
+
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
                      double beta, void *Out, int64_t ldo, hipStream_t st) {
-    if (M <= 0 || J <= 0) return;
-    dim3 grid((J + 63) / 64, (M + 63) / 64);
-    hipLaunchKernelGGL(zgemm_nn, grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw, (const double2 *)X,
-                       ldx, alpha, beta, (double2 *)Out, ldo);
-    PW_LAUNCH_CHECK();
+    const void *xs[1] = {X};
+    void *os[1] = {Out};
+    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st);
 }
 
 }  // namespace pw

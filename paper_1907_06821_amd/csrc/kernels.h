@@ -19,6 +19,8 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
               hipStream_t);
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
                      double beta, void *Out, int64_t ldo, hipStream_t);
+void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t);
 
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
 size_t cnt_partial_bytes(int M, int N, int K);

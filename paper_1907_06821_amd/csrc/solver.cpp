@@ -116,24 +116,32 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
         zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st);
         std::swap(blk, tmp);
     };
+    // (X, Y, AX) <- M . (X, Y, AX) in one batched launch
+    auto rotate3 = [&](const double2 *M) {
+        const void *in[3] = {X, Y, AX};
+        void *out[3] = {T1, T2, T3};
+        zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st);
+        std::swap(X, T1);
+        std::swap(Y, T2);
+        std::swap(AX, T3);
+    };
     auto orth = [&]() {
         zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
         chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
-        rotate(Tm, X, T1);
-        rotate(Tm, Y, T2);
-        rotate(Tm, AX, T3);
+        rotate3(Tm);
     };
     // Rayleigh-Ritz in A = (H - E)^2 on the iterate (Y, AX exact): Ritz values of
     // Y^H Y ascending; the search directions and gradients turn with the bands.
     auto a_rr = [&](bool rotate_dirs) {
         zgemm_nt(nb, nb, npw, true, Y, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
         jacobi_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
-        rotate(Rm, X, T1);
-        rotate(Rm, Y, T2);
-        rotate(Rm, AX, T3);
+        rotate3(Rm);
         if (rotate_dirs) {
-            rotate(Rm, P, T1);
-            rotate(Rm, G, T2);
+            const void *in[2] = {P, G};
+            void *out[2] = {T1, T2};
+            zgemm_nn_batch(2, nb, npw, nb, Rm, nb, in, L, 1.0, 0.0, out, L, st);
+            std::swap(P, T1);
+            std::swap(G, T2);
         }
     };
     // Rayleigh-Ritz in H on copies of the block: lam = theta - E ascending and the
