@@ -47,7 +47,7 @@ def stage_work(ctx, nb, dtype_bytes, nproj):
     }
 
 
-def cpu_baseline(prob, nb_sample=16, iters=1):
+def cpu_baseline(prob, nb_sample=64, iters=2):
     """The FP64 oracle's folded CG (numpy FFT H psi) on a bounded sample of the
     same cell: nb_sample bands, `iters` iterations."""
     import numpy as np
@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--cpu-bands", type=int, default=16)
+    ap.add_argument("--cpu-bands", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver shards no work across GPUs in this build",

@@ -167,6 +167,8 @@ typedef struct {
     int32_t precision;    /* 0 FP64 throughout; 1 mixed (complex64 H psi, FP64 block algebra) */
     int32_t check_every;  /* iterations between exact residual checks */
     int32_t verbose;      /* print the residual at each check to stderr */
+    double mixed_switch;  /* mixed: use FP64 H psi once max Delta < mixed_switch (default 1e-4) */
+    int32_t stall_checks; /* mixed: also switch after this many checks without a 2x gain (0 = never) */
 } pw_cg_opts;
 
 typedef struct {

@@ -55,7 +55,8 @@ class pw_ctx_info(C.Structure):
 
 class pw_cg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precond", C.c_int32), ("delta_e", C.c_double),
-                ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32)]
+                ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32),
+                ("mixed_switch", C.c_double), ("stall_checks", C.c_int32)]
 
 
 class pw_cg_stats(C.Structure):

@@ -225,11 +225,13 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
                 converged = true;
                 break;
             }
-            // precision ladder: leave the low-precision operator once it stops helping
+            // precision ladder: leave the low-precision operator below mixed_switch, or
+            // once the best residual has not improved by 2x over stall_checks checks
             if (use_mixed) {
-                if (mx < 0.7 * best) { best = mx; stall = 0; }
-                else if (++stall >= 2) use_mixed = false;
-                if (mx < 1e-4) use_mixed = false;
+                if (mx < 0.5 * best) { best = mx; stall = 0; }
+                else if (o.stall_checks > 0 && ++stall >= o.stall_checks) use_mixed = false;
+                if (mx < o.mixed_switch) use_mixed = false;
+                if (!use_mixed && o.verbose) fprintf(stderr, "[pw] it %6d  switching to FP64 H psi\n", it);
             }
         }
     }
@@ -288,6 +290,8 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->precision = 0;
     o->check_every = 20;
     o->verbose = 0;
+    o->mixed_switch = 1e-4;
+    o->stall_checks = 10;
 }
 
 pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld, double *eig,
