@@ -169,6 +169,9 @@ typedef struct {
     int32_t verbose;      /* print the residual at each check to stderr */
     double mixed_switch;  /* mixed: use FP64 H psi once max Delta < mixed_switch (default 1e-4) */
     int32_t stall_checks; /* mixed: also switch after this many checks without a 2x gain (0 = never) */
+    void *snap_buf;       /* optional device complex128 [snap_cap][nb][npw]: iterate snapshots for training */
+    int32_t snap_every;   /* store X after every snap_every-th iteration (0 = never) */
+    int32_t snap_cap;     /* capacity of snap_buf in snapshots */
 } pw_cg_opts;
 
 typedef struct {
@@ -179,6 +182,7 @@ typedef struct {
     double seconds;       /* wall time of the solve */
     int32_t n_hist;       /* in: capacity of hist; out: entries written */
     double *hist;         /* host, optional: [n_hist][2] = (iteration, max Delta) */
+    int32_t n_snap;       /* out: snapshots written to snap_buf */
 } pw_cg_stats;
 
 void pw_cg_opts_default(pw_cg_opts *opts);
@@ -192,6 +196,57 @@ void pw_cg_opts_default(pw_cg_opts *opts);
 pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld,
                              double *eig, double *resid, const pw_cg_opts *opts,
                              pw_cg_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner (precond = 2).  Not in the paper: a network standing in
+ * for the diagonal preconditioner (the paper's is M(G), Sec. II.B).  Per |G+k|
+ * shell s and band i, f_si = MLP(T_s/Ecut, T_i/Ecut, E_ref/Ecut), a 3-64-64-1 tanh
+ * network with output 8 tanh(r/8); the CG uses K_i(G) = K_TPA(T_G/T_i)^2 exp(f).
+ * Parameters (float32, PW_MLP_NPARAM): W1[64][3], b1[64], W2[64][64], b2[64],
+ * W3[64], b3.  Training loss per band and snapshot: 1 - Re<K g, e>/(|K g| |e|),
+ * e = -(I - Psi* Psi*^H) psi the band's error outside the converged subspace; it
+ * depends on a snapshot only through shell tables A_si = sum_{G in s} Re(conj e
+ * K0 g), B_si = sum |K0 g|^2, C_si = sum |e|^2 (doubles, [3][nshell][nb]).
+ * All pointers below are device pointers unless stated.
+ * ------------------------------------------------------------------------- */
+#define PW_MLP_NPARAM 4481
+
+/* Install the network used by precond = 2 (weights copied into the context). */
+pw_status pw_mlp_set(pw_ctx *ctx, const float *weights);
+
+/* f [nshell][nb] for shell energies shell_t [nshell], band kinetic energies
+ * tband [nb] (both float64, Ha) at one e_ref; ecut scales the inputs. */
+pw_status pw_mlp_forward(int32_t nshell, int32_t nb, const double *shell_t, const double *tband, double e_ref,
+                         double ecut, const float *weights, float *f, void *stream);
+
+/* Shell tables of one snapshot: x_snap [nb][ld] an iterate of a solve at e_ref,
+ * x_conv [nb][ld] the converged orthonormal block.  Recomputes the gradient
+ * g = A x - <x|A|x> x with two FP64 H psi, the TPA weights K0 and the band kinetic
+ * energies (written to tband [nb]), and writes tabs [3][nshell][nb]. */
+pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
+                         double *tabs, double *tband, void *stream);
+
+/* Scratch bytes needed by pw_mlp_loss_grad (host function). */
+int64_t pw_mlp_work_bytes(int32_t nshell, int32_t nb, int32_t nsnap);
+
+/* Mean loss over nsnap snapshots x nb bands and its gradient (float32 [NPARAM]).
+ * tband [nsnap][nb], e_ref [nsnap], tabs [nsnap][3][nshell][nb]; loss: one float;
+ * work: caller-allocated, >= pw_mlp_work_bytes.  Deterministic (no atomics). */
+pw_status pw_mlp_loss_grad(int32_t nshell, int32_t nb, int32_t nsnap, const double *shell_t, const double *tband,
+                           const double *e_ref, double ecut, const double *tabs, const float *weights, float *grad,
+                           float *loss, void *work, int64_t work_bytes, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8); step counts from 1. */
+pw_status pw_mlp_adam(float *weights, const float *grad, float *m, float *v, int32_t step, float lr, void *stream);
+
+/* nsteps full-batch training steps (loss/gradient, then Adam at steps step0+1 ..
+ * step0+nsteps) on the device.  grad [NPARAM] and m, v (Adam moments) are
+ * caller-owned device float32; loss_hist (host, optional, [nsteps]) receives the
+ * loss before each step.  Synchronises once at the end. */
+pw_status pw_mlp_train(int32_t nshell, int32_t nb, int32_t nsnap, const double *shell_t, const double *tband,
+                       const double *e_ref, double ecut, const double *tabs, float *weights, float *grad, float *m,
+                       float *v, int32_t step0, int32_t nsteps, float lr, float *loss_hist, void *work,
+                       int64_t work_bytes, void *stream);
 
 /* Per-stage timing with HIP events recorded on the stream each stage is
  * launched on.  pw_profile_begin allocates room for max_records stage launches

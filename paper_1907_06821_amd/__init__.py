@@ -27,7 +27,8 @@ _STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EHIP", -4
 EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy", "pw_ctx_get_info",
            "pw_ctx_kinetic", "pw_ctx_shells", "pw_hpsi", "pw_wave_to_grid", "pw_grid_to_wave",
            "pw_orthonormalize", "pw_cg_opts_default", "pw_folded_cg_solve", "pw_dense_eigh",
-           "pw_dense_chol_inv", "pw_profile_begin",
+           "pw_dense_chol_inv", "pw_mlp_set", "pw_mlp_forward", "pw_mlp_harvest", "pw_mlp_work_bytes",
+           "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
            "pw_profile_end", "pw_last_error")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
 PW_PROF_NKINDS = 8
@@ -56,12 +57,14 @@ class pw_ctx_info(C.Structure):
 class pw_cg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precond", C.c_int32), ("delta_e", C.c_double),
                 ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32),
-                ("mixed_switch", C.c_double), ("stall_checks", C.c_int32)]
+                ("mixed_switch", C.c_double), ("stall_checks", C.c_int32), ("snap_buf", C.c_void_p),
+                ("snap_every", C.c_int32), ("snap_cap", C.c_int32)]
 
 
 class pw_cg_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_hpsi", C.c_int64), ("max_resid", C.c_double),
-                ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double))]
+                ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double)),
+                ("n_snap", C.c_int32)]
 
 
 _lib = None
@@ -92,6 +95,13 @@ def lib():
                                    C.POINTER(pw_cg_stats), vp],
             "pw_dense_eigh": [i32, vp, i64, vp, vp, i32, dbl, C.POINTER(i32), vp],
             "pw_dense_chol_inv": [i32, vp, i64, vp, vp],
+            "pw_mlp_set": [vp, vp],
+            "pw_mlp_forward": [i32, i32, vp, vp, dbl, dbl, vp, vp, vp],
+            "pw_mlp_harvest": [vp, dbl, i32, vp, vp, i64, vp, vp, vp],
+            "pw_mlp_loss_grad": [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp],
+            "pw_mlp_adam": [vp, vp, vp, vp, i32, C.c_float, vp],
+            "pw_mlp_train": [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i32, i32, C.c_float,
+                             C.POINTER(C.c_float), vp, i64, vp],
             "pw_profile_begin": [vp, i32],
             "pw_profile_end": [vp, C.POINTER(dbl), C.POINTER(i64)],
         }
@@ -99,6 +109,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
+        L.pw_mlp_work_bytes.argtypes = [i32, i32, i32]
+        L.pw_mlp_work_bytes.restype = C.c_int64
         L.pw_cg_opts_default.argtypes = [C.POINTER(pw_cg_opts)]
         L.pw_cg_opts_default.restype = None
         L.pw_last_error.argtypes = []
@@ -292,6 +304,103 @@ def dense_chol_inv(s, stream=None):
     return t
 
 
+MLP_NPARAM = 4481
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, n=None):
+    import torch
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or (n is not None and t.numel() != n):
+        raise ValueError(f"expected a contiguous CUDA {dtype} tensor" + (f" of {n} elements" if n else ""))
+
+
+def mlp_set(ctx, weights):
+    """Install float32 network weights (device, MLP_NPARAM) for precond=2."""
+    import torch
+    _need(weights, torch.float32, MLP_NPARAM)
+    _check(lib().pw_mlp_set(ctx.handle, _dptr(weights)))
+
+
+def mlp_forward(shell_t, tband, e_ref, ecut, weights, stream=None):
+    """f [nshell, nb] (float32) for device float64 shell_t [nshell], tband [nb]."""
+    import torch
+    _need(shell_t, torch.float64)
+    _need(tband, torch.float64)
+    _need(weights, torch.float32, MLP_NPARAM)
+    f = torch.empty((shell_t.numel(), tband.numel()), dtype=torch.float32, device=shell_t.device)
+    _check(lib().pw_mlp_forward(shell_t.numel(), tband.numel(), _dptr(shell_t), _dptr(tband), float(e_ref),
+                                float(ecut), _dptr(weights), _dptr(f), _stream_ptr(stream)))
+    return f
+
+
+def mlp_harvest(ctx, e_ref, x_snap, x_conv, stream=None):
+    """Training tables of one snapshot: (tabs [3, nshell, nb] float64, tband [nb])."""
+    import torch
+    _check_block(x_snap, ctx.npw)
+    _check_block(x_conv, ctx.npw)
+    nb = x_snap.shape[0]
+    if x_conv.shape[0] != nb or x_snap.stride(0) != x_conv.stride(0):
+        raise ValueError("x_snap and x_conv must have the same shape and stride")
+    tabs = torch.empty((3, ctx.nshell, nb), dtype=torch.float64, device=x_snap.device)
+    tband = torch.empty(nb, dtype=torch.float64, device=x_snap.device)
+    _check(lib().pw_mlp_harvest(ctx.handle, float(e_ref), nb, _dptr(x_snap), _dptr(x_conv), x_snap.stride(0),
+                                _dptr(tabs), _dptr(tband), _stream_ptr(stream)))
+    return tabs, tband
+
+
+def mlp_work_bytes(nshell, nb, nsnap):
+    return int(lib().pw_mlp_work_bytes(nshell, nb, nsnap))
+
+
+def mlp_loss_grad(shell_t, tband, e_ref, ecut, tabs, weights, stream=None):
+    """(loss, grad) on device; tband [nsnap, nb], e_ref [nsnap], tabs [nsnap, 3, nshell, nb]."""
+    import torch
+    nsnap, nb = tband.shape
+    ns = shell_t.numel()
+    for t in (shell_t, tband, e_ref, tabs):
+        _need(t, torch.float64)
+    if tuple(tabs.shape) != (nsnap, 3, ns, nb) or e_ref.numel() != nsnap:
+        raise ValueError("table shapes do not match")
+    _need(weights, torch.float32, MLP_NPARAM)
+    wb = mlp_work_bytes(ns, nb, nsnap)
+    work = torch.empty(wb, dtype=torch.uint8, device=tabs.device)
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=tabs.device)
+    loss = torch.empty(1, dtype=torch.float32, device=tabs.device)
+    _check(lib().pw_mlp_loss_grad(ns, nb, nsnap, _dptr(shell_t), _dptr(tband), _dptr(e_ref), float(ecut),
+                                  _dptr(tabs), _dptr(weights), _dptr(grad), _dptr(loss), _dptr(work), wb,
+                                  _stream_ptr(stream)))
+    return loss, grad
+
+
+def mlp_adam(weights, grad, m, v, step, lr, stream=None):
+    _check(lib().pw_mlp_adam(_dptr(weights), _dptr(grad), _dptr(m), _dptr(v), int(step), float(lr),
+                             _stream_ptr(stream)))
+
+
+def mlp_train(shell_t, tband, e_ref, ecut, tabs, weights, nsteps, lr=3e-3, m=None, v=None, step0=0, stream=None):
+    """nsteps Adam steps on the device (weights updated in place); returns the loss history."""
+    import torch
+    nsnap, nb = tband.shape
+    ns = shell_t.numel()
+    for t in (shell_t, tband, e_ref, tabs):
+        _need(t, torch.float64)
+    _need(weights, torch.float32, MLP_NPARAM)
+    dev = weights.device
+    m = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=dev) if m is None else m
+    v = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=dev) if v is None else v
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=dev)
+    wb = mlp_work_bytes(ns, nb, nsnap) + 4 * (nsteps + 64)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    hist = np.zeros(max(nsteps, 1), dtype=np.float32)
+    _check(lib().pw_mlp_train(ns, nb, nsnap, _dptr(shell_t), _dptr(tband), _dptr(e_ref), float(ecut), _dptr(tabs),
+                              _dptr(weights), _dptr(grad), _dptr(m), _dptr(v), int(step0), int(nsteps), float(lr),
+                              hist.ctypes.data_as(C.POINTER(C.c_float)), _dptr(work), wb, _stream_ptr(stream)))
+    return hist[:nsteps], m, v
+
+
 def profile_begin(ctx, max_records=100000):
     _check(ctx._lib.pw_profile_begin(ctx.handle, int(max_records)))
 
@@ -318,10 +427,20 @@ def cg_opts(**kw):
 def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_on_noconv=True, **kw):
     """Folded-spectrum PCG on the complex128 block psi (in: start, out: Ritz vectors).
 
+    snapshots (optional): complex128 device tensor [cap, nb, npw] receiving the
+    iterate every `snap_every` iterations.
     Returns (eig [nb] ascending, resid [nb], stats dict)."""
     _check_block(psi, ctx.npw)
     nb = psi.shape[0]
+    snaps = kw.pop("snapshots", None)
     o = opts if opts is not None else cg_opts(**kw)
+    if snaps is not None:
+        import torch
+        if (snaps.dtype != torch.complex128 or not snaps.is_cuda or not snaps.is_contiguous()
+                or tuple(snaps.shape[1:]) != (nb, ctx.npw)):
+            raise ValueError("snapshots must be a contiguous complex128 [cap, nb, npw] CUDA tensor")
+        o.snap_buf = snaps.data_ptr()
+        o.snap_cap = snaps.shape[0]
     eig = np.zeros(nb)
     res = np.zeros(nb)
     st = pw_cg_stats()
@@ -333,7 +452,7 @@ def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_o
                                          res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o), C.byref(st),
                                          _stream_ptr(stream))
     stats = dict(iters=st.iters, converged=bool(st.converged), n_hpsi=st.n_hpsi, max_resid=st.max_resid,
-                 seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status)
+                 seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status, n_snap=st.n_snap)
     if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
         _check(status)
     return eig, res, stats

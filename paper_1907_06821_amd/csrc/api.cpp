@@ -82,10 +82,11 @@ static void hpsi_c128(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *ou
         {
             ProfScope p(ctx, 3, st);
             zgemm_nt(ctx->nproj, nb, npw, true, ctx->d_beta64.p, npw, psi, ld, 1.0, ctx->d_dproj.as<double>(), 0.0,
-                     ctx->d_proj.p, ctx->nproj, true, ctx->d_partial.p, st);
+                     ctx->d_proj.p, ctx->nproj, true, ctx->d_partial.p, st, true);
         }
         ProfScope p(ctx, 4, st);
-        zgemm_nn_launch(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->nproj, ctx->d_beta64.p, npw, 1.0, 1.0, out, ldo, st);
+        zgemm_nn_launch(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->nproj, ctx->d_beta64.p, npw, 1.0, 1.0, out, ldo, st,
+                        true);
     }
 }
 
@@ -208,6 +209,18 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
     upload(c->d_zmap, zmap, acct);
     upload(c->d_colpos, colpos, acct);
     upload(c->d_shell, b.shell, acct);
+    upload(c->d_shell_t, b.shell_t, acct);
+    {
+        // plane waves grouped by shell (CSR), for the learned preconditioner's tables
+        const int ns = (int)b.shell_t.size();
+        std::vector<int32_t> off(ns + 1, 0), pws(b.npw);
+        for (int g = 0; g < b.npw; ++g) ++off[b.shell[g] + 1];
+        for (int s = 0; s < ns; ++s) off[s + 1] += off[s];
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (int g = 0; g < b.npw; ++g) pws[fill[b.shell[g]]++] = g;
+        upload(c->d_shell_off, off, acct);
+        upload(c->d_shell_pw, pws, acct);
+    }
     for (int a = 0; a < 3; ++a) {
         std::vector<double> t64;
         std::vector<float> t32;
@@ -406,6 +419,72 @@ pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void
     PW_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));
     PW_CHECK(h == 0, PW_ENOTPD, "matrix not positive definite at pivot %d", h - 1);
+    PW_API_END
+}
+
+pw_status pw_mlp_set(pw_ctx *ctx, const float *weights) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && weights, PW_EINVAL, "null argument");
+    PW_CHECK(mlp_nparam() == PW_MLP_NPARAM, PW_EINVAL, "parameter count mismatch");
+    if (!ctx->d_mlp.p) ctx->d_mlp.alloc(PW_MLP_NPARAM * sizeof(float));
+    PW_HIP(hipMemcpy(ctx->d_mlp.p, weights, PW_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice));
+    std::vector<float> h(PW_MLP_NPARAM);
+    PW_HIP(hipMemcpy(h.data(), weights, PW_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    for (float x : h) PW_CHECK(std::isfinite(x), PW_ENAN, "non-finite network weight");
+    PW_API_END
+}
+
+pw_status pw_mlp_forward(int32_t nshell, int32_t nb, const double *shell_t, const double *tband, double e_ref,
+                         double ecut, const float *weights, float *f, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(nshell >= 1 && nb >= 1 && shell_t && tband && weights && f && ecut > 0, PW_EINVAL,
+             "bad pw_mlp_forward arguments");
+    mlp_infer(nshell, nb, shell_t, tband, e_ref, ecut, weights, f, (hipStream_t)stream);
+    PW_API_END
+}
+
+int64_t pw_mlp_work_bytes(int32_t nshell, int32_t nb, int32_t nsnap) {
+    if (nshell < 1 || nb < 1 || nsnap < 1) return -1;
+    return (int64_t)mlp_work_bytes(nshell, nb, nsnap);
+}
+
+pw_status pw_mlp_loss_grad(int32_t nshell, int32_t nb, int32_t nsnap, const double *shell_t, const double *tband,
+                           const double *e_ref, double ecut, const double *tabs, const float *weights, float *grad,
+                           float *loss, void *work, int64_t work_bytes, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(nshell >= 1 && nb >= 1 && nsnap >= 1 && shell_t && tband && e_ref && tabs && weights && grad && work &&
+                 ecut > 0, PW_EINVAL, "bad pw_mlp_loss_grad arguments");
+    PW_CHECK(work_bytes >= (int64_t)mlp_work_bytes(nshell, nb, nsnap), PW_EINVAL, "work buffer too small");
+    mlp_loss_grad(nshell, nb, nsnap, shell_t, tband, e_ref, ecut, tabs, weights, grad, loss, work,
+                  (hipStream_t)stream);
+    PW_API_END
+}
+
+pw_status pw_mlp_adam(float *weights, const float *grad, float *m, float *v, int32_t step, float lr, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(weights && grad && m && v && step >= 1 && lr > 0, PW_EINVAL, "bad pw_mlp_adam arguments");
+    mlp_adam(weights, grad, m, v, step, lr, (hipStream_t)stream);
+    PW_API_END
+}
+
+pw_status pw_mlp_train(int32_t nshell, int32_t nb, int32_t nsnap, const double *shell_t, const double *tband,
+                       const double *e_ref, double ecut, const double *tabs, float *weights, float *grad, float *m,
+                       float *v, int32_t step0, int32_t nsteps, float lr, float *loss_hist, void *work,
+                       int64_t work_bytes, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(nshell >= 1 && nb >= 1 && nsnap >= 1 && nsteps >= 0 && step0 >= 0 && lr > 0 && shell_t && tband &&
+                 e_ref && tabs && weights && grad && m && v && work, PW_EINVAL, "bad pw_mlp_train arguments");
+    PW_CHECK(work_bytes >= (int64_t)mlp_work_bytes(nshell, nb, nsnap) + (int64_t)sizeof(float) * (nsteps + 64),
+             PW_EINVAL, "work buffer too small (needs pw_mlp_work_bytes + 4 (nsteps + 64) bytes)");
+    hipStream_t st = (hipStream_t)stream;
+    float *losses = (float *)((char *)work + mlp_work_bytes(nshell, nb, nsnap));
+    for (int t = 0; t < nsteps; ++t) {
+        mlp_loss_grad(nshell, nb, nsnap, shell_t, tband, e_ref, ecut, tabs, weights, grad, losses + t, work, st);
+        mlp_adam(weights, grad, m, v, step0 + t + 1, lr, st);
+    }
+    if (loss_hist && nsteps > 0)
+        PW_HIP(hipMemcpyAsync(loss_hist, losses, sizeof(float) * nsteps, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
     PW_API_END
 }
 

@@ -143,6 +143,8 @@ struct pw_ctx {
     pw::DevBuf d_proj;               // projections [nproj][max_bands] complex128
     pw::DevBuf d_partial;            // split-K partial sums
     pw::DevBuf d_ortho_ws, d_ortho_small;   // pw_orthonormalize scratch
+    pw::DevBuf d_shell_t, d_shell_off, d_shell_pw;   // shell energies and plane waves grouped by shell
+    pw::DevBuf d_mlp;                // learned-preconditioner weights (float32), empty until pw_mlp_set
     pw::Solver *solver = nullptr;
     // profiling (pw_profile_begin / pw_profile_end)
     bool prof_on = false;

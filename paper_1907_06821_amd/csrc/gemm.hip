@@ -38,7 +38,8 @@ __device__ inline void cmfma(const double2 a, const double2 b, v4d &ar, v4d &ai)
 // NT split-K partials: partial[s][m][n] = sum_{k in chunk s} op(A[m][k]) * B[n][k]
 // op = conj when CONJA.  Waves WM x WN, each BM x BN blocks of 16 x 16.
 // ---------------------------------------------------------------------------
-template <int WM, int WN, int BM, int BN, bool CONJA>
+// TAG only separates the projector launches from the block-algebra ones in profiles
+template <int WM, int WN, int BM, int BN, bool CONJA, int TAG>
 __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, int K, const double2 *__restrict__ A,
                                                                  int64_t lda, const double2 *__restrict__ B,
                                                                  int64_t ldb, int kchunk,
@@ -154,7 +155,7 @@ struct NNBatch {
     double2 *Out[4];
 };
 
-template <int WM, int WJ, int BM, int BJ>
+template <int WM, int WJ, int BM, int BJ, int TAG>
 __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, int K, const double2 *__restrict__ W,
                                                                 int64_t ldw, NNBatch bt, int64_t ldx, double alpha,
                                                                 double beta, int64_t ldo) {
@@ -263,7 +264,7 @@ size_t nt_partial_bytes(int M, int N, int K) {
 // C (M x N, ldc) = alpha * rowscale o (op(A) B^T) (+ beta C); trans: write C^T (N x M)
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
-              hipStream_t st) {
+              hipStream_t st, bool proj) {
     if (M <= 0 || N <= 0) return;
     const int ns = nt_splits(M, N, K);
     int kchunk = (K + ns - 1) / ns;
@@ -272,11 +273,14 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     dim3 grid((M + NT_TM - 1) / NT_TM, (N + NT_TN - 1) / NT_TN, nsplit);
     if (K <= 0) {
         fill_zero(partial, (size_t)M * N * sizeof(double2), st);
+    } else if (conja && proj) {
+        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, true, 1>), grid, dim3(256), 0, st, M, N, K,
+                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
     } else if (conja) {
-        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, true>), grid, dim3(256), 0, st, M, N, K,
+        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, true, 0>), grid, dim3(256), 0, st, M, N, K,
                            (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
     } else {
-        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, false>), grid, dim3(256), 0, st, M, N, K,
+        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, false, 0>), grid, dim3(256), 0, st, M, N, K,
                            (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
     }
     PW_LAUNCH_CHECK();
@@ -293,7 +297,7 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
 
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
-                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st) {
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st, bool proj) {
     if (M <= 0 || J <= 0 || nz <= 0) return;
     PW_CHECK(nz <= 4, PW_EINVAL, "at most 4 blocks per batched rotation");
     NNBatch bt{};
@@ -301,25 +305,29 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.X[z] = (const double2 *)X[z];
         bt.Out[z] = (double2 *)Out[z];
     }
-    if (M > 64) {
+    if (M > 64 && proj) {
+        dim3 grid((J + 63) / 64, (M + 127) / 128, nz);
+        hipLaunchKernelGGL((zgemm_nn_kernel<4, 1, 2, 4, 1>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
+                           bt, ldx, alpha, beta, ldo);
+    } else if (M > 64) {
         // 128 x 64 tiles: 4 waves stacked in M, each 32 x 64
         dim3 grid((J + 63) / 64, (M + 127) / 128, nz);
-        hipLaunchKernelGGL((zgemm_nn_kernel<4, 1, 2, 4>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
+        hipLaunchKernelGGL((zgemm_nn_kernel<4, 1, 2, 4, 0>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
                            bt, ldx, alpha, beta, ldo);
     } else {
         // 64 x 64 tiles: 2 x 2 waves, each 32 x 32
         dim3 grid((J + 63) / 64, (M + 63) / 64, nz);
-        hipLaunchKernelGGL((zgemm_nn_kernel<2, 2, 2, 2>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
+        hipLaunchKernelGGL((zgemm_nn_kernel<2, 2, 2, 2, 0>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
                            bt, ldx, alpha, beta, ldo);
     }
     PW_LAUNCH_CHECK();
 }
 
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
-                     double beta, void *Out, int64_t ldo, hipStream_t st) {
+                     double beta, void *Out, int64_t ldo, hipStream_t st, bool proj) {
     const void *xs[1] = {X};
     void *os[1] = {Out};
-    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st);
+    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st, proj);
 }
 
 }  // namespace pw

@@ -16,11 +16,11 @@ int nt_splits(int M, int N, int K);
 size_t nt_partial_bytes(int M, int N, int K);
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
-              hipStream_t);
+              hipStream_t, bool proj = false);
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
-                     double beta, void *Out, int64_t ldo, hipStream_t);
+                     double beta, void *Out, int64_t ldo, hipStream_t, bool proj = false);
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
-                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t);
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t, bool proj = false);
 
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
 size_t cnt_partial_bytes(int M, int N, int K);
@@ -33,6 +33,17 @@ void backproj_bf16(int nb, int npw, int nproj, const void *projT, const void *be
 void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t);
 void jacobi_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
                  double ref, int *info, hipStream_t);
+
+// mlp.hip
+int mlp_nparam();
+void mlp_infer(int nshell, int nb, const double *shell_t, const double *tband, double e_ref, double ecut,
+               const float *w, float *f, hipStream_t);
+size_t mlp_work_bytes(int nshell, int nb, int nsnap);
+void mlp_loss_grad(int nshell, int nb, int nsnap, const double *shell_t, const double *tband, const double *e_ref,
+                   double ecut, const double *tabs, const float *w, float *grad, float *loss, void *work, hipStream_t);
+void mlp_adam(float *w, const float *g, float *m, float *v, int step, float lr, hipStream_t);
+void shell_tables(int nshell, int nb, int npw, const int32_t *shell_off, const int32_t *shell_pw, const void *E,
+                  const void *Z, int64_t ld, double *tabs, hipStream_t);
 
 // blas1.hip -------------------------------------------------------------------
 struct PrecArgs {

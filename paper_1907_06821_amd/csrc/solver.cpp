@@ -35,6 +35,7 @@ struct Solver {
     DevBuf vec;                    // per-band vectors
     DevBuf red;                    // reduction partials
     DevBuf status;                 // ints
+    DevBuf ftab;                   // learned preconditioner scaling [nshell][nb] (float)
     int nsplit = 0;
 };
 
@@ -58,6 +59,7 @@ static Solver *solver_get(pw_ctx *ctx, int nb, bool mixed) {
         s->nsplit = band_splits(npw);
         s->red.alloc((size_t)4 * s->nbmax * s->nsplit * 8);
         s->status.alloc(256);
+        s->ftab.alloc((size_t)ctx->basis.shell_t.size() * s->nbmax * sizeof(float));
         ctx->solver = s;
         ctx->device_bytes += (int64_t)(11 * blk + 6 * nn + s->vec.bytes + s->red.bytes + 256);
     }
@@ -91,7 +93,8 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
     bool use_mixed = mixed;
 
     PrecArgs pa{};
-    pa.kind = o.precond == 1 ? 1 : 0;
+    pa.kind = o.precond;
+    pa.ftab = s->ftab.as<float>();
     pa.kin = ctx->d_kin.as<double>();
     pa.tband = tband;
     pa.e_ref = E;
@@ -176,8 +179,17 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
     int nhist = 0;
     const int check = std::max(1, o.check_every);
     pw_status result = PW_OK;
-    for (it = 1; it <= o.maxit; ++it) {
+    const int nshell = (int)ctx->basis.shell_t.size();
+    // band kinetic energies, then (learned preconditioner) the per-shell scaling table
+    auto band_stats = [&]() {
         red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
+        if (pa.kind == 2)
+            mlp_infer(nshell, nb, ctx->d_shell_t.as<double>(), tband, E, ctx->cell.ecut, ctx->d_mlp.as<float>(),
+                      s->ftab.as<float>(), st);
+    };
+    int nsnap = 0;
+    for (it = 1; it <= o.maxit; ++it) {
+        band_stats();
         red_grad(nb, npw, X, AX, G, Z, L, mu, pa, gz, gzo, br, st);
         pupdate(nb, npw, Z, P, L, gz, gzo, gz_old, st);
         // P -= X (X^H P): W[b][j] = -<x_j|p_b>
@@ -188,12 +200,16 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
         line_coef(nb, mu, line4, coef, st);
         combine3(nb, npw, X, Y, AX, P, YP, AP, L, coef, st);
         orth();
+        if (o.snap_every > 0 && o.snap_buf && it % o.snap_every == 0 && nsnap < o.snap_cap) {
+            copy_block(nb, npw, X, L, (char *)o.snap_buf + (size_t)nsnap * nb * npw * 16, npw, st);
+            ++nsnap;
+        }
         if (it % check == 0 || it == o.maxit) {
             fold(X, Y, AX, false);
             a_rr(true);
             h_resid();
             // PR denominator for the rotated gradients
-            red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
+            band_stats();
             red_gzold(nb, npw, G, L, pa, gz_old, br, st);
             PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
             PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
@@ -272,14 +288,62 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
         stats->converged = converged ? 1 : 0;
         stats->n_hpsi = n_hpsi;
         stats->n_hist = nhist;
+        stats->n_snap = nsnap;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     }
     return result;
 }
 
+// Training tables of one snapshot (see pw_mlp_harvest in pw.h), using the solver's
+// blocks as scratch.
+void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, int64_t ld, double *tabs,
+                 double *tband_out, hipStream_t st) {
+    const int npw = ctx->basis.npw;
+    Solver *s = solver_get(ctx, nb, false);
+    const int64_t L = npw;
+    void *X = s->X.p, *Y = s->Y.p, *AX = s->AX.p, *G = s->G.p, *Z = s->Z.p, *T1 = s->T1.p, *Xc = s->T2.p;
+    double *v = (double *)s->vec.p;
+    double *mu = v, *tband = v + nb, *gz = v + 2 * nb, *gzo = v + 3 * nb;
+    double2 *Wm = (double2 *)s->small.p;
+    BandRed br{(double *)s->red.p, s->nsplit};
+    copy_block(nb, npw, xs, ld, X, L, st);
+    copy_block(nb, npw, xc, ld, Xc, L, st);
+    hpsi_any(ctx, PW_C128, nb, X, L, Y, L, E, st);
+    hpsi_any(ctx, PW_C128, nb, Y, L, AX, L, E, st);
+    red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
+    PrecArgs pa{};
+    pa.kind = 0;
+    pa.kin = ctx->d_kin.as<double>();
+    pa.tband = tband;
+    pa.nb = nb;
+    fill_zero(G, (size_t)nb * npw * 16, st);
+    red_grad(nb, npw, X, AX, G, Z, L, mu, pa, gz, gzo, br, st);     // G = A x - mu x, Z = K0 o G
+    // E = W . Xc - X with W[i][j] = <xc_j | x_i>: minus the part of x_i outside span(Xc)
+    zgemm_nt(nb, nb, npw, true, Xc, L, X, L, 1.0, nullptr, 0.0, Wm, nb, true, ctx->d_partial.p, st);
+    copy_block(nb, npw, X, L, T1, L, st);
+    zgemm_nn_launch(nb, npw, nb, Wm, nb, Xc, L, 1.0, -1.0, T1, L, st);
+    shell_tables((int)ctx->basis.shell_t.size(), nb, npw, ctx->d_shell_off.as<int32_t>(),
+                 ctx->d_shell_pw.as<int32_t>(), T1, Z, L, tabs, st);
+    PW_HIP(hipMemcpyAsync(tband_out, tband, nb * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
 }  // namespace pw
 
 extern "C" {
+
+pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
+                         double *tabs, double *tband, void *stream) {
+    try {
+        PW_CHECK(ctx && x_snap && x_conv && tabs && tband, PW_EINVAL, "null argument");
+        PW_CHECK(ctx->flags & PW_PREP_C128, PW_EUNSUPPORTED, "harvest needs a complex128 context");
+        PW_CHECK(nb >= 1 && nb <= ctx->max_bands && nb <= 1024 && ld >= ctx->basis.npw, PW_EINVAL,
+                 "bad harvest sizes");
+        pw::mlp_harvest(ctx, e_ref, nb, x_snap, x_conv, ld, tabs, tband, (hipStream_t)stream);
+        return PW_OK;
+    } catch (const pw::Fail &f) {
+        return f.st;
+    }
+}
 
 void pw_cg_opts_default(pw_cg_opts *o) {
     if (!o) return;
@@ -308,7 +372,9 @@ pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, i
         pw_cg_opts_default(&o);
         if (opts) o = *opts;
         PW_CHECK(o.tol > 0 && o.maxit >= 1 && o.check_every >= 1, PW_EINVAL, "bad solver options");
-        PW_CHECK(o.precond == 0 || o.precond == 1, PW_EUNSUPPORTED, "preconditioner %d not available", o.precond);
+        PW_CHECK(o.precond >= 0 && o.precond <= 2, PW_EINVAL, "preconditioner %d unknown", o.precond);
+        PW_CHECK(o.precond != 2 || ctx->d_mlp.p, PW_EUNSUPPORTED, "precond 2 needs pw_mlp_set first");
+        PW_CHECK(o.snap_every <= 0 || (o.snap_buf && o.snap_cap >= 0), PW_EINVAL, "snapshots need a buffer");
         PW_CHECK(o.precision == 0 || o.precision == 1, PW_EINVAL, "precision must be 0 or 1");
         if (o.precision == 1)
             PW_CHECK(ctx->flags & PW_PREP_C64, PW_EUNSUPPORTED, "mixed precision needs PW_PREP_C64");
