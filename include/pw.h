@@ -172,6 +172,8 @@ typedef struct {
     void *snap_buf;       /* optional device complex128 [snap_cap][nb][npw]: iterate snapshots for training */
     int32_t snap_every;   /* store X after every snap_every-th iteration (0 = never) */
     int32_t snap_cap;     /* capacity of snap_buf in snapshots */
+    int32_t nconv;        /* only the nconv Ritz pairs nearest e_ref must reach tol (0 = all nb); the
+                             other nb - nconv bands are buffer bands that widen the folded gap */
 } pw_cg_opts;
 
 typedef struct {
@@ -204,7 +206,8 @@ pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, i
  * network with output 8 tanh(r/8); the CG uses K_i(G) = K_TPA(T_G/T_i)^2 exp(f).
  * Parameters (float32, PW_MLP_NPARAM): W1[64][3], b1[64], W2[64][64], b2[64],
  * W3[64], b3.  Training loss per band and snapshot: 1 - Re<K g, e>/(|K g| |e|),
- * e = -(I - Psi* Psi*^H) psi the band's error outside the converged subspace; it
+ * e = (I - Psi* Psi*^H) psi the band's error outside the converged subspace (the
+ * CG steps along -K g, so K g should point along e); it
  * depends on a snapshot only through shell tables A_si = sum_{G in s} Re(conj e
  * K0 g), B_si = sum |K0 g|^2, C_si = sum |e|^2 (doubles, [3][nshell][nb]).
  * All pointers below are device pointers unless stated.

@@ -10,8 +10,9 @@ Network (3 -> 64 -> 64 -> 1, tanh), per |G+k| shell s and band i:
     f_si   = 8 tanh(r / 8)                      (smooth clamp to [-8, 8])
 Preconditioner: K_i(G) = K0_i(G) exp(f_{s(G), i}) with K0 the folded TPA weight.
 
-Loss (one snapshot): for band i with gradient g_i and target correction
-e_i = -(I - Psi* Psi*^H) psi_i (psi_i's error outside the converged subspace),
+Loss (one snapshot): for band i with gradient g_i and error
+e_i = (I - Psi* Psi*^H) psi_i (the part of psi_i outside the converged subspace;
+the CG steps along -z_i, so the ideal preconditioned gradient points along e_i),
 z_i = K_i o g_i and
     L_i = 1 - Re<z_i, e_i> / (||z_i|| ||e_i||).
 With shell sums A_si = sum_{G in s} Re(conj(e_i) K0_i g_i), B_si = sum_{G in s}
@@ -128,7 +129,7 @@ def harvest_tables(x_snap, x_conv, g, k0, shell, nshell):
     g [nb][npw] gradients, k0 [nb][npw] base preconditioner weights, shell [npw].
     Returns A [nshell][nb], B [nshell][nb], E [nb]."""
     coef = x_snap @ x_conv.conj().T            # [i][j] = <x_conv_j | x_i>
-    e = -(x_snap - coef @ x_conv)              # -(I - P*) x_i
+    e = x_snap - coef @ x_conv                 # (I - P*) x_i
     kg = k0 * g
     nb = x_snap.shape[0]
     a = np.zeros((nshell, nb))

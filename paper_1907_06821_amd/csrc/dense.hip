@@ -87,6 +87,10 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(int N, const double2 *__
 // ---------------------------------------------------------------------------
 __device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
+// largest matrix whose packed triangle (N (N + 1) / 2 complex128) fits in LDS
+constexpr int kLdsMaxN = 136;
+constexpr int kLdsPairs = kLdsMaxN / 2;
+
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
                                                           double2 *__restrict__ T, int *__restrict__ status) {
@@ -138,22 +142,34 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
     for (int j = N - 1; j >= 0; --j) {
         constexpr int G = NT / 128;
         const double djj = 1.0 / L[tri(j, j)].x;
-        double ar = 0.0, ai = 0.0;
-        const int i = j + 1 + tid / G, sub = tid % G;
-        if (i < N) {
-            for (int k = j + 1 + sub; k <= i; k += G) {
-                const double2 a = L[tri(i, k)], b = L[tri(k, j)];   // Linv[i][k], L[k][j]
-                ar += a.x * b.x - a.y * b.y;
-                ai += a.x * b.y + a.y * b.x;
-            }
-        }
+        const int sub = tid % G;
+        double rr[2], ri[2];
+        // rows j+1+tid/G and j+1+tid/G+128 (N <= 256)
 #pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) {
-            ar += __shfl_xor(ar, o, G);
-            ai += __shfl_xor(ai, o, G);
+        for (int h = 0; h < 2; ++h) {
+            double ar = 0.0, ai = 0.0;
+            const int i = j + 1 + tid / G + h * (NT / G);
+            if (i < N) {
+                for (int k = j + 1 + sub; k <= i; k += G) {
+                    const double2 a = L[tri(i, k)], b = L[tri(k, j)];   // Linv[i][k], L[k][j]
+                    ar += a.x * b.x - a.y * b.y;
+                    ai += a.x * b.y + a.y * b.x;
+                }
+            }
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                ar += __shfl_xor(ar, o, G);
+                ai += __shfl_xor(ai, o, G);
+            }
+            rr[h] = ar;
+            ri[h] = ai;
         }
         __syncthreads();
-        if (i < N && sub == 0) L[tri(i, j)] = make_double2(-ar * djj, -ai * djj);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = j + 1 + tid / G + h * (NT / G);
+            if (i < N && sub == 0) L[tri(i, j)] = make_double2(-rr[h] * djj, -ri[h] * djj);
+        }
         if (tid == 0) L[tri(j, j)] = make_double2(djj, 0.0);
         __syncthreads();
     }
@@ -338,9 +354,9 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(int N, const double2 *__
                                                         double tol, int *__restrict__ info) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);            // packed lower triangle
-    __shared__ int pp[64], qq[64];
-    __shared__ double cs[64], sn[64];
-    __shared__ double2 ph[64];
+    __shared__ int pp[kLdsPairs], qq[kLdsPairs];
+    __shared__ double cs[kLdsPairs], sn[kLdsPairs];
+    __shared__ double2 ph[kLdsPairs];
     __shared__ double red[NT];
     __shared__ int sweeps_done;
     const int tid = threadIdx.x;
@@ -409,7 +425,7 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(int N, const double2 *__
             // eigenvector rows, first half: Vt[p] <- c Vt[p] - s e Vt[q], Vt[q] <- s Vt[p] + c e Vt[q].
             // Each element is touched once per round, so every load is issued here,
             // ahead of the LDS block updates, and the stores follow them.
-            constexpr int MAXIT = 64 * 128 / NT;
+            constexpr int MAXIT = (kLdsPairs * kLdsMaxN + NT - 1) / NT;
             double2 vp[MAXIT], vq[MAXIT];
 #pragma unroll
             for (int it = 0; it < MAXIT; ++it) {
@@ -504,7 +520,7 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(int N, const double2 *__
 // host wrappers
 // ---------------------------------------------------------------------------
 void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t st) {
-    if (N <= 128) {
+    if (N <= kLdsMaxN) {
         PW_CHECK(N > 0 && N < 4096, PW_EINVAL, "bad Cholesky size");   // inverse keeps one band per thread
         const size_t bytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
         static size_t attr_bytes = 64 * 1024;   // default dynamic LDS limit
@@ -525,7 +541,7 @@ void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *statu
 void jacobi_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
                  double ref, int *info, hipStream_t st) {
     PW_CHECK(N <= 1024, PW_EUNSUPPORTED, "Jacobi eigensolver limited to N <= 1024");
-    if (N <= 128) {
+    if (N <= kLdsMaxN) {
         const size_t bytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
         static size_t attr_bytes = 64 * 1024;
         if (bytes > attr_bytes) {

@@ -46,8 +46,7 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
                                                                  double2 *__restrict__ partial) {
     constexpr int NT = WM * WN * 64;
     constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
-    constexpr int LA = TM * KT / NT, LB = TN * KT / NT;     // complex loads per thread per stage
-    static_assert(TM * KT % NT == 0 && TN * KT % NT == 0, "tile/thread mismatch");
+    constexpr int LA = (TM * KT + NT - 1) / NT, LB = (TN * KT + NT - 1) / NT;   // loads per thread per stage
     __shared__ double2 As[TM][KT + 1];
     __shared__ double2 Bs[TN][KT + 1];
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN, s = blockIdx.z;
@@ -65,19 +64,25 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
 #pragma unroll
         for (int it = 0; it < LA; ++it) {
             const int e = tid + it * NT, r = e / KT, kk = e % KT, gk = k0 + kk, gm = m0 + r;
-            ra[it] = (gm < M && gk < kend) ? A[(int64_t)gm * lda + gk] : make_double2(0.0, 0.0);
+            ra[it] = (e < TM * KT && gm < M && gk < kend) ? A[(int64_t)gm * lda + gk] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int it = 0; it < LB; ++it) {
             const int e = tid + it * NT, r = e / KT, kk = e % KT, gk = k0 + kk, gn = n0 + r;
-            rb[it] = (gn < N && gk < kend) ? B[(int64_t)gn * ldb + gk] : make_double2(0.0, 0.0);
+            rb[it] = (e < TN * KT && gn < N && gk < kend) ? B[(int64_t)gn * ldb + gk] : make_double2(0.0, 0.0);
         }
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int it = 0; it < LA; ++it) { const int e = tid + it * NT; As[e / KT][e % KT] = ra[it]; }
+        for (int it = 0; it < LA; ++it) {
+            const int e = tid + it * NT;
+            if (e < TM * KT) As[e / KT][e % KT] = ra[it];
+        }
 #pragma unroll
-        for (int it = 0; it < LB; ++it) { const int e = tid + it * NT; Bs[e / KT][e % KT] = rb[it]; }
+        for (int it = 0; it < LB; ++it) {
+            const int e = tid + it * NT;
+            if (e < TN * KT) Bs[e / KT][e % KT] = rb[it];
+        }
     };
     if (kbeg < kend) {
         fetch(kbeg);
@@ -161,8 +166,7 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
                                                                 double beta, int64_t ldo) {
     constexpr int NT = WM * WJ * 64;
     constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
-    constexpr int LW = TM * KT / NT, LX = KT * TJ / NT;
-    static_assert(TM * KT % NT == 0 && KT * TJ % NT == 0, "tile/thread mismatch");
+    constexpr int LW = (TM * KT + NT - 1) / NT, LX = (KT * TJ + NT - 1) / NT;
     __shared__ double2 Ws[TM][KT + 1];
     __shared__ double2 Xs[KT][TJ + 1];
     const double2 *__restrict__ X = bt.X[blockIdx.z];
@@ -180,19 +184,25 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
 #pragma unroll
         for (int it = 0; it < LW; ++it) {
             const int e = tid + it * NT, r = e / KT, kk = e % KT, gm = m0 + r, gk = k0 + kk;
-            rw[it] = (gm < M && gk < K) ? W[(int64_t)gm * ldw + gk] : make_double2(0.0, 0.0);
+            rw[it] = (e < TM * KT && gm < M && gk < K) ? W[(int64_t)gm * ldw + gk] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int it = 0; it < LX; ++it) {
             const int e = tid + it * NT, kk = e / TJ, c = e % TJ, gk = k0 + kk, gj = j0 + c;
-            rx[it] = (gk < K && gj < J) ? X[(int64_t)gk * ldx + gj] : make_double2(0.0, 0.0);
+            rx[it] = (e < KT * TJ && gk < K && gj < J) ? X[(int64_t)gk * ldx + gj] : make_double2(0.0, 0.0);
         }
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int it = 0; it < LW; ++it) { const int e = tid + it * NT; Ws[e / KT][e % KT] = rw[it]; }
+        for (int it = 0; it < LW; ++it) {
+            const int e = tid + it * NT;
+            if (e < TM * KT) Ws[e / KT][e % KT] = rw[it];
+        }
 #pragma unroll
-        for (int it = 0; it < LX; ++it) { const int e = tid + it * NT; Xs[e / TJ][e % TJ] = rx[it]; }
+        for (int it = 0; it < LX; ++it) {
+            const int e = tid + it * NT;
+            if (e < KT * TJ) Xs[e / TJ][e % TJ] = rx[it];
+        }
     };
     if (K > 0) {
         fetch(0);
@@ -241,13 +251,16 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
-// NT tile 64 x 128 (4 waves of 32 x 64)
-constexpr int NT_TM = 64, NT_TN = 128;
+// NT tiles: TM = 64 rows of A; TN = 64 (N <= 64), 128 (N <= 128) or 144 (N <= 144,
+// for 128 wanted bands plus buffer bands), else 128.
+static int nt_tn(int N) { return N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128)); }
+constexpr int NT_TM = 64;
 
 // K-splits: enough workgroups to cover the chip (~512) while keeping at least
 // four LDS stages per chunk and the partial sums under 64 MiB.
 int nt_splits(int M, int N, int K) {
-    const int tiles = ((M + NT_TM - 1) / NT_TM) * ((N + NT_TN - 1) / NT_TN);
+    const int tn = nt_tn(N);
+    const int tiles = ((M + NT_TM - 1) / NT_TM) * ((N + tn - 1) / tn);
     int s = (512 + tiles - 1) / tiles;
     const int maxs = (K + 4 * KT - 1) / (4 * KT);
     if (s > maxs) s = maxs;
@@ -261,6 +274,21 @@ size_t nt_partial_bytes(int M, int N, int K) {
     return (size_t)nt_splits(M, N, K) * M * N * sizeof(double2);
 }
 
+template <int WM, int WN, int BM, int BN>
+static void nt_go(dim3 grid, bool conja, bool proj, hipStream_t st, int M, int N, int K, const void *A, int64_t lda,
+                  const void *B, int64_t ldb, int kchunk, void *partial) {
+    const dim3 blk(WM * WN * 64);
+    if (conja && proj)
+        hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, true, 1>), grid, blk, 0, st, M, N, K, (const double2 *)A,
+                           lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
+    else if (conja)
+        hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, true, 0>), grid, blk, 0, st, M, N, K, (const double2 *)A,
+                           lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
+    else
+        hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, false, 0>), grid, blk, 0, st, M, N, K,
+                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
+}
+
 // C (M x N, ldc) = alpha * rowscale o (op(A) B^T) (+ beta C); trans: write C^T (N x M)
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
@@ -270,19 +298,12 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     int kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + KT - 1) / KT) * KT;
     const int nsplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
-    dim3 grid((M + NT_TM - 1) / NT_TM, (N + NT_TN - 1) / NT_TN, nsplit);
-    if (K <= 0) {
-        fill_zero(partial, (size_t)M * N * sizeof(double2), st);
-    } else if (conja && proj) {
-        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, true, 1>), grid, dim3(256), 0, st, M, N, K,
-                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
-    } else if (conja) {
-        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, true, 0>), grid, dim3(256), 0, st, M, N, K,
-                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
-    } else {
-        hipLaunchKernelGGL((zgemm_nt_partial<2, 2, 2, 4, false, 0>), grid, dim3(256), 0, st, M, N, K,
-                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
-    }
+    const int tn = nt_tn(N);
+    dim3 grid((M + NT_TM - 1) / NT_TM, (N + tn - 1) / tn, nsplit);
+    if (K <= 0) fill_zero(partial, (size_t)M * N * sizeof(double2), st);
+    else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tn == 128) nt_go<2, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else nt_go<2, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     PW_LAUNCH_CHECK();
     const int64_t tot = (int64_t)M * N;
     const int nblk = (int)((tot + 255) / 256);
@@ -295,7 +316,22 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     PW_LAUNCH_CHECK();
 }
 
+template <int WM, int WJ, int BM, int BJ>
+static void nn_go(int nz, bool proj, hipStream_t st, int M, int J, int K, const void *W, int64_t ldw,
+                  const NNBatch &bt, int64_t ldx, double alpha, double beta, int64_t ldo) {
+    constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
+    dim3 grid((J + TJ - 1) / TJ, (M + TM - 1) / TM, nz);
+    const dim3 blk(WM * WJ * 64);
+    if (proj)
+        hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 1>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
+                           bt, ldx, alpha, beta, ldo);
+    else
+        hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 0>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
+                           bt, ldx, alpha, beta, ldo);
+}
+
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
+// M tiles: 64 (M <= 64), 144 (128 < M <= 144), else 128.
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
                     double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st, bool proj) {
     if (M <= 0 || J <= 0 || nz <= 0) return;
@@ -305,21 +341,9 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.X[z] = (const double2 *)X[z];
         bt.Out[z] = (double2 *)Out[z];
     }
-    if (M > 64 && proj) {
-        dim3 grid((J + 63) / 64, (M + 127) / 128, nz);
-        hipLaunchKernelGGL((zgemm_nn_kernel<4, 1, 2, 4, 1>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
-                           bt, ldx, alpha, beta, ldo);
-    } else if (M > 64) {
-        // 128 x 64 tiles: 4 waves stacked in M, each 32 x 64
-        dim3 grid((J + 63) / 64, (M + 127) / 128, nz);
-        hipLaunchKernelGGL((zgemm_nn_kernel<4, 1, 2, 4, 0>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
-                           bt, ldx, alpha, beta, ldo);
-    } else {
-        // 64 x 64 tiles: 2 x 2 waves, each 32 x 32
-        dim3 grid((J + 63) / 64, (M + 63) / 64, nz);
-        hipLaunchKernelGGL((zgemm_nn_kernel<2, 2, 2, 2, 0>), grid, dim3(256), 0, st, M, J, K, (const double2 *)W, ldw,
-                           bt, ldx, alpha, beta, ldo);
-    }
+    if (M <= 64) nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
+    else if (M > 128 && M <= 144) nn_go<3, 1, 3, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
+    else nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
     PW_LAUNCH_CHECK();
 }
 

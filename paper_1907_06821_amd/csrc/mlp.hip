@@ -7,8 +7,9 @@
 //   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), r = W3 h2 + b3, f = 8 tanh(r / 8)
 //   loss (per band, per snapshot): 1 - sum_s w A / (sqrt(sum_s w^2 B) sqrt(E)), w = exp(f)
 // with A_si = sum_{G in s} Re(conj e_i . K0 g_i), B_si = sum_{G in s} |K0 g_i|^2,
-// E_i = ||e_i||^2, e_i = -(I - Psi* Psi*^H) psi_i the band's error outside the converged
-// subspace.  Parameters: W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3 (4481 floats).
+// E_i = ||e_i||^2, e_i = (I - Psi* Psi*^H) psi_i the band's error outside the converged
+// subspace (the CG steps along -K g, so K g should point along e).  Parameters:
+// W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3 (4481 floats).
 #include "kernels.h"
 
 namespace pw {
@@ -281,7 +282,7 @@ void mlp_adam(float *w, const float *g, float *m, float *v, int step, float lr, 
 }
 
 // ---------------------------------------------------------------------------
-// harvest: shell sums of one snapshot.  E = -(I - P*) X (band-major, [nb][npw]),
+// harvest: shell sums of one snapshot.  E = (I - P*) X (band-major, [nb][npw]),
 // Z = K0 o g.  tabs[0][s][i] = sum Re(conj E . Z), [1] = sum |Z|^2, [2] = sum |E|^2,
 // summed over the plane waves of shell s listed in shell_pw[shell_off[s] ..].
 // ---------------------------------------------------------------------------

@@ -171,6 +171,16 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
     fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
 
     std::vector<double> h_lam(nb), h_res(nb);
+    // largest residual among the nconv Ritz values (theta - E) nearest zero
+    const int nwant = (o.nconv > 0 && o.nconv < nb) ? o.nconv : nb;
+    auto wanted_max = [&](const std::vector<double> &lamv, const std::vector<double> &resv) {
+        std::vector<int> idx(nb);
+        for (int b = 0; b < nb; ++b) idx[b] = b;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return std::fabs(lamv[a]) < std::fabs(lamv[c]); });
+        double m = 0.0;
+        for (int r = 0; r < nwant; ++r) m = std::max(m, resv[idx[r]]);
+        return m;
+    };
     int h_status[8];
     int it = 0;
     bool converged = false;
@@ -220,12 +230,10 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
                 result = PW_ENOTPD;
                 break;
             }
-            double mx = 0.0;
             bool finite = true;
-            for (int b = 0; b < nb; ++b) {
+            for (int b = 0; b < nb; ++b)
                 if (!std::isfinite(h_res[b]) || !std::isfinite(h_lam[b])) finite = false;
-                mx = std::max(mx, h_res[b]);
-            }
+            const double mx = finite ? wanted_max(h_lam, h_res) : INFINITY;
             if (!finite) {
                 set_error("non-finite residual at iteration %d", it);
                 result = PW_ENAN;
@@ -265,12 +273,11 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
         PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
         PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
         PW_HIP(hipStreamSynchronize(st));
-        double mx = 0.0;
         for (int b = 0; b < nb; ++b) {
             if (eig) eig[b] = h_lam[b] + E;
             if (resid) resid[b] = h_res[b];
-            mx = std::max(mx, h_res[b]);
         }
+        const double mx = wanted_max(h_lam, h_res);
         if (!converged) {
             converged = mx <= o.tol;
             if (!converged) {
@@ -318,10 +325,10 @@ void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, 
     pa.nb = nb;
     fill_zero(G, (size_t)nb * npw * 16, st);
     red_grad(nb, npw, X, AX, G, Z, L, mu, pa, gz, gzo, br, st);     // G = A x - mu x, Z = K0 o G
-    // E = W . Xc - X with W[i][j] = <xc_j | x_i>: minus the part of x_i outside span(Xc)
+    // E = X - W . Xc with W[i][j] = <xc_j | x_i>: the part of x_i outside span(Xc)
     zgemm_nt(nb, nb, npw, true, Xc, L, X, L, 1.0, nullptr, 0.0, Wm, nb, true, ctx->d_partial.p, st);
     copy_block(nb, npw, X, L, T1, L, st);
-    zgemm_nn_launch(nb, npw, nb, Wm, nb, Xc, L, 1.0, -1.0, T1, L, st);
+    zgemm_nn_launch(nb, npw, nb, Wm, nb, Xc, L, -1.0, 1.0, T1, L, st);
     shell_tables((int)ctx->basis.shell_t.size(), nb, npw, ctx->d_shell_off.as<int32_t>(),
                  ctx->d_shell_pw.as<int32_t>(), T1, Z, L, tabs, st);
     PW_HIP(hipMemcpyAsync(tband_out, tband, nb * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -356,6 +363,10 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->verbose = 0;
     o->mixed_switch = 1e-4;
     o->stall_checks = 10;
+    o->snap_buf = nullptr;
+    o->snap_every = 0;
+    o->snap_cap = 0;
+    o->nconv = 0;
 }
 
 pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld, double *eig,

@@ -14,7 +14,7 @@ def _herm(n, seed, spread=1.0):
     return (q * w) @ q.conj().T, w
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 128, 160])
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 128, 136, 137, 160])
 def test_dense_eigh_random(torch_cuda, n):
     import torch
     import paper_1907_06821_amd as pw
@@ -56,7 +56,7 @@ def test_dense_eigh_key_orders_by_distance(torch_cuda):
     assert np.max(np.abs(np.sort(w) - w_ref)) < 1e-13
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 128, 200])
+@pytest.mark.parametrize("n", [1, 5, 64, 128, 136, 137, 200])
 def test_dense_chol_inv(torch_cuda, n):
     import torch
     import paper_1907_06821_amd as pw

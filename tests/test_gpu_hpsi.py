@@ -124,17 +124,18 @@ def test_hpsi_chunks_and_strides(torch_cuda):
     pw.hpsi(ctx, big[:0, :op.npw], out=out[:0, :op.npw])
 
 
-def test_hpsi_wire256_sampled_bands(torch_cuda):
+@pytest.mark.parametrize("nb", [128, 136])
+def test_hpsi_wire256_sampled_bands(torch_cuda, nb):
     """Full wire cell (48x48x192 grid, 1024 projectors) in the benchmark's launch
-    shape (128 bands at once); sampled bands checked against the oracle's
-    matrix-free H psi."""
+    shape (128 bands, or 136 with buffer bands, at once); sampled bands checked
+    against the oracle's matrix-free H psi."""
     import paper_1907_06821_amd as pw
     prob = synth.config(2)
     op = oracle_for(prob)
-    ctx = gpu_context(prob, max_bands=128)
-    c = random_block(6, 128, op.npw)
+    ctx = gpu_context(prob, max_bands=nb)
+    c = random_block(6, nb, op.npw)
     got = pw.hpsi(ctx, to_dev(c), shift=prob.e_ref).cpu().numpy()
-    for b in (0, 57, 127):
+    for b in (0, 57, nb - 1):
         ref = op.apply(c[b:b + 1], shift=prob.e_ref)[0]
         err_ = rel_err(got[b], ref)
         assert err_ < 1e-12, err_
@@ -172,17 +173,18 @@ def test_hpsi_c64_error_bound(torch_cuda):
         assert err <= bound, (b, err, bound)
 
 
-def test_orthonormalize_matches_oracle(torch_cuda):
+@pytest.mark.parametrize("nb", [128, 136, 150])
+def test_orthonormalize_matches_oracle(torch_cuda, nb):
     import paper_1907_06821_amd as pw
     from oracle.eigen import cholesky_orthonormalize
     prob = synth.config(2)
-    ctx = gpu_context(prob, max_bands=128)
-    c = random_block(9, 128, ctx.npw)
+    ctx = gpu_context(prob, max_bands=nb)
+    c = random_block(9, nb, ctx.npw)
     t = to_dev(c)
     pw.orthonormalize(ctx, t)
     got = t.cpu().numpy()
     s = got.conj() @ got.T
-    assert np.max(np.abs(s - np.eye(128))) < 1e-12
+    assert np.max(np.abs(s - np.eye(nb))) < 1e-12
     ref = cholesky_orthonormalize(c)
     err_ = rel_err(got, ref)
     assert err_ < 1e-11, err_

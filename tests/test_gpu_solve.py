@@ -87,3 +87,19 @@ def test_solve_deterministic(torch_cuda):
     e1, r1, s1, v1 = _solve(ctx, prob, psi0, tol=1e-9, maxit=2000, check_every=10)
     e2, r2, s2, v2 = _solve(ctx, prob, psi0, tol=1e-9, maxit=2000, check_every=10)
     assert np.array_equal(e1, e2) and np.array_equal(v1, v2) and s1["iters"] == s2["iters"]
+
+
+def test_solve_buffer_bands(torch_cuda):
+    """nb = 10 with nconv = 8: the 8 Ritz pairs nearest E_ref are the dense
+    nearest eigenpairs; the two buffer bands need not converge."""
+    prob = synth.config(1)
+    op = oracle_for(prob)
+    lam, u, _, _ = nearest_eigenpairs(op.dense(), prob.e_ref, 8)
+    ctx = gpu_context(prob, max_bands=10)
+    psi0 = synth.start_vectors(1, 10, op.npw)
+    eig, res, st, vec = _solve(ctx, prob, psi0, tol=1e-9, maxit=5000, check_every=10, nconv=8, precond=1)
+    assert st["converged"]
+    near = np.sort(np.argsort(np.abs(eig - prob.e_ref))[:8])
+    assert np.max(np.abs(eig[near] - lam)) < 1e-8
+    assert np.max(res[near]) <= 1e-9
+    assert principal_cosines(u, vec[near]).min() > 1 - 1e-8
