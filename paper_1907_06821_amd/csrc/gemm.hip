@@ -342,7 +342,7 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.Out[z] = (double2 *)Out[z];
     }
     if (M <= 64) nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
-    else if (M > 128 && M <= 144) nn_go<3, 1, 3, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
+    else if (M > 128 && M <= 144) nn_go<9, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
     else nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
     PW_LAUNCH_CHECK();
 }
