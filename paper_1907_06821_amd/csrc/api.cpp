@@ -398,11 +398,12 @@ pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *
     DevBuf work;
     work.alloc((size_t)2 * n * n * 16 + 256);
     int *info = (int *)((char *)work.p + (size_t)2 * n * n * 16);
-    jacobi_eigh(n, A, lda, work.p, (char *)work.p + (size_t)n * n * 16, w, R, key, ref, info, st);
+    dense_eigh(n, A, lda, work.p, (char *)work.p + (size_t)n * n * 16, w, R, key, ref, info, st);
     int h = 0;
     PW_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));
     if (sweeps) *sweeps = h;
+    PW_CHECK(h >= 0, PW_ENOCONV, "tridiagonal QL iteration did not converge");
     PW_API_END
 }
 

@@ -1,13 +1,17 @@
 // Small dense FP64 linear algebra on the GPU for the block solver.
 //
-//   chol_inv_kernel : S = L L^H (Cholesky), T = conj(L^{-1}), so that the band-major
-//                     block Psi' = T . Psi is orthonormal (Gram/Cholesky step).
-//   jacobi_kernel   : Hermitian eigensolver (cyclic Jacobi, round-robin parallel
-//                     ordering) for the Rayleigh-Ritz subspace step; outputs the
-//                     eigenvalues and the band-major rotation R with Psi' = R . Psi.
-// Both run as one workgroup on matrices held in global memory (N <= 1024); they
-// are O(N^3) on N x N matrices and off the O(N^2 npw) critical path.
+//   chol_inv_*         : S = L L^H (Cholesky), T = conj(L^{-1}), so that the band-major
+//                        block Psi' = T . Psi is orthonormal (Gram/Cholesky step).
+//   tridiag_ql_kernel + backtransform_kernel (N <= 136) and jacobi_kernel (larger N):
+//                        Hermitian eigensolver for the Rayleigh-Ritz subspace step;
+//                        outputs the eigenvalues and the band-major rotation R with
+//                        Psi' = R . Psi.
+// The factorisations run as one workgroup; they are O(N^3) on N x N matrices and
+// off the O(N^2 npw) critical path.
 #include "common.h"
+
+#include <algorithm>
+#include <cfloat>
 
 namespace pw {
 
@@ -89,7 +93,6 @@ __device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
 // largest matrix whose packed triangle (N (N + 1) / 2 complex128) fits in LDS
 constexpr int kLdsMaxN = 136;
-constexpr int kLdsPairs = kLdsMaxN / 2;
 
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
@@ -333,202 +336,329 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int N, const double2 *__re
 }
 
 // ---------------------------------------------------------------------------
-// Hermitian Jacobi for N <= 128 with the packed lower triangle of A in LDS and
-// the eigenvectors as rows of Vt (Vt[i][r] = V[r][i]) in global memory.  In a
-// round the N/2 disjoint rotations J act at once, A <- J^H A J: every 2 x 2 block
-// of A between two pairs (r, s) x (p, q) becomes U_rs^H B U_pq, so one pass over
-// the blocks does both sides.  Same outputs as jacobi_kernel.
+// Hermitian eigensolver for N <= kLdsMaxN in two launches.
+//
+// tridiag_ql_kernel (one workgroup, A in LDS as a packed lower triangle):
+//   1. Householder reduction A = Q T Q^H, T real symmetric tridiagonal,
+//      Q = H_0 H_1 ... H_{N-2}.  H_k = I - tau_k v_k v_k^H acts on rows k+1..N-1
+//      with v_k[k+1] = 1 and H_k^H sending column k below the diagonal to
+//      beta_k e_1, beta_k real (complex reflectors in the convention of LAPACK's
+//      zlarfg; the two-sided update A22 <- H^H A22 H is the rank-2 form
+//      A22 - v w^H - w v^H with w = tau A22 v - (tau/2)(tau A22 v)^H v v).
+//      v_k (entries k+1..N-1) is stored at hv + k(N-1) - k(k-1)/2, tau_k at
+//      hv + N(N-1)/2 + k.
+//   2. T = Z diag(d) Z^T by implicit QL with Wilkinson's shift (the tql2
+//      algorithm of Bowdler, Martin, Reinsch and Wilkinson, 1968).  One lane
+//      runs the scalar recurrence of a QL sweep and records its Givens
+//      rotations; every lane then applies them to its own row of Z (held
+//      column-major in the LDS the triangle used).
+//   3. Eigenvalues ordered by key into lam; Z column m to zg[m N + r] and its
+//      rank to rank[m].  info = largest QL iteration count of an eigenvalue,
+//      -1 if one needed more than kQlMaxIter.
+// backtransform_kernel: eigenvector m of A is Q Z[:, m]; written as row rank[m]
+//   of R (R . Psi rotates a band-major block, as for jacobi_kernel).
 // ---------------------------------------------------------------------------
+constexpr int kQlMaxIter = 60;
+
+__device__ inline double2 zfma(double2 a, double2 b, double2 c) {
+    return make_double2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
+}
 __device__ inline double2 lds_get(const double2 *L, int i, int k) {
     return i >= k ? L[tri(i, k)] : zconj(L[tri(k, i)]);
 }
-__device__ inline void lds_put(double2 *L, int i, int k, double2 v) {
-    if (i >= k) L[tri(i, k)] = v;
-    else L[tri(k, i)] = zconj(v);
+__device__ inline double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
 }
+// (row, column) of entry q of a packed lower triangle
+__device__ inline void tri_rc(int q, int &i, int &k) {
+    int r = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > q) --r;
+    while ((r + 1) * (r + 2) / 2 <= q) ++r;
+    i = r;
+    k = q - r * (r + 1) / 2;
+}
+__host__ __device__ inline int refl_off(int k, int N) { return k * (N - 1) - k * (k - 1) / 2; }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void jacobi_lds_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
-                                                        double2 *__restrict__ Vt, double *__restrict__ lam,
-                                                        double2 *__restrict__ R, int key, double ref, int max_sweeps,
-                                                        double tol, int *__restrict__ info) {
+__global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
+                                                        double2 *__restrict__ hv, double *__restrict__ zg,
+                                                        int *__restrict__ rank, double *__restrict__ lam, int key,
+                                                        double ref, int *__restrict__ info) {
     extern __shared__ unsigned char smem_raw[];
-    double2 *L = reinterpret_cast<double2 *>(smem_raw);            // packed lower triangle
-    __shared__ int pp[kLdsPairs], qq[kLdsPairs];
-    __shared__ double cs[kLdsPairs], sn[kLdsPairs];
-    __shared__ double2 ph[kLdsPairs];
-    __shared__ double red[NT];
-    __shared__ int sweeps_done;
-    const int tid = threadIdx.x;
-    const int Ne = N + (N & 1);
-    const int npair = Ne / 2;
-    for (int i = 0; i < N; ++i)
-        for (int k = tid; k <= i; k += NT) {
-            const double2 a = Ain[(int64_t)i * lda + k], b = Ain[(int64_t)k * lda + i];
-            L[tri(i, k)] = make_double2(0.5 * (a.x + b.x), i == k ? 0.0 : 0.5 * (a.y - b.y));
-        }
-    for (int e = tid; e < N * N; e += NT) Vt[e] = make_double2((e / N) == (e % N) ? 1.0 : 0.0, 0.0);
-    if (tid == 0) sweeps_done = 0;
-    __syncthreads();
-    double prev_offs = INFINITY;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int e = tid; e < N * (N + 1) / 2; e += NT) {
-            // row of packed index e
-            int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while (i * (i + 1) / 2 > e) --i;
-            while ((i + 1) * (i + 2) / 2 <= e) ++i;
-            const int k = e - i * (i + 1) / 2;
-            const double2 a = L[e];
-            if (k != i) off += 2.0 * (a.x * a.x + a.y * a.y);
-            else dia += a.x * a.x;
-        }
-        red[tid] = off;
-        __syncthreads();
-        for (int s = NT / 2; s > 0; s >>= 1) { if (tid < s) red[tid] += red[tid + s]; __syncthreads(); }
-        const double offs = red[0];
-        __syncthreads();
-        red[tid] = dia;
-        __syncthreads();
-        for (int s = NT / 2; s > 0; s >>= 1) { if (tid < s) red[tid] += red[tid + s]; __syncthreads(); }
-        const double dias = red[0];
-        __syncthreads();
-        const double tot = dias + offs;
-        if (offs <= tol * tol * tot || offs == 0.0) break;
-        if (sweep > 0 && offs <= 1e-28 * tot && offs >= 0.5 * prev_offs) break;   // rounding floor
-        prev_offs = offs;
-        if (tid == 0) sweeps_done = sweep + 1;
-        for (int r = 0; r < Ne - 1; ++r) {
-            if (tid < npair) {
-                const int k = tid;
-                int p, q;
-                if (k == 0) { p = r; q = Ne - 1; }
-                else { p = (r + k) % (Ne - 1); q = (r - k + Ne - 1) % (Ne - 1); }
-                if (p > q) { int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0;
-                double2 e = make_double2(1.0, 0.0);
-                if (q < N) {
-                    const double app = L[tri(p, p)].x, aqq = L[tri(q, q)].x;
-                    const double2 apq = zconj(L[tri(q, p)]);
-                    const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
-                    if (mag > 0.0) {
-                        const double tau = (aqq - app) / (2.0 * mag);
-                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                        e = make_double2(apq.x / mag, -apq.y / mag);    // exp(-i phi)
-                    }
-                }
-                pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; ph[k] = e;
-            }
-            __syncthreads();
-            // eigenvector rows, first half: Vt[p] <- c Vt[p] - s e Vt[q], Vt[q] <- s Vt[p] + c e Vt[q].
-            // Each element is touched once per round, so every load is issued here,
-            // ahead of the LDS block updates, and the stores follow them.
-            constexpr int MAXIT = (kLdsPairs * kLdsMaxN + NT - 1) / NT;
-            double2 vp[MAXIT], vq[MAXIT];
-#pragma unroll
-            for (int it = 0; it < MAXIT; ++it) {
-                const int w = tid + it * NT;
-                vp[it] = vq[it] = make_double2(0.0, 0.0);
-                if (w < npair * N) {
-                    const int k = w / N, row = w - k * N;
-                    const int p = pp[k], q = qq[k];
-                    if (q < N && sn[k] != 0.0) {
-                        vp[it] = Vt[(int64_t)p * N + row];
-                        vq[it] = Vt[(int64_t)q * N + row];
-                    }
-                }
-            }
-            // blocks (k1 <= k2): B = A[{r1, s1}][{p2, q2}] <- U1^H B U2, U = [[c, s], [-e s, e c]]
-            for (int w = tid; w < npair * npair; w += NT) {
-                const int k1 = w / npair, k2 = w - k1 * npair;
-                if (k1 > k2) continue;
-                const int i0 = pp[k1], i1 = qq[k1], j0 = pp[k2], j1 = qq[k2];
-                const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
-                const double2 e1 = ph[k1], e2 = ph[k2];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const bool v1 = i1 < N, v2 = j1 < N;
-                double2 b00 = lds_get(L, i0, j0);
-                double2 b01 = v2 ? lds_get(L, i0, j1) : make_double2(0.0, 0.0);
-                double2 b10 = v1 ? lds_get(L, i1, j0) : make_double2(0.0, 0.0);
-                double2 b11 = (v1 && v2) ? lds_get(L, i1, j1) : make_double2(0.0, 0.0);
-                // left: rows (i0, i1) <- U1^H rows: new0 = c1 b0 - s1 conj(e1) b1 ; new1 = s1 b0 + c1 conj(e1) b1
-                const double2 ce1 = zconj(e1);
-                double2 t00 = zmul(ce1, b10), t01 = zmul(ce1, b11);
-                double2 l00 = make_double2(c1 * b00.x - s1 * t00.x, c1 * b00.y - s1 * t00.y);
-                double2 l01 = make_double2(c1 * b01.x - s1 * t01.x, c1 * b01.y - s1 * t01.y);
-                double2 l10 = make_double2(s1 * b00.x + c1 * t00.x, s1 * b00.y + c1 * t00.y);
-                double2 l11 = make_double2(s1 * b01.x + c1 * t01.x, s1 * b01.y + c1 * t01.y);
-                // right: cols (j0, j1) <- cols U2: new0 = c2 a0 - s2 e2 a1 ; new1 = s2 a0 + c2 e2 a1
-                double2 u0 = zmul(e2, l01), u1 = zmul(e2, l11);
-                double2 r00 = make_double2(c2 * l00.x - s2 * u0.x, c2 * l00.y - s2 * u0.y);
-                double2 r01 = make_double2(s2 * l00.x + c2 * u0.x, s2 * l00.y + c2 * u0.y);
-                double2 r10 = make_double2(c2 * l10.x - s2 * u1.x, c2 * l10.y - s2 * u1.y);
-                double2 r11 = make_double2(s2 * l10.x + c2 * u1.x, s2 * l10.y + c2 * u1.y);
-                if (k1 == k2) {
-                    // diagonal block: the rotation zeroes the off-diagonal pair
-                    L[tri(i0, i0)] = make_double2(r00.x, 0.0);
-                    if (v1) {
-                        L[tri(i1, i1)] = make_double2(r11.x, 0.0);
-                        L[tri(i1, i0)] = make_double2(0.0, 0.0);
-                    }
-                } else {
-                    lds_put(L, i0, j0, r00);
-                    if (v2) lds_put(L, i0, j1, r01);
-                    if (v1) lds_put(L, i1, j0, r10);
-                    if (v1 && v2) lds_put(L, i1, j1, r11);
-                }
-            }
-            // eigenvector rows, second half: combine and store
-#pragma unroll
-            for (int it = 0; it < MAXIT; ++it) {
-                const int w = tid + it * NT;
-                if (w < npair * N) {
-                    const int k = w / N, row = w - k * N;
-                    const int p = pp[k], q = qq[k];
-                    if (q < N && sn[k] != 0.0) {
-                        const double c = cs[k], s = sn[k];
-                        const double2 ev = zmul(ph[k], vq[it]);
-                        Vt[(int64_t)p * N + row] = make_double2(c * vp[it].x - s * ev.x, c * vp[it].y - s * ev.y);
-                        Vt[(int64_t)q * N + row] = make_double2(s * vp[it].x + c * ev.x, s * vp[it].y + c * ev.y);
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    double2 *L = reinterpret_cast<double2 *>(smem_raw);     // packed lower triangle of A
+    double *Zt = reinterpret_cast<double *>(smem_raw);      // afterwards: Zt[i N + r] = Z[r][i]
+    __shared__ double2 v[kLdsMaxN], w[kLdsMaxN];
+    __shared__ double d[kLdsMaxN], e[kLdsMaxN], cs[kLdsMaxN], sn[kLdsMaxN];
+    __shared__ double2 sc[3][2];                            // tau, 1/(alpha - beta), w correction; by parity of k
+    __shared__ int ctl[2];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ntri = N * (N + 1) / 2;
+    const int tau_off = N * (N - 1) / 2;
+    for (int q = tid; q < ntri; q += NT) {
+        int i, k;
+        tri_rc(q, i, k);
+        const double2 a = Ain[(int64_t)i * lda + k], b = Ain[(int64_t)k * lda + i];
+        L[q] = make_double2(0.5 * (a.x + b.x), i == k ? 0.0 : 0.5 * (a.y - b.y));
     }
-    double *dval = red;
-    for (int i = tid; i < N; i += NT) dval[i] = L[tri(i, i)].x;
     __syncthreads();
+
+    // 1. Householder reduction
+    for (int k = 0; k + 1 < N; ++k) {
+        const int par = k & 1, m = N - 1 - k;
+        if (wid == 0) {
+            double s2 = 0.0;
+            for (int i = k + 2 + lane; i < N; i += 64) {
+                const double2 a = L[tri(i, k)];
+                s2 += a.x * a.x + a.y * a.y;
+            }
+            s2 = wave_sum(s2);
+            if (lane == 0) {
+                const double2 al = L[tri(k + 1, k)];
+                double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
+                double beta = al.x;
+                if (s2 > 0.0 || al.y != 0.0) {
+                    const double nrm = sqrt(al.x * al.x + al.y * al.y + s2);
+                    beta = al.x >= 0.0 ? -nrm : nrm;
+                    tau = make_double2((beta - al.x) / beta, -al.y / beta);
+                    const double2 den = make_double2(al.x - beta, al.y);
+                    const double dd = den.x * den.x + den.y * den.y;
+                    scl = make_double2(den.x / dd, -den.y / dd);
+                }
+                d[k] = L[tri(k, k)].x;
+                e[k] = beta;
+                sc[0][par] = tau;
+                sc[1][par] = scl;
+                hv[tau_off + k] = tau;
+            }
+        }
+        __syncthreads();
+        const double2 tau = sc[0][par], scl = sc[1][par];
+        if (tau.x == 0.0 && tau.y == 0.0) continue;        // H_k = I: nothing to update
+        const int off = refl_off(k, N);
+        for (int i = k + 1 + tid; i < N; i += NT) {
+            const double2 x = i == k + 1 ? make_double2(1.0, 0.0) : zmul(L[tri(i, k)], scl);
+            v[i] = x;
+            hv[off + (i - k - 1)] = x;
+        }
+        __syncthreads();
+        // w = tau A22 v, eight lanes per row
+        {
+            const int g = tid >> 3, s = tid & 7;
+            for (int r = g; r < m; r += NT / 8) {
+                const int i = k + 1 + r;
+                double2 acc = make_double2(0.0, 0.0);
+                for (int j = k + 1 + s; j < N; j += 8) acc = zfma(lds_get(L, i, j), v[j], acc);
+                for (int o = 4; o > 0; o >>= 1) {
+                    acc.x += __shfl_xor(acc.x, o);
+                    acc.y += __shfl_xor(acc.y, o);
+                }
+                if (s == 0) w[i] = zmul(tau, acc);
+            }
+        }
+        __syncthreads();
+        if (wid == 0) {
+            double2 t = make_double2(0.0, 0.0);             // w^H v
+            for (int i = k + 1 + lane; i < N; i += 64) t = zfma(zconj(w[i]), v[i], t);
+            t.x = wave_sum(t.x);
+            t.y = wave_sum(t.y);
+            if (lane == 0) {
+                const double2 h = zmul(tau, t);
+                sc[2][par] = make_double2(-0.5 * h.x, -0.5 * h.y);
+            }
+        }
+        __syncthreads();
+        const double2 a2 = sc[2][par];
+        for (int q = tid; q < m * (m + 1) / 2; q += NT) {
+            int ii, jj;
+            tri_rc(q, ii, jj);
+            const int i = k + 1 + ii, j = k + 1 + jj;
+            const double2 vi = v[i], vj = v[j];
+            const double2 wi = zfma(a2, vi, w[i]), wj = zfma(a2, vj, w[j]);
+            const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
+            double2 a = L[tri(i, j)];
+            a.x -= t1.x + t2.x;
+            a.y = i == j ? 0.0 : a.y - (t1.y + t2.y);
+            L[tri(i, j)] = a;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[N - 1] = L[tri(N - 1, N - 1)].x;
+        e[N - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
+    __syncthreads();
+
+    // 2. implicit QL; lane 0 carries (l, iter) from sweep to sweep
+    int l = 0, iter = 0, maxiter = 0;
+    bool fail = false;
+    for (;;) {
+        if (tid == 0) {
+            int msweep = -1, nrot = 0;
+            while (l < N) {
+                int m = l;
+                for (; m < N - 1; ++m) {
+                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
+                    if (fabs(e[m]) <= DBL_EPSILON * dd) break;
+                }
+                if (m == l) {
+                    maxiter = max(maxiter, iter);
+                    ++l;
+                    iter = 0;
+                    continue;
+                }
+                if (iter == kQlMaxIter) {
+                    fail = true;
+                    ++l;
+                    iter = 0;
+                    continue;
+                }
+                ++iter;
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = hypot(g, 1.0);
+                g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+                double s = 1.0, c = 1.0, p = 0.0;
+                bool split = false;
+                for (int i = m - 1; i >= l; --i) {
+                    const double f = s * e[i], b = c * e[i];
+                    r = hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {                          // T splits: restart on the shorter block
+                        d[i + 1] -= p;
+                        e[m] = 0.0;
+                        split = true;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * b;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - b;
+                    cs[nrot] = c;
+                    sn[nrot] = s;
+                    ++nrot;
+                }
+                if (!split) {
+                    d[l] -= p;
+                    e[l] = g;
+                    e[m] = 0.0;
+                }
+                msweep = m;
+                break;
+            }
+            ctl[0] = msweep;
+            ctl[1] = nrot;
+        }
+        __syncthreads();
+        const int msweep = ctl[0], nrot = ctl[1];
+        if (msweep < 0) break;
+        if (tid < N && nrot > 0) {
+            // rotation t mixes columns (i, i+1), i = msweep - 1 - t; carry holds column i+1
+            double carry = Zt[msweep * N + tid];
+            for (int t = 0; t < nrot; ++t) {
+                const int i = msweep - 1 - t;
+                const double zi = Zt[i * N + tid];
+                Zt[(i + 1) * N + tid] = sn[t] * zi + cs[t] * carry;
+                carry = cs[t] * zi - sn[t] * carry;
+            }
+            Zt[(msweep - nrot) * N + tid] = carry;
+        }
+        __syncthreads();
+    }
+
+    // 3. order, eigenvalues, tridiagonal eigenvectors
     for (int i = tid; i < N; i += NT) {
-        const double li = dval[i];
+        const double li = d[i];
         const double ki = key ? fabs(li - ref) : li;
-        int rank = 0;
+        int rk = 0;
         for (int j = 0; j < N; ++j) {
-            const double lj = dval[j];
+            const double lj = d[j];
             const double kj = key ? fabs(lj - ref) : lj;
-            if (kj < ki || (kj == ki && (lj < li || (lj == li && j < i)))) ++rank;
+            if (kj < ki || (kj == ki && (lj < li || (lj == li && j < i)))) ++rk;
         }
-        lam[rank] = li;
-        for (int j = 0; j < N; ++j) R[(int64_t)rank * N + j] = Vt[(int64_t)i * N + j];
+        lam[rk] = li;
+        rank[i] = rk;
     }
-    if (tid == 0 && info) info[0] = sweeps_done;
+    for (int q = tid; q < N * N; q += NT) zg[q] = Zt[q];
+    if (tid == 0 && info) info[0] = fail ? -1 : maxiter;
+}
+
+// One wave per eigenvector, NW waves per workgroup; all reflectors staged in LDS.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const double2 *__restrict__ hv,
+                                                                const double *__restrict__ zg,
+                                                                const int *__restrict__ rank,
+                                                                double2 *__restrict__ R) {
+    extern __shared__ unsigned char smem_raw[];
+    double2 *sv = reinterpret_cast<double2 *>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tau_off = N * (N - 1) / 2;
+    for (int q = tid; q < tau_off + N - 1; q += 64 * NW) sv[q] = hv[q];
+    __syncthreads();
+    constexpr int Q = (kLdsMaxN + 63) / 64;
+    const int m = blockIdx.x * NW + wid;
+    if (m >= N) return;
+    double2 y[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int r = lane + 64 * q;
+        y[q] = make_double2(r < N ? zg[(int64_t)m * N + r] : 0.0, 0.0);
+    }
+    for (int k = N - 2; k >= 0; --k) {
+        const double2 tk = sv[tau_off + k];
+        if (tk.x == 0.0 && tk.y == 0.0) continue;
+        const int off = refl_off(k, N) - (k + 1);           // v_k[r] = sv[off + r], r > k
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int r = lane + 64 * q;
+            if (r > k && r < N) s = zfma(zconj(sv[off + r]), y[q], s);
+        }
+        s.x = wave_sum(s.x);
+        s.y = wave_sum(s.y);
+        const double2 ts = zmul(tk, s);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int r = lane + 64 * q;
+            if (r > k && r < N) {
+                const double2 u = zmul(ts, sv[off + r]);
+                y[q].x -= u.x;
+                y[q].y -= u.y;
+            }
+        }
+    }
+    const int64_t row = (int64_t)rank[m] * N;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int r = lane + 64 * q;
+        if (r < N) R[row + r] = y[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
+namespace {
+// raise a kernel's dynamic LDS limit to the bytes it is launched with
+void lds_limit(const void *fn, size_t bytes, size_t &have) {
+    if (bytes > have) {
+        PW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        have = bytes;
+    }
+}
+constexpr int kBackNW = 4;
+}  // namespace
+
 void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t st) {
     if (N <= kLdsMaxN) {
         PW_CHECK(N > 0 && N < 4096, PW_EINVAL, "bad Cholesky size");   // inverse keeps one band per thread
         const size_t bytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
         static size_t attr_bytes = 64 * 1024;   // default dynamic LDS limit
-        if (bytes > attr_bytes) {
-            PW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(chol_inv_lds_kernel<1024>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-            attr_bytes = bytes;
-        }
+        lds_limit(reinterpret_cast<const void *>(chol_inv_lds_kernel<1024>), bytes, attr_bytes);
         hipLaunchKernelGGL(chol_inv_lds_kernel<1024>, dim3(1), dim3(1024), bytes, st, N, (const double2 *)S, lds,
                            (double2 *)T, status);
     } else {
@@ -538,19 +668,24 @@ void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *statu
     PW_LAUNCH_CHECK();
 }
 
-void jacobi_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
-                 double ref, int *info, hipStream_t st) {
-    PW_CHECK(N <= 1024, PW_EUNSUPPORTED, "Jacobi eigensolver limited to N <= 1024");
+void dense_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
+                double ref, int *info, hipStream_t st) {
+    PW_CHECK(N >= 1 && N <= 1024, PW_EUNSUPPORTED, "dense eigensolver limited to 1 <= N <= 1024");
     if (N <= kLdsMaxN) {
-        const size_t bytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
-        static size_t attr_bytes = 64 * 1024;
-        if (bytes > attr_bytes) {
-            PW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(jacobi_lds_kernel<512>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-            attr_bytes = bytes;
-        }
-        hipLaunchKernelGGL(jacobi_lds_kernel<512>, dim3(1), dim3(512), bytes, st, N, (const double2 *)A, lda,
-                           (double2 *)work_v, lam, (double2 *)R, key, ref, 25, 1e-13, info);
+        // work_a: reflectors and taus (N (N + 1) / 2 complex); work_v: Z (N^2 real) then the ranks
+        double2 *hv = (double2 *)work_a;
+        double *zg = (double *)work_v;
+        int *rank = (int *)(zg + (size_t)N * N);
+        const size_t b1 = std::max((size_t)N * (N + 1) / 2 * sizeof(double2), (size_t)N * N * sizeof(double));
+        static size_t attr1 = 64 * 1024, attr2 = 64 * 1024;
+        lds_limit(reinterpret_cast<const void *>(tridiag_ql_kernel<1024>), b1, attr1);
+        hipLaunchKernelGGL(tridiag_ql_kernel<1024>, dim3(1), dim3(1024), b1, st, N, (const double2 *)A, lda, hv,
+                           zg, rank, lam, key, ref, info);
+        PW_LAUNCH_CHECK();
+        const size_t b2 = std::max<size_t>(1, (size_t)N * (N - 1) / 2 + N - 1) * sizeof(double2);
+        lds_limit(reinterpret_cast<const void *>(backtransform_kernel<kBackNW>), b2, attr2);
+        hipLaunchKernelGGL(backtransform_kernel<kBackNW>, dim3((N + kBackNW - 1) / kBackNW), dim3(64 * kBackNW), b2,
+                           st, N, (const double2 *)hv, (const double *)zg, (const int *)rank, (double2 *)R);
         PW_LAUNCH_CHECK();
         return;
     }
