@@ -148,11 +148,10 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * pw_dense_eigh: eigen-decomposition of the Hermitian part of A (n x n, ld lda):
  *   w (device, n) eigenvalues ordered by key (0: ascending, 1: ascending
  *   |w - ref|), R (device, n x n) with row b the eigenvector of w[b] in the input
- *   basis (so a band-major block rotates as Psi' = R . Psi).  n <= 136:
- *   Householder tridiagonalisation + implicit QL; sweeps (host, optional) gets
- *   the largest QL iteration count of one eigenvalue, and PW_ENOCONV is returned
- *   if one exceeds 60.  n > 136: cyclic Jacobi; sweeps gets the sweep count.
- *   Synchronises.
+ *   basis (so a band-major block rotates as Psi' = R . Psi).  Householder
+ *   tridiagonalisation + implicit QL; sweeps (host, optional) gets the largest
+ *   QL iteration count of one eigenvalue, and PW_ENOCONV is returned if one
+ *   exceeds 60.  Synchronises.
  * pw_dense_chol_inv: S = L L^H for Hermitian positive definite S (n x n, lds),
  *   T = conj(L^{-1}) (n x n) so that Psi' = T . Psi has Psi'^H Psi' = I when
  *   S = Psi^H Psi.  Returns PW_ENOTPD if a pivot is not positive.  Synchronises.

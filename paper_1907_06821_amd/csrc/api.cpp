@@ -396,9 +396,10 @@ pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *
     PW_CHECK(key == 0 || key == 1, PW_EINVAL, "key must be 0 or 1");
     hipStream_t st = (hipStream_t)stream;
     DevBuf work;
-    work.alloc((size_t)2 * n * n * 16 + 256);
-    int *info = (int *)((char *)work.p + (size_t)2 * n * n * 16);
-    dense_eigh(n, A, lda, work.p, (char *)work.p + (size_t)n * n * 16, w, R, key, ref, info, st);
+    const size_t wb = (dense_eigh_work_bytes(n) + 255) / 256 * 256;
+    work.alloc(wb + 256);
+    int *info = (int *)((char *)work.p + wb);
+    dense_eigh(n, A, lda, work.p, w, R, key, ref, info, st);
     int h = 0;
     PW_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));

@@ -2,10 +2,10 @@
 //
 //   chol_inv_*         : S = L L^H (Cholesky), T = conj(L^{-1}), so that the band-major
 //                        block Psi' = T . Psi is orthonormal (Gram/Cholesky step).
-//   tridiag_ql_kernel + backtransform_kernel (N <= 136) and jacobi_kernel (larger N):
-//                        Hermitian eigensolver for the Rayleigh-Ritz subspace step;
-//                        outputs the eigenvalues and the band-major rotation R with
-//                        Psi' = R . Psi.
+//   tridiag_ql_*_kernel + backtransform_kernel: Hermitian eigensolver for the
+//                        Rayleigh-Ritz subspace step (Householder tridiagonalisation,
+//                        implicit QL); outputs the eigenvalues and the band-major
+//                        rotation R with Psi' = R . Psi.
 // The factorisations run as one workgroup; they are O(N^3) on N x N matrices and
 // off the O(N^2 npw) critical path.
 #include "common.h"
@@ -184,181 +184,33 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
 }
 
 // ---------------------------------------------------------------------------
-// Hermitian Jacobi.  A (N x N, ld N) is overwritten; V accumulates eigenvectors
-// as columns.  Output: lam[b] (sorted by key), R[b][j] = V[j][perm b] so that
-// new band b = sum_j R[b][j] old_j.  key: 0 ascending lam, 1 ascending |lam - ref|
-// (ties by lam).  Odd N is handled by a dummy index that never rotates.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void jacobi_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
-                                                      double2 *__restrict__ A, double2 *__restrict__ V,
-                                                      double *__restrict__ lam, double2 *__restrict__ R,
-                                                      int key, double ref, int max_sweeps, double tol,
-                                                      int *__restrict__ info) {
-    extern __shared__ unsigned char smem_raw[];
-    // per pair: p, q, c, s (real), phase (complex)
-    int *pp = reinterpret_cast<int *>(smem_raw);
-    int *qq = pp + 512;
-    double *cs = reinterpret_cast<double *>(qq + 512);
-    double *sn = cs + 512;
-    double2 *ph = reinterpret_cast<double2 *>(sn + 512);
-    __shared__ double red[1024];
-    __shared__ int sweeps_done;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int Ne = N + (N & 1);        // even player count
-    const int npair = Ne / 2;
-    for (int e = tid; e < N * N; e += nt) {
-        const int i = e / N, k = e % N;
-        double2 a = Ain[(int64_t)i * lda + k];
-        const double2 b = Ain[(int64_t)k * lda + i];
-        A[e] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));   // Hermitian part
-        V[e] = make_double2(i == k ? 1.0 : 0.0, 0.0);
-    }
-    if (tid == 0) sweeps_done = 0;
-    __syncthreads();
-    double prev_offs = INFINITY;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // convergence: off-diagonal Frobenius norm vs diagonal
-        double off = 0.0, dia = 0.0;
-        for (int e = tid; e < N * N; e += nt) {
-            const int i = e / N, k = e % N;
-            const double2 a = A[e];
-            if (i != k) off += a.x * a.x + a.y * a.y;
-            else dia += a.x * a.x;
-        }
-        red[tid] = off;
-        __syncthreads();
-        for (int s = nt / 2; s > 0; s >>= 1) { if (tid < s) red[tid] += red[tid + s]; __syncthreads(); }
-        const double offs = red[0];
-        __syncthreads();
-        red[tid] = dia;
-        __syncthreads();
-        for (int s = nt / 2; s > 0; s >>= 1) { if (tid < s) red[tid] += red[tid + s]; __syncthreads(); }
-        const double dias = red[0];
-        __syncthreads();
-        // converged: relative off-diagonal Frobenius norm below tol, or at the
-        // rounding floor (no further decrease once already below 1e-10)
-        const double tot = dias + offs;
-        if (offs <= tol * tol * tot || offs == 0.0) break;
-        if (sweep > 0 && offs <= 1e-28 * tot && offs >= 0.5 * prev_offs) break;   // rounding floor
-        prev_offs = offs;
-        if (tid == 0) sweeps_done = sweep + 1;
-        for (int r = 0; r < Ne - 1; ++r) {
-            // pairs of this round (circle method)
-            for (int k = tid; k < npair; k += nt) {
-                int p, q;
-                if (k == 0) { p = r; q = Ne - 1; }
-                else { p = (r + k) % (Ne - 1); q = (r - k + Ne - 1) % (Ne - 1); }
-                if (p > q) { int t = p; p = q; q = t; }
-                pp[k] = p; qq[k] = q;
-                double c = 1.0, s = 0.0;
-                double2 e = make_double2(1.0, 0.0);
-                if (q < N) {
-                    const double app = A[(int64_t)p * N + p].x, aqq = A[(int64_t)q * N + q].x;
-                    const double2 apq = A[(int64_t)p * N + q];
-                    const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
-                    if (mag > 0.0) {
-                        const double tau = (aqq - app) / (2.0 * mag);
-                        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                        e = make_double2(apq.x / mag, -apq.y / mag);    // exp(-i phi)
-                    }
-                }
-                cs[k] = c; sn[k] = s; ph[k] = e;
-            }
-            __syncthreads();
-            // U = [[c, s], [-e s, e c]] with e = exp(-i phi); rows: A <- U^H A
-            for (int w = tid; w < npair * N; w += nt) {
-                const int k = w / N, col = w % N;
-                const int p = pp[k], q = qq[k];
-                if (q >= N || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double2 e = ph[k];
-                const double2 ap = A[(int64_t)p * N + col], aq = A[(int64_t)q * N + col];
-                // new_p = c ap - s conj(e) aq ; new_q = s ap + c conj(e) aq
-                const double2 ea = zmul(zconj(e), aq);
-                A[(int64_t)p * N + col] = make_double2(c * ap.x - s * ea.x, c * ap.y - s * ea.y);
-                A[(int64_t)q * N + col] = make_double2(s * ap.x + c * ea.x, s * ap.y + c * ea.y);
-            }
-            __syncthreads();
-            // columns: A <- A U, V <- V U
-            for (int w = tid; w < npair * N; w += nt) {
-                const int k = w / N, row = w % N;
-                const int p = pp[k], q = qq[k];
-                if (q >= N || sn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double2 e = ph[k];
-                {
-                    const double2 ap = A[(int64_t)row * N + p], aq = A[(int64_t)row * N + q];
-                    // new_p = c ap - s e aq ; new_q = s ap + c e aq
-                    const double2 ea = zmul(e, aq);
-                    A[(int64_t)row * N + p] = make_double2(c * ap.x - s * ea.x, c * ap.y - s * ea.y);
-                    A[(int64_t)row * N + q] = make_double2(s * ap.x + c * ea.x, s * ap.y + c * ea.y);
-                }
-                {
-                    const double2 vp = V[(int64_t)row * N + p], vq = V[(int64_t)row * N + q];
-                    const double2 ev = zmul(e, vq);
-                    V[(int64_t)row * N + p] = make_double2(c * vp.x - s * ev.x, c * vp.y - s * ev.y);
-                    V[(int64_t)row * N + q] = make_double2(s * vp.x + c * ev.x, s * vp.y + c * ev.y);
-                }
-            }
-            __syncthreads();
-            for (int k = tid; k < npair; k += nt) {
-                const int p = pp[k], q = qq[k];
-                if (q < N && sn[k] != 0.0) {
-                    A[(int64_t)p * N + q] = make_double2(0.0, 0.0);
-                    A[(int64_t)q * N + p] = make_double2(0.0, 0.0);
-                    A[(int64_t)p * N + p].y = 0.0;
-                    A[(int64_t)q * N + q].y = 0.0;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    // sort by key: rank of each eigenvalue
-    double *dval = reinterpret_cast<double *>(red);     // reuse (N <= 1024)
-    __syncthreads();
-    for (int i = tid; i < N; i += nt) dval[i] = A[(int64_t)i * N + i].x;
-    __syncthreads();
-    for (int i = tid; i < N; i += nt) {
-        const double li = dval[i];
-        const double ki = key ? fabs(li - ref) : li;
-        int rank = 0;
-        for (int j = 0; j < N; ++j) {
-            const double lj = dval[j];
-            const double kj = key ? fabs(lj - ref) : lj;
-            if (kj < ki || (kj == ki && (lj < li || (lj == li && j < i)))) ++rank;
-        }
-        lam[rank] = li;
-        for (int j = 0; j < N; ++j) R[(int64_t)rank * N + j] = V[(int64_t)j * N + i];
-    }
-    if (tid == 0 && info) info[0] = sweeps_done;
-}
-
-// ---------------------------------------------------------------------------
-// Hermitian eigensolver for N <= kLdsMaxN in two launches.
+// Hermitian eigensolver: A = Q T Q^H, T = Z diag(d) Z^T, eigenvectors Q Z.
 //
-// tridiag_ql_kernel (one workgroup, A in LDS as a packed lower triangle):
-//   1. Householder reduction A = Q T Q^H, T real symmetric tridiagonal,
-//      Q = H_0 H_1 ... H_{N-2}.  H_k = I - tau_k v_k v_k^H acts on rows k+1..N-1
-//      with v_k[k+1] = 1 and H_k^H sending column k below the diagonal to
-//      beta_k e_1, beta_k real (complex reflectors in the convention of LAPACK's
-//      zlarfg; the two-sided update A22 <- H^H A22 H is the rank-2 form
-//      A22 - v w^H - w v^H with w = tau A22 v - (tau/2)(tau A22 v)^H v v).
-//      v_k (entries k+1..N-1) is stored at hv + k(N-1) - k(k-1)/2, tau_k at
-//      hv + N(N-1)/2 + k.
-//   2. T = Z diag(d) Z^T by implicit QL with Wilkinson's shift (the tql2
-//      algorithm of Bowdler, Martin, Reinsch and Wilkinson, 1968).  One lane
-//      runs the scalar recurrence of a QL sweep and records its Givens
-//      rotations; every lane then applies them to its own row of Z (held
-//      column-major in the LDS the triangle used).
-//   3. Eigenvalues ordered by key into lam; Z column m to zg[m N + r] and its
-//      rank to rank[m].  info = largest QL iteration count of an eigenvalue,
-//      -1 if one needed more than kQlMaxIter.
-// backtransform_kernel: eigenvector m of A is Q Z[:, m]; written as row rank[m]
-//   of R (R . Psi rotates a band-major block, as for jacobi_kernel).
+// 1. Householder reduction to a real symmetric tridiagonal T,
+//    Q = H_0 H_1 ... H_{N-2}.  H_k = I - tau_k v_k v_k^H acts on rows k+1..N-1
+//    with v_k[k+1] = 1 and H_k^H sending column k below the diagonal to
+//    beta_k e_1, beta_k real (complex reflectors in the convention of LAPACK's
+//    zlarfg).  The two-sided update A22 <- H^H A22 H is the rank-2 form
+//    A22 - v w^H - w v^H with w = tau A22 v - (tau/2) ((tau A22 v)^H v) v.
+//    v_k (entries k+1..N-1) is stored at hv + k(N-1) - k(k-1)/2, tau_k at
+//    hv + N(N-1)/2 + k.
+// 2. Implicit QL with Wilkinson's shift on T (the tql2 algorithm of Bowdler,
+//    Martin, Reinsch and Wilkinson, 1968).  Wave 0 runs the scalar recurrence
+//    of the next sweep while the other waves apply the Givens rotations of the
+//    previous one to the rows of Z (double-buffered rotation lists).
+// 3. Eigenvalues ordered by key into lam; Z column m is zg[m N + r], its rank
+//    rank[m]; info = largest QL iteration count of one eigenvalue, -1 if one
+//    needed more than kQlMaxIter.
+// The back-transformation (second launch) writes Q Z[:, m] as row rank[m] of R,
+// so that R . Psi rotates a band-major block.
+//
+// tridiag_ql_lds_kernel (N <= kLdsMaxN): A as a packed lower triangle in LDS,
+// then Z in the same LDS.  tridiag_ql_global_kernel (N <= kEigMaxN): full A in
+// global memory (rows coalesced), Z in global memory over the dead A.
 // ---------------------------------------------------------------------------
 constexpr int kQlMaxIter = 60;
+constexpr int kEigNT = 1024;
+constexpr int kEigMaxN = 1024;
 
 __device__ inline double2 zfma(double2 a, double2 b, double2 c) {
     return make_double2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
@@ -370,6 +222,7 @@ __device__ inline double wave_sum(double x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     return x;
 }
+__device__ inline double2 wave_sum2(double2 x) { return make_double2(wave_sum(x.x), wave_sum(x.y)); }
 // (row, column) of entry q of a packed lower triangle
 __device__ inline void tri_rc(int q, int &i, int &k) {
     int r = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
@@ -380,18 +233,195 @@ __device__ inline void tri_rc(int q, int &i, int &k) {
 }
 __host__ __device__ inline int refl_off(int k, int N) { return k * (N - 1) - k * (k - 1) / 2; }
 
+// Reflector for x = (alpha, x2) with s2 = |x2|^2: tau, beta, 1/(alpha - beta).
+__device__ inline void householder(double2 al, double s2, double2 &tau, double &beta, double2 &scl) {
+    tau = make_double2(0.0, 0.0);
+    scl = make_double2(0.0, 0.0);
+    beta = al.x;
+    if (s2 > 0.0 || al.y != 0.0) {
+        const double nrm = sqrt(al.x * al.x + al.y * al.y + s2);
+        beta = al.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - al.x) / beta, -al.y / beta);
+        const double2 den = make_double2(al.x - beta, al.y);
+        const double dd = den.x * den.x + den.y * den.y;
+        scl = make_double2(den.x / dd, -den.y / dd);
+    }
+}
+
+// r = sqrt(f^2 + g^2) and 1/r: hardware reciprocal square root refined by two
+// Goldschmidt steps and a final Newton correction of r; library hypot outside
+// the range where f^2 + g^2 neither overflows nor underflows.  false if r == 0.
+__device__ __forceinline__ bool givens_norm(double f, double g, double &r, double &rinv) {
+    const double x = f * f + g * g;
+    if (!(x >= 1e-290 && x <= 1e290)) {
+        r = hypot(f, g);
+        rinv = 1.0 / r;
+        return r != 0.0;
+    }
+    const double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * y, q = x * y;
+    double t = fma(-q, h, 0.5);
+    q = fma(q, t, q);
+    h = fma(h, t, h);
+    t = fma(-q, h, 0.5);
+    q = fma(q, t, q);
+    h = fma(h, t, h);
+    r = fma(fma(-q, q, x), h, q);
+    rinv = 2.0 * h;
+    return true;
+}
+
+// One implicit QL sweep of the tridiagonal (d, e), run uniformly by all 64 lanes
+// of a wave.  (l, iter, maxiter, fail) carry over between calls.  Records the
+// rotations (c_t, s_t) acting on columns (msweep-1-t, msweep-t) and returns
+// msweep, or -1 once every eigenvalue has converged.
+__device__ __forceinline__ int ql_sweep(int N, double *d, double *e, double *cs, double *sn, int &l, int &iter,
+                                        int &maxiter, bool &fail, int lane, int &nrot) {
+    nrot = 0;
+    while (l < N) {
+        int m = N - 1;
+        for (int base = l; base < N - 1; base += 64) {
+            const int idx = base + lane;
+            bool small = false;
+            if (idx < N - 1) small = fabs(e[idx]) <= DBL_EPSILON * (fabs(d[idx]) + fabs(d[idx + 1]));
+            const unsigned long long bal = __ballot(small);
+            if (bal) {
+                m = base + __ffsll((long long)bal) - 1;
+                break;
+            }
+        }
+        if (m == l) {
+            maxiter = max(maxiter, iter);
+            ++l;
+            iter = 0;
+            continue;
+        }
+        if (iter == kQlMaxIter) {
+            fail = true;
+            ++l;
+            iter = 0;
+            continue;
+        }
+        ++iter;
+        const double dl = d[l], el = e[l];
+        double g = (d[l + 1] - dl) / (2.0 * el);
+        double r = hypot(g, 1.0);
+        g = d[m] - dl + el / (g + copysign(r, g));
+        double s = 1.0, c = 1.0, p = 0.0;
+        double dip1 = d[m];                     // d[i+1] as it was before this sweep
+        double ei = e[m - 1], di = d[m - 1];
+        bool split = false;
+        for (int i = m - 1; i >= l; --i) {
+            double en = 0.0, dn = 0.0;
+            if (i > l) {
+                en = e[i - 1];
+                dn = d[i - 1];
+            }
+            const double f = s * ei, b = c * ei;
+            double rinv;
+            if (!givens_norm(f, g, r, rinv)) {  // T splits: the next search restarts on the shorter block
+                d[i + 1] = dip1 - p;
+                e[i + 1] = 0.0;
+                e[m] = 0.0;
+                split = true;
+                break;
+            }
+            e[i + 1] = r;
+            s = f * rinv;
+            c = g * rinv;
+            g = dip1 - p;
+            r = (di - g) * s + 2.0 * c * b;
+            p = s * r;
+            d[i + 1] = g + p;
+            g = c * r - b;
+            cs[nrot] = c;
+            sn[nrot] = s;
+            ++nrot;
+            dip1 = di;
+            ei = en;
+            di = dn;
+        }
+        if (!split) {
+            d[l] = dip1 - p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+        return m;
+    }
+    return -1;
+}
+
+// Rotation list of one sweep applied to row `row` of Z (Zt[i N + row] = Z[row][i]).
+__device__ __forceinline__ void ql_apply(double *Zt, int N, int row, int msweep, int nrot, const double *cs,
+                                         const double *sn) {
+    double carry = Zt[(int64_t)msweep * N + row];       // column i+1 of the current rotation
+#pragma unroll 4
+    for (int t = 0; t < nrot; ++t) {
+        const int i = msweep - 1 - t;
+        const double zi = Zt[(int64_t)i * N + row];
+        Zt[(int64_t)(i + 1) * N + row] = sn[t] * zi + cs[t] * carry;
+        carry = cs[t] * zi - sn[t] * carry;
+    }
+    Zt[(int64_t)(msweep - nrot) * N + row] = carry;
+}
+
+// QL on (d, e) with Z (identity on entry) by the whole block, then eigenvalue
+// order.  NMAX sizes the rotation lists.
+template <int NT, int NMAX>
+__device__ __forceinline__ void ql_block(int N, double *d, double *e, double (*cs)[NMAX], double (*sn)[NMAX],
+                                         int (*ctl)[2], double *Zt, double *lam, int *rank, int key, double ref,
+                                         int *info) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) {
+        ctl[1][0] = -2;                                 // nothing to apply yet
+        ctl[1][1] = 0;
+    }
+    __syncthreads();
+    int l = 0, iter = 0, maxiter = 0;
+    bool fail = false;
+    for (int b = 0;; b ^= 1) {
+        if (wid == 0) {
+            int nrot;
+            const int ms = ql_sweep(N, d, e, cs[b], sn[b], l, iter, maxiter, fail, lane, nrot);
+            if (lane == 0) {
+                ctl[b][0] = ms;
+                ctl[b][1] = nrot;
+            }
+        } else {
+            const int pm = ctl[b ^ 1][0], pn = ctl[b ^ 1][1];
+            if (pm >= 0 && pn > 0)
+                for (int row = tid - 64; row < N; row += NT - 64) ql_apply(Zt, N, row, pm, pn, cs[b ^ 1], sn[b ^ 1]);
+        }
+        __syncthreads();
+        if (ctl[b][0] < 0) break;
+    }
+    for (int i = tid; i < N; i += NT) {
+        const double li = d[i];
+        const double ki = key ? fabs(li - ref) : li;
+        int rk = 0;
+        for (int j = 0; j < N; ++j) {
+            const double lj = d[j];
+            const double kj = key ? fabs(lj - ref) : lj;
+            if (kj < ki || (kj == ki && (lj < li || (lj == li && j < i)))) ++rk;
+        }
+        lam[rk] = li;
+        rank[i] = rk;
+    }
+    if (tid == 0 && info) info[0] = fail ? -1 : maxiter;
+}
+
 template <int NT>
-__global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
-                                                        double2 *__restrict__ hv, double *__restrict__ zg,
-                                                        int *__restrict__ rank, double *__restrict__ lam, int key,
-                                                        double ref, int *__restrict__ info) {
+__global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
+                                                            double2 *__restrict__ hv, double *__restrict__ zg,
+                                                            int *__restrict__ rank, double *__restrict__ lam, int key,
+                                                            double ref, int *__restrict__ info) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);     // packed lower triangle of A
     double *Zt = reinterpret_cast<double *>(smem_raw);      // afterwards: Zt[i N + r] = Z[r][i]
     __shared__ double2 v[kLdsMaxN], w[kLdsMaxN];
-    __shared__ double d[kLdsMaxN], e[kLdsMaxN], cs[kLdsMaxN], sn[kLdsMaxN];
+    __shared__ double d[kLdsMaxN], e[kLdsMaxN], cs[2][kLdsMaxN], sn[2][kLdsMaxN];
     __shared__ double2 sc[3][2];                            // tau, 1/(alpha - beta), w correction; by parity of k
-    __shared__ int ctl[2];
+    __shared__ int ctl[2][2];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ntri = N * (N + 1) / 2;
     const int tau_off = N * (N - 1) / 2;
@@ -402,8 +432,6 @@ __global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__
         L[q] = make_double2(0.5 * (a.x + b.x), i == k ? 0.0 : 0.5 * (a.y - b.y));
     }
     __syncthreads();
-
-    // 1. Householder reduction
     for (int k = 0; k + 1 < N; ++k) {
         const int par = k & 1, m = N - 1 - k;
         if (wid == 0) {
@@ -414,17 +442,9 @@ __global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__
             }
             s2 = wave_sum(s2);
             if (lane == 0) {
-                const double2 al = L[tri(k + 1, k)];
-                double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
-                double beta = al.x;
-                if (s2 > 0.0 || al.y != 0.0) {
-                    const double nrm = sqrt(al.x * al.x + al.y * al.y + s2);
-                    beta = al.x >= 0.0 ? -nrm : nrm;
-                    tau = make_double2((beta - al.x) / beta, -al.y / beta);
-                    const double2 den = make_double2(al.x - beta, al.y);
-                    const double dd = den.x * den.x + den.y * den.y;
-                    scl = make_double2(den.x / dd, -den.y / dd);
-                }
+                double2 tau, scl;
+                double beta;
+                householder(L[tri(k + 1, k)], s2, tau, beta, scl);
                 d[k] = L[tri(k, k)].x;
                 e[k] = beta;
                 sc[0][par] = tau;
@@ -442,8 +462,7 @@ __global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__
             hv[off + (i - k - 1)] = x;
         }
         __syncthreads();
-        // w = tau A22 v, eight lanes per row
-        {
+        {   // w = tau A22 v, eight lanes per row
             const int g = tid >> 3, s = tid & 7;
             for (int r = g; r < m; r += NT / 8) {
                 const int i = k + 1 + r;
@@ -460,8 +479,7 @@ __global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__
         if (wid == 0) {
             double2 t = make_double2(0.0, 0.0);             // w^H v
             for (int i = k + 1 + lane; i < N; i += 64) t = zfma(zconj(w[i]), v[i], t);
-            t.x = wave_sum(t.x);
-            t.y = wave_sum(t.y);
+            t = wave_sum2(t);
             if (lane == 0) {
                 const double2 h = zmul(tau, t);
                 sc[2][par] = make_double2(-0.5 * h.x, -0.5 * h.y);
@@ -489,117 +507,126 @@ __global__ __launch_bounds__(NT) void tridiag_ql_kernel(int N, const double2 *__
     }
     __syncthreads();
     for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
-    __syncthreads();
-
-    // 2. implicit QL; lane 0 carries (l, iter) from sweep to sweep
-    int l = 0, iter = 0, maxiter = 0;
-    bool fail = false;
-    for (;;) {
-        if (tid == 0) {
-            int msweep = -1, nrot = 0;
-            while (l < N) {
-                int m = l;
-                for (; m < N - 1; ++m) {
-                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                    if (fabs(e[m]) <= DBL_EPSILON * dd) break;
-                }
-                if (m == l) {
-                    maxiter = max(maxiter, iter);
-                    ++l;
-                    iter = 0;
-                    continue;
-                }
-                if (iter == kQlMaxIter) {
-                    fail = true;
-                    ++l;
-                    iter = 0;
-                    continue;
-                }
-                ++iter;
-                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = hypot(g, 1.0);
-                g = d[m] - d[l] + e[l] / (g + copysign(r, g));
-                double s = 1.0, c = 1.0, p = 0.0;
-                bool split = false;
-                for (int i = m - 1; i >= l; --i) {
-                    const double f = s * e[i], b = c * e[i];
-                    r = hypot(f, g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {                          // T splits: restart on the shorter block
-                        d[i + 1] -= p;
-                        e[m] = 0.0;
-                        split = true;
-                        break;
-                    }
-                    s = f / r;
-                    c = g / r;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * c * b;
-                    p = s * r;
-                    d[i + 1] = g + p;
-                    g = c * r - b;
-                    cs[nrot] = c;
-                    sn[nrot] = s;
-                    ++nrot;
-                }
-                if (!split) {
-                    d[l] -= p;
-                    e[l] = g;
-                    e[m] = 0.0;
-                }
-                msweep = m;
-                break;
-            }
-            ctl[0] = msweep;
-            ctl[1] = nrot;
-        }
-        __syncthreads();
-        const int msweep = ctl[0], nrot = ctl[1];
-        if (msweep < 0) break;
-        if (tid < N && nrot > 0) {
-            // rotation t mixes columns (i, i+1), i = msweep - 1 - t; carry holds column i+1
-            double carry = Zt[msweep * N + tid];
-            for (int t = 0; t < nrot; ++t) {
-                const int i = msweep - 1 - t;
-                const double zi = Zt[i * N + tid];
-                Zt[(i + 1) * N + tid] = sn[t] * zi + cs[t] * carry;
-                carry = cs[t] * zi - sn[t] * carry;
-            }
-            Zt[(msweep - nrot) * N + tid] = carry;
-        }
-        __syncthreads();
-    }
-
-    // 3. order, eigenvalues, tridiagonal eigenvectors
-    for (int i = tid; i < N; i += NT) {
-        const double li = d[i];
-        const double ki = key ? fabs(li - ref) : li;
-        int rk = 0;
-        for (int j = 0; j < N; ++j) {
-            const double lj = d[j];
-            const double kj = key ? fabs(lj - ref) : lj;
-            if (kj < ki || (kj == ki && (lj < li || (lj == li && j < i)))) ++rk;
-        }
-        lam[rk] = li;
-        rank[i] = rk;
-    }
+    ql_block<NT, kLdsMaxN>(N, d, e, cs, sn, ctl, Zt, lam, rank, key, ref, info);
     for (int q = tid; q < N * N; q += NT) zg[q] = Zt[q];
-    if (tid == 0 && info) info[0] = fail ? -1 : maxiter;
 }
 
-// One wave per eigenvector, NW waves per workgroup; all reflectors staged in LDS.
-template <int NW>
+// Same algorithm for N <= kEigMaxN.  Ag: N x N work copy of A (full Hermitian,
+// rows coalesced); Z overwrites it once the reduction is done (zg == Ag).
+template <int NT>
+__global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
+                                                               double2 *__restrict__ Ag, double2 *__restrict__ hv,
+                                                               int *__restrict__ rank, double *__restrict__ lam,
+                                                               int key, double ref, int *__restrict__ info) {
+    __shared__ double2 v[kEigMaxN], w[kEigMaxN];
+    __shared__ double d[kEigMaxN], e[kEigMaxN], cs[2][kEigMaxN], sn[2][kEigMaxN];
+    __shared__ double2 sc[3][2];
+    __shared__ int ctl[2][2];
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tau_off = N * (N - 1) / 2;
+    for (int i = wid; i < N; i += NW)
+        for (int j = lane; j < N; j += 64) {
+            const double2 a = Ain[(int64_t)i * lda + j], b = Ain[(int64_t)j * lda + i];
+            Ag[(int64_t)i * N + j] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+        }
+    __syncthreads();
+    for (int k = 0; k + 1 < N; ++k) {
+        const int par = k & 1, m = N - 1 - k;
+        const double2 *rowk = Ag + (int64_t)k * N;          // A[k][i] = conj(A[i][k])
+        if (wid == 0) {
+            double s2 = 0.0;
+            for (int i = k + 2 + lane; i < N; i += 64) {
+                const double2 a = rowk[i];
+                s2 += a.x * a.x + a.y * a.y;
+            }
+            s2 = wave_sum(s2);
+            if (lane == 0) {
+                double2 tau, scl;
+                double beta;
+                householder(zconj(rowk[k + 1]), s2, tau, beta, scl);
+                d[k] = rowk[k].x;
+                e[k] = beta;
+                sc[0][par] = tau;
+                sc[1][par] = scl;
+                hv[tau_off + k] = tau;
+            }
+        }
+        __syncthreads();
+        const double2 tau = sc[0][par], scl = sc[1][par];
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        const int off = refl_off(k, N);
+        for (int i = k + 1 + tid; i < N; i += NT) {
+            const double2 x = i == k + 1 ? make_double2(1.0, 0.0) : zmul(zconj(rowk[i]), scl);
+            v[i] = x;
+            hv[off + (i - k - 1)] = x;
+        }
+        __syncthreads();
+        for (int r = wid; r < m; r += NW) {                 // w = tau A22 v, one wave per row
+            const int i = k + 1 + r;
+            const double2 *row = Ag + (int64_t)i * N;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = k + 1 + lane; j < N; j += 64) acc = zfma(row[j], v[j], acc);
+            acc = wave_sum2(acc);
+            if (lane == 0) w[i] = zmul(tau, acc);
+        }
+        __syncthreads();
+        if (wid == 0) {
+            double2 t = make_double2(0.0, 0.0);
+            for (int i = k + 1 + lane; i < N; i += 64) t = zfma(zconj(w[i]), v[i], t);
+            t = wave_sum2(t);
+            if (lane == 0) {
+                const double2 h = zmul(tau, t);
+                sc[2][par] = make_double2(-0.5 * h.x, -0.5 * h.y);
+            }
+        }
+        __syncthreads();
+        const double2 a2 = sc[2][par];
+        for (int r = wid; r < m; r += NW) {
+            const int i = k + 1 + r;
+            double2 *row = Ag + (int64_t)i * N;
+            const double2 vi = v[i], wi = zfma(a2, vi, w[i]);
+            for (int j = k + 1 + lane; j < N; j += 64) {
+                const double2 vj = v[j], wj = zfma(a2, vj, w[j]);
+                const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
+                double2 a = row[j];
+                a.x -= t1.x + t2.x;
+                a.y = i == j ? 0.0 : a.y - (t1.y + t2.y);
+                row[j] = a;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[N - 1] = Ag[(int64_t)(N - 1) * N + (N - 1)].x;
+        e[N - 1] = 0.0;
+    }
+    __syncthreads();
+    double *Zt = reinterpret_cast<double *>(Ag);
+    for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
+    __syncthreads();
+    ql_block<NT, kEigMaxN>(N, d, e, cs, sn, ctl, Zt, lam, rank, key, ref, info);
+}
+
+// Back-transformation, one wave per eigenvector, NW waves per workgroup.
+// LDS_V: all reflectors staged in LDS (N <= kLdsMaxN); otherwise read from
+// global memory one reflector ahead.
+template <int NW, int NMAX, bool LDS_V>
 __global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const double2 *__restrict__ hv,
                                                                 const double *__restrict__ zg,
                                                                 const int *__restrict__ rank,
                                                                 double2 *__restrict__ R) {
     extern __shared__ unsigned char smem_raw[];
-    double2 *sv = reinterpret_cast<double2 *>(smem_raw);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int tau_off = N * (N - 1) / 2;
-    for (int q = tid; q < tau_off + N - 1; q += 64 * NW) sv[q] = hv[q];
-    __syncthreads();
-    constexpr int Q = (kLdsMaxN + 63) / 64;
+    const double2 *sv = hv;
+    if constexpr (LDS_V) {
+        double2 *s = reinterpret_cast<double2 *>(smem_raw);
+        for (int q = tid; q < tau_off + N - 1; q += 64 * NW) s[q] = hv[q];
+        __syncthreads();
+        sv = s;
+    }
+    constexpr int Q = (NMAX + 63) / 64;
     const int m = blockIdx.x * NW + wid;
     if (m >= N) return;
     double2 y[Q];
@@ -612,23 +639,22 @@ __global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const dou
         const double2 tk = sv[tau_off + k];
         if (tk.x == 0.0 && tk.y == 0.0) continue;
         const int off = refl_off(k, N) - (k + 1);           // v_k[r] = sv[off + r], r > k
-        double2 s = make_double2(0.0, 0.0);
+        double2 vk[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int r = lane + 64 * q;
-            if (r > k && r < N) s = zfma(zconj(sv[off + r]), y[q], s);
+            vk[q] = (r > k && r < N) ? sv[off + r] : make_double2(0.0, 0.0);
         }
-        s.x = wave_sum(s.x);
-        s.y = wave_sum(s.y);
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s = zfma(zconj(vk[q]), y[q], s);
+        s = wave_sum2(s);
         const double2 ts = zmul(tk, s);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int r = lane + 64 * q;
-            if (r > k && r < N) {
-                const double2 u = zmul(ts, sv[off + r]);
-                y[q].x -= u.x;
-                y[q].y -= u.y;
-            }
+            const double2 u = zmul(ts, vk[q]);
+            y[q].x -= u.x;
+            y[q].y -= u.y;
         }
     }
     const int64_t row = (int64_t)rank[m] * N;
@@ -668,30 +694,37 @@ void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *statu
     PW_LAUNCH_CHECK();
 }
 
-void dense_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
-                double ref, int *info, hipStream_t st) {
-    PW_CHECK(N >= 1 && N <= 1024, PW_EUNSUPPORTED, "dense eigensolver limited to 1 <= N <= 1024");
-    if (N <= kLdsMaxN) {
-        // work_a: reflectors and taus (N (N + 1) / 2 complex); work_v: Z (N^2 real) then the ranks
-        double2 *hv = (double2 *)work_a;
-        double *zg = (double *)work_v;
-        int *rank = (int *)(zg + (size_t)N * N);
+size_t dense_eigh_work_bytes(int N) { return (size_t)32 * N * N; }
+
+void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void *R, int key, double ref, int *info,
+                hipStream_t st) {
+    PW_CHECK(N >= 1 && N <= kEigMaxN, PW_EUNSUPPORTED, "dense eigensolver limited to 1 <= N <= 1024");
+    // work: reflectors and taus, then Z (N^2 real; for N > kLdsMaxN the N x N
+    // complex copy of A that Z overwrites), then the ranks: 24 N^2 + 12 N bytes at most
+    const bool lds = N <= kLdsMaxN;
+    double2 *hv = (double2 *)work;
+    double2 *zbuf = hv + ((size_t)N * (N - 1) / 2 + N);
+    int *rank = (int *)((char *)zbuf + (size_t)N * N * (lds ? 8 : 16));
+    static size_t attr1 = 64 * 1024, attr2 = 64 * 1024;
+    if (lds) {
         const size_t b1 = std::max((size_t)N * (N + 1) / 2 * sizeof(double2), (size_t)N * N * sizeof(double));
-        static size_t attr1 = 64 * 1024, attr2 = 64 * 1024;
-        lds_limit(reinterpret_cast<const void *>(tridiag_ql_kernel<1024>), b1, attr1);
-        hipLaunchKernelGGL(tridiag_ql_kernel<1024>, dim3(1), dim3(1024), b1, st, N, (const double2 *)A, lda, hv,
-                           zg, rank, lam, key, ref, info);
+        lds_limit(reinterpret_cast<const void *>(tridiag_ql_lds_kernel<kEigNT>), b1, attr1);
+        hipLaunchKernelGGL(tridiag_ql_lds_kernel<kEigNT>, dim3(1), dim3(kEigNT), b1, st, N, (const double2 *)A, lda,
+                           hv, (double *)zbuf, rank, lam, key, ref, info);
         PW_LAUNCH_CHECK();
         const size_t b2 = std::max<size_t>(1, (size_t)N * (N - 1) / 2 + N - 1) * sizeof(double2);
-        lds_limit(reinterpret_cast<const void *>(backtransform_kernel<kBackNW>), b2, attr2);
-        hipLaunchKernelGGL(backtransform_kernel<kBackNW>, dim3((N + kBackNW - 1) / kBackNW), dim3(64 * kBackNW), b2,
-                           st, N, (const double2 *)hv, (const double *)zg, (const int *)rank, (double2 *)R);
+        lds_limit(reinterpret_cast<const void *>(backtransform_kernel<kBackNW, kLdsMaxN, true>), b2, attr2);
+        hipLaunchKernelGGL((backtransform_kernel<kBackNW, kLdsMaxN, true>), dim3((N + kBackNW - 1) / kBackNW),
+                           dim3(64 * kBackNW), b2, st, N, (const double2 *)hv, (const double *)zbuf,
+                           (const int *)rank, (double2 *)R);
+    } else {
+        hipLaunchKernelGGL(tridiag_ql_global_kernel<kEigNT>, dim3(1), dim3(kEigNT), 0, st, N, (const double2 *)A,
+                           lda, zbuf, hv, rank, lam, key, ref, info);
         PW_LAUNCH_CHECK();
-        return;
+        hipLaunchKernelGGL((backtransform_kernel<kBackNW, kEigMaxN, false>), dim3((N + kBackNW - 1) / kBackNW),
+                           dim3(64 * kBackNW), 0, st, N, (const double2 *)hv, (const double *)zbuf, (const int *)rank,
+                           (double2 *)R);
     }
-    const size_t lds = 512 * (2 * sizeof(int) + 2 * sizeof(double) + sizeof(double2));
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), lds, st, N, (const double2 *)A, lda, (double2 *)work_a,
-                       (double2 *)work_v, lam, (double2 *)R, key, ref, 25, 1e-13, info);
     PW_LAUNCH_CHECK();
 }
 

@@ -31,8 +31,10 @@ void backproj_bf16(int nb, int npw, int nproj, const void *projT, const void *be
 
 // dense.hip
 void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t);
-void dense_eigh(int N, const void *A, int64_t lda, void *work_a, void *work_v, double *lam, void *R, int key,
-                 double ref, int *info, hipStream_t);
+// Hermitian eigensolver (1 <= N <= 1024); work: dense_eigh_work_bytes(N) device bytes.
+size_t dense_eigh_work_bytes(int N);
+void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void *R, int key, double ref, int *info,
+                hipStream_t);
 
 // mlp.hip
 int mlp_nparam();

@@ -137,7 +137,7 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
     // Y^H Y ascending; the search directions and gradients turn with the bands.
     auto a_rr = [&](bool rotate_dirs) {
         zgemm_nt(nb, nb, npw, true, Y, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
-        dense_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
+        dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
         rotate3(Rm);
         if (rotate_dirs) {
             const void *in[2] = {P, G};
@@ -151,7 +151,7 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
     // residuals Delta_i of the H-Ritz vectors (the iterate itself is left alone)
     auto h_resid = [&]() {
         zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
-        dense_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
+        dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
         zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st);
         zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st);
         red_resid(nb, npw, T2, T1, L, lam, res, br, st);
@@ -265,7 +265,7 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
         hpsi_any(ctx, PW_C128, nb, X, L, Y, L, E, st);
         n_hpsi += nb;
         zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
-        dense_eigh(nb, Sm, nb, Aw, Vw, lam, Rm, 0, 0.0, d_status + 4, st);
+        dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
         rotate(Rm, X, T1);
         rotate(Rm, Y, T2);
         red_resid(nb, npw, Y, X, L, lam, res, br, st);
