@@ -12,8 +12,16 @@ cell, 48 x 48 x 192 grid, Ecut 10 Ha (48,369 plane waves), 256-atom fcc wire
 with Gaussian wells and 4 Kleinman-Bylander projectors per atom, 128 bands
 nearest E_ref = 0.3 Ha, complex128.
 
+Second part of the metric ("solve"): folded-CG time to max_i Delta_i <= 1e-6
+for the 128 states nearest E_ref (8 buffer bands, the same seeded start) with
+FP64 H psi + Teter-Payne-Allan, FP64 + the paper's M(G), mixed precision with
+TPA, with M(G) and with the learned preconditioner (K_TPA^2 e^f) (weights trained by
+paper_1907_06821_amd.train_precond and committed); time includes MLP inference,
+training time is reported separately.
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
---no-cpu (skip the CPU oracle leg) --precision {fp64,mixed}.
+--no-cpu (skip the CPU oracle leg) --no-solve --solve-legs a,b
+--precision {fp64,mixed} (of the band-H psi leg).
 """
 from __future__ import annotations
 
@@ -69,6 +77,58 @@ def cpu_baseline(prob, nb_sample=64, iters=2):
                       f"Rayleigh-Ritz, {r['n_hpsi']} band-Hpsi in {dt:.1f} s"}
 
 
+SOLVE_LEGS = (("fp64_tpa", 0, 0), ("fp64_mg", 0, 1), ("mixed_tpa", 1, 0), ("mixed_mg", 1, 1),
+              ("mixed_learned", 1, 2))
+
+
+def solve_legs(ctx, prob, nb, nconv, legs, maxit=4000, log=None):
+    """Folded-CG time to max Delta_i <= 1e-6 (FP64 H psi residuals, final H
+    Rayleigh-Ritz) from the same seeded start for each (name, precision,
+    preconditioner); the learned network comes from the committed weights."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth, train_precond
+    wpath = os.path.join(train_precond.DATA_DIR, train_precond.WEIGHTS)
+    meta = None
+    if os.path.exists(wpath + ".npy"):
+        w = torch.from_numpy(np.load(wpath + ".npy")).to("cuda")
+        pw.mlp_set(ctx, w)
+        with open(wpath + ".json") as f:
+            meta = json.load(f)
+    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
+    out, ref = {}, None
+    for name, precision, precond in legs:
+        if precond == 2 and meta is None:
+            out[name] = {"skipped": "no trained weights"}
+            continue
+        psi = psi0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=maxit, check_every=20,
+                                          precision=precision, precond=precond, nconv=nconv,
+                                          raise_on_noconv=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        near = np.sort(eig[np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv]])
+        if ref is None:
+            ref = near
+        out[name] = {"seconds": round(dt, 3), "iters": st["iters"], "n_hpsi": st["n_hpsi"],
+                     "converged": bool(st["converged"]), "max_resid": st["max_resid"],
+                     "precision": "mixed" if precision else "fp64", "precond": ("tpa", "mg", "learned")[precond],
+                     "max_eig_diff_vs_first": float(np.max(np.abs(near - ref)))}
+        if log:
+            log(f"solve {name}: {out[name]}")
+    res = {"tol": 1e-6, "bands": nb, "nconv": nconv, "e_ref": prob.e_ref, "legs": out}
+    base, best = out.get("fp64_tpa", {}), out.get("mixed_learned", {})
+    if base.get("converged") and best.get("converged"):
+        res["speedup_mixed_learned_vs_fp64_tpa"] = round(base["seconds"] / best["seconds"], 3)
+    if meta is not None:
+        res["training"] = {k: meta[k] for k in ("harvest_seconds", "train_seconds", "train_steps", "loss_first",
+                                                 "loss_last", "samples")}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +137,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--cpu-bands", type=int, default=64)
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-residual solves")
+    ap.add_argument("--solve-legs", default=",".join(n for n, _, _ in SOLVE_LEGS))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver shards no work across GPUs in this build",
@@ -91,8 +153,8 @@ def main():
     torch.cuda.set_device(0)
     prob = synth.config(2)
     mixed = args.precision == "mixed"
-    flags = pw.PW_PREP_C128 | (pw.PW_PREP_C64 if mixed else 0)
-    ctx = pw.Context.from_problem(prob, max_bands=prob.nbands, flags=flags)
+    nbuf = 8                                       # buffer bands of the time-to-residual solves
+    ctx = pw.Context.from_problem(prob, max_bands=prob.nbands + nbuf, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
     nb = prob.nbands
     psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
     opts = dict(tol=1e-30, check_every=20, precision=1 if mixed else 0)
@@ -156,6 +218,10 @@ def main():
                    for k, v in stages.items()},
         "n_hpsi": st["n_hpsi"],
     }
+    if not args.no_solve:
+        legs = [l for l in SOLVE_LEGS if l[0] in args.solve_legs.split(",")]
+        line["solve"] = solve_legs(ctx, prob, nb + nbuf, nb, legs, log=lambda m: print(m, file=sys.stderr,
+                                                                                       flush=True))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
     else:

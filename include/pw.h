@@ -227,9 +227,13 @@ pw_status pw_mlp_forward(int32_t nshell, int32_t nb, const double *shell_t, cons
 /* Shell tables of one snapshot: x_snap [nb][ld] an iterate of a solve at e_ref,
  * x_conv [nb][ld] the converged orthonormal block.  Recomputes the gradient
  * g = A x - <x|A|x> x with two FP64 H psi, the TPA weights K0 and the band kinetic
- * energies (written to tband [nb]), and writes tabs [3][nshell][nb]. */
+ * energies (written to tband [nb]), and writes tabs [3][nshell][nb]: per shell s
+ * and band i, the sums over the shell of Re(conj(e) K0 g), |K0 g|^2 and |e|^2 with
+ * e = -(I - X* X*^H) x.  weight_delta >= 0 multiplies the sums of shell s by
+ * (T_s - e_ref)^2 + weight_delta^2 (an approximate A-norm for the cosine loss);
+ * weight_delta < 0 leaves them unweighted. */
 pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
-                         double *tabs, double *tband, void *stream);
+                         double weight_delta, double *tabs, double *tband, void *stream);
 
 /* Scratch bytes needed by pw_mlp_loss_grad (host function). */
 int64_t pw_mlp_work_bytes(int32_t nshell, int32_t nb, int32_t nsnap);

@@ -20,6 +20,12 @@ With shell sums A_si = sum_{G in s} Re(conj(e_i) K0_i g_i), B_si = sum_{G in s}
     L_i = 1 - (sum_s w_si A_si) / (sqrt(sum_s w_si^2 B_si) sqrt(E_i)).
 The training loss is the mean of L_i over bands and snapshots.
 
+Weighted variant (used for training): the inner products and norms above are
+taken in the metric diag(w_G), w_G = (T_G - E_ref)^2 + delta^2, the plane-wave
+diagonal of (H - E_ref)^2 without the potential (an approximate A-norm).  w is
+constant on a shell, so A_si, B_si and the shell parts of E_i are multiplied by
+w_s and the loss formula is unchanged.
+
 Parameter vector layout (4481 values): W1[64][3], b1[64], W2[64][64], b2[64],
 W3[64], b3.
 """
@@ -122,11 +128,12 @@ def adam_step(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def harvest_tables(x_snap, x_conv, g, k0, shell, nshell):
+def harvest_tables(x_snap, x_conv, g, k0, shell, nshell, weight=None):
     """Shell tables of one snapshot.
 
     x_snap [nb][npw] current bands, x_conv [nb][npw] converged orthonormal block,
-    g [nb][npw] gradients, k0 [nb][npw] base preconditioner weights, shell [npw].
+    g [nb][npw] gradients, k0 [nb][npw] base preconditioner weights, shell [npw],
+    weight [nshell] optional metric weight per shell (w_s above).
     Returns A [nshell][nb], B [nshell][nb], E [nb]."""
     coef = x_snap @ x_conv.conj().T            # [i][j] = <x_conv_j | x_i>
     e = x_snap - coef @ x_conv                 # (I - P*) x_i
@@ -136,7 +143,8 @@ def harvest_tables(x_snap, x_conv, g, k0, shell, nshell):
     b = np.zeros((nshell, nb))
     ra = np.real(np.conj(e) * kg)
     rb = np.abs(kg) ** 2
+    wg = np.ones(len(shell)) if weight is None else np.asarray(weight)[shell]
     for i in range(nb):
-        a[:, i] = np.bincount(shell, weights=ra[i], minlength=nshell)
-        b[:, i] = np.bincount(shell, weights=rb[i], minlength=nshell)
-    return a, b, np.sum(np.abs(e) ** 2, axis=1)
+        a[:, i] = np.bincount(shell, weights=wg * ra[i], minlength=nshell)
+        b[:, i] = np.bincount(shell, weights=wg * rb[i], minlength=nshell)
+    return a, b, np.sum(wg[None, :] * np.abs(e) ** 2, axis=1)

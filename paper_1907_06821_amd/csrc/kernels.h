@@ -45,7 +45,8 @@ void mlp_loss_grad(int nshell, int nb, int nsnap, const double *shell_t, const d
                    double ecut, const double *tabs, const float *w, float *grad, float *loss, void *work, hipStream_t);
 void mlp_adam(float *w, const float *g, float *m, float *v, int step, float lr, hipStream_t);
 void shell_tables(int nshell, int nb, int npw, const int32_t *shell_off, const int32_t *shell_pw, const void *E,
-                  const void *Z, int64_t ld, double *tabs, hipStream_t);
+                  const void *Z, int64_t ld, const double *shell_t, double e_ref, double delta, double *tabs,
+                  hipStream_t);
 
 // blas1.hip -------------------------------------------------------------------
 struct PrecArgs {

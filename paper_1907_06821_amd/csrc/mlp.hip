@@ -285,10 +285,14 @@ void mlp_adam(float *w, const float *g, float *m, float *v, int step, float lr, 
 // harvest: shell sums of one snapshot.  E = (I - P*) X (band-major, [nb][npw]),
 // Z = K0 o g.  tabs[0][s][i] = sum Re(conj E . Z), [1] = sum |Z|^2, [2] = sum |E|^2,
 // summed over the plane waves of shell s listed in shell_pw[shell_off[s] ..].
+// delta >= 0: every sum of shell s is weighted by (T_s - e_ref)^2 + delta^2, the
+// plane-wave diagonal of (H - E)^2 without the potential, so that the loss
+// compares K g and E in that approximate A-norm instead of the Euclidean one.
 // ---------------------------------------------------------------------------
 __global__ void k_shell_tables(int nshell, int nb, int npw, const int32_t *__restrict__ shell_off,
                                const int32_t *__restrict__ shell_pw, const double2 *__restrict__ E,
-                               const double2 *__restrict__ Z, int64_t ld, double *__restrict__ tabs) {
+                               const double2 *__restrict__ Z, int64_t ld, const double *__restrict__ shell_t,
+                               double e_ref, double delta, double *__restrict__ tabs) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nshell * nb) return;
     const int s = (int)(idx / nb), i = (int)(idx % nb);
@@ -300,16 +304,23 @@ __global__ void k_shell_tables(int nshell, int nb, int npw, const int32_t *__res
         b += z.x * z.x + z.y * z.y;
         c += e.x * e.x + e.y * e.y;
     }
+    if (delta >= 0.0) {
+        const double dt = shell_t[s] - e_ref, w = dt * dt + delta * delta;
+        a *= w;
+        b *= w;
+        c *= w;
+    }
     tabs[idx] = a;
     tabs[(int64_t)nshell * nb + idx] = b;
     tabs[2 * (int64_t)nshell * nb + idx] = c;
 }
 
 void shell_tables(int nshell, int nb, int npw, const int32_t *shell_off, const int32_t *shell_pw, const void *E,
-                  const void *Z, int64_t ld, double *tabs, hipStream_t st) {
+                  const void *Z, int64_t ld, const double *shell_t, double e_ref, double delta, double *tabs,
+                  hipStream_t st) {
     const int64_t n = (int64_t)nshell * nb;
     hipLaunchKernelGGL(k_shell_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nshell, nb, npw, shell_off,
-                       shell_pw, (const double2 *)E, (const double2 *)Z, ld, tabs);
+                       shell_pw, (const double2 *)E, (const double2 *)Z, ld, shell_t, e_ref, delta, tabs);
     PW_LAUNCH_CHECK();
 }
 

@@ -303,8 +303,8 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
 
 // Training tables of one snapshot (see pw_mlp_harvest in pw.h), using the solver's
 // blocks as scratch.
-void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, int64_t ld, double *tabs,
-                 double *tband_out, hipStream_t st) {
+void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, int64_t ld, double delta,
+                 double *tabs, double *tband_out, hipStream_t st) {
     const int npw = ctx->basis.npw;
     Solver *s = solver_get(ctx, nb, false);
     const int64_t L = npw;
@@ -330,7 +330,7 @@ void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, 
     copy_block(nb, npw, X, L, T1, L, st);
     zgemm_nn_launch(nb, npw, nb, Wm, nb, Xc, L, -1.0, 1.0, T1, L, st);
     shell_tables((int)ctx->basis.shell_t.size(), nb, npw, ctx->d_shell_off.as<int32_t>(),
-                 ctx->d_shell_pw.as<int32_t>(), T1, Z, L, tabs, st);
+                 ctx->d_shell_pw.as<int32_t>(), T1, Z, L, ctx->d_shell_t.as<double>(), E, delta, tabs, st);
     PW_HIP(hipMemcpyAsync(tband_out, tband, nb * sizeof(double), hipMemcpyDeviceToDevice, st));
 }
 
@@ -339,13 +339,13 @@ void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, 
 extern "C" {
 
 pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
-                         double *tabs, double *tband, void *stream) {
+                         double weight_delta, double *tabs, double *tband, void *stream) {
     try {
         PW_CHECK(ctx && x_snap && x_conv && tabs && tband, PW_EINVAL, "null argument");
         PW_CHECK(ctx->flags & PW_PREP_C128, PW_EUNSUPPORTED, "harvest needs a complex128 context");
         PW_CHECK(nb >= 1 && nb <= ctx->max_bands && nb <= 1024 && ld >= ctx->basis.npw, PW_EINVAL,
                  "bad harvest sizes");
-        pw::mlp_harvest(ctx, e_ref, nb, x_snap, x_conv, ld, tabs, tband, (hipStream_t)stream);
+        pw::mlp_harvest(ctx, e_ref, nb, x_snap, x_conv, ld, weight_delta, tabs, tband, (hipStream_t)stream);
         return PW_OK;
     } catch (const pw::Fail &f) {
         return f.st;

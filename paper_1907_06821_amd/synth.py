@@ -250,3 +250,18 @@ def small_nonlocal_problem(seed=0, grid=(12, 15, 20), cell=(7.0, 8.0, 9.0), ecut
     d = _kb_strengths(7, natom, 4, seed)
     return Problem("small_nl", tuple(cell), tuple(grid), float(ecut), pos, np.full(natom, -2.5), 1.1,
                    4, 0.8, d, e_ref, nbands, kpt=tuple(kpt), seed=seed)
+
+
+def mlp_init(seed=0, hidden=64):
+    """Initial draws of the 3-hidden-hidden-1 preconditioner network, flat float64
+    in the layout W1[h][3], b1[h], W2[h][h], b2[h], W3[h], b3: Glorot-uniform
+    weights, zero biases, the last layer scaled by 0.1 so that the network starts
+    near f = 0 (the plain preconditioner).  Seeds default_rng([5, seed])."""
+    rng = np.random.default_rng([5, seed])
+
+    def glorot(o, i):
+        lim = math.sqrt(6.0 / (o + i))
+        return rng.uniform(-lim, lim, size=(o, i))
+
+    return np.concatenate([glorot(hidden, 3).ravel(), np.zeros(hidden), glorot(hidden, hidden).ravel(),
+                           np.zeros(hidden), 0.1 * glorot(1, hidden).ravel(), np.zeros(1)])

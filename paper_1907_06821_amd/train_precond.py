@@ -1,0 +1,123 @@
+"""Training of the learned per-G-shell preconditioner, on the GPU.
+
+Samples come from the method's own solves: folded-spectrum CG runs on a cell
+store snapshots of the iterate X(t); once converged (X*), every snapshot gives
+the per-(shell, band) tables of its gradient g = A x - mu x and of its error
+direction e = -(I - X* X*^H) x (gauge invariant).  The network
+f(T_shell, T_band, E_ref) of the preconditioner K = K_TPA^2 e^f is then fitted
+to the cosine loss 1 - Re<K g, e> / (|K g| |e|) with the library's own loss,
+gradient and Adam kernels.  The inner products are taken in the metric
+diag((T_G - E_ref)^2 + delta^2), the plane-wave diagonal of the folded operator
+without the potential: trained that way the network takes fewer CG iterations
+than trained on the Euclidean cosine.
+
+    python -m paper_1907_06821_amd.train_precond --out paper_1907_06821_amd/data
+
+writes precond_wire256.npy (float32 weights) and precond_wire256.json (what the
+samples were, training time and loss history).  The training energies and start
+vectors are disjoint from the ones the benchmark solves with.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import paper_1907_06821_amd as pw  # noqa: E402
+from paper_1907_06821_amd import synth  # noqa: E402
+
+DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+WEIGHTS = "precond_wire256"
+
+
+def harvest(ctx, prob, energies, start_seed, nb, nconv, snap_every, nsnap, maxit, weight_delta=0.5, log=print):
+    """Solve once per energy with snapshots; returns device tables
+    (tabs [S, 3, nshell, nb], tband [S, nb], e_ref [S]) and a record per solve."""
+    import torch
+    tabs_l, tband_l, er_l, solves = [], [], [], []
+    for j, e in enumerate(energies):
+        psi = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=start_seed + j)).to("cuda")
+        snaps = torch.zeros((nsnap, nb, ctx.npw), dtype=torch.complex128, device="cuda")
+        eig, res, st = pw.folded_cg_solve(ctx, e, psi, tol=1e-6, maxit=maxit, check_every=20, precond=0,
+                                          nconv=nconv, snapshots=snaps, snap_every=snap_every,
+                                          raise_on_noconv=False)
+        rec = {"e_ref": e, "start_seed": start_seed + j, "iters": st["iters"], "seconds": round(st["seconds"], 2),
+               "max_resid": st["max_resid"], "snapshots": st["n_snap"]}
+        solves.append(rec)
+        log(f"harvest solve {rec}")
+        if not st["converged"]:
+            continue
+        for k in range(1, st["n_snap"]):      # the first snapshot is the random start
+            tb, tband = pw.mlp_harvest(ctx, e, snaps[k], psi, weight_delta=weight_delta)
+            tabs_l.append(tb)
+            tband_l.append(tband)
+            er_l.append(e)
+        del snaps
+    if not tabs_l:
+        raise RuntimeError("no harvest solve converged")
+    tabs = torch.stack(tabs_l).contiguous()
+    tband = torch.stack(tband_l).contiguous()
+    er = torch.tensor(er_l, dtype=torch.float64, device="cuda")
+    return tabs, tband, er, solves
+
+
+def train(ctx, prob, tabs, tband, er, steps, lr, seed=0):
+    import torch
+    shell_t = torch.from_numpy(ctx.shells()[1]).to("cuda")
+    w = torch.from_numpy(synth.mlp_init(seed).astype(np.float32)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, _, _ = pw.mlp_train(shell_t, tband, er, prob.ecut, tabs, w, steps, lr=lr)
+    torch.cuda.synchronize()
+    return w, hist, time.perf_counter() - t0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DATA_DIR)
+    ap.add_argument("--energies", default="0.25,0.35")
+    ap.add_argument("--start-seed", type=int, default=11)
+    ap.add_argument("--bands", type=int, default=136)
+    ap.add_argument("--nconv", type=int, default=128)
+    ap.add_argument("--snap-every", type=int, default=60)
+    ap.add_argument("--nsnap", type=int, default=16)
+    ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--weight-delta", type=float, default=0.5, help="metric delta (Ha); < 0: Euclidean")
+    a = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    prob = synth.config(2)
+    ctx = pw.Context.from_problem(prob, max_bands=a.bands)
+    energies = [float(x) for x in a.energies.split(",")]
+    t0 = time.perf_counter()
+    tabs, tband, er, solves = harvest(ctx, prob, energies, a.start_seed, a.bands, a.nconv, a.snap_every, a.nsnap,
+                                      a.maxit, a.weight_delta, log=lambda s: print(s, flush=True))
+    t_harvest = time.perf_counter() - t0
+    print(f"harvested {tabs.shape[0]} snapshots in {t_harvest:.1f} s", flush=True)
+    w, hist, t_train = train(ctx, prob, tabs, tband, er, a.steps, a.lr)
+    print(f"trained {a.steps} Adam steps in {t_train:.1f} s: loss {hist[0]:.4f} -> {hist[-1]:.4f}", flush=True)
+    os.makedirs(a.out, exist_ok=True)
+    np.save(os.path.join(a.out, WEIGHTS + ".npy"), w.cpu().numpy())
+    meta = {"workload": prob.name, "bands": a.bands, "nconv": a.nconv, "harvest_solves": solves,
+            "samples": {"snapshots": int(tabs.shape[0]), "shells": ctx.nshell, "bands": a.bands},
+            "harvest_seconds": round(t_harvest, 2), "train_steps": a.steps, "lr": a.lr,
+            "weight_delta": a.weight_delta,
+            "train_seconds": round(t_train, 2), "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+            "loss_every_20": [round(float(x), 5) for x in hist[::20]],
+            "command": "python -m paper_1907_06821_amd.train_precond " + " ".join(argv or sys.argv[1:])}
+    with open(os.path.join(a.out, WEIGHTS + ".json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps({k: meta[k] for k in ("harvest_seconds", "train_seconds", "loss_first", "loss_last")}))
+
+
+if __name__ == "__main__":
+    main()

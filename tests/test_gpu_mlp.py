@@ -71,9 +71,11 @@ def test_mlp_adam_matches_oracle(torch_cuda):
     assert np.max(np.abs(tm.cpu().numpy() - m1)) < 1e-6
 
 
-def test_mlp_harvest_matches_oracle(torch_cuda):
+@pytest.mark.parametrize("delta", [-1.0, 0.5])
+def test_mlp_harvest_matches_oracle(torch_cuda, delta):
     """Tables from a partly converged snapshot against the oracle's own gradient,
-    TPA weights, target correction and shell sums."""
+    TPA weights, target correction and shell sums, unweighted and in the
+    (T_s - E)^2 + delta^2 shell metric."""
     import paper_1907_06821_amd as pw
     prob = synth.small_nonlocal_problem(nbands=4, e_ref=0.8)
     op = oracle_for(prob)
@@ -85,7 +87,7 @@ def test_mlp_harvest_matches_oracle(torch_cuda):
     xs = xc + 0.05 * (rng.standard_normal(xc.shape) + 1j * rng.standard_normal(xc.shape))
     xs = np.linalg.qr(xs.T)[0].T.copy()
     ctx = gpu_context(prob, max_bands=4)
-    tabs, tband = pw.mlp_harvest(ctx, prob.e_ref, to_dev(xs), to_dev(xc))
+    tabs, tband = pw.mlp_harvest(ctx, prob.e_ref, to_dev(xs), to_dev(xc), weight_delta=delta)
     # oracle
     y = xs @ h.T - prob.e_ref * xs
     ax = y @ h.T - prob.e_ref * y
@@ -94,7 +96,8 @@ def test_mlp_harvest_matches_oracle(torch_cuda):
     tb = band_kinetic(xs, op.kin)
     k0 = tpa2(op.kin, tb)
     sid, st = shells(op.kin)
-    a, b, e = om.harvest_tables(xs, xc, g, k0, sid, len(st))
+    wsh = None if delta < 0 else (np.asarray(st) - prob.e_ref) ** 2 + delta ** 2
+    a, b, e = om.harvest_tables(xs, xc, g, k0, sid, len(st), weight=wsh)
     got = tabs.cpu().numpy()
     assert got.shape == (3, len(st), 4)
     assert np.max(np.abs(tband.cpu().numpy() - tb)) < 1e-12
@@ -117,3 +120,31 @@ def test_learned_preconditioner_solve_matches_dense(torch_cuda):
     t = to_dev(synth.start_vectors(7, 6, ctx.npw))
     eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, t, tol=1e-9, maxit=4000, check_every=10, precond=2)
     assert st["converged"] and np.max(np.abs(eig - lam)) < 1e-8
+
+
+def test_trained_network_beats_its_plain_base(torch_cuda):
+    """The committed network (trained on other energies and start vectors) against
+    the TPA preconditioner it scales, on the 256-atom wire: same mixed-precision
+    solve, same start; fewer iterations to max Delta <= 1e-6 and the same
+    eigenvalues."""
+    import os
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import train_precond
+    prob = synth.config(2)
+    nb, nconv = 136, 128
+    ctx = pw.Context.from_problem(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    w = np.load(os.path.join(train_precond.DATA_DIR, train_precond.WEIGHTS + ".npy"))
+    pw.mlp_set(ctx, torch.from_numpy(w).to("cuda"))
+    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=0)).to("cuda")
+    out = {}
+    for pc in (0, 2):
+        psi = psi0.clone()
+        eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=2000, check_every=20, precision=1,
+                                          precond=pc, nconv=nconv, raise_on_noconv=False)
+        near = np.sort(eig[np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv]])
+        out[pc] = (st["iters"], st["converged"], near)
+        print(f"precond {pc}: {st['iters']} iterations, {st['seconds']:.2f} s")
+    assert out[0][1] and out[2][1]
+    assert out[2][0] < 0.85 * out[0][0]
+    assert np.max(np.abs(out[2][2] - out[0][2])) < 1e-8
