@@ -142,6 +142,36 @@ pw_status pw_grid_to_wave(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *g
  * PW_ENOTPD (synchronising) if a Cholesky pivot is not positive. */
 pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void *stream);
 
+/* FFT launch autotuner.  A candidate is one launch variant of one pass of
+ * pw_hpsi's FFT: pass 0 the z inverse pass, 1 the xy planes with V(r), 2 the
+ * z forward pass with the kinetic term; kind 1 the kernel built for this
+ * length at compile time, kind 2 the runtime-plan kernel with nthr threads
+ * (256, 512 or 1024) and radix schedule sched (0: radices 8 first, 1: radix 4
+ * at most, 2: the radices of 0 in ascending order; radix[] lists the z plan or
+ * the xy axis-0 plan), kind 0 the built-in default. */
+typedef struct {
+    int32_t pass;
+    int32_t kind;
+    int32_t nthr;
+    int32_t sched;
+    int32_t nradix;
+    int32_t radix[12];
+    double ms;            /* out: time per launch on nb bands */
+    int32_t chosen;       /* out: 1 for the fastest of its pass */
+} pw_fft_cand;
+
+/* Times every candidate that fits this context's grid on nb (<= max_bands)
+ * bands of dtype, reps launches each, and installs the fastest of each pass
+ * for later pw_hpsi calls of that dtype.  The records (at most cap) go to
+ * cands (host), their number to *ncand.  Results are cached per (grid, sphere,
+ * dtype, nb) for the process, so equal cells are timed once.  Allocates
+ * scratch; synchronises. */
+pw_status pw_ctx_autotune(pw_ctx *ctx, pw_dtype dtype, int32_t nb, int32_t reps, pw_fft_cand *cands, int32_t cap,
+                          int32_t *ncand, void *stream);
+/* Installs one candidate (pass, kind, nthr, sched of *cand) for dtype; kind 0
+ * restores the default.  PW_EUNSUPPORTED if it does not fit the grid. */
+pw_status pw_ctx_fft_choose(pw_ctx *ctx, pw_dtype dtype, const pw_fft_cand *cand);
+
 /* Small dense FP64 kernels of the block algebra, exposed for direct use and
  * testing (one workgroup each, n <= 1024; device pointers, complex128, row-major).
  *
@@ -200,6 +230,23 @@ void pw_cg_opts_default(pw_cg_opts *opts);
 pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld,
                              double *eig, double *resid, const pw_cg_opts *opts,
                              pw_cg_stats *stats, void *stream);
+
+/* Batched folded-spectrum solves of nprob independent problems (many cells of
+ * uneven grid size and many E_ref values), each with its own context ctx[p]
+ * (distinct), start/result block psi[p] (device complex128 [nb][ld[p]]) and
+ * e_ref[p]; eig[p], resid[p] (host [nb] each; eig/resid may be NULL) as for
+ * pw_folded_cg_solve, stats (host [nprob], optional), status (host [nprob],
+ * optional) the per-problem result.  Every problem runs the kernels of its own
+ * pw_folded_cg_solve in the same order (same results); the check_every
+ * iterations between checks are recorded once per problem into a graph, and the
+ * graphs of all running problems are replayed as one graph (independent child
+ * graphs) on `stream`, one launch per check round, with one host read of every
+ * problem's residuals in between.  Snapshots are not supported.  Returns PW_OK
+ * if every problem converged, PW_ENOCONV if some did not, else the first other
+ * error.  Synchronises. */
+pw_status pw_batch_solve(int32_t nprob, pw_ctx *const *ctx, const double *e_ref, int32_t nb, void *const *psi,
+                         const int64_t *ld, double *const *eig, double *const *resid, const pw_cg_opts *opts,
+                         pw_cg_stats *stats, int32_t *status, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner (precond = 2).  Not in the paper: a network standing in

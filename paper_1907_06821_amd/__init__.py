@@ -29,7 +29,7 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_orthonormalize", "pw_cg_opts_default", "pw_folded_cg_solve", "pw_dense_eigh",
            "pw_dense_chol_inv", "pw_mlp_set", "pw_mlp_forward", "pw_mlp_harvest", "pw_mlp_work_bytes",
            "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
-           "pw_profile_end", "pw_last_error")
+           "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
 PW_PROF_NKINDS = 8
 
@@ -59,6 +59,11 @@ class pw_cg_opts(C.Structure):
                 ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32),
                 ("mixed_switch", C.c_double), ("stall_checks", C.c_int32), ("snap_buf", C.c_void_p),
                 ("snap_every", C.c_int32), ("snap_cap", C.c_int32), ("nconv", C.c_int32)]
+
+
+class pw_fft_cand(C.Structure):
+    _fields_ = [("pass_", C.c_int32), ("kind", C.c_int32), ("nthr", C.c_int32), ("sched", C.c_int32),
+                ("nradix", C.c_int32), ("radix", C.c_int32 * 12), ("ms", C.c_double), ("chosen", C.c_int32)]
 
 
 class pw_cg_stats(C.Structure):
@@ -104,6 +109,9 @@ def lib():
                              C.POINTER(C.c_float), vp, i64, vp],
             "pw_profile_begin": [vp, i32],
             "pw_profile_end": [vp, C.POINTER(dbl), C.POINTER(i64)],
+            "pw_batch_solve": [i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
+            "pw_ctx_autotune": [vp, i32, i32, i32, vp, i32, C.POINTER(i32), vp],
+            "pw_ctx_fft_choose": [vp, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -457,3 +465,67 @@ def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_o
     if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
         _check(status)
     return eig, res, stats
+
+
+def batch_solve(ctxs, e_refs, psis, opts=None, hist_len=0, stream=None, raise_on_noconv=True, **kw):
+    """Folded-spectrum PCG of independent problems in one batched call (one
+    context and one complex128 block [nb, npw_p] per problem, same nb).
+    Returns (eigs, resids, stats, status): lists of per-problem arrays/dicts and
+    the per-problem status codes."""
+    n = len(ctxs)
+    if not (n == len(e_refs) == len(psis)) or n == 0:
+        raise ValueError("ctxs, e_refs and psis must have the same non-zero length")
+    nb = psis[0].shape[0]
+    for c, p in zip(ctxs, psis):
+        _check_block(p, c.npw)
+        if p.shape[0] != nb:
+            raise ValueError("every block must have the same number of bands")
+    o = opts if opts is not None else cg_opts(**kw)
+    ctx_arr = (C.c_void_p * n)(*[c.handle for c in ctxs])
+    e_arr = np.ascontiguousarray(e_refs, dtype=np.float64)
+    psi_arr = (C.c_void_p * n)(*[p.data_ptr() for p in psis])
+    ld_arr = np.array([p.stride(0) for p in psis], dtype=np.int64)
+    eigs = [np.zeros(nb) for _ in range(n)]
+    ress = [np.zeros(nb) for _ in range(n)]
+    eig_arr = (C.c_void_p * n)(*[e.ctypes.data for e in eigs])
+    res_arr = (C.c_void_p * n)(*[r.ctypes.data for r in ress])
+    st_arr = (pw_cg_stats * n)()
+    hists = [np.zeros((max(hist_len, 0), 2)) for _ in range(n)]
+    for s_, h in zip(st_arr, hists):
+        s_.n_hist = int(hist_len)
+        s_.hist = h.ctypes.data_as(C.POINTER(C.c_double)) if hist_len else C.POINTER(C.c_double)()
+    status = np.zeros(n, dtype=np.int32)
+    rc = lib().pw_batch_solve(n, ctx_arr, e_arr.ctypes.data, nb, psi_arr, ld_arr.ctypes.data, eig_arr, res_arr,
+                              C.byref(o), st_arr, status.ctypes.data, _stream_ptr(stream))
+    stats = [dict(iters=s.iters, converged=bool(s.converged), n_hpsi=s.n_hpsi, max_resid=s.max_resid,
+                  seconds=s.seconds, hist=h[:s.n_hist].copy()) for s, h in zip(st_arr, hists)]
+    if rc != PW_OK and not (rc == PW_ENOCONV and not raise_on_noconv):
+        _check(rc)
+    return eigs, ress, stats, status
+
+
+FFT_PASSES = ("z_inverse", "xy_fft_v", "z_forward_kinetic")
+
+
+def _cand_dict(c):
+    return dict(pass_=c.pass_, kind=c.kind, nthr=c.nthr, sched=c.sched, radix=list(c.radix[:c.nradix]), ms=c.ms,
+                chosen=bool(c.chosen))
+
+
+def autotune(ctx, nb, dtype=PW_C128, reps=5, stream=None):
+    """Time every FFT launch variant of this context's grid on nb bands, install the
+    fastest per pass for `dtype`; returns the candidate records (dicts)."""
+    cap = 256
+    arr = (pw_fft_cand * cap)()
+    n = C.c_int32(0)
+    _check(lib().pw_ctx_autotune(ctx.handle, int(dtype), int(nb), int(reps), arr, cap, C.byref(n),
+                                 _stream_ptr(stream)))
+    return [_cand_dict(arr[i]) for i in range(min(n.value, cap))]
+
+
+def fft_choose(ctx, cand, dtype=PW_C128):
+    """Install one candidate (dict with pass_, kind, nthr, sched) for `dtype`."""
+    c = pw_fft_cand()
+    c.pass_, c.kind, c.nthr, c.sched = int(cand["pass_"]), int(cand["kind"]), int(cand.get("nthr", 0)), \
+        int(cand.get("sched", 0))
+    _check(lib().pw_ctx_fft_choose(ctx.handle, int(dtype), C.byref(c)))

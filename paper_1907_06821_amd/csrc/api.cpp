@@ -525,6 +525,30 @@ pw_status pw_profile_end(pw_ctx *ctx, double *ms, int64_t *launches) {
     PW_API_END
 }
 
+pw_status pw_ctx_autotune(pw_ctx *ctx, pw_dtype dtype, int32_t nb, int32_t reps, pw_fft_cand *cands, int32_t cap,
+                          int32_t *ncand, void *stream) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && (cands || cap == 0) && cap >= 0, PW_EINVAL, "bad autotune arguments");
+    PW_CHECK(dtype == PW_C128 || dtype == PW_C64, PW_EINVAL, "unknown dtype");
+    PW_CHECK(ctx->flags & (dtype == PW_C128 ? PW_PREP_C128 : PW_PREP_C64), PW_EUNSUPPORTED,
+             "context not prepared for this dtype");
+    std::vector<pw_fft_cand> recs;
+    if (dtype == PW_C128) autotune_fft<double>(ctx, nb, reps, recs, (hipStream_t)stream);
+    else autotune_fft<float>(ctx, nb, reps, recs, (hipStream_t)stream);
+    for (int i = 0; i < (int)recs.size() && i < cap; ++i) cands[i] = recs[i];
+    if (ncand) *ncand = (int32_t)recs.size();
+    PW_API_END
+}
+
+pw_status pw_ctx_fft_choose(pw_ctx *ctx, pw_dtype dtype, const pw_fft_cand *cand) {
+    PW_API_BEGIN
+    PW_CHECK(ctx && cand, PW_EINVAL, "null argument");
+    PW_CHECK(dtype == PW_C128 || dtype == PW_C64, PW_EINVAL, "unknown dtype");
+    if (dtype == PW_C128) fft_choose<double>(ctx, *cand);
+    else fft_choose<float>(ctx, *cand);
+    PW_API_END
+}
+
 pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void *stream) {
     PW_API_BEGIN
     check_block_args(ctx, PW_C128, nb, psi, ld);

@@ -125,4 +125,23 @@ FftPlan make_plan(int n) {
     return p;
 }
 
+FftPlan make_plan_sched(int n, int sched) {
+    FftPlan p = make_plan(n);
+    if (sched == 1) {
+        int m = n;
+        std::vector<int> r;
+        while (m % 4 == 0) { m /= 4; r.push_back(4); }
+        if (m % 2 == 0) { m /= 2; r.push_back(2); }
+        while (m % 3 == 0) { m /= 3; r.push_back(3); }
+        while (m % 5 == 0) { m /= 5; r.push_back(5); }
+        PW_CHECK((int)r.size() <= kMaxStages, PW_EINVAL, "FFT length %d needs too many stages", n);
+        std::sort(r.begin(), r.end(), [](int a, int b) { return a > b; });
+        p.nstages = (int)r.size();
+        for (int i = 0; i < p.nstages; ++i) p.radix[i] = r[i];
+    } else if (sched == 2) {
+        std::reverse(p.radix, p.radix + p.nstages);
+    }
+    return p;
+}
+
 }  // namespace pw

@@ -77,6 +77,21 @@ struct FftPlan {
     int radix[kMaxStages];
 };
 FftPlan make_plan(int n);   // factor n into radices 8, 4, 2, 3, 5
+// radix schedules the autotuner tries: 0 make_plan, 1 radices 4 (2) 3 5 only,
+// 2 make_plan's radices in ascending order
+FftPlan make_plan_sched(int n, int sched);
+
+// Launch choice of one FFT pass: kind 0 built-in default, 1 the compile-time
+// length kernel, 2 the runtime-plan kernel with nthr threads and plans p0 (and
+// p1 for the xy pass).
+struct FftChoice {
+    int kind = 0;
+    int nthr = 0;
+    FftPlan p0{}, p1{};
+};
+struct FftTune {
+    FftChoice zinv, xy, zfwd;
+};
 
 // ---------------------------------------------------------------------------
 // basis (host)
@@ -133,6 +148,7 @@ struct pw_ctx {
     int device = 0;
     int64_t device_bytes = 0;
     pw::FftPlan plan[3];
+    pw::FftTune tune[2];             // FFT launch choices: [0] complex128, [1] complex64
     int cb = 16;                     // z-columns per workgroup in the z passes
     // device tables
     pw::DevBuf d_kin, d_zmap, d_colpos, d_colstart, d_vz64, d_vz32, d_tw64[3], d_tw32[3];

@@ -10,8 +10,14 @@
 //                      sphere, fused with the kinetic term (T_G - shift) c(G)
 // Only the z-columns that touch the sphere travel through HBM.  Common grid
 // lengths are compiled with their radices built in (CtLen); other lengths use the
-// run-time plan (RtLen).
+// run-time plan (RtLen).  A context can carry per-pass launch choices (kernel
+// kind, radix schedule, threads) picked by the autotuner at the end of this file.
 #include "fft_core.h"
+#include "kernels.h"
+#include <vector>
+#include <tuple>
+#include <mutex>
+#include <map>
 
 namespace pw {
 
@@ -236,8 +242,22 @@ static void zfwd_go(const ZArgs &a, int ncb, int nb, size_t lds, hipStream_t s, 
 
 constexpr int kZcb = 16;   // columns per z-pass workgroup (pw_ctx::cb)
 
-// dispatch a functor on (length policy, threads) for a z-pass length
-template <typename T, typename F> static void with_zlen(int n2, int nthr_rt, F &&f) {
+template <typename T> static FftChoice &choice_of(pw_ctx *ctx, int pass) {
+    FftTune &t = ctx->tune[sizeof(T) == 8 ? 0 : 1];
+    return pass == 0 ? t.zinv : pass == 1 ? t.xy : t.zfwd;
+}
+
+static bool z_has_ct(int n2) {
+    switch (n2) {
+        case 16: case 20: case 32: case 40: case 48: case 64: case 96: case 128: case 192: case 384: case 512:
+            return true;
+        default: return false;
+    }
+}
+
+// dispatch a functor on (length policy, threads) for a z-pass length: the
+// compile-time length unless `runtime`, else the runtime plan with nthr_rt threads
+template <typename T, typename F> static void with_zlen(int n2, int nthr_rt, bool runtime, F &&f) {
 #define PW_ZCASE(L)                                                                   \
     case L: {                                                                         \
         constexpr int t = ct_threads<T>(L, kZcb);                                     \
@@ -245,10 +265,12 @@ template <typename T, typename F> static void with_zlen(int n2, int nthr_rt, F &
         f.template operator()<CtLen<L>, t>();                                         \
         return;                                                                       \
     }
-    switch (n2) {
-        PW_ZCASE(16) PW_ZCASE(20) PW_ZCASE(32) PW_ZCASE(40) PW_ZCASE(48) PW_ZCASE(64) PW_ZCASE(96)
-        PW_ZCASE(128) PW_ZCASE(192) PW_ZCASE(384) PW_ZCASE(512)
-        default: break;
+    if (!runtime) {
+        switch (n2) {
+            PW_ZCASE(16) PW_ZCASE(20) PW_ZCASE(32) PW_ZCASE(40) PW_ZCASE(48) PW_ZCASE(64) PW_ZCASE(96)
+            PW_ZCASE(128) PW_ZCASE(192) PW_ZCASE(384) PW_ZCASE(512)
+            default: break;
+        }
     }
 #undef PW_ZCASE
     switch (nthr_rt) {
@@ -272,14 +294,27 @@ template <typename T> struct ZfwdGo {
     }
 };
 
+// z passes honour the context's launch choice (autotuner) for their pass
+template <typename T> static int z_setup(pw_ctx *ctx, int pass, ZArgs &a, bool &runtime) {
+    const FftChoice &c = choice_of<T>(ctx, pass);
+    runtime = c.kind == 2;
+    if (runtime) {
+        a.plan = c.p0;
+        return c.nthr;
+    }
+    return pick_threads<T>(a.plan, a.cb);
+}
+
 template <typename T>
 void launch_zinv(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *cols, hipStream_t s) {
     ZArgs a = zargs<T>(ctx, nb);
     PW_CHECK(a.cb == kZcb, PW_EINVAL, "column block mismatch");
     const int ncb = (a.ncols + a.cb - 1) / a.cb;
     const size_t lds = sizeof(cplx<T>) * (a.n2 + (size_t)a.cb * (a.n2 + 1));
+    bool runtime;
+    const int nthr = z_setup<T>(ctx, 0, a, runtime);
     ZinvGo<T> go{a, ncb, nb, lds, s, psi, ld, cols};
-    with_zlen<T>(a.n2, pick_threads<T>(a.plan, a.cb), go);
+    with_zlen<T>(a.n2, nthr, runtime, go);
     PW_LAUNCH_CHECK();
 }
 
@@ -290,8 +325,10 @@ void launch_zfwd(pw_ctx *ctx, int nb, const void *cols, const void *psi, int64_t
     PW_CHECK(a.cb == kZcb, PW_EINVAL, "column block mismatch");
     const int ncb = (a.ncols + a.cb - 1) / a.cb;
     const size_t lds = sizeof(cplx<T>) * (a.n2 + (size_t)a.cb * (a.n2 + 1));
+    bool runtime;
+    const int nthr = z_setup<T>(ctx, 2, a, runtime);
     ZfwdGo<T> go{a, ncb, nb, lds, s, cols, psi, ld, kin, shift, scale, out, ldo};
-    with_zlen<T>(a.n2, pick_threads<T>(a.plan, a.cb), go);
+    with_zlen<T>(a.n2, nthr, runtime, go);
     PW_LAUNCH_CHECK();
 }
 
@@ -307,7 +344,8 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
     XYArgs a = xyargs<T>(ctx);
     const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
     PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
-    if (a.n0 == a.n1) {
+    const FftChoice &c = choice_of<T>(ctx, 1);
+    if (c.kind != 2 && a.n0 == a.n1) {
 #define PW_XYCASE(L)                                                                        \
     case L: {                                                                               \
         constexpr int t1 = ct_threads<T>(L, L), t = t1;                                    \
@@ -325,8 +363,14 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
 #undef PW_XYCASE
     }
     int nthr = 0;
-    for (int t : {256, 512, 1024})
-        if (fft_fits<T>(a.plan1, a.n0, t) && fft_fits<T>(a.plan0, a.n1, t)) { nthr = t; break; }
+    if (c.kind == 2) {
+        a.plan0 = c.p0;
+        a.plan1 = c.p1;
+        nthr = c.nthr;
+    } else {
+        for (int t : {256, 512, 1024})
+            if (fft_fits<T>(a.plan1, a.n0, t) && fft_fits<T>(a.plan0, a.n1, t)) { nthr = t; break; }
+    }
     switch (nthr) {
         case 256: xy_go<T, MODE, RtLen, RtLen, 256>(a, nb, lds, s, cols, grid); break;
         case 512: xy_go<T, MODE, RtLen, RtLen, 512>(a, nb, lds, s, cols, grid); break;
@@ -335,6 +379,178 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
     }
     PW_LAUNCH_CHECK();
 }
+
+// ---------------------------------------------------------------------------
+// Autotuner: for each pass (z inverse, xy with V, z forward) time every launch
+// variant that fits this grid -- the compile-time length kernel and the
+// runtime-plan kernel for each radix schedule and thread count -- on nb bands
+// and keep the fastest.  Results are cached per (grid, sphere, dtype, nb).
+// ---------------------------------------------------------------------------
+template <typename T> static bool xy_has_ct(int n) {
+    switch (n) {
+#define PW_XYH(L) \
+    case L: return ct_threads<T>(L, L) > 0;
+        PW_XYH(16) PW_XYH(32) PW_XYH(40) PW_XYH(48) PW_XYH(64) PW_XYH(96) PW_XYH(128)
+#undef PW_XYH
+        default: return false;
+    }
+}
+
+static bool same_plan(const FftPlan &a, const FftPlan &b) {
+    if (a.n != b.n || a.nstages != b.nstages) return false;
+    for (int i = 0; i < a.nstages; ++i)
+        if (a.radix[i] != b.radix[i]) return false;
+    return true;
+}
+
+// the choice a candidate record stands for; false if it does not fit
+template <typename T> static bool choice_from(pw_ctx *ctx, const pw_fft_cand &r, FftChoice &c) {
+    const int n0 = ctx->cell.n[0], n1 = ctx->cell.n[1], n2 = ctx->cell.n[2];
+    c = FftChoice{};
+    c.kind = r.kind;
+    if (r.kind == 0) return true;
+    if (r.kind == 1) return r.pass == 1 ? (n0 == n1 && xy_has_ct<T>(n0)) : z_has_ct(n2);
+    if (r.kind != 2 || r.sched < 0 || r.sched > 2) return false;
+    c.nthr = r.nthr;
+    if (c.nthr != 256 && c.nthr != 512 && c.nthr != 1024) return false;
+    if (r.pass == 1) {
+        c.p0 = make_plan_sched(n0, r.sched);
+        c.p1 = make_plan_sched(n1, r.sched);
+        return fft_fits<T>(c.p1, n0, c.nthr) && fft_fits<T>(c.p0, n1, c.nthr);
+    }
+    c.p0 = make_plan_sched(n2, r.sched);
+    return fft_fits<T>(c.p0, kZcb, c.nthr);
+}
+
+template <typename T> static std::vector<pw_fft_cand> candidates(pw_ctx *ctx, int pass) {
+    std::vector<pw_fft_cand> out;
+    pw_fft_cand r{};
+    r.pass = pass;
+    FftChoice c;
+    r.kind = 1;
+    if (choice_from<T>(ctx, r, c)) out.push_back(r);
+    std::vector<FftChoice> seen;
+    for (int sched = 0; sched < 3; ++sched) {
+        for (int t : {256, 512, 1024}) {
+            r = pw_fft_cand{};
+            r.pass = pass;
+            r.kind = 2;
+            r.sched = sched;
+            r.nthr = t;
+            if (!choice_from<T>(ctx, r, c)) continue;
+            bool dup = false;
+            for (const FftChoice &o : seen)
+                if (o.nthr == t && same_plan(o.p0, c.p0) && (pass != 1 || same_plan(o.p1, c.p1))) dup = true;
+            if (dup) continue;
+            seen.push_back(c);
+            r.nradix = c.p0.nstages;
+            for (int i = 0; i < c.p0.nstages; ++i) r.radix[i] = c.p0.radix[i];
+            out.push_back(r);
+        }
+    }
+    return out;
+}
+
+template <typename T>
+static void run_pass(pw_ctx *ctx, int pass, int nb, void *in, void *out, hipStream_t s) {
+    const int64_t ld = ctx->basis.npw;
+    if (pass == 0) launch_zinv<T>(ctx, nb, in, ld, ctx->d_cols.p, s);
+    else if (pass == 1) launch_xy<T, 0>(ctx, nb, ctx->d_cols.p, nullptr, s);
+    else launch_zfwd<T>(ctx, nb, ctx->d_cols.p, in, ld, ctx->d_kin.as<double>(), 0.0, 1.0, out, ld, s);
+}
+
+namespace {
+struct TuneKey {
+    int n[3], ncols, npw, dbl, nb;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(n[0], n[1], n[2], ncols, npw, dbl, nb) <
+               std::tie(o.n[0], o.n[1], o.n[2], o.ncols, o.npw, o.dbl, o.nb);
+    }
+};
+struct TuneVal {
+    FftTune tune;
+    std::vector<pw_fft_cand> recs;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+}  // namespace
+
+template <typename T>
+void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs, hipStream_t s) {
+    PW_CHECK(nb >= 1 && nb <= ctx->max_bands && reps >= 1, PW_EINVAL, "bad autotune sizes");
+    FftTune &tune = ctx->tune[sizeof(T) == 8 ? 0 : 1];
+    const TuneKey key{{ctx->cell.n[0], ctx->cell.n[1], ctx->cell.n[2]}, ctx->basis.ncols, ctx->basis.npw,
+                      sizeof(T) == 8, nb};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            tune = it->second.tune;
+            recs = it->second.recs;
+            return;
+        }
+    }
+    const size_t bytes = (size_t)nb * ctx->basis.npw * sizeof(cplx<T>);
+    DevBuf in, out;
+    in.alloc(bytes);
+    out.alloc(bytes);
+    fill_zero(in.p, bytes, s);
+    fill_zero(out.p, bytes, s);
+    tune = FftTune{};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PW_HIP(hipEventCreate(&e0));
+    struct Ev {
+        hipEvent_t &a, &b;
+        ~Ev() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    PW_HIP(hipEventCreate(&e1));
+    recs.clear();
+    run_pass<T>(ctx, 0, nb, in.p, out.p, s);              // column grid for the xy timings
+    for (int pass = 0; pass < 3; ++pass) {
+        std::vector<pw_fft_cand> cs = candidates<T>(ctx, pass);
+        const size_t first = recs.size();
+        int best = -1;
+        for (size_t k = 0; k < cs.size(); ++k) {
+            FftChoice c;
+            choice_from<T>(ctx, cs[k], c);
+            choice_of<T>(ctx, pass) = c;
+            run_pass<T>(ctx, pass, nb, in.p, out.p, s);   // warm-up (and LDS attribute)
+            PW_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) run_pass<T>(ctx, pass, nb, in.p, out.p, s);
+            PW_HIP(hipEventRecord(e1, s));
+            PW_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            cs[k].ms = ms / reps;
+            if (best < 0 || cs[k].ms < cs[best].ms) best = (int)k;
+            recs.push_back(cs[k]);
+        }
+        PW_CHECK(best >= 0, PW_EUNSUPPORTED, "no FFT launch variant fits pass %d", pass);
+        recs[first + best].chosen = 1;
+        FftChoice c;
+        choice_from<T>(ctx, cs[best], c);
+        choice_of<T>(ctx, pass) = c;
+        if (pass == 0) run_pass<T>(ctx, 0, nb, in.p, out.p, s);
+    }
+    PW_HIP(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = TuneVal{tune, recs};
+}
+
+template <typename T> void fft_choose(pw_ctx *ctx, const pw_fft_cand &r) {
+    PW_CHECK(r.pass >= 0 && r.pass <= 2, PW_EINVAL, "FFT pass %d unknown", r.pass);
+    FftChoice c;
+    PW_CHECK(choice_from<T>(ctx, r, c), PW_EUNSUPPORTED, "FFT launch variant does not fit this grid");
+    choice_of<T>(ctx, r.pass) = c;
+}
+
+template void autotune_fft<double>(pw_ctx *, int, int, std::vector<pw_fft_cand> &, hipStream_t);
+template void autotune_fft<float>(pw_ctx *, int, int, std::vector<pw_fft_cand> &, hipStream_t);
+template void fft_choose<double>(pw_ctx *, const pw_fft_cand &);
+template void fft_choose<float>(pw_ctx *, const pw_fft_cand &);
 
 // explicit instantiations used by api.cpp
 template void launch_zinv<double>(pw_ctx *, int, const void *, int64_t, void *, hipStream_t);

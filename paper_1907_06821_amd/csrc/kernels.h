@@ -66,6 +66,9 @@ struct BandRed {              // scratch for two-stage band reductions
 int band_splits(int npw);
 
 void fill_zero(void *p, size_t bytes, hipStream_t);
+template <typename T>
+void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs, hipStream_t s);
+template <typename T> void fft_choose(pw_ctx *ctx, const pw_fft_cand &r);
 void copy_block(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t);
 void red_mu_tband(int nb, int npw, const void *Y, const void *X, int64_t ld, const double *kin, double *mu,
                   double *tband, BandRed, hipStream_t);

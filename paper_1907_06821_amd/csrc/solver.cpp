@@ -17,6 +17,7 @@
 // Delta_i of a Rayleigh-Ritz in H taken on copies; the host syncs only here.
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <cmath>
 #include <utility>
 
@@ -73,36 +74,77 @@ static Solver *solver_get(pw_ctx *ctx, int nb, bool mixed) {
     return s;
 }
 
-pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double *eig, double *resid,
-                    const pw_cg_opts &o, pw_cg_stats *stats, hipStream_t st) {
-    const auto t_start = std::chrono::steady_clock::now();
-    const int npw = ctx->basis.npw;
-    const bool mixed = o.precision == 1;
-    Solver *s = solver_get(ctx, nb, mixed);
-    const int64_t L = npw;   // internal leading dimension
-    void *X = s->X.p, *Y = s->Y.p, *AX = s->AX.p, *P = s->P.p, *YP = s->YP.p, *AP = s->AP.p;
-    void *G = s->G.p, *Z = s->Z.p, *T1 = s->T1.p, *T2 = s->T2.p, *T3 = s->T3.p;
-    const size_t nn = (size_t)nb * nb;
-    double2 *Sm = (double2 *)s->small.p, *Wm = Sm + nn, *Tm = Wm + nn, *Rm = Tm + nn, *Aw = Rm + nn, *Vw = Aw + nn;
-    double *v = (double *)s->vec.p;
-    double *mu = v, *tband = v + nb, *gz = v + 2 * nb, *gzo = v + 3 * nb, *gz_old = v + 4 * nb;
-    double *line4 = v + 5 * nb, *coef = v + 9 * nb, *lam = v + 13 * nb, *res = v + 14 * nb;
-    int *d_status = (int *)s->status.p;
-    BandRed br{(double *)s->red.p, s->nsplit};
-    int64_t n_hpsi = 0;
-    bool use_mixed = mixed;
+// One folded-CG solve as a resumable object: setup(), then segments of
+// iterations each ending in the device part of a check (check_device), the host
+// decisions (check_host), and finish().  Segments are pure device work, so they
+// can be recorded into a graph; with swap_free set, rotations copy back into the
+// blocks instead of exchanging block pointers, so a recorded segment leaves the
+// pointers as it found them and can be replayed.
+struct FcgRun {
+    pw_ctx *ctx;
+    double E;
+    int nb;
+    void *psi;
+    int64_t ld;
+    double *eig, *resid;
+    pw_cg_opts o;
+    pw_cg_stats *stats;
+    hipStream_t st;
+    bool swap_free = false;
 
+    std::chrono::steady_clock::time_point t_start;
+    int npw = 0, nshell = 0, check = 1, nwant = 0;
+    bool mixed = false, use_mixed = false;
+    Solver *s = nullptr;
+    int64_t L = 0;
+    void *X, *Y, *AX, *P, *YP, *AP, *G, *Z, *T1, *T2, *T3;
+    double2 *Sm, *Wm, *Tm, *Rm, *Aw;
+    double *mu, *tband, *gz, *gzo, *gz_old, *line4, *coef, *lam, *res;
+    int *d_status;
+    BandRed br;
     PrecArgs pa{};
-    pa.kind = o.precond;
-    pa.ftab = s->ftab.as<float>();
-    pa.kin = ctx->d_kin.as<double>();
-    pa.tband = tband;
-    pa.e_ref = E;
-    pa.de2 = o.delta_e * o.delta_e;
-    pa.shell = ctx->d_shell.as<int32_t>();
-    pa.nb = nb;
+    int64_t n_hpsi = 0;
+    std::vector<double> h_lam, h_res;
+    int h_status[8] = {0};
+    int it = 0, stall = 0, nhist = 0, nsnap = 0;
+    bool converged = false;
+    double best = INFINITY;
+    pw_status result = PW_OK;
 
-    auto fold = [&](void *in, void *y, void *ay, bool low) {
+    FcgRun(pw_ctx *c, double e, int n, void *p, int64_t l, double *ev, double *rv, const pw_cg_opts &opt,
+           pw_cg_stats *sta, hipStream_t stream)
+        : ctx(c), E(e), nb(n), psi(p), ld(l), eig(ev), resid(rv), o(opt), stats(sta), st(stream) {
+        t_start = std::chrono::steady_clock::now();
+        npw = ctx->basis.npw;
+        mixed = use_mixed = o.precision == 1;
+        s = solver_get(ctx, nb, mixed);
+        L = npw;   // internal leading dimension
+        X = s->X.p; Y = s->Y.p; AX = s->AX.p; P = s->P.p; YP = s->YP.p; AP = s->AP.p;
+        G = s->G.p; Z = s->Z.p; T1 = s->T1.p; T2 = s->T2.p; T3 = s->T3.p;
+        const size_t nn = (size_t)nb * nb;
+        Sm = (double2 *)s->small.p; Wm = Sm + nn; Tm = Wm + nn; Rm = Tm + nn; Aw = Rm + nn;
+        double *v = (double *)s->vec.p;
+        mu = v; tband = v + nb; gz = v + 2 * nb; gzo = v + 3 * nb; gz_old = v + 4 * nb;
+        line4 = v + 5 * nb; coef = v + 9 * nb; lam = v + 13 * nb; res = v + 14 * nb;
+        d_status = (int *)s->status.p;
+        br = BandRed{(double *)s->red.p, s->nsplit};
+        pa.kind = o.precond;
+        pa.ftab = s->ftab.as<float>();
+        pa.kin = ctx->d_kin.as<double>();
+        pa.tband = tband;
+        pa.e_ref = E;
+        pa.de2 = o.delta_e * o.delta_e;
+        pa.shell = ctx->d_shell.as<int32_t>();
+        pa.nb = nb;
+        h_lam.assign(nb, 0.0);
+        h_res.assign(nb, 0.0);
+        // largest residual among the nconv Ritz values (theta - E) nearest zero
+        nwant = (o.nconv > 0 && o.nconv < nb) ? o.nconv : nb;
+        check = std::max(1, o.check_every);
+        nshell = (int)ctx->basis.shell_t.size();
+    }
+
+    void fold(void *in, void *y, void *ay, bool low) {
         if (low) {
             c128_to_c64(nb, npw, in, L, s->P32.p, L, st);
             hpsi_any(ctx, PW_C64, nb, s->P32.p, L, s->Q32.p, L, E, st);
@@ -114,28 +156,33 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
             hpsi_any(ctx, PW_C128, nb, y, L, ay, L, E, st);
         }
         n_hpsi += 2 * nb;
-    };
-    auto rotate = [&](const double2 *M, void *&blk, void *&tmp) {
+    }
+    // the rotated block takes tmp's storage, or (swap_free) is copied back
+    void settle(void *&blk, void *&tmp) {
+        if (swap_free) copy_block(nb, npw, tmp, L, blk, L, st);
+        else std::swap(blk, tmp);
+    }
+    void rotate(const double2 *M, void *&blk, void *&tmp) {
         zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st);
-        std::swap(blk, tmp);
-    };
+        settle(blk, tmp);
+    }
     // (X, Y, AX) <- M . (X, Y, AX) in one batched launch
-    auto rotate3 = [&](const double2 *M) {
+    void rotate3(const double2 *M) {
         const void *in[3] = {X, Y, AX};
         void *out[3] = {T1, T2, T3};
         zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st);
-        std::swap(X, T1);
-        std::swap(Y, T2);
-        std::swap(AX, T3);
-    };
-    auto orth = [&]() {
+        settle(X, T1);
+        settle(Y, T2);
+        settle(AX, T3);
+    }
+    void orth() {
         zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
         chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
         rotate3(Tm);
-    };
+    }
     // Rayleigh-Ritz in A = (H - E)^2 on the iterate (Y, AX exact): Ritz values of
     // Y^H Y ascending; the search directions and gradients turn with the bands.
-    auto a_rr = [&](bool rotate_dirs) {
+    void a_rr(bool rotate_dirs) {
         zgemm_nt(nb, nb, npw, true, Y, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
         dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
         rotate3(Rm);
@@ -143,62 +190,54 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
             const void *in[2] = {P, G};
             void *out[2] = {T1, T2};
             zgemm_nn_batch(2, nb, npw, nb, Rm, nb, in, L, 1.0, 0.0, out, L, st);
-            std::swap(P, T1);
-            std::swap(G, T2);
+            settle(P, T1);
+            settle(G, T2);
         }
-    };
+    }
     // Rayleigh-Ritz in H on copies of the block: lam = theta - E ascending and the
     // residuals Delta_i of the H-Ritz vectors (the iterate itself is left alone)
-    auto h_resid = [&]() {
+    void h_resid() {
         zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
         dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
         zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st);
         zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st);
         red_resid(nb, npw, T2, T1, L, lam, res, br, st);
-    };
-
-    fill_zero(s->status.p, 256, st);
-    copy_block(nb, npw, psi, ld, X, L, st);
-    fill_zero(P, (size_t)nb * npw * 16, st);
-    fill_zero(G, (size_t)nb * npw * 16, st);
-    fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
-    // initial orthonormalisation (Y, AX are garbage here but get overwritten)
-    zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
-    chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
-    rotate(Tm, X, T1);
-    fold(X, Y, AX, false);
-    a_rr(false);
-    fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
-
-    std::vector<double> h_lam(nb), h_res(nb);
-    // largest residual among the nconv Ritz values (theta - E) nearest zero
-    const int nwant = (o.nconv > 0 && o.nconv < nb) ? o.nconv : nb;
-    auto wanted_max = [&](const std::vector<double> &lamv, const std::vector<double> &resv) {
-        std::vector<int> idx(nb);
-        for (int b = 0; b < nb; ++b) idx[b] = b;
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return std::fabs(lamv[a]) < std::fabs(lamv[c]); });
-        double m = 0.0;
-        for (int r = 0; r < nwant; ++r) m = std::max(m, resv[idx[r]]);
-        return m;
-    };
-    int h_status[8];
-    int it = 0;
-    bool converged = false;
-    double best = INFINITY;
-    int stall = 0;
-    int nhist = 0;
-    const int check = std::max(1, o.check_every);
-    pw_status result = PW_OK;
-    const int nshell = (int)ctx->basis.shell_t.size();
+    }
     // band kinetic energies, then (learned preconditioner) the per-shell scaling table
-    auto band_stats = [&]() {
+    void band_stats() {
         red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
         if (pa.kind == 2)
             mlp_infer(nshell, nb, ctx->d_shell_t.as<double>(), tband, E, ctx->cell.ecut, ctx->d_mlp.as<float>(),
                       s->ftab.as<float>(), st);
-    };
-    int nsnap = 0;
-    for (it = 1; it <= o.maxit; ++it) {
+    }
+    double wanted_max() const {
+        std::vector<int> idx(nb);
+        for (int b = 0; b < nb; ++b) idx[b] = b;
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int a, int c) { return std::fabs(h_lam[a]) < std::fabs(h_lam[c]); });
+        double m = 0.0;
+        for (int r = 0; r < nwant; ++r) m = std::max(m, h_res[idx[r]]);
+        return m;
+    }
+
+    void setup() {
+        fill_zero(s->status.p, 256, st);
+        copy_block(nb, npw, psi, ld, X, L, st);
+        fill_zero(P, (size_t)nb * npw * 16, st);
+        fill_zero(G, (size_t)nb * npw * 16, st);
+        fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
+        // initial orthonormalisation (Y, AX are garbage here but get overwritten)
+        zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
+        rotate(Tm, X, T1);
+        fold(X, Y, AX, false);
+        a_rr(false);
+        fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
+    }
+    // iterations left before the next check
+    int segment_length() const { return std::min(check - it % check, o.maxit - it); }
+    void iteration() {
+        ++it;
         band_stats();
         red_grad(nb, npw, X, AX, G, Z, L, mu, pa, gz, gzo, br, st);
         pupdate(nb, npw, Z, P, L, gz, gzo, gz_old, st);
@@ -214,91 +253,254 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
             copy_block(nb, npw, X, L, (char *)o.snap_buf + (size_t)nsnap * nb * npw * 16, npw, st);
             ++nsnap;
         }
-        if (it % check == 0 || it == o.maxit) {
-            fold(X, Y, AX, false);
-            a_rr(true);
-            h_resid();
-            // PR denominator for the rotated gradients
-            band_stats();
-            red_gzold(nb, npw, G, L, pa, gz_old, br, st);
-            PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
-            PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
-            PW_HIP(hipMemcpyAsync(h_status, d_status, sizeof h_status, hipMemcpyDeviceToHost, st));
-            PW_HIP(hipStreamSynchronize(st));
-            if (h_status[0]) {
-                set_error("Gram matrix lost positive definiteness (pivot %d) before iteration %d", h_status[0] - 1, it);
-                result = PW_ENOTPD;
-                break;
-            }
-            bool finite = true;
-            for (int b = 0; b < nb; ++b)
-                if (!std::isfinite(h_res[b]) || !std::isfinite(h_lam[b])) finite = false;
-            const double mx = finite ? wanted_max(h_lam, h_res) : INFINITY;
-            if (!finite) {
-                set_error("non-finite residual at iteration %d", it);
-                result = PW_ENAN;
-                break;
-            }
-            if (stats && stats->hist && nhist < stats->n_hist) {
-                stats->hist[2 * nhist] = it;
-                stats->hist[2 * nhist + 1] = mx;
-                ++nhist;
-            }
-            if (o.verbose) fprintf(stderr, "[pw] it %6d  max resid %.3e%s\n", it, mx, use_mixed ? "  (mixed)" : "");
-            if (mx <= o.tol) {
-                converged = true;
-                break;
-            }
-            // precision ladder: leave the low-precision operator below mixed_switch, or
-            // once the best residual has not improved by 2x over stall_checks checks
-            if (use_mixed) {
-                if (mx < 0.5 * best) { best = mx; stall = 0; }
-                else if (o.stall_checks > 0 && ++stall >= o.stall_checks) use_mixed = false;
-                if (mx < o.mixed_switch) use_mixed = false;
-                if (!use_mixed && o.verbose) fprintf(stderr, "[pw] it %6d  switching to FP64 H psi\n", it);
-            }
-        }
     }
-    if (it > o.maxit) it = o.maxit;
-    // final Rayleigh-Ritz in H, ascending energies, FP64 residuals
-    if (result == PW_OK || result == PW_ENOCONV) {
-        hpsi_any(ctx, PW_C128, nb, X, L, Y, L, E, st);
-        n_hpsi += nb;
-        zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
-        dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
-        rotate(Rm, X, T1);
-        rotate(Rm, Y, T2);
-        red_resid(nb, npw, Y, X, L, lam, res, br, st);
-        copy_block(nb, npw, X, L, psi, ld, st);
+    void check_device() {
+        fold(X, Y, AX, false);
+        a_rr(true);
+        h_resid();
+        // PR denominator for the rotated gradients
+        band_stats();
+        red_gzold(nb, npw, G, L, pa, gz_old, br, st);
+    }
+    // the host side of a check; false once the solve stops (converged or failed)
+    bool check_host() {
         PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
         PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
+        PW_HIP(hipMemcpyAsync(h_status, d_status, sizeof h_status, hipMemcpyDeviceToHost, st));
         PW_HIP(hipStreamSynchronize(st));
-        for (int b = 0; b < nb; ++b) {
-            if (eig) eig[b] = h_lam[b] + E;
-            if (resid) resid[b] = h_res[b];
+        if (h_status[0]) {
+            set_error("Gram matrix lost positive definiteness (pivot %d) before iteration %d", h_status[0] - 1, it);
+            result = PW_ENOTPD;
+            return false;
         }
-        const double mx = wanted_max(h_lam, h_res);
-        if (!converged) {
-            converged = mx <= o.tol;
-            if (!converged) {
-                set_error("folded CG did not reach tol %.3e in %d iterations (max residual %.3e)", o.tol, o.maxit, mx);
-                result = PW_ENOCONV;
+        bool finite = true;
+        for (int b = 0; b < nb; ++b)
+            if (!std::isfinite(h_res[b]) || !std::isfinite(h_lam[b])) finite = false;
+        if (!finite) {
+            set_error("non-finite residual at iteration %d", it);
+            result = PW_ENAN;
+            return false;
+        }
+        const double mx = wanted_max();
+        if (stats && stats->hist && nhist < stats->n_hist) {
+            stats->hist[2 * nhist] = it;
+            stats->hist[2 * nhist + 1] = mx;
+            ++nhist;
+        }
+        if (o.verbose) fprintf(stderr, "[pw] it %6d  max resid %.3e%s\n", it, mx, use_mixed ? "  (mixed)" : "");
+        if (mx <= o.tol) {
+            converged = true;
+            return false;
+        }
+        // precision ladder: leave the low-precision operator below mixed_switch, or
+        // once the best residual has not improved by 2x over stall_checks checks
+        if (use_mixed) {
+            if (mx < 0.5 * best) {
+                best = mx;
+                stall = 0;
+            } else if (o.stall_checks > 0 && ++stall >= o.stall_checks) {
+                use_mixed = false;
             }
+            if (mx < o.mixed_switch) use_mixed = false;
+            if (!use_mixed && o.verbose) fprintf(stderr, "[pw] it %6d  switching to FP64 H psi\n", it);
         }
-        if (stats) stats->max_resid = mx;
+        return it < o.maxit;
     }
-    // the solver's scratch blocks may have been swapped: keep them in the struct
-    s->X.p = X; s->Y.p = Y; s->AX.p = AX; s->P.p = P; s->YP.p = YP; s->AP.p = AP;
-    s->G.p = G; s->Z.p = Z; s->T1.p = T1; s->T2.p = T2; s->T3.p = T3;
-    if (stats) {
-        stats->iters = it;
-        stats->converged = converged ? 1 : 0;
-        stats->n_hpsi = n_hpsi;
-        stats->n_hist = nhist;
-        stats->n_snap = nsnap;
-        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    // final Rayleigh-Ritz in H, ascending energies, FP64 residuals
+    pw_status finish() {
+        if (result == PW_OK || result == PW_ENOCONV) {
+            hpsi_any(ctx, PW_C128, nb, X, L, Y, L, E, st);
+            n_hpsi += nb;
+            zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+            dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
+            rotate(Rm, X, T1);
+            rotate(Rm, Y, T2);
+            red_resid(nb, npw, Y, X, L, lam, res, br, st);
+            copy_block(nb, npw, X, L, psi, ld, st);
+            PW_HIP(hipMemcpyAsync(h_lam.data(), lam, nb * 8, hipMemcpyDeviceToHost, st));
+            PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
+            PW_HIP(hipStreamSynchronize(st));
+            for (int b = 0; b < nb; ++b) {
+                if (eig) eig[b] = h_lam[b] + E;
+                if (resid) resid[b] = h_res[b];
+            }
+            const double mx = wanted_max();
+            if (!converged) {
+                converged = mx <= o.tol;
+                if (!converged) {
+                    set_error("folded CG did not reach tol %.3e in %d iterations (max residual %.3e)", o.tol, o.maxit,
+                              mx);
+                    result = PW_ENOCONV;
+                }
+            }
+            if (stats) stats->max_resid = mx;
+        }
+        // the solver's scratch blocks may have been swapped: keep them in the struct
+        s->X.p = X; s->Y.p = Y; s->AX.p = AX; s->P.p = P; s->YP.p = YP; s->AP.p = AP;
+        s->G.p = G; s->Z.p = Z; s->T1.p = T1; s->T2.p = T2; s->T3.p = T3;
+        if (stats) {
+            stats->iters = it;
+            stats->converged = converged ? 1 : 0;
+            stats->n_hpsi = n_hpsi;
+            stats->n_hist = nhist;
+            stats->n_snap = nsnap;
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        }
+        return result;
     }
-    return result;
+};
+
+pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double *eig, double *resid,
+                    const pw_cg_opts &o, pw_cg_stats *stats, hipStream_t st) {
+    FcgRun r(ctx, E, nb, psi, ld, eig, resid, o, stats, st);
+    r.setup();
+    for (;;) {
+        const int n = r.segment_length();
+        for (int k = 0; k < n; ++k) r.iteration();
+        r.check_device();
+        if (!r.check_host()) break;
+    }
+    return r.finish();
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves: independent problems (one context each) advance together.
+// Each problem's segment (check_every iterations and the device side of the
+// check) is recorded once per (length, H psi precision) into a graph; the
+// segments of all running problems are the independent child graphs of one
+// graph, launched once per check round on the caller's stream.  Between rounds
+// the host reads every problem's residuals; the graph is rebuilt only when a
+// problem finishes or changes precision.  Per problem, the kernels and their
+// order are those of the unbatched solve.
+// ---------------------------------------------------------------------------
+namespace {
+struct SegGraph {
+    int len = 0;
+    bool low = false;
+    hipGraph_t g = nullptr;
+    int64_t hpsi = 0;
+};
+struct BatchItem {
+    std::unique_ptr<FcgRun> run;
+    std::vector<SegGraph> segs;
+    bool active = true;
+    hipGraph_t cur = nullptr;
+    int len = 0;
+    int64_t hpsi = 0;
+};
+struct BatchRes {
+    std::vector<BatchItem> items;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchRes() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        for (auto &b : items)
+            for (auto &g : b.segs)
+                if (g.g) (void)hipGraphDestroy(g.g);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+SegGraph record_segment(FcgRun &r, int len, hipStream_t cap) {
+    SegGraph sg;
+    sg.len = len;
+    sg.low = r.use_mixed;
+    const hipStream_t keep = r.st;
+    const int it0 = r.it;
+    const int64_t h0 = r.n_hpsi;
+    r.st = cap;
+    PW_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int k = 0; k < len; ++k) r.iteration();
+        r.check_device();
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        r.st = keep;
+        throw;
+    }
+    r.st = keep;
+    PW_HIP(hipStreamEndCapture(cap, &sg.g));
+    sg.hpsi = r.n_hpsi - h0;
+    r.it = it0;          // recording does not advance the solve
+    r.n_hpsi = h0;
+    return sg;
+}
+}  // namespace
+
+pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int nb, void *const *psi,
+                      const int64_t *ld, double *const *eig, double *const *resid, const pw_cg_opts &o,
+                      pw_cg_stats *stats, int32_t *status, hipStream_t st) {
+    BatchRes R;
+    R.items.resize(nprob);
+    PW_HIP(hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking));
+    for (int p = 0; p < nprob; ++p) {
+        BatchItem &b = R.items[p];
+        b.run.reset(new FcgRun(ctxs[p], e_ref[p], nb, psi[p], ld[p], eig ? eig[p] : nullptr,
+                               resid ? resid[p] : nullptr, o, stats ? &stats[p] : nullptr, st));
+        b.run->swap_free = true;
+        b.run->setup();
+    }
+    for (;;) {
+        bool any = false, changed = false;
+        for (BatchItem &b : R.items) {
+            hipGraph_t want = nullptr;
+            if (b.active) {
+                FcgRun &r = *b.run;
+                const int len = r.segment_length();
+                SegGraph *sg = nullptr;
+                for (SegGraph &c : b.segs)
+                    if (c.len == len && c.low == r.use_mixed) sg = &c;
+                if (!sg) {
+                    b.segs.push_back(record_segment(r, len, R.cap));
+                    sg = &b.segs.back();
+                }
+                want = sg->g;
+                b.len = len;
+                b.hpsi = sg->hpsi;
+                any = true;
+            }
+            if (want != b.cur) changed = true;
+            b.cur = want;
+        }
+        if (!any) break;
+        if (changed || !R.exec) {
+            if (R.exec) {
+                PW_HIP(hipGraphExecDestroy(R.exec));
+                R.exec = nullptr;
+            }
+            hipGraph_t parent = nullptr;
+            PW_HIP(hipGraphCreate(&parent, 0));
+            try {
+                for (BatchItem &b : R.items) {
+                    if (!b.cur) continue;
+                    hipGraphNode_t node;
+                    PW_HIP(hipGraphAddChildGraphNode(&node, parent, nullptr, 0, b.cur));
+                }
+                PW_HIP(hipGraphInstantiate(&R.exec, parent, nullptr, nullptr, 0));
+            } catch (...) {
+                (void)hipGraphDestroy(parent);
+                throw;
+            }
+            PW_HIP(hipGraphDestroy(parent));
+        }
+        PW_HIP(hipGraphLaunch(R.exec, st));
+        for (BatchItem &b : R.items) {
+            if (!b.active) continue;
+            b.run->it += b.len;
+            b.run->n_hpsi += b.hpsi;
+        }
+        for (BatchItem &b : R.items)
+            if (b.active && !b.run->check_host()) b.active = false;
+    }
+    pw_status worst = PW_OK;
+    for (int p = 0; p < nprob; ++p) {
+        const pw_status r = R.items[p].run->finish();
+        if (status) status[p] = r;
+        if (r != PW_OK && (worst == PW_OK || worst == PW_ENOCONV)) worst = r;
+    }
+    return worst;
 }
 
 // Training tables of one snapshot (see pw_mlp_harvest in pw.h), using the solver's
@@ -394,6 +596,40 @@ pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, i
         return f.st;
     } catch (...) {
         pw::set_error("unexpected exception in pw_folded_cg_solve");
+        return PW_EINVAL;
+    }
+}
+
+pw_status pw_batch_solve(int32_t nprob, pw_ctx *const *ctx, const double *e_ref, int32_t nb, void *const *psi,
+                         const int64_t *ld, double *const *eig, double *const *resid, const pw_cg_opts *opts,
+                         pw_cg_stats *stats, int32_t *status, void *stream) {
+    try {
+        PW_CHECK(nprob >= 1 && ctx && e_ref && psi && ld, PW_EINVAL, "null argument or nprob < 1");
+        pw_cg_opts o;
+        pw_cg_opts_default(&o);
+        if (opts) o = *opts;
+        PW_CHECK(o.tol > 0 && o.maxit >= 1 && o.check_every >= 1, PW_EINVAL, "bad solver options");
+        PW_CHECK(o.precond >= 0 && o.precond <= 2, PW_EINVAL, "preconditioner %d unknown", o.precond);
+        PW_CHECK(o.snap_every <= 0, PW_EINVAL, "snapshots are not taken in batched solves");
+        PW_CHECK(o.precision == 0 || o.precision == 1, PW_EINVAL, "precision must be 0 or 1");
+        for (int p = 0; p < nprob; ++p) {
+            pw_ctx *c = ctx[p];
+            PW_CHECK(c && psi[p], PW_EINVAL, "problem %d: null context or block", p);
+            for (int q = 0; q < p; ++q) PW_CHECK(ctx[q] != c, PW_EINVAL, "problems %d and %d share a context", q, p);
+            PW_CHECK(c->flags & PW_PREP_C128, PW_EUNSUPPORTED, "problem %d: the solver needs a complex128 context", p);
+            PW_CHECK(nb >= 1 && nb <= c->max_bands && nb <= 1024 && nb <= c->basis.npw, PW_EINVAL,
+                     "problem %d: bad nb %d", p, nb);
+            PW_CHECK(ld[p] >= c->basis.npw, PW_EINVAL, "problem %d: ld < npw", p);
+            PW_CHECK(std::isfinite(e_ref[p]), PW_ENAN, "problem %d: non-finite e_ref", p);
+            PW_CHECK(o.precond != 2 || c->d_mlp.p, PW_EUNSUPPORTED, "problem %d: precond 2 needs pw_mlp_set", p);
+            PW_CHECK(o.precision == 0 || (c->flags & PW_PREP_C64), PW_EUNSUPPORTED,
+                     "problem %d: mixed precision needs PW_PREP_C64", p);
+        }
+        return pw::batch_solve(nprob, ctx, e_ref, nb, psi, ld, eig, resid, o, stats, status, (hipStream_t)stream);
+    } catch (const pw::Fail &f) {
+        return f.st;
+    } catch (...) {
+        pw::set_error("unexpected exception in pw_batch_solve");
         return PW_EINVAL;
     }
 }

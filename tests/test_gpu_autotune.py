@@ -1,0 +1,46 @@
+"""The FFT autotuner: every launch variant it may pick (compile-time length
+kernels, runtime plans over radix schedules and thread counts) computes the same
+H psi as the oracle, and it installs exactly one winner per pass."""
+import numpy as np
+import pytest
+
+from paper_1907_06821_amd import synth
+from tests._helpers import gpu_context, oracle_for, random_block, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("which", ["cube", "skew"])
+def test_every_fft_candidate_matches_oracle(torch_cuda, which):
+    import torch
+    import paper_1907_06821_amd as pw
+    if which == "cube":
+        prob = synth.batched_problems(4, seed=3)[2]          # one of the uneven cubes
+    else:
+        prob = synth.small_nonlocal_problem()                # 12 x 15 x 20 grid: xy runtime plans only
+    op = oracle_for(prob)
+    nb = 4
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    c = random_block(11, nb, op.npw)
+    ref = op.apply(c, shift=prob.e_ref)
+    # complex64 H psi takes its projector GEMMs in BF16 (about 1e-3 of the
+    # nonlocal term): its FFT variants are compared with each other at FP32
+    # rounding, and the tuned one with the oracle at the BF16 level
+    for dtype, tol_ref, tol_var in ((pw.PW_C128, 1e-12, 1e-12), (pw.PW_C64, 2e-3, 3e-6)):
+        recs = pw.autotune(ctx, nb, dtype=dtype, reps=2)
+        for p in range(3):
+            mine = [r for r in recs if r["pass_"] == p]
+            assert len(mine) >= 2
+            assert sum(r["chosen"] for r in mine) == 1
+            assert all(r["ms"] > 0 for r in mine)
+        tdt = "complex128" if dtype == pw.PW_C128 else "complex64"
+        base = pw.hpsi(ctx, to_dev(c, tdt), shift=prob.e_ref).cpu().numpy()
+        assert rel_err(base, ref) < tol_ref                  # the tuned choice
+        for r in recs:
+            pw.fft_choose(ctx, r, dtype=dtype)
+            got = pw.hpsi(ctx, to_dev(c, tdt), shift=prob.e_ref).cpu().numpy()
+            err_ = rel_err(got, ref if dtype == pw.PW_C128 else base)
+            assert err_ < tol_var, (r, err_)
+            pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0}, dtype=dtype)
+        with pytest.raises(pw.PwError):
+            pw.fft_choose(ctx, {"pass_": 1, "kind": 2, "nthr": 100, "sched": 0}, dtype=dtype)
