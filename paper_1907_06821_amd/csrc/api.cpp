@@ -103,11 +103,11 @@ static void hpsi_c64(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out
     if (ctx->nproj) {
         {
             ProfScope p(ctx, 3, st);
-            proj_bf16(ctx->nproj, nb, npw, ctx->d_beta_bf16.p, psi, ld, ctx->d_dproj32.as<float>(), ctx->d_proj.p,
-                      ctx->d_partial.p, st);
+            proj_bf16(ctx->nproj, nb, npw, ctx->max_bands, ctx->d_beta_bf16.p, ctx->d_dproj32.as<float>(), psi, ld,
+                      ctx->d_bf16_ws.p, ctx->d_partial.p, st);
         }
         ProfScope p(ctx, 4, st);
-        backproj_bf16(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->d_beta_bf16.p, out, ldo, st);
+        backproj_bf16(ctx->nproj, nb, npw, ctx->max_bands, ctx->d_betaT_bf16.p, ctx->d_bf16_ws.p, out, ldo, st);
     }
 }
 
@@ -253,7 +253,11 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
             c->d_beta_bf16.alloc((size_t)2 * c->nproj * c->ldb16 * 2);
             beta_to_bf16(c->nproj, b.npw, c->ldb16, c->d_beta64.p, c->d_beta_bf16.p,
                          (char *)c->d_beta_bf16.p + (size_t)c->nproj * c->ldb16 * 2, st);
-            acct += c->d_beta_bf16.bytes;
+            const size_t tplane = (size_t)bf16_ld(b.npw) * bf16_ld(c->nproj) * 2;
+            c->d_betaT_bf16.alloc(2 * tplane);
+            beta_to_bf16_t(c->nproj, b.npw, c->d_beta64.p, c->d_betaT_bf16.p, (char *)c->d_betaT_bf16.p + tplane, st);
+            c->d_bf16_ws.alloc(bf16_scratch_bytes(c->nproj, b.npw, max_bands));
+            acct += c->d_beta_bf16.bytes + c->d_betaT_bf16.bytes + c->d_bf16_ws.bytes;
             if (!(flags & PW_PREP_C128)) c->d_beta64.free_();
         }
         acct += c->d_beta64.bytes;
@@ -283,7 +287,7 @@ pw_status pw_ctx_destroy(pw_ctx *ctx) {
     ctx->prof_pool.clear();
     DevBuf *bufs[] = {&ctx->d_kin, &ctx->d_zmap, &ctx->d_colpos, &ctx->d_colstart, &ctx->d_vz64, &ctx->d_vz32,
                       &ctx->d_tw64[0], &ctx->d_tw64[1], &ctx->d_tw64[2], &ctx->d_tw32[0], &ctx->d_tw32[1],
-                      &ctx->d_tw32[2], &ctx->d_beta64, &ctx->d_beta_bf16, &ctx->d_dproj, &ctx->d_dproj32,
+                      &ctx->d_tw32[2], &ctx->d_beta64, &ctx->d_beta_bf16, &ctx->d_betaT_bf16, &ctx->d_bf16_ws, &ctx->d_dproj, &ctx->d_dproj32,
                       &ctx->d_shell, &ctx->d_cols, &ctx->d_proj, &ctx->d_partial, &ctx->d_ortho_ws,
                       &ctx->d_ortho_small};
     for (DevBuf *d : bufs) d->free_();

@@ -153,6 +153,8 @@ struct pw_ctx {
     // device tables
     pw::DevBuf d_kin, d_zmap, d_colpos, d_colstart, d_vz64, d_vz32, d_tw64[3], d_tw32[3];
     pw::DevBuf d_beta64, d_beta_bf16, d_dproj, d_dproj32, d_shell;
+    pw::DevBuf d_betaT_bf16;         // BF16 planes of the transposed table [ldg][ldp] (back-projection)
+    pw::DevBuf d_bf16_ws;            // per-call BF16 planes of psi and of D . C
     int64_t ldb16 = 0;               // row length of the BF16 projector planes
     // hpsi workspace
     pw::DevBuf d_cols;               // [max_bands][N2][ncols] complex128 (reused for c64)

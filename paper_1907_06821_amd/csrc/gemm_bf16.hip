@@ -3,9 +3,17 @@
 //
 //   projection      projT[b][p] = D_p sum_G conj(beta_p(G)) psi_b(G)     (split-K)
 //   back-projection out[b][G]  += sum_p projT[b][p] beta_p(G)
-// The projector table is stored once as two BF16 planes (real, imaginary),
-// [nproj][ldb] with ldb a multiple of 64 and zero padding.  Wave functions and
-// projections are rounded to BF16 (nearest even) as they are staged into LDS.
+//
+// Tables (built once per context, zero padded):
+//   beta   planes [nproj][ldg]   (ldg = npw rounded up to 64)   projection operand
+//   betaT  planes [ldg][ldp]     (ldp = nproj rounded up to 64) back-projection operand
+// so that every MFMA operand fragment (8 consecutive k of one row) is one
+// 16-byte load.  Per H psi the wave functions are rounded once to BF16 planes
+// [nb][ldg], and the projection's reduction writes D . C directly as BF16
+// planes [nb][ldp].  Workgroup tiles span all bands of a call (up to 144), so
+// each table is read once per H psi; the band operand of each tile is staged
+// in LDS and shared by the four waves, the table fragments go straight from
+// memory into registers.  Rounding is to nearest even.
 #include "kernels.h"
 
 namespace pw {
@@ -35,81 +43,127 @@ __device__ inline bf16x8 neg8(bf16x8 v) {
     return x.b;
 }
 
-constexpr int KB = 64;          // k-depth per LDS stage
-constexpr int LP = KB + 8;      // padded LDS row (bf16 elements)
+__device__ inline bf16x8 load8(const uint16_t *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+__device__ inline bf16x8 zero8() {
+    union { bf16x8 b; uint4 u; } x;
+    x.u = make_uint4(0, 0, 0, 0);
+    return x.b;
+}
+
+constexpr int KS = 64;          // k-depth per LDS stage
+constexpr int LPAD = KS + 8;    // padded LDS row (bf16 elements, 144 bytes)
+constexpr int MAXNB = 144;      // largest band tile (9 blocks of 16)
+
+int64_t bf16_ld(int n) { return ((int64_t)n + 63) / 64 * 64; }
 
 // ---------------------------------------------------------------------------
-// projection partials: partial[s][p][b] over K chunk s
+// complex64 rows -> BF16 planes [rows][ldp], zero beyond n
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void proj_bf16_partial(int M, int N, int K, const uint16_t *__restrict__ Br,
-                                                         const uint16_t *__restrict__ Bi, int64_t ldb,
-                                                         const float2 *__restrict__ psi, int64_t ld, int kchunk,
-                                                         float2 *__restrict__ partial) {
-    __shared__ __attribute__((aligned(16))) uint16_t Ar[64][LP], Ai[64][LP], Pr[64][LP], Pi[64][LP];
-    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64, s = blockIdx.z;
-    const int kbeg = s * kchunk;
-    const int kend = min(K, kbeg + kchunk);
+__global__ void k_c64_to_planes(int rows, int n, const float2 *__restrict__ src, int64_t lds, int64_t ldp,
+                                uint16_t *__restrict__ re, uint16_t *__restrict__ im) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (g >= ldp) return;
+    const float2 v = g < n ? src[(int64_t)r * lds + g] : make_float2(0.f, 0.f);
+    re[(int64_t)r * ldp + g] = f2bf(v.x);
+    im[(int64_t)r * ldp + g] = f2bf(v.y);
+}
+
+// complex128 table [rows][n] -> transposed BF16 planes [ldn][ldr] (zero padded)
+__global__ void k_c128_to_planes_t(int rows, int n, const double2 *__restrict__ src, int64_t ldr, int64_t ldn,
+                                   uint16_t *__restrict__ re, uint16_t *__restrict__ im) {
+    __shared__ double2 tile[32][33];
+    const int r0 = blockIdx.y * 32, g0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+    for (int y = ty; y < 32; y += 8) {
+        const int r = r0 + y, g = g0 + tx;
+        tile[y][tx] = (r < rows && g < n) ? src[(int64_t)r * n + g] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int g = g0 + y, r = r0 + tx;
+        if (g < ldn && r < ldr) {
+            const double2 v = tile[tx][y];
+            re[(int64_t)g * ldr + r] = f2bf((float)v.x);
+            im[(int64_t)g * ldr + r] = f2bf((float)v.y);
+        }
+    }
+}
+
+void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st) {
+    const int64_t ldr = bf16_ld(nproj), ldn = bf16_ld(npw);
+    dim3 grid((unsigned)((ldn + 31) / 32), (unsigned)((ldr + 31) / 32));
+    hipLaunchKernelGGL(k_c128_to_planes_t, grid, dim3(256), 0, st, nproj, npw, (const double2 *)beta64, ldr, ldn,
+                       (uint16_t *)tr, (uint16_t *)ti);
+    PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// projection partials: partial[s][p][b] = sum over G chunk s of conj(beta) psi.
+// Workgroup: 128 projectors (32 per wave) x NBLK*16 bands; grid (M tiles, splits).
+// ---------------------------------------------------------------------------
+template <int NBLK>
+__global__ __launch_bounds__(256) void proj16_partial(int M, int N, const uint16_t *__restrict__ Br,
+                                                      const uint16_t *__restrict__ Bi, int64_t ldg,
+                                                      const uint16_t *__restrict__ Pr,
+                                                      const uint16_t *__restrict__ Pi, int kchunk,
+                                                      float2 *__restrict__ partial) {
+    constexpr int NB = NBLK * 16;
+    __shared__ __attribute__((aligned(16))) uint16_t sPr[NB][LPAD], sPi[NB][LPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    v4f accr[2][2], acci[2][2];
+    const int m0 = blockIdx.x * 128 + wave * 32;
+    const int s = blockIdx.y;
+    const int kbeg = s * kchunk;
+    const int kend = (int)min((int64_t)kbeg + kchunk, ldg);
+    v4f ar_[2][NBLK], ai_[2][NBLK];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) { accr[i][j] = v4f{0, 0, 0, 0}; acci[i][j] = v4f{0, 0, 0, 0}; }
-    for (int k0 = kbeg; k0 < kend; k0 += KB) {
-        // projector planes: 64 rows x 64 bf16, 16-byte pieces
+        for (int j = 0; j < NBLK; ++j) { ar_[i][j] = v4f{0, 0, 0, 0}; ai_[i][j] = v4f{0, 0, 0, 0}; }
+    const int64_t rowA[2] = {(int64_t)(m0 + (lane & 15)), (int64_t)(m0 + 16 + (lane & 15))};
+    const bool okA[2] = {rowA[0] < M, rowA[1] < M};
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+        // projector fragments of this stage, straight from memory
+        bf16x8 fa_r[2][2], fa_i[2][2];
 #pragma unroll
-        for (int it = 0; it < 2; ++it) {
-            const int e = tid + it * 256;          // 0..511
-            const int r = e >> 3, c8 = (e & 7) * 8;
-            const int gm = m0 + r;
-            uint4 vr = make_uint4(0, 0, 0, 0), vi = make_uint4(0, 0, 0, 0);
-            if (gm < M) {
-                vr = *reinterpret_cast<const uint4 *>(Br + (int64_t)gm * ldb + k0 + c8);
-                vi = *reinterpret_cast<const uint4 *>(Bi + (int64_t)gm * ldb + k0 + c8);
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int64_t off = rowA[i] * ldg + k0 + ks * 32 + 8 * (lane >> 4);
+                fa_r[ks][i] = okA[i] ? load8(Br + off) : zero8();
+                fa_i[ks][i] = okA[i] ? load8(Bi + off) : zero8();
             }
-            *reinterpret_cast<uint4 *>(&Ar[r][c8]) = vr;
-            *reinterpret_cast<uint4 *>(&Ai[r][c8]) = vi;
-        }
-        // wave functions: 64 bands x 64 complex64, rounded to bf16
-#pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int e = tid + it * 256;          // 0..4095
-            const int r = e >> 6, c = e & 63;
-            const int gn = n0 + r, gk = k0 + c;
-            float2 v = make_float2(0.f, 0.f);
-            if (gn < N && gk < kend) v = psi[(int64_t)gn * ld + gk];
-            Pr[r][c] = f2bf(v.x);
-            Pi[r][c] = f2bf(v.y);
+        // band tile: NB rows x KS bf16 per plane, 16-byte pieces
+        for (int e = tid; e < NB * (KS / 8); e += 256) {
+            const int r = e >> 3, c8 = (e & 7) * 8;
+            uint4 vr = make_uint4(0, 0, 0, 0), vi = make_uint4(0, 0, 0, 0);
+            if (r < N) {
+                vr = *reinterpret_cast<const uint4 *>(Pr + (int64_t)r * ldg + k0 + c8);
+                vi = *reinterpret_cast<const uint4 *>(Pi + (int64_t)r * ldg + k0 + c8);
+            }
+            *reinterpret_cast<uint4 *>(&sPr[r][c8]) = vr;
+            *reinterpret_cast<uint4 *>(&sPi[r][c8]) = vi;
         }
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < KB / 32; ++ks) {
+        for (int ks = 0; ks < 2; ++ks) {
             const int kk = ks * 32 + 8 * (lane >> 4);
-            bf16x8 ar[2], ai[2], nai[2], br[2], bi[2];
+            bf16x8 nai[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int row = wm * 32 + i * 16 + (lane & 15);
-                ar[i] = *reinterpret_cast<const bf16x8 *>(&Ar[row][kk]);
-                ai[i] = *reinterpret_cast<const bf16x8 *>(&Ai[row][kk]);
-                nai[i] = neg8(ai[i]);
-            }
+            for (int i = 0; i < 2; ++i) nai[i] = neg8(fa_i[ks][i]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int row = wn * 32 + j * 16 + (lane & 15);
-                br[j] = *reinterpret_cast<const bf16x8 *>(&Pr[row][kk]);
-                bi[j] = *reinterpret_cast<const bf16x8 *>(&Pi[row][kk]);
-            }
+            for (int j = 0; j < NBLK; ++j) {
+                const int row = j * 16 + (lane & 15);
+                const bf16x8 br = load8(&sPr[row][kk]), bi = load8(&sPi[row][kk]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int i = 0; i < 2; ++i) {
                     // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
-                    accr[i][j] = mfma_bf16(ar[i], br[j], accr[i][j]);
-                    accr[i][j] = mfma_bf16(ai[i], bi[j], accr[i][j]);
-                    acci[i][j] = mfma_bf16(ar[i], bi[j], acci[i][j]);
-                    acci[i][j] = mfma_bf16(nai[i], br[j], acci[i][j]);
+                    ar_[i][j] = mfma_bf16(fa_r[ks][i], br, ar_[i][j]);
+                    ar_[i][j] = mfma_bf16(fa_i[ks][i], bi, ar_[i][j]);
+                    ai_[i][j] = mfma_bf16(fa_r[ks][i], bi, ai_[i][j]);
+                    ai_[i][j] = mfma_bf16(nai[i], br, ai_[i][j]);
                 }
+            }
         }
         __syncthreads();
     }
@@ -117,166 +171,210 @@ __global__ __launch_bounds__(256) void proj_bf16_partial(int M, int N, int K, co
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NBLK; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (row < M && col < N) P[(int64_t)row * N + col] = make_float2(accr[i][j][v], acci[i][j][v]);
+                const int row = m0 + i * 16 + 4 * (lane >> 4) + v;
+                const int col = j * 16 + (lane & 15);
+                if (row < M && col < N) P[(int64_t)row * N + col] = make_float2(ar_[i][j][v], ai_[i][j][v]);
             }
 }
 
-// projT[b][p] = d[p] * sum_s partial[s][p][b]
-__global__ void proj_bf16_reduce(int M, int N, int nsplit, const float2 *__restrict__ partial,
-                                 const float *__restrict__ d, float2 *__restrict__ projT) {
+// W planes [b][ldp] = bf16(d[p] * sum_s partial[s][p][b]), zero for p >= M
+__global__ void proj16_reduce(int M, int N, int nsplit, const float2 *__restrict__ partial,
+                              const float *__restrict__ d, int64_t ldp, uint16_t *__restrict__ Wr,
+                              uint16_t *__restrict__ Wi) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)M * N) return;
-    const int m = (int)(idx / N), n = (int)(idx % N);
-    double re = 0, im = 0;
-    for (int s = 0; s < nsplit; ++s) {
-        const float2 v = partial[(int64_t)s * M * N + idx];
-        re += v.x;
-        im += v.y;
-    }
-    const double sc = d ? d[m] : 1.0;
-    projT[(int64_t)n * M + m] = make_float2((float)(re * sc), (float)(im * sc));
-}
-
-static int bf16_splits(int M, int N, int K) {
-    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-    int s = (1024 + tiles - 1) / tiles;
-    const int maxs = (K + 4 * KB - 1) / (4 * KB);
-    if (s > maxs) s = maxs;
-    if (s < 1) s = 1;
-    return s;
-}
-
-size_t cnt_partial_bytes(int M, int N, int K) { return (size_t)bf16_splits(M, N, K) * M * N * sizeof(float2); }
-
-void proj_bf16(int nproj, int nb, int npw, const void *beta_bf16, const void *psi, int64_t ld, const float *d,
-               void *projT, void *partial, hipStream_t st) {
-    // ldb: planes are [nproj][ldb] with ldb = npw rounded up to 64
-    const int64_t ldb = ((npw + 63) / 64) * 64;
-    const uint16_t *Br = (const uint16_t *)beta_bf16;
-    const uint16_t *Bi = Br + (int64_t)nproj * ldb;
-    const int ns = bf16_splits(nproj, nb, npw);
-    int kchunk = (npw + ns - 1) / ns;
-    kchunk = ((kchunk + KB - 1) / KB) * KB;
-    const int nsplit = (npw + kchunk - 1) / kchunk;
-    dim3 grid((nproj + 63) / 64, (nb + 63) / 64, nsplit);
-    hipLaunchKernelGGL(proj_bf16_partial, grid, dim3(256), 0, st, nproj, nb, npw, Br, Bi, ldb, (const float2 *)psi,
-                       ld, kchunk, (float2 *)partial);
-    PW_LAUNCH_CHECK();
-    const int64_t tot = (int64_t)nproj * nb;
-    hipLaunchKernelGGL(proj_bf16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
-                       (const float2 *)partial, d, (float2 *)projT);
-    PW_LAUNCH_CHECK();
-}
-
-// ---------------------------------------------------------------------------
-// back-projection: out[b][G] += sum_p W[b][p] beta_p(G), W = projT (complex64)
-// tile 64 bands x 64 plane waves
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void backproj_bf16_kernel(int M, int J, int K, const float2 *__restrict__ W,
-                                                            const uint16_t *__restrict__ Br,
-                                                            const uint16_t *__restrict__ Bi, int64_t ldb,
-                                                            float2 *__restrict__ out, int64_t ldo) {
-    __shared__ __attribute__((aligned(16))) uint16_t Wr[64][LP], Wi[64][LP], Tr[64][LP], Ti[64][LP];
-    const int j0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wj = wave >> 1;
-    v4f accr[2][2], acci[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) { accr[i][j] = v4f{0, 0, 0, 0}; acci[i][j] = v4f{0, 0, 0, 0}; }
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        // W tile: 64 bands x 64 projectors
-#pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int e = tid + it * 256;
-            const int r = e >> 6, c = e & 63;
-            const int gm = m0 + r, gk = k0 + c;
-            float2 v = make_float2(0.f, 0.f);
-            if (gm < M && gk < K) v = W[(int64_t)gm * K + gk];
-            Wr[r][c] = f2bf(v.x);
-            Wi[r][c] = f2bf(v.y);
+    if (idx >= (int64_t)N * ldp) return;
+    const int n = (int)(idx / ldp), m = (int)(idx % ldp);
+    float re = 0.f, im = 0.f;
+    if (m < M) {
+        double sr = 0, si = 0;
+        for (int s = 0; s < nsplit; ++s) {
+            const float2 v = partial[(int64_t)s * M * N + (int64_t)m * N + n];
+            sr += v.x;
+            si += v.y;
         }
-        // projector tile, transposed into LDS: T[j][k] = beta[k0 + k][j0 + j]
+        const double sc = d ? d[m] : 1.0;
+        re = (float)(sr * sc);
+        im = (float)(si * sc);
+    }
+    Wr[idx] = f2bf(re);
+    Wi[idx] = f2bf(im);
+}
+
+// ---------------------------------------------------------------------------
+// back-projection: out[b][G] += sum_p W[b][p] beta_p(G), W from the BF16 planes.
+// Workgroup: NBLK*16 bands x 128 plane waves (32 per wave); grid: G tiles.
+// ---------------------------------------------------------------------------
+template <int NBLK>
+__global__ __launch_bounds__(256) void backproj16(int N, int J, int64_t ldp, const uint16_t *__restrict__ Wr,
+                                                  const uint16_t *__restrict__ Wi, const uint16_t *__restrict__ Tr,
+                                                  const uint16_t *__restrict__ Ti, float2 *__restrict__ out,
+                                                  int64_t ldo) {
+    constexpr int NB = NBLK * 16;
+    __shared__ __attribute__((aligned(16))) uint16_t sWr[NB][LPAD], sWi[NB][LPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j0 = blockIdx.x * 128 + wave * 32;
+    v4f ar_[NBLK][2], ai_[NBLK][2];
 #pragma unroll
-        for (int it = 0; it < 2; ++it) {
-            const int e = tid + it * 256;          // 0..511: 64 k-rows x 8 pieces of 8 plane waves
-            const int kr = e >> 3, c8 = (e & 7) * 8;
-            const int gk = k0 + kr;
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { ar_[i][j] = v4f{0, 0, 0, 0}; ai_[i][j] = v4f{0, 0, 0, 0}; }
+    const int64_t gcol[2] = {(int64_t)(j0 + (lane & 15)), (int64_t)(j0 + 16 + (lane & 15))};
+    const bool okB[2] = {gcol[0] < J, gcol[1] < J};
+    for (int k0 = 0; k0 < ldp; k0 += KS) {
+        // table fragments (betaT rows are plane waves), straight from memory
+        bf16x8 fb_r[2][2], fb_i[2][2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int64_t off = gcol[j] * ldp + k0 + ks * 32 + 8 * (lane >> 4);
+                fb_r[ks][j] = okB[j] ? load8(Tr + off) : zero8();
+                fb_i[ks][j] = okB[j] ? load8(Ti + off) : zero8();
+            }
+        for (int e = tid; e < NB * (KS / 8); e += 256) {
+            const int r = e >> 3, c8 = (e & 7) * 8;
             uint4 vr = make_uint4(0, 0, 0, 0), vi = make_uint4(0, 0, 0, 0);
-            if (gk < K && j0 + c8 < ldb) {
-                vr = *reinterpret_cast<const uint4 *>(Br + (int64_t)gk * ldb + j0 + c8);
-                vi = *reinterpret_cast<const uint4 *>(Bi + (int64_t)gk * ldb + j0 + c8);
+            if (r < N) {
+                vr = *reinterpret_cast<const uint4 *>(Wr + (int64_t)r * ldp + k0 + c8);
+                vi = *reinterpret_cast<const uint4 *>(Wi + (int64_t)r * ldp + k0 + c8);
             }
-            const uint16_t *pr = reinterpret_cast<const uint16_t *>(&vr);
-            const uint16_t *pi = reinterpret_cast<const uint16_t *>(&vi);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                Tr[c8 + q][kr] = pr[q];
-                Ti[c8 + q][kr] = pi[q];
-            }
+            *reinterpret_cast<uint4 *>(&sWr[r][c8]) = vr;
+            *reinterpret_cast<uint4 *>(&sWi[r][c8]) = vi;
         }
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < KB / 32; ++ks) {
+        for (int ks = 0; ks < 2; ++ks) {
             const int kk = ks * 32 + 8 * (lane >> 4);
-            bf16x8 ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int row = wm * 32 + i * 16 + (lane & 15);
-                ar[i] = *reinterpret_cast<const bf16x8 *>(&Wr[row][kk]);
-                ai[i] = *reinterpret_cast<const bf16x8 *>(&Wi[row][kk]);
-                nai[i] = neg8(ai[i]);
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int row = wj * 32 + j * 16 + (lane & 15);
-                br[j] = *reinterpret_cast<const bf16x8 *>(&Tr[row][kk]);
-                bi[j] = *reinterpret_cast<const bf16x8 *>(&Ti[row][kk]);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NBLK; ++i) {
+                const int row = i * 16 + (lane & 15);
+                const bf16x8 wr = load8(&sWr[row][kk]), wi = load8(&sWi[row][kk]);
+                const bf16x8 nwi = neg8(wi);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     // W beta: re = wr br - wi bi, im = wr bi + wi br
-                    accr[i][j] = mfma_bf16(ar[i], br[j], accr[i][j]);
-                    accr[i][j] = mfma_bf16(nai[i], bi[j], accr[i][j]);
-                    acci[i][j] = mfma_bf16(ar[i], bi[j], acci[i][j]);
-                    acci[i][j] = mfma_bf16(ai[i], br[j], acci[i][j]);
+                    ar_[i][j] = mfma_bf16(wr, fb_r[ks][j], ar_[i][j]);
+                    ar_[i][j] = mfma_bf16(nwi, fb_i[ks][j], ar_[i][j]);
+                    ai_[i][j] = mfma_bf16(wr, fb_i[ks][j], ai_[i][j]);
+                    ai_[i][j] = mfma_bf16(wi, fb_r[ks][j], ai_[i][j]);
                 }
+            }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NBLK; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-                const int col = j0 + wj * 32 + j * 16 + (lane & 15);
-                if (row < M && col < J) {
-                    float2 *o = out + (int64_t)row * ldo + col;
+                const int b = i * 16 + 4 * (lane >> 4) + v;
+                const int64_t g = gcol[j];
+                if (b < N && g < J) {
+                    float2 *o = out + (int64_t)b * ldo + g;
                     const float2 old = *o;
-                    *o = make_float2(old.x + accr[i][j][v], old.y + acci[i][j][v]);
+                    *o = make_float2(old.x + ar_[i][j][v], old.y + ai_[i][j][v]);
                 }
             }
 }
 
-void backproj_bf16(int nb, int npw, int nproj, const void *projT, const void *beta_bf16, void *out, int64_t ldo,
-                   hipStream_t st) {
-    const int64_t ldb = ((npw + 63) / 64) * 64;
-    const uint16_t *Br = (const uint16_t *)beta_bf16;
-    const uint16_t *Bi = Br + (int64_t)nproj * ldb;
-    dim3 grid((npw + 63) / 64, (nb + 63) / 64);
-    hipLaunchKernelGGL(backproj_bf16_kernel, grid, dim3(256), 0, st, nb, npw, nproj, (const float2 *)projT, Br, Bi,
-                       ldb, (float2 *)out, ldo);
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int band_blocks(int nb) { return nb <= 64 ? 4 : nb <= 128 ? 8 : 9; }
+static int band_chunk(int nb) { return nb <= MAXNB ? nb : 128; }
+
+static int proj_splits(int M, int64_t ldg) {
+    const int mt = (M + 127) / 128;
+    int s = (512 + mt - 1) / mt;
+    const int maxs = (int)((ldg + 2 * KS - 1) / (2 * KS));      // at least two stages per split
+    return std::max(1, std::min(s, maxs));
+}
+
+size_t cnt_partial_bytes(int M, int N, int K) {
+    return (size_t)proj_splits(M, bf16_ld(K)) * M * band_chunk(N) * sizeof(float2);
+}
+
+size_t bf16_scratch_bytes(int nproj, int npw, int max_bands) {
+    return (size_t)2 * max_bands * (bf16_ld(npw) + bf16_ld(nproj)) * sizeof(uint16_t);
+}
+
+template <int NBLK>
+static void proj_go(int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_t ldg, const uint16_t *Pr,
+                    const uint16_t *Pi, float2 *partial, int &nsplit, hipStream_t st) {
+    const int ns = proj_splits(M, ldg);
+    int kchunk = (int)((ldg + ns - 1) / ns);
+    kchunk = (kchunk + KS - 1) / KS * KS;
+    nsplit = (int)((ldg + kchunk - 1) / kchunk);
+    dim3 grid((M + 127) / 128, nsplit);
+    hipLaunchKernelGGL(proj16_partial<NBLK>, grid, dim3(256), 0, st, M, N, Br, Bi, ldg, Pr, Pi, kchunk, partial);
     PW_LAUNCH_CHECK();
+}
+
+template <int NBLK>
+static void back_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
+                    const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
+    hipLaunchKernelGGL(backproj16<NBLK>, dim3((J + 127) / 128), dim3(256), 0, st, N, J, ldp, Wr, Wi, Tr, Ti, out,
+                       ldo);
+    PW_LAUNCH_CHECK();
+}
+
+// Scratch (bf16_scratch_bytes): Pr, Pi [max_bands][ldg] then Wr, Wi [max_bands][ldp].
+struct Bf16Scratch {
+    uint16_t *Pr, *Pi, *Wr, *Wi;
+    Bf16Scratch(void *p, int max_bands, int64_t ldg, int64_t ldp) {
+        Pr = (uint16_t *)p;
+        Pi = Pr + (int64_t)max_bands * ldg;
+        Wr = Pi + (int64_t)max_bands * ldg;
+        Wi = Wr + (int64_t)max_bands * ldp;
+    }
+};
+
+// W = bf16(D o (B^H psi)) for the bands of a complex64 block (into the scratch)
+void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
+               int64_t ld, void *scratch, void *partial, hipStream_t st) {
+    const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
+    const uint16_t *Br = (const uint16_t *)beta16, *Bi = Br + (int64_t)nproj * ldg;
+    Bf16Scratch S(scratch, max_bands, ldg, ldp);
+    hipLaunchKernelGGL(k_c64_to_planes, dim3((unsigned)((ldg + 255) / 256), nb), dim3(256), 0, st, nb, npw,
+                       (const float2 *)psi, ld, ldg, S.Pr, S.Pi);
+    PW_LAUNCH_CHECK();
+    for (int b0 = 0; b0 < nb; b0 += band_chunk(nb)) {
+        const int n = std::min(band_chunk(nb), nb - b0);
+        const uint16_t *Pr = S.Pr + (int64_t)b0 * ldg, *Pi = S.Pi + (int64_t)b0 * ldg;
+        int nsplit = 1;
+        float2 *part = (float2 *)partial;
+        switch (band_blocks(n)) {
+            case 4: proj_go<4>(nproj, n, Br, Bi, ldg, Pr, Pi, part, nsplit, st); break;
+            case 8: proj_go<8>(nproj, n, Br, Bi, ldg, Pr, Pi, part, nsplit, st); break;
+            default: proj_go<9>(nproj, n, Br, Bi, ldg, Pr, Pi, part, nsplit, st); break;
+        }
+        const int64_t tot = (int64_t)n * ldp;
+        hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, n, nsplit,
+                           (const float2 *)part, d, ldp, S.Wr + (int64_t)b0 * ldp, S.Wi + (int64_t)b0 * ldp);
+        PW_LAUNCH_CHECK();
+    }
+}
+
+// out[b] += B . W[b] with W from proj_bf16's scratch
+void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,
+                   int64_t ldo, hipStream_t st) {
+    const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
+    const uint16_t *Tr = (const uint16_t *)betaT16, *Ti = Tr + ldg * ldp;
+    Bf16Scratch S(const_cast<void *>(scratch), max_bands, ldg, ldp);
+    for (int b0 = 0; b0 < nb; b0 += band_chunk(nb)) {
+        const int n = std::min(band_chunk(nb), nb - b0);
+        const uint16_t *Wr = S.Wr + (int64_t)b0 * ldp, *Wi = S.Wi + (int64_t)b0 * ldp;
+        float2 *po = (float2 *)out + (int64_t)b0 * ldo;
+        switch (band_blocks(n)) {
+            case 4: back_go<4>(n, npw, ldp, Wr, Wi, Tr, Ti, po, ldo, st); break;
+            case 8: back_go<8>(n, npw, ldp, Wr, Wi, Tr, Ti, po, ldo, st); break;
+            default: back_go<9>(n, npw, ldp, Wr, Wi, Tr, Ti, po, ldo, st); break;
+        }
+    }
 }
 
 }  // namespace pw

@@ -24,10 +24,13 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
 
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
 size_t cnt_partial_bytes(int M, int N, int K);
-void proj_bf16(int nproj, int nb, int npw, const void *beta_bf16, const void *psi, int64_t ld, const float *d,
-               void *projT, void *partial, hipStream_t);
-void backproj_bf16(int nb, int npw, int nproj, const void *projT, const void *beta_bf16, void *out, int64_t ldo,
-                   hipStream_t);
+int64_t bf16_ld(int n);
+size_t bf16_scratch_bytes(int nproj, int npw, int max_bands);
+void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st);
+void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
+               int64_t ld, void *scratch, void *partial, hipStream_t st);
+void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,
+                   int64_t ldo, hipStream_t st);
 
 // dense.hip
 void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t);
