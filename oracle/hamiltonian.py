@@ -147,6 +147,10 @@ class Operator:
     Built from a synthetic problem's raw inputs (cell, grid, ecut, kpt, atom
     centres, well depths/width, projector width, D)."""
 
+    # projector tables larger than this many entries are not stored: apply()
+    # then builds them a few atoms at a time (the same rows, summed by atom)
+    MAX_TABLE = 200_000_000
+
     def __init__(self, cell, grid, ecut, vgrid, pos=None, sigma=0.8, nl=0, dproj=None,
                  kpt=(0.0, 0.0, 0.0)):
         from .basis import plane_wave_basis, fits_grid
@@ -159,9 +163,13 @@ class Operator:
             raise ValueError("cutoff sphere does not fit the FFT grid")
         self.vgrid = np.asarray(vgrid, dtype=np.float64)
         self.nl = int(nl)
+        self.pos = None if pos is None else np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        self.sigma = float(sigma)
+        self.lazy = False
         if self.nl and pos is not None and len(pos):
-            self.beta = projectors(self.miller, self.cell, pos, sigma, nl, self.kpt)
             self.dproj = np.asarray(dproj, dtype=np.float64)
+            self.lazy = len(self.pos) * self.nl * self.miller.shape[0] > self.MAX_TABLE
+            self.beta = None if self.lazy else projectors(self.miller, self.cell, pos, sigma, nl, self.kpt)
         else:
             self.beta = None
             self.dproj = None
@@ -177,7 +185,18 @@ class Operator:
         return self.miller.shape[0]
 
     def dense(self):
+        if self.lazy:
+            raise ValueError("no dense H for a cell whose projector table is not stored")
         return dense_hamiltonian(self.miller, self.kin, self.vgrid, self.beta, self.dproj)
 
-    def apply(self, block, shift=0.0):
-        return hpsi(block, self.miller, self.kin, self.vgrid, self.beta, self.dproj, shift)
+    def apply(self, block, shift=0.0, atom_chunk=100):
+        if not self.lazy:
+            return hpsi(block, self.miller, self.kin, self.vgrid, self.beta, self.dproj, shift)
+        block = np.atleast_2d(np.asarray(block, dtype=np.complex128))
+        out = hpsi(block, self.miller, self.kin, self.vgrid, None, None, shift)
+        for a0 in range(0, len(self.pos), atom_chunk):
+            atoms = range(a0, min(a0 + atom_chunk, len(self.pos)))
+            beta = projectors(self.miller, self.cell, self.pos, self.sigma, self.nl, self.kpt, atoms=atoms)
+            d = self.dproj[a0 * self.nl:(a0 + len(atoms)) * self.nl]
+            out += ((block @ beta.conj().T) * d[None, :]) @ beta
+        return out

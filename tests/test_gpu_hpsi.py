@@ -218,3 +218,28 @@ def test_bad_arguments_rejected(torch_cuda):
     with pytest.raises(pw.PwError) as e:
         pw.Context((8, 8, 8), (10.0, 10.0, 10.0), 6.0, np.zeros((8, 8, 8)))
     assert e.value.status == pw.PW_EINVAL
+
+
+def test_hpsi_wire2000_sampled_bands(torch_cuda):
+    """The 2000-atom wire (96x96x384 grid, 8000 projectors, 387,091 plane waves)
+    with 512 bands in one call, complex128 and complex64 (BF16 projector GEMMs):
+    sampled bands against the oracle's matrix-free H psi, whose projector rows
+    are built atom by atom."""
+    import torch
+    import paper_1907_06821_amd as pw
+    prob = synth.config(3)
+    op = oracle_for(prob)
+    assert op.lazy
+    nb = 512
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    c = random_block(7, nb, op.npw)
+    x = to_dev(c)
+    y = pw.hpsi(ctx, x, shift=prob.e_ref)
+    y32 = pw.hpsi(ctx, x.to(torch.complex64), shift=prob.e_ref)
+    bands = [0, 301, nb - 1]
+    ref = op.apply(c[bands], shift=prob.e_ref)
+    got = y[bands].cpu().numpy()
+    got32 = y32[bands].cpu().numpy()
+    for i in range(len(bands)):
+        assert rel_err(got[i], ref[i]) < 1e-12
+        assert rel_err(got32[i], ref[i]) < 2e-3

@@ -237,3 +237,16 @@ def test_fsm_cg_nonlocal_kpoint(precond):
     r = fsm_cg(op.apply, prob.e_ref, synth.start_vectors(7, 6, op.npw), op.kin, tol=1e-9, maxit=3000,
                check_every=10, precond=precond)
     assert r["converged"] and np.max(np.abs(r["theta"] - lam)) < 1e-8
+
+
+def test_lazy_projectors_equal_stored_table():
+    """The atom-chunked nonlocal term (used when the projector table is too large
+    to store) equals the stored-table one."""
+    prob = synth.small_nonlocal_problem(seed=4, natom=5)
+    full = oh.Operator.from_problem(prob)
+    lazy = oh.Operator.from_problem(prob)
+    lazy.lazy, lazy.beta = True, None
+    x = synth.start_vectors(99, 3, full.npw, seed=2)
+    a = full.apply(x, shift=0.3)
+    b = lazy.apply(x, shift=0.3, atom_chunk=2)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
