@@ -77,6 +77,25 @@ def cpu_baseline(prob, nb_sample=64, iters=2):
                       f"Rayleigh-Ritz, {r['n_hpsi']} band-Hpsi in {dt:.1f} s"}
 
 
+def measured_traffic(stage, mixed, nb):
+    """HBM bytes per launch of the dominant stage from the committed counter runs
+    (FETCH_SIZE / WRITE_SIZE, copy-calibrated), if they were taken on this
+    workload and the kernel source has not changed since; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wire256_fp64_traffic.json")
+    if mixed or nb != 128 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, rec["source"])
+    if rec["stage"] != stage or not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["bytes_per_launch"]
+
+
 SOLVE_LEGS = (("fp64_tpa", 0, 0), ("fp64_mg", 0, 1), ("mixed_tpa", 1, 0), ("mixed_mg", 1, 1),
               ("mixed_learned", 1, 2))
 
@@ -139,7 +158,18 @@ def main():
     ap.add_argument("--cpu-bands", type=int, default=64)
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-residual solves")
     ap.add_argument("--solve-legs", default=",".join(n for n, _, _ in SOLVE_LEGS))
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver shards no work across GPUs in this build",
               file=sys.stderr)
@@ -194,7 +224,7 @@ def main():
     dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches"])
     d = stages[dom]
     roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
-                "frac": round(d["frac"], 4), "traffic": None, "kernel": dom}
+                "frac": round(d["frac"], 4), "traffic": measured_traffic(dom, mixed, nb), "kernel": dom}
 
     line = {
         "metric": "band-Hψ/sec and folded-CG time to residual 1e-6 (mixed+learned vs FP64)",
