@@ -18,6 +18,9 @@ namespace pw {
 __device__ inline double2 zmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 zmulc(double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }   // a conj(b)
 __device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double2 zfma(double2 a, double2 b, double2 c) {   // a b + c
+    return make_double2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
+}
 
 // ---------------------------------------------------------------------------
 // Cholesky + triangular inverse.  W: work copy of S (N x N, ld N), overwritten
@@ -94,6 +97,15 @@ __device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 // largest matrix whose packed triangle (N (N + 1) / 2 complex128) fits in LDS
 constexpr int kLdsMaxN = 136;
 
+// (row, column) of entry q of a packed lower triangle
+__device__ inline void tri_rc(int q, int &i, int &k) {
+    int r = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > q) --r;
+    while ((r + 1) * (r + 2) / 2 <= q) ++r;
+    i = r;
+    k = q - r * (r + 1) / 2;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
                                                           double2 *__restrict__ T, int *__restrict__ status) {
@@ -102,8 +114,11 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
     __shared__ double piv;
     __shared__ int bad;
     const int tid = threadIdx.x;
-    for (int i = 0; i < N; ++i)
-        for (int k = tid; k <= i; k += NT) L[tri(i, k)] = S[(int64_t)i * lds + k];
+    for (int q = tid; q < N * (N + 1) / 2; q += NT) {   // every load in flight at once
+        int i, k;
+        tri_rc(q, i, k);
+        L[q] = S[(int64_t)i * lds + k];
+    }
     if (tid == 0) bad = 0;
     __syncthreads();
     for (int j = 0; j < N; ++j) {
@@ -212,9 +227,6 @@ constexpr int kQlMaxIter = 60;
 constexpr int kEigNT = 1024;
 constexpr int kEigMaxN = 1024;
 
-__device__ inline double2 zfma(double2 a, double2 b, double2 c) {
-    return make_double2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
-}
 __device__ inline double2 lds_get(const double2 *L, int i, int k) {
     return i >= k ? L[tri(i, k)] : zconj(L[tri(k, i)]);
 }
@@ -223,14 +235,6 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 __device__ inline double2 wave_sum2(double2 x) { return make_double2(wave_sum(x.x), wave_sum(x.y)); }
-// (row, column) of entry q of a packed lower triangle
-__device__ inline void tri_rc(int q, int &i, int &k) {
-    int r = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
-    while (r * (r + 1) / 2 > q) --r;
-    while ((r + 1) * (r + 2) / 2 <= q) ++r;
-    i = r;
-    k = q - r * (r + 1) / 2;
-}
 __host__ __device__ inline int refl_off(int k, int N) { return k * (N - 1) - k * (k - 1) / 2; }
 
 // Reflector for x = (alpha, x2) with s2 = |x2|^2: tau, beta, 1/(alpha - beta).
@@ -250,13 +254,15 @@ __device__ inline void householder(double2 al, double s2, double2 &tau, double &
 
 // r = sqrt(f^2 + g^2) and 1/r: hardware reciprocal square root refined by two
 // Goldschmidt steps and a final Newton correction of r; library hypot outside
-// the range where f^2 + g^2 neither overflows nor underflows.  false if r == 0.
-__device__ __forceinline__ bool givens_norm(double f, double g, double &r, double &rinv) {
+// the range where f^2 + g^2 neither overflows nor underflows.  Returns 0 if
+// r == 0.  Every lane of the wave holds the same f and g, so the rare cases are
+// taken as scalar branches.
+__device__ __forceinline__ int givens_norm(double f, double g, double &r, double &rinv) {
     const double x = f * f + g * g;
-    if (!(x >= 1e-290 && x <= 1e290)) {
+    if (__builtin_amdgcn_readfirstlane((int)!(x >= 1e-290 && x <= 1e290))) {
         r = hypot(f, g);
         rinv = 1.0 / r;
-        return r != 0.0;
+        return __builtin_amdgcn_readfirstlane((int)(r != 0.0));
     }
     const double y = __builtin_amdgcn_rsq(x);
     double h = 0.5 * y, q = x * y;
@@ -268,7 +274,7 @@ __device__ __forceinline__ bool givens_norm(double f, double g, double &r, doubl
     h = fma(h, t, h);
     r = fma(fma(-q, q, x), h, q);
     rinv = 2.0 * h;
-    return true;
+    return 1;
 }
 
 // One implicit QL sweep of the tridiagonal (d, e), run uniformly by all 64 lanes
@@ -312,40 +318,44 @@ __device__ __forceinline__ int ql_sweep(int N, double *d, double *e, double *cs,
         double ei = e[m - 1], di = d[m - 1];
         bool split = false;
         for (int i = m - 1; i >= l; --i) {
-            double en = 0.0, dn = 0.0;
-            if (i > l) {
-                en = e[i - 1];
-                dn = d[i - 1];
-            }
+            // next step's operands, loaded ahead (index clamped on the last step)
+            const int ip = i > l ? i - 1 : i;
+            const double en = e[ip], dn = d[ip];
             const double f = s * ei, b = c * ei;
             double rinv;
             if (!givens_norm(f, g, r, rinv)) {  // T splits: the next search restarts on the shorter block
-                d[i + 1] = dip1 - p;
-                e[i + 1] = 0.0;
-                e[m] = 0.0;
+                if (lane == 0) {
+                    d[i + 1] = dip1 - p;
+                    e[i + 1] = 0.0;
+                    e[m] = 0.0;
+                }
                 split = true;
                 break;
             }
-            e[i + 1] = r;
             s = f * rinv;
             c = g * rinv;
             g = dip1 - p;
-            r = (di - g) * s + 2.0 * c * b;
-            p = s * r;
-            d[i + 1] = g + p;
-            g = c * r - b;
-            cs[nrot] = c;
-            sn[nrot] = s;
+            const double rr = (di - g) * s + 2.0 * c * b;
+            p = s * rr;
+            if (lane == 0) {
+                e[i + 1] = r;
+                d[i + 1] = g + p;
+                cs[nrot] = c;
+                sn[nrot] = s;
+            }
+            r = rr;
+            g = c * rr - b;
             ++nrot;
             dip1 = di;
             ei = en;
             di = dn;
         }
-        if (!split) {
+        if (!split && lane == 0) {
             d[l] = dip1 - p;
             e[l] = g;
             e[m] = 0.0;
         }
+        __builtin_amdgcn_wave_barrier();   // lane 0's stores stay ahead of the next sweep's loads
         return m;
     }
     return -1;

@@ -251,16 +251,17 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
-// NT tiles: TM = 64 rows of A; TN = 64 (N <= 64), 128 (N <= 128) or 144 (N <= 144,
-// for 128 wanted bands plus buffer bands), else 128.
+// NT tiles: TN = 64 (N <= 64), 128 (N <= 128) or 144 (N <= 144, for 128 wanted
+// bands plus buffer bands), else 128; TM = 128 rows of A when A is tall (the
+// projector table: B is then re-read half as often), else 64.
 static int nt_tn(int N) { return N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128)); }
-constexpr int NT_TM = 64;
+static int nt_tm(int M, int N) { return (M >= 512 && N > 64) ? 128 : 64; }
 
 // K-splits: enough workgroups to cover the chip (~512) while keeping at least
 // four LDS stages per chunk and the partial sums under 64 MiB.
 int nt_splits(int M, int N, int K) {
-    const int tn = nt_tn(N);
-    const int tiles = ((M + NT_TM - 1) / NT_TM) * ((N + tn - 1) / tn);
+    const int tn = nt_tn(N), tm = nt_tm(M, N);
+    const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
     int s = (512 + tiles - 1) / tiles;
     const int maxs = (K + 4 * KT - 1) / (4 * KT);
     if (s > maxs) s = maxs;
@@ -298,10 +299,12 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     int kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + KT - 1) / KT) * KT;
     const int nsplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
-    const int tn = nt_tn(N);
-    dim3 grid((M + NT_TM - 1) / NT_TM, (N + tn - 1) / tn, nsplit);
+    const int tn = nt_tn(N), tm = nt_tm(M, N);
+    dim3 grid((M + tm - 1) / tm, (N + tn - 1) / tn, nsplit);
     if (K <= 0) fill_zero(partial, (size_t)M * N * sizeof(double2), st);
     else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tm == 128 && tn == 128) nt_go<4, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tm == 128) nt_go<4, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tn == 128) nt_go<2, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else nt_go<2, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     PW_LAUNCH_CHECK();
