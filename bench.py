@@ -188,6 +188,8 @@ def main():
     nb = prob.nbands
     psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
     opts = dict(tol=1e-30, check_every=20, precision=1 if mixed else 0)
+    # launch variants picked by the library's autotuner for both band counts used below (not timed)
+    tuned = {n: [r for r in pw.autotune(ctx, n, dtype=pw.PW_C128, reps=3) if r["chosen"]] for n in (nb, nb + nbuf)}
 
     # warm-up (also allocates the solver workspace)
     psi = psi0.clone()
@@ -247,6 +249,8 @@ def main():
         "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                    for k, v in stages.items()},
         "n_hpsi": st["n_hpsi"],
+        "autotuned": {str(n): [{"pass": r["pass_"], "kind": r["kind"], "nthr": r["nthr"], "sched": r["sched"],
+                                "us": round(r["ms"] * 1e3, 1)} for r in rs] for n, rs in tuned.items()},
     }
     if not args.no_solve:
         legs = [l for l in SOLVE_LEGS if l[0] in args.solve_legs.split(",")]

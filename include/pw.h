@@ -148,7 +148,10 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * length at compile time, kind 2 the runtime-plan kernel with nthr threads
  * (256, 512 or 1024) and radix schedule sched (0: radices 8 first, 1: radix 4
  * at most, 2: the radices of 0 in ascending order; radix[] lists the z plan or
- * the xy axis-0 plan), kind 0 the built-in default. */
+ * the xy axis-0 plan), kind 0 the built-in default.  Pass 4 (complex128 only)
+ * is the back-projection GEMM: kind 3, sched the tile id, radix[0..1] the tile's
+ * rows and columns, radix[2] the band count it was timed at (the choice applies
+ * to calls with that many bands), nthr its threads. */
 typedef struct {
     int32_t pass;
     int32_t kind;
@@ -160,9 +163,9 @@ typedef struct {
     int32_t chosen;       /* out: 1 for the fastest of its pass */
 } pw_fft_cand;
 
-/* Times every candidate that fits this context's grid on nb (<= max_bands)
- * bands of dtype, reps launches each, and installs the fastest of each pass
- * for later pw_hpsi calls of that dtype.  The records (at most cap) go to
+/* Times every candidate that fits this context's grid (and projector table) on
+ * nb (<= max_bands) bands of dtype, reps launches each, and installs the fastest
+ * of each pass for later pw_hpsi calls of that dtype.  The records (at most cap) go to
  * cands (host), their number to *ncand.  Results are cached per (grid, sphere,
  * dtype, nb) for the process, so equal cells are timed once.  Allocates
  * scratch; synchronises. */

@@ -528,4 +528,8 @@ def fft_choose(ctx, cand, dtype=PW_C128):
     c = pw_fft_cand()
     c.pass_, c.kind, c.nthr, c.sched = int(cand["pass_"]), int(cand["kind"]), int(cand.get("nthr", 0)), \
         int(cand.get("sched", 0))
+    rad = list(cand.get("radix", []))[:12]
+    c.nradix = len(rad)
+    for i, v in enumerate(rad):
+        c.radix[i] = int(v)
     _check(lib().pw_ctx_fft_choose(ctx.handle, int(dtype), C.byref(c)))

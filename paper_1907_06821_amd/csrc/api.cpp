@@ -86,7 +86,7 @@ static void hpsi_c128(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *ou
         }
         ProfScope p(ctx, 4, st);
         zgemm_nn_launch(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->nproj, ctx->d_beta64.p, npw, 1.0, 1.0, out, ldo, st,
-                        true);
+                        true, ctx->nn_tune.get(nb));
     }
 }
 

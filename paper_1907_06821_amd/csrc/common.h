@@ -89,6 +89,25 @@ struct FftChoice {
     int nthr = 0;
     FftPlan p0{}, p1{};
 };
+// back-projection GEMM tile per band count (complex128); -1: chosen by band count
+struct GemmTune {
+    static constexpr int kSlots = 8;
+    int nb[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int id[kSlots] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    int get(int n) const {
+        for (int i = 0; i < kSlots; ++i)
+            if (nb[i] == n) return id[i];
+        return -1;
+    }
+    void set(int n, int v) {
+        int slot = -1;
+        for (int i = 0; i < kSlots && slot < 0; ++i)
+            if (nb[i] == n || nb[i] == 0) slot = i;
+        if (slot < 0) slot = kSlots - 1;
+        nb[slot] = n;
+        id[slot] = v;
+    }
+};
 struct FftTune {
     FftChoice zinv, xy, zfwd;
 };
@@ -149,6 +168,7 @@ struct pw_ctx {
     int64_t device_bytes = 0;
     pw::FftPlan plan[3];
     pw::FftTune tune[2];             // FFT launch choices: [0] complex128, [1] complex64
+    pw::GemmTune nn_tune;            // back-projection GEMM tiles by band count (autotuner)
     int cb = 16;                     // z-columns per workgroup in the z passes
     // device tables
     pw::DevBuf d_kin, d_zmap, d_colpos, d_colstart, d_vz64, d_vz32, d_tw64[3], d_tw32[3];

@@ -384,7 +384,8 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
 // Autotuner: for each pass (z inverse, xy with V, z forward) time every launch
 // variant that fits this grid -- the compile-time length kernel and the
 // runtime-plan kernel for each radix schedule and thread count -- on nb bands
-// and keep the fastest.  Results are cached per (grid, sphere, dtype, nb).
+// and keep the fastest; for complex128 also the back-projection GEMM's tile.
+// Results are cached per (grid, sphere, dtype, nb).
 // ---------------------------------------------------------------------------
 template <typename T> static bool xy_has_ct(int n) {
     switch (n) {
@@ -469,6 +470,7 @@ struct TuneKey {
 };
 struct TuneVal {
     FftTune tune;
+    int nn = -1;
     std::vector<pw_fft_cand> recs;
 };
 std::mutex g_tune_mu;
@@ -486,6 +488,7 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             tune = it->second.tune;
+            if (it->second.nn >= 0) ctx->nn_tune.set(nb, it->second.nn);
             recs = it->second.recs;
             return;
         }
@@ -508,6 +511,7 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
     } guard{e0, e1};
     PW_HIP(hipEventCreate(&e1));
     recs.clear();
+    int nn_best = -1;
     run_pass<T>(ctx, 0, nb, in.p, out.p, s);              // column grid for the xy timings
     for (int pass = 0; pass < 3; ++pass) {
         std::vector<pw_fft_cand> cs = candidates<T>(ctx, pass);
@@ -535,12 +539,52 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
         choice_of<T>(ctx, pass) = c;
         if (pass == 0) run_pass<T>(ctx, 0, nb, in.p, out.p, s);
     }
+    // complex128 back-projection GEMM tiles (pass 4) for this band count
+    if (sizeof(T) == 8 && ctx->nproj > 0 && ctx->d_beta64.p) {
+        const int npw = ctx->basis.npw, K = ctx->nproj;
+        fill_zero(ctx->d_proj.p, (size_t)nb * K * sizeof(double2), s);
+        const size_t first = recs.size();
+        int best = -1;
+        for (int id = 0; id < kNnCfgs; ++id) {
+            pw_fft_cand r{};
+            r.pass = 4;
+            r.kind = 3;
+            r.sched = id;
+            r.nradix = 3;
+            nn_cfg_shape(id, r.radix[0], r.radix[1], r.nthr);
+            r.radix[2] = nb;
+            auto go = [&]() {
+                zgemm_nn_launch(nb, npw, K, ctx->d_proj.p, K, ctx->d_beta64.p, npw, 1.0, 0.0, out.p, npw, s, true, id);
+            };
+            go();
+            PW_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) go();
+            PW_HIP(hipEventRecord(e1, s));
+            PW_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            r.ms = ms / reps;
+            if (best < 0 || r.ms < recs[first + best].ms) best = id;
+            recs.push_back(r);
+        }
+        recs[first + best].chosen = 1;
+        nn_best = best;
+        ctx->nn_tune.set(nb, best);
+    }
     PW_HIP(hipStreamSynchronize(s));
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = TuneVal{tune, recs};
+    g_tune_cache[key] = TuneVal{tune, nn_best, recs};
 }
 
 template <typename T> void fft_choose(pw_ctx *ctx, const pw_fft_cand &r) {
+    if (r.pass == 4) {
+        PW_CHECK(sizeof(T) == 8, PW_EUNSUPPORTED, "GEMM tiles are chosen for complex128 only");
+        PW_CHECK(r.kind == 0 || (r.kind == 3 && r.sched >= 0 && r.sched < kNnCfgs), PW_EUNSUPPORTED,
+                 "GEMM tile candidate unknown");
+        PW_CHECK(r.radix[2] >= 1, PW_EINVAL, "GEMM tile candidate needs its band count in radix[2]");
+        ctx->nn_tune.set(r.radix[2], r.kind == 0 ? -1 : r.sched);
+        return;
+    }
     PW_CHECK(r.pass >= 0 && r.pass <= 2, PW_EINVAL, "FFT pass %d unknown", r.pass);
     FftChoice c;
     PW_CHECK(choice_from<T>(ctx, r, c), PW_EUNSUPPORTED, "FFT launch variant does not fit this grid");

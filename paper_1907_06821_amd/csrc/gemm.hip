@@ -335,8 +335,21 @@ static void nn_go(int nz, bool proj, hipStream_t st, int M, int J, int K, const 
 
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
 // M tiles: 64 (M <= 64), 144 (128 < M <= 144), else 128.
+// NN tile configurations (waves over rows x columns, 16 x 16 blocks per wave)
+// the autotuner chooses between; id: {WM, WJ, BM, BJ}, tile (16 WM BM) x (16 WJ BJ)
+static const int kNnCfg[kNnCfgs][4] = {{2, 2, 2, 2}, {4, 1, 2, 4}, {9, 1, 1, 4}, {4, 2, 2, 2},
+                                       {8, 1, 1, 4}, {4, 1, 2, 2}, {2, 4, 2, 2}};
+
+void nn_cfg_shape(int id, int &tm, int &tj, int &nthr) {
+    PW_CHECK(id >= 0 && id < kNnCfgs, PW_EINVAL, "NN tile %d unknown", id);
+    const int *c = kNnCfg[id];
+    tm = 16 * c[0] * c[2];
+    tj = 16 * c[1] * c[3];
+    nthr = 64 * c[0] * c[1];
+}
+
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
-                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st, bool proj) {
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st, bool proj, int cfg) {
     if (M <= 0 || J <= 0 || nz <= 0) return;
     PW_CHECK(nz <= 4, PW_EINVAL, "at most 4 blocks per batched rotation");
     NNBatch bt{};
@@ -344,17 +357,25 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.X[z] = (const double2 *)X[z];
         bt.Out[z] = (double2 *)Out[z];
     }
-    if (M <= 64) nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
-    else if (M > 128 && M <= 144) nn_go<9, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
-    else nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo);
+    if (cfg < 0) cfg = M <= 64 ? 0 : (M > 128 && M <= 144) ? 2 : 1;
+    switch (cfg) {
+        case 0: nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 1: nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 2: nn_go<9, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 3: nn_go<4, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 4: nn_go<8, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 5: nn_go<4, 1, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 6: nn_go<2, 4, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
+    }
     PW_LAUNCH_CHECK();
 }
 
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
-                     double beta, void *Out, int64_t ldo, hipStream_t st, bool proj) {
+                     double beta, void *Out, int64_t ldo, hipStream_t st, bool proj, int cfg) {
     const void *xs[1] = {X};
     void *os[1] = {Out};
-    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st, proj);
+    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st, proj, cfg);
 }
 
 }  // namespace pw

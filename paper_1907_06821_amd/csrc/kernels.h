@@ -17,10 +17,13 @@ size_t nt_partial_bytes(int M, int N, int K);
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
               hipStream_t, bool proj = false);
+// NN GEMM tile configurations: cfg < 0 picks by M, else one of kNnCfgs (autotuner)
+constexpr int kNnCfgs = 7;
+void nn_cfg_shape(int id, int &tm, int &tj, int &nthr);
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
-                     double beta, void *Out, int64_t ldo, hipStream_t, bool proj = false);
+                     double beta, void *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1);
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
-                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t, bool proj = false);
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1);
 
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
 size_t cnt_partial_bytes(int M, int N, int K);

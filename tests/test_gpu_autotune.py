@@ -41,6 +41,6 @@ def test_every_fft_candidate_matches_oracle(torch_cuda, which):
             got = pw.hpsi(ctx, to_dev(c, tdt), shift=prob.e_ref).cpu().numpy()
             err_ = rel_err(got, ref if dtype == pw.PW_C128 else base)
             assert err_ < tol_var, (r, err_)
-            pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0}, dtype=dtype)
+            pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0, "radix": r["radix"]}, dtype=dtype)
         with pytest.raises(pw.PwError):
             pw.fft_choose(ctx, {"pass_": 1, "kind": 2, "nthr": 100, "sched": 0}, dtype=dtype)
