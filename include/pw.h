@@ -182,9 +182,10 @@ pw_status pw_ctx_fft_choose(pw_ctx *ctx, pw_dtype dtype, const pw_fft_cand *cand
  *   w (device, n) eigenvalues ordered by key (0: ascending, 1: ascending
  *   |w - ref|), R (device, n x n) with row b the eigenvector of w[b] in the input
  *   basis (so a band-major block rotates as Psi' = R . Psi).  Householder
- *   tridiagonalisation + implicit QL; sweeps (host, optional) gets the largest
- *   QL iteration count of one eigenvalue, and PW_ENOCONV is returned if one
- *   exceeds 60.  Synchronises.
+ *   tridiagonalisation, then divide and conquer on the tridiagonal (leaves of at
+ *   most 16 rows by implicit QL, rank-one merges); sweeps (host, optional) gets
+ *   the largest QL iteration count of one leaf eigenvalue, and PW_ENOCONV is
+ *   returned if one exceeds 60.  Synchronises.
  * pw_dense_chol_inv: S = L L^H for Hermitian positive definite S (n x n, lds),
  *   T = conj(L^{-1}) (n x n) so that Psi' = T . Psi has Psi'^H Psi' = I when
  *   S = Psi^H Psi.  Returns PW_ENOTPD if a pivot is not positive.  Synchronises.

@@ -4,8 +4,9 @@
 //                        block Psi' = T . Psi is orthonormal (Gram/Cholesky step).
 //   tridiag_ql_*_kernel + backtransform_kernel: Hermitian eigensolver for the
 //                        Rayleigh-Ritz subspace step (Householder tridiagonalisation,
-//                        implicit QL); outputs the eigenvalues and the band-major
-//                        rotation R with Psi' = R . Psi.
+//                        divide and conquer with implicit QL on the leaves); outputs
+//                        the eigenvalues and the band-major rotation R with
+//                        Psi' = R . Psi.
 // The factorisations run as one workgroup; they are O(N^3) on N x N matrices and
 // off the O(N^2 npw) critical path.
 #include "common.h"
@@ -209,10 +210,9 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
 //    A22 - v w^H - w v^H with w = tau A22 v - (tau/2) ((tau A22 v)^H v) v.
 //    v_k (entries k+1..N-1) is stored at hv + k(N-1) - k(k-1)/2, tau_k at
 //    hv + N(N-1)/2 + k.
-// 2. Implicit QL with Wilkinson's shift on T (the tql2 algorithm of Bowdler,
-//    Martin, Reinsch and Wilkinson, 1968).  Wave 0 runs the scalar recurrence
-//    of the next sweep while the other waves apply the Givens rotations of the
-//    previous one to the rows of Z (double-buffered rotation lists).
+// 2. T = Z diag(d) Z^T by divide and conquer (see dc_block below); its leaves
+//    use implicit QL with Wilkinson's shift (the tql2 algorithm of Bowdler,
+//    Martin, Reinsch and Wilkinson, 1968), one wave per leaf.
 // 3. Eigenvalues ordered by key into lam; Z column m is zg[m N + r], its rank
 //    rank[m]; info = largest QL iteration count of one eigenvalue, -1 if one
 //    needed more than kQlMaxIter.
@@ -220,11 +220,13 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
 // so that R . Psi rotates a band-major block.
 //
 // tridiag_ql_lds_kernel (N <= kLdsMaxN): A as a packed lower triangle in LDS,
-// then Z in the same LDS.  tridiag_ql_global_kernel (N <= kEigMaxN): full A in
-// global memory (rows coalesced), Z in global memory over the dead A.
+// whose space then holds the divide and conquer's scratch; Z, V and the
+// product's temporary in global work memory.  tridiag_ql_global_kernel
+// (N <= kEigMaxN): full A in global memory (rows coalesced), Z and the rest over
+// the dead A.
 // ---------------------------------------------------------------------------
 constexpr int kQlMaxIter = 60;
-constexpr int kEigNT = 1024;
+constexpr int kEigNT = 512;
 constexpr int kEigMaxN = 1024;
 
 __device__ inline double2 lds_get(const double2 *L, int i, int k) {
@@ -375,36 +377,399 @@ __device__ __forceinline__ void ql_apply(double *Zt, int N, int row, int msweep,
     Zt[(int64_t)(msweep - nrot) * N + row] = carry;
 }
 
-// QL on (d, e) with Z (identity on entry) by the whole block, then eigenvalue
-// order.  NMAX sizes the rotation lists.
-template <int NT, int NMAX>
-__device__ __forceinline__ void ql_block(int N, double *d, double *e, double (*cs)[NMAX], double (*sn)[NMAX],
-                                         int (*ctl)[2], double *Zt, double *lam, int *rank, int key, double ref,
-                                         int *info) {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) {
-        ctl[1][0] = -2;                                 // nothing to apply yet
-        ctl[1][1] = 0;
+// ---------------------------------------------------------------------------
+// Divide and conquer on the tridiagonal (Cuppen's rank-one tearing, eigenvectors
+// by the Gu-Eisenstat formula).  T is torn at the boundaries of P = 2^k leaves of
+// at most kDcLeaf rows: T = diag(T_1', ..., T_P') + sum of rank-one terms
+// |beta| w w^T, w = e_{b-1} + sign(beta) e_b, with T_i' = T_i minus |beta| on the
+// torn corners.  Each leaf is solved by the QL sweeps above (one wave per leaf,
+// concurrently); pairs of solved blocks are then merged level by level:
+// diag(D) + rho z z^T with z the last row of the left block's eigenvectors and
+// sign(beta) times the first row of the right block's.  A merge sorts D,
+// deflates (rho |z_j| below tol, or a Givens rotation folding z_j into a nearly
+// equal neighbour), solves the secular equation 1 + rho sum z_j^2/(d_j - x) = 0
+// for each remaining root (one thread per root, safeguarded Newton in the
+// coordinate tau = x - d_origin of the nearer pole, so that d_j - x keeps full
+// relative accuracy), recomputes z from the roots (Gu-Eisenstat) for
+// orthogonal eigenvectors, and forms the block's new eigenvectors Z V.
+// Z (Zt[i N + r] = Z[r][i]), V and the product's temporary are in global memory.
+// ---------------------------------------------------------------------------
+constexpr int kDcLeaf = 16;
+
+// LDS scratch of the divide and conquer for n rows (carved from `base`)
+struct DcLds {
+    double *sD, *sz, *kd, *kz, *tau, *zh, *lamv, *rc, *rs, *beta;
+    double *gz, *gv;        // dc_kc(n)-deep chunks of Z_kept and V for the product
+    int *perm, *flag, *kept, *org, *ri, *rj, *ctl;
+    double *wcs, *wsn;      // per-wave rotation lists of the leaf QL sweeps
+    double *dbl;
+};
+// depth of the product's k chunks: each chunk holds dc_kc(n) n <= 2048 doubles
+__host__ __device__ inline int dc_kc(int n) { return min(16, 2048 / n); }
+// chunks: whether the scratch also holds the two product chunks
+__host__ __device__ inline size_t dc_lds_bytes(int n, int nwaves, bool chunks) {
+    return (size_t)n * (9 * sizeof(double) + 6 * sizeof(int)) + (chunks ? (size_t)2 * dc_kc(n) * n * sizeof(double) : 0) +
+           64 * sizeof(double) + 16 * sizeof(int) +
+           (size_t)nwaves * 2 * kDcLeaf * sizeof(double) + 16 * sizeof(double) + 64;
+}
+// gz, gv: the product chunks if they live elsewhere, else null (carved here)
+__device__ inline DcLds dc_carve(unsigned char *base, int n, int nwaves, double *gz, double *gv) {
+    DcLds t;
+    double *p = reinterpret_cast<double *>(base);
+    t.sD = p; p += n;
+    t.sz = p; p += n;
+    t.kd = p; p += n;
+    t.kz = p; p += n;
+    t.tau = p; p += n;
+    t.zh = p; p += n;
+    t.lamv = p; p += n;
+    t.rc = p; p += n;
+    t.rs = p; p += n;
+    t.beta = p; p += 64;
+    if (gz) {
+        t.gz = gz;
+        t.gv = gv;
+    } else {
+        t.gz = p; p += dc_kc(n) * n;
+        t.gv = p; p += dc_kc(n) * n;
+    }
+    t.wcs = p; p += nwaves * kDcLeaf;
+    t.wsn = p; p += nwaves * kDcLeaf;
+    t.dbl = p; p += 16;
+    int *q = reinterpret_cast<int *>(p);
+    t.perm = q; q += n;
+    t.flag = q; q += n;
+    t.kept = q; q += n;
+    t.org = q; q += n;
+    t.ri = q; q += n;
+    t.rj = q; q += n;
+    t.ctl = q;
+    return t;
+}
+
+// 1/x: hardware reciprocal estimate refined by two Newton steps (about 1 ulp)
+__device__ inline double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// sum over the G consecutive lanes of a group
+template <int G> __device__ inline double group_sum(double x) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+    return x;
+}
+
+// root i of 1 + rho sum_j z_j^2 / (d_j - x) (d ascending, z_j != 0) by a group of
+// G lanes (lane `sub` sums the terms j = sub mod G): the nearer pole's index in
+// *org, tau = x - d[*org] returned.  Newton on h(tau) = (d_org - x) g(x), which has
+// no pole at the origin, safeguarded by the bracket; the first iterate is h's
+// linearisation at tau = 0.
+template <int G>
+__device__ inline double secular_root(int i, int K, const double *d, const double *z, double rho, int sub, int *org) {
+    double lo, hi;
+    int o;
+    if (i < K - 1) {
+        const double mid = 0.5 * (d[i] + d[i + 1]);
+        double f = 0.0;
+        for (int j = sub; j < K; j += G) f += rho * z[j] * z[j] * rcp64(d[j] - mid);
+        f = 1.0 + group_sum<G>(f);
+        if (f > 0.0) {
+            o = i;
+            lo = 0.0;
+            hi = mid - d[i];
+        } else {
+            o = i + 1;
+            lo = mid - d[i + 1];
+            hi = 0.0;
+        }
+    } else {
+        o = K - 1;
+        double zz = 0.0;
+        for (int j = sub; j < K; j += G) zz += z[j] * z[j];
+        lo = 0.0;
+        hi = rho * group_sum<G>(zz);
+    }
+    const double dorg = d[o], rzo = rho * z[o] * z[o];
+    double s0 = 0.0;
+    for (int j = sub; j < K; j += G)
+        if (j != o) s0 += rho * z[j] * z[j] * rcp64(d[j] - dorg);
+    s0 = 1.0 + group_sum<G>(s0);
+    double tau = s0 != 0.0 ? rzo / s0 : 0.5 * (lo + hi);
+    if (!(tau > lo && tau < hi)) tau = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double sv = 0.0, sp = 0.0;
+        for (int j = sub; j < K; j += G) {
+            if (j == o) continue;
+            const double inv = rcp64((d[j] - dorg) - tau);
+            const double t = rho * z[j] * z[j] * inv;
+            sv += t;
+            sp += t * inv;
+        }
+        sv = 1.0 + group_sum<G>(sv);
+        sp = group_sum<G>(sp);
+        const double h = rzo - tau * sv, hp = -sv - tau * sp;
+        const bool below = tau > 0.0 ? h > 0.0 : (tau < 0.0 && h < 0.0);   // g(tau) < 0: root above tau
+        if (below) lo = tau;
+        else hi = tau;
+        double tn = hp != 0.0 ? tau - h / hp : 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        const bool done = fabs(tn - tau) <= 2.0 * DBL_EPSILON * fabs(tn) ||
+                          hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi));
+        tau = tn;
+        if (done) break;
+    }
+    *org = o;
+    return tau;
+}
+
+// merge the solved blocks [a, b) and [b, c) (whole workgroup)
+template <int NT>
+__device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V, double *Ztmp,
+                         const DcLds &t) {
+    const int tid = threadIdx.x;
+    const int n = c - a;
+    const double rho = fabs(beta), sg = beta >= 0.0 ? 1.0 : -1.0;
+    // z and the ascending order of the block's eigenvalues
+    for (int j = tid; j < n; j += NT) {
+        const int col = a + j;
+        const double zj = col < b ? Zt[(int64_t)col * N + (b - 1)] : sg * Zt[(int64_t)col * N + b];
+        const double dj = d[col];
+        int rk = 0;
+        for (int k = 0; k < n; ++k) {
+            const double dk = d[a + k];
+            if (dk < dj || (dk == dj && k < j)) ++rk;
+        }
+        t.sD[rk] = dj;
+        t.sz[rk] = zj;
+        t.perm[rk] = col;
     }
     __syncthreads();
-    int l = 0, iter = 0, maxiter = 0;
-    bool fail = false;
-    for (int b = 0;; b ^= 1) {
-        if (wid == 0) {
-            int nrot;
-            const int ms = ql_sweep(N, d, e, cs[b], sn[b], l, iter, maxiter, fail, lane, nrot);
-            if (lane == 0) {
-                ctl[b][0] = ms;
-                ctl[b][1] = nrot;
-            }
-        } else {
-            const int pm = ctl[b ^ 1][0], pn = ctl[b ^ 1][1];
-            if (pm >= 0 && pn > 0)
-                for (int row = tid - 64; row < N; row += NT - 64) ql_apply(Zt, N, row, pm, pn, cs[b ^ 1], sn[b ^ 1]);
+    // deflation (one thread, in ascending order)
+    if (tid == 0) {
+        double nz = 0.0, dmax = 0.0;
+        for (int j = 0; j < n; ++j) {
+            nz += t.sz[j] * t.sz[j];
+            dmax = fmax(dmax, fabs(t.sD[j]));
         }
-        __syncthreads();
-        if (ctl[b][0] < 0) break;
+        nz = sqrt(nz);
+        const double rhon = rho * nz * nz;
+        const double tol = 8.0 * DBL_EPSILON * fmax(dmax, rhon);
+        for (int j = 0; j < n; ++j) t.sz[j] /= nz;
+        int pj = -1, nrot = 0;
+        for (int j = 0; j < n; ++j) {
+            t.flag[j] = 0;
+            if (rhon * fabs(t.sz[j]) <= tol) {
+                t.flag[j] = 1;
+                continue;
+            }
+            if (pj < 0) {
+                pj = j;
+                continue;
+            }
+            const double h = hypot(t.sz[pj], t.sz[j]);
+            const double cc = t.sz[j] / h, ss = t.sz[pj] / h;
+            if (fabs((t.sD[j] - t.sD[pj]) * cc * ss) <= tol) {
+                t.ri[nrot] = pj;
+                t.rj[nrot] = j;
+                t.rc[nrot] = cc;
+                t.rs[nrot] = ss;
+                ++nrot;
+                const double dp = t.sD[pj], dq = t.sD[j];
+                t.sD[pj] = dp * cc * cc + dq * ss * ss;
+                t.sD[j] = dp * ss * ss + dq * cc * cc;
+                t.sz[pj] = 0.0;
+                t.sz[j] = h;
+                t.flag[pj] = 1;
+            }
+            pj = j;
+        }
+        int K = 0;
+        for (int j = 0; j < n; ++j)
+            if (!t.flag[j]) {
+                t.kept[K] = j;
+                t.kd[K] = t.sD[j];
+                t.kz[K] = t.sz[j];
+                ++K;
+            }
+        t.ctl[0] = K;
+        t.ctl[1] = nrot;
+        t.dbl[0] = rhon;
     }
+    __syncthreads();
+    const int K = t.ctl[0], nrot = t.ctl[1];
+    const double rhon = t.dbl[0];
+    // the deflation's rotations act on the block's eigenvector columns, row by row
+    for (int r = a + tid; r < c; r += NT)
+        for (int q = 0; q < nrot; ++q) {
+            double *zp = Zt + (int64_t)t.perm[t.ri[q]] * N + r;
+            double *zq = Zt + (int64_t)t.perm[t.rj[q]] * N + r;
+            const double x = *zp, y = *zq;
+            *zp = t.rc[q] * x - t.rs[q] * y;
+            *zq = t.rs[q] * x + t.rc[q] * y;
+        }
+    // roots of the secular equation, four lanes each; flag of a kept position = -(root + 1)
+    {
+        constexpr int G = 4;
+        const int sub = tid % G;
+        for (int i = tid / G; i < K; i += NT / G) {
+            int o;
+            const double tv = secular_root<G>(i, K, t.kd, t.kz, rhon, sub, &o);
+            if (sub == 0) {
+                t.tau[i] = tv;
+                t.org[i] = o;
+                t.flag[t.kept[i]] = -(i + 1);
+            }
+        }
+    }
+    __syncthreads();
+    // z recomputed from the roots: zh_j^2 = prod_i (x_i - d_j) / (rho prod_{i != j} (d_i - d_j))
+    for (int j = tid; j < K; j += NT) {
+        double w = 1.0;
+        for (int i = 0; i < K; ++i) {
+            const double xi = (t.kd[t.org[i]] - t.kd[j]) + t.tau[i];
+            w *= i == j ? xi : xi * rcp64(t.kd[i] - t.kd[j]);
+        }
+        t.zh[j] = copysign(sqrt(fmax(w, 0.0) / rhon), t.kz[j]);
+    }
+    // eigenvalues in ascending (sorted) position; deflated ones keep their D
+    for (int j = tid; j < n; j += NT) t.lamv[j] = t.sD[j];
+    __syncthreads();
+    for (int i = tid; i < K; i += NT) t.lamv[t.kept[i]] = t.kd[t.org[i]] + t.tau[i];
+    // eigenvectors of diag(D) + rho z z^T on the kept set: V[i][j] = zh_j / (d_j - x_i), normalised
+    for (int i = tid; i < K; i += NT) {
+        const int o = t.org[i];
+        const double ti = t.tau[i], dorg = t.kd[o];
+        double nrm = 0.0;
+        for (int j = 0; j < K; ++j) {
+            const double v = t.zh[j] * rcp64((t.kd[j] - dorg) - ti);
+            V[(int64_t)i * K + j] = v;
+            nrm += v * v;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int j = 0; j < K; ++j) V[(int64_t)i * K + j] *= inv;
+    }
+    __syncthreads();
+    // new columns in ascending order: deflated ones copied, kept ones (Z_kept V^T):
+    // k chunks of Z_kept (rows of the block) and V staged in LDS, each thread
+    // accumulating 4 x 4 tiles of the product
+    for (int e = tid; e < n * n; e += NT) {
+        const int tcol = e / n;
+        if (t.flag[tcol] > 0) Ztmp[e] = Zt[(int64_t)t.perm[tcol] * N + a + e % n];
+    }
+    {
+        constexpr int RT = 4;
+        const int KC = dc_kc(N);
+        double *zc = t.gz, *vc = t.gv;                    // [KC][n], [KC][K]
+        const int nr = (n + RT - 1) / RT, nc = (K + RT - 1) / RT;
+        for (int k0 = 0; k0 < K; k0 += KC) {
+            const int kc = min(KC, K - k0);
+            for (int e = tid; e < kc * n; e += NT) {
+                const int jj = e / n, r = e % n;
+                zc[jj * n + r] = Zt[(int64_t)t.perm[t.kept[k0 + jj]] * N + a + r];
+            }
+            for (int e = tid; e < K * kc; e += NT) {
+                const int i = e / kc, jj = e % kc;
+                vc[jj * K + i] = V[(int64_t)i * K + k0 + jj];
+            }
+            __syncthreads();
+            for (int tile = tid; tile < nr * nc; tile += NT) {
+                const int r0 = (tile % nr) * RT, c0 = (tile / nr) * RT;
+                double acc[RT][RT];
+#pragma unroll
+                for (int x = 0; x < RT; ++x)
+#pragma unroll
+                    for (int y = 0; y < RT; ++y) acc[x][y] = 0.0;
+                if (k0 > 0) {
+#pragma unroll
+                    for (int x = 0; x < RT; ++x)
+#pragma unroll
+                        for (int y = 0; y < RT; ++y)
+                            if (r0 + x < n && c0 + y < K) acc[x][y] = Ztmp[(int64_t)t.kept[c0 + y] * n + r0 + x];
+                }
+                for (int jj = 0; jj < kc; ++jj) {
+                    double zr[RT], vr[RT];
+#pragma unroll
+                    for (int x = 0; x < RT; ++x) zr[x] = r0 + x < n ? zc[jj * n + r0 + x] : 0.0;
+#pragma unroll
+                    for (int y = 0; y < RT; ++y) vr[y] = c0 + y < K ? vc[jj * K + c0 + y] : 0.0;
+#pragma unroll
+                    for (int x = 0; x < RT; ++x)
+#pragma unroll
+                        for (int y = 0; y < RT; ++y) acc[x][y] = fma(zr[x], vr[y], acc[x][y]);
+                }
+#pragma unroll
+                for (int x = 0; x < RT; ++x)
+#pragma unroll
+                    for (int y = 0; y < RT; ++y)
+                        if (r0 + x < n && c0 + y < K) Ztmp[(int64_t)t.kept[c0 + y] * n + r0 + x] = acc[x][y];
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < n * n; e += NT) {
+        const int tcol = e / n, r = e % n;
+        Zt[(int64_t)(a + tcol) * N + a + r] = Ztmp[e];
+    }
+    for (int j = tid; j < n; j += NT) d[a + j] = t.lamv[j];
+    __syncthreads();
+}
+
+// Eigen-decomposition of the tridiagonal (d, e) into d (eigenvalues) and Zt
+// (global), then eigenvalue order.  e is overwritten.
+template <int NT>
+__device__ void dc_block(int N, double *d, double *e, double *Zt, double *V, double *Ztmp, unsigned char *scratch,
+                         double *gz, double *gv, double *lam, int *rank, int key, double ref, int *info) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const DcLds t = dc_carve(scratch, N, NW, gz, gv);
+    int P = 1;
+    while ((N + P - 1) / P > kDcLeaf) P *= 2;
+    for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
+    if (tid == 0) {
+        for (int i = 1; i < P; ++i) {
+            const int bb = (int)((int64_t)i * N / P);
+            const double be = e[bb - 1];
+            t.beta[i] = be;
+            d[bb - 1] -= fabs(be);
+            d[bb] -= fabs(be);
+            e[bb - 1] = 0.0;
+        }
+        t.ctl[2] = 0;                                       // largest QL iteration count
+        t.ctl[3] = 0;                                       // a leaf failed to converge
+    }
+    __syncthreads();
+    // leaves: implicit QL, one wave per leaf
+    for (int leaf = wid; leaf < P; leaf += NW) {
+        const int a = (int)((int64_t)leaf * N / P), b = (int)((int64_t)(leaf + 1) * N / P);
+        const int n = b - a;
+        double *cs = t.wcs + wid * kDcLeaf, *sn = t.wsn + wid * kDcLeaf;
+        int l = 0, iter = 0, maxiter = 0;
+        bool fail = false;
+        for (;;) {
+            int nrot;
+            const int ms = ql_sweep(n, d + a, e + a, cs, sn, l, iter, maxiter, fail, lane, nrot);
+            if (ms < 0) break;
+            if (lane < n && nrot > 0) ql_apply(Zt + (int64_t)a * N + a, N, lane, ms, nrot, cs, sn);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane == 0) {
+            atomicMax(&t.ctl[2], maxiter);
+            if (fail) t.ctl[3] = 1;
+        }
+    }
+    __syncthreads();
+    // merges, level by level
+    for (int span = 2; span <= P; span *= 2)
+        for (int k = 0; k < P; k += span) {
+            const int a = (int)((int64_t)k * N / P), b = (int)((int64_t)(k + span / 2) * N / P);
+            const int c = (int)((int64_t)(k + span) * N / P);
+            const double be = t.beta[k + span / 2];
+            if (be != 0.0) dc_merge<NT>(N, a, b, c, be, d, Zt, V, Ztmp, t);
+        }
     for (int i = tid; i < N; i += NT) {
         const double li = d[i];
         const double ki = key ? fabs(li - ref) : li;
@@ -417,7 +782,7 @@ __device__ __forceinline__ void ql_block(int N, double *d, double *e, double (*c
         lam[rk] = li;
         rank[i] = rk;
     }
-    if (tid == 0 && info) info[0] = fail ? -1 : maxiter;
+    if (tid == 0 && info) info[0] = t.ctl[3] ? -1 : t.ctl[2];
 }
 
 template <int NT>
@@ -427,11 +792,9 @@ __global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2
                                                             double ref, int *__restrict__ info) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);     // packed lower triangle of A
-    double *Zt = reinterpret_cast<double *>(smem_raw);      // afterwards: Zt[i N + r] = Z[r][i]
     __shared__ double2 v[kLdsMaxN], w[kLdsMaxN];
-    __shared__ double d[kLdsMaxN], e[kLdsMaxN], cs[2][kLdsMaxN], sn[2][kLdsMaxN];
+    __shared__ double d[kLdsMaxN], e[kLdsMaxN];
     __shared__ double2 sc[3][2];                            // tau, 1/(alpha - beta), w correction; by parity of k
-    __shared__ int ctl[2][2];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ntri = N * (N + 1) / 2;
     const int tau_off = N * (N - 1) / 2;
@@ -516,9 +879,9 @@ __global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2
         e[N - 1] = 0.0;
     }
     __syncthreads();
-    for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
-    ql_block<NT, kLdsMaxN>(N, d, e, cs, sn, ctl, Zt, lam, rank, key, ref, info);
-    for (int q = tid; q < N * N; q += NT) zg[q] = Zt[q];
+    // the triangle is dead: its LDS becomes the divide and conquer's scratch
+    dc_block<NT>(N, d, e, zg, zg + (size_t)N * N, zg + 2 * (size_t)N * N, smem_raw, nullptr, nullptr, lam, rank, key,
+                 ref, info);
 }
 
 // Same algorithm for N <= kEigMaxN.  Ag: N x N work copy of A (full Hermitian,
@@ -528,10 +891,10 @@ __global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const doub
                                                                double2 *__restrict__ Ag, double2 *__restrict__ hv,
                                                                int *__restrict__ rank, double *__restrict__ lam,
                                                                int key, double ref, int *__restrict__ info) {
+    extern __shared__ unsigned char smem_raw[];            // the divide and conquer's scratch
     __shared__ double2 v[kEigMaxN], w[kEigMaxN];
-    __shared__ double d[kEigMaxN], e[kEigMaxN], cs[2][kEigMaxN], sn[2][kEigMaxN];
+    __shared__ double d[kEigMaxN], e[kEigMaxN];
     __shared__ double2 sc[3][2];
-    __shared__ int ctl[2][2];
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int tau_off = N * (N - 1) / 2;
@@ -612,10 +975,11 @@ __global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const doub
         e[N - 1] = 0.0;
     }
     __syncthreads();
+    // A is dead: its storage holds Z and the product's temporary, V follows it;
+    // the reflector staging v, w (2048 doubles each) holds the product chunks
     double *Zt = reinterpret_cast<double *>(Ag);
-    for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
-    __syncthreads();
-    ql_block<NT, kEigMaxN>(N, d, e, cs, sn, ctl, Zt, lam, rank, key, ref, info);
+    dc_block<NT>(N, d, e, Zt, Zt + 2 * (size_t)N * N, Zt + (size_t)N * N, smem_raw, reinterpret_cast<double *>(v),
+                 reinterpret_cast<double *>(w), lam, rank, key, ref, info);
 }
 
 // Back-transformation, one wave per eigenvector, NW waves per workgroup.
@@ -704,20 +1068,23 @@ void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *statu
     PW_LAUNCH_CHECK();
 }
 
-size_t dense_eigh_work_bytes(int N) { return (size_t)32 * N * N; }
+size_t dense_eigh_work_bytes(int N) {
+    // reflectors and taus, then 3 N^2 doubles (Z, V, the product's temporary; or the
+    // N x N complex copy of A followed by V), then the ranks
+    return ((size_t)N * (N - 1) / 2 + N) * sizeof(double2) + (size_t)24 * N * N + (size_t)4 * N + 256;
+}
 
 void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void *R, int key, double ref, int *info,
                 hipStream_t st) {
     PW_CHECK(N >= 1 && N <= kEigMaxN, PW_EUNSUPPORTED, "dense eigensolver limited to 1 <= N <= 1024");
-    // work: reflectors and taus, then Z (N^2 real; for N > kLdsMaxN the N x N
-    // complex copy of A that Z overwrites), then the ranks: 24 N^2 + 12 N bytes at most
     const bool lds = N <= kLdsMaxN;
     double2 *hv = (double2 *)work;
     double2 *zbuf = hv + ((size_t)N * (N - 1) / 2 + N);
-    int *rank = (int *)((char *)zbuf + (size_t)N * N * (lds ? 8 : 16));
-    static size_t attr1 = 64 * 1024, attr2 = 64 * 1024;
+    int *rank = (int *)((char *)zbuf + (size_t)24 * N * N);
+    const size_t dcb = dc_lds_bytes(N, kEigNT / 64, lds);
+    static size_t attr1 = 64 * 1024, attr2 = 64 * 1024, attr3 = 64 * 1024;
     if (lds) {
-        const size_t b1 = std::max((size_t)N * (N + 1) / 2 * sizeof(double2), (size_t)N * N * sizeof(double));
+        const size_t b1 = std::max((size_t)N * (N + 1) / 2 * sizeof(double2), dcb);
         lds_limit(reinterpret_cast<const void *>(tridiag_ql_lds_kernel<kEigNT>), b1, attr1);
         hipLaunchKernelGGL(tridiag_ql_lds_kernel<kEigNT>, dim3(1), dim3(kEigNT), b1, st, N, (const double2 *)A, lda,
                            hv, (double *)zbuf, rank, lam, key, ref, info);
@@ -728,7 +1095,8 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
                            dim3(64 * kBackNW), b2, st, N, (const double2 *)hv, (const double *)zbuf,
                            (const int *)rank, (double2 *)R);
     } else {
-        hipLaunchKernelGGL(tridiag_ql_global_kernel<kEigNT>, dim3(1), dim3(kEigNT), 0, st, N, (const double2 *)A,
+        lds_limit(reinterpret_cast<const void *>(tridiag_ql_global_kernel<kEigNT>), dcb, attr3);
+        hipLaunchKernelGGL(tridiag_ql_global_kernel<kEigNT>, dim3(1), dim3(kEigNT), dcb, st, N, (const double2 *)A,
                            lda, zbuf, hv, rank, lam, key, ref, info);
         PW_LAUNCH_CHECK();
         hipLaunchKernelGGL((backtransform_kernel<kBackNW, kEigMaxN, false>), dim3((N + kBackNW - 1) / kBackNW),

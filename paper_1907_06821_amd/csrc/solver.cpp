@@ -55,14 +55,14 @@ static Solver *solver_get(pw_ctx *ctx, int nb, bool mixed) {
         DevBuf *blocks[] = {&s->X, &s->Y, &s->AX, &s->P, &s->YP, &s->AP, &s->G, &s->Z, &s->T1, &s->T2, &s->T3};
         for (DevBuf *d : blocks) d->alloc(blk);
         const size_t nn = (size_t)s->nbmax * s->nbmax * 16;
-        s->small.alloc(6 * nn);
+        s->small.alloc(4 * nn + dense_eigh_work_bytes(s->nbmax));
         s->vec.alloc((size_t)s->nbmax * 8 * 24);
         s->nsplit = band_splits(npw);
         s->red.alloc((size_t)4 * s->nbmax * s->nsplit * 8);
         s->status.alloc(256);
         s->ftab.alloc((size_t)ctx->basis.shell_t.size() * s->nbmax * sizeof(float));
         ctx->solver = s;
-        ctx->device_bytes += (int64_t)(11 * blk + 6 * nn + s->vec.bytes + s->red.bytes + 256);
+        ctx->device_bytes += (int64_t)(11 * blk + s->small.bytes + s->vec.bytes + s->red.bytes + 256);
     }
     if (mixed && !s->P32.p) {
         const size_t blk32 = (size_t)s->nbmax * npw * 8;

@@ -32,7 +32,9 @@ def test_dense_eigh_random(torch_cuda, n):
     assert sweeps <= 12
 
 
-def test_dense_eigh_near_diagonal_is_quick(torch_cuda):
+def test_dense_eigh_near_diagonal(torch_cuda):
+    """A nearly converged Rayleigh-Ritz matrix (what late solver checks see): small
+    eigenvalues to absolute 1e-15 and eigenvectors to 1e-12."""
     import torch
     import paper_1907_06821_amd as pw
     n = 128
@@ -41,9 +43,32 @@ def test_dense_eigh_near_diagonal_is_quick(torch_cuda):
     e = 1e-9 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
     a = d + e + e.conj().T
     w, r, sweeps = pw.dense_eigh(torch.from_numpy(a).to("cuda"))
-    print("near-diagonal sweeps", sweeps)
+    print("near-diagonal QL iterations", sweeps)
     assert np.max(np.abs(w.cpu().numpy() - np.linalg.eigvalsh(a))) < 1e-15
-    assert sweeps <= 4
+    v = r.cpu().numpy().T
+    assert np.max(np.abs(a @ v - v * w.cpu().numpy()[None, :])) < 1e-15
+    assert np.max(np.abs(v.conj().T @ v - np.eye(n))) < 1e-12
+    assert 0 <= sweeps <= 10
+
+
+@pytest.mark.parametrize("n", [136, 512])
+def test_dense_eigh_folded_clusters(torch_cuda, n):
+    """The spectrum a folded Rayleigh-Ritz matrix has: pairs (x - E)^2 of states
+    either side of E nearly coincide, plus an exact degeneracy."""
+    import torch
+    import paper_1907_06821_amd as pw
+    rng = np.random.default_rng(n + 1)
+    x = np.sort(rng.uniform(-0.4, 0.4, n // 2))
+    w_ref = np.sort(np.concatenate([x ** 2, (x + 1e-9) ** 2]))
+    w_ref[5] = w_ref[4]                                  # an exact double eigenvalue
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    a = (q * w_ref) @ q.conj().T
+    w, r, _ = pw.dense_eigh(torch.from_numpy(a).to("cuda"))
+    w = w.cpu().numpy()
+    v = r.cpu().numpy().T
+    assert np.max(np.abs(w - w_ref)) < 1e-14
+    assert np.max(np.abs(a @ v - v * w[None, :])) < 1e-13
+    assert np.max(np.abs(v.conj().T @ v - np.eye(n))) < 1e-12
 
 
 def test_dense_eigh_key_orders_by_distance(torch_cuda):
