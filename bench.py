@@ -77,10 +77,11 @@ def cpu_baseline(prob, nb_sample=64, iters=2):
                       f"Rayleigh-Ritz, {r['n_hpsi']} band-Hpsi in {dt:.1f} s"}
 
 
-def measured_traffic(stage, mixed, nb):
+def measured_traffic(stage, mixed, nb, nn_cfg):
     """HBM bytes per launch of the dominant stage from the committed counter runs
     (FETCH_SIZE / WRITE_SIZE, copy-calibrated), if they were taken on this
-    workload and the kernel source has not changed since; else None."""
+    workload, on the launch variant the autotuner picked here (nn_cfg: its
+    back-projection tile) and the kernel source has not changed since; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "wire256_fp64_traffic.json")
     if mixed or nb != 128 or not os.path.exists(path):
@@ -88,12 +89,15 @@ def measured_traffic(stage, mixed, nb):
     with open(path) as f:
         rec = json.load(f)
     src = os.path.join(ROOT, rec["source"])
-    if rec["stage"] != stage or not os.path.exists(src):
+    st = rec["stages"].get(stage)
+    if st is None or not os.path.exists(src):
+        return None
+    if st["nn_cfg"] is not None and st["nn_cfg"] != nn_cfg:
         return None
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
             return None
-    return rec["bytes_per_launch"]
+    return st["bytes_per_launch"]
 
 
 SOLVE_LEGS = (("fp64_tpa", 0, 0), ("fp64_mg", 0, 1), ("mixed_tpa", 1, 0), ("mixed_mg", 1, 1),
@@ -226,7 +230,9 @@ def main():
     dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches"])
     d = stages[dom]
     roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
-                "frac": round(d["frac"], 4), "traffic": measured_traffic(dom, mixed, nb), "kernel": dom}
+                "frac": round(d["frac"], 4), "kernel": dom,
+                "traffic": measured_traffic(dom, mixed, nb, next((r["sched"] for r in tuned[nb] if r["pass_"] == 4),
+                                                                 None))}
 
     line = {
         "metric": "band-Hψ/sec and folded-CG time to residual 1e-6 (mixed+learned vs FP64)",
