@@ -148,10 +148,14 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * length at compile time, kind 2 the runtime-plan kernel with nthr threads
  * (256, 512 or 1024) and radix schedule sched (0: radices 8 first, 1: radix 4
  * at most, 2: the radices of 0 in ascending order; radix[] lists the z plan or
- * the xy axis-0 plan), kind 0 the built-in default.  Pass 4 (complex128 only)
+ * the xy axis-0 plan), for pass 1 on planes of 16, 32, 48 or 64 points a side
+ * kind 3 the four-lane register kernel with nthr threads (128, 192 or 256; the
+ * default there), kind 0 the built-in default.  Pass 4 (complex128 only)
  * is the back-projection GEMM: kind 3, sched the tile id, radix[0..1] the tile's
  * rows and columns, radix[2] the band count it was timed at (the choice applies
- * to calls with that many bands), nthr its threads. */
+ * to calls with that many bands), nthr its threads.  Pass 5 (complex128 only),
+ * in the same form, is the block-rotation GEMM of the solver (an nb x nb matrix
+ * times the nb-band block). */
 typedef struct {
     int32_t pass;
     int32_t kind;

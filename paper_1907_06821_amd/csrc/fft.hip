@@ -10,7 +10,9 @@
 //                      sphere, fused with the kinetic term (T_G - shift) c(G)
 // Only the z-columns that touch the sphere travel through HBM.  Common grid
 // lengths are compiled with their radices built in (CtLen); other lengths use the
-// run-time plan (RtLen).  A context can carry per-pass launch choices (kernel
+// run-time plan (RtLen).  Planes of 16, 32, 48 or 64 points a side take the
+// four-lane xy kernel (xy_quad) by default: each 1D transform lives in the
+// registers of four lanes, exchanging through DPP quad permutes.  A context can carry per-pass launch choices (kernel
 // kind, radix schedule, threads) picked by the autotuner at the end of this file.
 #include "fft_core.h"
 #include "kernels.h"
@@ -174,6 +176,217 @@ __global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// xy pass with four lanes per transform (MODE 0, n0 == n1 == L = 4 M, M in
+// {4, 8, 12, 16}).  A length-L DFT splits as L = 4 x M:
+//   quad_a: lane q holds x[q + 4 m] (m < M): M-point DFT over m in registers,
+//           twiddle exp(s 2 pi i q k / L), 4-point DFT across the quad (DPP
+//           exchanges, decimation in frequency); lane q then holds
+//           X[k + M rho(q)], rho = the 2-bit reversal.
+//   quad_b: lane q holds x[n + M rho(q)] (n < M): 4-point DFT across the quad
+//           (decimation in time), twiddle exp(s 2 pi i n q / L), M-point DFT in
+//           registers; lane q then holds X[q + 4 k].
+// quad_a's output layout is quad_b's input layout, so the x transforms run
+// inverse -> V(r) -> forward in registers.  Per plane: zero the touched rows,
+// scatter the columns, y inverse on the touched rows, x inverse . V . x forward
+// per y, y forward on the touched rows, gather: five barriers in all.
+// ---------------------------------------------------------------------------
+template <int N> struct CosTab;
+template <> struct CosTab<12> {
+    static constexpr double c[12] = {1.0, 0.86602540378443864676, 0.5, 0.0, -0.5, -0.86602540378443864676,
+                                     -1.0, -0.86602540378443864676, -0.5, 0.0, 0.5, 0.86602540378443864676};
+};
+template <> struct CosTab<16> {
+    static constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                     0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                     -1.0, -0.92387953251128675613, -0.70710678118654752440,
+                                     -0.38268343236508977173, 0.0, 0.38268343236508977173, 0.70710678118654752440,
+                                     0.92387953251128675613};
+};
+
+// exp(S 2 pi i t / N)
+template <typename T, int N, int S> __device__ inline cplx<T> wconst(int t) {
+    return cmake<T>((T)CosTab<N>::c[t % N], (T)(S * CosTab<N>::c[(t + 3 * N / 4) % N]));
+}
+
+// in-register DFT of length P Q: index b + P a in, c + Q d out
+template <typename T, int P, int Q, int S> __device__ inline void dft_pq(cplx<T> *v) {
+    constexpr int M = P * Q;
+    cplx<T> t[P][Q];
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+        cplx<T> u[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) u[a] = v[b + P * a];
+        Dft<T, Q>::run(u, S);
+#pragma unroll
+        for (int c = 0; c < Q; ++c) t[b][c] = (b > 0 && c > 0) ? cmul<T>(u[c], wconst<T, M, S>(b * c)) : u[c];
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        cplx<T> u[P];
+#pragma unroll
+        for (int b = 0; b < P; ++b) u[b] = t[b][c];
+        Dft<T, P>::run(u, S);
+#pragma unroll
+        for (int d = 0; d < P; ++d) v[c + Q * d] = u[d];
+    }
+}
+
+template <typename T, int M, int S> __device__ inline void reg_dft(cplx<T> *v) {
+    if constexpr (M == 4) Dft<T, 4>::run(v, S);
+    else if constexpr (M == 8) Dft<T, 8>::run(v, S);
+    else if constexpr (M == 12) dft_pq<T, 3, 4, S>(v);
+    else {
+        static_assert(M == 16, "register DFT length");
+        dft_pq<T, 4, 4, S>(v);
+    }
+}
+
+// value of lane (this lane's quad position permuted by quad_perm CTRL)
+// (every lane of a quad is active wherever these run, so no lane reads an inactive one)
+template <int CTRL> __device__ inline float quad_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ inline double quad_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kQuadXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+
+// radix-2 step across lane pairs q, q ^ BIT: the lane with BIT clear keeps
+// own + partner, the other partner - own
+template <typename T, int M, int CTRL, int BIT> __device__ inline void quad_bfly(cplx<T> *v, int q) {
+    const T sg = (q & BIT) ? (T)-1 : (T)1;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const T px = quad_mov<CTRL>(v[k].x), py = quad_mov<CTRL>(v[k].y);
+        v[k] = cmake<T>(px + sg * v[k].x, py + sg * v[k].y);
+    }
+}
+
+// lane 3 of the quad multiplies by exp(S 2 pi i / 4) = S i
+template <typename T, int M, int S> __device__ inline void quad_w4(cplx<T> *v, int q) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = q == 3 ? mul_si<T>(v[k], S) : v[k];
+}
+
+// v[k] *= exp(S 2 pi i q k / L) from the table tw[t] = exp(-2 pi i t / L)
+template <typename T, int M, int S> __device__ inline void quad_tw(cplx<T> *v, const cplx<T> *tw, int q) {
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+        const cplx<T> w = tw[q * k];
+        v[k] = S > 0 ? cmulc<T>(v[k], w) : cmul<T>(v[k], w);
+    }
+}
+
+template <typename T, int M, int S> __device__ inline void quad_a(cplx<T> *v, const cplx<T> *tw, int q) {
+    reg_dft<T, M, S>(v);
+    quad_tw<T, M, S>(v, tw, q);
+    quad_bfly<T, M, kQuadXor2, 2>(v, q);
+    quad_w4<T, M, S>(v, q);
+    quad_bfly<T, M, kQuadXor1, 1>(v, q);
+}
+
+template <typename T, int M, int S> __device__ inline void quad_b(cplx<T> *v, const cplx<T> *tw, int q) {
+    quad_bfly<T, M, kQuadXor1, 1>(v, q);
+    quad_w4<T, M, S>(v, q);
+    quad_bfly<T, M, kQuadXor2, 2>(v, q);
+    quad_tw<T, M, S>(v, tw, q);
+    reg_dft<T, M, S>(v);
+}
+
+template <typename T, int M, int NTHR>
+__global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ cols) {
+    constexpr int L = 4 * M, RS = L + 1, NQ = NTHR / 4;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);   // [L]
+    cplx<T> *pl = tw + L;                                   // [L][RS]
+    const int z = blockIdx.x, b = blockIdx.y;
+    const int tid = threadIdx.x, q = tid & 3, quad = tid >> 2;
+    const int rq = ((q & 1) << 1) | (q >> 1);
+    const int nrows = a.nrows, rowlo = a.rowlo;
+    cplx<T> *crow = cols + ((int64_t)b * a.n2 + z) * a.ncols;
+    // the first CPF columns per thread are loaded before the zeroing, so that their
+    // latency overlaps it
+    constexpr int CPF = 4;
+    cplx<T> cv[CPF];
+#pragma unroll
+    for (int j = 0; j < CPF; ++j) {
+        const int c = tid + j * NTHR;
+        if (c < a.ncols) cv[j] = crow[c];
+    }
+    load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw0), L);
+    for (int i = tid; i < nrows * RS; i += NTHR) {
+        const int r = i / RS;
+        int row = rowlo + r;
+        if (row >= L) row -= L;
+        pl[row * RS + (i - r * RS)] = cmake<T>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CPF; ++j) {
+        const int c = tid + j * NTHR;
+        if (c < a.ncols) pl[a.colpos[c]] = cv[j];
+    }
+    for (int c = tid + CPF * NTHR; c < a.ncols; c += NTHR) pl[a.colpos[c]] = crow[c];
+    __syncthreads();
+    for (int f = quad; f < nrows; f += NQ) {                 // y inverse, touched rows
+        int row = rowlo + f;
+        if (row >= L) row -= L;
+        cplx<T> *p = pl + row * RS;
+        cplx<T> v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = p[q + 4 * m];
+        quad_a<T, M, 1>(v, tw, q);
+#pragma unroll
+        for (int k = 0; k < M; ++k) p[k + M * rq] = v[k];
+    }
+    __syncthreads();
+    const T *vz = reinterpret_cast<const T *>(a.vz) + (int64_t)z * L * L;
+    // complex64 loads V(r) ahead of the x transforms; complex128 at its use, which
+    // keeps it within 128 VGPRs (four waves per SIMD)
+    constexpr bool VPF = sizeof(T) == 4;
+    for (int y = quad; y < L; y += NQ) {                     // x inverse, V, x forward
+        T vv[M];
+        if constexpr (VPF) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) vv[k] = vz[(k + M * rq) * L + y];
+        }
+        cplx<T> v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int x = q + 4 * m;
+            int dx = x - rowlo;
+            if (dx < 0) dx += L;
+            v[m] = dx < nrows ? pl[x * RS + y] : cmake<T>(0, 0);
+        }
+        quad_a<T, M, 1>(v, tw, q);
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = cscale<T>(v[k], VPF ? vv[k] : vz[(k + M * rq) * L + y]);
+        quad_b<T, M, -1>(v, tw, q);
+#pragma unroll
+        for (int k = 0; k < M; ++k) pl[(q + 4 * k) * RS + y] = v[k];
+    }
+    __syncthreads();
+    for (int f = quad; f < nrows; f += NQ) {                 // y forward, touched rows
+        int row = rowlo + f;
+        if (row >= L) row -= L;
+        cplx<T> *p = pl + row * RS;
+        cplx<T> v[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = p[k + M * rq];
+        quad_b<T, M, -1>(v, tw, q);
+#pragma unroll
+        for (int k = 0; k < M; ++k) p[q + 4 * k] = v[k];
+    }
+    __syncthreads();
+    for (int c = tid; c < a.ncols; c += NTHR) crow[c] = pl[a.colpos[c]];
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 template <typename T> static int pick_threads(const FftPlan &p, int howmany) {
@@ -332,6 +545,29 @@ void launch_zfwd(pw_ctx *ctx, int nb, const void *cols, const void *psi, int64_t
     PW_LAUNCH_CHECK();
 }
 
+static bool xy_has_quad(int n0, int n1) {
+    return n0 == n1 && (n0 == 16 || n0 == 32 || n0 == 48 || n0 == 64);
+}
+
+template <typename T, int M, int NTHR>
+static void quad_go(const XYArgs &a, int nb, hipStream_t s, void *cols) {
+    constexpr int L = 4 * M;
+    const size_t lds = sizeof(cplx<T>) * ((size_t)L + (size_t)L * (L + 1));
+    allow_lds(xy_quad<T, M, NTHR>, lds);
+    hipLaunchKernelGGL((xy_quad<T, M, NTHR>), dim3(a.n2, nb), dim3(NTHR), lds, s, a,
+                       reinterpret_cast<cplx<T> *>(cols));
+}
+
+template <typename T, int NTHR> static void quad_len(const XYArgs &a, int nb, hipStream_t s, void *cols) {
+    switch (a.n0) {
+        case 16: quad_go<T, 4, NTHR>(a, nb, s, cols); break;
+        case 32: quad_go<T, 8, NTHR>(a, nb, s, cols); break;
+        case 48: quad_go<T, 12, NTHR>(a, nb, s, cols); break;
+        case 64: quad_go<T, 16, NTHR>(a, nb, s, cols); break;
+        default: PW_CHECK(false, PW_EUNSUPPORTED, "no four-lane xy kernel for %d x %d", a.n0, a.n1);
+    }
+}
+
 template <typename T, int MODE, typename L0, typename L1, int NTHR>
 static void xy_go(const XYArgs &a, int nb, size_t lds, hipStream_t s, void *cols, void *grid) {
     allow_lds(xy_pass<T, NTHR, MODE, L0, L1>, lds);
@@ -345,6 +581,19 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
     const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
     PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
     const FftChoice &c = choice_of<T>(ctx, 1);
+    // default for the V(r) pass on 16/32/48/64-point planes: the four-lane kernel
+    if (MODE == 0 && (c.kind == 3 || (c.kind == 0 && xy_has_quad(a.n0, a.n1)))) {
+        PW_CHECK(xy_has_quad(a.n0, a.n1), PW_EUNSUPPORTED, "no four-lane xy kernel for %d x %d", a.n0, a.n1);
+        const int nthr = c.kind == 3 ? c.nthr : (sizeof(T) == 8 ? 256 : 192);
+        switch (nthr) {
+            case 128: quad_len<T, 128>(a, nb, s, cols); break;
+            case 192: quad_len<T, 192>(a, nb, s, cols); break;
+            case 256: quad_len<T, 256>(a, nb, s, cols); break;
+            default: PW_CHECK(false, PW_EUNSUPPORTED, "four-lane xy kernel with %d threads", nthr);
+        }
+        PW_LAUNCH_CHECK();
+        return;
+    }
     if (c.kind != 2 && a.n0 == a.n1) {
 #define PW_XYCASE(L)                                                                        \
     case L: {                                                                               \
@@ -384,7 +633,8 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
 // Autotuner: for each pass (z inverse, xy with V, z forward) time every launch
 // variant that fits this grid -- the compile-time length kernel and the
 // runtime-plan kernel for each radix schedule and thread count -- on nb bands
-// and keep the fastest; for complex128 also the back-projection GEMM's tile.
+// and keep the fastest; for complex128 also the tiles of the back-projection GEMM
+// and of the block-rotation GEMM.
 // Results are cached per (grid, sphere, dtype, nb).
 // ---------------------------------------------------------------------------
 template <typename T> static bool xy_has_ct(int n) {
@@ -411,6 +661,10 @@ template <typename T> static bool choice_from(pw_ctx *ctx, const pw_fft_cand &r,
     c.kind = r.kind;
     if (r.kind == 0) return true;
     if (r.kind == 1) return r.pass == 1 ? (n0 == n1 && xy_has_ct<T>(n0)) : z_has_ct(n2);
+    if (r.kind == 3) {
+        c.nthr = r.nthr;
+        return r.pass == 1 && xy_has_quad(n0, n1) && (c.nthr == 128 || c.nthr == 192 || c.nthr == 256);
+    }
     if (r.kind != 2 || r.sched < 0 || r.sched > 2) return false;
     c.nthr = r.nthr;
     if (c.nthr != 256 && c.nthr != 512 && c.nthr != 1024) return false;
@@ -430,6 +684,13 @@ template <typename T> static std::vector<pw_fft_cand> candidates(pw_ctx *ctx, in
     FftChoice c;
     r.kind = 1;
     if (choice_from<T>(ctx, r, c)) out.push_back(r);
+    for (int t : {128, 192, 256}) {
+        r = pw_fft_cand{};
+        r.pass = pass;
+        r.kind = 3;
+        r.nthr = t;
+        if (choice_from<T>(ctx, r, c)) out.push_back(r);
+    }
     std::vector<FftChoice> seen;
     for (int sched = 0; sched < 3; ++sched) {
         for (int t : {256, 512, 1024}) {
@@ -470,7 +731,7 @@ struct TuneKey {
 };
 struct TuneVal {
     FftTune tune;
-    int nn = -1;
+    int nn = -1, rot = -1;
     std::vector<pw_fft_cand> recs;
 };
 std::mutex g_tune_mu;
@@ -489,6 +750,7 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
         if (it != g_tune_cache.end()) {
             tune = it->second.tune;
             if (it->second.nn >= 0) ctx->nn_tune.set(nb, it->second.nn);
+            if (it->second.rot >= 0) ctx->rot_tune.set(nb, it->second.rot);
             recs = it->second.recs;
             return;
         }
@@ -511,7 +773,7 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
     } guard{e0, e1};
     PW_HIP(hipEventCreate(&e1));
     recs.clear();
-    int nn_best = -1;
+    int nn_best = -1, rot_best = -1;
     run_pass<T>(ctx, 0, nb, in.p, out.p, s);              // column grid for the xy timings
     for (int pass = 0; pass < 3; ++pass) {
         std::vector<pw_fft_cand> cs = candidates<T>(ctx, pass);
@@ -571,18 +833,51 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
         nn_best = best;
         ctx->nn_tune.set(nb, best);
     }
+    // complex128 block-rotation GEMM tiles (pass 5): Out = W . X with W nb x nb
+    if (sizeof(T) == 8) {
+        const int npw = ctx->basis.npw;
+        DevBuf w;
+        w.alloc((size_t)nb * nb * sizeof(double2));
+        fill_zero(w.p, (size_t)nb * nb * sizeof(double2), s);
+        const size_t first = recs.size();
+        int best = -1;
+        for (int id = 0; id < kNnCfgs; ++id) {
+            pw_fft_cand r{};
+            r.pass = 5;
+            r.kind = 3;
+            r.sched = id;
+            r.nradix = 3;
+            nn_cfg_shape(id, r.radix[0], r.radix[1], r.nthr);
+            r.radix[2] = nb;
+            auto go = [&]() { zgemm_nn_launch(nb, npw, nb, w.p, nb, in.p, npw, 1.0, 0.0, out.p, npw, s, false, id); };
+            go();
+            PW_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) go();
+            PW_HIP(hipEventRecord(e1, s));
+            PW_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            r.ms = ms / reps;
+            if (best < 0 || r.ms < recs[first + best].ms) best = id;
+            recs.push_back(r);
+        }
+        recs[first + best].chosen = 1;
+        rot_best = best;
+        ctx->rot_tune.set(nb, best);
+        PW_HIP(hipStreamSynchronize(s));
+    }
     PW_HIP(hipStreamSynchronize(s));
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = TuneVal{tune, nn_best, recs};
+    g_tune_cache[key] = TuneVal{tune, nn_best, rot_best, recs};
 }
 
 template <typename T> void fft_choose(pw_ctx *ctx, const pw_fft_cand &r) {
-    if (r.pass == 4) {
+    if (r.pass == 4 || r.pass == 5) {
         PW_CHECK(sizeof(T) == 8, PW_EUNSUPPORTED, "GEMM tiles are chosen for complex128 only");
         PW_CHECK(r.kind == 0 || (r.kind == 3 && r.sched >= 0 && r.sched < kNnCfgs), PW_EUNSUPPORTED,
                  "GEMM tile candidate unknown");
         PW_CHECK(r.radix[2] >= 1, PW_EINVAL, "GEMM tile candidate needs its band count in radix[2]");
-        ctx->nn_tune.set(r.radix[2], r.kind == 0 ? -1 : r.sched);
+        (r.pass == 4 ? ctx->nn_tune : ctx->rot_tune).set(r.radix[2], r.kind == 0 ? -1 : r.sched);
         return;
     }
     PW_CHECK(r.pass >= 0 && r.pass <= 2, PW_EINVAL, "FFT pass %d unknown", r.pass);

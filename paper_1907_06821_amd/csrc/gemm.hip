@@ -127,20 +127,41 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
             }
 }
 
-// out = alpha * rowscale[m] * sum_s partial[s][m][n] (+ beta * out); TRANS writes out[n][m]
+// out = alpha * rowscale[m] * sum_s partial[s][m][n] (+ beta * out); TRANS writes out[n][m].
+// A workgroup of 256 threads takes 64 consecutive elements: wave g sums the
+// splits s = g (mod 4) for each, then wave 0 adds the four sums in order (fixed
+// summation order, so the result does not depend on scheduling).
+constexpr int kRedElems = 64, kRedGroups = 4;
+
 template <bool TRANS>
-__global__ void reduce_partial(int M, int N, int nsplit, const double2 *__restrict__ partial, double alpha,
-                               const double *__restrict__ rowscale, double beta, double2 *__restrict__ out,
-                               int64_t ldo) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)M * N) return;
-    const int m = (int)(idx / N), n = (int)(idx % N);
+__global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial(int M, int N, int nsplit,
+                                                                         const double2 *__restrict__ partial,
+                                                                         double alpha,
+                                                                         const double *__restrict__ rowscale,
+                                                                         double beta, double2 *__restrict__ out,
+                                                                         int64_t ldo) {
+    __shared__ double2 sum[kRedGroups][kRedElems];
+    const int e = threadIdx.x % kRedElems, g = threadIdx.x / kRedElems;
+    const int64_t tot = (int64_t)M * N;
+    const int64_t idx = (int64_t)blockIdx.x * kRedElems + e;
     double re = 0, im = 0;
-    for (int s = 0; s < nsplit; ++s) {
-        const double2 v = partial[(int64_t)s * M * N + idx];
-        re += v.x;
-        im += v.y;
+    if (idx < tot)
+        for (int s = g; s < nsplit; s += kRedGroups) {
+            const double2 v = partial[(int64_t)s * tot + idx];
+            re += v.x;
+            im += v.y;
+        }
+    sum[g][e] = make_double2(re, im);
+    __syncthreads();
+    if (g != 0 || idx >= tot) return;
+    re = 0;
+    im = 0;
+#pragma unroll
+    for (int q = 0; q < kRedGroups; ++q) {
+        re += sum[q][e].x;
+        im += sum[q][e].y;
     }
+    const int m = (int)(idx / N), n = (int)(idx % N);
     double sc = alpha * (rowscale ? rowscale[m] : 1.0);
     double2 *o = TRANS ? out + (int64_t)n * ldo + m : out + (int64_t)m * ldo + n;
     if (beta != 0.0) {
@@ -309,13 +330,14 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     else nt_go<2, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     PW_LAUNCH_CHECK();
     const int64_t tot = (int64_t)M * N;
-    const int nblk = (int)((tot + 255) / 256);
+    const int nblk = (int)((tot + kRedElems - 1) / kRedElems);
+    const dim3 rblk(kRedElems * kRedGroups);
     if (trans)
-        hipLaunchKernelGGL((reduce_partial<true>), dim3(nblk), dim3(256), 0, st, M, N, nsplit,
-                           (const double2 *)partial, alpha, rowscale, beta, (double2 *)C, ldc);
+        hipLaunchKernelGGL((reduce_partial<true>), dim3(nblk), rblk, 0, st, M, N, nsplit, (const double2 *)partial,
+                           alpha, rowscale, beta, (double2 *)C, ldc);
     else
-        hipLaunchKernelGGL((reduce_partial<false>), dim3(nblk), dim3(256), 0, st, M, N, nsplit,
-                           (const double2 *)partial, alpha, rowscale, beta, (double2 *)C, ldc);
+        hipLaunchKernelGGL((reduce_partial<false>), dim3(nblk), rblk, 0, st, M, N, nsplit, (const double2 *)partial,
+                           alpha, rowscale, beta, (double2 *)C, ldc);
     PW_LAUNCH_CHECK();
 }
 

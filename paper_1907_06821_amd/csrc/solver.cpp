@@ -163,14 +163,14 @@ struct FcgRun {
         else std::swap(blk, tmp);
     }
     void rotate(const double2 *M, void *&blk, void *&tmp) {
-        zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st);
+        zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st, false, ctx->rot_tune.get(nb));
         settle(blk, tmp);
     }
     // (X, Y, AX) <- M . (X, Y, AX) in one batched launch
     void rotate3(const double2 *M) {
         const void *in[3] = {X, Y, AX};
         void *out[3] = {T1, T2, T3};
-        zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st);
+        zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st, false, ctx->rot_tune.get(nb));
         settle(X, T1);
         settle(Y, T2);
         settle(AX, T3);
@@ -189,7 +189,7 @@ struct FcgRun {
         if (rotate_dirs) {
             const void *in[2] = {P, G};
             void *out[2] = {T1, T2};
-            zgemm_nn_batch(2, nb, npw, nb, Rm, nb, in, L, 1.0, 0.0, out, L, st);
+            zgemm_nn_batch(2, nb, npw, nb, Rm, nb, in, L, 1.0, 0.0, out, L, st, false, ctx->rot_tune.get(nb));
             settle(P, T1);
             settle(G, T2);
         }
@@ -199,8 +199,8 @@ struct FcgRun {
     void h_resid() {
         zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
         dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
-        zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st);
-        zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st);
+        zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st, false, ctx->rot_tune.get(nb));
+        zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st, false, ctx->rot_tune.get(nb));
         red_resid(nb, npw, T2, T1, L, lam, res, br, st);
     }
     // band kinetic energies, then (learned preconditioner) the per-shell scaling table
@@ -243,7 +243,7 @@ struct FcgRun {
         pupdate(nb, npw, Z, P, L, gz, gzo, gz_old, st);
         // P -= X (X^H P): W[b][j] = -<x_j|p_b>
         zgemm_nt(nb, nb, npw, true, X, L, P, L, -1.0, nullptr, 0.0, Wm, nb, true, ctx->d_partial.p, st);
-        zgemm_nn_launch(nb, npw, nb, Wm, nb, X, L, 1.0, 1.0, P, L, st);
+        zgemm_nn_launch(nb, npw, nb, Wm, nb, X, L, 1.0, 1.0, P, L, st, false, ctx->rot_tune.get(nb));
         fold(P, YP, AP, use_mixed);
         red_line(nb, npw, Y, YP, P, L, line4, br, st);
         line_coef(nb, mu, line4, coef, st);
@@ -530,7 +530,7 @@ void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, 
     // E = X - W . Xc with W[i][j] = <xc_j | x_i>: the part of x_i outside span(Xc)
     zgemm_nt(nb, nb, npw, true, Xc, L, X, L, 1.0, nullptr, 0.0, Wm, nb, true, ctx->d_partial.p, st);
     copy_block(nb, npw, X, L, T1, L, st);
-    zgemm_nn_launch(nb, npw, nb, Wm, nb, Xc, L, -1.0, 1.0, T1, L, st);
+    zgemm_nn_launch(nb, npw, nb, Wm, nb, Xc, L, -1.0, 1.0, T1, L, st, false, ctx->rot_tune.get(nb));
     shell_tables((int)ctx->basis.shell_t.size(), nb, npw, ctx->d_shell_off.as<int32_t>(),
                  ctx->d_shell_pw.as<int32_t>(), T1, Z, L, ctx->d_shell_t.as<double>(), E, delta, tabs, st);
     PW_HIP(hipMemcpyAsync(tband_out, tband, nb * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -1,6 +1,8 @@
 """The FFT autotuner: every launch variant it may pick (compile-time length
-kernels, runtime plans over radix schedules and thread counts) computes the same
-H psi as the oracle, and it installs exactly one winner per pass."""
+kernels, runtime plans over radix schedules and thread counts, the four-lane xy
+kernels on 16/32/48/64-point planes, the GEMM tiles of the back-projection and
+of the block rotation) computes the same result as the oracle or as the
+definition, and it installs exactly one winner per pass."""
 import numpy as np
 import pytest
 
@@ -10,12 +12,16 @@ from tests._helpers import gpu_context, oracle_for, random_block, rel_err, to_de
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("which", ["cube", "skew"])
+@pytest.mark.parametrize("which", ["cube", "cube48", "tiny", "skew"])
 def test_every_fft_candidate_matches_oracle(torch_cuda, which):
     import torch
     import paper_1907_06821_amd as pw
     if which == "cube":
-        prob = synth.batched_problems(4, seed=3)[2]          # one of the uneven cubes
+        prob = synth.batched_problems(4, seed=3)[2]          # one of the uneven cubes (40^3)
+    elif which == "cube48":
+        prob = synth.batched_problems(4, seed=3)[1]          # 48^3: the four-lane xy kernel (M = 12)
+    elif which == "tiny":
+        prob = synth.config(1)                               # 16^3: the four-lane xy kernel (M = 4)
     else:
         prob = synth.small_nonlocal_problem()                # 12 x 15 x 20 grid: xy runtime plans only
     op = oracle_for(prob)
@@ -28,6 +34,8 @@ def test_every_fft_candidate_matches_oracle(torch_cuda, which):
     # rounding, and the tuned one with the oracle at the BF16 level
     for dtype, tol_ref, tol_var in ((pw.PW_C128, 1e-12, 1e-12), (pw.PW_C64, 2e-3, 3e-6)):
         recs = pw.autotune(ctx, nb, dtype=dtype, reps=2)
+        if which in ("cube48", "tiny"):
+            assert sum(r["pass_"] == 1 and r["kind"] == 3 for r in recs) == 3
         for p in range(3):
             mine = [r for r in recs if r["pass_"] == p]
             assert len(mine) >= 2
@@ -36,11 +44,20 @@ def test_every_fft_candidate_matches_oracle(torch_cuda, which):
         tdt = "complex128" if dtype == pw.PW_C128 else "complex64"
         base = pw.hpsi(ctx, to_dev(c, tdt), shift=prob.e_ref).cpu().numpy()
         assert rel_err(base, ref) < tol_ref                  # the tuned choice
+        if dtype == pw.PW_C128:
+            assert sum(r["pass_"] == 5 and r["chosen"] for r in recs) == 1
         for r in recs:
             pw.fft_choose(ctx, r, dtype=dtype)
             got = pw.hpsi(ctx, to_dev(c, tdt), shift=prob.e_ref).cpu().numpy()
             err_ = rel_err(got, ref if dtype == pw.PW_C128 else base)
             assert err_ < tol_var, (r, err_)
+            if r["pass_"] == 5:                              # block rotation: Gram/Cholesky orthonormalisation
+                q = pw.orthonormalize(ctx, to_dev(c)).cpu().numpy()
+                assert np.abs(q.conj() @ q.T - np.eye(nb)).max() < 1e-13, r
+                # Psi = L^H Q with L^H upper triangular: the spans agree band by band
+                coef = q.conj() @ c.T
+                assert np.abs(np.tril(coef, -1)).max() < 1e-12 * np.abs(coef).max(), r
+                assert rel_err(coef.T @ q, c) < 1e-13, r
             pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0, "radix": r["radix"]}, dtype=dtype)
         with pytest.raises(pw.PwError):
             pw.fft_choose(ctx, {"pass_": 1, "kind": 2, "nthr": 100, "sched": 0}, dtype=dtype)
