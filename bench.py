@@ -92,11 +92,11 @@ def measured_traffic(stage, mixed, nb, nn_cfg):
     st = rec["stages"].get(stage)
     if st is None or not os.path.exists(src):
         return None
-    if st["nn_cfg"] is not None and st["nn_cfg"] != nn_cfg:
-        return None
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
             return None
+    if "bytes_by_nn_cfg" in st:
+        return st["bytes_by_nn_cfg"].get(str(nn_cfg))
     return st["bytes_per_launch"]
 
 
