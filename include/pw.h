@@ -207,8 +207,11 @@ typedef struct {
     int32_t precision;    /* 0 FP64 throughout; 1 mixed (complex64 H psi, FP64 block algebra) */
     int32_t check_every;  /* iterations between exact residual checks */
     int32_t verbose;      /* print the residual at each check to stderr */
-    double mixed_switch;  /* mixed: use FP64 H psi once max Delta < mixed_switch (default 1e-4) */
-    int32_t stall_checks; /* mixed: also switch after this many checks without a 2x gain (0 = never) */
+    double mixed_switch;  /* mixed: use FP64 H psi once max Delta < mixed_switch (default 5e-4, above
+                             the floor the BF16 projector products leave on the 256-atom wire) */
+    int32_t stall_checks; /* mixed: also switch after this many checks (default 5) without a 2x gain of
+                             the best residual once it is below 20 x mixed_switch, or after 10 x this
+                             many anywhere (0 = never) */
     void *snap_buf;       /* optional device complex128 [snap_cap][nb][npw]: iterate snapshots for training */
     int32_t snap_every;   /* store X after every snap_every-th iteration (0 = never) */
     int32_t snap_cap;     /* capacity of snap_buf in snapshots */

@@ -294,12 +294,17 @@ struct FcgRun {
         }
         // precision ladder: leave the low-precision operator below mixed_switch, or
         // once the best residual has not improved by 2x over stall_checks checks
+        // while within 20 x mixed_switch (a stall higher up is the search for the
+        // last wanted states, which the operator's precision does not limit), or
+        // over 10 x stall_checks checks anywhere
         if (use_mixed) {
             if (mx < 0.5 * best) {
                 best = mx;
                 stall = 0;
-            } else if (o.stall_checks > 0 && ++stall >= o.stall_checks) {
-                use_mixed = false;
+            } else if (o.stall_checks > 0) {
+                ++stall;
+                if ((stall >= o.stall_checks && best < 20.0 * o.mixed_switch) || stall >= 10 * o.stall_checks)
+                    use_mixed = false;
             }
             if (mx < o.mixed_switch) use_mixed = false;
             if (!use_mixed && o.verbose) fprintf(stderr, "[pw] it %6d  switching to FP64 H psi\n", it);
@@ -563,8 +568,8 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->precision = 0;
     o->check_every = 20;
     o->verbose = 0;
-    o->mixed_switch = 1e-4;
-    o->stall_checks = 10;
+    o->mixed_switch = 5e-4;
+    o->stall_checks = 5;
     o->snap_buf = nullptr;
     o->snap_every = 0;
     o->snap_cap = 0;
