@@ -208,7 +208,7 @@ typedef struct {
     int32_t check_every;  /* iterations between exact residual checks */
     int32_t verbose;      /* print the residual at each check to stderr */
     double mixed_switch;  /* mixed: use FP64 H psi once max Delta < mixed_switch (default 5e-4, above
-                             the floor the BF16 projector products leave on the 256-atom wire) */
+                             the level where BF16 projector products slow the 256-atom wire) */
     int32_t stall_checks; /* mixed: also switch after this many checks (default 5) without a 2x gain of
                              the best residual once it is below 20 x mixed_switch, or after 10 x this
                              many anywhere (0 = never) */
