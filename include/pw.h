@@ -263,7 +263,8 @@ pw_status pw_batch_solve(int32_t nprob, pw_ctx *const *ctx, const double *e_ref,
  * Learned preconditioner (precond = 2).  Not in the paper: a network standing in
  * for the diagonal preconditioner (the paper's is M(G), Sec. II.B).  Per |G+k|
  * shell s and band i, f_si = MLP(T_s/Ecut, T_i/Ecut, E_ref/Ecut), a 3-64-64-1 tanh
- * network with output 8 tanh(r/8); the CG uses K_i(G) = K_TPA(T_G/T_i)^2 exp(f).
+ * network with output 8 tanh(r/8); the CG uses K_i(G) = M(G) exp(f), M(G) the
+ * paper's preconditioner with the solve's delta_e.
  * Parameters (float32, PW_MLP_NPARAM): W1[64][3], b1[64], W2[64][64], b2[64],
  * W3[64], b3.  Training loss per band and snapshot: 1 - Re<K g, e>/(|K g| |e|),
  * e = (I - Psi* Psi*^H) psi the band's error outside the converged subspace (the
@@ -284,14 +285,15 @@ pw_status pw_mlp_forward(int32_t nshell, int32_t nb, const double *shell_t, cons
 
 /* Shell tables of one snapshot: x_snap [nb][ld] an iterate of a solve at e_ref,
  * x_conv [nb][ld] the converged orthonormal block.  Recomputes the gradient
- * g = A x - <x|A|x> x with two FP64 H psi, the TPA weights K0 and the band kinetic
- * energies (written to tband [nb]), and writes tabs [3][nshell][nb]: per shell s
+ * g = A x - <x|A|x> x with two FP64 H psi, the weights K0 = M(G) with delta_e
+ * (> 0, Ha) and the band kinetic energies (written to tband [nb]), and writes
+ * tabs [3][nshell][nb]: per shell s
  * and band i, the sums over the shell of Re(conj(e) K0 g), |K0 g|^2 and |e|^2 with
  * e = -(I - X* X*^H) x.  weight_delta >= 0 multiplies the sums of shell s by
  * (T_s - e_ref)^2 + weight_delta^2 (an approximate A-norm for the cosine loss);
  * weight_delta < 0 leaves them unweighted. */
 pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
-                         double weight_delta, double *tabs, double *tband, void *stream);
+                         double delta_e, double weight_delta, double *tabs, double *tband, void *stream);
 
 /* Scratch bytes needed by pw_mlp_loss_grad (host function). */
 int64_t pw_mlp_work_bytes(int32_t nshell, int32_t nb, int32_t nsnap);

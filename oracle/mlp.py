@@ -8,7 +8,8 @@ Network (3 -> 64 -> 64 -> 1, tanh), per |G+k| shell s and band i:
     x      = (T_s / Ecut, T_i / Ecut, E_ref / Ecut)
     h1     = tanh(W1 x + b1),  h2 = tanh(W2 h1 + b2),  r = W3 h2 + b3
     f_si   = 8 tanh(r / 8)                      (smooth clamp to [-8, 8])
-Preconditioner: K_i(G) = K0_i(G) exp(f_{s(G), i}) with K0 the folded TPA weight.
+Preconditioner: K_i(G) = K0_i(G) exp(f_{s(G), i}) with K0 the base diagonal
+preconditioner (the library uses the paper's M(G); any K0 > 0 works here).
 
 Loss (one snapshot): for band i with gradient g_i and error
 e_i = (I - Psi* Psi*^H) psi_i (the part of psi_i outside the converged subspace;
@@ -51,7 +52,7 @@ def unpack(theta):
 
 def init_params(seed=0):
     """Glorot-uniform weights, zero biases, last layer scaled by 0.1 (network
-    starts close to f = 0, i.e. the plain TPA preconditioner)."""
+    starts close to f = 0, i.e. the base preconditioner K0)."""
     rng = np.random.default_rng([5, seed])
     def glorot(o, i):
         lim = np.sqrt(6.0 / (o + i))

@@ -102,7 +102,7 @@ def lib():
             "pw_dense_chol_inv": [i32, vp, i64, vp, vp],
             "pw_mlp_set": [vp, vp],
             "pw_mlp_forward": [i32, i32, vp, vp, dbl, dbl, vp, vp, vp],
-            "pw_mlp_harvest": [vp, dbl, i32, vp, vp, i64, dbl, vp, vp, vp],
+            "pw_mlp_harvest": [vp, dbl, i32, vp, vp, i64, dbl, dbl, vp, vp, vp],
             "pw_mlp_loss_grad": [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp],
             "pw_mlp_adam": [vp, vp, vp, vp, i32, C.c_float, vp],
             "pw_mlp_train": [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i32, i32, C.c_float,
@@ -344,9 +344,10 @@ def mlp_forward(shell_t, tband, e_ref, ecut, weights, stream=None):
     return f
 
 
-def mlp_harvest(ctx, e_ref, x_snap, x_conv, weight_delta=-1.0, stream=None):
+def mlp_harvest(ctx, e_ref, x_snap, x_conv, weight_delta=-1.0, delta_e=1.0, stream=None):
     """Training tables of one snapshot: (tabs [3, nshell, nb] float64, tband [nb]);
-    weight_delta >= 0 weights shell s by (T_s - e_ref)^2 + weight_delta^2."""
+    K0 = M(G) with delta_e; weight_delta >= 0 weights shell s by
+    (T_s - e_ref)^2 + weight_delta^2."""
     import torch
     _check_block(x_snap, ctx.npw)
     _check_block(x_conv, ctx.npw)
@@ -356,7 +357,8 @@ def mlp_harvest(ctx, e_ref, x_snap, x_conv, weight_delta=-1.0, stream=None):
     tabs = torch.empty((3, ctx.nshell, nb), dtype=torch.float64, device=x_snap.device)
     tband = torch.empty(nb, dtype=torch.float64, device=x_snap.device)
     _check(lib().pw_mlp_harvest(ctx.handle, float(e_ref), nb, _dptr(x_snap), _dptr(x_conv), x_snap.stride(0),
-                                float(weight_delta), _dptr(tabs), _dptr(tband), _stream_ptr(stream)))
+                                float(delta_e), float(weight_delta), _dptr(tabs), _dptr(tband),
+                                _stream_ptr(stream)))
     return tabs, tband
 
 

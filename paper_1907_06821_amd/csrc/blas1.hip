@@ -20,12 +20,13 @@ __device__ inline double tpa_k(double x) {
 
 __device__ inline double prec_weight(const PrecArgs &pa, int b, int g) {
     const double t = pa.kin[g];
-    if (pa.kind == 1) {
-        const double d = t - pa.e_ref;
-        return 1.0 / (d * d + pa.de2);
+    if (pa.kind == 0) {
+        const double k = tpa_k(t / pa.tband[b]);
+        return k * k;
     }
-    const double k = tpa_k(t / pa.tband[b]);
-    double w = k * k;
+    // the paper's M(G); the learned preconditioner scales it by exp(f)
+    const double d = t - pa.e_ref;
+    double w = 1.0 / (d * d + pa.de2);
     if (pa.kind == 2) w *= exp((double)pa.ftab[(int64_t)pa.shell[g] * pa.nb + b]);
     return w;
 }

@@ -1,5 +1,5 @@
 // Learned preconditioner: a per-|G+k|-shell network (3 -> 64 -> 64 -> 1, tanh) that
-// scales the folded TPA weight by exp(f) inside the folded CG, with hand-written
+// scales the paper's M(G) by exp(f) inside the folded CG, with hand-written
 // FP32 inference, loss/gradient and Adam kernels, and the kernels that turn solver
 // snapshots into training tables.
 //

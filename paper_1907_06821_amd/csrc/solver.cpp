@@ -510,8 +510,8 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
 
 // Training tables of one snapshot (see pw_mlp_harvest in pw.h), using the solver's
 // blocks as scratch.
-void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, int64_t ld, double delta,
-                 double *tabs, double *tband_out, hipStream_t st) {
+void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, int64_t ld, double delta_e,
+                 double delta, double *tabs, double *tband_out, hipStream_t st) {
     const int npw = ctx->basis.npw;
     Solver *s = solver_get(ctx, nb, false);
     const int64_t L = npw;
@@ -526,8 +526,10 @@ void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, 
     hpsi_any(ctx, PW_C128, nb, Y, L, AX, L, E, st);
     red_mu_tband(nb, npw, Y, X, L, ctx->d_kin.as<double>(), mu, tband, br, st);
     PrecArgs pa{};
-    pa.kind = 0;
+    pa.kind = 1;                                                    // K0 = the paper's M(G)
     pa.kin = ctx->d_kin.as<double>();
+    pa.e_ref = E;
+    pa.de2 = delta_e * delta_e;
     pa.tband = tband;
     pa.nb = nb;
     fill_zero(G, (size_t)nb * npw * 16, st);
@@ -546,13 +548,14 @@ void mlp_harvest(pw_ctx *ctx, double E, int nb, const void *xs, const void *xc, 
 extern "C" {
 
 pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
-                         double weight_delta, double *tabs, double *tband, void *stream) {
+                         double delta_e, double weight_delta, double *tabs, double *tband, void *stream) {
     try {
         PW_CHECK(ctx && x_snap && x_conv && tabs && tband, PW_EINVAL, "null argument");
         PW_CHECK(ctx->flags & PW_PREP_C128, PW_EUNSUPPORTED, "harvest needs a complex128 context");
         PW_CHECK(nb >= 1 && nb <= ctx->max_bands && nb <= 1024 && ld >= ctx->basis.npw, PW_EINVAL,
                  "bad harvest sizes");
-        pw::mlp_harvest(ctx, e_ref, nb, x_snap, x_conv, ld, weight_delta, tabs, tband, (hipStream_t)stream);
+        PW_CHECK(delta_e > 0.0, PW_EINVAL, "delta_e must be positive");
+        pw::mlp_harvest(ctx, e_ref, nb, x_snap, x_conv, ld, delta_e, weight_delta, tabs, tband, (hipStream_t)stream);
         return PW_OK;
     } catch (const pw::Fail &f) {
         return f.st;

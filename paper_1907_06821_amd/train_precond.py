@@ -4,7 +4,7 @@ Samples come from the method's own solves: folded-spectrum CG runs on a cell
 store snapshots of the iterate X(t); once converged (X*), every snapshot gives
 the per-(shell, band) tables of its gradient g = A x - mu x and of its error
 direction e = -(I - X* X*^H) x (gauge invariant).  The network
-f(T_shell, T_band, E_ref) of the preconditioner K = K_TPA^2 e^f is then fitted
+f(T_shell, T_band, E_ref) of the preconditioner K = M(G) e^f is then fitted
 to the cosine loss 1 - Re<K g, e> / (|K g| |e|) with the library's own loss,
 gradient and Adam kernels.  The inner products are taken in the metric
 diag((T_G - E_ref)^2 + delta^2), the plane-wave diagonal of the folded operator
@@ -45,7 +45,7 @@ def harvest(ctx, prob, energies, start_seed, nb, nconv, snap_every, nsnap, maxit
     for j, e in enumerate(energies):
         psi = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=start_seed + j)).to("cuda")
         snaps = torch.zeros((nsnap, nb, ctx.npw), dtype=torch.complex128, device="cuda")
-        eig, res, st = pw.folded_cg_solve(ctx, e, psi, tol=1e-6, maxit=maxit, check_every=20, precond=0,
+        eig, res, st = pw.folded_cg_solve(ctx, e, psi, tol=1e-6, maxit=maxit, check_every=20, precond=1,
                                           nconv=nconv, snapshots=snaps, snap_every=snap_every,
                                           raise_on_noconv=False)
         rec = {"e_ref": e, "start_seed": start_seed + j, "iters": st["iters"], "seconds": round(st["seconds"], 2),
@@ -86,11 +86,11 @@ def main(argv=None):
     ap.add_argument("--start-seed", type=int, default=11)
     ap.add_argument("--bands", type=int, default=136)
     ap.add_argument("--nconv", type=int, default=128)
-    ap.add_argument("--snap-every", type=int, default=60)
+    ap.add_argument("--snap-every", type=int, default=40)
     ap.add_argument("--nsnap", type=int, default=16)
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--weight-delta", type=float, default=0.5, help="metric delta (Ha); < 0: Euclidean")
     a = ap.parse_args(argv)
     import torch
