@@ -40,6 +40,25 @@ __device__ inline float mlp_forward(const float *P, const float x[3], float h1[M
     return 8.0f * t;
 }
 
+// the same forward without the hidden states (inference): h1 indexed only by
+// unrolled constants stays in registers; sums in the order of mlp_forward
+__device__ inline float mlp_eval(const float *P, const float x[3]) {
+    float h1[MH];
+#pragma unroll
+    for (int o = 0; o < MH; ++o)
+        h1[o] = tanhf(P[OW1 + 3 * o] * x[0] + P[OW1 + 3 * o + 1] * x[1] + P[OW1 + 3 * o + 2] * x[2] + P[OB1 + o]);
+    float r = P[OB3];
+#pragma unroll 1
+    for (int o = 0; o < MH; ++o) {
+        const float *w2 = P + OW2 + MH * o;
+        float a = P[OB2 + o];
+#pragma unroll
+        for (int i = 0; i < MH; ++i) a += w2[i] * h1[i];
+        r += P[OW3 + o] * tanhf(a);
+    }
+    return 8.0f * tanhf(r * 0.125f);
+}
+
 // f[s][i] for one snapshot (inference inside the solver)
 __global__ __launch_bounds__(256) void k_mlp_infer(int nshell, int nb, const double *__restrict__ shell_t,
                                                    const double *__restrict__ tband, double e_ref, double ecut,
@@ -50,8 +69,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(int nshell, int nb, const dou
     if (idx >= nshell * nb) return;
     const int s = idx / nb, i = idx - s * nb;
     const float x[3] = {(float)(shell_t[s] / ecut), (float)(tband[i] / ecut), (float)(e_ref / ecut)};
-    float h1[MH], h2[MH], t;
-    f[idx] = mlp_forward(P, x, h1, h2, t);
+    f[idx] = mlp_eval(P, x);
 }
 
 void mlp_infer(int nshell, int nb, const double *shell_t, const double *tband, double e_ref, double ecut,
