@@ -174,22 +174,22 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial(int M, 
 // ---------------------------------------------------------------------------
 // NN: Out_z[m][j] = alpha * sum_k W[m][k] X_z[k][j] + beta * Out_z[m][j]
 // for up to 4 (X_z, Out_z) pairs sharing W (blockIdx.z).  Waves WM x WJ, each
-// BM x BJ blocks of 16 x 16.
+// BM x BJ blocks of 16 x 16; KD-deep LDS stages (a multiple of 4).
 // ---------------------------------------------------------------------------
 struct NNBatch {
     const double2 *X[4];
     double2 *Out[4];
 };
 
-template <int WM, int WJ, int BM, int BJ, int TAG>
+template <int WM, int WJ, int BM, int BJ, int TAG, int KD>
 __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, int K, const double2 *__restrict__ W,
                                                                 int64_t ldw, NNBatch bt, int64_t ldx, double alpha,
                                                                 double beta, int64_t ldo) {
     constexpr int NT = WM * WJ * 64;
     constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
-    constexpr int LW = (TM * KT + NT - 1) / NT, LX = (KT * TJ + NT - 1) / NT;
-    __shared__ double2 Ws[TM][KT + 1];
-    __shared__ double2 Xs[KT][TJ + 1];
+    constexpr int LW = (TM * KD + NT - 1) / NT, LX = (KD * TJ + NT - 1) / NT;
+    __shared__ double2 Ws[TM][KD + 1];
+    __shared__ double2 Xs[KD][TJ + 1];
     const double2 *__restrict__ X = bt.X[blockIdx.z];
     double2 *__restrict__ Out = bt.Out[blockIdx.z];
     const int j0 = blockIdx.x * TJ, m0 = blockIdx.y * TM;
@@ -204,25 +204,25 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int it = 0; it < LW; ++it) {
-            const int e = tid + it * NT, r = e / KT, kk = e % KT, gm = m0 + r, gk = k0 + kk;
-            rw[it] = (e < TM * KT && gm < M && gk < K) ? W[(int64_t)gm * ldw + gk] : make_double2(0.0, 0.0);
+            const int e = tid + it * NT, r = e / KD, kk = e % KD, gm = m0 + r, gk = k0 + kk;
+            rw[it] = (e < TM * KD && gm < M && gk < K) ? W[(int64_t)gm * ldw + gk] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int it = 0; it < LX; ++it) {
             const int e = tid + it * NT, kk = e / TJ, c = e % TJ, gk = k0 + kk, gj = j0 + c;
-            rx[it] = (e < KT * TJ && gk < K && gj < J) ? X[(int64_t)gk * ldx + gj] : make_double2(0.0, 0.0);
+            rx[it] = (e < KD * TJ && gk < K && gj < J) ? X[(int64_t)gk * ldx + gj] : make_double2(0.0, 0.0);
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int it = 0; it < LW; ++it) {
             const int e = tid + it * NT;
-            if (e < TM * KT) Ws[e / KT][e % KT] = rw[it];
+            if (e < TM * KD) Ws[e / KD][e % KD] = rw[it];
         }
 #pragma unroll
         for (int it = 0; it < LX; ++it) {
             const int e = tid + it * NT;
-            if (e < KT * TJ) Xs[e / TJ][e % TJ] = rx[it];
+            if (e < KD * TJ) Xs[e / TJ][e % TJ] = rx[it];
         }
     };
     if (K > 0) {
@@ -230,11 +230,11 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
         stash();
     }
     __syncthreads();
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        const bool more = k0 + KT < K;
-        if (more) fetch(k0 + KT);
+    for (int k0 = 0; k0 < K; k0 += KD) {
+        const bool more = k0 + KD < K;
+        if (more) fetch(k0 + KD);
 #pragma unroll
-        for (int kq = 0; kq < KT / 4; ++kq) {
+        for (int kq = 0; kq < KD / 4; ++kq) {
             const int k = kq * 4 + (lane >> 4);
             double2 a[BM], b[BJ];
 #pragma unroll
@@ -341,26 +341,30 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     PW_LAUNCH_CHECK();
 }
 
-template <int WM, int WJ, int BM, int BJ>
+template <int WM, int WJ, int BM, int BJ, int KD = KT>
 static void nn_go(int nz, bool proj, hipStream_t st, int M, int J, int K, const void *W, int64_t ldw,
                   const NNBatch &bt, int64_t ldx, double alpha, double beta, int64_t ldo) {
+    static_assert(KD % 4 == 0, "LDS stage depth");
     constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
     dim3 grid((J + TJ - 1) / TJ, (M + TM - 1) / TM, nz);
     const dim3 blk(WM * WJ * 64);
     if (proj)
-        hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 1>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
+        hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 1, KD>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
                            bt, ldx, alpha, beta, ldo);
     else
-        hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 0>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
+        hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 0, KD>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
                            bt, ldx, alpha, beta, ldo);
 }
 
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
-// M tiles: 64 (M <= 64), 144 (128 < M <= 144), else 128.
+// Default tiles: 64 rows (M <= 64), 144 (128 < M <= 144), else 128.
 // NN tile configurations (waves over rows x columns, 16 x 16 blocks per wave)
-// the autotuner chooses between; id: {WM, WJ, BM, BJ}, tile (16 WM BM) x (16 WJ BJ)
-static const int kNnCfg[kNnCfgs][4] = {{2, 2, 2, 2}, {4, 1, 2, 4}, {9, 1, 1, 4}, {4, 2, 2, 2},
-                                       {8, 1, 1, 4}, {4, 1, 2, 2}, {2, 4, 2, 2}};
+// the autotuner chooses between; id: {WM, WJ, BM, BJ, KD}, tile (16 WM BM) x
+// (16 WJ BJ), KD-deep stages.  A workgroup of 9 waves leaves one SIMD with three
+// waves and the others with two; the 12-wave 144-row tiles spread evenly.
+static const int kNnCfg[kNnCfgs][5] = {{2, 2, 2, 2, 16}, {4, 1, 2, 4, 16}, {9, 1, 1, 4, 16}, {4, 2, 2, 2, 16},
+                                       {8, 1, 1, 4, 16}, {4, 1, 2, 2, 16}, {2, 4, 2, 2, 16}, {9, 1, 1, 4, 8},
+                                       {3, 2, 3, 2, 8},  {8, 1, 1, 4, 8},  {3, 4, 3, 2, 8},  {3, 4, 3, 1, 8}};
 
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr) {
     PW_CHECK(id >= 0 && id < kNnCfgs, PW_EINVAL, "NN tile %d unknown", id);
@@ -379,7 +383,7 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.X[z] = (const double2 *)X[z];
         bt.Out[z] = (double2 *)Out[z];
     }
-    if (cfg < 0) cfg = M <= 64 ? 0 : (M > 128 && M <= 144) ? 2 : 1;
+    if (cfg < 0) cfg = M <= 64 ? 0 : (M > 128 && M <= 144) ? 11 : 9;
     switch (cfg) {
         case 0: nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 1: nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
@@ -388,6 +392,11 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         case 4: nn_go<8, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 5: nn_go<4, 1, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 6: nn_go<2, 4, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 7: nn_go<9, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 8: nn_go<3, 2, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 9: nn_go<8, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 10: nn_go<3, 4, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 11: nn_go<3, 4, 3, 1, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
     }
     PW_LAUNCH_CHECK();
