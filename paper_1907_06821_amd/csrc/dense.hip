@@ -107,55 +107,57 @@ __device__ inline void tri_rc(int q, int &i, int &k) {
     k = q - r * (r + 1) / 2;
 }
 
+// N <= kLdsMaxN.  The packed lower triangle lives in LDS.  Factorisation: right-
+// looking without square roots during the sweep: step j subtracts
+// L_ij conj(L_kj) / L_jj from the trailing triangle (rows i > j, columns j < k <= i)
+// and leaves column j unscaled, so one barrier per column suffices (column j is
+// read, never written, in step j).  Then every column k is divided by sqrt(L_kk),
+// which turns the diagonal into sqrt(L_kk) as well.  Inverse in place, column by
+// column from the last.
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
                                                           double2 *__restrict__ T, int *__restrict__ status) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);
-    __shared__ double piv;
-    __shared__ int bad;
+    __shared__ double sd[kLdsMaxN];
     const int tid = threadIdx.x;
     for (int q = tid; q < N * (N + 1) / 2; q += NT) {   // every load in flight at once
         int i, k;
         tri_rc(q, i, k);
         L[q] = S[(int64_t)i * lds + k];
     }
-    if (tid == 0) bad = 0;
     __syncthreads();
+    constexpr int G = NT / 128;
+    const int sub = tid % G;
     for (int j = 0; j < N; ++j) {
-        if (tid == 0) {
-            const double d = L[tri(j, j)].x;
-            if (!(d > 0.0) || !isfinite(d)) { bad = j + 1; piv = 1.0; }
-            else { piv = sqrt(d); L[tri(j, j)] = make_double2(piv, 0.0); }
+        const double d = L[tri(j, j)].x;                 // the same value in every thread
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (tid == 0) status[0] = j + 1;
+            return;
         }
-        __syncthreads();
-        if (bad) break;
-        const double inv = 1.0 / piv;
-        for (int i = j + 1 + tid; i < N; i += NT) {
-            const double2 v = L[tri(i, j)];
-            L[tri(i, j)] = make_double2(v.x * inv, v.y * inv);
-        }
-        __syncthreads();
-        // trailing update L[i][k] -= L[i][j] conj(L[k][j]): a row per group of G
-        // threads, the group's lanes striding over the row's columns
-        {
-            constexpr int G = NT / 128;
-            const int sub = tid % G;
-            for (int i = j + 1 + tid / G; i < N; i += NT / G) {
-                const double2 lij = L[tri(i, j)];
-                const int base = tri(i, 0);
-                for (int k = j + 1 + sub; k <= i; k += G) {
-                    const double2 lkj = L[tri(k, j)];
-                    const double2 u = zmulc(lij, lkj);
-                    const double2 w = L[base + k];
-                    L[base + k] = make_double2(w.x - u.x, w.y - u.y);
-                }
+        const double rd = 1.0 / d;
+        // a row per group of G threads, the group's lanes striding over the row's columns
+        for (int i = j + 1 + tid / G; i < N; i += NT / G) {
+            const double2 lij = L[tri(i, j)];
+            const double2 s_ = make_double2(lij.x * rd, lij.y * rd);
+            const int base = tri(i, 0);
+            for (int k = j + 1 + sub; k <= i; k += G) {
+                const double2 u = zmulc(s_, L[tri(k, j)]);
+                const double2 w = L[base + k];
+                L[base + k] = make_double2(w.x - u.x, w.y - u.y);
             }
         }
         __syncthreads();
     }
-    if (tid == 0 && bad) status[0] = bad;
-    if (bad) return;
+    for (int k = tid; k < N; k += NT) sd[k] = 1.0 / sqrt(L[tri(k, k)].x);
+    __syncthreads();
+    for (int q = tid; q < N * (N + 1) / 2; q += NT) {
+        int i, k;
+        tri_rc(q, i, k);
+        const double f = sd[k];
+        L[q] = make_double2(L[q].x * f, L[q].y * f);
+    }
+    __syncthreads();
     // in-place inverse: column j of L^{-1} from columns > j (already inverted);
     // each row's dot product is split over a group of G lanes and summed by shuffles
     for (int j = N - 1; j >= 0; --j) {
