@@ -99,88 +99,92 @@ void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, 
 }
 
 // ---------------------------------------------------------------------------
-// projection partials: partial[s][p][b] = sum over G chunk s of conj(beta) psi.
-// Workgroup: 128 projectors (32 per wave) x NBLK*16 bands; grid (M tiles, splits).
+// projection partials: partial[s][b][p] = sum over G chunk s of conj(beta) psi.
+// Workgroup: NW*16 projectors (16 per wave) x NBLK*16 bands; grid (M tiles,
+// splits).  The next stage's projector fragments and band pieces are loaded into
+// registers while the current stage is multiplied.
 // ---------------------------------------------------------------------------
-template <int NBLK>
-__global__ __launch_bounds__(256) void proj16_partial(int M, int N, const uint16_t *__restrict__ Br,
-                                                      const uint16_t *__restrict__ Bi, int64_t ldg,
-                                                      const uint16_t *__restrict__ Pr,
-                                                      const uint16_t *__restrict__ Pi, int kchunk,
-                                                      float2 *__restrict__ partial) {
-    constexpr int NB = NBLK * 16;
+template <int NBLK, int NW>
+__global__ __launch_bounds__(NW * 64) void proj16_partial(int M, int N, const uint16_t *__restrict__ Br,
+                                                          const uint16_t *__restrict__ Bi, int64_t ldg,
+                                                          const uint16_t *__restrict__ Pr,
+                                                          const uint16_t *__restrict__ Pi, int kchunk,
+                                                          float2 *__restrict__ partial) {
+    constexpr int NB = NBLK * 16, NT = NW * 64;
+    constexpr int PPT = (NB * (KS / 8) + NT - 1) / NT;   // 16-byte band pieces per thread and plane
     __shared__ __attribute__((aligned(16))) uint16_t sPr[NB][LPAD], sPi[NB][LPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.x * 128 + wave * 32;
+    const int m0 = blockIdx.x * (NW * 16) + wave * 16;
     const int s = blockIdx.y;
     const int kbeg = s * kchunk;
     const int kend = (int)min((int64_t)kbeg + kchunk, ldg);
-    v4f ar_[2][NBLK], ai_[2][NBLK];
+    v4f ar_[NBLK], ai_[NBLK];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < NBLK; ++j) { ar_[j] = v4f{0, 0, 0, 0}; ai_[j] = v4f{0, 0, 0, 0}; }
+    const int64_t rowA = m0 + (lane & 15);
+    const bool okA = rowA < M;
+    bf16x8 fa_r[2], fa_i[2];
+    uint4 pr_n[PPT], pi_n[PPT];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int j = 0; j < NBLK; ++j) { ar_[i][j] = v4f{0, 0, 0, 0}; ai_[i][j] = v4f{0, 0, 0, 0}; }
-    const int64_t rowA[2] = {(int64_t)(m0 + (lane & 15)), (int64_t)(m0 + 16 + (lane & 15))};
-    const bool okA[2] = {rowA[0] < M, rowA[1] < M};
-    for (int k0 = kbeg; k0 < kend; k0 += KS) {
-        // projector fragments of this stage, straight from memory
-        bf16x8 fa_r[2][2], fa_i[2][2];
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int64_t off = rowA[i] * ldg + k0 + ks * 32 + 8 * (lane >> 4);
-                fa_r[ks][i] = okA[i] ? load8(Br + off) : zero8();
-                fa_i[ks][i] = okA[i] ? load8(Bi + off) : zero8();
-            }
-        // band tile: NB rows x KS bf16 per plane, 16-byte pieces
-        for (int e = tid; e < NB * (KS / 8); e += 256) {
-            const int r = e >> 3, c8 = (e & 7) * 8;
-            uint4 vr = make_uint4(0, 0, 0, 0), vi = make_uint4(0, 0, 0, 0);
-            if (r < N) {
-                vr = *reinterpret_cast<const uint4 *>(Pr + (int64_t)r * ldg + k0 + c8);
-                vi = *reinterpret_cast<const uint4 *>(Pi + (int64_t)r * ldg + k0 + c8);
-            }
-            *reinterpret_cast<uint4 *>(&sPr[r][c8]) = vr;
-            *reinterpret_cast<uint4 *>(&sPi[r][c8]) = vi;
+        for (int ks = 0; ks < 2; ++ks) {
+            const int64_t off = rowA * ldg + k0 + ks * 32 + 8 * (lane >> 4);
+            fa_r[ks] = okA ? load8(Br + off) : zero8();
+            fa_i[ks] = okA ? load8(Bi + off) : zero8();
         }
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+            const int e = tid + t * NT, r = e >> 3, c8 = (e & 7) * 8;
+            pr_n[t] = make_uint4(0, 0, 0, 0);
+            pi_n[t] = make_uint4(0, 0, 0, 0);
+            if (e < NB * (KS / 8) && r < N) {
+                pr_n[t] = *reinterpret_cast<const uint4 *>(Pr + (int64_t)r * ldg + k0 + c8);
+                pi_n[t] = *reinterpret_cast<const uint4 *>(Pi + (int64_t)r * ldg + k0 + c8);
+            }
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+            const int e = tid + t * NT, r = e >> 3, c8 = (e & 7) * 8;
+            if (e < NB * (KS / 8)) {
+                *reinterpret_cast<uint4 *>(&sPr[r][c8]) = pr_n[t];
+                *reinterpret_cast<uint4 *>(&sPi[r][c8]) = pi_n[t];
+            }
+        }
+        const bf16x8 ca_r[2] = {fa_r[0], fa_r[1]}, ca_i[2] = {fa_i[0], fa_i[1]};
         __syncthreads();
+        if (k0 + KS < kend) fetch(k0 + KS);
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             const int kk = ks * 32 + 8 * (lane >> 4);
-            bf16x8 nai[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) nai[i] = neg8(fa_i[ks][i]);
+            const bf16x8 nai = neg8(ca_i[ks]);
 #pragma unroll
             for (int j = 0; j < NBLK; ++j) {
                 const int row = j * 16 + (lane & 15);
                 const bf16x8 br = load8(&sPr[row][kk]), bi = load8(&sPi[row][kk]);
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
-                    ar_[i][j] = mfma_bf16(fa_r[ks][i], br, ar_[i][j]);
-                    ar_[i][j] = mfma_bf16(fa_i[ks][i], bi, ar_[i][j]);
-                    ai_[i][j] = mfma_bf16(fa_r[ks][i], bi, ai_[i][j]);
-                    ai_[i][j] = mfma_bf16(nai[i], br, ai_[i][j]);
-                }
+                // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
+                ar_[j] = mfma_bf16(ca_r[ks], br, ar_[j]);
+                ar_[j] = mfma_bf16(ca_i[ks], bi, ar_[j]);
+                ai_[j] = mfma_bf16(ca_r[ks], bi, ai_[j]);
+                ai_[j] = mfma_bf16(nai, br, ai_[j]);
             }
         }
         __syncthreads();
     }
     float2 *P = partial + (int64_t)s * M * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < NBLK; ++j)
 #pragma unroll
-        for (int j = 0; j < NBLK; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = m0 + i * 16 + 4 * (lane >> 4) + v;
-                const int col = j * 16 + (lane & 15);
-                if (row < M && col < N) P[(int64_t)row * N + col] = make_float2(ar_[i][j][v], ai_[i][j][v]);
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int row = m0 + 4 * (lane >> 4) + v;
+            const int col = j * 16 + (lane & 15);
+            if (row < M && col < N) P[(int64_t)col * M + row] = make_float2(ar_[j][v], ai_[j][v]);
+        }
 }
 
-// W planes [b][ldp] = bf16(d[p] * sum_s partial[s][p][b]), zero for p >= M
+// W planes [b][ldp] = bf16(d[p] * sum_s partial[s][b][p]), zero for p >= M
 __global__ void proj16_reduce(int M, int N, int nsplit, const float2 *__restrict__ partial,
                               const float *__restrict__ d, int64_t ldp, uint16_t *__restrict__ Wr,
                               uint16_t *__restrict__ Wi) {
@@ -191,7 +195,7 @@ __global__ void proj16_reduce(int M, int N, int nsplit, const float2 *__restrict
     if (m < M) {
         double sr = 0, si = 0;
         for (int s = 0; s < nsplit; ++s) {
-            const float2 v = partial[(int64_t)s * M * N + (int64_t)m * N + n];
+            const float2 v = partial[(int64_t)s * M * N + (int64_t)n * M + m];
             sr += v.x;
             si += v.y;
         }
@@ -205,46 +209,58 @@ __global__ void proj16_reduce(int M, int N, int nsplit, const float2 *__restrict
 
 // ---------------------------------------------------------------------------
 // back-projection: out[b][G] += sum_p W[b][p] beta_p(G), W from the BF16 planes.
-// Workgroup: NBLK*16 bands x 128 plane waves (32 per wave); grid: G tiles.
+// Workgroup: NBLK*16 bands x NW*16 plane waves (16 per wave); grid: G tiles.  The
+// next stage's table fragments and W pieces are loaded into registers while the
+// current stage is multiplied.
 // ---------------------------------------------------------------------------
-template <int NBLK>
-__global__ __launch_bounds__(256) void backproj16(int N, int J, int64_t ldp, const uint16_t *__restrict__ Wr,
-                                                  const uint16_t *__restrict__ Wi, const uint16_t *__restrict__ Tr,
-                                                  const uint16_t *__restrict__ Ti, float2 *__restrict__ out,
-                                                  int64_t ldo) {
-    constexpr int NB = NBLK * 16;
+template <int NBLK, int NW>
+__global__ __launch_bounds__(NW * 64) void backproj16(int N, int J, int64_t ldp, const uint16_t *__restrict__ Wr,
+                                                      const uint16_t *__restrict__ Wi,
+                                                      const uint16_t *__restrict__ Tr,
+                                                      const uint16_t *__restrict__ Ti, float2 *__restrict__ out,
+                                                      int64_t ldo) {
+    constexpr int NB = NBLK * 16, NT = NW * 64;
+    constexpr int WPT = (NB * (KS / 8) + NT - 1) / NT;   // 16-byte W pieces per thread and plane
     __shared__ __attribute__((aligned(16))) uint16_t sWr[NB][LPAD], sWi[NB][LPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int j0 = blockIdx.x * 128 + wave * 32;
-    v4f ar_[NBLK][2], ai_[NBLK][2];
+    const int64_t gcol = (int64_t)blockIdx.x * (NW * 16) + wave * 16 + (lane & 15);
+    const bool okB = gcol < J;
+    v4f ar_[NBLK], ai_[NBLK];
 #pragma unroll
-    for (int i = 0; i < NBLK; ++i)
+    for (int i = 0; i < NBLK; ++i) { ar_[i] = v4f{0, 0, 0, 0}; ai_[i] = v4f{0, 0, 0, 0}; }
+    bf16x8 fb_r[2], fb_i[2];
+    uint4 wr_n[WPT], wi_n[WPT];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) { ar_[i][j] = v4f{0, 0, 0, 0}; ai_[i][j] = v4f{0, 0, 0, 0}; }
-    const int64_t gcol[2] = {(int64_t)(j0 + (lane & 15)), (int64_t)(j0 + 16 + (lane & 15))};
-    const bool okB[2] = {gcol[0] < J, gcol[1] < J};
-    for (int k0 = 0; k0 < ldp; k0 += KS) {
-        // table fragments (betaT rows are plane waves), straight from memory
-        bf16x8 fb_r[2][2], fb_i[2][2];
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int64_t off = gcol[j] * ldp + k0 + ks * 32 + 8 * (lane >> 4);
-                fb_r[ks][j] = okB[j] ? load8(Tr + off) : zero8();
-                fb_i[ks][j] = okB[j] ? load8(Ti + off) : zero8();
-            }
-        for (int e = tid; e < NB * (KS / 8); e += 256) {
-            const int r = e >> 3, c8 = (e & 7) * 8;
-            uint4 vr = make_uint4(0, 0, 0, 0), vi = make_uint4(0, 0, 0, 0);
-            if (r < N) {
-                vr = *reinterpret_cast<const uint4 *>(Wr + (int64_t)r * ldp + k0 + c8);
-                vi = *reinterpret_cast<const uint4 *>(Wi + (int64_t)r * ldp + k0 + c8);
-            }
-            *reinterpret_cast<uint4 *>(&sWr[r][c8]) = vr;
-            *reinterpret_cast<uint4 *>(&sWi[r][c8]) = vi;
+        for (int ks = 0; ks < 2; ++ks) {
+            const int64_t off = gcol * ldp + k0 + ks * 32 + 8 * (lane >> 4);
+            fb_r[ks] = okB ? load8(Tr + off) : zero8();
+            fb_i[ks] = okB ? load8(Ti + off) : zero8();
         }
+#pragma unroll
+        for (int t = 0; t < WPT; ++t) {
+            const int e = tid + t * NT, r = e >> 3, c8 = (e & 7) * 8;
+            wr_n[t] = make_uint4(0, 0, 0, 0);
+            wi_n[t] = make_uint4(0, 0, 0, 0);
+            if (e < NB * (KS / 8) && r < N) {
+                wr_n[t] = *reinterpret_cast<const uint4 *>(Wr + (int64_t)r * ldp + k0 + c8);
+                wi_n[t] = *reinterpret_cast<const uint4 *>(Wi + (int64_t)r * ldp + k0 + c8);
+            }
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < ldp; k0 += KS) {
+#pragma unroll
+        for (int t = 0; t < WPT; ++t) {
+            const int e = tid + t * NT, r = e >> 3, c8 = (e & 7) * 8;
+            if (e < NB * (KS / 8)) {
+                *reinterpret_cast<uint4 *>(&sWr[r][c8]) = wr_n[t];
+                *reinterpret_cast<uint4 *>(&sWi[r][c8]) = wi_n[t];
+            }
+        }
+        const bf16x8 cb_r[2] = {fb_r[0], fb_r[1]}, cb_i[2] = {fb_i[0], fb_i[1]};
         __syncthreads();
+        if (k0 + KS < ldp) fetch(k0 + KS);
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             const int kk = ks * 32 + 8 * (lane >> 4);
@@ -252,15 +268,11 @@ __global__ __launch_bounds__(256) void backproj16(int N, int J, int64_t ldp, con
             for (int i = 0; i < NBLK; ++i) {
                 const int row = i * 16 + (lane & 15);
                 const bf16x8 wr = load8(&sWr[row][kk]), wi = load8(&sWi[row][kk]);
-                const bf16x8 nwi = neg8(wi);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    // W beta: re = wr br - wi bi, im = wr bi + wi br
-                    ar_[i][j] = mfma_bf16(wr, fb_r[ks][j], ar_[i][j]);
-                    ar_[i][j] = mfma_bf16(nwi, fb_i[ks][j], ar_[i][j]);
-                    ai_[i][j] = mfma_bf16(wr, fb_i[ks][j], ai_[i][j]);
-                    ai_[i][j] = mfma_bf16(wi, fb_r[ks][j], ai_[i][j]);
-                }
+                // W beta: re = wr br - wi bi, im = wr bi + wi br
+                ar_[i] = mfma_bf16(wr, cb_r[ks], ar_[i]);
+                ar_[i] = mfma_bf16(neg8(wi), cb_i[ks], ar_[i]);
+                ai_[i] = mfma_bf16(wr, cb_i[ks], ai_[i]);
+                ai_[i] = mfma_bf16(wi, cb_r[ks], ai_[i]);
             }
         }
         __syncthreads();
@@ -268,17 +280,14 @@ __global__ __launch_bounds__(256) void backproj16(int N, int J, int64_t ldp, con
 #pragma unroll
     for (int i = 0; i < NBLK; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = i * 16 + 4 * (lane >> 4) + v;
-                const int64_t g = gcol[j];
-                if (b < N && g < J) {
-                    float2 *o = out + (int64_t)b * ldo + g;
-                    const float2 old = *o;
-                    *o = make_float2(old.x + ar_[i][j][v], old.y + ai_[i][j][v]);
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int b = i * 16 + 4 * (lane >> 4) + v;
+            if (b < N && okB) {
+                float2 *o = out + (int64_t)b * ldo + gcol;
+                const float2 old = *o;
+                *o = make_float2(old.x + ar_[i][v], old.y + ai_[i][v]);
             }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -287,8 +296,10 @@ __global__ __launch_bounds__(256) void backproj16(int N, int J, int64_t ldp, con
 static int band_blocks(int nb) { return nb <= 64 ? 4 : nb <= 128 ? 8 : 9; }
 static int band_chunk(int nb) { return nb <= MAXNB ? nb : 128; }
 
+constexpr int kB16ProjNW = 4;   // waves (16 projectors each) per projection workgroup
+
 static int proj_splits(int M, int64_t ldg) {
-    const int mt = (M + 127) / 128;
+    const int mt = (M + 16 * kB16ProjNW - 1) / (16 * kB16ProjNW);
     int s = (512 + mt - 1) / mt;
     const int maxs = (int)((ldg + 2 * KS - 1) / (2 * KS));      // at least two stages per split
     return std::max(1, std::min(s, maxs));
@@ -309,16 +320,19 @@ static void proj_go(int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_
     int kchunk = (int)((ldg + ns - 1) / ns);
     kchunk = (kchunk + KS - 1) / KS * KS;
     nsplit = (int)((ldg + kchunk - 1) / kchunk);
-    dim3 grid((M + 127) / 128, nsplit);
-    hipLaunchKernelGGL(proj16_partial<NBLK>, grid, dim3(256), 0, st, M, N, Br, Bi, ldg, Pr, Pi, kchunk, partial);
+    dim3 grid((M + 16 * kB16ProjNW - 1) / (16 * kB16ProjNW), nsplit);
+    hipLaunchKernelGGL((proj16_partial<NBLK, kB16ProjNW>), grid, dim3(64 * kB16ProjNW), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
+                       kchunk, partial);
     PW_LAUNCH_CHECK();
 }
+
+constexpr int kB16BackNW = 4;   // waves (16 plane waves each) per back-projection workgroup
 
 template <int NBLK>
 static void back_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
                     const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
-    hipLaunchKernelGGL(backproj16<NBLK>, dim3((J + 127) / 128), dim3(256), 0, st, N, J, ldp, Wr, Wi, Tr, Ti, out,
-                       ldo);
+    hipLaunchKernelGGL((backproj16<NBLK, kB16BackNW>), dim3((J + 16 * kB16BackNW - 1) / (16 * kB16BackNW)),
+                       dim3(64 * kB16BackNW), 0, st, N, J, ldp, Wr, Wi, Tr, Ti, out, ldo);
     PW_LAUNCH_CHECK();
 }
 
