@@ -104,10 +104,13 @@ SOLVE_LEGS = (("fp64_tpa", 0, 0), ("fp64_mg", 0, 1), ("mixed_tpa", 1, 0), ("mixe
               ("mixed_learned", 1, 2))
 
 
-def solve_legs(ctx, prob, nb, nconv, legs, maxit=4000, log=None):
+def solve_legs(ctx, prob, nb, nconv, legs, seeds=(0, 5, 9), maxit=4000, log=None):
     """Folded-CG time to max Delta_i <= 1e-6 (FP64 H psi residuals, final H
-    Rayleigh-Ritz) from the same seeded start for each (name, precision,
-    preconditioner); the learned network comes from the committed weights."""
+    Rayleigh-Ritz) for each (name, precision, preconditioner) from the same seeded
+    starts; the step count of a folded solve swings by 10-20% with small
+    perturbations (the search for the last wanted states), so each leg reports the
+    median over `seeds`.  The learned network comes from the committed weights."""
+    import statistics
     import numpy as np
     import torch
     import paper_1907_06821_amd as pw
@@ -119,33 +122,41 @@ def solve_legs(ctx, prob, nb, nconv, legs, maxit=4000, log=None):
         pw.mlp_set(ctx, w)
         with open(wpath + ".json") as f:
             meta = json.load(f)
-    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
-    out, ref = {}, None
+    out, ref = {}, {}
     for name, precision, precond in legs:
         if precond == 2 and meta is None:
             out[name] = {"skipped": "no trained weights"}
             continue
-        psi = psi0.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=maxit, check_every=20,
-                                          precision=precision, precond=precond, nconv=nconv,
-                                          raise_on_noconv=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        near = np.sort(eig[np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv]])
-        if ref is None:
-            ref = near
-        out[name] = {"seconds": round(dt, 3), "iters": st["iters"], "n_hpsi": st["n_hpsi"],
-                     "converged": bool(st["converged"]), "max_resid": st["max_resid"],
+        runs = []
+        for seed in seeds:
+            psi = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=seed)).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=maxit, check_every=20,
+                                              precision=precision, precond=precond, nconv=nconv,
+                                              raise_on_noconv=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            near = np.sort(eig[np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv]])
+            ref.setdefault(seed, near)
+            runs.append({"seed": seed, "seconds": round(dt, 3), "iters": st["iters"], "n_hpsi": st["n_hpsi"],
+                         "converged": bool(st["converged"]), "max_resid": st["max_resid"],
+                         "max_eig_diff_vs_first_leg": float(np.max(np.abs(near - ref[seed])))})
+        out[name] = {"seconds": statistics.median(r["seconds"] for r in runs),
+                     "iters": statistics.median(r["iters"] for r in runs),
+                     "converged": all(r["converged"] for r in runs),
                      "precision": "mixed" if precision else "fp64", "precond": ("tpa", "mg", "learned")[precond],
-                     "max_eig_diff_vs_first": float(np.max(np.abs(near - ref)))}
+                     "per_seed": runs}
         if log:
             log(f"solve {name}: {out[name]}")
-    res = {"tol": 1e-6, "bands": nb, "nconv": nconv, "e_ref": prob.e_ref, "legs": out}
+    res = {"tol": 1e-6, "bands": nb, "nconv": nconv, "e_ref": prob.e_ref, "seeds": list(seeds),
+           "statistic": "median over seeds", "legs": out}
     base, best = out.get("fp64_tpa", {}), out.get("mixed_learned", {})
     if base.get("converged") and best.get("converged"):
         res["speedup_mixed_learned_vs_fp64_tpa"] = round(base["seconds"] / best["seconds"], 3)
+    mg = out.get("mixed_mg", {})
+    if mg.get("converged") and best.get("converged"):
+        res["speedup_mixed_learned_vs_mixed_mg"] = round(mg["seconds"] / best["seconds"], 3)
     if meta is not None:
         res["training"] = {k: meta[k] for k in ("harvest_seconds", "train_seconds", "train_steps", "loss_first",
                                                  "loss_last", "samples")}
