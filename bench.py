@@ -13,9 +13,10 @@ with Gaussian wells and 4 Kleinman-Bylander projectors per atom, 128 bands
 nearest E_ref = 0.3 Ha, complex128.
 
 Second part of the metric ("solve"): folded-CG time to max_i Delta_i <= 1e-6
-for the 128 states nearest E_ref (8 buffer bands, the same seeded start) with
-FP64 H psi + Teter-Payne-Allan, FP64 + the paper's M(G), mixed precision with
-TPA, with M(G) and with the learned preconditioner (K_TPA^2 e^f) (weights trained by
+for the 128 states nearest E_ref (8 buffer bands; median over three seeded
+starts, every leg from the same starts) with FP64 H psi + Teter-Payne-Allan,
+FP64 + the paper's M(G), mixed precision with TPA, with M(G) and with the
+learned preconditioner (M(G) e^f; weights trained by
 paper_1907_06821_amd.train_precond and committed); time includes MLP inference,
 training time is reported separately.
 

@@ -56,7 +56,7 @@ void shell_tables(int nshell, int nb, int npw, const int32_t *shell_off, const i
 
 // blas1.hip -------------------------------------------------------------------
 struct PrecArgs {
-    int kind;                 // 0 TPA^2, 1 paper M(G), 2 TPA^2 * exp(f[shell][band])
+    int kind;                 // 0 TPA^2, 1 paper M(G), 2 M(G) * exp(f[shell][band])
     const double *kin;        // [npw]
     const double *tband;      // [nb] band kinetic energies (TPA)
     double e_ref, de2;        // M(G)
