@@ -61,3 +61,31 @@ def test_every_fft_candidate_matches_oracle(torch_cuda, which):
             pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0, "radix": r["radix"]}, dtype=dtype)
         with pytest.raises(pw.PwError):
             pw.fft_choose(ctx, {"pass_": 1, "kind": 2, "nthr": 100, "sched": 0}, dtype=dtype)
+
+
+def test_gemm_tiles_at_136_bands(torch_cuda):
+    """Every back-projection and block-rotation tile at 136 bands (row tiles of
+    64, 128 and 144 with a ragged last tile): H psi against the oracle and the
+    Gram/Cholesky orthonormalisation against its definition."""
+    import paper_1907_06821_amd as pw
+    prob = synth.batched_problems(4, seed=3)[1]              # 48^3 cube
+    op = oracle_for(prob)
+    nb = 136
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128)
+    assert op.npw > nb
+    c = random_block(12, nb, op.npw)
+    ref = op.apply(c, shift=prob.e_ref)
+    recs = [r for r in pw.autotune(ctx, nb, dtype=pw.PW_C128, reps=1) if r["pass_"] in (4, 5)]
+    assert len(recs) == 24
+    for r in recs:
+        pw.fft_choose(ctx, r)
+        if r["pass_"] == 4:
+            got = pw.hpsi(ctx, to_dev(c), shift=prob.e_ref).cpu().numpy()
+            assert rel_err(got, ref) < 1e-12, r
+        else:
+            q = pw.orthonormalize(ctx, to_dev(c)).cpu().numpy()
+            assert np.abs(q.conj() @ q.T - np.eye(nb)).max() < 1e-12, r
+            coef = q.conj() @ c.T
+            assert np.abs(np.tril(coef, -1)).max() < 1e-11 * np.abs(coef).max(), r
+            assert rel_err(coef.T @ q, c) < 1e-12, r
+        pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0, "radix": r["radix"]})
