@@ -23,6 +23,8 @@
 
 namespace pw {
 
+constexpr int kZpf = 4;   // sphere coefficients per thread loaded ahead in the inverse z pass
+
 struct ZArgs {
     FftPlan plan;             // length N2
     int n2, ncols, cb, nb;
@@ -59,12 +61,26 @@ __global__ __launch_bounds__(NTHR) void zpass_inv(ZArgs a, const cplx<T> *__rest
     const int c1 = min(c0 + a.cb, a.ncols);
     const int nc = c1 - c0;
     const int rs = n2 + 1;
+    // the first kZpf coefficients per thread are loaded before the zero fill, so
+    // that their latency overlaps it
+    const int g0 = a.colstart[c0], g1 = a.colstart[c1];
+    const cplx<T> *src = psi + (int64_t)b * ld;
+    cplx<T> pv[kZpf];
+    int pz[kZpf];
+#pragma unroll
+    for (int j = 0; j < kZpf; ++j) {
+        const int g = g0 + threadIdx.x + j * NTHR;
+        const bool in = g < g1;
+        pv[j] = in ? src[g] : cmake<T>(0, 0);
+        pz[j] = in ? a.zmap[g] : -1;
+    }
     load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw), n2);
     for (int i = threadIdx.x; i < nc * rs; i += NTHR) buf[i] = cmake<T>(0, 0);
     __syncthreads();
-    const int g0 = a.colstart[c0], g1 = a.colstart[c1];
-    const cplx<T> *src = psi + (int64_t)b * ld;
-    for (int g = g0 + threadIdx.x; g < g1; g += NTHR) buf[a.zmap[g]] = src[g];
+#pragma unroll
+    for (int j = 0; j < kZpf; ++j)
+        if (pz[j] >= 0) buf[pz[j]] = pv[j];
+    for (int g = g0 + threadIdx.x + kZpf * NTHR; g < g1; g += NTHR) buf[a.zmap[g]] = src[g];
     __syncthreads();
     FftGeom geo{n2, nc, 1, rs, 0, nc};
     LZ::template fft<T, NTHR, 0>(buf, a.plan, geo, tw, +1);
