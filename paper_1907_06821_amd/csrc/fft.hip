@@ -23,7 +23,8 @@
 
 namespace pw {
 
-constexpr int kZpf = 4;   // sphere coefficients per thread loaded ahead in the inverse z pass
+constexpr int kZpf = 4;    // sphere coefficients per thread loaded ahead in the inverse z pass
+constexpr int kZcb = 16;   // columns per z-pass workgroup (pw_ctx::cb)
 
 struct ZArgs {
     FftPlan plan;             // length N2
@@ -111,9 +112,28 @@ __global__ __launch_bounds__(NTHR) void zpass_fwd(ZArgs a, const cplx<T> *__rest
     const int rs = n2 + 1;
     load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw), n2);
     const cplx<T> *src = cols + (int64_t)b * n2 * a.ncols + c0;
-    for (int e = threadIdx.x; e < nc * n2; e += NTHR) {
-        const int z = e / nc, ci = e - z * nc;
-        buf[ci * rs + z] = src[(int64_t)z * a.ncols + ci];
+    if constexpr (LZ::N > 0) {
+        // compile-time length: every load of the block is issued before the first
+        // LDS store (nc <= kZcb, checked on the host)
+        constexpr int PER = (kZcb * LZ::N + NTHR - 1) / NTHR;
+        cplx<T> v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * NTHR;
+            const int z = e / nc, ci = e - z * nc;
+            v[q] = e < nc * n2 ? src[(int64_t)z * a.ncols + ci] : cmake<T>(0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * NTHR;
+            const int z = e / nc, ci = e - z * nc;
+            if (e < nc * n2) buf[ci * rs + z] = v[q];
+        }
+    } else {
+        for (int e = threadIdx.x; e < nc * n2; e += NTHR) {
+            const int z = e / nc, ci = e - z * nc;
+            buf[ci * rs + z] = src[(int64_t)z * a.ncols + ci];
+        }
     }
     __syncthreads();
     FftGeom geo{n2, nc, 1, rs, 0, nc};
@@ -469,7 +489,6 @@ static void zfwd_go(const ZArgs &a, int ncb, int nb, size_t lds, hipStream_t s, 
                        shift, scale, reinterpret_cast<cplx<T> *>(out), ldo);
 }
 
-constexpr int kZcb = 16;   // columns per z-pass workgroup (pw_ctx::cb)
 
 template <typename T> static FftChoice &choice_of(pw_ctx *ctx, int pass) {
     FftTune &t = ctx->tune[sizeof(T) == 8 ? 0 : 1];
