@@ -112,14 +112,15 @@ __device__ inline void tri_rc(int q, int &i, int &k) {
 // L_ij conj(L_kj) / L_jj from the trailing triangle (rows i > j, columns j < k <= i)
 // and leaves column j unscaled, so one barrier per column suffices (column j is
 // read, never written, in step j).  Then every column k is divided by sqrt(L_kk),
-// which turns the diagonal into sqrt(L_kk) as well.  Inverse in place, column by
-// column from the last.
+// which turns the diagonal into sqrt(L_kk) as well.  Inverse in place by block
+// rows of 16 (nine barrier rounds at N = 136 instead of two per column).
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
                                                           double2 *__restrict__ T, int *__restrict__ status) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);
     __shared__ double sd[kLdsMaxN];
+    __shared__ double2 dinv[16][17];
     const int tid = threadIdx.x;
     for (int q = tid; q < N * (N + 1) / 2; q += NT) {   // every load in flight at once
         int i, k;
@@ -158,41 +159,81 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
         L[q] = make_double2(L[q].x * f, L[q].y * f);
     }
     __syncthreads();
-    // in-place inverse: column j of L^{-1} from columns > j (already inverted);
-    // each row's dot product is split over a group of G lanes and summed by shuffles
-    for (int j = N - 1; j >= 0; --j) {
-        constexpr int G = NT / 128;
-        const double djj = 1.0 / L[tri(j, j)].x;
-        const int sub = tid % G;
-        double rr[2], ri[2];
-        // rows j+1+tid/G and j+1+tid/G+128 (N <= 256)
+    // in-place inverse X = L^{-1} by block rows of BS: for block row I, with rows
+    // above already holding X,
+    //   X_II = inv(L_II)                         (one thread per column of the block)
+    //   X_Ic = -X_II sum_{k = c}^{r0 - 1} L[r0 + ., k] X[k][c]   for every column c < r0
+    // the sums run one output per lane (16 lanes per column, one per row of the block)
+    // and the multiplication by X_II exchanges the column's 16 sums by shuffles.  The
+    // results wait in registers until every read of the block row is done.
+    {
+        constexpr int BS = 16, CPT = 2;              // columns per 16-lane group
+        static_assert(CPT * NT / BS >= (kLdsMaxN - 1) / BS * BS, "columns left of the last block row");
+        const int r = tid % BS, grp = tid / BS;
+        for (int r0 = 0; r0 < N; r0 += BS) {
+            const int nr = min(BS, N - r0);
+            if (tid < BS) {                          // column tid of inv(L_II), forward substitution
+                const int c = tid;                   // unrolled: the block's loads issue ahead of the sums
+                double2 col[BS];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            double ar = 0.0, ai = 0.0;
-            const int i = j + 1 + tid / G + h * (NT / G);
-            if (i < N) {
-                for (int k = j + 1 + sub; k <= i; k += G) {
-                    const double2 a = L[tri(i, k)], b = L[tri(k, j)];   // Linv[i][k], L[k][j]
-                    ar += a.x * b.x - a.y * b.y;
-                    ai += a.x * b.y + a.y * b.x;
+                for (int i = 0; i < BS; ++i) {
+                    double2 acc = make_double2(i == c ? 1.0 : 0.0, 0.0);
+                    if (i < nr) {
+#pragma unroll
+                        for (int q = 0; q < i; ++q)
+                            if (q >= c) {
+                                const double2 u = zmul(L[tri(r0 + i, r0 + q)], col[q]);
+                                acc = make_double2(acc.x - u.x, acc.y - u.y);
+                            }
+                        const double inv = 1.0 / L[tri(r0 + i, r0 + i)].x;
+                        acc = make_double2(acc.x * inv, acc.y * inv);
+                    }
+                    col[i] = i < c ? make_double2(0.0, 0.0) : acc;
                 }
-            }
 #pragma unroll
-            for (int o = G / 2; o > 0; o >>= 1) {
-                ar += __shfl_xor(ar, o, G);
-                ai += __shfl_xor(ai, o, G);
+                for (int i = 0; i < BS; ++i) dinv[i][c] = col[i];
             }
-            rr[h] = ar;
-            ri[h] = ai;
-        }
-        __syncthreads();
+            __syncthreads();
+            double2 xo[CPT];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = j + 1 + tid / G + h * (NT / G);
-            if (i < N && sub == 0) L[tri(i, j)] = make_double2(-rr[h] * djj, -ri[h] * djj);
+            for (int h = 0; h < CPT; ++h) {
+                const int c = grp + h * (NT / BS);   // the same for the group's 16 lanes
+                double2 sacc = make_double2(0.0, 0.0);
+                if (c < r0 && r < nr) {
+                    // four partial sums keep several LDS reads in flight
+                    const int base = tri(r0 + r, 0);
+                    double2 s4[4] = {sacc, sacc, sacc, sacc};
+                    int k = c;
+                    for (; k + 3 < r0; k += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) s4[u] = zfma(L[base + k + u], L[tri(k + u, c)], s4[u]);
+                    }
+                    for (; k < r0; ++k) s4[0] = zfma(L[base + k], L[tri(k, c)], s4[0]);
+                    sacc = make_double2((s4[0].x + s4[1].x) + (s4[2].x + s4[3].x),
+                                        (s4[0].y + s4[1].y) + (s4[2].y + s4[3].y));
+                }
+                double2 x = make_double2(0.0, 0.0);
+                if (c < r0) {
+#pragma unroll
+                    for (int q = 0; q < BS; ++q) {
+                        const double2 sq = make_double2(__shfl(sacc.x, q, BS), __shfl(sacc.y, q, BS));
+                        if (q <= r && r < nr) x = zfma(dinv[r][q], sq, x);
+                    }
+                }
+                xo[h] = make_double2(-x.x, -x.y);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < CPT; ++h) {
+                const int c = grp + h * (NT / BS);
+                if (c < r0 && r < nr) L[tri(r0 + r, c)] = xo[h];
+            }
+            for (int e = tid; e < nr * nr; e += NT) {
+                const int i = e / nr, c = e % nr;
+                if (c <= i) L[tri(r0 + i, r0 + c)] = dinv[i][c];
+            }
+            __syncthreads();
         }
-        if (tid == 0) L[tri(j, j)] = make_double2(djj, 0.0);
-        __syncthreads();
     }
     for (int e = tid; e < N * N; e += NT) {
         const int i = e / N, c = e % N;
