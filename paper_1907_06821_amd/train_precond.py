@@ -82,7 +82,7 @@ def train(ctx, prob, tabs, tband, er, steps, lr, seed=0):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DATA_DIR)
-    ap.add_argument("--energies", default="0.25,0.35")
+    ap.add_argument("--energies", default="0.2,0.25,0.35,0.4")
     ap.add_argument("--start-seed", type=int, default=11)
     ap.add_argument("--bands", type=int, default=136)
     ap.add_argument("--nconv", type=int, default=128)
