@@ -274,9 +274,10 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
 // ---------------------------------------------------------------------------
 // NT tiles: TN = 64 (N <= 64), 128 (N <= 128) or 144 (N <= 144, for 128 wanted
 // bands plus buffer bands), else 128; TM = 128 rows of A when A is tall (the
-// projector table: B is then re-read half as often), else 64.
+// projector table: B is then re-read half as often) or of a square band-by-band
+// product of up to 128 (Gram matrices: one tile), else 64.
 static int nt_tn(int N) { return N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128)); }
-static int nt_tm(int M, int N) { return (M >= 512 && N > 64) ? 128 : 64; }
+static int nt_tm(int M, int N) { return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64; }
 
 // K-splits: enough workgroups to cover the chip (~512) while keeping at least
 // four LDS stages per chunk and the partial sums under 64 MiB.

@@ -89,3 +89,18 @@ def test_gemm_tiles_at_136_bands(torch_cuda):
             assert np.abs(np.tril(coef, -1)).max() < 1e-11 * np.abs(coef).max(), r
             assert rel_err(coef.T @ q, c) < 1e-12, r
         pw.fft_choose(ctx, {"pass_": r["pass_"], "kind": 0, "radix": r["radix"]})
+
+
+@pytest.mark.parametrize("nb", [96, 128])
+def test_gram_single_tile(torch_cuda, nb):
+    """Square band-by-band products of 65..128 bands take one 128 x 128 NT tile:
+    the Gram/Cholesky orthonormalisation against its definition."""
+    import paper_1907_06821_amd as pw
+    prob = synth.batched_problems(4, seed=3)[1]              # 48^3 cube
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128)
+    c = random_block(13, nb, ctx.npw)
+    q = pw.orthonormalize(ctx, to_dev(c)).cpu().numpy()
+    assert np.abs(q.conj() @ q.T - np.eye(nb)).max() < 1e-12
+    coef = q.conj() @ c.T
+    assert np.abs(np.tril(coef, -1)).max() < 1e-11 * np.abs(coef).max()
+    assert rel_err(coef.T @ q, c) < 1e-12
