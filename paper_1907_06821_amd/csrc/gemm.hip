@@ -275,9 +275,13 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
 // NT tiles: TN = 64 (N <= 64), 128 (N <= 128) or 144 (N <= 144, for 128 wanted
 // bands plus buffer bands), else 128; TM = 128 rows of A when A is tall (the
 // projector table: B is then re-read half as often) or of a square band-by-band
-// product of up to 128 (Gram matrices: one tile), else 64.
+// product of up to 128 (Gram matrices: one tile); 48 for square products of
+// 129..144 (three waves of 3 x 3 blocks, 48 x 144 tiles), else 64.
 static int nt_tn(int N) { return N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128)); }
-static int nt_tm(int M, int N) { return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64; }
+static int nt_tm(int M, int N) {
+    if (M == N && M > 128 && M <= 144) return 48;
+    return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
+}
 
 // K-splits: enough workgroups to cover the chip (~512) while keeping at least
 // four LDS stages per chunk and the partial sums under 64 MiB.
@@ -325,6 +329,7 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     dim3 grid((M + tm - 1) / tm, (N + tn - 1) / tn, nsplit);
     if (K <= 0) fill_zero(partial, (size_t)M * N * sizeof(double2), st);
     else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tm == 48) nt_go<1, 3, 3, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tm == 128 && tn == 128) nt_go<4, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tm == 128) nt_go<4, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tn == 128) nt_go<2, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
