@@ -446,6 +446,7 @@ struct DcLds {
     int *perm, *flag, *kept, *org, *ri, *rj, *ctl;
     double *wcs, *wsn;      // per-wave rotation lists of the leaf QL sweeps
     double *dbl;
+    int kc;                 // depth of the product's k chunks
 };
 // depth of the product's k chunks: each chunk holds dc_kc(n) n <= 2048 doubles
 __host__ __device__ inline int dc_kc(int n) { return min(16, 2048 / n); }
@@ -487,7 +488,46 @@ __device__ inline DcLds dc_carve(unsigned char *base, int n, int nwaves, double 
     t.ri = q; q += n;
     t.rj = q; q += n;
     t.ctl = q;
+    t.kc = dc_kc(n);
     return t;
+}
+
+// Levels of the divide and conquer whose merges are at most kDcWaveSpan leaves wide
+// run their merges concurrently, one wave each, with scratch of their own behind
+// the workgroup's (LDS kernel only).
+constexpr int kDcWaveSpan = 4;
+__host__ __device__ inline int dc_leaves(int n) {
+    int P = 1;
+    while ((n + P - 1) / P > kDcLeaf) P *= 2;
+    return P;
+}
+__host__ __device__ inline size_t dc_round(size_t b) { return (b + 255) / 256 * 256; }
+// bytes of one wave's merge scratch at a level of merges `span` leaves wide
+__host__ __device__ inline size_t dc_wave_merge_bytes(int N, int span) {
+    const int P = dc_leaves(N);
+    return dc_round(dc_lds_bytes((span * N + P - 1) / P + 1, 1, true));
+}
+// all of the waves' scratch (the largest level)
+__host__ __device__ inline size_t dc_wave_bytes(int N, int nwaves) {
+    const int P = dc_leaves(N);
+    size_t m = 0;
+    for (int span = 2; span <= kDcWaveSpan && span <= P; span *= 2) {
+        const int nm = P / span;
+        if (nm < 2) break;
+        const size_t b = (size_t)(nm < nwaves ? nm : nwaves) * dc_wave_merge_bytes(N, span);
+        m = b > m ? b : m;
+    }
+    return m;
+}
+
+// workgroup-wide or (NT = 64) wave-wide barrier of the merges
+template <int NT> __device__ __forceinline__ void dc_sync() {
+    if constexpr (NT == 64) {
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
 }
 
 // 1/x: hardware reciprocal estimate refined by two Newton steps (about 1 ulp)
@@ -573,7 +613,7 @@ __device__ inline double secular_root(int i, int K, const double *d, const doubl
 template <int NT>
 __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V, double *Ztmp,
                          const DcLds &t) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x % NT;
     const int n = c - a;
     const double rho = fabs(beta), sg = beta >= 0.0 ? 1.0 : -1.0;
     // z and the ascending order of the block's eigenvalues
@@ -590,7 +630,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
         t.sz[rk] = zj;
         t.perm[rk] = col;
     }
-    __syncthreads();
+    dc_sync<NT>();
     // deflation (one thread, in ascending order)
     if (tid == 0) {
         double nz = 0.0, dmax = 0.0;
@@ -642,7 +682,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
         t.ctl[1] = nrot;
         t.dbl[0] = rhon;
     }
-    __syncthreads();
+    dc_sync<NT>();
     const int K = t.ctl[0], nrot = t.ctl[1];
     const double rhon = t.dbl[0];
     // the deflation's rotations act on the block's eigenvector columns, row by row
@@ -668,7 +708,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
             }
         }
     }
-    __syncthreads();
+    dc_sync<NT>();
     // z recomputed from the roots: zh_j^2 = prod_i (x_i - d_j) / (rho prod_{i != j} (d_i - d_j))
     for (int j = tid; j < K; j += NT) {
         double w = 1.0;
@@ -680,7 +720,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
     }
     // eigenvalues in ascending (sorted) position; deflated ones keep their D
     for (int j = tid; j < n; j += NT) t.lamv[j] = t.sD[j];
-    __syncthreads();
+    dc_sync<NT>();
     for (int i = tid; i < K; i += NT) t.lamv[t.kept[i]] = t.kd[t.org[i]] + t.tau[i];
     // eigenvectors of diag(D) + rho z z^T on the kept set: V[i][j] = zh_j / (d_j - x_i), normalised
     for (int i = tid; i < K; i += NT) {
@@ -695,7 +735,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
         const double inv = 1.0 / sqrt(nrm);
         for (int j = 0; j < K; ++j) V[(int64_t)i * K + j] *= inv;
     }
-    __syncthreads();
+    dc_sync<NT>();
     // new columns in ascending order: deflated ones copied, kept ones (Z_kept V^T):
     // k chunks of Z_kept (rows of the block) and V staged in LDS, each thread
     // accumulating 4 x 4 tiles of the product
@@ -705,7 +745,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
     }
     {
         constexpr int RT = 4;
-        const int KC = dc_kc(N);
+        const int KC = t.kc;
         double *zc = t.gz, *vc = t.gv;                    // [KC][n], [KC][K]
         const int nr = (n + RT - 1) / RT, nc = (K + RT - 1) / RT;
         for (int k0 = 0; k0 < K; k0 += KC) {
@@ -718,7 +758,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
                 const int i = e / kc, jj = e % kc;
                 vc[jj * K + i] = V[(int64_t)i * K + k0 + jj];
             }
-            __syncthreads();
+            dc_sync<NT>();
             for (int tile = tid; tile < nr * nc; tile += NT) {
                 const int r0 = (tile % nr) * RT, c0 = (tile / nr) * RT;
                 double acc[RT][RT];
@@ -750,7 +790,7 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
                     for (int y = 0; y < RT; ++y)
                         if (r0 + x < n && c0 + y < K) Ztmp[(int64_t)t.kept[c0 + y] * n + r0 + x] = acc[x][y];
             }
-            __syncthreads();
+            dc_sync<NT>();
         }
     }
     for (int e = tid; e < n * n; e += NT) {
@@ -758,19 +798,19 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
         Zt[(int64_t)(a + tcol) * N + a + r] = Ztmp[e];
     }
     for (int j = tid; j < n; j += NT) d[a + j] = t.lamv[j];
-    __syncthreads();
+    dc_sync<NT>();
 }
 
 // Eigen-decomposition of the tridiagonal (d, e) into d (eigenvalues) and Zt
 // (global), then eigenvalue order.  e is overwritten.
 template <int NT>
 __device__ void dc_block(int N, double *d, double *e, double *Zt, double *V, double *Ztmp, unsigned char *scratch,
-                         double *gz, double *gv, double *lam, int *rank, int key, double ref, int *info) {
+                         double *gz, double *gv, bool wave_merges, double *lam, int *rank, int key, double ref,
+                         int *info) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const DcLds t = dc_carve(scratch, N, NW, gz, gv);
-    int P = 1;
-    while ((N + P - 1) / P > kDcLeaf) P *= 2;
+    const int P = dc_leaves(N);
     for (int q = tid; q < N * N; q += NT) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
     if (tid == 0) {
         for (int i = 1; i < P; ++i) {
@@ -805,14 +845,34 @@ __device__ void dc_block(int N, double *d, double *e, double *Zt, double *V, dou
         }
     }
     __syncthreads();
-    // merges, level by level
-    for (int span = 2; span <= P; span *= 2)
+    // merges, level by level; narrow levels one wave per merge, each in its own
+    // scratch and in the rows [a, c) of V and Ztmp
+    for (int span = 2; span <= P; span *= 2) {
+        const int nm = P / span;
+        if (wave_merges && span <= kDcWaveSpan && nm >= 2) {
+            const size_t wb = dc_wave_merge_bytes(N, span);
+            const int maxn = (span * N + P - 1) / P + 1;
+            unsigned char *mine = scratch + dc_round(dc_lds_bytes(N, NW, gz == nullptr)) + (size_t)wid * wb;
+            for (int m = wid; m < nm; m += NW) {
+                const int k = m * span;
+                const int a = (int)((int64_t)k * N / P), b = (int)((int64_t)(k + span / 2) * N / P);
+                const int c = (int)((int64_t)(k + span) * N / P);
+                const double be = t.beta[k + span / 2];
+                if (be != 0.0) {
+                    const DcLds tw = dc_carve(mine, maxn, 1, nullptr, nullptr);
+                    dc_merge<64>(N, a, b, c, be, d, Zt, V + (int64_t)a * N, Ztmp + (int64_t)a * N, tw);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
         for (int k = 0; k < P; k += span) {
             const int a = (int)((int64_t)k * N / P), b = (int)((int64_t)(k + span / 2) * N / P);
             const int c = (int)((int64_t)(k + span) * N / P);
             const double be = t.beta[k + span / 2];
             if (be != 0.0) dc_merge<NT>(N, a, b, c, be, d, Zt, V, Ztmp, t);
         }
+    }
     for (int i = tid; i < N; i += NT) {
         const double li = d[i];
         const double ki = key ? fabs(li - ref) : li;
@@ -923,8 +983,8 @@ __global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2
     }
     __syncthreads();
     // the triangle is dead: its LDS becomes the divide and conquer's scratch
-    dc_block<NT>(N, d, e, zg, zg + (size_t)N * N, zg + 2 * (size_t)N * N, smem_raw, nullptr, nullptr, lam, rank, key,
-                 ref, info);
+    dc_block<NT>(N, d, e, zg, zg + (size_t)N * N, zg + 2 * (size_t)N * N, smem_raw, nullptr, nullptr, true, lam, rank,
+                 key, ref, info);
 }
 
 // Same algorithm for N <= kEigMaxN.  Ag: N x N work copy of A (full Hermitian,
@@ -1022,7 +1082,7 @@ __global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const doub
     // the reflector staging v, w (2048 doubles each) holds the product chunks
     double *Zt = reinterpret_cast<double *>(Ag);
     dc_block<NT>(N, d, e, Zt, Zt + 2 * (size_t)N * N, Zt + (size_t)N * N, smem_raw, reinterpret_cast<double *>(v),
-                 reinterpret_cast<double *>(w), lam, rank, key, ref, info);
+                 reinterpret_cast<double *>(w), false, lam, rank, key, ref, info);
 }
 
 // Back-transformation, one wave per eigenvector, NW waves per workgroup.
@@ -1124,7 +1184,8 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
     double2 *hv = (double2 *)work;
     double2 *zbuf = hv + ((size_t)N * (N - 1) / 2 + N);
     int *rank = (int *)((char *)zbuf + (size_t)24 * N * N);
-    const size_t dcb = dc_lds_bytes(N, kEigNT / 64, lds);
+    const size_t dcb = lds ? dc_round(dc_lds_bytes(N, kEigNT / 64, true)) + dc_wave_bytes(N, kEigNT / 64)
+                           : dc_lds_bytes(N, kEigNT / 64, false);
     static size_t attr1 = 64 * 1024, attr2 = 64 * 1024, attr3 = 64 * 1024;
     if (lds) {
         const size_t b1 = std::max((size_t)N * (N + 1) / 2 * sizeof(double2), dcb);
