@@ -14,9 +14,14 @@ stand-ins of the same shape: an fcc wire cut to a cylinder along z, each atom
 carrying a Gaussian local well and four Gaussian Kleinman-Bylander projectors
 (s + three p).
 
+The sources w of the folded linear equation are sums of Gaussian blobs placed
+near the cell's z boundary (the paper's w is nonzero only near the boundary,
+far from the central region, Sec. II.A), given by their closed-form
+plane-wave coefficients at Miller triples the caller supplies.
+
 Seeds: ``numpy.random.default_rng([cfg_id, purpose])`` with purpose
 0 = positions, 1 = D strengths, 2 = start vectors, 3 = vacancies,
-4 = per-problem draws, 5 = network initialisation.
+4 = per-problem draws, 5 = network initialisation, 6 = linear-equation sources.
 """
 from __future__ import annotations
 
@@ -27,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "config", "cubic_random_problem", "fcc_wire_sites",
-    "gaussian_potential_grid", "start_vectors", "CONFIG_NAMES",
+    "gaussian_potential_grid", "start_vectors", "boundary_sources", "CONFIG_NAMES",
 ]
 
 FCC_A = 6.82  # fcc lattice constant (bohr) of the copper-like wire
@@ -147,6 +152,29 @@ def start_vectors(cfg_id, nbands, npw, seed=0):
     x = rng.standard_normal((nbands, npw))
     y = rng.standard_normal((nbands, npw))
     return (x + 1j * y) / math.sqrt(2.0)
+
+
+def boundary_sources(cfg_id, nrhs, miller, cell, kpt=(0.0, 0.0, 0.0), seed=0, nblob=8, width=1.0,
+                     slab=0.1):
+    """Right-hand sides w [nrhs][npw] of the folded linear equation, one unit-norm
+    row per source: w_l(G) proportional to sum_k a_lk exp(-|q|^2 width^2 / 2 - i q.R_lk),
+    q = 2 pi n / L + k, the plane-wave coefficients of Gaussian blobs of the given
+    width centred at R_lk.  Blob centres: x, y uniform over the cell, z within
+    slab * L_z of the plane z = 0 (the cell boundary along the wire); a_lk complex
+    normal.  miller [npw][3] in the caller's coefficient order."""
+    rng = np.random.default_rng([cfg_id, 6, seed])
+    m = np.asarray(miller, dtype=np.float64).reshape(-1, 3)
+    cell = np.asarray(cell, dtype=np.float64)
+    q = 2.0 * np.pi * m / cell[None, :] + np.asarray(kpt, dtype=np.float64)[None, :]
+    env = np.exp(-0.5 * width * width * np.sum(q * q, axis=1))
+    out = np.empty((nrhs, m.shape[0]), dtype=np.complex128)
+    for l in range(nrhs):
+        r = rng.uniform(0.0, 1.0, size=(nblob, 3)) * cell[None, :]
+        r[:, 2] = rng.uniform(-slab, slab, size=nblob) * cell[2]
+        a = (rng.standard_normal(nblob) + 1j * rng.standard_normal(nblob)) / math.sqrt(2.0)
+        w = (np.exp(-1j * (q @ r.T)) @ a) * env
+        out[l] = w / np.linalg.norm(w)
+    return out
 
 
 def _kb_strengths(cfg_id, natom, nl, seed=0):
