@@ -260,6 +260,61 @@ pw_status pw_batch_solve(int32_t nprob, pw_ctx *const *ctx, const double *e_ref,
                          pw_cg_stats *stats, int32_t *status, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Folded linear equation of the system states (Sec. II.A system-state equation,
+ * Sec. II.B folded equation, functional F and preconditioner M').
+ *
+ * Solves (H - E)^2 psi_l = (H - E) w_l for nrhs sources at once by column-wise
+ * preconditioned CG (each column its own step lengths); the error of a column
+ * is the paper's ||(H - E) psi_l - w_l||, and the solve stops when its maximum
+ * over the columns is <= tol.  Preconditioner:
+ *   precond 0: the paper's G-diagonal M(G) = 1 / ((T_G - E)^2 + delta_e^2);
+ *   precond 1: M' built from nev approximate eigenpairs (phi_i, eps_i, Delta_i),
+ *     applied in its Hermitian form
+ *       M' = (1 - P) M (1 - P) + sum_i |phi_i><phi_i| / ((eps_i - E)^2 + Delta_i^2),
+ *     P = sum_i |phi_i><phi_i| (the paper prints M (1 - P) + ..., which is not
+ *     Hermitian unless M commutes with P; both agree on span{phi_i}).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double tol;           /* stop when max_l ||(H - E) psi_l - w_l|| <= tol (paper: 1e-8 a.u.) */
+    int32_t maxit;        /* PCG iterations cap */
+    int32_t precond;      /* 0 M(G), 1 M' (needs nev >= 1 eigenpairs) */
+    double delta_e;       /* dE of M(G) (Ha), > 0 */
+    int32_t check_every;  /* iterations between reads of the error by the host */
+    int32_t verbose;      /* print the error at each check to stderr */
+} pw_lin_opts;
+
+typedef struct {
+    int32_t iters;        /* PCG iterations done */
+    int32_t converged;    /* 1 if the error reached tol at a check */
+    int64_t n_hpsi;       /* band-H psi applications */
+    double max_resid;     /* final max_l ||(H - E) psi_l - w_l|| from a fresh H psi */
+    double seconds;       /* wall time of the solve */
+    int32_t n_hist;       /* in: capacity of hist; out: entries written */
+    double *hist;         /* host, optional: [n_hist][2] = (iteration, max error) */
+} pw_lin_stats;
+
+void pw_lin_opts_default(pw_lin_opts *opts);
+
+/* ctx    complex128 context; nrhs in [1, max_bands].
+ * w      device complex128 [nrhs][ldw], the sources (read only).
+ * psi    device complex128 [nrhs][ld]: in, the start guess (zeros for psi_0 = 0);
+ *        out, the solution.
+ * phi    device complex128 [nev][ldphi], orthonormal approximate eigenvectors
+ *        (e.g. pw_folded_cg_solve's output); used when precond = 1, may be NULL
+ *        with nev = 0 otherwise.
+ * eps, delta  host [nev]: their energies eps_i (Ha) and errors Delta_i =
+ *        ||H phi_i - eps_i phi_i|| (pw_folded_cg_solve's eig and resid).
+ * resid  host [nrhs] (optional): final ||(H - E) psi_l - w_l|| from a fresh H psi.
+ * Allocates its workspace (8 blocks of nrhs x npw complex128, and for M' an
+ * nrhs x nev coefficient set) for the call and frees it at the end.  Returns
+ * PW_ENOCONV (solution and residuals still written) if maxit is reached first.
+ * Synchronises `stream` once per check_every iterations. */
+pw_status pw_folded_linear_solve(pw_ctx *ctx, double e, int32_t nrhs, const void *w, int64_t ldw, void *psi,
+                                 int64_t ld, int32_t nev, const void *phi, int64_t ldphi, const double *eps,
+                                 const double *delta, double *resid, const pw_lin_opts *opts, pw_lin_stats *stats,
+                                 void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned preconditioner (precond = 2).  Not in the paper: a network standing in
  * for the diagonal preconditioner (the paper's is M(G), Sec. II.B).  Per |G+k|
  * shell s and band i, f_si = MLP(T_s/Ecut, T_i/Ecut, E_ref/Ecut), a 3-64-64-1 tanh

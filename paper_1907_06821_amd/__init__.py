@@ -29,7 +29,8 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_orthonormalize", "pw_cg_opts_default", "pw_folded_cg_solve", "pw_dense_eigh",
            "pw_dense_chol_inv", "pw_mlp_set", "pw_mlp_forward", "pw_mlp_harvest", "pw_mlp_work_bytes",
            "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
-           "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose")
+           "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose",
+           "pw_lin_opts_default", "pw_folded_linear_solve")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
 PW_PROF_NKINDS = 8
 
@@ -59,6 +60,16 @@ class pw_cg_opts(C.Structure):
                 ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32),
                 ("mixed_switch", C.c_double), ("stall_checks", C.c_int32), ("snap_buf", C.c_void_p),
                 ("snap_every", C.c_int32), ("snap_cap", C.c_int32), ("nconv", C.c_int32)]
+
+
+class pw_lin_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precond", C.c_int32), ("delta_e", C.c_double),
+                ("check_every", C.c_int32), ("verbose", C.c_int32)]
+
+
+class pw_lin_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_hpsi", C.c_int64), ("max_resid", C.c_double),
+                ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double))]
 
 
 class pw_fft_cand(C.Structure):
@@ -112,6 +123,9 @@ def lib():
             "pw_batch_solve": [i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
             "pw_ctx_autotune": [vp, i32, i32, i32, vp, i32, C.POINTER(i32), vp],
             "pw_ctx_fft_choose": [vp, i32, vp],
+            "pw_folded_linear_solve": [vp, dbl, i32, vp, i64, vp, i64, i32, vp, i64, C.POINTER(dbl),
+                                       C.POINTER(dbl), C.POINTER(dbl), C.POINTER(pw_lin_opts),
+                                       C.POINTER(pw_lin_stats), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -121,6 +135,8 @@ def lib():
         L.pw_mlp_work_bytes.restype = C.c_int64
         L.pw_cg_opts_default.argtypes = [C.POINTER(pw_cg_opts)]
         L.pw_cg_opts_default.restype = None
+        L.pw_lin_opts_default.argtypes = [C.POINTER(pw_lin_opts)]
+        L.pw_lin_opts_default.restype = None
         L.pw_last_error.argtypes = []
         L.pw_last_error.restype = C.c_char_p
         _lib = L
@@ -467,6 +483,58 @@ def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_o
     if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
         _check(status)
     return eig, res, stats
+
+
+def lin_opts(**kw):
+    o = pw_lin_opts()
+    lib().pw_lin_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def folded_linear_solve(ctx, e, w, psi, phi=None, eps=None, delta=None, opts=None, hist_len=0, stream=None,
+                        raise_on_noconv=True, **kw):
+    """PCG on (H - E)^2 psi = (H - E) w for the complex128 sources w [nrhs, npw]
+    (psi: in, start guess; out, solution).  precond=1 builds M' from the
+    eigenpairs (phi [nev, npw] device, eps and delta host arrays [nev]).
+    Returns (resid [nrhs], stats dict)."""
+    import torch
+    for t in (w, psi) + ((phi,) if phi is not None else ()):
+        _check_block(t, ctx.npw)
+        if t.dtype != torch.complex128:
+            raise ValueError("the linear solve takes complex128 blocks")
+    if tuple(w.shape) != tuple(psi.shape):
+        raise ValueError("w and psi must have the same shape")
+    nrhs = psi.shape[0]
+    o = opts if opts is not None else lin_opts(**kw)
+    nev, phi_ptr, ldphi = 0, None, 0
+    eps_a = delta_a = None
+    if phi is not None:
+        nev, phi_ptr, ldphi = phi.shape[0], phi.data_ptr(), phi.stride(0)
+        eps_a = np.ascontiguousarray(eps, dtype=np.float64)
+        delta_a = np.ascontiguousarray(delta, dtype=np.float64)
+        if eps_a.shape != (nev,) or delta_a.shape != (nev,):
+            raise ValueError("eps and delta must have one entry per eigenvector")
+    dp = C.POINTER(C.c_double)
+    res = np.zeros(nrhs)
+    st = pw_lin_stats()
+    hist = np.zeros((max(hist_len, 0), 2))
+    st.n_hist = int(hist_len)
+    st.hist = hist.ctypes.data_as(dp) if hist_len else dp()
+    status = ctx._lib.pw_folded_linear_solve(
+        ctx.handle, float(e), nrhs, C.c_void_p(w.data_ptr()), w.stride(0), C.c_void_p(psi.data_ptr()),
+        psi.stride(0), nev, C.c_void_p(phi_ptr), ldphi,
+        eps_a.ctypes.data_as(dp) if eps_a is not None else dp(),
+        delta_a.ctypes.data_as(dp) if delta_a is not None else dp(),
+        res.ctypes.data_as(dp), C.byref(o), C.byref(st), _stream_ptr(stream))
+    stats = dict(iters=st.iters, converged=bool(st.converged), n_hpsi=st.n_hpsi, max_resid=st.max_resid,
+                 seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status)
+    if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
+        _check(status)
+    return res, stats
 
 
 def batch_solve(ctxs, e_refs, psis, opts=None, hist_len=0, stream=None, raise_on_noconv=True, **kw):

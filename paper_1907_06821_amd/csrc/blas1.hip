@@ -305,6 +305,202 @@ void band_norms(int nb, int npw, const void *X, int64_t ld, double *out, BandRed
 }
 
 // ---------------------------------------------------------------------------
+// Column-wise PCG of the folded linear equation (H - E)^2 x = (H - E) w.  Every
+// column (right-hand side) has its own alpha and beta; the scalars stay on the
+// device, each written by one thread per column.
+
+// alpha = rz / <p, A p> with <p, A p> = ||YP||^2 (YP = (H - E) p)
+__global__ void k_lin_alpha(int nb, int nsplit, const double *__restrict__ partial, const double *__restrict__ rz,
+                            double *__restrict__ alpha) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double pap = 0;
+    for (int k = 0; k < nsplit; ++k) pap += partial[(int64_t)b * nsplit + k];
+    alpha[b] = pap > 0.0 ? rz[b] / pap : 0.0;
+}
+
+void lin_alpha(int nb, int npw, const void *YP, int64_t ld, const double *rz, double *alpha, BandRed r,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_norm2, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)YP, ld, r.partial,
+                       r.nsplit);
+    PW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_lin_alpha, dim3((nb + 255) / 256), dim3(256), 0, st, nb, r.nsplit, r.partial, rz, alpha);
+    PW_LAUNCH_CHECK();
+}
+
+// X += alpha P, Y += alpha YP, R -= alpha AP
+__global__ void k_lin_update(int nb, int npw, double2 *__restrict__ X, double2 *__restrict__ Y,
+                             double2 *__restrict__ R, const double2 *__restrict__ P, const double2 *__restrict__ YP,
+                             const double2 *__restrict__ AP, int64_t ld, const double *__restrict__ alpha) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const double a = alpha[b];
+    const int64_t i = (int64_t)b * ld + g;
+    const double2 p = P[i], yp = YP[i], ap = AP[i];
+    double2 x = X[i], y = Y[i], r = R[i];
+    x.x += a * p.x;  x.y += a * p.y;
+    y.x += a * yp.x; y.y += a * yp.y;
+    r.x -= a * ap.x; r.y -= a * ap.y;
+    X[i] = x;
+    Y[i] = y;
+    R[i] = r;
+}
+
+void lin_update(int nb, int npw, void *X, void *Y, void *R, const void *P, const void *YP, const void *AP, int64_t ld,
+                const double *alpha, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_update, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (double2 *)X,
+                       (double2 *)Y, (double2 *)R, (const double2 *)P, (const double2 *)YP, (const double2 *)AP, ld,
+                       alpha);
+    PW_LAUNCH_CHECK();
+}
+
+// Z = M o (R - U) with the paper's M(G) (U may be null); partial sums of Re<R, Z>
+__global__ __launch_bounds__(RT) void k_lin_mdiag(int nb, int npw, const double2 *__restrict__ R,
+                                                  const double2 *__restrict__ U, double2 *__restrict__ Z, int64_t ld,
+                                                  const double *__restrict__ kin, double e_ref, double de2,
+                                                  double *partial, int nsplit) {
+    double acc[1] = {0};
+    BAND_LOOP(npw) {
+        const int64_t i = (int64_t)b * ld + g;
+        const double2 r = R[i];
+        double2 v = r;
+        if (U) {
+            const double2 u = U[i];
+            v.x -= u.x;
+            v.y -= u.y;
+        }
+        const double d = kin[g] - e_ref;
+        const double m = 1.0 / (d * d + de2);
+        const double2 z = make_double2(m * v.x, m * v.y);
+        acc[0] += r.x * z.x + r.y * z.y;
+        Z[i] = z;
+    }
+    block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+__global__ __launch_bounds__(RT) void k_lin_rz(int nb, int npw, const double2 *__restrict__ R,
+                                               const double2 *__restrict__ Z, int64_t ld, double *partial,
+                                               int nsplit) {
+    double acc[1] = {0};
+    BAND_LOOP(npw) {
+        const int64_t i = (int64_t)b * ld + g;
+        const double2 r = R[i], z = Z[i];
+        acc[0] += r.x * z.x + r.y * z.y;
+    }
+    block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+// rz_new = sum of partials; beta = rz_new / rz (0 on the first call); rz <- rz_new
+__global__ void k_lin_beta(int nb, int nsplit, const double *__restrict__ partial, double *__restrict__ rz,
+                           double *__restrict__ beta, int first) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double s = 0;
+    for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)b * nsplit + k];
+    const double old = rz[b];
+    beta[b] = (!first && old > 0.0) ? s / old : 0.0;
+    rz[b] = s;
+}
+
+void lin_mdiag(int nb, int npw, const void *R, const void *U, void *Z, int64_t ld, const double *kin, double e_ref,
+               double de2, double *rz, double *beta, bool first, bool with_rz, BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_mdiag, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)R,
+                       (const double2 *)U, (double2 *)Z, ld, kin, e_ref, de2, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    if (with_rz) {
+        hipLaunchKernelGGL(k_lin_beta, dim3((nb + 255) / 256), dim3(256), 0, st, nb, r.nsplit, r.partial, rz, beta,
+                           first ? 1 : 0);
+        PW_LAUNCH_CHECK();
+    }
+}
+
+void lin_rz_beta(int nb, int npw, const void *R, const void *Z, int64_t ld, double *rz, double *beta, bool first,
+                 BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_rz, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)R,
+                       (const double2 *)Z, ld, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_lin_beta, dim3((nb + 255) / 256), dim3(256), 0, st, nb, r.nsplit, r.partial, rz, beta,
+                       first ? 1 : 0);
+    PW_LAUNCH_CHECK();
+}
+
+// P = Z + beta P
+__global__ void k_lin_pupdate(int nb, int npw, const double2 *__restrict__ Z, double2 *__restrict__ P, int64_t ld,
+                              const double *__restrict__ beta) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const double be = beta[b];
+    const int64_t i = (int64_t)b * ld + g;
+    const double2 z = Z[i], p = P[i];
+    P[i] = make_double2(z.x + be * p.x, z.y + be * p.y);
+}
+
+void lin_pupdate(int nb, int npw, const void *Z, void *P, int64_t ld, const double *beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_pupdate, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (const double2 *)Z,
+                       (double2 *)P, ld, beta);
+    PW_LAUNCH_CHECK();
+}
+
+// E[l][i] = C[l][i] / d_i - D[l][i]   (coefficients of the eigenstate part of M')
+__global__ void k_lin_coef(int n, int nev, const double2 *__restrict__ C, const double2 *__restrict__ D,
+                           const double *__restrict__ invd, double2 *__restrict__ E) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n * nev) return;
+    const double s = invd[k % nev];
+    const double2 c = C[k], d = D[k];
+    E[k] = make_double2(c.x * s - d.x, c.y * s - d.y);
+}
+
+void lin_coef(int nrhs, int nev, const void *C, const void *D, const double *invd, void *E, hipStream_t st) {
+    const int n = nrhs * nev;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_lin_coef, dim3((n + 255) / 256), dim3(256), 0, st, nrhs, nev, (const double2 *)C,
+                       (const double2 *)D, invd, (double2 *)E);
+    PW_LAUNCH_CHECK();
+}
+
+// err[b] = ||Y_b - W_b||
+__global__ __launch_bounds__(RT) void k_lin_err(int nb, int npw, const double2 *__restrict__ Y, int64_t ldy,
+                                                const double2 *__restrict__ W, int64_t ldw, double *partial,
+                                                int nsplit) {
+    double acc[1] = {0};
+    BAND_LOOP(npw) {
+        const double2 y = Y[(int64_t)b * ldy + g], w = W[(int64_t)b * ldw + g];
+        const double rx = y.x - w.x, ry = y.y - w.y;
+        acc[0] += rx * rx + ry * ry;
+    }
+    block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+void lin_err(int nb, int npw, const void *Y, int64_t ldy, const void *W, int64_t ldw, double *err, BandRed r,
+             hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_err, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)Y, ldy,
+                       (const double2 *)W, ldw, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    finish(1, nb, r, err, st);
+    hipLaunchKernelGGL(k_sqrt, dim3((nb + 255) / 256), dim3(256), 0, st, nb, err);
+    PW_LAUNCH_CHECK();
+}
+
+// R -= AX
+__global__ void k_lin_sub(int nb, int npw, double2 *__restrict__ R, const double2 *__restrict__ AX, int64_t ld) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const int64_t i = (int64_t)b * ld + g;
+    const double2 r = R[i], a = AX[i];
+    R[i] = make_double2(r.x - a.x, r.y - a.y);
+}
+
+void lin_sub(int nb, int npw, void *R, const void *AX, int64_t ld, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_sub, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (double2 *)R,
+                       (const double2 *)AX, ld);
+    PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
 __global__ void k_fill_zero(uint4 *p, size_t n16) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) p[i] = make_uint4(0, 0, 0, 0);

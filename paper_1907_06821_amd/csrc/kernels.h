@@ -94,5 +94,18 @@ void band_norms(int nb, int npw, const void *X, int64_t ld, double *out, BandRed
 void c64_to_c128(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t);
 void c128_to_c64(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t);
 void nan_check(size_t n, const double *x, int *flag, hipStream_t);
+// folded linear equation, column-wise PCG (per-column scalars on the device)
+void lin_alpha(int nb, int npw, const void *YP, int64_t ld, const double *rz, double *alpha, BandRed, hipStream_t);
+void lin_update(int nb, int npw, void *X, void *Y, void *R, const void *P, const void *YP, const void *AP, int64_t ld,
+                const double *alpha, hipStream_t);
+void lin_mdiag(int nb, int npw, const void *R, const void *U, void *Z, int64_t ld, const double *kin, double e_ref,
+               double de2, double *rz, double *beta, bool first, bool with_rz, BandRed, hipStream_t);
+void lin_rz_beta(int nb, int npw, const void *R, const void *Z, int64_t ld, double *rz, double *beta, bool first,
+                 BandRed, hipStream_t);
+void lin_pupdate(int nb, int npw, const void *Z, void *P, int64_t ld, const double *beta, hipStream_t);
+void lin_coef(int nrhs, int nev, const void *C, const void *D, const double *invd, void *E, hipStream_t);
+void lin_err(int nb, int npw, const void *Y, int64_t ldy, const void *W, int64_t ldw, double *err, BandRed,
+             hipStream_t);
+void lin_sub(int nb, int npw, void *R, const void *AX, int64_t ld, hipStream_t);
 
 }  // namespace pw
