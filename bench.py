@@ -20,8 +20,13 @@ learned preconditioner (M(G) e^f; weights trained by
 paper_1907_06821_amd.train_precond and committed); time includes MLP inference,
 training time is reported separately.
 
+Third part ("linear"): the folded linear equation (H - E)^2 psi = (H - E) w
+of the system states for 8 boundary sources, PCG to ||(H - E) psi - w|| <= 1e-8
+with the eigenstate-augmented preconditioner M' (from 136 eigenpairs of a mixed
++ M(G) eigensolve) against M(G) alone under the same iteration cap.
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
---no-cpu (skip the CPU oracle leg) --no-solve --solve-legs a,b
+--no-cpu (skip the CPU oracle leg) --no-solve --solve-legs a,b --no-linear
 --precision {fp64,mixed} (of the band-H psi leg).
 """
 from __future__ import annotations
@@ -164,6 +169,46 @@ def solve_legs(ctx, prob, nb, nconv, legs, seeds=(0, 5, 9), maxit=4000, log=None
     return res
 
 
+def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
+    """The folded linear equation (H - E)^2 psi = (H - E) w for nrhs boundary
+    sources at E_ref, to the paper's error ||(H - E) psi - w|| <= 1e-8: first
+    the eigensolve that supplies the states near E (mixed precision + M(G),
+    seed 0; its time is reported apart), then PCG with M' built from those nb
+    eigenpairs and their residuals, and PCG with M(G) alone under the same
+    iteration cap."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+    phi = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=0)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, phi, tol=1e-6, maxit=4000, check_every=20, precision=1,
+                                      precond=1, nconv=nconv, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    out = {"tol": tol, "nrhs": nrhs, "e_ref": prob.e_ref, "sources": "Gaussian blobs within 0.1 L_z of z = 0",
+           "eigensolve": {"seconds": round(time.perf_counter() - t0, 3), "iters": st["iters"], "nev": nb,
+                          "converged": bool(st["converged"]), "max_delta_wanted": st["max_resid"],
+                          "max_delta_all": float(np.max(res))}}
+    miller = pw.basis_miller(prob.grid, prob.cell, prob.ecut, prob.kpt)
+    w = torch.from_numpy(synth.boundary_sources(2, nrhs, miller, prob.cell, kpt=prob.kpt, seed=0)).to("cuda")
+    for name, kw in (("mprime", dict(precond=1, phi=phi, eps=eig, delta=res)), ("m_only", dict(precond=0))):
+        x = torch.zeros_like(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        err, lst = pw.folded_linear_solve(ctx, prob.e_ref, w, x, tol=tol, maxit=maxit, check_every=10,
+                                          raise_on_noconv=False, hist_len=maxit // 10, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": round(dt, 3), "iters": lst["iters"], "converged": lst["converged"],
+                     "max_error": lst["max_resid"], "band_hpsi_per_s": round(lst["n_hpsi"] / dt, 1)}
+        if log:
+            log(f"linear {name}: {out[name]}")
+    if out["mprime"]["converged"]:
+        out["iters_ratio_m_only_vs_mprime"] = round(out["m_only"]["iters"] / out["mprime"]["iters"], 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +219,7 @@ def main():
     ap.add_argument("--cpu-bands", type=int, default=64)
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-residual solves")
     ap.add_argument("--solve-legs", default=",".join(n for n, _, _ in SOLVE_LEGS))
+    ap.add_argument("--no-linear", action="store_true", help="skip the folded linear-equation leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -274,6 +320,8 @@ def main():
         legs = [l for l in SOLVE_LEGS if l[0] in args.solve_legs.split(",")]
         line["solve"] = solve_legs(ctx, prob, nb + nbuf, nb, legs, log=lambda m: print(m, file=sys.stderr,
                                                                                        flush=True))
+    if not args.no_linear:
+        line["linear"] = linear_leg(ctx, prob, nb + nbuf, nb, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
     else:
