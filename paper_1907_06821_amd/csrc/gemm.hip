@@ -272,13 +272,18 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
-// NT tiles: TN = 64 (N <= 64), 128 (N <= 128) or 144 (N <= 144, for 128 wanted
-// bands plus buffer bands), else 128; TM = 128 rows of A when A is tall (the
-// projector table: B is then re-read half as often) or of a square band-by-band
-// product of up to 128 (Gram matrices: one tile); 48 for square products of
-// 129..144 (three waves of 3 x 3 blocks, 48 x 144 tiles), else 64.
-static int nt_tn(int N) { return N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128)); }
+// NT tiles: TN = 16 (N <= 16), 32 (N <= 32), 64 (N <= 64), 128 (N <= 128) or 144
+// (N <= 144, for 128 wanted bands plus buffer bands), else 128; TM = 128 rows of A
+// when A is tall (the projector table: B is then re-read half as often) or of a
+// square band-by-band product of up to 128 (Gram matrices: one tile); 48 for
+// square products of 129..144 (three waves of 3 x 3 blocks, 48 x 144 tiles), else
+// 64.  The narrow tiles serve a few right-hand sides against the whole table,
+// where a 64-wide tile would spend most of its matrix-core work on padding.
+static int nt_tn(int N) {
+    return N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128))));
+}
 static int nt_tm(int M, int N) {
+    if (N <= 32) return M >= 512 ? 128 : 64;
     if (M == N && M > 128 && M <= 144) return 48;
     return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
 }
@@ -328,6 +333,10 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     const int tn = nt_tn(N), tm = nt_tm(M, N);
     dim3 grid((M + tm - 1) / tm, (N + tn - 1) / tn, nsplit);
     if (K <= 0) fill_zero(partial, (size_t)M * N * sizeof(double2), st);
+    else if (tn == 16 && tm == 128) nt_go<4, 1, 2, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tn == 16) nt_go<4, 1, 1, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tn == 32 && tm == 128) nt_go<4, 1, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tn == 32) nt_go<4, 1, 1, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tm == 48) nt_go<1, 3, 3, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
     else if (tm == 128 && tn == 128) nt_go<4, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
@@ -363,14 +372,16 @@ static void nn_go(int nz, bool proj, hipStream_t st, int M, int J, int K, const 
 }
 
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
-// Default tiles: 64 rows (M <= 64), 144 (128 < M <= 144), else 128.
+// Default tiles: 16 rows (M <= 16), 32 (M <= 32), 64 (M <= 64), 144 (128 < M <= 144), else 128.
 // NN tile configurations (waves over rows x columns, 16 x 16 blocks per wave)
 // the autotuner chooses between; id: {WM, WJ, BM, BJ, KD}, tile (16 WM BM) x
 // (16 WJ BJ), KD-deep stages.  A workgroup of 9 waves leaves one SIMD with three
-// waves and the others with two; the 12-wave 144-row tiles spread evenly.
+// waves and the others with two; the 12-wave 144-row tiles spread evenly.  Tiles
+// 12 and 13 (16 and 32 rows) serve a few right-hand sides against the table.
 static const int kNnCfg[kNnCfgs][5] = {{2, 2, 2, 2, 16}, {4, 1, 2, 4, 16}, {9, 1, 1, 4, 16}, {4, 2, 2, 2, 16},
                                        {8, 1, 1, 4, 16}, {4, 1, 2, 2, 16}, {2, 4, 2, 2, 16}, {9, 1, 1, 4, 8},
-                                       {3, 2, 3, 2, 8},  {8, 1, 1, 4, 8},  {3, 4, 3, 2, 8},  {3, 4, 3, 1, 8}};
+                                       {3, 2, 3, 2, 8},  {8, 1, 1, 4, 8},  {3, 4, 3, 2, 8},  {3, 4, 3, 1, 8},
+                                       {1, 4, 1, 4, 16}, {2, 4, 1, 2, 16}};
 
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr) {
     PW_CHECK(id >= 0 && id < kNnCfgs, PW_EINVAL, "NN tile %d unknown", id);
@@ -389,7 +400,7 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.X[z] = (const double2 *)X[z];
         bt.Out[z] = (double2 *)Out[z];
     }
-    if (cfg < 0) cfg = M <= 64 ? 0 : (M > 128 && M <= 144) ? 11 : 9;
+    if (cfg < 0) cfg = M <= 16 ? 12 : M <= 32 ? 13 : M <= 64 ? 0 : (M > 128 && M <= 144) ? 11 : 9;
     switch (cfg) {
         case 0: nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 1: nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
@@ -403,6 +414,8 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         case 9: nn_go<8, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 10: nn_go<3, 4, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 11: nn_go<3, 4, 3, 1, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 12: nn_go<1, 4, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 13: nn_go<2, 4, 1, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
     }
     PW_LAUNCH_CHECK();

@@ -18,7 +18,7 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
               hipStream_t, bool proj = false);
 // NN GEMM tile configurations: cfg < 0 picks by M, else one of kNnCfgs (autotuner)
-constexpr int kNnCfgs = 12;
+constexpr int kNnCfgs = 14;
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr);
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
                      double beta, void *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1);

@@ -65,7 +65,7 @@ def test_every_fft_candidate_matches_oracle(torch_cuda, which):
 
 def test_gemm_tiles_at_136_bands(torch_cuda):
     """Every back-projection and block-rotation tile at 136 bands (row tiles of
-    64, 128 and 144 with a ragged last tile): H psi against the oracle and the
+    16, 32, 64, 128 and 144 with a ragged last tile): H psi against the oracle and the
     Gram/Cholesky orthonormalisation against its definition."""
     import paper_1907_06821_amd as pw
     prob = synth.batched_problems(4, seed=3)[1]              # 48^3 cube
@@ -76,7 +76,7 @@ def test_gemm_tiles_at_136_bands(torch_cuda):
     c = random_block(12, nb, op.npw)
     ref = op.apply(c, shift=prob.e_ref)
     recs = [r for r in pw.autotune(ctx, nb, dtype=pw.PW_C128, reps=1) if r["pass_"] in (4, 5)]
-    assert len(recs) == 24
+    assert len(recs) == 28
     for r in recs:
         pw.fft_choose(ctx, r)
         if r["pass_"] == 4:
@@ -99,6 +99,27 @@ def test_gram_single_tile(torch_cuda, nb):
     prob = synth.batched_problems(4, seed=3)[1]              # 48^3 cube
     ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128)
     c = random_block(13, nb, ctx.npw)
+    q = pw.orthonormalize(ctx, to_dev(c)).cpu().numpy()
+    assert np.abs(q.conj() @ q.T - np.eye(nb)).max() < 1e-12
+    coef = q.conj() @ c.T
+    assert np.abs(np.tril(coef, -1)).max() < 1e-11 * np.abs(coef).max()
+    assert rel_err(coef.T @ q, c) < 1e-12
+
+
+@pytest.mark.parametrize("nb", [1, 5, 16, 17, 32, 33])
+def test_narrow_tiles_few_bands(torch_cuda, nb):
+    """A few bands against a tall projector table (520 projectors): the 16- and
+    32-wide NT tiles (128-row tiles of the table) and the 16- and 32-row NN tiles,
+    with ragged edges; H psi against the oracle, and the Gram/Cholesky
+    orthonormalisation (64 x 16 and 64 x 32 NT tiles) against its definition."""
+    import paper_1907_06821_amd as pw
+    prob = synth.cubic_random_problem(10.0, (40, 40, 40), 8.0, 130, 0.3, nb, seed=2)
+    op = oracle_for(prob)
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128)
+    assert ctx.nproj == 520
+    c = random_block(14, nb, op.npw)
+    got = pw.hpsi(ctx, to_dev(c), shift=prob.e_ref).cpu().numpy()
+    assert rel_err(got, op.apply(c, shift=prob.e_ref)) < 1e-12
     q = pw.orthonormalize(ctx, to_dev(c)).cpu().numpy()
     assert np.abs(q.conj() @ q.T - np.eye(nb)).max() < 1e-12
     coef = q.conj() @ c.T
