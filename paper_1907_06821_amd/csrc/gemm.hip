@@ -372,16 +372,19 @@ static void nn_go(int nz, bool proj, hipStream_t st, int M, int J, int K, const 
 }
 
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
-// Default tiles: 16 rows (M <= 16), 32 (M <= 32), 64 (M <= 64), 144 (128 < M <= 144), else 128.
+// Default tiles: 16 x 64 (M <= 16), 32 x 32 (M <= 32), 64 (M <= 64), 144 (128 < M <= 144), else 128 rows.
 // NN tile configurations (waves over rows x columns, 16 x 16 blocks per wave)
 // the autotuner chooses between; id: {WM, WJ, BM, BJ, KD}, tile (16 WM BM) x
 // (16 WJ BJ), KD-deep stages.  A workgroup of 9 waves leaves one SIMD with three
 // waves and the others with two; the 12-wave 144-row tiles spread evenly.  Tiles
-// 12 and 13 (16 and 32 rows) serve a few right-hand sides against the table.
+// 12 and 13 (16 x 64 and 32 x 32, one 16 x 16 block per wave) serve a few
+// right-hand sides against the table: many small workgroups keep every CU
+// streaming it (8 bands: 134 us against 446 us for the 64-row tile and 222 us
+// for a 16 x 256 tile on the 0.79 GB table).
 static const int kNnCfg[kNnCfgs][5] = {{2, 2, 2, 2, 16}, {4, 1, 2, 4, 16}, {9, 1, 1, 4, 16}, {4, 2, 2, 2, 16},
                                        {8, 1, 1, 4, 16}, {4, 1, 2, 2, 16}, {2, 4, 2, 2, 16}, {9, 1, 1, 4, 8},
                                        {3, 2, 3, 2, 8},  {8, 1, 1, 4, 8},  {3, 4, 3, 2, 8},  {3, 4, 3, 1, 8},
-                                       {1, 4, 1, 4, 16}, {2, 4, 1, 2, 16}};
+                                       {1, 4, 1, 1, 16}, {2, 2, 1, 1, 16}};
 
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr) {
     PW_CHECK(id >= 0 && id < kNnCfgs, PW_EINVAL, "NN tile %d unknown", id);
@@ -414,8 +417,8 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         case 9: nn_go<8, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 10: nn_go<3, 4, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         case 11: nn_go<3, 4, 3, 1, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 12: nn_go<1, 4, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 13: nn_go<2, 4, 1, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 12: nn_go<1, 4, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 13: nn_go<2, 2, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
         default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
     }
     PW_LAUNCH_CHECK();
