@@ -90,7 +90,7 @@ def measured_traffic(stage, mixed, nb, nn_cfg):
     back-projection tile) and the kernel source has not changed since; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "wire256_fp64_traffic.json")
-    if mixed or nb != 128 or not os.path.exists(path):
+    if mixed or not os.path.exists(path) or (nb != 128 and not stage.startswith("linear_")):
         return None
     with open(path) as f:
         rec = json.load(f)
@@ -192,20 +192,53 @@ def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
                           "max_delta_all": float(np.max(res))}}
     miller = pw.basis_miller(prob.grid, prob.cell, prob.ecut, prob.kpt)
     w = torch.from_numpy(synth.boundary_sources(2, nrhs, miller, prob.cell, kpt=prob.kpt, seed=0)).to("cuda")
+    prof = None
     for name, kw in (("mprime", dict(precond=1, phi=phi, eps=eig, delta=res)), ("m_only", dict(precond=0))):
         x = torch.zeros_like(w)
+        if name == "mprime":
+            pw.profile_begin(ctx, 200000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         err, lst = pw.folded_linear_solve(ctx, prob.e_ref, w, x, tol=tol, maxit=maxit, check_every=10,
                                           raise_on_noconv=False, hist_len=maxit // 10, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        if name == "mprime":
+            prof = pw.profile_end(ctx)
         out[name] = {"seconds": round(dt, 3), "iters": lst["iters"], "converged": lst["converged"],
                      "max_error": lst["max_resid"], "band_hpsi_per_s": round(lst["n_hpsi"] / dt, 1)}
         if log:
             log(f"linear {name}: {out[name]}")
     if out["mprime"]["converged"]:
         out["iters_ratio_m_only_vs_mprime"] = round(out["m_only"]["iters"] / out["mprime"]["iters"], 2)
+    # H psi stages of the M' solve against HBM: at a few bands the projector GEMMs
+    # read the whole table per launch for 8 nrhs flops per 16-byte element, below
+    # the FP64 ridge, so every stage is bandwidth-bound
+    npw, nproj = ctx.npw, ctx.nproj
+    n0, n1, n2 = ctx.grid
+    table = nproj * npw * 16
+    stage_bytes = {
+        "z_inverse": nrhs * (npw + ctx.ncols * n2) * 16,
+        "xy_fft_v": nrhs * 2 * ctx.ncols * n2 * 16 + n0 * n1 * n2 * 8,
+        "z_forward_kinetic": nrhs * (ctx.ncols * n2 + 2 * npw) * 16,
+        "projection": table + nrhs * npw * 16 + nrhs * nproj * 16,
+        "back_projection": table + nrhs * nproj * 16 + 2 * nrhs * npw * 16,
+    }
+    stages = {}
+    for k, (ms, n) in (prof or {}).items():
+        if n == 0 or k not in stage_bytes:
+            continue
+        ach = stage_bytes[k] / (ms / n / 1e3) / 1e9
+        stages[k] = {"avg_us": round(ms / n * 1e3, 2), "launches": n, "bytes": stage_bytes[k],
+                     "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "share": round(ms / 1e3 / out["mprime"]["seconds"], 4)}
+    if stages:
+        dom = max(stages, key=lambda k: stages[k]["avg_us"] * stages[k]["launches"])
+        d = stages[dom]
+        out["roofline"] = {"bound": "hbm", "achieved": d["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": d["frac"], "kernel": dom, "bytes_per_launch": d["bytes"],
+                           "traffic": measured_traffic("linear_" + dom, False, nrhs, None)}
+        out["stages"] = stages
     return out
 
 
@@ -220,6 +253,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-residual solves")
     ap.add_argument("--solve-legs", default=",".join(n for n, _, _ in SOLVE_LEGS))
     ap.add_argument("--no-linear", action="store_true", help="skip the folded linear-equation leg")
+    ap.add_argument("--linear-maxit", type=int, default=3000, help="iteration cap of the linear-equation leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -321,7 +355,8 @@ def main():
         line["solve"] = solve_legs(ctx, prob, nb + nbuf, nb, legs, log=lambda m: print(m, file=sys.stderr,
                                                                                        flush=True))
     if not args.no_linear:
-        line["linear"] = linear_leg(ctx, prob, nb + nbuf, nb, log=lambda m: print(m, file=sys.stderr, flush=True))
+        line["linear"] = linear_leg(ctx, prob, nb + nbuf, nb, maxit=args.linear_maxit,
+                                    log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
     else:
