@@ -315,6 +315,42 @@ pw_status pw_folded_linear_solve(pw_ctx *ctx, double e, int32_t nrhs, const void
                                  void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Chebyshev filter diagonalisation of an energy window (Sec. II.B, ChebFD
+ * paragraph: a Chebyshev polynomial p(H) imitating a window around E, applied to
+ * a block of vectors, then a subspace diagonalisation; repeated).
+ *
+ * The filter is p(H) = sum_{k<=degree} g_k mu_k T_k((H - c)/h) with c, h the
+ * centre and half width of [emin, emax], mu_k the Chebyshev coefficients of the
+ * indicator of [e - half_width, e + half_width] and g_k Jackson's damping
+ * factors; one complex128 H psi per degree.  [emin, emax] must contain the whole
+ * spectrum of H (else the recurrence grows without bound); pw_spectral_bounds
+ * estimates it.  All three synchronise `stream`; blocks are device complex128
+ * band-major [nb][ld], 1 <= nb <= max_bands; each call allocates its scratch
+ * (four nb x npw blocks) and frees it before returning.
+ * ------------------------------------------------------------------------- */
+
+/* out = p(H) psi (psi and out must not alias).  PW_EINVAL for degree outside
+ * [0, 100000], emax <= emin, half_width <= 0 or a window outside [emin, emax]. */
+pw_status pw_cheb_filter(pw_ctx *ctx, int32_t nb, const void *psi, int64_t ld, void *out, int64_t ldo, double e,
+                         double half_width, int32_t degree, double emin, double emax, void *stream);
+
+/* One ChebFD step in place: psi <- Rayleigh-Ritz vectors of H on span p(H) psi
+ * (Gram/Cholesky orthonormalisation, then <phi_i|H|phi_j> diagonalised), with
+ * eig (host [nb], optional) the Ritz values ascending and resid (host [nb],
+ * optional) ||H phi_i - eps_i phi_i||.  nb <= 1024.  PW_ENOTPD if the filtered
+ * block lost rank (more bands than the filter keeps), PW_ENAN if it is not
+ * finite (bounds that miss part of the spectrum). */
+pw_status pw_chebfd_step(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, double e, double half_width, int32_t degree,
+                         double emin, double emax, double *eig, double *resid, void *stream);
+
+/* Estimate of an interval holding the spectrum of H: `steps` (2..1024) Lanczos
+ * steps from the start vector v0 (device complex128 [npw], not zero; the caller
+ * draws it), the extreme Ritz values of the tridiagonal widened by twice their
+ * residual bounds and by 1% of their spread.  An estimate, not a proof: a start
+ * vector orthogonal to an extreme eigenvector misses it. */
+pw_status pw_spectral_bounds(pw_ctx *ctx, const void *v0, int32_t steps, double *emin, double *emax, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Learned preconditioner (precond = 2).  Not in the paper: a network standing in
  * for the diagonal preconditioner (the paper's is M(G), Sec. II.B).  Per |G+k|
  * shell s and band i, f_si = MLP(T_s/Ecut, T_i/Ecut, E_ref/Ecut), a 3-64-64-1 tanh

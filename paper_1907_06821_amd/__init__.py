@@ -30,7 +30,8 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_dense_chol_inv", "pw_mlp_set", "pw_mlp_forward", "pw_mlp_harvest", "pw_mlp_work_bytes",
            "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
            "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose",
-           "pw_lin_opts_default", "pw_folded_linear_solve")
+           "pw_lin_opts_default", "pw_folded_linear_solve", "pw_cheb_filter", "pw_chebfd_step",
+           "pw_spectral_bounds")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
 PW_PROF_NKINDS = 8
 
@@ -126,6 +127,9 @@ def lib():
             "pw_folded_linear_solve": [vp, dbl, i32, vp, i64, vp, i64, i32, vp, i64, C.POINTER(dbl),
                                        C.POINTER(dbl), C.POINTER(dbl), C.POINTER(pw_lin_opts),
                                        C.POINTER(pw_lin_stats), vp],
+            "pw_cheb_filter": [vp, i32, vp, i64, vp, i64, dbl, dbl, i32, dbl, dbl, vp],
+            "pw_chebfd_step": [vp, i32, vp, i64, dbl, dbl, i32, dbl, dbl, C.POINTER(dbl), C.POINTER(dbl), vp],
+            "pw_spectral_bounds": [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -535,6 +539,48 @@ def folded_linear_solve(ctx, e, w, psi, phi=None, eps=None, delta=None, opts=Non
     if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
         _check(status)
     return res, stats
+
+
+def _c128_block(t, npw):
+    import torch
+    _check_block(t, npw)
+    if t.dtype != torch.complex128:
+        raise ValueError("expected a complex128 block")
+
+
+def cheb_filter(ctx, psi, e, half_width, degree, emin, emax, stream=None):
+    """p(H) psi for the Chebyshev window filter of [e - w, e + w] (new tensor)."""
+    import torch
+    _c128_block(psi, ctx.npw)
+    out = torch.empty_like(psi)
+    _check(ctx._lib.pw_cheb_filter(ctx.handle, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                   C.c_void_p(out.data_ptr()), out.stride(0), float(e), float(half_width),
+                                   int(degree), float(emin), float(emax), _stream_ptr(stream)))
+    return out
+
+
+def chebfd_step(ctx, psi, e, half_width, degree, emin, emax, stream=None):
+    """One ChebFD step in place on psi; returns (eig ascending, resid)."""
+    _c128_block(psi, ctx.npw)
+    nb = psi.shape[0]
+    eig = np.zeros(nb)
+    res = np.zeros(nb)
+    dp = C.POINTER(C.c_double)
+    _check(ctx._lib.pw_chebfd_step(ctx.handle, nb, C.c_void_p(psi.data_ptr()), psi.stride(0), float(e),
+                                   float(half_width), int(degree), float(emin), float(emax),
+                                   eig.ctypes.data_as(dp), res.ctypes.data_as(dp), _stream_ptr(stream)))
+    return eig, res
+
+
+def spectral_bounds(ctx, v0, steps=40, stream=None):
+    """(emin, emax) estimate from `steps` Lanczos steps on H from v0 (complex128 [npw] on the GPU)."""
+    import torch
+    if not v0.is_cuda or v0.dtype != torch.complex128 or v0.numel() != ctx.npw or not v0.is_contiguous():
+        raise ValueError("v0 must be a contiguous complex128 CUDA vector of npw entries")
+    lo, hi = C.c_double(), C.c_double()
+    _check(ctx._lib.pw_spectral_bounds(ctx.handle, C.c_void_p(v0.data_ptr()), int(steps), C.byref(lo), C.byref(hi),
+                                       _stream_ptr(stream)))
+    return lo.value, hi.value
 
 
 def batch_solve(ctxs, e_refs, psis, opts=None, hist_len=0, stream=None, raise_on_noconv=True, **kw):

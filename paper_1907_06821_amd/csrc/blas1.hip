@@ -501,6 +501,79 @@ void lin_sub(int nb, int npw, void *R, const void *AX, int64_t ld, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
+// Chebyshev filter: U_{k+1} = s (H - c) U_k - U_{k-1} with T = (H - c) U_k given;
+// the new vector overwrites U_{k-1} (first: U_1 = s T, U_0 untouched) and
+// Y += gamma U_{k+1}.
+__global__ void k_cheb_step(int nb, int npw, const double2 *__restrict__ T, double2 *__restrict__ Uprev,
+                            double2 *__restrict__ Y, int64_t ld, double s, double gamma, int first) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const int64_t i = (int64_t)b * ld + g;
+    const double2 t = T[i];
+    double2 u = make_double2(s * t.x, s * t.y);
+    if (!first) {
+        const double2 p = Uprev[i];
+        u.x -= p.x;
+        u.y -= p.y;
+    }
+    Uprev[i] = u;
+    double2 y = Y[i];
+    y.x += gamma * u.x;
+    y.y += gamma * u.y;
+    Y[i] = y;
+}
+
+void cheb_step(int nb, int npw, const void *T, void *Uprev, void *Y, int64_t ld, double s, double gamma, bool first,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_cheb_step, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (const double2 *)T,
+                       (double2 *)Uprev, (double2 *)Y, ld, s, gamma, first ? 1 : 0);
+    PW_LAUNCH_CHECK();
+}
+
+// dst = s * src
+__global__ void k_scale_copy(int nb, int npw, const double2 *__restrict__ src, int64_t lds, double2 *__restrict__ dst,
+                             int64_t ldd, double s) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const double2 v = src[(int64_t)b * lds + g];
+    dst[(int64_t)b * ldd + g] = make_double2(s * v.x, s * v.y);
+}
+
+void scale_copy(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, double s, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_copy, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (const double2 *)src, lds,
+                       (double2 *)dst, ldd, s);
+    PW_LAUNCH_CHECK();
+}
+
+// Lanczos: W -= alpha V + beta Vprev (one vector)
+__global__ void k_lanczos(int npw, double2 *__restrict__ W, const double2 *__restrict__ V,
+                          const double2 *__restrict__ Vp, double alpha, double beta) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw) return;
+    const double2 v = V[g], p = Vp[g];
+    double2 w = W[g];
+    w.x -= alpha * v.x + beta * p.x;
+    w.y -= alpha * v.y + beta * p.y;
+    W[g] = w;
+}
+
+void lanczos_update(int npw, void *W, const void *V, const void *Vp, double alpha, double beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_lanczos, dim3((npw + 255) / 256), dim3(256), 0, st, npw, (double2 *)W, (const double2 *)V,
+                       (const double2 *)Vp, alpha, beta);
+    PW_LAUNCH_CHECK();
+}
+
+// out[b] = Re <A_b, B_b>
+void red_dot_re(int nb, int npw, const void *A, const void *B, int64_t ld, double *out, BandRed r, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin_rz, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)A, (const double2 *)B,
+                       ld, r.partial, r.nsplit);
+    PW_LAUNCH_CHECK();
+    finish(1, nb, r, out, st);
+}
+
+// ---------------------------------------------------------------------------
 __global__ void k_fill_zero(uint4 *p, size_t n16) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) p[i] = make_uint4(0, 0, 0, 0);

@@ -107,5 +107,11 @@ void lin_coef(int nrhs, int nev, const void *C, const void *D, const double *inv
 void lin_err(int nb, int npw, const void *Y, int64_t ldy, const void *W, int64_t ldw, double *err, BandRed,
              hipStream_t);
 void lin_sub(int nb, int npw, void *R, const void *AX, int64_t ld, hipStream_t);
+// Chebyshev filter and Lanczos bounds
+void cheb_step(int nb, int npw, const void *T, void *Uprev, void *Y, int64_t ld, double s, double gamma, bool first,
+               hipStream_t);
+void scale_copy(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, double s, hipStream_t);
+void lanczos_update(int npw, void *W, const void *V, const void *Vp, double alpha, double beta, hipStream_t);
+void red_dot_re(int nb, int npw, const void *A, const void *B, int64_t ld, double *out, BandRed, hipStream_t);
 
 }  // namespace pw
