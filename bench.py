@@ -25,8 +25,14 @@ of the system states for 8 boundary sources, PCG to ||(H - E) psi - w|| <= 1e-8
 with the eigenstate-augmented preconditioner M' (from 136 eigenpairs of a mixed
 + M(G) eigensolve) against M(G) alone under the same iteration cap.
 
+Fourth part ("chebfd"): Chebyshev filter diagonalisation of a window around
+E_ref holding 64 states, 136 vectors, 3 steps of a degree-1500 filter (the
+paper's degree), bounds from 40 Lanczos steps; per step, the residuals of the
+Ritz pairs nearest the folded solve's eigenvalues in the window.
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
 --no-cpu (skip the CPU oracle leg) --no-solve --solve-legs a,b --no-linear
+--linear-maxit N --no-chebfd --chebfd-degree D --chebfd-steps S
 --precision {fp64,mixed} (of the band-H psi leg).
 """
 from __future__ import annotations
@@ -196,7 +202,7 @@ def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
     for name, kw in (("mprime", dict(precond=1, phi=phi, eps=eig, delta=res)), ("m_only", dict(precond=0))):
         x = torch.zeros_like(w)
         if name == "mprime":
-            pw.profile_begin(ctx, 200000)
+            pw.profile_begin(ctx, 40000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         err, lst = pw.folded_linear_solve(ctx, prob.e_ref, w, x, tol=tol, maxit=maxit, check_every=10,
@@ -209,6 +215,7 @@ def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
                      "max_error": lst["max_resid"], "band_hpsi_per_s": round(lst["n_hpsi"] / dt, 1)}
         if log:
             log(f"linear {name}: {out[name]}")
+    out["_eig"] = eig
     if out["mprime"]["converged"]:
         out["iters_ratio_m_only_vs_mprime"] = round(out["m_only"]["iters"] / out["mprime"]["iters"], 2)
     # H psi stages of the M' solve against HBM: at a few bands the projector GEMMs
@@ -242,6 +249,77 @@ def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
     return out
 
 
+def chebfd_leg(ctx, prob, nb, eig_ref=None, n_window=64, degree=1500, steps=3, log=None):
+    """Chebyshev filter diagonalisation of a window around E_ref: spectral bounds
+    from 40 Lanczos steps, a window holding n_window of the eigenvalues eig_ref
+    (from the folded eigensolve; its edge midway between the n_window-th and the
+    next distance from E_ref), nb filtered vectors from a seeded random start,
+    `steps` ChebFD steps of the given degree.  Reports the residual of the states
+    inside the window after each step, the eigenvalue agreement with the folded
+    solve, and the roofline of the dominant H psi stage over the filtering."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+    e = prob.e_ref
+    v0 = torch.from_numpy(synth.start_vectors(2, 1, ctx.npw, seed=21)[0]).to("cuda")
+    t0 = time.perf_counter()
+    lo, hi = pw.spectral_bounds(ctx, v0, steps=40)
+    t_bounds = time.perf_counter() - t0
+    ref = None
+    if eig_ref is not None:
+        d = np.sort(np.abs(np.asarray(eig_ref) - e))
+        w = 0.5 * (d[n_window - 1] + d[n_window])
+        ref = np.sort(np.asarray(eig_ref)[np.abs(np.asarray(eig_ref) - e) <= w])
+    else:
+        w = 0.05
+    psi = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=22)).to("cuda")
+    out = {"e_ref": e, "half_width": w, "degree": degree, "nb": nb, "n_window": n_window, "bounds": [lo, hi],
+           "bounds_seconds": round(t_bounds, 3), "steps": []}
+    pw.profile_begin(ctx, 20000)
+    tot = 0.0
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eig, res = pw.chebfd_step(ctx, psi, e, w, degree, lo, hi)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tot += dt
+        sel = np.abs(eig - e) <= w
+        rec = {"seconds": round(dt, 3), "ritz_in_window": int(sel.sum())}
+        if ref is not None:
+            # each eigenvalue of the folded solve inside the window, paired with the nearest Ritz value
+            # (extra Ritz values in the window are mixtures of states outside it)
+            near = np.array([np.argmin(np.abs(eig - x)) for x in ref])
+            rec.update({"max_resid_matched": float(res[near].max()),
+                        "max_eig_diff_matched": float(np.max(np.abs(eig[near] - ref))),
+                        "max_resid_matched_inner_half": float(res[near[np.abs(ref - e) <= 0.5 * w]].max())})
+        out["steps"].append(rec)
+        if log:
+            log(f"chebfd step {k + 1}: {rec}")
+    prof = pw.profile_end(ctx)
+    out["seconds_per_step"] = round(tot / steps, 3)
+    out["band_hpsi_per_s"] = round(steps * (degree + 1) * nb / tot, 1)
+    work = stage_work(ctx, nb, 16, ctx.nproj)
+    stages = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        bound, amount, unit = work[k]
+        avg_s = ms / n / 1e3
+        ach = amount / avg_s / (1e9 if bound == "hbm" else 1e12)
+        peak = HBM_PEAK_GBS if bound == "hbm" else FP64_PEAK_TFS
+        stages[k] = {"bound": bound, "avg_ms": round(ms / n, 4), "launches": n, "achieved": round(ach, 2),
+                     "peak": peak, "frac": round(ach / peak, 4)}
+    if stages:
+        dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches"])
+        d = stages[dom]
+        out["roofline"] = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                           "unit": "GB/s" if d["bound"] == "hbm" else "TFLOP/s", "frac": d["frac"], "kernel": dom}
+        out["stages"] = stages
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +332,10 @@ def main():
     ap.add_argument("--solve-legs", default=",".join(n for n, _, _ in SOLVE_LEGS))
     ap.add_argument("--no-linear", action="store_true", help="skip the folded linear-equation leg")
     ap.add_argument("--linear-maxit", type=int, default=3000, help="iteration cap of the linear-equation leg")
+    ap.add_argument("--no-chebfd", action="store_true", help="skip the Chebyshev filter diagonalisation leg")
+    ap.add_argument("--chebfd-degree", type=int, default=1500)
+    ap.add_argument("--chebfd-steps", type=int, default=3)
+    ap.add_argument("--chebfd-window", type=int, default=64, help="eigenstates inside the ChebFD window")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -354,9 +436,15 @@ def main():
         legs = [l for l in SOLVE_LEGS if l[0] in args.solve_legs.split(",")]
         line["solve"] = solve_legs(ctx, prob, nb + nbuf, nb, legs, log=lambda m: print(m, file=sys.stderr,
                                                                                        flush=True))
+    eig_ref = None
     if not args.no_linear:
         line["linear"] = linear_leg(ctx, prob, nb + nbuf, nb, maxit=args.linear_maxit,
                                     log=lambda m: print(m, file=sys.stderr, flush=True))
+        eig_ref = line["linear"].pop("_eig")
+    if not args.no_chebfd:
+        line["chebfd"] = chebfd_leg(ctx, prob, nb + nbuf, eig_ref, n_window=args.chebfd_window,
+                                    degree=args.chebfd_degree,
+                                    steps=args.chebfd_steps, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
     else:
