@@ -18,6 +18,7 @@ Modules
   mlp          the per-shell preconditioner network: forward, backward, loss
   linsolve     spectral closed form and PCG for (H - E)^2 psi = (H - E) w
   chebfd       Chebyshev window filter p(H) and ChebFD steps
+  kinterp      wave-function interpolation between two k-points
 
 Every public function names the passage of the paper (or the textbook
 definition) it follows.  Pins live in tests/test_oracle_*.py.
