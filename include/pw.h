@@ -350,6 +350,22 @@ pw_status pw_chebfd_step(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, double 
  * vector orthogonal to an extreme eigenvector misses it. */
 pw_status pw_spectral_bounds(pw_ctx *ctx, const void *v0, int32_t steps, double *emin, double *emax, void *stream);
 
+/* Wave-function interpolation between two k-points (Sec. II.C): from n
+ * orthonormal eigenstates psi1 (device complex128 [n][ld1] on ctx1's sphere) with
+ * energies eps1 (host [n]) at k1, and psi2/eps2 likewise at k2, the energies
+ * eps_out (host [n], ascending) at k = k2 + alpha (k1 - k2) from
+ *   H_ij(k) = alpha eps1_i delta_ij + (1 - alpha) sum_m conj(U_im) U_jm eps2_m,
+ * U the row-wise Gram-Schmidt of S_ij = <psi_j(k2)|psi_i(k1)>; and, if psi_out is
+ * not NULL, the interpolated states alpha sum_j c_j psi1_j + (1 - alpha)
+ * sum_jl c_j U_jl psi2_l on ctxk's sphere (device complex128 [n][ldo]; not
+ * renormalised).  The three contexts (at k1, k2 and k) must share cell, grid and
+ * cutoff; coefficients are matched by Miller triple, one missing from a sphere
+ * counting as zero.  n <= 1024.  PW_ENOTPD if the overlap rows are linearly
+ * dependent.  Allocates its scratch for the call; synchronises `stream`. */
+pw_status pw_kinterp(pw_ctx *ctx1, pw_ctx *ctx2, pw_ctx *ctxk, double alpha, int32_t n, const void *psi1, int64_t ld1,
+                     const double *eps1, const void *psi2, int64_t ld2, const double *eps2, double *eps_out,
+                     void *psi_out, int64_t ldo, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned preconditioner (precond = 2).  Not in the paper: a network standing in
  * for the diagonal preconditioner (the paper's is M(G), Sec. II.B).  Per |G+k|

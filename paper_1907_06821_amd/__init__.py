@@ -31,7 +31,7 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
            "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose",
            "pw_lin_opts_default", "pw_folded_linear_solve", "pw_cheb_filter", "pw_chebfd_step",
-           "pw_spectral_bounds")
+           "pw_spectral_bounds", "pw_kinterp")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
 PW_PROF_NKINDS = 8
 
@@ -130,6 +130,8 @@ def lib():
             "pw_cheb_filter": [vp, i32, vp, i64, vp, i64, dbl, dbl, i32, dbl, dbl, vp],
             "pw_chebfd_step": [vp, i32, vp, i64, dbl, dbl, i32, dbl, dbl, C.POINTER(dbl), C.POINTER(dbl), vp],
             "pw_spectral_bounds": [vp, vp, i32, C.POINTER(dbl), C.POINTER(dbl), vp],
+            "pw_kinterp": [vp, vp, vp, dbl, i32, vp, i64, C.POINTER(dbl), vp, i64, C.POINTER(dbl), C.POINTER(dbl),
+                           vp, i64, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -581,6 +583,31 @@ def spectral_bounds(ctx, v0, steps=40, stream=None):
     _check(ctx._lib.pw_spectral_bounds(ctx.handle, C.c_void_p(v0.data_ptr()), int(steps), C.byref(lo), C.byref(hi),
                                        _stream_ptr(stream)))
     return lo.value, hi.value
+
+
+def kinterp(ctx1, ctx2, ctxk, alpha, psi1, eps1, psi2, eps2, states=True, stream=None):
+    """Energies at k = k2 + alpha (k1 - k2) interpolated from the eigenpairs at k1
+    and k2 (complex128 blocks [n, npw] on each context's sphere); with states=True
+    also the interpolated states on ctxk's sphere.  Returns (eps, psi_k or None)."""
+    import torch
+    _c128_block(psi1, ctx1.npw)
+    _c128_block(psi2, ctx2.npw)
+    n = psi1.shape[0]
+    if psi2.shape[0] != n:
+        raise ValueError("psi1 and psi2 must hold the same number of states")
+    e1 = np.ascontiguousarray(eps1, dtype=np.float64)
+    e2 = np.ascontiguousarray(eps2, dtype=np.float64)
+    if e1.shape != (n,) or e2.shape != (n,):
+        raise ValueError("one energy per state")
+    out = torch.empty((n, ctxk.npw), dtype=torch.complex128, device=psi1.device) if states else None
+    eps = np.zeros(n)
+    dp = C.POINTER(C.c_double)
+    _check(ctx1._lib.pw_kinterp(ctx1.handle, ctx2.handle, ctxk.handle, float(alpha), n, C.c_void_p(psi1.data_ptr()),
+                                psi1.stride(0), e1.ctypes.data_as(dp), C.c_void_p(psi2.data_ptr()), psi2.stride(0),
+                                e2.ctypes.data_as(dp), eps.ctypes.data_as(dp),
+                                C.c_void_p(out.data_ptr() if out is not None else None),
+                                out.stride(0) if out is not None else 0, _stream_ptr(stream)))
+    return eps, out
 
 
 def batch_solve(ctxs, e_refs, psis, opts=None, hist_len=0, stream=None, raise_on_noconv=True, **kw):

@@ -574,6 +574,51 @@ void red_dot_re(int nb, int npw, const void *A, const void *B, int64_t ld, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Wave-function interpolation between k-points.
+
+// dst[b][g] = src[b][map[g]] (0 where map[g] < 0): coefficients onto another sphere
+__global__ void k_gather_pw(int nb, int npw_to, const double2 *__restrict__ src, int64_t lds,
+                            const int32_t *__restrict__ map, double2 *__restrict__ dst, int64_t ldd) {
+    const int b = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw_to) return;
+    const int32_t m = map[g];
+    dst[(int64_t)b * ldd + g] = m >= 0 ? src[(int64_t)b * lds + m] : make_double2(0.0, 0.0);
+}
+
+void gather_pw(int nb, int npw_to, const void *src, int64_t lds, const int32_t *map, void *dst, int64_t ldd,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_pw, dim3((npw_to + 255) / 256, nb), dim3(256), 0, st, nb, npw_to, (const double2 *)src,
+                       lds, map, (double2 *)dst, ldd);
+    PW_LAUNCH_CHECK();
+}
+
+// Hk[i][j] = alpha e1[i] delta_ij + (1 - alpha) sum_m conj(U[i][m]) U[j][m] e2[m]
+__global__ void k_kinterp_hk(int n, double alpha, const double *__restrict__ e1, const double *__restrict__ e2,
+                             const double2 *__restrict__ U, double2 *__restrict__ Hk) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n * n) return;
+    const int i = k / n, j = k % n;
+    double re = 0.0, im = 0.0;
+    for (int m = 0; m < n; ++m) {
+        const double2 a = U[(int64_t)i * n + m], b = U[(int64_t)j * n + m];
+        const double w = e2[m];
+        re += w * (a.x * b.x + a.y * b.y);        // conj(a) b
+        im += w * (a.x * b.y - a.y * b.x);
+    }
+    re *= 1.0 - alpha;
+    im *= 1.0 - alpha;
+    if (i == j) re += alpha * e1[i];
+    Hk[k] = make_double2(re, im);
+}
+
+void kinterp_hk(int n, double alpha, const double *e1, const double *e2, const void *U, void *Hk, hipStream_t st) {
+    hipLaunchKernelGGL(k_kinterp_hk, dim3((n * n + 255) / 256), dim3(256), 0, st, n, alpha, e1, e2,
+                       (const double2 *)U, (double2 *)Hk);
+    PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
 __global__ void k_fill_zero(uint4 *p, size_t n16) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) p[i] = make_uint4(0, 0, 0, 0);

@@ -15,7 +15,7 @@ HERE = Path(__file__).resolve().parent
 PKG = HERE.parent
 ROOT = PKG.parent
 OUT = PKG / "libpw.so"
-SOURCES = ["basis.cpp", "api.cpp", "solver.cpp", "linsolve.cpp", "chebfd.cpp", "fft.hip", "gemm.hip", "gemm_bf16.hip", "dense.hip", "mlp.hip",
+SOURCES = ["basis.cpp", "api.cpp", "solver.cpp", "linsolve.cpp", "chebfd.cpp", "kinterp.cpp", "fft.hip", "gemm.hip", "gemm_bf16.hip", "dense.hip", "mlp.hip",
            "blas1.hip", "tables.hip"]
 ARCH = os.environ.get("PW_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

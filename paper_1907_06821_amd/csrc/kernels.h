@@ -113,5 +113,9 @@ void cheb_step(int nb, int npw, const void *T, void *Uprev, void *Y, int64_t ld,
 void scale_copy(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, double s, hipStream_t);
 void lanczos_update(int npw, void *W, const void *V, const void *Vp, double alpha, double beta, hipStream_t);
 void red_dot_re(int nb, int npw, const void *A, const void *B, int64_t ld, double *out, BandRed, hipStream_t);
+// wave-function interpolation
+void gather_pw(int nb, int npw_to, const void *src, int64_t lds, const int32_t *map, void *dst, int64_t ldd,
+               hipStream_t);
+void kinterp_hk(int n, double alpha, const double *e1, const double *e2, const void *U, void *Hk, hipStream_t);
 
 }  // namespace pw
