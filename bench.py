@@ -30,9 +30,12 @@ E_ref holding 64 states, 136 vectors, 3 steps of a degree-1500 filter (the
 paper's degree), bounds from 40 Lanczos steps; per step, the residuals of the
 Ritz pairs nearest the folded solve's eigenvalues in the window.
 
+Fifth part ("kinterp"): wave-function interpolation of the 128 states near E_ref
+between k = 0 and k = (0, 0, 0.02) to the midpoint, against a direct solve there.
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
 --no-cpu (skip the CPU oracle leg) --no-solve --solve-legs a,b --no-linear
---linear-maxit N --no-chebfd --chebfd-degree D --chebfd-steps S
+--linear-maxit N --no-chebfd --chebfd-degree D --chebfd-steps S --chebfd-window N --no-kinterp
 --precision {fp64,mixed} (of the band-H psi leg).
 """
 from __future__ import annotations
@@ -320,6 +323,51 @@ def chebfd_leg(ctx, prob, nb, eig_ref=None, n_window=64, degree=1500, steps=3, l
     return out
 
 
+def kinterp_leg(prob, nb, nconv, dk=0.02, log=None):
+    """Wave-function interpolation along the wire axis: folded eigensolves (mixed +
+    M(G), 136 bands, 128 wanted) at k2 = 0 and k1 = (0, 0, dk), interpolation of
+    the 128 wanted states to the midpoint (alpha = 1/2), and a direct eigensolve
+    there for reference.  Reports the interpolation time against a solve's, and the
+    energy error of the interpolated states in the inner half of the window."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+    out = {"dk": dk, "alpha": 0.5, "n": nconv}
+    sol = {}
+    for name, kz in (("k2", 0.0), ("k1", dk), ("k", 0.5 * dk)):
+        p = dataclasses.replace(prob, kpt=(0.0, 0.0, kz))
+        ctx = pw.Context.from_problem(p, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+        psi = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=31)).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eig, res, st = pw.folded_cg_solve(ctx, p.e_ref, psi, tol=1e-6, maxit=4000, check_every=20, precision=1,
+                                          precond=1, nconv=nconv, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        keep = np.sort(np.argsort(np.abs(eig - p.e_ref), kind="stable")[:nconv])
+        sol[name] = (ctx, psi[torch.from_numpy(keep).to("cuda")].contiguous(), eig[keep])
+        out[f"solve_{name}_seconds"] = round(time.perf_counter() - t0, 3)
+        out[f"solve_{name}_converged"] = bool(st["converged"])
+    (c1, p1, e1), (c2, p2, e2), (ck, pk, ek) = sol["k1"], sol["k2"], sol["k"]
+    pw.kinterp(c1, c2, ck, 0.5, p1, e1, p2, e2)                   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eps, psik = pw.kinterp(c1, c2, ck, 0.5, p1, e1, p2, e2)
+    torch.cuda.synchronize()
+    out["interp_seconds"] = round(time.perf_counter() - t0, 4)
+    w = np.max(np.abs(ek - prob.e_ref))
+    inner = np.abs(ek - prob.e_ref) <= 0.5 * w
+    err = [np.min(np.abs(eps - x)) for x in ek[inner]]
+    out["inner_states"] = int(inner.sum())
+    out["max_energy_error_inner"] = float(np.max(err))
+    out["median_energy_error_inner"] = float(np.median(err))
+    out["speedup_vs_solve"] = round(out["solve_k_seconds"] / out["interp_seconds"], 1)
+    if log:
+        log(f"kinterp: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +384,7 @@ def main():
     ap.add_argument("--chebfd-degree", type=int, default=1500)
     ap.add_argument("--chebfd-steps", type=int, default=3)
     ap.add_argument("--chebfd-window", type=int, default=64, help="eigenstates inside the ChebFD window")
+    ap.add_argument("--no-kinterp", action="store_true", help="skip the k-point interpolation leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -445,6 +494,8 @@ def main():
         line["chebfd"] = chebfd_leg(ctx, prob, nb + nbuf, eig_ref, n_window=args.chebfd_window,
                                     degree=args.chebfd_degree,
                                     steps=args.chebfd_steps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if not args.no_kinterp:
+        line["kinterp"] = kinterp_leg(prob, nb + nbuf, nb, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
     else:
