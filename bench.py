@@ -456,6 +456,17 @@ def main():
                 "frac": round(d["frac"], 4), "kernel": dom,
                 "traffic": measured_traffic(dom, mixed, nb, next((r["sched"] for r in tuned[nb] if r["pass_"] == 4),
                                                                  None))}
+    # whole-step roofline: the ideal time of every H psi launch at its bound (bytes at HBM peak or flops at
+    # the matrix peak) plus the FP64 block GEMMs of each CG iteration (Gram X^H X, X^H P, the P update and
+    # the three rotations of X, Y, AX: six products of 8 npw nb^2 flops), over the measured time
+    ideal = 0.0
+    for k, v in stages.items():
+        bound, amount, unit = work[k]
+        ideal += v["launches"] * amount / ((HBM_PEAK_GBS * 1e9) if bound == "hbm" else
+                                           ((BF16_PEAK_TFS if mixed else FP64_PEAK_TFS) * 1e12))
+    block = 6 * 8.0 * ctx.npw * nb * nb / (FP64_PEAK_TFS * 1e12) * args.steps
+    roofline["step_frac"] = round((ideal + block) / dt, 4)
+    roofline["step_ideal_ms"] = round((ideal + block) / args.steps * 1e3, 4)
 
     line = {
         "metric": "band-Hψ/sec and folded-CG time to residual 1e-6 (mixed+learned vs FP64)",
