@@ -128,3 +128,20 @@ def test_chebfd_wire256_sampled_residuals(torch_cuda):
     for b in (0, 17):
         r = np.linalg.norm(op.apply(v[b:b + 1])[0] - eig[b] * v[b])
         assert abs(r - res[b]) < 1e-9 * max(1.0, res[b]), (b, r, res[b])
+
+
+def test_chebfd_single_vector(torch_cuda):
+    """nb = 1: the step returns the Rayleigh quotient of the filtered, normalised
+    vector and its residual, as the oracle's step does."""
+    import paper_1907_06821_amd as pw
+    prob = synth.small_nonlocal_problem(kpt=(0.11, -0.23, 0.07))
+    op = oracle_for(prob)
+    lam, emin, emax = _bounds(op.dense())
+    v0 = synth.start_vectors(4, 1, op.npw)
+    ctx = gpu_context(prob, max_bands=1)
+    t = to_dev(v0)
+    eig, res = pw.chebfd_step(ctx, t, 0.6, 0.3, 60, emin, emax)
+    oeps, ov, ores = chebfd_step(op.apply, v0, 0.6, 0.3, emin, emax, 60)
+    assert abs(eig[0] - oeps[0]) < 1e-12 and abs(res[0] - ores[0]) < 1e-11
+    v = t.cpu().numpy()
+    assert abs(abs(np.vdot(ov[0], v[0])) - 1.0) < 1e-12

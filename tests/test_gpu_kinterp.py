@@ -65,3 +65,20 @@ def test_kinterp_errors(torch_cuda):
     with pytest.raises(pw.PwError) as ex:                        # k2 states all zero: no Gram-Schmidt
         pw.kinterp(ctxs[0], ctxs[1], ctxs[2], 0.5, to_dev(v1), e1, to_dev(np.zeros_like(v2)), e2)
     assert ex.value.status == pw.PW_ENOTPD
+
+
+def test_single_state_closed_form(torch_cuda):
+    """n = 1: U = S/|S| has modulus one, so eps(k) = alpha eps1 + (1 - alpha) eps2,
+    and the state is alpha psi1 + (1 - alpha) U psi2."""
+    import paper_1907_06821_amd as pw
+    ops, ctxs, e1, v1, e2, v2 = _pair(0.11, 0.21, 0.16, n=1)
+    for alpha in (0.3, 0.8):
+        eps, psik = pw.kinterp(ctxs[0], ctxs[1], ctxs[0], alpha, to_dev(v1), e1, to_dev(v2), e2)
+        assert abs(eps[0] - (alpha * e1[0] + (1 - alpha) * e2[0])) < 1e-13
+        from oracle.kinterp import to_basis
+        p2 = to_basis(v2, ops[1].miller, ops[0].miller)
+        s = np.vdot(p2[0], v1[0])
+        want = alpha * v1[0] + (1 - alpha) * (s / abs(s)) * p2[0]
+        got = psik.cpu().numpy()[0]
+        ph = np.vdot(want, got)
+        assert np.max(np.abs(got * (abs(ph) / ph) - want)) < 1e-12
