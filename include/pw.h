@@ -360,8 +360,9 @@ pw_status pw_spectral_bounds(pw_ctx *ctx, const void *v0, int32_t steps, double 
  * sum_jl c_j U_jl psi2_l on ctxk's sphere (device complex128 [n][ldo]; not
  * renormalised).  The three contexts (at k1, k2 and k) must share cell, grid and
  * cutoff; coefficients are matched by Miller triple, one missing from a sphere
- * counting as zero.  n <= 1024.  PW_ENOTPD if the overlap rows are linearly
- * dependent.  Allocates its scratch for the call; synchronises `stream`. */
+ * counting as zero.  n <= 1024; psi_out must not alias psi1 or psi2.  PW_ENOTPD
+ * if the overlap rows are linearly dependent.  Allocates its scratch for the
+ * call; synchronises `stream`. */
 pw_status pw_kinterp(pw_ctx *ctx1, pw_ctx *ctx2, pw_ctx *ctxk, double alpha, int32_t n, const void *psi1, int64_t ld1,
                      const double *eps1, const void *psi2, int64_t ld2, const double *eps2, double *eps_out,
                      void *psi_out, int64_t ldo, void *stream);

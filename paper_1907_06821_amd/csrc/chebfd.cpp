@@ -96,6 +96,7 @@ pw_status pw_cheb_filter(pw_ctx *ctx, int32_t nb, const void *psi, int64_t ld, v
         PW_CHECK(ctx->flags & PW_PREP_C128, PW_EUNSUPPORTED, "the filter needs a complex128 context");
         PW_CHECK(nb >= 1 && nb <= ctx->max_bands, PW_EINVAL, "nb %d must be in [1, max_bands]", nb);
         PW_CHECK(ld >= ctx->basis.npw && ldo >= ctx->basis.npw, PW_EINVAL, "ld or ldo < npw");
+        PW_CHECK(psi != out, PW_EINVAL, "psi and out must not alias");
         check_window(e, half_width, degree, emin, emax);
         hipStream_t st = (hipStream_t)stream;
         const int npw = ctx->basis.npw;

@@ -62,6 +62,7 @@ pw_status pw_kinterp(pw_ctx *ctx1, pw_ctx *ctx2, pw_ctx *ctxk, double alpha, int
         PW_CHECK(n >= 1 && n <= 1024 && n <= np1 && n <= np2, PW_EINVAL, "n %d must be in [1, min(1024, npw)]", n);
         PW_CHECK(ld1 >= np1 && ld2 >= np2, PW_EINVAL, "ld1 or ld2 smaller than its sphere");
         PW_CHECK(!psi_out || ldo >= npk, PW_EINVAL, "ldo < npw of the k context");
+        PW_CHECK(psi_out != psi1 && psi_out != psi2, PW_EINVAL, "psi_out must not alias psi1 or psi2");
         PW_CHECK(std::isfinite(alpha), PW_ENAN, "non-finite alpha");
         for (int i = 0; i < n; ++i)
             PW_CHECK(std::isfinite(eps1[i]) && std::isfinite(eps2[i]), PW_ENAN, "non-finite energy %d", i);
