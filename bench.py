@@ -202,19 +202,25 @@ def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
                           "max_delta_all": float(np.max(res))}}
     miller = pw.basis_miller(prob.grid, prob.cell, prob.ecut, prob.kpt)
     w = torch.from_numpy(synth.boundary_sources(2, nrhs, miller, prob.cell, kpt=prob.kpt, seed=0)).to("cuda")
-    prof = None
+    # per-stage times from a profiled run of the M' solve (launched kernel by kernel: the per-stage events
+    # are recorded by the host), then the timed runs (each check interval replayed from a recorded graph)
+    x = torch.zeros_like(w)
+    pw.profile_begin(ctx, 40000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pw.folded_linear_solve(ctx, prob.e_ref, w, x, tol=tol, maxit=maxit, check_every=10, raise_on_noconv=False,
+                           precond=1, phi=phi, eps=eig, delta=res)
+    torch.cuda.synchronize()
+    out["mprime_profiled_seconds"] = round(time.perf_counter() - t0, 3)
+    prof = pw.profile_end(ctx)
     for name, kw in (("mprime", dict(precond=1, phi=phi, eps=eig, delta=res)), ("m_only", dict(precond=0))):
         x = torch.zeros_like(w)
-        if name == "mprime":
-            pw.profile_begin(ctx, 40000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         err, lst = pw.folded_linear_solve(ctx, prob.e_ref, w, x, tol=tol, maxit=maxit, check_every=10,
                                           raise_on_noconv=False, hist_len=maxit // 10, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        if name == "mprime":
-            prof = pw.profile_end(ctx)
         out[name] = {"seconds": round(dt, 3), "iters": lst["iters"], "converged": lst["converged"],
                      "max_error": lst["max_resid"], "band_hpsi_per_s": round(lst["n_hpsi"] / dt, 1)}
         if log:
@@ -255,7 +261,7 @@ def linear_leg(ctx, prob, nb, nconv, nrhs=8, tol=1e-8, maxit=3000, log=None):
         ach = stage_bytes[k] / (ms / n / 1e3) / 1e9
         stages[k] = {"avg_us": round(ms / n * 1e3, 2), "launches": n, "bytes": stage_bytes[k],
                      "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "share": round(ms / 1e3 / out["mprime"]["seconds"], 4)}
+                     "share": round(ms / 1e3 / out["mprime_profiled_seconds"], 4)}
     if stages:
         dom = max(stages, key=lambda k: stages[k]["avg_us"] * stages[k]["launches"])
         d = stages[dom]

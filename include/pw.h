@@ -281,6 +281,9 @@ typedef struct {
     double delta_e;       /* dE of M(G) (Ha), > 0 */
     int32_t check_every;  /* iterations between reads of the error by the host */
     int32_t verbose;      /* print the error at each check to stderr */
+    int32_t use_graph;    /* 1 (default): record the check_every iterations between two error reads
+                             once into a HIP graph and replay it (same kernels in the same order);
+                             0: launch them one by one.  Not used while per-stage profiling is on. */
 } pw_lin_opts;
 
 typedef struct {

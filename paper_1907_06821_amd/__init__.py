@@ -65,7 +65,7 @@ class pw_cg_opts(C.Structure):
 
 class pw_lin_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precond", C.c_int32), ("delta_e", C.c_double),
-                ("check_every", C.c_int32), ("verbose", C.c_int32)]
+                ("check_every", C.c_int32), ("verbose", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class pw_lin_stats(C.Structure):

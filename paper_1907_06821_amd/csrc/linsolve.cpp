@@ -8,7 +8,9 @@
 //   X += alpha P, Y += alpha YP, R -= alpha AP       (Y = (H - E) X carried along)
 //   Z = K R, beta = <r', z'> / <r, z>, P = Z + beta P
 // The paper's error ||(H - E) x - w|| is ||Y - W||, read by the host every
-// check_every iterations; the final value comes from a fresh H psi.
+// check_every iterations; the final value comes from a fresh H psi.  The
+// check_every iterations between two reads are recorded once into a HIP graph and
+// replayed (the step lengths live on the device and the blocks never move).
 //
 // K is the paper's M(G) or the eigenstate-augmented M' (Sec. II.B, M' equation)
 // in its Hermitian form
@@ -23,6 +25,19 @@
 #include "kernels.h"
 
 namespace pw {
+
+namespace {
+struct SegmentGraph {
+    hipStream_t cap = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~SegmentGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (g) (void)hipGraphDestroy(g);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+}  // namespace
 
 void hpsi_any(pw_ctx *ctx, pw_dtype dt, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
               hipStream_t st);
@@ -68,8 +83,10 @@ pw_status folded_linsolve(pw_ctx *ctx, double E, int nrhs, const void *w, int64_
         PW_HIP(hipMemcpyAsync(invd.p, h_invd.data(), (size_t)nev * 8, hipMemcpyHostToDevice, st));
         PW_HIP(hipStreamSynchronize(st));
     }
+    hipStream_t cur = st;   // the launch stream: st, or the capture stream while a segment is recorded
     // Z = K R, then rz <- <R, Z> and beta = rz_new / rz_old
     auto precondition = [&](bool first) {
+        const hipStream_t st = cur;
         if (!aug) {
             lin_mdiag(nrhs, npw, R, nullptr, Z, L, kin, E, de2, rz, beta, first, true, br, st);
             return;
@@ -83,11 +100,7 @@ pw_status folded_linsolve(pw_ctx *ctx, double E, int nrhs, const void *w, int64_
         lin_rz_beta(nrhs, npw, R, Z, L, rz, beta, first, br, st);
     };
 
-    int64_t n_hpsi = 0;
-    auto hm = [&](const void *in, int64_t ldi, void *out) {
-        hpsi_any(ctx, PW_C128, nrhs, in, ldi, out, L, E, st);
-        n_hpsi += nrhs;
-    };
+    auto hm = [&](const void *in, int64_t ldi, void *out) { hpsi_any(ctx, PW_C128, nrhs, in, ldi, out, L, E, cur); };
     // set-up: R = (H - E) w - (H - E)^2 x0, Y = (H - E) x0, P = Z = K R
     copy_block(nrhs, npw, psi, ld, X, L, st);
     hm(X, L, Y);
@@ -101,16 +114,49 @@ pw_status folded_linsolve(pw_ctx *ctx, double E, int nrhs, const void *w, int64_
     const int check = std::max(1, o.check_every);
     int it = 0, nhist = 0;
     bool converged = false;
+    // one segment: `len` PCG iterations and the device side of the check that ends it
+    auto segment = [&](int len) {
+        const hipStream_t st = cur;
+        for (int k = 0; k < len; ++k) {
+            hm(P, L, YP);
+            hm(YP, L, AP);
+            lin_alpha(nrhs, npw, YP, L, rz, alpha, br, st);
+            lin_update(nrhs, npw, X, Y, R, P, YP, AP, L, alpha, st);
+            precondition(false);
+            lin_pupdate(nrhs, npw, Z, P, L, beta, st);
+        }
+        lin_err(nrhs, npw, Y, L, w, ldw, err, br, st);
+    };
+    // a full segment is pure device work with fixed pointers: it is recorded once into a graph and
+    // replayed (not while per-stage profiling is on, whose events are recorded on the host's side)
+    SegmentGraph graph;
+    const bool use_graph = o.use_graph && !ctx->prof_on;
     while (it < o.maxit) {
-        ++it;
-        hm(P, L, YP);
-        hm(YP, L, AP);
-        lin_alpha(nrhs, npw, YP, L, rz, alpha, br, st);
-        lin_update(nrhs, npw, X, Y, R, P, YP, AP, L, alpha, st);
-        precondition(false);
-        lin_pupdate(nrhs, npw, Z, P, L, beta, st);
-        if (it % check == 0 || it == o.maxit) {
-            lin_err(nrhs, npw, Y, L, w, ldw, err, br, st);
+        const int len = std::min(check, o.maxit - it);
+        if (use_graph && len == check) {
+            if (!graph.exec) {
+                PW_HIP(hipStreamCreateWithFlags(&graph.cap, hipStreamNonBlocking));
+                PW_HIP(hipStreamBeginCapture(graph.cap, hipStreamCaptureModeThreadLocal));
+                cur = graph.cap;
+                try {
+                    segment(len);
+                } catch (...) {
+                    cur = st;
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(graph.cap, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                cur = st;
+                PW_HIP(hipStreamEndCapture(graph.cap, &graph.g));
+                PW_HIP(hipGraphInstantiate(&graph.exec, graph.g, nullptr, nullptr, 0));
+            }
+            PW_HIP(hipGraphLaunch(graph.exec, st));
+        } else {
+            segment(len);
+        }
+        it += len;
+        {
             PW_HIP(hipMemcpyAsync(h_err.data(), err, (size_t)nrhs * 8, hipMemcpyDeviceToHost, st));
             PW_HIP(hipStreamSynchronize(st));
             double mx = 0.0;
@@ -143,6 +189,7 @@ pw_status folded_linsolve(pw_ctx *ctx, double E, int nrhs, const void *w, int64_
         if (resid) resid[l] = h_err[l];
         mx = std::max(mx, h_err[l]);
     }
+    const int64_t n_hpsi = (int64_t)(3 + 2 * it + 1) * nrhs;    // set-up, two per iteration, final check
     if (stats) {
         stats->iters = it;
         stats->converged = converged ? 1 : 0;
@@ -170,6 +217,7 @@ void pw_lin_opts_default(pw_lin_opts *o) {
     o->delta_e = 1.0;
     o->check_every = 10;
     o->verbose = 0;
+    o->use_graph = 1;
 }
 
 pw_status pw_folded_linear_solve(pw_ctx *ctx, double e, int32_t nrhs, const void *w, int64_t ldw, void *psi,

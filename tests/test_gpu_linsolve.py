@@ -194,3 +194,29 @@ def test_lin_wire256_mprime_residuals_by_oracle(wire_eigs):
     for l in (0, 5):
         r = np.linalg.norm(op.apply(x[l:l + 1], shift=e)[0] - w[l])
         assert r <= 1.5e-8, (l, r)
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_lin_graph_replays_equal_eager(torch_cuda, precond):
+    """The recorded segment, replayed at every check (with the host's reads in
+    between), gives bit for bit the eager solve: same iterations, solution and
+    errors; a maxit that is not a multiple of check_every ends with an eager
+    segment."""
+    prob = synth.config(1)
+    op = oracle_for(prob)
+    h = op.dense()
+    w = synth.boundary_sources(1, 3, op.miller, prob.cell, seed=9)
+    kw = {}
+    if precond:
+        from oracle.eigen import nearest_eigenpairs
+        eps, phi, _, _ = nearest_eigenpairs(h, prob.e_ref, 8)
+        kw = dict(phi=phi, eps=eps, delta=np.full(8, 1e-6))
+    ctx = gpu_context(prob, max_bands=8)
+    for maxit in (4000, 47):
+        runs = [_lin(ctx, prob.e_ref, w, precond=precond, tol=1e-11, maxit=maxit, check_every=5, use_graph=g,
+                     raise_on_noconv=False, hist_len=1000, **kw) for g in (0, 1)]
+        (xa, ra, sa), (xb, rb, sb) = runs
+        assert np.array_equal(xa, xb) and np.array_equal(ra, rb)
+        assert sa["iters"] == sb["iters"] and sa["n_hpsi"] == sb["n_hpsi"]
+        assert np.array_equal(sa["hist"], sb["hist"])
+        assert (sa["iters"] == maxit) == (maxit == 47)
