@@ -217,6 +217,10 @@ typedef struct {
     int32_t snap_cap;     /* capacity of snap_buf in snapshots */
     int32_t nconv;        /* only the nconv Ritz pairs nearest e_ref must reach tol (0 = all nb); the
                              other nb - nconv bands are buffer bands that widen the folded gap */
+    int32_t batch_launch; /* pw_batch_solve only: 1 (default) launches each problem's recorded segment
+                             graph in turn every check round; 0 launches one graph holding all running
+                             problems' segments as child graphs (rebuilt when a problem finishes or
+                             changes precision).  Same kernels and results either way. */
 } pw_cg_opts;
 
 typedef struct {
@@ -249,9 +253,9 @@ pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, i
  * pw_folded_cg_solve, stats (host [nprob], optional), status (host [nprob],
  * optional) the per-problem result.  Every problem runs the kernels of its own
  * pw_folded_cg_solve in the same order (same results); the check_every
- * iterations between checks are recorded once per problem into a graph, and the
- * graphs of all running problems are replayed as one graph (independent child
- * graphs) on `stream`, one launch per check round, with one host read of every
+ * iterations between checks are recorded once per problem into a graph, and every
+ * check round replays the running problems' graphs on `stream` (one after another,
+ * or as one graph of child graphs: opts->batch_launch), with one host read of every
  * problem's residuals in between.  Snapshots are not supported.  Returns PW_OK
  * if every problem converged, PW_ENOCONV if some did not, else the first other
  * error.  Synchronises. */

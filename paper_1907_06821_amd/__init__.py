@@ -60,7 +60,8 @@ class pw_cg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precond", C.c_int32), ("delta_e", C.c_double),
                 ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32),
                 ("mixed_switch", C.c_double), ("stall_checks", C.c_int32), ("snap_buf", C.c_void_p),
-                ("snap_every", C.c_int32), ("snap_cap", C.c_int32), ("nconv", C.c_int32)]
+                ("snap_every", C.c_int32), ("snap_cap", C.c_int32), ("nconv", C.c_int32),
+                ("batch_launch", C.c_int32)]
 
 
 class pw_lin_opts(C.Structure):

@@ -371,18 +371,20 @@ pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double
 // ---------------------------------------------------------------------------
 // Batched solves: independent problems (one context each) advance together.
 // Each problem's segment (check_every iterations and the device side of the
-// check) is recorded once per (length, H psi precision) into a graph; the
-// segments of all running problems are the independent child graphs of one
-// graph, launched once per check round on the caller's stream.  Between rounds
-// the host reads every problem's residuals; the graph is rebuilt only when a
-// problem finishes or changes precision.  Per problem, the kernels and their
-// order are those of the unbatched solve.
+// check) is recorded once per (length, H psi precision) into a graph.  Each
+// check round then either launches every running problem's instantiated segment
+// back to back on the caller's stream (batch_launch = 1), or launches one graph
+// whose independent child graphs are those segments (batch_launch = 0; rebuilt
+// and instantiated again whenever a problem finishes or changes precision).
+// Between rounds the host reads every problem's residuals.  Per problem, the
+// kernels and their order are those of the unbatched solve.
 // ---------------------------------------------------------------------------
 namespace {
 struct SegGraph {
     int len = 0;
     bool low = false;
     hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
     int64_t hpsi = 0;
 };
 struct BatchItem {
@@ -400,8 +402,10 @@ struct BatchRes {
     ~BatchRes() {
         if (exec) (void)hipGraphExecDestroy(exec);
         for (auto &b : items)
-            for (auto &g : b.segs)
+            for (auto &g : b.segs) {
+                if (g.exec) (void)hipGraphExecDestroy(g.exec);
                 if (g.g) (void)hipGraphDestroy(g.g);
+            }
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -437,6 +441,7 @@ SegGraph record_segment(FcgRun &r, int len, hipStream_t cap) {
 pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int nb, void *const *psi,
                       const int64_t *ld, double *const *eig, double *const *resid, const pw_cg_opts &o,
                       pw_cg_stats *stats, int32_t *status, hipStream_t st) {
+    const bool each = o.batch_launch != 0;   // launch each problem's recorded segment, or one graph of them all
     BatchRes R;
     R.items.resize(nprob);
     PW_HIP(hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking));
@@ -460,7 +465,9 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
                 if (!sg) {
                     b.segs.push_back(record_segment(r, len, R.cap));
                     sg = &b.segs.back();
+                    if (each) PW_HIP(hipGraphInstantiate(&sg->exec, sg->g, nullptr, nullptr, 0));
                 }
+                if (each) PW_HIP(hipGraphLaunch(sg->exec, st));
                 want = sg->g;
                 b.len = len;
                 b.hpsi = sg->hpsi;
@@ -470,7 +477,7 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
             b.cur = want;
         }
         if (!any) break;
-        if (changed || !R.exec) {
+        if (!each && (changed || !R.exec)) {
             if (R.exec) {
                 PW_HIP(hipGraphExecDestroy(R.exec));
                 R.exec = nullptr;
@@ -490,7 +497,7 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
             }
             PW_HIP(hipGraphDestroy(parent));
         }
-        PW_HIP(hipGraphLaunch(R.exec, st));
+        if (!each) PW_HIP(hipGraphLaunch(R.exec, st));
         for (BatchItem &b : R.items) {
             if (!b.active) continue;
             b.run->it += b.len;
@@ -577,6 +584,7 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->snap_every = 0;
     o->snap_cap = 0;
     o->nconv = 0;
+    o->batch_launch = 1;
 }
 
 pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld, double *eig,

@@ -1,6 +1,7 @@
-"""Batched solves of uneven cubic problems (recorded graphs replayed)
-against the same problems solved one by one: the same kernels in the same order,
-so every check's residuals and the final eigenpairs agree bit for bit."""
+"""Batched solves of uneven cubic problems (recorded graphs replayed, each
+problem's in turn or all as one graph) against the same problems solved one by
+one: the same kernels in the same order, so every check's residuals and the
+final eigenpairs agree bit for bit."""
 import numpy as np
 import pytest
 
@@ -9,8 +10,9 @@ from paper_1907_06821_amd import synth
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("launch", [1, 0])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batch_equals_individual_solves(torch_cuda, precision):
+def test_batch_equals_individual_solves(torch_cuda, precision, launch):
     import torch
     import paper_1907_06821_amd as pw
     probs = synth.batched_problems(6, seed=1)
@@ -25,7 +27,7 @@ def test_batch_equals_individual_solves(torch_cuda, precision):
         ind.append((e, r, st, psi))
     psis = [s.clone() for s in starts]
     eigs, ress, sts, status = pw.batch_solve(ctxs, [p.e_ref for p in probs], psis, hist_len=16,
-                                             raise_on_noconv=False, **kw)
+                                             raise_on_noconv=False, batch_launch=launch, **kw)
     for i in range(len(probs)):
         e, r, st, psi = ind[i]
         assert sts[i]["iters"] == st["iters"]
