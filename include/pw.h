@@ -7,7 +7,10 @@
  * the paper's folded equation (Sec. II.B); the few-states-near-E use is the
  * folded-spectrum method the paper names in Sec. II.B; the G-diagonal
  * preconditioner M(G) and the eigen-residual Delta_i = ||H phi_i - eps_i phi_i||
- * are defined under the paper's M' equation (Sec. II.B).
+ * are defined under the paper's M' equation (Sec. II.B).  Around the eigensolve:
+ * the folded linear equation of the system states with the eigenstate-augmented
+ * preconditioner M' (Sec. II.B), Chebyshev filter diagonalisation of an energy
+ * window (Sec. II.B) and wave-function interpolation between k-points (Sec. II.C).
  *
  * Conventions shared by every entry point
  *   - Cell: orthorhombic, lengths L = (L0, L1, L2) bohr, axis 2 is z.
