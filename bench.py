@@ -388,6 +388,53 @@ def kinterp_leg(prob, nb, nconv, dk=0.02, log=None):
     return out
 
 
+def wire4000_hpsi(steps=3, warmup=1):
+    """Complex64 + BF16 H psi on the 4000-atom wire (50 x 50 x 200 bohr, 128 x 128 x 512 grid,
+    755,605 plane waves, 16,000 projectors) for 1024 bands in one call, from a complex64-only
+    context (BF16 projector planes built 64 atoms at a time).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+    torch.cuda.set_device(0)
+    prob = synth.config(5)
+    nb = prob.nbands
+    t0 = time.perf_counter()
+    ctx = pw.Context.from_problem(prob, max_bands=nb, flags=pw.PW_PREP_C64)
+    torch.cuda.synchronize()
+    t_ctx = time.perf_counter() - t0
+    psi = torch.from_numpy(synth.start_vectors(5, nb, ctx.npw).astype(np.complex64)).to("cuda")
+    out = torch.empty_like(psi)
+    for _ in range(warmup):
+        pw.hpsi(ctx, psi, shift=prob.e_ref, out=out)
+    torch.cuda.synchronize()
+    pw.profile_begin(ctx, 100)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pw.hpsi(ctx, psi, shift=prob.e_ref, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = pw.profile_end(ctx)
+    work = stage_work(ctx, nb, 8, ctx.nproj)
+    stages = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        bound, amount, unit = work[k]
+        avg_s = ms / n / 1e3
+        ach = amount / avg_s / (1e9 if bound == "hbm" else 1e12)
+        peak = HBM_PEAK_GBS if bound == "hbm" else BF16_PEAK_TFS
+        stages[k] = {"bound": bound, "avg_ms": round(ms / n, 3), "achieved": round(ach, 1), "peak": peak,
+                     "frac": round(ach / peak, 4)}
+    print(json.dumps({"metric": "band-Hpsi/s, complex64 + BF16 projector GEMMs", "value": round(nb * steps / dt, 1),
+                      "unit": "band-Hpsi/s", "ms_per_hpsi": round(dt / steps * 1e3, 3), "dtype": "c64+bf16",
+                      "config": {"workload": "wire4000: 50x50x200 bohr, 128x128x512 grid, Ecut 10 Ha, 4000 atoms x 4 "
+                                             "KB projectors, 1024 bands in one call", "npw": ctx.npw,
+                                 "nproj": ctx.nproj, "bands": nb, "grid": list(ctx.grid)},
+                      "context_seconds": round(t_ctx, 2), "device_bytes": ctx.info()["device_bytes"],
+                      "stages": stages}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -405,9 +452,14 @@ def main():
     ap.add_argument("--chebfd-steps", type=int, default=3)
     ap.add_argument("--chebfd-window", type=int, default=64, help="eigenstates inside the ChebFD window")
     ap.add_argument("--no-kinterp", action="store_true", help="skip the k-point interpolation leg")
+    ap.add_argument("--wire4000-hpsi", action="store_true",
+                    help="only: complex64 H psi throughput on the 4000-atom wire (1024 bands, about 150 GB)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.wire4000_hpsi and args.gpus == 1:
+        wire4000_hpsi(steps=max(1, args.steps if args.steps != 40 else 3), warmup=max(1, args.warmup))
+        return
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")

@@ -245,20 +245,40 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
         upload(d_mil, mil, tmp);
         std::vector<double> pos(pot->pos, pot->pos + 3 * c->natom);
         upload(d_pos, pos, tmp);
-        c->d_beta64.alloc((size_t)c->nproj * b.npw * 16);
-        build_projectors(b.npw, c->natom, c->nl, d_mil.as<int32_t>(), *cell, d_pos.as<double>(), pot->sigma,
-                         c->d_beta64.p, st);
+        const bool c128 = flags & PW_PREP_C128;
+        if (c128) {
+            c->d_beta64.alloc((size_t)c->nproj * b.npw * 16);
+            build_projectors(b.npw, c->natom, c->nl, d_mil.as<int32_t>(), *cell, d_pos.as<double>(), pot->sigma,
+                             c->d_beta64.p, st);
+        }
         if (flags & PW_PREP_C64) {
             c->ldb16 = ((b.npw + 63) / 64) * 64;
             c->d_beta_bf16.alloc((size_t)2 * c->nproj * c->ldb16 * 2);
-            beta_to_bf16(c->nproj, b.npw, c->ldb16, c->d_beta64.p, c->d_beta_bf16.p,
-                         (char *)c->d_beta_bf16.p + (size_t)c->nproj * c->ldb16 * 2, st);
+            char *br = (char *)c->d_beta_bf16.p, *bi = br + (size_t)c->nproj * c->ldb16 * 2;
             const size_t tplane = (size_t)bf16_ld(b.npw) * bf16_ld(c->nproj) * 2;
             c->d_betaT_bf16.alloc(2 * tplane);
-            beta_to_bf16_t(c->nproj, b.npw, c->d_beta64.p, c->d_betaT_bf16.p, (char *)c->d_betaT_bf16.p + tplane, st);
+            char *tr = (char *)c->d_betaT_bf16.p, *ti = tr + tplane;
+            if (c128) {
+                beta_to_bf16(c->nproj, b.npw, c->ldb16, c->d_beta64.p, br, bi, st);
+                beta_to_bf16_t(c->nproj, b.npw, c->d_beta64.p, tr, ti, st);
+            } else {
+                // complex64 only: the FP64 rows are built and rounded 64 atoms at a time, so the FP64
+                // table (16 nproj npw bytes) never exists whole; the BF16 planes are the same bits
+                constexpr int kAtomChunk = 64;
+                DevBuf chunk;
+                chunk.alloc((size_t)std::min(c->natom, kAtomChunk) * c->nl * b.npw * 16);
+                for (int a0 = 0; a0 < c->natom; a0 += kAtomChunk) {
+                    const int na = std::min(kAtomChunk, c->natom - a0), p0 = a0 * c->nl, rows = na * c->nl;
+                    build_projectors(b.npw, na, c->nl, d_mil.as<int32_t>(), *cell, d_pos.as<double>() + 3 * a0,
+                                     pot->sigma, chunk.p, st);
+                    beta_to_bf16(rows, b.npw, c->ldb16, chunk.p, br + (size_t)p0 * c->ldb16 * 2,
+                                 bi + (size_t)p0 * c->ldb16 * 2, st);
+                    beta_to_bf16_t_rows(c->nproj, p0, rows, b.npw, chunk.p, tr, ti, st);
+                }
+                PW_HIP(hipStreamSynchronize(st));     // the chunk buffer dies here
+            }
             c->d_bf16_ws.alloc(bf16_scratch_bytes(c->nproj, b.npw, max_bands));
             acct += c->d_beta_bf16.bytes + c->d_betaT_bf16.bytes + c->d_bf16_ws.bytes;
-            if (!(flags & PW_PREP_C128)) c->d_beta64.free_();
         }
         acct += c->d_beta64.bytes;
         PW_HIP(hipStreamSynchronize(st));   // d_mil, d_pos die here

@@ -69,20 +69,21 @@ __global__ void k_c64_to_planes(int rows, int n, const float2 *__restrict__ src,
     im[(int64_t)r * ldp + g] = f2bf(v.y);
 }
 
-// complex128 table [rows][n] -> transposed BF16 planes [ldn][ldr] (zero padded)
+// complex128 table rows [r_off, r_off + rows) ([rows][n]) -> columns of the transposed BF16 planes
+// [ldn][ldr]; columns from r_off + rows up to r_end are written as zeros (padding)
 __global__ void k_c128_to_planes_t(int rows, int n, const double2 *__restrict__ src, int64_t ldr, int64_t ldn,
-                                   uint16_t *__restrict__ re, uint16_t *__restrict__ im) {
+                                   uint16_t *__restrict__ re, uint16_t *__restrict__ im, int r_off, int64_t r_end) {
     __shared__ double2 tile[32][33];
-    const int r0 = blockIdx.y * 32, g0 = blockIdx.x * 32;
+    const int r0 = r_off + blockIdx.y * 32, g0 = blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
     for (int y = ty; y < 32; y += 8) {
-        const int r = r0 + y, g = g0 + tx;
+        const int r = r0 + y - r_off, g = g0 + tx;
         tile[y][tx] = (r < rows && g < n) ? src[(int64_t)r * n + g] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int y = ty; y < 32; y += 8) {
         const int g = g0 + y, r = r0 + tx;
-        if (g < ldn && r < ldr) {
+        if (g < ldn && r < r_end) {
             const double2 v = tile[tx][y];
             re[(int64_t)g * ldr + r] = f2bf((float)v.x);
             im[(int64_t)g * ldr + r] = f2bf((float)v.y);
@@ -91,10 +92,19 @@ __global__ void k_c128_to_planes_t(int rows, int n, const double2 *__restrict__ 
 }
 
 void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st) {
+    beta_to_bf16_t_rows(nproj, 0, nproj, npw, beta64, tr, ti, st);
+}
+
+// rows [p0, p0 + rows) of an nproj-row table (beta64 holds just those rows); the
+// chunk that ends the table also writes the zero columns up to the padded width
+void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
+                         hipStream_t st) {
     const int64_t ldr = bf16_ld(nproj), ldn = bf16_ld(npw);
-    dim3 grid((unsigned)((ldn + 31) / 32), (unsigned)((ldr + 31) / 32));
-    hipLaunchKernelGGL(k_c128_to_planes_t, grid, dim3(256), 0, st, nproj, npw, (const double2 *)beta64, ldr, ldn,
-                       (uint16_t *)tr, (uint16_t *)ti);
+    PW_CHECK(p0 % 32 == 0 && p0 + rows <= nproj, PW_EINVAL, "table chunk must start on a 32-row boundary");
+    const int64_t r_end = p0 + rows == nproj ? ldr : p0 + rows;
+    dim3 grid((unsigned)((ldn + 31) / 32), (unsigned)((r_end - p0 + 31) / 32));
+    hipLaunchKernelGGL(k_c128_to_planes_t, grid, dim3(256), 0, st, rows, npw, (const double2 *)beta64, ldr, ldn,
+                       (uint16_t *)tr, (uint16_t *)ti, p0, r_end);
     PW_LAUNCH_CHECK();
 }
 

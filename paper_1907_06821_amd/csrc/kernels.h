@@ -30,6 +30,8 @@ size_t cnt_partial_bytes(int M, int N, int K);
 int64_t bf16_ld(int n);
 size_t bf16_scratch_bytes(int nproj, int npw, int max_bands);
 void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st);
+void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
+                         hipStream_t st);
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
                int64_t ld, void *scratch, void *partial, hipStream_t st);
 void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,

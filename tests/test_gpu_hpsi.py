@@ -243,3 +243,25 @@ def test_hpsi_wire2000_sampled_bands(torch_cuda):
     for i in range(len(bands)):
         assert rel_err(got[i], ref[i]) < 1e-12
         assert rel_err(got32[i], ref[i]) < 2e-3
+
+
+@pytest.mark.parametrize("which", ["wire256", "cube"])
+def test_c64_only_context_builds_the_same_tables(torch_cuda, which):
+    """A complex64-only context builds its BF16 projector planes from FP64 rows
+    64 atoms at a time (the FP64 table never exists whole); its complex64 H psi
+    equals that of a context that built the whole FP64 table first, bit for bit
+    (wire256: four chunks; the cube: a partial last chunk)."""
+    import paper_1907_06821_amd as pw
+    if which == "wire256":
+        prob = synth.config(2)
+    else:
+        prob = max(synth.batched_problems(8, seed=2), key=lambda p: p.natom)
+        assert 64 < prob.natom < 128
+    nb = 16
+    full = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    only = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C64)
+    c = to_dev(synth.start_vectors(3, nb, full.npw), "complex64")
+    a = pw.hpsi(full, c, shift=prob.e_ref).cpu().numpy()
+    b = pw.hpsi(only, c, shift=prob.e_ref).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert only.info()["device_bytes"] < full.info()["device_bytes"]
