@@ -200,3 +200,25 @@ class Operator:
             d = self.dproj[a0 * self.nl:(a0 + len(atoms)) * self.nl]
             out += ((block @ beta.conj().T) * d[None, :]) @ beta
         return out
+
+
+def matrix_elements(op, rows, cols, vt=None):
+    """H_{G G'} for G in rows and G' in cols (index arrays into op.miller): the
+    definition in the module docstring evaluated only there.  The projector rows
+    are built at the needed plane waves alone, so this stays cheap for cells whose
+    full projector table is never stored.  vt: optional precomputed
+    potential_fourier(op.vgrid)."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    grid = np.asarray(op.grid)
+    if vt is None:
+        vt = potential_fourier(op.vgrid)
+    m = np.asarray(op.miller)
+    d = (m[rows][:, None, :] - m[cols][None, :, :]) % grid[None, None, :]
+    h = vt[d[..., 0], d[..., 1], d[..., 2]].astype(np.complex128)
+    h += (rows[:, None] == cols[None, :]) * np.asarray(op.kin)[rows][:, None]
+    if op.nl and op.pos is not None and len(op.pos):
+        br = projectors(m[rows], op.cell, op.pos, op.sigma, op.nl, op.kpt)     # [nproj, |rows|]
+        bc = projectors(m[cols], op.cell, op.pos, op.sigma, op.nl, op.kpt)     # [nproj, |cols|]
+        h += (br.T * op.dproj[None, :]) @ bc.conj()
+    return h

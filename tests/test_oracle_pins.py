@@ -250,3 +250,17 @@ def test_lazy_projectors_equal_stored_table():
     a = full.apply(x, shift=0.3)
     b = lazy.apply(x, shift=0.3, atom_chunk=2)
     assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_matrix_elements_equal_dense_entries():
+    """H restricted to chosen rows and columns equals the same entries of the
+    dense matrix (local-only cell, and a k-point cell with projectors)."""
+    from oracle.hamiltonian import matrix_elements
+    rng = np.random.default_rng(11)
+    for prob in (synth.config(1), synth.small_nonlocal_problem(kpt=(0.11, -0.23, 0.07))):
+        op = oh.Operator.from_problem(prob)
+        h = op.dense()
+        rows = rng.choice(op.npw, size=17, replace=False)
+        cols = rng.choice(op.npw, size=5, replace=False)
+        cols[0] = rows[3]                        # one diagonal entry
+        assert np.max(np.abs(matrix_elements(op, rows, cols) - h[np.ix_(rows, cols)])) < 1e-13
