@@ -39,6 +39,7 @@ struct XYArgs {
     int n0, n1, n2, ncols;
     int rowlo, nrows;         // x rows that hold columns: (rowlo + r) mod n0, r < nrows
     const int32_t *colpos;    // [ncols]: i0 * (n1 + 1) + i1 (padded plane index)
+    const int32_t *colslot;   // [ncols]: ((i0 - rowlo) mod n0) * (n1 + 1) + i1 (touched-rows plane)
     const void *tw0, *tw1;
     const void *vz;           // [n2][n0][n1] potential, z-major (or null)
 };
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // xy pass with four lanes per transform (MODE 0, n0 == n1 == L = 4 M, M in
-// {4, 8, 12, 16}).  A length-L DFT splits as L = 4 x M:
+// {4, 8, 12, 16, 24, 32}).  A length-L DFT splits as L = 4 x M:
 //   quad_a: lane q holds x[q + 4 m] (m < M): M-point DFT over m in registers,
 //           twiddle exp(s 2 pi i q k / L), 4-point DFT across the quad (DPP
 //           exchanges, decimation in frequency); lane q then holds
@@ -224,7 +225,11 @@ __global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ 
 // quad_a's output layout is quad_b's input layout, so the x transforms run
 // inverse -> V(r) -> forward in registers.  Per plane: zero the touched rows,
 // scatter the columns, y inverse on the touched rows, x inverse . V . x forward
-// per y, y forward on the touched rows, gather: five barriers in all.
+// per y, y forward on the touched rows, gather: five barriers in all.  LDS holds
+// only the nrows x rows the sphere touches (slot r is row rowlo + r mod L): the
+// x transforms read the other rows as zeros and keep only the touched rows of
+// their output, which is all the y forward transforms and the gather use.  So a
+// 128-point complex128 plane of the 4000-atom wire (71 touched rows) fits LDS.
 // ---------------------------------------------------------------------------
 template <int N> struct CosTab;
 template <> struct CosTab<12> {
@@ -237,6 +242,25 @@ template <> struct CosTab<16> {
                                      -1.0, -0.92387953251128675613, -0.70710678118654752440,
                                      -0.38268343236508977173, 0.0, 0.38268343236508977173, 0.70710678118654752440,
                                      0.92387953251128675613};
+};
+
+template <> struct CosTab<24> {
+    static constexpr double c[24] = {
+        1.0, 0.96592582628906828675, 0.86602540378443864676, 0.70710678118654752440, 0.5,
+        0.25881904510252076235, 0.0, -0.25881904510252076235, -0.5, -0.70710678118654752440,
+        -0.86602540378443864676, -0.96592582628906828675, -1.0, -0.96592582628906828675,
+        -0.86602540378443864676, -0.70710678118654752440, -0.5, -0.25881904510252076235, 0.0,
+        0.25881904510252076235, 0.5, 0.70710678118654752440, 0.86602540378443864676, 0.96592582628906828675};
+};
+template <> struct CosTab<32> {
+    static constexpr double c[32] = {
+        1.0, 0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708, 0.70710678118654752440,
+        0.55557023301960222474, 0.38268343236508977173, 0.19509032201612826785, 0.0, -0.19509032201612826785,
+        -0.38268343236508977173, -0.55557023301960222474, -0.70710678118654752440, -0.83146961230254523708,
+        -0.92387953251128675613, -0.98078528040323044913, -1.0, -0.98078528040323044913, -0.92387953251128675613,
+        -0.83146961230254523708, -0.70710678118654752440, -0.55557023301960222474, -0.38268343236508977173,
+        -0.19509032201612826785, 0.0, 0.19509032201612826785, 0.38268343236508977173, 0.55557023301960222474,
+        0.70710678118654752440, 0.83146961230254523708, 0.92387953251128675613, 0.98078528040323044913};
 };
 
 // exp(S 2 pi i t / N)
@@ -272,9 +296,11 @@ template <typename T, int M, int S> __device__ inline void reg_dft(cplx<T> *v) {
     if constexpr (M == 4) Dft<T, 4>::run(v, S);
     else if constexpr (M == 8) Dft<T, 8>::run(v, S);
     else if constexpr (M == 12) dft_pq<T, 3, 4, S>(v);
+    else if constexpr (M == 16) dft_pq<T, 4, 4, S>(v);
+    else if constexpr (M == 24) dft_pq<T, 3, 8, S>(v);
     else {
-        static_assert(M == 16, "register DFT length");
-        dft_pq<T, 4, 4, S>(v);
+        static_assert(M == 32, "register DFT length");
+        dft_pq<T, 4, 8, S>(v);
     }
 }
 
@@ -339,7 +365,7 @@ __global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ 
     constexpr int L = 4 * M, RS = L + 1, NQ = NTHR / 4;
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);   // [L]
-    cplx<T> *pl = tw + L;                                   // [L][RS]
+    cplx<T> *pl = tw + L;                                   // [nrows][RS], touched x rows only
     const int z = blockIdx.x, b = blockIdx.y;
     const int tid = threadIdx.x, q = tid & 3, quad = tid >> 2;
     const int rq = ((q & 1) << 1) | (q >> 1);
@@ -355,24 +381,17 @@ __global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ 
         if (c < a.ncols) cv[j] = crow[c];
     }
     load_tw<T>(tw, reinterpret_cast<const cplx<T> *>(a.tw0), L);
-    for (int i = tid; i < nrows * RS; i += NTHR) {
-        const int r = i / RS;
-        int row = rowlo + r;
-        if (row >= L) row -= L;
-        pl[row * RS + (i - r * RS)] = cmake<T>(0, 0);
-    }
+    for (int i = tid; i < nrows * RS; i += NTHR) pl[i] = cmake<T>(0, 0);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CPF; ++j) {
         const int c = tid + j * NTHR;
-        if (c < a.ncols) pl[a.colpos[c]] = cv[j];
+        if (c < a.ncols) pl[a.colslot[c]] = cv[j];
     }
-    for (int c = tid + CPF * NTHR; c < a.ncols; c += NTHR) pl[a.colpos[c]] = crow[c];
+    for (int c = tid + CPF * NTHR; c < a.ncols; c += NTHR) pl[a.colslot[c]] = crow[c];
     __syncthreads();
     for (int f = quad; f < nrows; f += NQ) {                 // y inverse, touched rows
-        int row = rowlo + f;
-        if (row >= L) row -= L;
-        cplx<T> *p = pl + row * RS;
+        cplx<T> *p = pl + f * RS;
         cplx<T> v[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) v[m] = p[q + 4 * m];
@@ -394,23 +413,24 @@ __global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ 
         cplx<T> v[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const int x = q + 4 * m;
-            int dx = x - rowlo;
+            int dx = q + 4 * m - rowlo;
             if (dx < 0) dx += L;
-            v[m] = dx < nrows ? pl[x * RS + y] : cmake<T>(0, 0);
+            v[m] = dx < nrows ? pl[dx * RS + y] : cmake<T>(0, 0);
         }
         quad_a<T, M, 1>(v, tw, q);
 #pragma unroll
         for (int k = 0; k < M; ++k) v[k] = cscale<T>(v[k], VPF ? vv[k] : vz[(k + M * rq) * L + y]);
         quad_b<T, M, -1>(v, tw, q);
 #pragma unroll
-        for (int k = 0; k < M; ++k) pl[(q + 4 * k) * RS + y] = v[k];
+        for (int k = 0; k < M; ++k) {
+            int dx = q + 4 * k - rowlo;
+            if (dx < 0) dx += L;
+            if (dx < nrows) pl[dx * RS + y] = v[k];
+        }
     }
     __syncthreads();
     for (int f = quad; f < nrows; f += NQ) {                 // y forward, touched rows
-        int row = rowlo + f;
-        if (row >= L) row -= L;
-        cplx<T> *p = pl + row * RS;
+        cplx<T> *p = pl + f * RS;
         cplx<T> v[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) v[k] = p[k + M * rq];
@@ -419,7 +439,7 @@ __global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ 
         for (int k = 0; k < M; ++k) p[q + 4 * k] = v[k];
     }
     __syncthreads();
-    for (int c = tid; c < a.ncols; c += NTHR) crow[c] = pl[a.colpos[c]];
+    for (int c = tid; c < a.ncols; c += NTHR) crow[c] = pl[a.colslot[c]];
 }
 
 // ---------------------------------------------------------------------------
@@ -457,6 +477,7 @@ static XYArgs xyargs(pw_ctx *ctx) {
     a.rowlo = ((ctx->basis.n0min % a.n0) + a.n0) % a.n0;
     a.nrows = ctx->basis.n0max - ctx->basis.n0min + 1;
     a.colpos = ctx->d_colpos.as<int32_t>();
+    a.colslot = ctx->d_colslot.as<int32_t>();
     a.tw0 = sizeof(T) == 8 ? ctx->d_tw64[0].p : ctx->d_tw32[0].p;
     a.tw1 = sizeof(T) == 8 ? ctx->d_tw64[1].p : ctx->d_tw32[1].p;
     a.vz = sizeof(T) == 8 ? ctx->d_vz64.p : ctx->d_vz32.p;
@@ -581,13 +602,17 @@ void launch_zfwd(pw_ctx *ctx, int nb, const void *cols, const void *psi, int64_t
 }
 
 static bool xy_has_quad(int n0, int n1) {
-    return n0 == n1 && (n0 == 16 || n0 == 32 || n0 == 48 || n0 == 64);
+    return n0 == n1 && (n0 == 16 || n0 == 32 || n0 == 48 || n0 == 64 || n0 == 96 || n0 == 128);
+}
+
+// LDS of the four-lane kernel: twiddles and the touched rows of one plane
+template <typename T> static size_t quad_lds(const XYArgs &a) {
+    return sizeof(cplx<T>) * ((size_t)a.n0 + (size_t)a.nrows * (a.n1 + 1));
 }
 
 template <typename T, int M, int NTHR>
 static void quad_go(const XYArgs &a, int nb, hipStream_t s, void *cols) {
-    constexpr int L = 4 * M;
-    const size_t lds = sizeof(cplx<T>) * ((size_t)L + (size_t)L * (L + 1));
+    const size_t lds = quad_lds<T>(a);
     allow_lds(xy_quad<T, M, NTHR>, lds);
     hipLaunchKernelGGL((xy_quad<T, M, NTHR>), dim3(a.n2, nb), dim3(NTHR), lds, s, a,
                        reinterpret_cast<cplx<T> *>(cols));
@@ -599,6 +624,8 @@ template <typename T, int NTHR> static void quad_len(const XYArgs &a, int nb, hi
         case 32: quad_go<T, 8, NTHR>(a, nb, s, cols); break;
         case 48: quad_go<T, 12, NTHR>(a, nb, s, cols); break;
         case 64: quad_go<T, 16, NTHR>(a, nb, s, cols); break;
+        case 96: quad_go<T, 24, NTHR>(a, nb, s, cols); break;
+        case 128: quad_go<T, 32, NTHR>(a, nb, s, cols); break;
         default: PW_CHECK(false, PW_EUNSUPPORTED, "no four-lane xy kernel for %d x %d", a.n0, a.n1);
     }
 }
@@ -613,22 +640,23 @@ static void xy_go(const XYArgs &a, int nb, size_t lds, hipStream_t s, void *cols
 template <typename T, int MODE>
 void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
     XYArgs a = xyargs<T>(ctx);
-    const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
-    PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
     const FftChoice &c = choice_of<T>(ctx, 1);
-    // default for the V(r) pass on 16/32/48/64-point planes: the four-lane kernel
-    if (MODE == 0 && (c.kind == 3 || (c.kind == 0 && xy_has_quad(a.n0, a.n1)))) {
+    // default for the V(r) pass on 16/32/48/64/96/128-point planes: the four-lane kernel
+    if (MODE == 0 && (c.kind == 3 || (c.kind == 0 && xy_has_quad(a.n0, a.n1) && quad_lds<T>(a) <= 160 * 1024))) {
         PW_CHECK(xy_has_quad(a.n0, a.n1), PW_EUNSUPPORTED, "no four-lane xy kernel for %d x %d", a.n0, a.n1);
-        const int nthr = c.kind == 3 ? c.nthr : (sizeof(T) == 8 ? 256 : 192);
+        const int nthr = c.kind == 3 ? c.nthr : (sizeof(T) == 8 || a.n0 > 64 ? 256 : 192);
         switch (nthr) {
             case 128: quad_len<T, 128>(a, nb, s, cols); break;
             case 192: quad_len<T, 192>(a, nb, s, cols); break;
             case 256: quad_len<T, 256>(a, nb, s, cols); break;
+            case 512: quad_len<T, 512>(a, nb, s, cols); break;
             default: PW_CHECK(false, PW_EUNSUPPORTED, "four-lane xy kernel with %d threads", nthr);
         }
         PW_LAUNCH_CHECK();
         return;
     }
+    const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
+    PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
     if (c.kind != 2 && a.n0 == a.n1) {
 #define PW_XYCASE(L)                                                                        \
     case L: {                                                                               \
@@ -698,7 +726,9 @@ template <typename T> static bool choice_from(pw_ctx *ctx, const pw_fft_cand &r,
     if (r.kind == 1) return r.pass == 1 ? (n0 == n1 && xy_has_ct<T>(n0)) : z_has_ct(n2);
     if (r.kind == 3) {
         c.nthr = r.nthr;
-        return r.pass == 1 && xy_has_quad(n0, n1) && (c.nthr == 128 || c.nthr == 192 || c.nthr == 256);
+        // (512 threads would spill the complex128 96- and 128-point kernels: not offered)
+        return r.pass == 1 && xy_has_quad(n0, n1) && quad_lds<T>(xyargs<T>(ctx)) <= 160 * 1024 &&
+               (c.nthr == 128 || c.nthr == 192 || c.nthr == 256 || (c.nthr == 512 && (sizeof(T) == 4 || n0 <= 64)));
     }
     if (r.kind != 2 || r.sched < 0 || r.sched > 2) return false;
     c.nthr = r.nthr;
@@ -719,7 +749,7 @@ template <typename T> static std::vector<pw_fft_cand> candidates(pw_ctx *ctx, in
     FftChoice c;
     r.kind = 1;
     if (choice_from<T>(ctx, r, c)) out.push_back(r);
-    for (int t : {128, 192, 256}) {
+    for (int t : {128, 192, 256, 512}) {
         r = pw_fft_cand{};
         r.pass = pass;
         r.kind = 3;
@@ -776,6 +806,7 @@ std::map<TuneKey, TuneVal> g_tune_cache;
 template <typename T>
 void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs, hipStream_t s) {
     PW_CHECK(nb >= 1 && nb <= ctx->max_bands && reps >= 1, PW_EINVAL, "bad autotune sizes");
+    PW_CHECK(nb <= ctx->cols_bands, PW_EINVAL, "autotune on %d bands: the column grid holds %d", nb, ctx->cols_bands);
     FftTune &tune = ctx->tune[sizeof(T) == 8 ? 0 : 1];
     const TuneKey key{{ctx->cell.n[0], ctx->cell.n[1], ctx->cell.n[2]}, ctx->basis.ncols, ctx->basis.npw,
                       sizeof(T) == 8, nb};
