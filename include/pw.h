@@ -92,6 +92,10 @@ typedef struct {
 /* Context flags: which precisions to prepare tables for. */
 #define PW_PREP_C128 1    /* complex128 projector table [nproj][npw] */
 #define PW_PREP_C64  2    /* BF16 projector table and complex64 potential */
+#define PW_PREP_C128_OTF 4 /* complex128 H psi without a stored table: each H psi generates the
+                              complex128 projector rows from their closed form a chunk of atoms at a
+                              time (a few GB of scratch) and applies them chunk by chunk; for cells
+                              whose table (16 nproj npw bytes) does not fit.  Implies PW_PREP_C128. */
 
 typedef struct {
     int32_t npw;          /* plane waves in the sphere */
@@ -101,6 +105,7 @@ typedef struct {
     int32_t grid[3];
     int32_t max_bands;
     int64_t device_bytes; /* workspace + tables owned by the context */
+    int32_t cols_bands;   /* bands per FFT launch (the column grid holds that many; H psi loops) */
 } pw_ctx_info;
 
 /* Number of plane waves in the sphere (host only, no GPU). */
@@ -118,6 +123,12 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
                         int32_t flags, void *stream, pw_ctx **out);
 pw_status pw_ctx_destroy(pw_ctx *ctx);
 pw_status pw_ctx_get_info(const pw_ctx *ctx, pw_ctx_info *info);
+
+/* Atoms per chunk of a PW_PREP_C128_OTF context (default: as many as fit 4 GB of
+ * complex128 rows).  Reallocates the chunk buffer (allocates; synchronises).
+ * Results do not depend on it beyond the order in which chunks are summed.
+ * PW_EUNSUPPORTED for a context with a stored table. */
+pw_status pw_ctx_set_otf_atoms(pw_ctx *ctx, int32_t atoms);
 
 /* Host copies of per-plane-wave tables: kinetic energy (1/2)|G+k|^2 (float64
  * [npw]) and shell index (int32 [npw], shells ascending in energy). */
@@ -235,6 +246,10 @@ typedef struct {
     int32_t n_hist;       /* in: capacity of hist; out: entries written */
     double *hist;         /* host, optional: [n_hist][2] = (iteration, max Delta) */
     int32_t n_snap;       /* out: snapshots written to snap_buf */
+    double ms[4];         /* out: GPU time (HIP events on the stream) of the set-up (first orthonormalisation,
+                             two H psi, Rayleigh-Ritz), the CG iterations, the checks (residuals and
+                             Rayleigh-Ritz every check_every iterations) and the final Rayleigh-Ritz in H;
+                             zeros from pw_batch_solve */
 } pw_cg_stats;
 
 void pw_cg_opts_default(pw_cg_opts *opts);
@@ -407,7 +422,7 @@ pw_status pw_mlp_forward(int32_t nshell, int32_t nb, const double *shell_t, cons
  * (> 0, Ha) and the band kinetic energies (written to tband [nb]), and writes
  * tabs [3][nshell][nb]: per shell s
  * and band i, the sums over the shell of Re(conj(e) K0 g), |K0 g|^2 and |e|^2 with
- * e = -(I - X* X*^H) x.  weight_delta >= 0 multiplies the sums of shell s by
+ * e = (I - X* X*^H) x.  weight_delta >= 0 multiplies the sums of shell s by
  * (T_s - e_ref)^2 + weight_delta^2 (an approximate A-norm for the cosine loss);
  * weight_delta < 0 leaves them unweighted. */
 pw_status pw_mlp_harvest(pw_ctx *ctx, double e_ref, int32_t nb, const void *x_snap, const void *x_conv, int64_t ld,
@@ -440,7 +455,14 @@ pw_status pw_mlp_train(int32_t nshell, int32_t nb, int32_t nsnap, const double *
  * (allocation happens here, not in the timed calls); pw_profile_end waits for
  * the recorded events and returns, per stage kind, the summed milliseconds and
  * the launch count.  Kinds: 0 z pass inverse, 1 xy pass (2D FFTs and V),
- * 2 z pass forward + kinetic, 3 projection <beta|psi>, 4 back-projection. */
+ * 2 z pass forward + kinetic, 3 projection <beta|psi>, 4 back-projection
+ * (for generated rows: per chunk, the row generation counted with neither), and
+ * the folded-CG solver's FP64 block products: 5 the rotation of X, Y and AX by
+ * one nb x nb matrix (three products of 8 npw nb^2 flops in one launch), 6 the nb x nb
+ * Gram-type products A^H B (8 npw nb^2 flops), 7 the other single rotations
+ * nb x nb times nb x npw (8 npw nb^2 flops; the P update, the Ritz rotations).
+ * Inside pw_folded_cg_solve only the CG iterations are recorded, not the set-up,
+ * the checks or the final Rayleigh-Ritz. */
 #define PW_PROF_NKINDS 8
 pw_status pw_profile_begin(pw_ctx *ctx, int32_t max_records);
 pw_status pw_profile_end(pw_ctx *ctx, double *ms, int64_t *launches);

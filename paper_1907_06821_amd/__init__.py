@@ -18,7 +18,7 @@ LIBPATH = _HERE / "libpw.so"
 
 PW_OK, PW_EINVAL, PW_ENOMEM, PW_EHIP, PW_ENOTPD, PW_ENOCONV, PW_ENAN, PW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 PW_C128, PW_C64 = 0, 1
-PW_PREP_C128, PW_PREP_C64 = 1, 2
+PW_PREP_C128, PW_PREP_C64, PW_PREP_C128_OTF = 1, 2, 4
 
 _STATUS_NAMES = {0: "PW_OK", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EHIP", -4: "PW_ENOTPD",
                  -5: "PW_ENOCONV", -6: "PW_ENAN", -7: "PW_EUNSUPPORTED"}
@@ -31,8 +31,9 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
            "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose",
            "pw_lin_opts_default", "pw_folded_linear_solve", "pw_cheb_filter", "pw_chebfd_step",
-           "pw_spectral_bounds", "pw_kinterp")
-PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection")
+           "pw_spectral_bounds", "pw_kinterp", "pw_ctx_set_otf_atoms")
+PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection", "block_rotate3",
+              "block_gram", "block_rotate")
 PW_PROF_NKINDS = 8
 
 
@@ -53,7 +54,8 @@ class pw_potential(C.Structure):
 
 class pw_ctx_info(C.Structure):
     _fields_ = [("npw", C.c_int32), ("ncols", C.c_int32), ("nshell", C.c_int32), ("nproj", C.c_int32),
-                ("grid", C.c_int32 * 3), ("max_bands", C.c_int32), ("device_bytes", C.c_int64)]
+                ("grid", C.c_int32 * 3), ("max_bands", C.c_int32), ("device_bytes", C.c_int64),
+                ("cols_bands", C.c_int32)]
 
 
 class pw_cg_opts(C.Structure):
@@ -82,7 +84,7 @@ class pw_fft_cand(C.Structure):
 class pw_cg_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_hpsi", C.c_int64), ("max_resid", C.c_double),
                 ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double)),
-                ("n_snap", C.c_int32)]
+                ("n_snap", C.c_int32), ("ms", C.c_double * 4)]
 
 
 _lib = None
@@ -103,6 +105,7 @@ def lib():
             "pw_ctx_create": [C.POINTER(pw_cell), C.POINTER(pw_potential), i32, i32, vp, C.POINTER(vp)],
             "pw_ctx_destroy": [vp],
             "pw_ctx_get_info": [vp, C.POINTER(pw_ctx_info)],
+            "pw_ctx_set_otf_atoms": [vp, i32],
             "pw_ctx_kinetic": [vp, C.POINTER(dbl)],
             "pw_ctx_shells": [vp, C.POINTER(i32), C.POINTER(dbl)],
             "pw_hpsi": [vp, i32, i32, vp, i64, vp, i64, dbl, vp],
@@ -204,7 +207,8 @@ class Context:
 
     vgrid: float64 [N0, N1, N2] local potential samples (numpy or torch).
     pos, dproj: atom centres [natom, 3] (bohr) and KB strengths [natom * nl] (Ha).
-    flags: PW_PREP_C128 and/or PW_PREP_C64."""
+    flags: PW_PREP_C128 and/or PW_PREP_C64, or PW_PREP_C128_OTF (complex128 without a stored
+    projector table: rows generated per H psi)."""
 
     def __init__(self, grid, cell, ecut, vgrid, pos=None, nl=0, sigma=0.8, dproj=None, kpt=(0.0, 0.0, 0.0),
                  max_bands=128, flags=PW_PREP_C128, stream=None):
@@ -231,6 +235,7 @@ class Context:
         info = pw_ctx_info()
         _check(self._lib.pw_ctx_get_info(self.handle, C.byref(info)))
         self.npw, self.ncols, self.nshell, self.nproj = info.npw, info.ncols, info.nshell, info.nproj
+        self.cols_bands = info.cols_bands
         self.grid = tuple(int(x) for x in grid)
         self.max_bands = int(max_bands)
 
@@ -239,6 +244,10 @@ class Context:
         return cls(prob.grid, prob.cell, prob.ecut, prob.vgrid() if vgrid is None else vgrid,
                    pos=prob.pos, nl=prob.nl, sigma=prob.sigma, dproj=prob.dproj, kpt=prob.kpt,
                    max_bands=max_bands or prob.nbands, flags=flags)
+
+    def set_otf_atoms(self, atoms):
+        """Atoms per chunk of the generated projector rows (PW_PREP_C128_OTF contexts)."""
+        _check(self._lib.pw_ctx_set_otf_atoms(self.handle, int(atoms)))
 
     def info(self):
         info = pw_ctx_info()
@@ -486,7 +495,8 @@ def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_o
                                          res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o), C.byref(st),
                                          _stream_ptr(stream))
     stats = dict(iters=st.iters, converged=bool(st.converged), n_hpsi=st.n_hpsi, max_resid=st.max_resid,
-                 seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status, n_snap=st.n_snap)
+                 seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status, n_snap=st.n_snap,
+                 ms_setup=st.ms[0], ms_iters=st.ms[1], ms_checks=st.ms[2], ms_final=st.ms[3])
     if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
         _check(status)
     return eig, res, stats

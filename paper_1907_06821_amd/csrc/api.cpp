@@ -56,28 +56,70 @@ static void twiddles(int n, std::vector<double> &t64, std::vector<float> &t32) {
 size_t hpsi_partial_bytes(const pw_ctx *ctx) {
     size_t b = 0;
     const int npw = ctx->basis.npw;
+    const bool c128 = ctx->flags & PW_PREP_C128, c64 = ctx->flags & PW_PREP_C64;
     for (int n = 1; n <= ctx->max_bands; ++n) {
-        if (ctx->nproj) {
+        if (ctx->nproj && c128) {
             b = std::max(b, nt_partial_bytes(ctx->nproj, n, npw));
-            b = std::max(b, cnt_partial_bytes(ctx->nproj, n, npw));
+            if (ctx->beta_otf) {
+                // the chunk of rows and the last, shorter one
+                b = std::max(b, nt_partial_bytes(ctx->otf_atoms * ctx->nl, n, npw));
+                const int tail = ctx->natom % ctx->otf_atoms;
+                if (tail) b = std::max(b, nt_partial_bytes(tail * ctx->nl, n, npw));
+            }
         }
-        b = std::max(b, nt_partial_bytes(n, n, npw));
+        if (ctx->nproj && c64) b = std::max(b, cnt_partial_bytes(ctx->nproj, n, npw));
+        if (c128) b = std::max(b, nt_partial_bytes(n, n, npw));
     }
     return b;
+}
+
+// The local and kinetic part of (H - shift) psi: the three FFT passes, cols_bands bands per launch
+template <typename T>
+static void hpsi_local(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
+                       hipStream_t st) {
+    const double scale = 1.0 / ((double)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2]);
+    const size_t es = 2 * sizeof(T);
+    for (int b0 = 0; b0 < nb; b0 += ctx->cols_bands) {
+        const int n = std::min(ctx->cols_bands, nb - b0);
+        const char *pi = (const char *)psi + (size_t)b0 * ld * es;
+        char *po = (char *)out + (size_t)b0 * ldo * es;
+        { ProfScope p(ctx, 0, st); launch_zinv<T>(ctx, n, pi, ld, ctx->d_cols.p, st); }
+        { ProfScope p(ctx, 1, st); launch_xy<T, 0>(ctx, n, ctx->d_cols.p, nullptr, st); }
+        {
+            ProfScope p(ctx, 2, st);
+            launch_zfwd<T>(ctx, n, ctx->d_cols.p, pi, ld, ctx->d_kin.as<double>(), shift, scale, po, ldo, st);
+        }
+    }
+}
+
+// Nonlocal term with projector rows generated per call: for each chunk of otf_atoms
+// atoms, the rows beta_p(G) of its projectors are written to the chunk buffer, then
+// projT[b][p] = D_p <beta_p|psi_b> and out += projT . beta over that chunk's rows.
+static void nonlocal_otf(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, hipStream_t st) {
+    const int npw = ctx->basis.npw, nl = ctx->nl;
+    double2 *proj = ctx->d_proj.as<double2>();
+    for (int a0 = 0; a0 < ctx->natom; a0 += ctx->otf_atoms) {
+        const int na = std::min(ctx->otf_atoms, ctx->natom - a0), p0 = a0 * nl, rows = na * nl;
+        build_projectors(npw, na, nl, ctx->d_miller.as<int32_t>(), ctx->cell, ctx->d_pos.as<double>() + 3 * a0,
+                         ctx->sigma, ctx->d_beta_chunk.p, st);
+        {
+            ProfScope p(ctx, 3, st);
+            zgemm_nt(rows, nb, npw, true, ctx->d_beta_chunk.p, npw, psi, ld, 1.0, ctx->d_dproj.as<double>() + p0, 0.0,
+                     proj + p0, ctx->nproj, true, ctx->d_partial.p, st, true);
+        }
+        ProfScope p(ctx, 4, st);
+        zgemm_nn_launch(nb, npw, rows, proj + p0, ctx->nproj, ctx->d_beta_chunk.p, npw, 1.0, 1.0, out, ldo, st, true);
+    }
 }
 
 // (H - shift) psi for one chunk of at most max_bands bands, complex128
 static void hpsi_c128(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
                       hipStream_t st) {
     const int npw = ctx->basis.npw;
-    const double scale = 1.0 / ((double)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2]);
-    { ProfScope p(ctx, 0, st); launch_zinv<double>(ctx, nb, psi, ld, ctx->d_cols.p, st); }
-    { ProfScope p(ctx, 1, st); launch_xy<double, 0>(ctx, nb, ctx->d_cols.p, nullptr, st); }
-    {
-        ProfScope p(ctx, 2, st);
-        launch_zfwd<double>(ctx, nb, ctx->d_cols.p, psi, ld, ctx->d_kin.as<double>(), shift, scale, out, ldo, st);
-    }
-    if (ctx->nproj) {
+    hpsi_local<double>(ctx, nb, psi, ld, out, ldo, shift, st);
+    if (ctx->nproj && ctx->beta_otf) {
+        nonlocal_otf(ctx, nb, psi, ld, out, ldo, st);
+    } else if (ctx->nproj) {
         // projT[b][p] = D_p <beta_p | psi_b>, then out += projT . beta
         {
             ProfScope p(ctx, 3, st);
@@ -93,13 +135,7 @@ static void hpsi_c128(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *ou
 static void hpsi_c64(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out, int64_t ldo, double shift,
                      hipStream_t st) {
     const int npw = ctx->basis.npw;
-    const double scale = 1.0 / ((double)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2]);
-    { ProfScope p(ctx, 0, st); launch_zinv<float>(ctx, nb, psi, ld, ctx->d_cols.p, st); }
-    { ProfScope p(ctx, 1, st); launch_xy<float, 0>(ctx, nb, ctx->d_cols.p, nullptr, st); }
-    {
-        ProfScope p(ctx, 2, st);
-        launch_zfwd<float>(ctx, nb, ctx->d_cols.p, psi, ld, ctx->d_kin.as<double>(), shift, scale, out, ldo, st);
-    }
+    hpsi_local<float>(ctx, nb, psi, ld, out, ldo, shift, st);
     if (ctx->nproj) {
         {
             ProfScope p(ctx, 3, st);
@@ -180,7 +216,11 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
     PW_CHECK(pot->v_r, PW_EINVAL, "v_r is null");
     PW_CHECK(pot->natom >= 0 && (pot->natom == 0 || (pot->pos && pot->d)), PW_EINVAL, "bad atom arrays");
     PW_CHECK(pot->nl == 0 || pot->nl == 1 || pot->nl == 4, PW_EINVAL, "nl must be 0, 1 or 4");
+    PW_CHECK(!(flags & ~(PW_PREP_C128 | PW_PREP_C64 | PW_PREP_C128_OTF)), PW_EINVAL, "unknown context flags %d",
+             flags);
+    if (flags & PW_PREP_C128_OTF) flags |= PW_PREP_C128;
     if (!(flags & (PW_PREP_C128 | PW_PREP_C64))) flags |= PW_PREP_C128;
+    PW_CHECK(pot->natom == 0 || pot->nl == 0 || std::isfinite(pot->sigma), PW_ENAN, "non-finite projector width");
     *out = nullptr;
     std::unique_ptr<pw_ctx> c(new pw_ctx());
     hipStream_t st = (hipStream_t)stream;
@@ -198,9 +238,11 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
     int64_t acct = 0;
     upload(c->d_kin, b.kin, acct);
     upload(c->d_colstart, b.col_start, acct);
-    std::vector<int32_t> zmap(b.npw), colpos(b.ncols);
+    std::vector<int32_t> zmap(b.npw), colpos(b.ncols), colslot(b.ncols);
+    const int rowlo = ((b.n0min % n0) + n0) % n0;
     for (int col = 0; col < b.ncols; ++col) {
         colpos[col] = b.col_i0[col] * (n1 + 1) + b.col_i1[col];
+        colslot[col] = ((b.col_i0[col] - rowlo + n0) % n0) * (n1 + 1) + b.col_i1[col];
         for (int g = b.col_start[col]; g < b.col_start[col + 1]; ++g) {
             const int n2v = b.miller[3 * g + 2];
             zmap[g] = (col % c->cb) * (n2 + 1) + ((n2v % n2) + n2) % n2;
@@ -208,6 +250,7 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
     }
     upload(c->d_zmap, zmap, acct);
     upload(c->d_colpos, colpos, acct);
+    upload(c->d_colslot, colslot, acct);
     upload(c->d_shell, b.shell, acct);
     upload(c->d_shell_t, b.shell_t, acct);
     {
@@ -228,8 +271,14 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
         upload(c->d_tw64[a], t64, acct);
         upload(c->d_tw32[a], t32, acct);
     }
+    // V(r) is checked for NaN/Inf on the host (one copy), then kept z-major per prepared precision
     const int64_t ngrid = (int64_t)n0 * n1 * n2;
-    c->d_vz64.alloc(ngrid * 8);
+    {
+        std::vector<double> hv(ngrid);
+        PW_HIP(hipMemcpy(hv.data(), pot->v_r, ngrid * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : hv) PW_CHECK(std::isfinite(v), PW_ENAN, "non-finite local potential sample");
+    }
+    if (flags & PW_PREP_C128) c->d_vz64.alloc(ngrid * 8);
     if (flags & PW_PREP_C64) c->d_vz32.alloc(ngrid * 4);
     acct += c->d_vz64.bytes + c->d_vz32.bytes;
     build_vz(n0, n1, n2, pot->v_r, c->d_vz64.as<double>(), c->d_vz32.as<float>(), st);
@@ -245,7 +294,19 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
         upload(d_mil, mil, tmp);
         std::vector<double> pos(pot->pos, pot->pos + 3 * c->natom);
         upload(d_pos, pos, tmp);
-        const bool c128 = flags & PW_PREP_C128;
+        c->beta_otf = flags & PW_PREP_C128_OTF;
+        const bool c128 = (flags & PW_PREP_C128) && !c->beta_otf;   // a stored complex128 table
+        if (c->beta_otf) {
+            // rows of otf_atoms atoms per chunk: about kOtfBytes of scratch, at least one atom
+            constexpr size_t kOtfBytes = size_t(4) << 30;
+            const size_t per_atom = (size_t)c->nl * b.npw * 16;
+            c->otf_atoms = (int)std::max<size_t>(1, std::min<size_t>(c->natom, kOtfBytes / per_atom));
+            c->sigma = pot->sigma;
+            c->d_beta_chunk.alloc((size_t)c->otf_atoms * per_atom);
+            upload(c->d_miller, mil, acct);
+            upload(c->d_pos, pos, acct);
+            acct += c->d_beta_chunk.bytes;
+        }
         if (c128) {
             c->d_beta64.alloc((size_t)c->nproj * b.npw * 16);
             build_projectors(b.npw, c->natom, c->nl, d_mil.as<int32_t>(), *cell, d_pos.as<double>(), pot->sigma,
@@ -283,10 +344,19 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
         acct += c->d_beta64.bytes;
         PW_HIP(hipStreamSynchronize(st));   // d_mil, d_pos die here
     }
-    c->d_cols.alloc((size_t)max_bands * n2 * b.ncols * 16);
+    // column grid for cols_bands bands of the widest prepared dtype: all max_bands bands up to
+    // kColsBytes, else the FFT passes run that many bands per launch
+    {
+        constexpr size_t kColsBytes = size_t(4) << 30;
+        const size_t per_band = (size_t)n2 * b.ncols * ((flags & PW_PREP_C128) ? 16 : 8);
+        c->cols_bands = (int)std::max<size_t>(1, std::min<size_t>(max_bands, kColsBytes / per_band));
+        c->d_cols.alloc((size_t)c->cols_bands * per_band);
+    }
     c->d_proj.alloc((size_t)max_bands * std::max(1, c->nproj) * 16);
     c->d_partial.alloc(hpsi_partial_bytes(c.get()));
-    c->d_ortho_ws.alloc((size_t)max_bands * b.npw * 16);
+    // pw_orthonormalize's block scratch: complex128 contexts with a stored table only (a
+    // PW_PREP_C128_OTF context allocates it on its first pw_orthonormalize call)
+    if ((flags & PW_PREP_C128) && !c->beta_otf) c->d_ortho_ws.alloc((size_t)max_bands * b.npw * 16);
     c->d_ortho_small.alloc((size_t)3 * max_bands * max_bands * 16 + 256);
     acct += c->d_cols.bytes + c->d_proj.bytes + c->d_partial.bytes + c->d_ortho_ws.bytes + c->d_ortho_small.bytes;
     c->device_bytes = acct;
@@ -309,10 +379,27 @@ pw_status pw_ctx_destroy(pw_ctx *ctx) {
                       &ctx->d_tw64[0], &ctx->d_tw64[1], &ctx->d_tw64[2], &ctx->d_tw32[0], &ctx->d_tw32[1],
                       &ctx->d_tw32[2], &ctx->d_beta64, &ctx->d_beta_bf16, &ctx->d_betaT_bf16, &ctx->d_bf16_ws, &ctx->d_dproj, &ctx->d_dproj32,
                       &ctx->d_shell, &ctx->d_cols, &ctx->d_proj, &ctx->d_partial, &ctx->d_ortho_ws,
+                      &ctx->d_colslot, &ctx->d_miller, &ctx->d_pos, &ctx->d_beta_chunk,
                       &ctx->d_ortho_small};
     for (DevBuf *d : bufs) d->free_();
     (void)hipSetDevice(cur);
     delete ctx;
+    PW_API_END
+}
+
+pw_status pw_ctx_set_otf_atoms(pw_ctx *ctx, int32_t atoms) {
+    PW_API_BEGIN
+    PW_CHECK(ctx, PW_EINVAL, "null context");
+    PW_CHECK(ctx->beta_otf, PW_EUNSUPPORTED, "context has a stored projector table");
+    PW_CHECK(atoms >= 1, PW_EINVAL, "atoms per chunk must be positive");
+    atoms = std::min(atoms, ctx->natom);
+    PW_HIP(hipDeviceSynchronize());
+    const size_t old = ctx->d_beta_chunk.bytes;
+    ctx->d_beta_chunk.alloc((size_t)atoms * ctx->nl * ctx->basis.npw * 16);
+    ctx->otf_atoms = atoms;
+    ctx->device_bytes += (int64_t)ctx->d_beta_chunk.bytes - (int64_t)old;
+    const size_t need = hpsi_partial_bytes(ctx);
+    if (need > ctx->d_partial.bytes) ctx->d_partial.alloc(need);
     PW_API_END
 }
 
@@ -326,6 +413,7 @@ pw_status pw_ctx_get_info(const pw_ctx *ctx, pw_ctx_info *info) {
     for (int a = 0; a < 3; ++a) info->grid[a] = ctx->cell.n[a];
     info->max_bands = ctx->max_bands;
     info->device_bytes = ctx->device_bytes;
+    info->cols_bands = ctx->cols_bands;
     PW_API_END
 }
 
@@ -374,8 +462,8 @@ pw_status pw_wave_to_grid(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *p
     hipStream_t st = (hipStream_t)stream;
     const size_t es = dtype == PW_C128 ? 16 : 8;
     const size_t ng = (size_t)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2];
-    for (int b0 = 0; b0 < nb; b0 += ctx->max_bands) {
-        const int nbc = std::min(ctx->max_bands, nb - b0);
+    for (int b0 = 0; b0 < nb; b0 += ctx->cols_bands) {
+        const int nbc = std::min(ctx->cols_bands, nb - b0);
         const char *pi = (const char *)psi + (size_t)b0 * ld * es;
         char *go = (char *)grid + (size_t)b0 * ng * es;
         if (dtype == PW_C128) {
@@ -398,8 +486,8 @@ pw_status pw_grid_to_wave(pw_ctx *ctx, pw_dtype dtype, int32_t nb, const void *g
     const size_t es = dtype == PW_C128 ? 16 : 8;
     const size_t ng = (size_t)ctx->cell.n[0] * ctx->cell.n[1] * ctx->cell.n[2];
     const double scale = 1.0 / (double)ng;
-    for (int b0 = 0; b0 < nb; b0 += ctx->max_bands) {
-        const int nbc = std::min(ctx->max_bands, nb - b0);
+    for (int b0 = 0; b0 < nb; b0 += ctx->cols_bands) {
+        const int nbc = std::min(ctx->cols_bands, nb - b0);
         char *po = (char *)psi + (size_t)b0 * ld * es;
         const char *gi = (const char *)grid + (size_t)b0 * ng * es;
         if (dtype == PW_C128) {
@@ -452,11 +540,13 @@ pw_status pw_mlp_set(pw_ctx *ctx, const float *weights) {
     PW_API_BEGIN
     PW_CHECK(ctx && weights, PW_EINVAL, "null argument");
     PW_CHECK(mlp_nparam() == PW_MLP_NPARAM, PW_EINVAL, "parameter count mismatch");
-    if (!ctx->d_mlp.p) ctx->d_mlp.alloc(PW_MLP_NPARAM * sizeof(float));
-    PW_HIP(hipMemcpy(ctx->d_mlp.p, weights, PW_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice));
+    // validate a host copy first: rejected weights never reach the context, which
+    // keeps the network it had (or none)
     std::vector<float> h(PW_MLP_NPARAM);
     PW_HIP(hipMemcpy(h.data(), weights, PW_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
     for (float x : h) PW_CHECK(std::isfinite(x), PW_ENAN, "non-finite network weight");
+    if (!ctx->d_mlp.p) ctx->d_mlp.alloc(PW_MLP_NPARAM * sizeof(float));
+    PW_HIP(hipMemcpy(ctx->d_mlp.p, h.data(), PW_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
     PW_API_END
 }
 
@@ -579,6 +669,7 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
     PW_CHECK(nb <= ctx->max_bands, PW_EINVAL, "nb %d > max_bands %d", nb, ctx->max_bands);
     if (nb == 0) return PW_OK;
     hipStream_t st = (hipStream_t)stream;
+    if (!ctx->d_ortho_ws.p) ctx->d_ortho_ws.alloc((size_t)ctx->max_bands * ctx->basis.npw * 16);
     int *d_status = (int *)((char *)ctx->d_ortho_small.p + (size_t)3 * ctx->max_bands * ctx->max_bands * 16);
     fill_zero(d_status, 16, st);
     orthonormalize_c128(ctx, nb, psi, ld, ctx->d_ortho_ws.p, ctx->d_ortho_small.p, d_status, st);

@@ -173,12 +173,20 @@ struct pw_ctx {
     int cb = 16;                     // z-columns per workgroup in the z passes
     // device tables
     pw::DevBuf d_kin, d_zmap, d_colpos, d_colstart, d_vz64, d_vz32, d_tw64[3], d_tw32[3];
+    pw::DevBuf d_colslot;            // [ncols]: column's place in a plane that holds only the touched x rows
     pw::DevBuf d_beta64, d_beta_bf16, d_dproj, d_dproj32, d_shell;
     pw::DevBuf d_betaT_bf16;         // BF16 planes of the transposed table [ldg][ldp] (back-projection)
+    // complex128 projector rows generated per H psi, otf_atoms atoms at a time, instead of a stored
+    // table (PW_PREP_C128_OTF): Miller triples and atom centres on the device, one chunk of rows
+    bool beta_otf = false;
+    int otf_atoms = 0;
+    double sigma = 0.0;
+    pw::DevBuf d_miller, d_pos, d_beta_chunk;
     pw::DevBuf d_bf16_ws;            // per-call BF16 planes of psi and of D . C
     int64_t ldb16 = 0;               // row length of the BF16 projector planes
     // hpsi workspace
-    pw::DevBuf d_cols;               // [max_bands][N2][ncols] complex128 (reused for c64)
+    pw::DevBuf d_cols;               // [cols_bands][N2][ncols] of the widest prepared dtype
+    int cols_bands = 0;              // bands per FFT launch (the column grid holds that many)
     pw::DevBuf d_proj;               // projections [nproj][max_bands] complex128
     pw::DevBuf d_partial;            // split-K partial sums
     pw::DevBuf d_ortho_ws, d_ortho_small;   // pw_orthonormalize scratch
@@ -187,6 +195,7 @@ struct pw_ctx {
     pw::Solver *solver = nullptr;
     // profiling (pw_profile_begin / pw_profile_end)
     bool prof_on = false;
+    bool prof_pause = false;         // set by the folded-CG solver outside its iterations
     std::vector<hipEvent_t> prof_pool;
     std::vector<pw::ProfRec> prof_rec;
     size_t prof_next = 0;
@@ -199,7 +208,8 @@ struct ProfScope {
     hipStream_t st;
     hipEvent_t b = nullptr;
     ProfScope(pw_ctx *ctx, int kind, hipStream_t s) : c(ctx), st(s) {
-        if (c->prof_on && c->prof_next + 2 <= c->prof_pool.size() && c->prof_rec.size() < c->prof_rec.capacity()) {
+        if (c->prof_on && !c->prof_pause && c->prof_next + 2 <= c->prof_pool.size() &&
+            c->prof_rec.size() < c->prof_rec.capacity()) {
             hipEvent_t a = c->prof_pool[c->prof_next++];
             b = c->prof_pool[c->prof_next++];
             c->prof_rec.push_back(ProfRec{kind, a, b});

@@ -31,7 +31,6 @@ void hpsi_any(pw_ctx *ctx, pw_dtype dt, int nb, const void *psi, int64_t ld, voi
 struct Solver {
     int nbmax = 0, npw = 0;
     DevBuf X, Y, AX, P, YP, AP, G, Z, T1, T2, T3;
-    DevBuf P32, Q32, R32;          // complex64 staging for mixed-precision H psi
     DevBuf small;                  // N x N work matrices
     DevBuf vec;                    // per-band vectors
     DevBuf red;                    // reduction partials
@@ -64,13 +63,7 @@ static Solver *solver_get(pw_ctx *ctx, int nb, bool mixed) {
         ctx->solver = s;
         ctx->device_bytes += (int64_t)(11 * blk + s->small.bytes + s->vec.bytes + s->red.bytes + 256);
     }
-    if (mixed && !s->P32.p) {
-        const size_t blk32 = (size_t)s->nbmax * npw * 8;
-        s->P32.alloc(blk32);
-        s->Q32.alloc(blk32);
-        s->R32.alloc(blk32);
-        ctx->device_bytes += (int64_t)(3 * blk32);
-    }
+    (void)mixed;   // the complex64 staging of mixed H psi lives in the rotation temporaries
     return s;
 }
 
@@ -146,11 +139,14 @@ struct FcgRun {
 
     void fold(void *in, void *y, void *ay, bool low) {
         if (low) {
-            c128_to_c64(nb, npw, in, L, s->P32.p, L, st);
-            hpsi_any(ctx, PW_C64, nb, s->P32.p, L, s->Q32.p, L, E, st);
-            hpsi_any(ctx, PW_C64, nb, s->Q32.p, L, s->R32.p, L, E, st);
-            c64_to_c128(nb, npw, s->Q32.p, L, y, L, st);
-            c64_to_c128(nb, npw, s->R32.p, L, ay, L, st);
+            // complex64 staging in the rotation temporaries, which hold nothing live during a
+            // fold: T1 = [P32 | Q32] (each nb x npw complex64 fits half a block), T2 = [R32]
+            void *P32 = T1, *Q32 = (char *)T1 + (size_t)nb * npw * 8, *R32 = T2;
+            c128_to_c64(nb, npw, in, L, P32, L, st);
+            hpsi_any(ctx, PW_C64, nb, P32, L, Q32, L, E, st);
+            hpsi_any(ctx, PW_C64, nb, Q32, L, R32, L, E, st);
+            c64_to_c128(nb, npw, Q32, L, y, L, st);
+            c64_to_c128(nb, npw, R32, L, ay, L, st);
         } else {
             hpsi_any(ctx, PW_C128, nb, in, L, y, L, E, st);
             hpsi_any(ctx, PW_C128, nb, y, L, ay, L, E, st);
@@ -163,27 +159,38 @@ struct FcgRun {
         else std::swap(blk, tmp);
     }
     void rotate(const double2 *M, void *&blk, void *&tmp) {
-        zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st, false, ctx->rot_tune.get(nb));
+        {
+            ProfScope p(ctx, 7, st);
+            zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st, false, ctx->rot_tune.get(nb));
+        }
         settle(blk, tmp);
+    }
+    // S (nb x nb) = A^H B over the plane waves
+    void gram(const void *A, const void *B, double alpha, double2 *S, bool trans) {
+        ProfScope p(ctx, 6, st);
+        zgemm_nt(nb, nb, npw, true, A, L, B, L, alpha, nullptr, 0.0, S, nb, trans, ctx->d_partial.p, st);
     }
     // (X, Y, AX) <- M . (X, Y, AX) in one batched launch
     void rotate3(const double2 *M) {
         const void *in[3] = {X, Y, AX};
         void *out[3] = {T1, T2, T3};
-        zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st, false, ctx->rot_tune.get(nb));
+        {
+            ProfScope p(ctx, 5, st);
+            zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st, false, ctx->rot_tune.get(nb));
+        }
         settle(X, T1);
         settle(Y, T2);
         settle(AX, T3);
     }
     void orth() {
-        zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        gram(X, X, 1.0, Sm, false);
         chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
         rotate3(Tm);
     }
     // Rayleigh-Ritz in A = (H - E)^2 on the iterate (Y, AX exact): Ritz values of
     // Y^H Y ascending; the search directions and gradients turn with the bands.
     void a_rr(bool rotate_dirs) {
-        zgemm_nt(nb, nb, npw, true, Y, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        gram(Y, Y, 1.0, Sm, false);
         dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
         rotate3(Rm);
         if (rotate_dirs) {
@@ -197,10 +204,16 @@ struct FcgRun {
     // Rayleigh-Ritz in H on copies of the block: lam = theta - E ascending and the
     // residuals Delta_i of the H-Ritz vectors (the iterate itself is left alone)
     void h_resid() {
-        zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        gram(X, Y, 1.0, Sm, false);
         dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
-        zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st, false, ctx->rot_tune.get(nb));
-        zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st, false, ctx->rot_tune.get(nb));
+        {
+            ProfScope p(ctx, 7, st);
+            zgemm_nn_launch(nb, npw, nb, Rm, nb, X, L, 1.0, 0.0, T1, L, st, false, ctx->rot_tune.get(nb));
+        }
+        {
+            ProfScope p(ctx, 7, st);
+            zgemm_nn_launch(nb, npw, nb, Rm, nb, Y, L, 1.0, 0.0, T2, L, st, false, ctx->rot_tune.get(nb));
+        }
         red_resid(nb, npw, T2, T1, L, lam, res, br, st);
     }
     // band kinetic energies, then (learned preconditioner) the per-shell scaling table
@@ -227,7 +240,7 @@ struct FcgRun {
         fill_zero(G, (size_t)nb * npw * 16, st);
         fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
         // initial orthonormalisation (Y, AX are garbage here but get overwritten)
-        zgemm_nt(nb, nb, npw, true, X, L, X, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+        gram(X, X, 1.0, Sm, false);
         chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
         rotate(Tm, X, T1);
         fold(X, Y, AX, false);
@@ -242,8 +255,11 @@ struct FcgRun {
         red_grad(nb, npw, X, AX, G, Z, L, mu, pa, gz, gzo, br, st);
         pupdate(nb, npw, Z, P, L, gz, gzo, gz_old, st);
         // P -= X (X^H P): W[b][j] = -<x_j|p_b>
-        zgemm_nt(nb, nb, npw, true, X, L, P, L, -1.0, nullptr, 0.0, Wm, nb, true, ctx->d_partial.p, st);
-        zgemm_nn_launch(nb, npw, nb, Wm, nb, X, L, 1.0, 1.0, P, L, st, false, ctx->rot_tune.get(nb));
+        gram(X, P, -1.0, Wm, true);
+        {
+            ProfScope p(ctx, 7, st);
+            zgemm_nn_launch(nb, npw, nb, Wm, nb, X, L, 1.0, 1.0, P, L, st, false, ctx->rot_tune.get(nb));
+        }
         fold(P, YP, AP, use_mixed);
         red_line(nb, npw, Y, YP, P, L, line4, br, st);
         line_coef(nb, mu, line4, coef, st);
@@ -316,7 +332,7 @@ struct FcgRun {
         if (result == PW_OK || result == PW_ENOCONV) {
             hpsi_any(ctx, PW_C128, nb, X, L, Y, L, E, st);
             n_hpsi += nb;
-            zgemm_nt(nb, nb, npw, true, X, L, Y, L, 1.0, nullptr, 0.0, Sm, nb, false, ctx->d_partial.p, st);
+            gram(X, Y, 1.0, Sm, false);
             dense_eigh(nb, Sm, nb, Aw, lam, Rm, 0, 0.0, d_status + 4, st);
             rotate(Rm, X, T1);
             rotate(Rm, Y, T2);
@@ -355,17 +371,71 @@ struct FcgRun {
     }
 };
 
+namespace {
+// HIP events on the solver's stream around the phases of a solve (set-up, iteration
+// segments, checks, final Rayleigh-Ritz); elapsed times are read after the host has
+// synchronised anyway
+struct PhaseClock {
+    hipEvent_t ev[6] = {};
+    double ms[4] = {0, 0, 0, 0};
+    PhaseClock() {
+        for (hipEvent_t &e : ev) PW_HIP(hipEventCreate(&e));
+    }
+    ~PhaseClock() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t st) { PW_HIP(hipEventRecord(ev[i], st)); }
+    void add(int phase, int a, int b) {
+        float t = 0.f;
+        PW_HIP(hipEventElapsedTime(&t, ev[a], ev[b]));
+        ms[phase] += t;
+    }
+};
+}  // namespace
+
 pw_status folded_cg(pw_ctx *ctx, double E, int nb, void *psi, int64_t ld, double *eig, double *resid,
                     const pw_cg_opts &o, pw_cg_stats *stats, hipStream_t st) {
     FcgRun r(ctx, E, nb, psi, ld, eig, resid, o, stats, st);
+    PhaseClock clk;
+    // per-stage profiling (pw_profile_begin) records the iterations only
+    struct Pause {
+        pw_ctx *c;
+        ~Pause() { c->prof_pause = false; }
+    } pause{ctx};
+    ctx->prof_pause = true;
+    clk.mark(0, st);
     r.setup();
+    clk.mark(1, st);
+    bool first = true;
     for (;;) {
         const int n = r.segment_length();
+        clk.mark(2, st);
+        ctx->prof_pause = false;
         for (int k = 0; k < n; ++k) r.iteration();
+        ctx->prof_pause = true;
+        clk.mark(3, st);
         r.check_device();
-        if (!r.check_host()) break;
+        clk.mark(4, st);
+        const bool more = r.check_host();     // synchronises the stream
+        if (first) clk.add(0, 0, 1);
+        first = false;
+        clk.add(1, 2, 3);
+        clk.add(2, 3, 4);
+        if (!more) break;
     }
-    return r.finish();
+    clk.mark(5, st);
+    const pw_status res = r.finish();         // synchronises the stream
+    {
+        float t = 0.f;
+        PW_HIP(hipEventRecord(clk.ev[4], st));
+        PW_HIP(hipEventSynchronize(clk.ev[4]));
+        PW_HIP(hipEventElapsedTime(&t, clk.ev[5], clk.ev[4]));
+        clk.ms[3] = t;
+    }
+    if (stats)
+        for (int k = 0; k < 4; ++k) stats->ms[k] = clk.ms[k];
+    return res;
 }
 
 // ---------------------------------------------------------------------------

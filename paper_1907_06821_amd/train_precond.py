@@ -3,7 +3,8 @@
 Samples come from the method's own solves: folded-spectrum CG runs on a cell
 store snapshots of the iterate X(t); once converged (X*), every snapshot gives
 the per-(shell, band) tables of its gradient g = A x - mu x and of its error
-direction e = -(I - X* X*^H) x (gauge invariant).  The network
+direction e = (I - X* X*^H) x (gauge invariant; the CG steps along -K g, so
+K g should point along e).  The network
 f(T_shell, T_band, E_ref) of the preconditioner K = M(G) e^f is then fitted
 to the cosine loss 1 - Re<K g, e> / (|K g| |e|) with the library's own loss,
 gradient and Adam kernels.  The inner products are taken in the metric
