@@ -1,0 +1,158 @@
+"""Folded-spectrum solves on the GPU judged by the CPU oracle alone.
+
+* Mixed precision (complex64 H psi with BF16 projector products, FP64 block
+  algebra, the precision ladder) with each preconditioner, on the tiny cell and
+  on a small cell with projectors at a k-point: the nearest eigenpairs of the
+  dense H within 1e-8 Ha, and the residuals ||H psi - theta psi|| recomputed by
+  the oracle from the returned vectors.
+* The uneven batch (cubes of 8-14 bohr on 32^3-64^3 grids): sixteen problems
+  whose 16 nearest states are separated from the 17th (decided by the oracle's
+  dense spectrum) solved together to convergence, each against its dense
+  nearest eigenpairs.
+* The 256-atom wire in FP64 and in mixed precision: the 128 eigenvalues nearest
+  E_ref against the oracle's shift-invert values, whose completeness was proven
+  by Sylvester inertia (tests/golden/wire256_nearest.json), plus residuals of
+  sampled Ritz pairs recomputed with the oracle's H psi, and the per-band
+  difference between the mixed and the FP64 eigenvalues.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1907_06821_amd import synth
+from oracle.eigen import nearest_eigenpairs, principal_cosines
+from tests._helpers import oracle_for, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wire256_nearest.json")
+
+
+def _network(seed=4, scale=0.5):
+    """A fixed, untrained network (the learned preconditioner only changes the path)."""
+    import torch
+    w = synth.mlp_init(seed) * (1.0 + scale)
+    return torch.from_numpy(w.astype(np.float32)).to("cuda")
+
+
+def _ctx(prob, nb):
+    import paper_1907_06821_amd as pw
+    return pw.Context.from_problem(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+
+
+@pytest.mark.parametrize("precond", [0, 1, 2])
+@pytest.mark.parametrize("which", ["tiny", "small_nl_kpt"])
+def test_mixed_precision_solve_matches_dense(torch_cuda, which, precond):
+    import paper_1907_06821_amd as pw
+    if which == "tiny":
+        prob = synth.config(1)
+    else:
+        prob = synth.small_nonlocal_problem(kpt=(0.11, -0.23, 0.07), nbands=6, e_ref=0.8)
+    op = oracle_for(prob)
+    lam, u, _, gap = nearest_eigenpairs(op.dense(), prob.e_ref, prob.nbands)
+    assert gap > 1e-3
+    nb = prob.nbands
+    ctx = _ctx(prob, nb)
+    if precond == 2:
+        pw.mlp_set(ctx, _network())
+    t = to_dev(synth.start_vectors(1, nb, op.npw, seed=5))
+    eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, t, tol=1e-9, maxit=6000, check_every=10, precision=1,
+                                      precond=precond)
+    vec = t.cpu().numpy()
+    assert st["converged"], st
+    assert np.max(np.abs(eig - lam)) < 1e-8
+    assert principal_cosines(u, vec).min() > 1 - 1e-8
+    r = np.linalg.norm(op.apply(vec) - eig[:, None] * vec, axis=1)
+    assert np.max(r) < 1e-8
+    assert np.max(np.abs(r - res)) < 1e-10
+
+
+def _separated_cubes(count, nwant=16, min_gap=2e-3):
+    """The first `count` problems of the uneven batch whose nwant nearest states
+    end at least min_gap (folded distance) before the next one, with their dense
+    nearest eigenvalues (the oracle decides which problems qualify)."""
+    out = []
+    for p in synth.batched_problems(64, seed=0):
+        op = oracle_for(p)
+        lam, _, _, gap = nearest_eigenpairs(op.dense(), p.e_ref, nwant)
+        if gap >= min_gap:
+            out.append((p, lam))
+        if len(out) == count:
+            break
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_uneven_batch_converges_to_dense_eigenpairs(torch_cuda, precision):
+    import torch
+    import paper_1907_06821_amd as pw
+    sel = _separated_cubes(16)
+    assert len(sel) == 16
+    nb, nconv = 24, 16
+    probs = [p for p, _ in sel]
+    ctxs = [_ctx(p, nb) for p in probs]
+    psis = [torch.from_numpy(synth.start_vectors(4, nb, c.npw, seed=i)).to("cuda") for i, c in enumerate(ctxs)]
+    # tol 1e-6 (the paper's eigen-residual): by Kato-Temple the eigenvalue error is at most tol^2 / gap,
+    # 5e-10 Ha at the 2e-3 Ha separation the selection demands (some FP64 cube solves creep below 1e-7)
+    eigs, ress, sts, status = pw.batch_solve(ctxs, [p.e_ref for p in probs], psis, tol=1e-6, maxit=6000,
+                                             check_every=20, precision=precision, precond=1, nconv=nconv,
+                                             raise_on_noconv=False)
+    worst = 0.0
+    for i, (p, lam) in enumerate(sel):
+        assert sts[i]["converged"], (i, p.name, sts[i])
+        e = eigs[i]
+        near = np.sort(e[np.argsort(np.abs(e - p.e_ref), kind="stable")[:nconv]])
+        worst = max(worst, float(np.max(np.abs(near - lam))))
+    print(f"16 cubes, precision {precision}: max |eig - dense| {worst:.2e}")
+    assert worst < 1e-8
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        pytest.fail("tests/golden/wire256_nearest.json missing (written by tests/golden/make_wire256_nearest.py)")
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(os.path.dirname(GOLDEN),
+                                                                     "make_wire256_nearest.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    prob = synth.config(2)
+    assert g["input_sha256"] == mk.input_hash(prob, prob.vgrid()), "golden values were made from other inputs"
+    assert g["complete"] and g["count_in_window"] == g["nwant"] == 128
+    return prob, g
+
+
+def test_wire256_fp64_and_mixed_match_shift_invert(torch_cuda):
+    import torch
+    import paper_1907_06821_amd as pw
+    prob, g = _golden()
+    ref = np.asarray(g["nearest"])
+    nb, nconv = 136, 128
+    ctx = _ctx(prob, nb)
+    op = oracle_for(prob)
+    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=0)).to("cuda")
+    got = {}
+    for precision in (0, 1):
+        psi = psi0.clone()
+        eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=4000, check_every=20,
+                                          precision=precision, precond=1, nconv=nconv, raise_on_noconv=False)
+        assert st["converged"], st
+        idx = np.sort(np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv])
+        near = eig[idx]
+        err = np.abs(near - ref)
+        print(f"precision {precision}: {st['iters']} iterations, max |eig - shift-invert| {err.max():.2e}, "
+              f"max residual {res[idx].max():.2e}")
+        assert err.max() < 1e-8
+        # residuals of sampled Ritz pairs recomputed with the oracle's H psi
+        sample = idx[[0, 31, 64, 97, 127]]
+        vec = psi[torch.as_tensor(sample, device="cuda")].cpu().numpy()
+        r = np.linalg.norm(op.apply(vec) - eig[sample][:, None] * vec, axis=1)
+        assert np.max(r) <= 1.05e-6
+        assert np.max(np.abs(r - res[sample])) < 1e-9
+        got[precision] = near
+    d = np.abs(got[1] - got[0])
+    print("per-band |theta_mixed - theta_fp64| (Ha): max %.2e, median %.2e" % (d.max(), np.median(d)))
+    assert d.max() < 1e-8
