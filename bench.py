@@ -1,43 +1,34 @@
-"""Benchmark: band-H psi/s of the folded-spectrum CG on the 256-atom wire cell.
+"""Benchmark of the folded-spectrum CG: band-H psi/s on the 4000-atom wire, and
+the time-to-residual solves of the metric on the 256-atom wire.
 
-One step = one folded-spectrum PCG iteration on the whole block: gradient and
-preconditioner, conjugation and projection, the two H applications
-Y = (H - E)P and A P = (H - E) Y, the per-band line minimisation and the
-Gram/Cholesky re-orthonormalisation.  K steps run as one solve of K
-iterations (its set-up, one residual check and the final Rayleigh-Ritz are
-inside the timed region too).  value = band-H psi applications per second.
+Headline (the JSON line's value): folded-spectrum PCG iterations on the
+4000-atom wire, the largest cell of the workload list (50 x 50 x 200 bohr,
+128 x 128 x 512 grid, Ecut 10 Ha, 755,605 plane waves, an fcc wire of 4040
+sites minus 40 seeded vacancies with Gaussian wells and 4 Kleinman-Bylander
+projectors per atom, 1024 bands near E_ref = 0.3 Ha; synthetic stand-in for
+the paper's copper nanowire), mixed precision: complex64 FFT/pointwise and
+BF16 projector GEMMs with FP32 accumulation for the two H psi of each
+iteration, FP64 for the block algebra.  One step = one CG iteration on the
+whole block (gradient and preconditioner, conjugation and projection, two H
+psi, per-band line minimisation, Gram/Cholesky re-orthonormalisation);
+value = band-H psi per second of iteration time (HIP events on the solver's
+stream).  The roofline object is the dominant kernel of the iterations.
 
-Workload (synthetic stand-in for the paper's copper nanowire): 20 x 20 x 80 bohr
-cell, 48 x 48 x 192 grid, Ecut 10 Ha (48,369 plane waves), 256-atom fcc wire
-with Gaussian wells and 4 Kleinman-Bylander projectors per atom, 128 bands
-nearest E_ref = 0.3 Ha, complex128.
-
-Second part of the metric ("solve"): folded-CG time to max_i Delta_i <= 1e-6
-for the 128 states nearest E_ref (8 buffer bands; median over three seeded
-starts, every leg from the same starts) with FP64 H psi + Teter-Payne-Allan,
-FP64 + the paper's M(G), mixed precision with TPA, with M(G) and with the
-learned preconditioner (M(G) e^f; weights trained by
-paper_1907_06821_amd.train_precond and committed); time includes MLP inference,
-training time is reported separately.
-
-Third part ("linear"): the folded linear equation (H - E)^2 psi = (H - E) w
-of the system states for 8 boundary sources, PCG to ||(H - E) psi - w|| <= 1e-8
-with the eigenstate-augmented preconditioner M' (from 136 eigenpairs of a mixed
-+ M(G) eigensolve) against M(G) alone under the same iteration cap, and M' again
-for 32 sources.
-
-Fourth part ("chebfd"): Chebyshev filter diagonalisation of a window around
-E_ref holding 64 states, 136 vectors, 3 steps of a degree-1500 filter (the
-paper's degree), bounds from 40 Lanczos steps; per step, the residuals of the
-Ritz pairs nearest the folded solve's eigenvalues in the window.
-
-Fifth part ("kinterp"): wave-function interpolation of the 128 states near E_ref
-between k = 0 and k = (0, 0, 0.02) to the midpoint, against a direct solve there.
+Extra legs on the 256-atom wire (20 x 20 x 80 bohr, 48 x 48 x 192, 48,369
+plane waves, 256 atoms, 128 bands): FP64 iterations; the folded-CG time to
+max_i Delta_i <= 1e-6 for the 128 states nearest E_ref (8 buffer bands, median
+over three seeded starts) with FP64 + Teter-Payne-Allan, FP64 + the paper's
+M(G), mixed with TPA, with M(G) and with the learned preconditioner; the folded
+linear equation with the eigenstate-augmented M' (8 and 32 boundary sources);
+ChebFD (degree 1500, a window of 64 states); wave-function interpolation
+between k-points.  cpu_baseline: the FP64 oracle's H psi on a bounded sample
+of the 4000-atom wire.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
---no-cpu (skip the CPU oracle leg) --no-solve --solve-legs a,b --no-linear
---linear-maxit N --no-chebfd --chebfd-degree D --chebfd-steps S --chebfd-window N --no-kinterp
---precision {fp64,mixed} (of the band-H psi leg).
+--no-cpu --no-wire256 --wire256-steps N --no-solve --solve-legs a,b --no-linear
+--linear-maxit N --no-chebfd --chebfd-degree D --chebfd-steps S --chebfd-window N
+--no-kinterp; --wire4000-hpsi (only the complex64 H psi of 1024 bands);
+--copy-probe BYTES (HBM counter calibration).
 """
 from __future__ import annotations
 
@@ -435,14 +426,280 @@ def wire4000_hpsi(steps=3, warmup=1):
                       "stages": stages}))
 
 
+def wire4000_step(steps, warmup, log=None):
+    """The headline: folded-spectrum CG iterations on the 4000-atom wire (50 x 50 x
+    200 bohr, 128 x 128 x 512 grid, Ecut 10 Ha, 755,605 plane waves, 4000 atoms x 4
+    KB projectors, 1024 bands near E_ref = 0.3 Ha), mixed precision: complex64
+    FFT/pointwise and BF16 projector GEMMs (FP32 accumulation) for the two H psi
+    of each iteration, FP64 for the block algebra (Gram/Cholesky, projections,
+    rotations); the residual checks use FP64 H psi with projector rows generated
+    per call (the 193 GB FP64 table is never stored).  The learned preconditioner
+    (committed weights) if present, else the paper's M(G).
+
+    One step = one CG iteration on the whole block.  `warmup` iterations run as a
+    solve of their own first; then a solve of `steps` iterations whose iterations
+    alone are timed by HIP events on the solver's stream (its set-up, its one
+    residual check and its final Rayleigh-Ritz are reported apart).  value =
+    2 nb steps / iteration time."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth, train_precond
+    prob = synth.config(5)
+    nb = prob.nbands
+    t0 = time.perf_counter()
+    ctx = pw.Context.from_problem(prob, max_bands=nb, flags=pw.PW_PREP_C64 | pw.PW_PREP_C128_OTF)
+    torch.cuda.synchronize()
+    t_ctx = time.perf_counter() - t0
+    if log:
+        log(f"wire4000 context: {t_ctx:.1f} s, {ctx.info()['device_bytes'] / 1e9:.1f} GB, "
+            f"{ctx.cols_bands} bands per FFT launch")
+    # complex64 FFT launch variants picked by the library's autotuner (not timed)
+    tuned = [r for r in pw.autotune(ctx, min(128, ctx.cols_bands), dtype=pw.PW_C64, reps=2) if r["chosen"]]
+    wpath = os.path.join(train_precond.DATA_DIR, train_precond.WEIGHTS + ".npy")
+    precond = 1
+    if os.path.exists(wpath):
+        pw.mlp_set(ctx, torch.from_numpy(np.load(wpath)).to("cuda"))
+        precond = 2
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    psi = torch.randn((nb, ctx.npw), dtype=torch.complex128, device="cuda", generator=gen)
+    opts = dict(tol=1e-30, precision=1, precond=precond, raise_on_noconv=False)
+    _, _, stw = pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=max(1, warmup), check_every=max(1, warmup), **opts)
+    torch.cuda.synchronize()
+    if log:
+        log(f"wire4000 warm-up: {stw['iters']} iterations, {stw['ms_iters']:.0f} ms of iterations, "
+            f"set-up {stw['ms_setup']:.0f} ms, check {stw['ms_checks']:.0f} ms, max residual {stw['max_resid']:.3e}")
+    pw.profile_begin(ctx, 100000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=steps, check_every=steps, **opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = pw.profile_end(ctx)
+    it_s = st["ms_iters"] / 1e3
+    band_hpsi = 2 * nb * steps
+    value = band_hpsi / it_s
+    stages = stage_rooflines(ctx, nb, band_hpsi, True, prof)
+    dom = max(stages, key=lambda k: stages[k]["total_ms"])
+    d = stages[dom]
+    roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
+                "frac": round(d["frac"], 4), "kernel": dom, "work_per_launch": d["work_per_launch"],
+                "traffic": measured_traffic_wire4000(dom)}
+    ideal = sum(v["work_per_launch"] * v["launches"] / (v["peak"] * (1e9 if v["bound"] == "hbm" else 1e12))
+                for v in stages.values())
+    roofline["step_frac"] = round(ideal / it_s, 4)
+    roofline["step_ideal_ms"] = round(ideal / steps * 1e3, 3)
+    line = {
+        "metric": "band-Hψ/sec and folded-CG time to residual 1e-6 (mixed+learned vs FP64)",
+        "value": round(value, 1),
+        "unit": "band-Hpsi/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(st["ms_iters"] / steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+bf16 H psi, f64 block algebra",
+        "data": "synthetic",
+        "config": {"workload": "wire4000: 50x50x200 bohr, 128x128x512 grid, Ecut 10 Ha, npw 755605, 4000 atoms x 4 "
+                               "KB projectors (1% vacancies), 1024 bands near E_ref 0.3 Ha, folded-spectrum PCG "
+                               "iteration, mixed precision",
+                   "npw": ctx.npw, "bands": nb, "nproj": ctx.nproj, "grid": list(ctx.grid), "precision": "mixed",
+                   "precond": ("tpa", "mg", "learned")[precond], "cols_bands": ctx.cols_bands},
+        "roofline": roofline,
+        "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                   for k, v in stages.items()},
+        "phases_ms": {"setup": round(st["ms_setup"], 1), "iterations": round(st["ms_iters"], 1),
+                      "check": round(st["ms_checks"], 1), "final_rayleigh_ritz": round(st["ms_final"], 1)},
+        "solve_wall_s": round(wall, 2),
+        "context_s": round(t_ctx, 2),
+        "device_bytes": ctx.info()["device_bytes"],
+        "max_resid_fp64": st["max_resid"],
+        "autotuned": [{"pass": r["pass_"], "kind": r["kind"], "nthr": r["nthr"], "sched": r["sched"],
+                       "us": round(r["ms"] * 1e3, 1)} for r in tuned],
+    }
+    if log:
+        log(f"wire4000: {value:.1f} band-Hpsi/s, {st['ms_iters'] / steps:.1f} ms per iteration, dominant {dom} "
+            f"{d['frac']:.3f} of peak")
+    ctx.close()
+    del psi
+    torch.cuda.empty_cache()
+    return line
+
+
+def measured_traffic_wire4000(stage):
+    """HBM bytes per launch of `stage` on the 4000-atom wire from the committed
+    counter runs (FETCH_SIZE / WRITE_SIZE, copy-calibrated), if they were taken
+    on the current source of the kernel; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wire4000_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    st = rec.get("stages", {}).get(stage)
+    if st is None:
+        return None
+    src = os.path.join(ROOT, st["source"])
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != st["source_sha256"]:
+            return None
+    return st["bytes_per_launch"]
+
+
+def cpu_baseline_wire4000(atoms=100, log=None):
+    """The FP64 oracle's matrix-free H psi (numpy FFT, projector rows built a
+    hundred atoms at a time) on the 4000-atom wire, timed on a bounded sample: one
+    band's local and kinetic part, plus the nonlocal part of one chunk of `atoms`
+    atoms, scaled to all 4000 atoms (the chunks cost the same).  Run on all the
+    host's threads and on one."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.hamiltonian import Operator, hpsi, projectors
+    from paper_1907_06821_amd import synth
+    prob = synth.config(5)
+    op = Operator.from_problem(prob)
+    c = synth.start_vectors(5, 1, op.npw, seed=1)
+
+    def one():
+        t0 = time.perf_counter()
+        hpsi(c, op.miller, op.kin, op.vgrid, None, None, prob.e_ref)
+        t1 = time.perf_counter()
+        beta = projectors(op.miller, op.cell, op.pos, op.sigma, op.nl, op.kpt, atoms=range(atoms))
+        d = op.dproj[:atoms * op.nl]
+        _ = ((c @ beta.conj().T) * d[None, :]) @ beta
+        t2 = time.perf_counter()
+        return (t1 - t0) + (t2 - t1) * (prob.natom / atoms)
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    t_all = one()
+    with threadpool_limits(limits=1):
+        t_one = one()
+    out = {"value": round(1.0 / t_all, 4), "unit": "band-Hpsi/s", "cores": threads, "kind": "oracle",
+           "value_1core": round(1.0 / t_one, 4),
+           "sample": f"wire4000: one band-H psi (FP64), local part plus the nonlocal part of {atoms} of "
+                     f"{prob.natom} atoms scaled by {prob.natom // atoms}; {t_all:.1f} s per band-H psi on "
+                     f"{threads} threads, {t_one:.1f} s on 1"}
+    if log:
+        log(f"cpu baseline: {out}")
+    return out
+
+
+def wire256_legs(args, log):
+    """The 256-atom wire (20 x 20 x 80 bohr, 48 x 48 x 192 grid, 48,369 plane waves,
+    1024 projectors): FP64 folded-CG iterations at 128 bands (band-H psi/s and its
+    roofline), the time-to-residual solves of the metric, the folded linear
+    equation, ChebFD and the k-point interpolation."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+    prob = synth.config(2)
+    nbuf = 8
+    ctx = pw.Context.from_problem(prob, max_bands=prob.nbands + nbuf, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    nb = prob.nbands
+    steps = args.wire256_steps
+    tuned = {n: [r for r in pw.autotune(ctx, n, dtype=pw.PW_C128, reps=3) if r["chosen"]] for n in (nb, nb + nbuf)}
+    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
+    opts = dict(tol=1e-30, check_every=20, precision=0, raise_on_noconv=False)
+    psi = psi0.clone()
+    pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=3, **opts)
+    psi = psi0.clone()
+    pw.profile_begin(ctx, 200000)
+    eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=steps, **opts)
+    torch.cuda.synchronize()
+    prof = pw.profile_end(ctx)
+    it_s = st["ms_iters"] / 1e3
+    stages = stage_rooflines(ctx, nb, 2 * nb * steps, False, prof)
+    dom = max(stages, key=lambda k: stages[k]["total_ms"])
+    d = stages[dom]
+    ideal = sum(v["work_per_launch"] * v["launches"] / (v["peak"] * (1e9 if v["bound"] == "hbm" else 1e12))
+                for v in stages.values())
+    out = {"step": {"workload": "wire256: 20x20x80 bohr, 48x48x192 grid, Ecut 10 Ha, npw 48369, 256 atoms x 4 KB "
+                                "projectors, 128 bands near E_ref 0.3 Ha, FP64 folded-spectrum PCG iteration",
+                    "steps": steps, "value": round(2 * nb * steps / it_s, 1), "unit": "band-Hpsi/s",
+                    "ms_per_step": round(st["ms_iters"] / steps, 4), "dtype": "c128",
+                    "roofline": {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"],
+                                 "unit": d["unit"], "frac": round(d["frac"], 4), "kernel": dom,
+                                 "traffic": measured_traffic(dom, False, nb, next(
+                                     (r["sched"] for r in tuned[nb] if r["pass_"] == 4), None)),
+                                 "step_frac": round(ideal / it_s, 4)},
+                    "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                               for k, v in stages.items()},
+                    "autotuned": {str(n): [{"pass": r["pass_"], "kind": r["kind"], "nthr": r["nthr"],
+                                            "sched": r["sched"], "us": round(r["ms"] * 1e3, 1)} for r in rs]
+                                  for n, rs in tuned.items()}}}
+    log(f"wire256 step: {out['step']['value']} band-Hpsi/s, dominant {dom} {d['frac']:.3f}")
+    if not args.no_solve:
+        legs = [l for l in SOLVE_LEGS if l[0] in args.solve_legs.split(",")]
+        out["solve"] = solve_legs(ctx, prob, nb + nbuf, nb, legs, log=log)
+    eig_ref = None
+    if not args.no_linear:
+        out["linear"] = linear_leg(ctx, prob, nb + nbuf, nb, maxit=args.linear_maxit, log=log)
+        eig_ref = out["linear"].pop("_eig")
+    if not args.no_chebfd:
+        out["chebfd"] = chebfd_leg(ctx, prob, nb + nbuf, eig_ref, n_window=args.chebfd_window,
+                                   degree=args.chebfd_degree, steps=args.chebfd_steps, log=log)
+    if not args.no_kinterp:
+        out["kinterp"] = kinterp_leg(prob, nb + nbuf, nb, log=log)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
+    ctx.close()
+    return out
+
+
+def stage_rooflines(ctx, nb, band_hpsi, mixed, prof):
+    """Per-stage achieved rate against its bound, from the per-stage profile of a
+    solve's iterations (HIP events on the solver's stream).  Algorithmic work:
+    FFT passes move the bytes of stage_work per band-H psi (band_hpsi of them in
+    the profiled iterations; the xy pass also reads V once per launch) against
+    HBM; the projector GEMMs do 8 nproj npw flops per band-H psi against the
+    matrix peak of their precision (BF16 mixed, FP64 otherwise); the solver's FP64
+    block products do 8 npw nb^2 flops per product (three in block_rotate3)
+    against the FP64 peak.  avg_ms and work_per_launch are totals over launches."""
+    npw = ctx.npw
+    n0, n1, n2 = ctx.grid
+    per_band = stage_work(ctx, 1, 8 if mixed else 16, ctx.nproj)
+    vbytes = n0 * n1 * n2 * (4 if mixed else 8)
+    blk = 8.0 * npw * nb * nb
+    stages = {}
+    for k, (ms, n) in prof.items():
+        if n == 0 or ms <= 0:
+            continue
+        if k.startswith("block_"):
+            bound, peak = "mfma", FP64_PEAK_TFS
+            total = (3 if k == "block_rotate3" else 1) * blk * n
+        else:
+            bound, amount, _ = per_band[k]
+            if k == "xy_fft_v":
+                amount -= vbytes                      # stage_work counts V once per call
+            total = amount * band_hpsi + (vbytes * n if k == "xy_fft_v" else 0)
+            peak = HBM_PEAK_GBS if bound == "hbm" else (BF16_PEAK_TFS if mixed else FP64_PEAK_TFS)
+        scale = 1e9 if bound == "hbm" else 1e12
+        ach = total / (ms / 1e3) / scale
+        stages[k] = {"bound": bound, "avg_ms": ms / n, "launches": n, "total_ms": ms, "achieved": ach,
+                     "peak": peak, "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "frac": ach / peak,
+                     "work_per_launch": total / n}
+    return stages
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--cpu-bands", type=int, default=64)
+    ap.add_argument("--no-wire256", action="store_true", help="skip every wire256 leg")
+    ap.add_argument("--wire256-steps", type=int, default=40)
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-residual solves")
     ap.add_argument("--solve-legs", default=",".join(n for n, _, _ in SOLVE_LEGS))
     ap.add_argument("--no-linear", action="store_true", help="skip the folded linear-equation leg")
@@ -453,12 +710,16 @@ def main():
     ap.add_argument("--chebfd-window", type=int, default=64, help="eigenstates inside the ChebFD window")
     ap.add_argument("--no-kinterp", action="store_true", help="skip the k-point interpolation leg")
     ap.add_argument("--wire4000-hpsi", action="store_true",
-                    help="only: complex64 H psi throughput on the 4000-atom wire (1024 bands, about 150 GB)")
+                    help="only: complex64 H psi throughput on the 4000-atom wire (1024 bands in one call)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
-    if args.wire4000_hpsi and args.gpus == 1:
-        wire4000_hpsi(steps=max(1, args.steps if args.steps != 40 else 3), warmup=max(1, args.warmup))
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver shards no work across GPUs in this build",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.wire4000_hpsi:
+        wire4000_hpsi(steps=max(1, args.steps), warmup=max(1, args.warmup))
         return
     if args.copy_probe:
         import torch
@@ -469,118 +730,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 5}))
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the solver shards no work across GPUs in this build",
-              file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
     import torch
-    import paper_1907_06821_amd as pw
-    from paper_1907_06821_amd import synth
-
     torch.cuda.set_device(0)
-    prob = synth.config(2)
-    mixed = args.precision == "mixed"
-    nbuf = 8                                       # buffer bands of the time-to-residual solves
-    ctx = pw.Context.from_problem(prob, max_bands=prob.nbands + nbuf, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
-    nb = prob.nbands
-    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw)).to("cuda")
-    opts = dict(tol=1e-30, check_every=20, precision=1 if mixed else 0)
-    # launch variants picked by the library's autotuner for both band counts used below (not timed)
-    tuned = {n: [r for r in pw.autotune(ctx, n, dtype=pw.PW_C128, reps=3) if r["chosen"]] for n in (nb, nb + nbuf)}
-
-    # warm-up (also allocates the solver workspace)
-    psi = psi0.clone()
-    pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=max(1, args.warmup), raise_on_noconv=False, **opts)
-    torch.cuda.synchronize()
-
-    psi = psi0.clone()
-    pw.profile_begin(ctx, 200000)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, maxit=args.steps, raise_on_noconv=False, **opts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = pw.profile_end(ctx)
-    dt = t1 - t0
-    value = st["n_hpsi"] / dt
-
-    # dominant stage and its roofline
-    work = stage_work(ctx, nb, 8 if mixed else 16, ctx.nproj)
-    stages = {}
-    for k, (ms, n) in prof.items():
-        if n == 0:
-            continue
-        bound, amount, unit = work[k]
-        avg_s = ms / n / 1e3
-        if bound == "hbm":
-            ach = amount / avg_s / 1e9
-            peak, u = HBM_PEAK_GBS, "GB/s"
-        else:
-            ach = amount / avg_s / 1e12
-            peak, u = (BF16_PEAK_TFS if mixed else FP64_PEAK_TFS), "TFLOP/s"
-        stages[k] = {"bound": bound, "avg_ms": ms / n, "launches": n, "achieved": ach, "peak": peak, "unit": u,
-                     "frac": ach / peak, "share": ms / (dt * 1e3)}
-    dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches"])
-    d = stages[dom]
-    roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
-                "frac": round(d["frac"], 4), "kernel": dom,
-                "traffic": measured_traffic(dom, mixed, nb, next((r["sched"] for r in tuned[nb] if r["pass_"] == 4),
-                                                                 None))}
-    # whole-step roofline: the ideal time of every H psi launch at its bound (bytes at HBM peak or flops at
-    # the matrix peak) plus the FP64 block GEMMs of each CG iteration (Gram X^H X, X^H P, the P update and
-    # the three rotations of X, Y, AX: six products of 8 npw nb^2 flops), over the measured time
-    ideal = 0.0
-    for k, v in stages.items():
-        bound, amount, unit = work[k]
-        ideal += v["launches"] * amount / ((HBM_PEAK_GBS * 1e9) if bound == "hbm" else
-                                           ((BF16_PEAK_TFS if mixed else FP64_PEAK_TFS) * 1e12))
-    block = 6 * 8.0 * ctx.npw * nb * nb / (FP64_PEAK_TFS * 1e12) * args.steps
-    roofline["step_frac"] = round((ideal + block) / dt, 4)
-    roofline["step_ideal_ms"] = round((ideal + block) / args.steps * 1e3, 4)
-
-    line = {
-        "metric": "band-Hψ/sec and folded-CG time to residual 1e-6 (mixed+learned vs FP64)",
-        "value": round(value, 1),
-        "unit": "band-Hpsi/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "c64+bf16" if mixed else "c128",
-        "data": "synthetic",
-        "config": {"workload": "wire256: 20x20x80 bohr, 48x48x192 grid, Ecut 10 Ha, npw 48369, 256 atoms x 4 KB "
-                               "projectors, 128 bands near E_ref 0.3 Ha, folded-spectrum PCG iteration",
-                   "npw": ctx.npw, "bands": nb, "nproj": ctx.nproj, "grid": list(ctx.grid),
-                   "precision": args.precision},
-        "roofline": roofline,
-        "stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                   for k, v in stages.items()},
-        "n_hpsi": st["n_hpsi"],
-        "autotuned": {str(n): [{"pass": r["pass_"], "kind": r["kind"], "nthr": r["nthr"], "sched": r["sched"],
-                                "us": round(r["ms"] * 1e3, 1)} for r in rs] for n, rs in tuned.items()},
-    }
-    if not args.no_solve:
-        legs = [l for l in SOLVE_LEGS if l[0] in args.solve_legs.split(",")]
-        line["solve"] = solve_legs(ctx, prob, nb + nbuf, nb, legs, log=lambda m: print(m, file=sys.stderr,
-                                                                                       flush=True))
-    eig_ref = None
-    if not args.no_linear:
-        line["linear"] = linear_leg(ctx, prob, nb + nbuf, nb, maxit=args.linear_maxit,
-                                    log=lambda m: print(m, file=sys.stderr, flush=True))
-        eig_ref = line["linear"].pop("_eig")
-    if not args.no_chebfd:
-        line["chebfd"] = chebfd_leg(ctx, prob, nb + nbuf, eig_ref, n_window=args.chebfd_window,
-                                    degree=args.chebfd_degree,
-                                    steps=args.chebfd_steps, log=lambda m: print(m, file=sys.stderr, flush=True))
-    if not args.no_kinterp:
-        line["kinterp"] = kinterp_leg(prob, nb + nbuf, nb, log=lambda m: print(m, file=sys.stderr, flush=True))
+    log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    line = wire4000_step(args.steps, args.warmup, log=log)
+    if not args.no_wire256:
+        line["wire256"] = wire256_legs(args, log)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(prob, nb_sample=args.cpu_bands)
+        line["cpu_baseline"] = cpu_baseline_wire4000(log=log)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line))
