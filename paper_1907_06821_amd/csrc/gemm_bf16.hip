@@ -10,10 +10,11 @@
 // so that every MFMA operand fragment (8 consecutive k of one row) is one
 // 16-byte load.  Per H psi the wave functions are rounded once to BF16 planes
 // [nb][ldg], and the projection's reduction writes D . C directly as BF16
-// planes [nb][ldp].  Workgroup tiles span all bands of a call (up to 144), so
-// each table is read once per H psi; the band operand of each tile is staged
-// in LDS and shared by the four waves, the table fragments go straight from
-// memory into registers.  Rounding is to nearest even.
+// planes [nb][ldp].  Up to 144 bands, workgroup tiles span all bands of the
+// call, so each table is read once per H psi; beyond that, wide tiles of 256
+// bands (each wave 32 table rows by 128 bands) read it once per 256 bands.  The
+// band operand of each tile is staged in LDS and shared by the waves, the table
+// fragments go straight from memory into registers.  Rounding is to nearest even.
 #include "kernels.h"
 
 namespace pw {
@@ -301,6 +302,207 @@ __global__ __launch_bounds__(NW * 64) void backproj16(int N, int J, int64_t ldp,
 }
 
 // ---------------------------------------------------------------------------
+// Wide band blocks (calls of more than MAXNB bands).  A workgroup of WM x WN waves
+// covers WM*RB*16 table rows (projection) or plane waves (back-projection) by
+// WN*NBLK*16 = 256 bands; each wave takes RB row blocks by NBLK band blocks, so a
+// band fragment read from LDS feeds RB complex products and a table fragment
+// (straight from memory into registers) NBLK of them.  The table is read once per
+// 256 bands (four times for 1024 bands, where 128-band chunks read it eight
+// times), and every LDS read feeds twice the matrix work of the narrow kernels.
+// KW-deep stages; the next stage's table fragments and band pieces are loaded
+// into registers while the current one is multiplied.
+// ---------------------------------------------------------------------------
+constexpr int KW = 32;           // k-depth per LDS stage of the wide kernels
+constexpr int LPW = KW + 8;      // padded LDS row (80 bytes: 16 rows hit 16 distinct 4-bank groups)
+
+template <int RB, int NBLK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const uint16_t *__restrict__ Br,
+                                                          const uint16_t *__restrict__ Bi, int64_t ldg,
+                                                          const uint16_t *__restrict__ Pr,
+                                                          const uint16_t *__restrict__ Pi, int kchunk,
+                                                          float2 *__restrict__ partial) {
+    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW;
+    constexpr int PPT = NB * (KW / 8) / NT;              // 16-byte band pieces per thread and plane
+    static_assert(NB * (KW / 8) % NT == 0, "band pieces must divide evenly over the threads");
+    __shared__ __attribute__((aligned(16))) uint16_t sPr[NB][LPW], sPi[NB][LPW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int m0 = blockIdx.x * (WM * RB * 16) + wm * RB * 16;
+    const int n0 = blockIdx.y * NB;
+    const int s = blockIdx.z;
+    const int kbeg = s * kchunk;
+    const int kend = (int)min((int64_t)kbeg + kchunk, ldg);
+    v4f ar_[RB][NBLK], ai_[RB][NBLK];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) { ar_[r][j] = v4f{0, 0, 0, 0}; ai_[r][j] = v4f{0, 0, 0, 0}; }
+    int64_t rowA[RB];
+    bool okA[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        rowA[r] = m0 + r * 16 + (lane & 15);
+        okA[r] = rowA[r] < M;
+    }
+    bf16x8 fa_r[RB], fa_i[RB];
+    uint4 pr_n[PPT], pi_n[PPT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int64_t off = rowA[r] * ldg + k0 + 8 * (lane >> 4);
+            fa_r[r] = okA[r] ? load8(Br + off) : zero8();
+            fa_i[r] = okA[r] ? load8(Bi + off) : zero8();
+        }
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
+            const int band = n0 + r;
+            pr_n[t] = make_uint4(0, 0, 0, 0);
+            pi_n[t] = make_uint4(0, 0, 0, 0);
+            if (band < N) {
+                pr_n[t] = *reinterpret_cast<const uint4 *>(Pr + (int64_t)band * ldg + k0 + c8);
+                pi_n[t] = *reinterpret_cast<const uint4 *>(Pi + (int64_t)band * ldg + k0 + c8);
+            }
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += KW) {
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
+            *reinterpret_cast<uint4 *>(&sPr[r][c8]) = pr_n[t];
+            *reinterpret_cast<uint4 *>(&sPi[r][c8]) = pi_n[t];
+        }
+        bf16x8 ca_r[RB], ca_i[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) { ca_r[r] = fa_r[r]; ca_i[r] = neg8(fa_i[r]); }
+        bf16x8 cb_i[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) cb_i[r] = fa_i[r];
+        __syncthreads();
+        if (k0 + KW < kend) fetch(k0 + KW);
+        const int kk = 8 * (lane >> 4);
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) {
+            const int row = wn * NBW + j * 16 + (lane & 15);
+            const bf16x8 br = load8(&sPr[row][kk]), bi = load8(&sPi[row][kk]);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
+                ar_[r][j] = mfma_bf16(ca_r[r], br, ar_[r][j]);
+                ar_[r][j] = mfma_bf16(cb_i[r], bi, ar_[r][j]);
+                ai_[r][j] = mfma_bf16(ca_r[r], bi, ai_[r][j]);
+                ai_[r][j] = mfma_bf16(ca_i[r], br, ai_[r][j]);
+            }
+        }
+        __syncthreads();
+    }
+    float2 *P = partial + (int64_t)s * M * N;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + r * 16 + 4 * (lane >> 4) + v;
+                const int col = n0 + wn * NBW + j * 16 + (lane & 15);
+                if (row < M && col < N) P[(int64_t)col * M + row] = make_float2(ar_[r][j][v], ai_[r][j][v]);
+            }
+}
+
+template <int GB, int NBLK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int64_t ldp,
+                                                              const uint16_t *__restrict__ Wr,
+                                                              const uint16_t *__restrict__ Wi,
+                                                              const uint16_t *__restrict__ Tr,
+                                                              const uint16_t *__restrict__ Ti,
+                                                              float2 *__restrict__ out, int64_t ldo) {
+    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW;
+    constexpr int WPT = NB * (KW / 8) / NT;              // 16-byte W pieces per thread and plane
+    static_assert(NB * (KW / 8) % NT == 0, "W pieces must divide evenly over the threads");
+    __shared__ __attribute__((aligned(16))) uint16_t sWr[NB][LPW], sWi[NB][LPW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int b0 = blockIdx.y * NB;
+    int64_t gcol[GB];
+    bool okB[GB];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+        gcol[q] = (int64_t)blockIdx.x * (WM * GB * 16) + wm * GB * 16 + q * 16 + (lane & 15);
+        okB[q] = gcol[q] < J;
+    }
+    v4f ar_[NBLK][GB], ai_[NBLK][GB];
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int q = 0; q < GB; ++q) { ar_[i][q] = v4f{0, 0, 0, 0}; ai_[i][q] = v4f{0, 0, 0, 0}; }
+    bf16x8 fb_r[GB], fb_i[GB];
+    uint4 wr_n[WPT], wi_n[WPT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+            const int64_t off = gcol[q] * ldp + k0 + 8 * (lane >> 4);
+            fb_r[q] = okB[q] ? load8(Tr + off) : zero8();
+            fb_i[q] = okB[q] ? load8(Ti + off) : zero8();
+        }
+#pragma unroll
+        for (int t = 0; t < WPT; ++t) {
+            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
+            const int band = b0 + r;
+            wr_n[t] = make_uint4(0, 0, 0, 0);
+            wi_n[t] = make_uint4(0, 0, 0, 0);
+            if (band < N) {
+                wr_n[t] = *reinterpret_cast<const uint4 *>(Wr + (int64_t)band * ldp + k0 + c8);
+                wi_n[t] = *reinterpret_cast<const uint4 *>(Wi + (int64_t)band * ldp + k0 + c8);
+            }
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < ldp; k0 += KW) {
+#pragma unroll
+        for (int t = 0; t < WPT; ++t) {
+            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
+            *reinterpret_cast<uint4 *>(&sWr[r][c8]) = wr_n[t];
+            *reinterpret_cast<uint4 *>(&sWi[r][c8]) = wi_n[t];
+        }
+        bf16x8 cb_r[GB], cb_i[GB];
+#pragma unroll
+        for (int q = 0; q < GB; ++q) { cb_r[q] = fb_r[q]; cb_i[q] = fb_i[q]; }
+        __syncthreads();
+        if (k0 + KW < ldp) fetch(k0 + KW);
+        const int kk = 8 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < NBLK; ++i) {
+            const int row = wn * NBW + i * 16 + (lane & 15);
+            const bf16x8 wr = load8(&sWr[row][kk]), wi = load8(&sWi[row][kk]);
+            const bf16x8 nwi = neg8(wi);
+#pragma unroll
+            for (int q = 0; q < GB; ++q) {
+                // W beta: re = wr br - wi bi, im = wr bi + wi br
+                ar_[i][q] = mfma_bf16(wr, cb_r[q], ar_[i][q]);
+                ar_[i][q] = mfma_bf16(nwi, cb_i[q], ar_[i][q]);
+                ai_[i][q] = mfma_bf16(wr, cb_i[q], ai_[i][q]);
+                ai_[i][q] = mfma_bf16(wi, cb_r[q], ai_[i][q]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int q = 0; q < GB; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = b0 + wn * NBW + i * 16 + 4 * (lane >> 4) + v;
+                if (b < N && okB[q]) {
+                    float2 *o = out + (int64_t)b * ldo + gcol[q];
+                    const float2 old = *o;
+                    *o = make_float2(old.x + ar_[i][q][v], old.y + ai_[i][q][v]);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static int band_blocks(int nb) { return nb <= 64 ? 4 : nb <= 128 ? 8 : 9; }
@@ -315,7 +517,20 @@ static int proj_splits(int M, int64_t ldg) {
     return std::max(1, std::min(s, maxs));
 }
 
+// wide kernels: 128 table rows (or plane waves) by 256 bands per workgroup
+constexpr int kWideRB = 2, kWideNBLK = 8, kWideWM = 4, kWideWN = 2;
+constexpr int kWideRows = kWideWM * kWideRB * 16, kWideBands = kWideWN * kWideNBLK * 16;
+
+// split-K of the wide projection: about 512 workgroups, at least four stages per split
+static int wide_splits(int M, int N, int64_t ldg) {
+    const int tiles = ((M + kWideRows - 1) / kWideRows) * ((N + kWideBands - 1) / kWideBands);
+    const int s = (512 + tiles - 1) / tiles;
+    const int maxs = (int)std::max<int64_t>(1, ldg / (4 * KW));
+    return std::max(1, std::min(s, maxs));
+}
+
 size_t cnt_partial_bytes(int M, int N, int K) {
+    if (N > MAXNB) return (size_t)wide_splits(M, N, bf16_ld(K)) * M * N * sizeof(float2);
     return (size_t)proj_splits(M, bf16_ld(K)) * M * band_chunk(N) * sizeof(float2);
 }
 
@@ -366,6 +581,22 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
     hipLaunchKernelGGL(k_c64_to_planes, dim3((unsigned)((ldg + 255) / 256), nb), dim3(256), 0, st, nb, npw,
                        (const float2 *)psi, ld, ldg, S.Pr, S.Pi);
     PW_LAUNCH_CHECK();
+    if (nb > MAXNB) {
+        // every band in one launch of 128 x 256 tiles, split over the plane waves
+        const int ns = wide_splits(nproj, nb, ldg);
+        int kchunk = (int)((ldg + ns - 1) / ns);
+        kchunk = (kchunk + KW - 1) / KW * KW;
+        const int nsplit = (int)((ldg + kchunk - 1) / kchunk);
+        dim3 grid((nproj + kWideRows - 1) / kWideRows, (nb + kWideBands - 1) / kWideBands, nsplit);
+        hipLaunchKernelGGL((proj_wide<kWideRB, kWideNBLK, kWideWM, kWideWN>), grid, dim3(64 * kWideWM * kWideWN), 0,
+                           st, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, kchunk, (float2 *)partial);
+        PW_LAUNCH_CHECK();
+        const int64_t tot = (int64_t)nb * ldp;
+        hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
+                           (const float2 *)partial, d, ldp, S.Wr, S.Wi);
+        PW_LAUNCH_CHECK();
+        return;
+    }
     for (int b0 = 0; b0 < nb; b0 += band_chunk(nb)) {
         const int n = std::min(band_chunk(nb), nb - b0);
         const uint16_t *Pr = S.Pr + (int64_t)b0 * ldg, *Pi = S.Pi + (int64_t)b0 * ldg;
@@ -389,6 +620,13 @@ void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT1
     const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
     const uint16_t *Tr = (const uint16_t *)betaT16, *Ti = Tr + ldg * ldp;
     Bf16Scratch S(const_cast<void *>(scratch), max_bands, ldg, ldp);
+    if (nb > MAXNB) {
+        dim3 grid((unsigned)((npw + kWideRows - 1) / kWideRows), (nb + kWideBands - 1) / kWideBands);
+        hipLaunchKernelGGL((backproj_wide<kWideRB, kWideNBLK, kWideWM, kWideWN>), grid, dim3(64 * kWideWM * kWideWN),
+                           0, st, nb, npw, ldp, S.Wr, S.Wi, Tr, Ti, (float2 *)out, ldo);
+        PW_LAUNCH_CHECK();
+        return;
+    }
     for (int b0 = 0; b0 < nb; b0 += band_chunk(nb)) {
         const int n = std::min(band_chunk(nb), nb - b0);
         const uint16_t *Wr = S.Wr + (int64_t)b0 * ldp, *Wi = S.Wi + (int64_t)b0 * ldp;
