@@ -212,6 +212,17 @@ pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *
                         int32_t *sweeps, void *stream);
 pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void *stream);
 
+/* pw_dense_eigh for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * eigensolver, kernels and results, with its work memory in a device array
+ * inside the library (about 8.4 MB on each GPU it runs on, held until the
+ * process ends) instead of a per-call allocation, so n <= 512 (PW_EINVAL above).
+ * The array keeps the last call's contents and every call on one GPU shares it:
+ * calls that overlap on one GPU (other streams or threads) race.  Arguments,
+ * outputs and errors as pw_dense_eigh; synchronises `stream`. */
+pw_status pw_dense_eigh_noalloc(int32_t n, const void *A, int64_t lda, double *w, void *R, int32_t key, double ref,
+                                int32_t *sweeps, void *stream);
+
 /* Solver options. */
 typedef struct {
     double tol;           /* stop when max_i Delta_i <= tol (Ha); paper's accuracy 1e-6 */

@@ -31,7 +31,7 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_mlp_loss_grad", "pw_mlp_adam", "pw_mlp_train", "pw_profile_begin",
            "pw_profile_end", "pw_last_error", "pw_batch_solve", "pw_ctx_autotune", "pw_ctx_fft_choose",
            "pw_lin_opts_default", "pw_folded_linear_solve", "pw_cheb_filter", "pw_chebfd_step",
-           "pw_spectral_bounds", "pw_kinterp", "pw_ctx_set_otf_atoms")
+           "pw_spectral_bounds", "pw_kinterp", "pw_ctx_set_otf_atoms", "pw_dense_eigh_noalloc")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection", "block_rotate3",
               "block_gram", "block_rotate")
 PW_PROF_NKINDS = 8
@@ -115,6 +115,7 @@ def lib():
             "pw_folded_cg_solve": [vp, dbl, i32, vp, i64, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(pw_cg_opts),
                                    C.POINTER(pw_cg_stats), vp],
             "pw_dense_eigh": [i32, vp, i64, vp, vp, i32, dbl, C.POINTER(i32), vp],
+            "pw_dense_eigh_noalloc": [i32, vp, i64, vp, vp, i32, dbl, C.POINTER(i32), vp],
             "pw_dense_chol_inv": [i32, vp, i64, vp, vp],
             "pw_mlp_set": [vp, vp],
             "pw_mlp_forward": [i32, i32, vp, vp, dbl, dbl, vp, vp, vp],
@@ -317,9 +318,10 @@ def orthonormalize(ctx, psi, stream=None):
     return psi
 
 
-def dense_eigh(a, key=0, ref=0.0, stream=None):
+def dense_eigh(a, key=0, ref=0.0, stream=None, noalloc=False):
     """Hermitian eigensolver on a [n, n] complex128 device matrix: (w, R, sweeps),
-    rows of R are eigenvectors (w ordered by key: 0 ascending, 1 by |w - ref|)."""
+    rows of R are eigenvectors (w ordered by key: 0 ascending, 1 by |w - ref|).
+    noalloc: call pw_dense_eigh_noalloc (library-held work memory, n <= 512)."""
     import torch
     n = a.shape[0]
     if a.dtype != torch.complex128 or not a.is_cuda or a.shape != (n, n) or a.stride(1) != 1:
@@ -327,8 +329,9 @@ def dense_eigh(a, key=0, ref=0.0, stream=None):
     w = torch.empty(n, dtype=torch.float64, device=a.device)
     r = torch.empty((n, n), dtype=torch.complex128, device=a.device)
     sw = C.c_int32()
-    _check(lib().pw_dense_eigh(n, C.c_void_p(a.data_ptr()), a.stride(0), C.c_void_p(w.data_ptr()),
-                               C.c_void_p(r.data_ptr()), int(key), float(ref), C.byref(sw), _stream_ptr(stream)))
+    fn = lib().pw_dense_eigh_noalloc if noalloc else lib().pw_dense_eigh
+    _check(fn(n, C.c_void_p(a.data_ptr()), a.stride(0), C.c_void_p(w.data_ptr()), C.c_void_p(r.data_ptr()),
+              int(key), float(ref), C.byref(sw), _stream_ptr(stream)))
     return w, r, sw.value
 
 

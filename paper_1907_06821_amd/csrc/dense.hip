@@ -9,10 +9,11 @@
 //                        Psi' = R . Psi.
 // The factorisations run as one workgroup; they are O(N^3) on N x N matrices and
 // off the O(N^2 npw) critical path.
-#include "common.h"
+#include "kernels.h"
 
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
 
 namespace pw {
 
@@ -1210,4 +1211,67 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
     PW_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// The eigensolver without allocation (pw_dense_eigh_noalloc): its work memory is
+// the file-scope device array `scratch`, one copy per GPU for the life of the
+// process.  In host code the array's name only stands for the symbol, so host
+// code never hands it to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device current
+// and kept per device.  Sized for N <= kNoAllocMaxN: the eigensolver's work, then
+// 256 bytes for the QL iteration count.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocMaxN = 512;
+constexpr size_t kNoAllocWork = (((size_t)kNoAllocMaxN * (kNoAllocMaxN - 1) / 2 + kNoAllocMaxN) * sizeof(double2) +
+                                 (size_t)24 * kNoAllocMaxN * kNoAllocMaxN + (size_t)4 * kNoAllocMaxN + 256 + 255) /
+                                256 * 256;
+constexpr size_t kScratchBytes = kNoAllocWork + 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// device address of `scratch` on the current device (looked up on its first use there)
+static void *scratch_on_current_device() {
+    int dev = 0;
+    PW_HIP(hipGetDevice(&dev));
+    PW_CHECK(dev >= 0 && dev < kMaxDevices, PW_EUNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        PW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        PW_CHECK(ptr != nullptr, PW_EHIP, "no device address for the eigensolver scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace pw
+
+extern "C" pw_status pw_dense_eigh_noalloc(int32_t n, const void *A, int64_t lda, double *w, void *R, int32_t key,
+                                           double ref, int32_t *sweeps, void *stream) {
+    try {
+        PW_CHECK(n >= 1 && n <= pw::kNoAllocMaxN && lda >= n && A && w && R, PW_EINVAL,
+                 "bad pw_dense_eigh_noalloc arguments (1 <= n <= %d)", pw::kNoAllocMaxN);
+        PW_CHECK(key == 0 || key == 1, PW_EINVAL, "key must be 0 or 1");
+        PW_CHECK(pw::dense_eigh_work_bytes(n) <= pw::kNoAllocWork, PW_EUNSUPPORTED, "scratch too small for n = %d", n);
+        hipStream_t st = (hipStream_t)stream;
+        char *base = (char *)pw::scratch_on_current_device();
+        int *info = (int *)(base + pw::kNoAllocWork);
+        pw::fill_zero(info, 16, st);                 // the array keeps the last call's contents
+        pw::dense_eigh(n, A, lda, base, w, R, key, ref, info, st);
+        int h = 0;
+        PW_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+        PW_HIP(hipStreamSynchronize(st));
+        if (sweeps) *sweeps = h;
+        PW_CHECK(h >= 0, PW_ENOCONV, "tridiagonal QL iteration did not converge");
+        return PW_OK;
+    } catch (const pw::Fail &f) {
+        return f.st;
+    } catch (...) {
+        pw::set_error("unexpected exception in pw_dense_eigh_noalloc");
+        return PW_EINVAL;
+    }
+}
