@@ -194,7 +194,7 @@ pw_status pw_ctx_autotune(pw_ctx *ctx, pw_dtype dtype, int32_t nb, int32_t reps,
 pw_status pw_ctx_fft_choose(pw_ctx *ctx, pw_dtype dtype, const pw_fft_cand *cand);
 
 /* Small dense FP64 kernels of the block algebra, exposed for direct use and
- * testing (one workgroup each, n <= 1024; device pointers, complex128, row-major).
+ * testing (device pointers, complex128, row-major).
  *
  * pw_dense_eigh: eigen-decomposition of the Hermitian part of A (n x n, ld lda):
  *   w (device, n) eigenvalues ordered by key (0: ascending, 1: ascending
@@ -204,10 +204,15 @@ pw_status pw_ctx_fft_choose(pw_ctx *ctx, pw_dtype dtype, const pw_fft_cand *cand
  *   most 16 rows by implicit QL, rank-one merges); sweeps (host, optional) gets
  *   the largest QL iteration count of one leaf eigenvalue, and PW_ENOCONV is
  *   returned if one exceeds 60.  Synchronises.
- * pw_dense_chol_inv: S = L L^H for Hermitian positive definite S (n x n, lds),
- *   T = conj(L^{-1}) (n x n) so that Psi' = T . Psi has Psi'^H Psi' = I when
- *   S = Psi^H Psi.  Returns PW_ENOTPD if a pivot is not positive.  Synchronises.
+ * pw_dense_chol_inv: S = L L^H for Hermitian positive definite S (n x n, lds,
+ *   n <= 8192), T = conj(L^{-1}) (n x n, zero above the diagonal) so that
+ *   Psi' = T . Psi has Psi'^H Psi' = I when S = Psi^H Psi.  n <= 136: one
+ *   workgroup with the packed triangle in LDS; larger n: blocked by 128 (that
+ *   kernel on the diagonal blocks, matrix-core products for the panels, the
+ *   trailing updates and the inverse).  Returns PW_ENOTPD, naming the first
+ *   pivot that is not positive.  Synchronises.
  * Both are the Rayleigh-Ritz and Gram/Cholesky steps of the solver. */
+/* pw_dense_eigh: n <= 1024, one workgroup for the reduction and the divide and conquer. */
 pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *R, int32_t key, double ref,
                         int32_t *sweeps, void *stream);
 pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void *stream);

@@ -31,10 +31,19 @@ import numpy as np
 from .hamiltonian import potential_fourier
 
 
+def work_matrix(n):
+    """An [n, n] complex128 torch CPU tensor in column-major order: LAPACK's
+    factorisation then works on it in place (a row-major one is copied first)."""
+    import torch
+    return torch.empty_strided((n, n), (1, n), dtype=torch.complex128)
+
+
 def dense_shifted_into(out, miller, kin, vgrid, beta=None, dproj=None, sigma=0.0, rows=512):
     """Write H - sigma I (the dense matrix of oracle.hamiltonian.dense_hamiltonian)
-    into `out`, a C-ordered [npw, npw] complex128 array (numpy or torch CPU),
-    `rows` rows at a time so that no npw x npw temporary is formed."""
+    into `out`, an [npw, npw] complex128 array (numpy, or a torch CPU tensor of
+    either memory order), `rows` rows at a time so that no npw x npw temporary
+    is formed.  A column-major torch tensor receives the conjugate transpose of
+    each row block as a block of columns (H is Hermitian), a contiguous write."""
     miller = np.asarray(miller)
     grid = np.asarray(np.asarray(vgrid).shape)
     vt = potential_fourier(vgrid).ravel()
@@ -54,6 +63,9 @@ def dense_shifted_into(out, miller, kin, vgrid, beta=None, dproj=None, sigma=0.0
             blk += bt[r0:r1] @ bconj
         if isinstance(out, np.ndarray):
             out[r0:r1] = blk
+        elif out.stride(0) == 1:
+            import torch
+            out[:, r0:r1] = torch.from_numpy(np.ascontiguousarray(blk.conj().T))
         else:
             import torch
             out[r0:r1] = torch.from_numpy(blk)
@@ -105,9 +117,8 @@ def negative_count(ld, piv):
 def count_below(op, sigma, work=None):
     """Number of eigenvalues of the operator's dense H strictly below sigma
     (Sylvester inertia of H - sigma I).  `work`: optional preallocated torch
-    complex128 [npw, npw] array that is overwritten."""
-    import torch
-    m = work if work is not None else torch.empty((op.npw, op.npw), dtype=torch.complex128)
+    complex128 [npw, npw] array (work_matrix) that is overwritten."""
+    m = work if work is not None else work_matrix(op.npw)
     dense_shifted_into(m, op.miller, op.kin, op.vgrid, op.beta, op.dproj, sigma)
     ld, piv = ldl_inplace(m)
     return negative_count(ld, piv)
@@ -123,7 +134,7 @@ def nearest_by_shift_invert(op, e_ref, k, work=None, tol=1e-13, ncv=None, v0_see
     import torch
     from scipy.sparse.linalg import LinearOperator, eigsh
     n = op.npw
-    m = work if work is not None else torch.empty((n, n), dtype=torch.complex128)
+    m = work if work is not None else work_matrix(n)
     dense_shifted_into(m, op.miller, op.kin, op.vgrid, op.beta, op.dproj, e_ref)
     if log:
         log("dense H - E I built")

@@ -159,16 +159,21 @@ void hpsi_any(pw_ctx *ctx, pw_dtype dt, int nb, const void *psi, int64_t ld, voi
     }
 }
 
+// pw_orthonormalize's small work: S and T (nb x nb each), then the Cholesky work
+static size_t ortho_small_bytes(int nb) {
+    return ((size_t)2 * nb * nb * 16 + chol_inv_work_bytes(nb) + 255) / 256 * 256;
+}
+
 // Psi <- Psi L^{-H} for a complex128 block, using ws (>= nb*npw complex128) as scratch
 void orthonormalize_c128(pw_ctx *ctx, int nb, void *psi, int64_t ld, void *ws, void *small, int *d_status,
                          hipStream_t st) {
     const int npw = ctx->basis.npw;
     double2 *S = (double2 *)small;
-    double2 *W = S + (size_t)nb * nb;
-    double2 *T = W + (size_t)nb * nb;
+    double2 *T = S + (size_t)nb * nb;
+    double2 *W = T + (size_t)nb * nb;     // chol_inv_work_bytes(nb)
     zgemm_nt(nb, nb, npw, true, psi, ld, psi, ld, 1.0, nullptr, 0.0, S, nb, false, ctx->d_partial.p, st);
     chol_inv(nb, S, nb, W, T, d_status, st);
-    zgemm_nn_launch(nb, npw, nb, T, nb, psi, ld, 1.0, 0.0, ws, npw, st, false, ctx->rot_tune.get(nb));
+    zgemm_nn_launch(nb, npw, nb, T, nb, psi, ld, 1.0, 0.0, ws, npw, st, false, ctx->rot_tune.get(nb), true);
     copy_block(nb, npw, ws, npw, psi, ld, st);
 }
 
@@ -357,7 +362,7 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
     // pw_orthonormalize's block scratch: complex128 contexts with a stored table only (a
     // PW_PREP_C128_OTF context allocates it on its first pw_orthonormalize call)
     if ((flags & PW_PREP_C128) && !c->beta_otf) c->d_ortho_ws.alloc((size_t)max_bands * b.npw * 16);
-    c->d_ortho_small.alloc((size_t)3 * max_bands * max_bands * 16 + 256);
+    c->d_ortho_small.alloc(ortho_small_bytes(max_bands) + 256);
     acct += c->d_cols.bytes + c->d_proj.bytes + c->d_partial.bytes + c->d_ortho_ws.bytes + c->d_ortho_small.bytes;
     c->device_bytes = acct;
     PW_HIP(hipStreamSynchronize(st));
@@ -522,11 +527,12 @@ pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *
 
 pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void *stream) {
     PW_API_BEGIN
-    PW_CHECK(n >= 1 && n <= 1024 && lds >= n && S && T, PW_EINVAL, "bad pw_dense_chol_inv arguments");
+    PW_CHECK(n >= 1 && n <= 8192 && lds >= n && S && T, PW_EINVAL, "bad pw_dense_chol_inv arguments");
     hipStream_t st = (hipStream_t)stream;
     DevBuf work;
-    work.alloc((size_t)n * n * 16 + 256);
-    int *status = (int *)((char *)work.p + (size_t)n * n * 16);
+    const size_t wb = (chol_inv_work_bytes(n) + 255) / 256 * 256;
+    work.alloc(wb + 256);
+    int *status = (int *)((char *)work.p + wb);
     fill_zero(status, 16, st);
     chol_inv(n, S, lds, work.p, T, status, st);
     int h = 0;
@@ -670,7 +676,7 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
     if (nb == 0) return PW_OK;
     hipStream_t st = (hipStream_t)stream;
     if (!ctx->d_ortho_ws.p) ctx->d_ortho_ws.alloc((size_t)ctx->max_bands * ctx->basis.npw * 16);
-    int *d_status = (int *)((char *)ctx->d_ortho_small.p + (size_t)3 * ctx->max_bands * ctx->max_bands * 16);
+    int *d_status = (int *)((char *)ctx->d_ortho_small.p + ortho_small_bytes(ctx->max_bands));
     fill_zero(d_status, 16, st);
     orthonormalize_c128(ctx, nb, psi, ld, ctx->d_ortho_ws.p, ctx->d_ortho_small.p, d_status, st);
     int status = 0;

@@ -25,74 +25,10 @@ __device__ inline double2 zfma(double2 a, double2 b, double2 c) {   // a b + c
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky + triangular inverse.  W: work copy of S (N x N, ld N), overwritten
-// with L in its lower triangle.  T (N x N): conj(L^{-1}).  status[0] = 0 ok,
-// j + 1 if pivot j is not positive.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void chol_inv_kernel(int N, const double2 *__restrict__ S, int64_t lds,
-                                                        double2 *__restrict__ W, double2 *__restrict__ T,
-                                                        int *__restrict__ status) {
-    __shared__ double piv;
-    __shared__ int bad;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < N * N; e += nt) {
-        const int i = e / N, k = e % N;
-        W[e] = S[(int64_t)i * lds + k];
-    }
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    for (int j = 0; j < N; ++j) {
-        if (tid == 0) {
-            const double d = W[(int64_t)j * N + j].x;
-            if (!(d > 0.0) || !isfinite(d)) { bad = j + 1; piv = 1.0; }
-            else piv = sqrt(d);
-        }
-        __syncthreads();
-        if (bad) break;
-        const double inv = 1.0 / piv;
-        for (int i = j + 1 + tid; i < N; i += nt) {
-            double2 v = W[(int64_t)i * N + j];
-            W[(int64_t)i * N + j] = make_double2(v.x * inv, v.y * inv);
-        }
-        if (tid == 0) W[(int64_t)j * N + j] = make_double2(piv, 0.0);
-        __syncthreads();
-        const int m = N - j - 1;
-        for (int e = tid; e < m * m; e += nt) {
-            const int i = j + 1 + e / m, k = j + 1 + e % m;
-            if (k <= i) {
-                const double2 lij = W[(int64_t)i * N + j], lkj = W[(int64_t)k * N + j];
-                const double2 u = zmulc(lij, lkj);
-                double2 w = W[(int64_t)i * N + k];
-                W[(int64_t)i * N + k] = make_double2(w.x - u.x, w.y - u.y);
-            }
-        }
-        __syncthreads();
-    }
-    if (tid == 0 && bad) status[0] = bad;   // sticky: callers clear it
-    if (bad) return;
-    // Linv by rows: Linv[i][c] = (delta_ic - sum_{c<=k<i} L[i][k] Linv[k][c]) / L[i][i]; stored conj in T
-    for (int e = tid; e < N * N; e += nt) T[e] = make_double2(0.0, 0.0);
-    __syncthreads();
-    for (int i = 0; i < N; ++i) {
-        const double dinv = 1.0 / W[(int64_t)i * N + i].x;
-        for (int c = tid; c <= i; c += nt) {
-            double re = (c == i) ? 1.0 : 0.0, im = 0.0;
-            for (int k = c; k < i; ++k) {
-                const double2 l = W[(int64_t)i * N + k];
-                const double2 x = zconj(T[(int64_t)k * N + c]);   // Linv[k][c]
-                re -= l.x * x.x - l.y * x.y;
-                im -= l.x * x.y + l.y * x.x;
-            }
-            T[(int64_t)i * N + c] = make_double2(re * dinv, -im * dinv);   // conj(Linv[i][c])
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Same result for N <= 128 with the packed lower triangle held in LDS
-// (N (N + 1) / 2 complex values, 132 KiB at N = 128): Cholesky by columns, then
-// L^{-1} in place from the last column backwards.
+// Cholesky + triangular inverse: S = L L^H, T = conj(L^{-1}) (N x N, zero above
+// the diagonal); status[0] = j + 1 for the first pivot j that is not positive
+// (callers clear it).  N <= kLdsMaxN: one workgroup (chol_inv_lds_kernel);
+// larger N: blocked, below.
 // ---------------------------------------------------------------------------
 __device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
@@ -117,7 +53,8 @@ __device__ inline void tri_rc(int q, int &i, int &k) {
 // rows of 16 (nine barrier rounds at N = 136 instead of two per column).
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
-                                                          double2 *__restrict__ T, int *__restrict__ status) {
+                                                          double2 *__restrict__ T, int64_t ldt, int pivot_base,
+                                                          int *__restrict__ status) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);
     __shared__ double sd[kLdsMaxN];
@@ -134,7 +71,7 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
     for (int j = 0; j < N; ++j) {
         const double d = L[tri(j, j)].x;                 // the same value in every thread
         if (!(d > 0.0) || !isfinite(d)) {
-            if (tid == 0) status[0] = j + 1;
+            if (tid == 0 && status[0] == 0) status[0] = pivot_base + j + 1;   // the first failure is kept
             return;
         }
         const double rd = 1.0 / d;
@@ -239,7 +176,7 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
     for (int e = tid; e < N * N; e += NT) {
         const int i = e / N, c = e % N;
         const double2 v = c <= i ? L[tri(i, c)] : make_double2(0.0, 0.0);
-        T[e] = make_double2(v.x, -v.y);
+        T[(int64_t)i * ldt + c] = make_double2(v.x, -v.y);
     }
 }
 
@@ -1157,19 +1094,100 @@ void lds_limit(const void *fn, size_t bytes, size_t &have) {
 constexpr int kBackNW = 4;
 }  // namespace
 
-void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t st) {
-    if (N <= kLdsMaxN) {
-        PW_CHECK(N > 0 && N < 4096, PW_EINVAL, "bad Cholesky size");   // inverse keeps one band per thread
-        const size_t bytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
-        static size_t attr_bytes = 64 * 1024;   // default dynamic LDS limit
-        lds_limit(reinterpret_cast<const void *>(chol_inv_lds_kernel<1024>), bytes, attr_bytes);
-        hipLaunchKernelGGL(chol_inv_lds_kernel<1024>, dim3(1), dim3(1024), bytes, st, N, (const double2 *)S, lds,
-                           (double2 *)T, status);
-    } else {
-        hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, N, (const double2 *)S, lds,
-                           (double2 *)work, (double2 *)T, status);
+// ---------------------------------------------------------------------------
+// Blocked Cholesky and inverse for N > kLdsMaxN (right-looking, blocks of kCholB):
+// for each diagonal block, the one-workgroup LDS kernel factors it and writes
+// T_kk = conj(L_kk^-1) into T's diagonal block; the panel below becomes
+// L_ik = A_ik L_kk^-H = A_ik T_kk^T and the trailing matrix A -= L_p L_p^H, both
+// multi-workgroup FP64 MFMA products.  Then T by block rows (T = conj(X),
+// X = L^-1): T_ij = -T_ii sum_{m = j}^{i-1} conj(L_im) T_mj, i.e. one product
+// with T's rows above and one with T_ii.  Work: W (N x N) holding L, then the
+// transposed diagonal inverse (B x B), the panel (N x B) and its conjugate
+// transpose (B x N), reused for conj(L)'s block row and the sums in the inverse.
+// ---------------------------------------------------------------------------
+constexpr int kCholB = 128;
+
+__global__ void k_transpose_block(int rows, int cols, const double2 *__restrict__ src, int64_t lds,
+                                  double2 *__restrict__ dst, int64_t ldd, int conjugate) {
+    __shared__ double2 tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+    for (int y = ty; y < 32; y += 8) {
+        const int r = r0 + y, c = c0 + tx;
+        if (r < rows && c < cols) tile[y][tx] = src[(int64_t)r * lds + c];
     }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int c = c0 + y, r = r0 + tx;
+        if (r < rows && c < cols) {
+            const double2 v = tile[tx][y];
+            dst[(int64_t)c * ldd + r] = conjugate ? make_double2(v.x, -v.y) : v;
+        }
+    }
+}
+
+__global__ void k_conj_copy(int rows, int cols, const double2 *__restrict__ src, int64_t lds,
+                            double2 *__restrict__ dst, int64_t ldd) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c < cols) {
+        const double2 v = src[(int64_t)r * lds + c];
+        dst[(int64_t)r * ldd + c] = make_double2(v.x, -v.y);
+    }
+}
+
+static void transpose_block(int rows, int cols, const double2 *src, int64_t lds, double2 *dst, int64_t ldd, bool cj,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_transpose_block, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, rows, cols, src,
+                       lds, dst, ldd, cj ? 1 : 0);
     PW_LAUNCH_CHECK();
+}
+
+size_t chol_inv_work_bytes(int N) {
+    if (N <= kLdsMaxN) return (size_t)N * N * sizeof(double2);
+    return ((size_t)N * N + (size_t)kCholB * kCholB + (size_t)2 * N * kCholB) * sizeof(double2);
+}
+
+static void chol_diag(int b, const double2 *A, int64_t lda, double2 *T, int64_t ldt, int pivot_base, int *status,
+                      hipStream_t st) {
+    const size_t bytes = (size_t)b * (b + 1) / 2 * sizeof(double2);
+    static size_t attr_bytes = 64 * 1024;   // default dynamic LDS limit
+    lds_limit(reinterpret_cast<const void *>(chol_inv_lds_kernel<1024>), bytes, attr_bytes);
+    hipLaunchKernelGGL(chol_inv_lds_kernel<1024>, dim3(1), dim3(1024), bytes, st, b, A, lda, T, ldt, pivot_base,
+                       status);
+    PW_LAUNCH_CHECK();
+}
+
+void chol_inv(int N, const void *S_, int64_t lds, void *work, void *T_, int *status, hipStream_t st) {
+    PW_CHECK(N > 0 && N <= 8192, PW_EINVAL, "bad Cholesky size %d", N);
+    const double2 *S = (const double2 *)S_;
+    double2 *T = (double2 *)T_;
+    if (N <= kLdsMaxN) {
+        chol_diag(N, S, lds, T, N, 0, status, st);
+        return;
+    }
+    constexpr int B = kCholB;
+    double2 *W = (double2 *)work;
+    double2 *TkT = W + (size_t)N * N, *P = TkT + (size_t)B * B, *PH = P + (size_t)N * B;
+    copy_block(N, N, S, lds, W, N, st);
+    fill_zero(T, (size_t)N * N * sizeof(double2), st);
+    for (int k0 = 0; k0 < N; k0 += B) {
+        const int b = std::min(B, N - k0), r0 = k0 + b, rows = N - r0;
+        chol_diag(b, W + (size_t)k0 * N + k0, N, T + (size_t)k0 * N + k0, N, k0, status, st);
+        if (rows == 0) break;
+        transpose_block(b, b, T + (size_t)k0 * N + k0, N, TkT, b, false, st);                // T_kk^T = L_kk^-H
+        zgemm_nn_launch(rows, b, b, W + (size_t)r0 * N + k0, N, TkT, b, 1.0, 0.0, P, b, st);  // L_ik
+        copy_block(rows, b, P, b, W + (size_t)r0 * N + k0, N, st);
+        transpose_block(rows, b, P, b, PH, rows, true, st);                                  // L_p^H
+        zgemm_nn_launch(rows, rows, b, P, b, PH, rows, -1.0, 1.0, W + (size_t)r0 * N + r0, N, st);
+    }
+    for (int i0 = B; i0 < N; i0 += B) {
+        const int b = std::min(B, N - i0);
+        hipLaunchKernelGGL(k_conj_copy, dim3((i0 + 255) / 256, b), dim3(256), 0, st, b, i0,
+                           (const double2 *)(W + (size_t)i0 * N), (int64_t)N, P, (int64_t)i0);
+        PW_LAUNCH_CHECK();
+        zgemm_nn_launch(b, i0, i0, P, i0, T, N, 1.0, 0.0, PH, i0, st);                         // sums
+        zgemm_nn_launch(b, i0, b, T + (size_t)i0 * N + i0, N, PH, i0, -1.0, 0.0, T + (size_t)i0 * N, N, st);
+    }
 }
 
 size_t dense_eigh_work_bytes(int N) {

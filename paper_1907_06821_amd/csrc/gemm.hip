@@ -184,7 +184,7 @@ struct NNBatch {
 template <int WM, int WJ, int BM, int BJ, int TAG, int KD>
 __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, int K, const double2 *__restrict__ W,
                                                                 int64_t ldw, NNBatch bt, int64_t ldx, double alpha,
-                                                                double beta, int64_t ldo) {
+                                                                double beta, int64_t ldo, int lower) {
     constexpr int NT = WM * WJ * 64;
     constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
     constexpr int LW = (TM * KD + NT - 1) / NT, LX = (KD * TJ + NT - 1) / NT;
@@ -225,13 +225,16 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
             if (e < KD * TJ) Xs[e / TJ][e % TJ] = rx[it];
         }
     };
-    if (K > 0) {
+    // lower: W is lower triangular (zero above the diagonal), so this row tile's
+    // products end at its last row; the skipped terms are exact zeros
+    const int kend = lower ? min(K, m0 + TM) : K;
+    if (kend > 0) {
         fetch(0);
         stash();
     }
     __syncthreads();
-    for (int k0 = 0; k0 < K; k0 += KD) {
-        const bool more = k0 + KD < K;
+    for (int k0 = 0; k0 < kend; k0 += KD) {
+        const bool more = k0 + KD < kend;
         if (more) fetch(k0 + KD);
 #pragma unroll
         for (int kq = 0; kq < KD / 4; ++kq) {
@@ -358,17 +361,17 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
 
 template <int WM, int WJ, int BM, int BJ, int KD = KT>
 static void nn_go(int nz, bool proj, hipStream_t st, int M, int J, int K, const void *W, int64_t ldw,
-                  const NNBatch &bt, int64_t ldx, double alpha, double beta, int64_t ldo) {
+                  const NNBatch &bt, int64_t ldx, double alpha, double beta, int64_t ldo, int lower) {
     static_assert(KD % 4 == 0, "LDS stage depth");
     constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
     dim3 grid((J + TJ - 1) / TJ, (M + TM - 1) / TM, nz);
     const dim3 blk(WM * WJ * 64);
     if (proj)
         hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 1, KD>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
-                           bt, ldx, alpha, beta, ldo);
+                           bt, ldx, alpha, beta, ldo, lower);
     else
         hipLaunchKernelGGL((zgemm_nn_kernel<WM, WJ, BM, BJ, 0, KD>), grid, blk, 0, st, M, J, K, (const double2 *)W, ldw,
-                           bt, ldx, alpha, beta, ldo);
+                           bt, ldx, alpha, beta, ldo, lower);
 }
 
 // Out_z (M x J, ldo) = alpha * W (M x K, ldw) . X_z (K x J, ldx) + beta * Out_z, z < nz <= 4
@@ -395,7 +398,9 @@ void nn_cfg_shape(int id, int &tm, int &tj, int &nthr) {
 }
 
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
-                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st, bool proj, int cfg) {
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t st, bool proj, int cfg,
+                    bool lower) {
+    const int lw = lower ? 1 : 0;
     if (M <= 0 || J <= 0 || nz <= 0) return;
     PW_CHECK(nz <= 4, PW_EINVAL, "at most 4 blocks per batched rotation");
     NNBatch bt{};
@@ -405,30 +410,30 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
     }
     if (cfg < 0) cfg = M <= 16 ? 12 : M <= 32 ? 13 : M <= 64 ? 0 : (M > 128 && M <= 144) ? 11 : 9;
     switch (cfg) {
-        case 0: nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 1: nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 2: nn_go<9, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 3: nn_go<4, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 4: nn_go<8, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 5: nn_go<4, 1, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 6: nn_go<2, 4, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 7: nn_go<9, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 8: nn_go<3, 2, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 9: nn_go<8, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 10: nn_go<3, 4, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 11: nn_go<3, 4, 3, 1, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 12: nn_go<1, 4, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
-        case 13: nn_go<2, 2, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo); break;
+        case 0: nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 1: nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 2: nn_go<9, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 3: nn_go<4, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 4: nn_go<8, 1, 1, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 5: nn_go<4, 1, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 6: nn_go<2, 4, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 7: nn_go<9, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 8: nn_go<3, 2, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 9: nn_go<8, 1, 1, 4, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 10: nn_go<3, 4, 3, 2, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 11: nn_go<3, 4, 3, 1, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 12: nn_go<1, 4, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        case 13: nn_go<2, 2, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
         default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
     }
     PW_LAUNCH_CHECK();
 }
 
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
-                     double beta, void *Out, int64_t ldo, hipStream_t st, bool proj, int cfg) {
+                     double beta, void *Out, int64_t ldo, hipStream_t st, bool proj, int cfg, bool lower) {
     const void *xs[1] = {X};
     void *os[1] = {Out};
-    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st, proj, cfg);
+    zgemm_nn_batch(1, M, J, K, W, ldw, xs, ldx, alpha, beta, os, ldo, st, proj, cfg, lower);
 }
 
 }  // namespace pw

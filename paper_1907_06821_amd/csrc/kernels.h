@@ -20,10 +20,13 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
 // NN GEMM tile configurations: cfg < 0 picks by M, else one of kNnCfgs (autotuner)
 constexpr int kNnCfgs = 14;
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr);
+// lower: W is lower triangular (zeros above its diagonal are skipped; same results)
 void zgemm_nn_launch(int M, int J, int K, const void *W, int64_t ldw, const void *X, int64_t ldx, double alpha,
-                     double beta, void *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1);
+                     double beta, void *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1,
+                     bool lower = false);
 void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, const void *const *X, int64_t ldx,
-                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1);
+                    double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1,
+                    bool lower = false);
 
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
 size_t cnt_partial_bytes(int M, int N, int K);
@@ -38,6 +41,8 @@ void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT1
                    int64_t ldo, hipStream_t st);
 
 // dense.hip
+// S = L L^H, T = conj(L^-1); work: chol_inv_work_bytes(N) device bytes
+size_t chol_inv_work_bytes(int N);
 void chol_inv(int N, const void *S, int64_t lds, void *work, void *T, int *status, hipStream_t);
 // Hermitian eigensolver (1 <= N <= 1024); work: dense_eigh_work_bytes(N) device bytes.
 size_t dense_eigh_work_bytes(int N);

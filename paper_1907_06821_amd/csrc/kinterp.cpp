@@ -73,12 +73,12 @@ pw_status pw_kinterp(pw_ctx *ctx1, pw_ctx *ctx2, pw_ctx *ctxk, double alpha, int
         DevBuf dmap, P2, mats, work, part, vec;
         dmap.alloc((size_t)(np1 + 2 * npk) * 4);
         P2.alloc((size_t)n * np1 * 16);
-        mats.alloc(8 * nn * 16 + 256);
-        work.alloc(dense_eigh_work_bytes(n));
+        mats.alloc(7 * nn * 16 + 256);
+        work.alloc(std::max(dense_eigh_work_bytes(n), chol_inv_work_bytes(n)));
         part.alloc(std::max(nt_partial_bytes(n, n, np1), nt_partial_bytes(n, n, n)));
         vec.alloc((size_t)3 * n * 8);
-        double2 *S = mats.as<double2>(), *G = S + nn, *W = G + nn, *T = W + nn, *U = T + nn, *Hk = U + nn,
-                *R = Hk + nn, *RU = R + nn;
+        double2 *S = mats.as<double2>(), *G = S + nn, *T = G + nn, *U = T + nn, *Hk = U + nn, *R = Hk + nn,
+                *RU = R + nn;
         int *d_status = (int *)(RU + nn);
         double *d_e1 = vec.as<double>(), *d_e2 = d_e1 + n, *d_lam = d_e2 + n;
         int32_t *d_m21 = dmap.as<int32_t>();
@@ -91,7 +91,7 @@ pw_status pw_kinterp(pw_ctx *ctx1, pw_ctx *ctx2, pw_ctx *ctxk, double alpha, int
         zgemm_nt(n, n, np1, true, P2.p, np1, psi1, ld1, 1.0, nullptr, 0.0, S, n, true, part.p, st);
         // Gram-Schmidt of the rows of S: G[a][b] = sum_j conj(S_aj) S_bj = L L^H, U = conj(L^-1) . S
         zgemm_nt(n, n, n, true, S, n, S, n, 1.0, nullptr, 0.0, G, n, false, part.p, st);
-        chol_inv(n, G, n, W, T, d_status, st);
+        chol_inv(n, G, n, work.p, T, d_status, st);   // the eigensolver's work is free here
         int chol = 0;
         PW_HIP(hipMemcpyAsync(&chol, d_status, sizeof(int), hipMemcpyDeviceToHost, st));
         PW_HIP(hipStreamSynchronize(st));

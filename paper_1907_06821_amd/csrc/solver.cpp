@@ -54,7 +54,8 @@ static Solver *solver_get(pw_ctx *ctx, int nb, bool mixed) {
         DevBuf *blocks[] = {&s->X, &s->Y, &s->AX, &s->P, &s->YP, &s->AP, &s->G, &s->Z, &s->T1, &s->T2, &s->T3};
         for (DevBuf *d : blocks) d->alloc(blk);
         const size_t nn = (size_t)s->nbmax * s->nbmax * 16;
-        s->small.alloc(4 * nn + dense_eigh_work_bytes(s->nbmax));
+        // Sm, Wm, Tm, Rm, then the eigensolver's work, which the Cholesky inverse borrows
+        s->small.alloc(4 * nn + std::max(dense_eigh_work_bytes(s->nbmax), chol_inv_work_bytes(s->nbmax)));
         s->vec.alloc((size_t)s->nbmax * 8 * 24);
         s->nsplit = band_splits(npw);
         s->red.alloc((size_t)4 * s->nbmax * s->nsplit * 8);
@@ -158,10 +159,10 @@ struct FcgRun {
         if (swap_free) copy_block(nb, npw, tmp, L, blk, L, st);
         else std::swap(blk, tmp);
     }
-    void rotate(const double2 *M, void *&blk, void *&tmp) {
+    void rotate(const double2 *M, void *&blk, void *&tmp, bool lower = false) {
         {
             ProfScope p(ctx, 7, st);
-            zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st, false, ctx->rot_tune.get(nb));
+            zgemm_nn_launch(nb, npw, nb, M, nb, blk, L, 1.0, 0.0, tmp, L, st, false, ctx->rot_tune.get(nb), lower);
         }
         settle(blk, tmp);
     }
@@ -170,13 +171,13 @@ struct FcgRun {
         ProfScope p(ctx, 6, st);
         zgemm_nt(nb, nb, npw, true, A, L, B, L, alpha, nullptr, 0.0, S, nb, trans, ctx->d_partial.p, st);
     }
-    // (X, Y, AX) <- M . (X, Y, AX) in one batched launch
-    void rotate3(const double2 *M) {
+    // (X, Y, AX) <- M . (X, Y, AX) in one batched launch (lower: M lower triangular)
+    void rotate3(const double2 *M, bool lower = false) {
         const void *in[3] = {X, Y, AX};
         void *out[3] = {T1, T2, T3};
         {
             ProfScope p(ctx, 5, st);
-            zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st, false, ctx->rot_tune.get(nb));
+            zgemm_nn_batch(3, nb, npw, nb, M, nb, in, L, 1.0, 0.0, out, L, st, false, ctx->rot_tune.get(nb), lower);
         }
         settle(X, T1);
         settle(Y, T2);
@@ -184,8 +185,8 @@ struct FcgRun {
     }
     void orth() {
         gram(X, X, 1.0, Sm, false);
-        chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
-        rotate3(Tm);
+        chol_inv(nb, Sm, nb, Aw, Tm, d_status, st);
+        rotate3(Tm, true);                    // conj(L^-1) is lower triangular
     }
     // Rayleigh-Ritz in A = (H - E)^2 on the iterate (Y, AX exact): Ritz values of
     // Y^H Y ascending; the search directions and gradients turn with the bands.
@@ -241,8 +242,8 @@ struct FcgRun {
         fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);
         // initial orthonormalisation (Y, AX are garbage here but get overwritten)
         gram(X, X, 1.0, Sm, false);
-        chol_inv(nb, Sm, nb, Wm, Tm, d_status, st);
-        rotate(Tm, X, T1);
+        chol_inv(nb, Sm, nb, Aw, Tm, d_status, st);
+        rotate(Tm, X, T1, true);
         fold(X, Y, AX, false);
         a_rr(false);
         fill_zero(gz_old, ((size_t)nb * 8 + 15) / 16 * 16, st);

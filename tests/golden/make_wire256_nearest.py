@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 from paper_1907_06821_amd import synth  # noqa: E402  (seeded inputs only)
 from oracle.hamiltonian import Operator  # noqa: E402
-from oracle.shift_invert import count_below, nearest_by_shift_invert  # noqa: E402
+from oracle.shift_invert import count_below, nearest_by_shift_invert, work_matrix  # noqa: E402
 
 NWANT = 128
 K = 140
@@ -42,7 +42,6 @@ def input_hash(prob, vgrid):
 
 
 def main():
-    import torch
     t0 = time.perf_counter()
 
     def log(msg):
@@ -53,7 +52,7 @@ def main():
     op = Operator.from_problem(prob, vgrid=vgrid)
     e = prob.e_ref
     log(f"wire256: npw {op.npw}, {op.beta.shape[0]} projectors")
-    work = torch.empty((op.npw, op.npw), dtype=torch.complex128)
+    work = work_matrix(op.npw)
     r = nearest_by_shift_invert(op, e, K, work=work, log=log)
     lam = r["lam"]
     order = np.lexsort((lam, np.abs(lam - e)))

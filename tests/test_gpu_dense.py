@@ -81,7 +81,7 @@ def test_dense_eigh_key_orders_by_distance(torch_cuda):
     assert np.max(np.abs(np.sort(w) - w_ref)) < 1e-13
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 128, 136, 137, 200])
+@pytest.mark.parametrize("n", [1, 5, 64, 128, 136, 137, 200, 256, 300, 1024])
 def test_dense_chol_inv(torch_cuda, n):
     import torch
     import paper_1907_06821_amd as pw
@@ -104,3 +104,20 @@ def test_dense_chol_inv_not_pd(torch_cuda):
     with pytest.raises(pw.PwError) as e:
         pw.dense_chol_inv(torch.from_numpy(s).to("cuda"))
     assert e.value.status == pw.PW_ENOTPD
+
+
+@pytest.mark.parametrize("n, bad", [(4, 2), (300, 250), (1024, 700)])
+def test_dense_chol_inv_not_pd_reports_the_pivot(torch_cuda, n, bad):
+    """The leading bad x bad block is positive definite and pivot `bad` is not:
+    the blocked factorisation (n > 136) reports the first failing pivot of the
+    whole matrix, not of its diagonal block."""
+    import torch
+    import paper_1907_06821_amd as pw
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n + 20, n)) + 1j * rng.standard_normal((n + 20, n))
+    s = x.conj().T @ x
+    s[bad, bad] = -1e6
+    with pytest.raises(pw.PwError) as e:
+        pw.dense_chol_inv(torch.from_numpy(s).to("cuda"))
+    assert e.value.status == pw.PW_ENOTPD
+    assert f"pivot {bad}" in str(e.value)
