@@ -455,7 +455,11 @@ def wire4000_step(steps, warmup, log=None):
         log(f"wire4000 context: {t_ctx:.1f} s, {ctx.info()['device_bytes'] / 1e9:.1f} GB, "
             f"{ctx.cols_bands} bands per FFT launch")
     # complex64 FFT launch variants picked by the library's autotuner (not timed)
-    tuned = [r for r in pw.autotune(ctx, min(128, ctx.cols_bands), dtype=pw.PW_C64, reps=2) if r["chosen"]]
+    recs = pw.autotune(ctx, min(128, ctx.cols_bands), dtype=pw.PW_C64, reps=2)
+    tuned = [r for r in recs if r["chosen"]]
+    if log:
+        log("wire4000 BF16 GEMM variants (projection + back-projection, ms): " +
+            ", ".join(f"{r['sched']}: {r['ms']:.1f}" for r in recs if r["pass_"] == 6))
     wpath = os.path.join(train_precond.DATA_DIR, train_precond.WEIGHTS + ".npy")
     precond = 1
     if os.path.exists(wpath):
@@ -675,8 +679,10 @@ def stage_rooflines(ctx, nb, band_hpsi, mixed, prof):
         if n == 0 or ms <= 0:
             continue
         if k.startswith("block_"):
+            # block_rotate3 rotates by the Cholesky inverse, lower triangular: nb (nb + 1) / 2 of its
+            # entries are not zero, 3 blocks x 8 npw flops each
             bound, peak = "mfma", FP64_PEAK_TFS
-            total = (3 if k == "block_rotate3" else 1) * blk * n
+            total = (3 * 8.0 * npw * nb * (nb + 1) / 2 if k == "block_rotate3" else blk) * n
         else:
             bound, amount, _ = per_band[k]
             if k == "xy_fft_v":

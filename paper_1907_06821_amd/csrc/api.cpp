@@ -140,10 +140,11 @@ static void hpsi_c64(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *out
         {
             ProfScope p(ctx, 3, st);
             proj_bf16(ctx->nproj, nb, npw, ctx->max_bands, ctx->d_beta_bf16.p, ctx->d_dproj32.as<float>(), psi, ld,
-                      ctx->d_bf16_ws.p, ctx->d_partial.p, st);
+                      ctx->d_bf16_ws.p, ctx->d_partial.p, st, ctx->bf16_variant);
         }
         ProfScope p(ctx, 4, st);
-        backproj_bf16(ctx->nproj, nb, npw, ctx->max_bands, ctx->d_betaT_bf16.p, ctx->d_bf16_ws.p, out, ldo, st);
+        backproj_bf16(ctx->nproj, nb, npw, ctx->max_bands, ctx->d_betaT_bf16.p, ctx->d_bf16_ws.p, out, ldo, st,
+                      ctx->bf16_variant);
     }
 }
 

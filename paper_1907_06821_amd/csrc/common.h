@@ -170,6 +170,7 @@ struct pw_ctx {
     pw::FftTune tune[2];             // FFT launch choices: [0] complex128, [1] complex64
     pw::GemmTune nn_tune;            // back-projection GEMM tiles by band count (autotuner)
     pw::GemmTune rot_tune;           // block-rotation GEMM tiles (M = K = bands) by band count (autotuner)
+    int bf16_variant = 0;            // launch variant of the BF16 projector GEMMs beyond 144 bands (autotuner)
     int cb = 16;                     // z-columns per workgroup in the z passes
     // device tables
     pw::DevBuf d_kin, d_zmap, d_colpos, d_colstart, d_vz64, d_vz32, d_tw64[3], d_tw32[3];

@@ -788,16 +788,17 @@ static void run_pass(pw_ctx *ctx, int pass, int nb, void *in, void *out, hipStre
 
 namespace {
 struct TuneKey {
-    int n[3], ncols, npw, dbl, nb;
+    int n[3], ncols, npw, dbl, nb, nproj, max_bands;
     bool operator<(const TuneKey &o) const {
-        return std::tie(n[0], n[1], n[2], ncols, npw, dbl, nb) <
-               std::tie(o.n[0], o.n[1], o.n[2], o.ncols, o.npw, o.dbl, o.nb);
+        return std::tie(n[0], n[1], n[2], ncols, npw, dbl, nb, nproj, max_bands) <
+               std::tie(o.n[0], o.n[1], o.n[2], o.ncols, o.npw, o.dbl, o.nb, o.nproj, o.max_bands);
     }
 };
 struct TuneVal {
     FftTune tune;
     int nn = -1, rot = -1;
     std::vector<pw_fft_cand> recs;
+    int bf16 = -1;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
@@ -809,7 +810,7 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
     PW_CHECK(nb <= ctx->cols_bands, PW_EINVAL, "autotune on %d bands: the column grid holds %d", nb, ctx->cols_bands);
     FftTune &tune = ctx->tune[sizeof(T) == 8 ? 0 : 1];
     const TuneKey key{{ctx->cell.n[0], ctx->cell.n[1], ctx->cell.n[2]}, ctx->basis.ncols, ctx->basis.npw,
-                      sizeof(T) == 8, nb};
+                      sizeof(T) == 8, nb, ctx->nproj, ctx->max_bands};
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -817,6 +818,7 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
             tune = it->second.tune;
             if (it->second.nn >= 0) ctx->nn_tune.set(nb, it->second.nn);
             if (it->second.rot >= 0) ctx->rot_tune.set(nb, it->second.rot);
+            if (it->second.bf16 >= 0) ctx->bf16_variant = it->second.bf16;
             recs = it->second.recs;
             return;
         }
@@ -932,12 +934,57 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
         ctx->rot_tune.set(nb, best);
         PW_HIP(hipStreamSynchronize(s));
     }
+    // complex64 BF16 projector GEMMs beyond 144 bands (pass 6): every launch variant of the
+    // projection and back-projection pair, timed on max_bands bands
+    int bf16_best = -1;
+    if (sizeof(T) == 4 && ctx->nproj > 0 && ctx->max_bands > 144 && ctx->d_beta_bf16.p) {
+        const int nbw = ctx->max_bands, npw = ctx->basis.npw;
+        DevBuf win, wout;
+        win.alloc((size_t)nbw * npw * 8);
+        wout.alloc((size_t)nbw * npw * 8);
+        fill_zero(win.p, (size_t)nbw * npw * 8, s);
+        fill_zero(wout.p, (size_t)nbw * npw * 8, s);
+        const size_t first = recs.size();
+        for (int v = 0; v < kBf16WideVariants; ++v) {
+            pw_fft_cand r{};
+            r.pass = 6;
+            r.kind = 3;
+            r.sched = v;
+            r.radix[2] = nbw;
+            auto go = [&]() {
+                proj_bf16(ctx->nproj, nbw, npw, ctx->max_bands, ctx->d_beta_bf16.p, ctx->d_dproj32.as<float>(),
+                          win.p, npw, ctx->d_bf16_ws.p, ctx->d_partial.p, s, v);
+                backproj_bf16(ctx->nproj, nbw, npw, ctx->max_bands, ctx->d_betaT_bf16.p, ctx->d_bf16_ws.p, wout.p,
+                              npw, s, v);
+            };
+            go();
+            PW_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) go();
+            PW_HIP(hipEventRecord(e1, s));
+            PW_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            r.ms = ms / reps;
+            if (bf16_best < 0 || r.ms < recs[first + bf16_best].ms) bf16_best = v;
+            recs.push_back(r);
+        }
+        recs[first + bf16_best].chosen = 1;
+        ctx->bf16_variant = bf16_best;
+        PW_HIP(hipStreamSynchronize(s));
+    }
     PW_HIP(hipStreamSynchronize(s));
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = TuneVal{tune, nn_best, rot_best, recs};
+    g_tune_cache[key] = TuneVal{tune, nn_best, rot_best, recs, bf16_best};
 }
 
 template <typename T> void fft_choose(pw_ctx *ctx, const pw_fft_cand &r) {
+    if (r.pass == 6) {
+        PW_CHECK(sizeof(T) == 4, PW_EUNSUPPORTED, "BF16 GEMM variants are chosen for complex64 only");
+        PW_CHECK(r.kind == 0 || (r.kind == 3 && r.sched >= 0 && r.sched < kBf16WideVariants), PW_EUNSUPPORTED,
+                 "BF16 GEMM variant unknown");
+        ctx->bf16_variant = r.kind == 0 ? 0 : r.sched;
+        return;
+    }
     if (r.pass == 4 || r.pass == 5) {
         PW_CHECK(sizeof(T) == 8, PW_EUNSUPPORTED, "GEMM tiles are chosen for complex128 only");
         PW_CHECK(r.kind == 0 || (r.kind == 3 && r.sched >= 0 && r.sched < kNnCfgs), PW_EUNSUPPORTED,

@@ -312,18 +312,16 @@ __global__ __launch_bounds__(NW * 64) void backproj16(int N, int J, int64_t ldp,
 // KW-deep stages; the next stage's table fragments and band pieces are loaded
 // into registers while the current one is multiplied.
 // ---------------------------------------------------------------------------
-constexpr int KW = 32;           // k-depth per LDS stage of the wide kernels
-constexpr int LPW = KW + 8;      // padded LDS row (80 bytes: 16 rows hit 16 distinct 4-bank groups)
 
-template <int RB, int NBLK, int WM, int WN>
+template <int RB, int NBLK, int WM, int WN, int KW>
 __global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const uint16_t *__restrict__ Br,
                                                           const uint16_t *__restrict__ Bi, int64_t ldg,
                                                           const uint16_t *__restrict__ Pr,
                                                           const uint16_t *__restrict__ Pi, int kchunk,
                                                           float2 *__restrict__ partial) {
-    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW;
+    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW, LPW = KW + 8, KSUB = KW / 32;
     constexpr int PPT = NB * (KW / 8) / NT;              // 16-byte band pieces per thread and plane
-    static_assert(NB * (KW / 8) % NT == 0, "band pieces must divide evenly over the threads");
+    static_assert(KW % 32 == 0 && NB * (KW / 8) % NT == 0, "band pieces must divide evenly over the threads");
     __shared__ __attribute__((aligned(16))) uint16_t sPr[NB][LPW], sPi[NB][LPW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -344,15 +342,17 @@ __global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const ui
         rowA[r] = m0 + r * 16 + (lane & 15);
         okA[r] = rowA[r] < M;
     }
-    bf16x8 fa_r[RB], fa_i[RB];
+    bf16x8 fa_r[RB][KSUB], fa_i[RB][KSUB];
     uint4 pr_n[PPT], pi_n[PPT];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int64_t off = rowA[r] * ldg + k0 + 8 * (lane >> 4);
-            fa_r[r] = okA[r] ? load8(Br + off) : zero8();
-            fa_i[r] = okA[r] ? load8(Bi + off) : zero8();
-        }
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int q = 0; q < KSUB; ++q) {
+                const int64_t off = rowA[r] * ldg + k0 + 32 * q + 8 * (lane >> 4);
+                fa_r[r][q] = okA[r] ? load8(Br + off) : zero8();
+                fa_i[r][q] = okA[r] ? load8(Bi + off) : zero8();
+            }
 #pragma unroll
         for (int t = 0; t < PPT; ++t) {
             const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
@@ -373,26 +373,32 @@ __global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const ui
             *reinterpret_cast<uint4 *>(&sPr[r][c8]) = pr_n[t];
             *reinterpret_cast<uint4 *>(&sPi[r][c8]) = pi_n[t];
         }
-        bf16x8 ca_r[RB], ca_i[RB];
+        bf16x8 ca_r[RB][KSUB], ca_i[RB][KSUB], cn_i[RB][KSUB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) { ca_r[r] = fa_r[r]; ca_i[r] = neg8(fa_i[r]); }
-        bf16x8 cb_i[RB];
+        for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int r = 0; r < RB; ++r) cb_i[r] = fa_i[r];
+            for (int q = 0; q < KSUB; ++q) {
+                ca_r[r][q] = fa_r[r][q];
+                ca_i[r][q] = fa_i[r][q];
+                cn_i[r][q] = neg8(fa_i[r][q]);
+            }
         __syncthreads();
         if (k0 + KW < kend) fetch(k0 + KW);
-        const int kk = 8 * (lane >> 4);
 #pragma unroll
-        for (int j = 0; j < NBLK; ++j) {
-            const int row = wn * NBW + j * 16 + (lane & 15);
-            const bf16x8 br = load8(&sPr[row][kk]), bi = load8(&sPi[row][kk]);
+        for (int q = 0; q < KSUB; ++q) {
+            const int kk = 32 * q + 8 * (lane >> 4);
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
-                ar_[r][j] = mfma_bf16(ca_r[r], br, ar_[r][j]);
-                ar_[r][j] = mfma_bf16(cb_i[r], bi, ar_[r][j]);
-                ai_[r][j] = mfma_bf16(ca_r[r], bi, ai_[r][j]);
-                ai_[r][j] = mfma_bf16(ca_i[r], br, ai_[r][j]);
+            for (int j = 0; j < NBLK; ++j) {
+                const int row = wn * NBW + j * 16 + (lane & 15);
+                const bf16x8 pr = load8(&sPr[row][kk]), pi = load8(&sPi[row][kk]);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
+                    ar_[r][j] = mfma_bf16(ca_r[r][q], pr, ar_[r][j]);
+                    ar_[r][j] = mfma_bf16(ca_i[r][q], pi, ar_[r][j]);
+                    ai_[r][j] = mfma_bf16(ca_r[r][q], pi, ai_[r][j]);
+                    ai_[r][j] = mfma_bf16(cn_i[r][q], pr, ai_[r][j]);
+                }
             }
         }
         __syncthreads();
@@ -410,16 +416,16 @@ __global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const ui
             }
 }
 
-template <int GB, int NBLK, int WM, int WN>
+template <int GB, int NBLK, int WM, int WN, int KW>
 __global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int64_t ldp,
                                                               const uint16_t *__restrict__ Wr,
                                                               const uint16_t *__restrict__ Wi,
                                                               const uint16_t *__restrict__ Tr,
                                                               const uint16_t *__restrict__ Ti,
                                                               float2 *__restrict__ out, int64_t ldo) {
-    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW;
+    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW, LPW = KW + 8, KSUB = KW / 32;
     constexpr int WPT = NB * (KW / 8) / NT;              // 16-byte W pieces per thread and plane
-    static_assert(NB * (KW / 8) % NT == 0, "W pieces must divide evenly over the threads");
+    static_assert(KW % 32 == 0 && NB * (KW / 8) % NT == 0, "W pieces must divide evenly over the threads");
     __shared__ __attribute__((aligned(16))) uint16_t sWr[NB][LPW], sWi[NB][LPW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -427,24 +433,26 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int6
     int64_t gcol[GB];
     bool okB[GB];
 #pragma unroll
-    for (int q = 0; q < GB; ++q) {
-        gcol[q] = (int64_t)blockIdx.x * (WM * GB * 16) + wm * GB * 16 + q * 16 + (lane & 15);
-        okB[q] = gcol[q] < J;
+    for (int g = 0; g < GB; ++g) {
+        gcol[g] = (int64_t)blockIdx.x * (WM * GB * 16) + wm * GB * 16 + g * 16 + (lane & 15);
+        okB[g] = gcol[g] < J;
     }
     v4f ar_[NBLK][GB], ai_[NBLK][GB];
 #pragma unroll
     for (int i = 0; i < NBLK; ++i)
 #pragma unroll
-        for (int q = 0; q < GB; ++q) { ar_[i][q] = v4f{0, 0, 0, 0}; ai_[i][q] = v4f{0, 0, 0, 0}; }
-    bf16x8 fb_r[GB], fb_i[GB];
+        for (int g = 0; g < GB; ++g) { ar_[i][g] = v4f{0, 0, 0, 0}; ai_[i][g] = v4f{0, 0, 0, 0}; }
+    bf16x8 fb_r[GB][KSUB], fb_i[GB][KSUB];
     uint4 wr_n[WPT], wi_n[WPT];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < GB; ++q) {
-            const int64_t off = gcol[q] * ldp + k0 + 8 * (lane >> 4);
-            fb_r[q] = okB[q] ? load8(Tr + off) : zero8();
-            fb_i[q] = okB[q] ? load8(Ti + off) : zero8();
-        }
+        for (int g = 0; g < GB; ++g)
+#pragma unroll
+            for (int q = 0; q < KSUB; ++q) {
+                const int64_t off = gcol[g] * ldp + k0 + 32 * q + 8 * (lane >> 4);
+                fb_r[g][q] = okB[g] ? load8(Tr + off) : zero8();
+                fb_i[g][q] = okB[g] ? load8(Ti + off) : zero8();
+            }
 #pragma unroll
         for (int t = 0; t < WPT; ++t) {
             const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
@@ -465,24 +473,29 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int6
             *reinterpret_cast<uint4 *>(&sWr[r][c8]) = wr_n[t];
             *reinterpret_cast<uint4 *>(&sWi[r][c8]) = wi_n[t];
         }
-        bf16x8 cb_r[GB], cb_i[GB];
+        bf16x8 cb_r[GB][KSUB], cb_i[GB][KSUB];
 #pragma unroll
-        for (int q = 0; q < GB; ++q) { cb_r[q] = fb_r[q]; cb_i[q] = fb_i[q]; }
+        for (int g = 0; g < GB; ++g)
+#pragma unroll
+            for (int q = 0; q < KSUB; ++q) { cb_r[g][q] = fb_r[g][q]; cb_i[g][q] = fb_i[g][q]; }
         __syncthreads();
         if (k0 + KW < ldp) fetch(k0 + KW);
-        const int kk = 8 * (lane >> 4);
 #pragma unroll
-        for (int i = 0; i < NBLK; ++i) {
-            const int row = wn * NBW + i * 16 + (lane & 15);
-            const bf16x8 wr = load8(&sWr[row][kk]), wi = load8(&sWi[row][kk]);
-            const bf16x8 nwi = neg8(wi);
+        for (int q = 0; q < KSUB; ++q) {
+            const int kk = 32 * q + 8 * (lane >> 4);
 #pragma unroll
-            for (int q = 0; q < GB; ++q) {
-                // W beta: re = wr br - wi bi, im = wr bi + wi br
-                ar_[i][q] = mfma_bf16(wr, cb_r[q], ar_[i][q]);
-                ar_[i][q] = mfma_bf16(nwi, cb_i[q], ar_[i][q]);
-                ai_[i][q] = mfma_bf16(wr, cb_i[q], ai_[i][q]);
-                ai_[i][q] = mfma_bf16(wi, cb_r[q], ai_[i][q]);
+            for (int i = 0; i < NBLK; ++i) {
+                const int row = wn * NBW + i * 16 + (lane & 15);
+                const bf16x8 wr = load8(&sWr[row][kk]), wi = load8(&sWi[row][kk]);
+                const bf16x8 nwi = neg8(wi);
+#pragma unroll
+                for (int g = 0; g < GB; ++g) {
+                    // W beta: re = wr br - wi bi, im = wr bi + wi br
+                    ar_[i][g] = mfma_bf16(wr, cb_r[g][q], ar_[i][g]);
+                    ar_[i][g] = mfma_bf16(nwi, cb_i[g][q], ar_[i][g]);
+                    ai_[i][g] = mfma_bf16(wr, cb_i[g][q], ai_[i][g]);
+                    ai_[i][g] = mfma_bf16(wi, cb_r[g][q], ai_[i][g]);
+                }
             }
         }
         __syncthreads();
@@ -490,14 +503,14 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int6
 #pragma unroll
     for (int i = 0; i < NBLK; ++i)
 #pragma unroll
-        for (int q = 0; q < GB; ++q)
+        for (int g = 0; g < GB; ++g)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int b = b0 + wn * NBW + i * 16 + 4 * (lane >> 4) + v;
-                if (b < N && okB[q]) {
-                    float2 *o = out + (int64_t)b * ldo + gcol[q];
+                if (b < N && okB[g]) {
+                    float2 *o = out + (int64_t)b * ldo + gcol[g];
                     const float2 old = *o;
-                    *o = make_float2(old.x + ar_[i][q][v], old.y + ai_[i][q][v]);
+                    *o = make_float2(old.x + ar_[i][g][v], old.y + ai_[i][g][v]);
                 }
             }
 }
@@ -517,21 +530,52 @@ static int proj_splits(int M, int64_t ldg) {
     return std::max(1, std::min(s, maxs));
 }
 
-// wide kernels: 128 table rows (or plane waves) by 256 bands per workgroup
-constexpr int kWideRB = 2, kWideNBLK = 8, kWideWM = 4, kWideWN = 2;
-constexpr int kWideRows = kWideWM * kWideRB * 16, kWideBands = kWideWN * kWideNBLK * 16;
+// wide kernels: launch variants {RB (row blocks per wave), NBLK (band blocks per
+// wave), WM x WN waves, KW stage depth}; every variant spans 256 bands
+static const int kWide[kBf16WideVariants][5] = {{2, 8, 4, 2, 32}, {2, 8, 4, 2, 64}, {2, 8, 2, 2, 32},
+                                                {2, 8, 2, 2, 64}, {4, 4, 2, 4, 32}, {1, 8, 4, 2, 64}};
+constexpr int kWideBands = 256;
+static int wide_rows(int v) { return kWide[v][2] * kWide[v][0] * 16; }
 
 // split-K of the wide projection: about 512 workgroups, at least four stages per split
-static int wide_splits(int M, int N, int64_t ldg) {
-    const int tiles = ((M + kWideRows - 1) / kWideRows) * ((N + kWideBands - 1) / kWideBands);
+static int wide_splits(int v, int M, int N, int64_t ldg) {
+    const int tiles = ((M + wide_rows(v) - 1) / wide_rows(v)) * ((N + kWideBands - 1) / kWideBands);
     const int s = (512 + tiles - 1) / tiles;
-    const int maxs = (int)std::max<int64_t>(1, ldg / (4 * KW));
+    const int maxs = (int)std::max<int64_t>(1, ldg / (4 * kWide[v][4]));
     return std::max(1, std::min(s, maxs));
 }
 
 size_t cnt_partial_bytes(int M, int N, int K) {
-    if (N > MAXNB) return (size_t)wide_splits(M, N, bf16_ld(K)) * M * N * sizeof(float2);
+    if (N > MAXNB) {
+        int s = 1;
+        for (int v = 0; v < kBf16WideVariants; ++v) s = std::max(s, wide_splits(v, M, N, bf16_ld(K)));
+        return (size_t)s * M * N * sizeof(float2);
+    }
     return (size_t)proj_splits(M, bf16_ld(K)) * M * band_chunk(N) * sizeof(float2);
+}
+
+template <int RB, int NBLK, int WM, int WN, int KW>
+static void proj_wide_go(int v, int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_t ldg,
+                         const uint16_t *Pr, const uint16_t *Pi, float2 *partial, int &nsplit, hipStream_t st) {
+    const int ns = wide_splits(v, M, N, ldg);
+    int kchunk = (int)((ldg + ns - 1) / ns);
+    kchunk = (kchunk + KW - 1) / KW * KW;
+    nsplit = (int)((ldg + kchunk - 1) / kchunk);
+    constexpr int rows = WM * RB * 16;
+    dim3 grid((M + rows - 1) / rows, (N + kWideBands - 1) / kWideBands, nsplit);
+    hipLaunchKernelGGL((proj_wide<RB, NBLK, WM, WN, KW>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
+                       kchunk, partial);
+    PW_LAUNCH_CHECK();
+}
+
+template <int GB, int NBLK, int WM, int WN, int KW>
+static void back_wide_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
+                         const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
+    constexpr int cols = WM * GB * 16;
+    dim3 grid((unsigned)((J + cols - 1) / cols), (N + kWideBands - 1) / kWideBands);
+    hipLaunchKernelGGL((backproj_wide<GB, NBLK, WM, WN, KW>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi, Tr,
+                       Ti, out, ldo);
+    PW_LAUNCH_CHECK();
 }
 
 size_t bf16_scratch_bytes(int nproj, int npw, int max_bands) {
@@ -574,7 +618,7 @@ struct Bf16Scratch {
 
 // W = bf16(D o (B^H psi)) for the bands of a complex64 block (into the scratch)
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
-               int64_t ld, void *scratch, void *partial, hipStream_t st) {
+               int64_t ld, void *scratch, void *partial, hipStream_t st, int variant) {
     const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
     const uint16_t *Br = (const uint16_t *)beta16, *Bi = Br + (int64_t)nproj * ldg;
     Bf16Scratch S(scratch, max_bands, ldg, ldp);
@@ -582,15 +626,18 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
                        (const float2 *)psi, ld, ldg, S.Pr, S.Pi);
     PW_LAUNCH_CHECK();
     if (nb > MAXNB) {
-        // every band in one launch of 128 x 256 tiles, split over the plane waves
-        const int ns = wide_splits(nproj, nb, ldg);
-        int kchunk = (int)((ldg + ns - 1) / ns);
-        kchunk = (kchunk + KW - 1) / KW * KW;
-        const int nsplit = (int)((ldg + kchunk - 1) / kchunk);
-        dim3 grid((nproj + kWideRows - 1) / kWideRows, (nb + kWideBands - 1) / kWideBands, nsplit);
-        hipLaunchKernelGGL((proj_wide<kWideRB, kWideNBLK, kWideWM, kWideWN>), grid, dim3(64 * kWideWM * kWideWN), 0,
-                           st, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, kchunk, (float2 *)partial);
-        PW_LAUNCH_CHECK();
+        // every band in one launch of 256-band tiles, split over the plane waves
+        PW_CHECK(variant >= 0 && variant < kBf16WideVariants, PW_EINVAL, "BF16 tile variant %d unknown", variant);
+        int nsplit = 1;
+        float2 *part = (float2 *)partial;
+        switch (variant) {
+            case 0: proj_wide_go<2, 8, 4, 2, 32>(0, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 1: proj_wide_go<2, 8, 4, 2, 64>(1, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 2: proj_wide_go<2, 8, 2, 2, 32>(2, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 3: proj_wide_go<2, 8, 2, 2, 64>(3, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 4: proj_wide_go<4, 4, 2, 4, 32>(4, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            default: proj_wide_go<1, 8, 4, 2, 64>(5, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+        }
         const int64_t tot = (int64_t)nb * ldp;
         hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
                            (const float2 *)partial, d, ldp, S.Wr, S.Wi);
@@ -616,15 +663,22 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
 
 // out[b] += B . W[b] with W from proj_bf16's scratch
 void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,
-                   int64_t ldo, hipStream_t st) {
+                   int64_t ldo, hipStream_t st, int variant) {
     const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
     const uint16_t *Tr = (const uint16_t *)betaT16, *Ti = Tr + ldg * ldp;
     Bf16Scratch S(const_cast<void *>(scratch), max_bands, ldg, ldp);
     if (nb > MAXNB) {
-        dim3 grid((unsigned)((npw + kWideRows - 1) / kWideRows), (nb + kWideBands - 1) / kWideBands);
-        hipLaunchKernelGGL((backproj_wide<kWideRB, kWideNBLK, kWideWM, kWideWN>), grid, dim3(64 * kWideWM * kWideWN),
-                           0, st, nb, npw, ldp, S.Wr, S.Wi, Tr, Ti, (float2 *)out, ldo);
-        PW_LAUNCH_CHECK();
+        PW_CHECK(variant >= 0 && variant < kBf16WideVariants, PW_EINVAL, "BF16 tile variant %d unknown", variant);
+        const uint16_t *Wr = S.Wr, *Wi = S.Wi;
+        float2 *o = (float2 *)out;
+        switch (variant) {
+            case 0: back_wide_go<2, 8, 4, 2, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 1: back_wide_go<2, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 2: back_wide_go<2, 8, 2, 2, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 3: back_wide_go<2, 8, 2, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 4: back_wide_go<4, 4, 2, 4, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            default: back_wide_go<1, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+        }
         return;
     }
     for (int b0 = 0; b0 < nb; b0 += band_chunk(nb)) {

@@ -35,10 +35,12 @@ size_t bf16_scratch_bytes(int nproj, int npw, int max_bands);
 void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st);
 void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
                          hipStream_t st);
+// variant: launch variant of the kernels for more than 144 bands (autotuner pass 6)
+constexpr int kBf16WideVariants = 6;
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
-               int64_t ld, void *scratch, void *partial, hipStream_t st);
+               int64_t ld, void *scratch, void *partial, hipStream_t st, int variant = 0);
 void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,
-                   int64_t ldo, hipStream_t st);
+                   int64_t ldo, hipStream_t st, int variant = 0);
 
 // dense.hip
 // S = L L^H, T = conj(L^-1); work: chol_inv_work_bytes(N) device bytes

@@ -1,5 +1,6 @@
 """GPU parity of the H psi path (FFT passes, kinetic epilogue, projector GEMMs)
 against the FP64 CPU oracle.  All inputs are seeded synthetic problems."""
+import dataclasses
 import math
 
 import numpy as np
@@ -265,3 +266,30 @@ def test_c64_only_context_builds_the_same_tables(torch_cuda, which):
     b = pw.hpsi(only, c, shift=prob.e_ref).cpu().numpy()
     assert np.array_equal(a, b)
     assert only.info()["device_bytes"] < full.info()["device_bytes"]
+
+
+def test_bf16_wide_variants_agree(torch_cuda):
+    """Every launch variant of the BF16 projector GEMMs for more than 144 bands
+    (pass 6 of the autotuner) on the 2000-atom wire with 512 bands: the complex64
+    H psi of each is within the BF16 bound of the complex128 one (4 u of the
+    nonlocal part plus single precision FFT rounding), and the autotuner installs
+    exactly one."""
+    import torch
+    import paper_1907_06821_amd as pw
+    prob = synth.config(3)
+    nb = 512
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    loc = pw.Context.from_problem(dataclasses.replace(prob, pos=prob.pos[:0], depth=prob.depth[:0],
+                                                      dproj=prob.dproj[:0]), max_bands=nb, flags=pw.PW_PREP_C128)
+    x = to_dev(random_block(13, nb, ctx.npw))
+    ref = pw.hpsi(ctx, x, shift=prob.e_ref)
+    nl = ref - pw.hpsi(loc, x, shift=prob.e_ref)
+    bound = 4 * 2.0 ** -8 * torch.linalg.vector_norm(nl, dim=1) + 1e-5 * torch.linalg.vector_norm(ref, dim=1)
+    x32 = x.to(torch.complex64)
+    recs = [r for r in pw.autotune(ctx, 64, dtype=pw.PW_C64, reps=1) if r["pass_"] == 6]
+    assert len(recs) == 6 and sum(r["chosen"] for r in recs) == 1
+    for r in recs:
+        pw.fft_choose(ctx, r, dtype=pw.PW_C64)
+        got = pw.hpsi(ctx, x32, shift=prob.e_ref).to(torch.complex128)
+        err = torch.linalg.vector_norm(got - ref, dim=1)
+        assert bool(torch.all(err <= bound)), (r["sched"], float((err / bound).max()))
