@@ -251,6 +251,13 @@ typedef struct {
                              graph in turn every check round; 0 launches one graph holding all running
                              problems' segments as child graphs (rebuilt when a problem finishes or
                              changes precision).  Same kernels and results either way. */
+    int32_t learned_stall;/* precond 2: fall back to the paper's M(G) after this many checks without the
+                             best residual halving (default 8; 0 = never) */
+    int32_t recover;      /* 1 (default): when the Gram matrix loses positive definiteness, restart from
+                             the iterate of the last check (kept in psi) with the failing band replaced by
+                             a seeded random vector, up to three times; 0: return PW_ENOTPD */
+    int32_t fault_check;  /* tests of the recovery: at this check (1-based) the host marks the Gram
+                             factorisation as failed at band nb / 2 before reading its status (0 = never) */
 } pw_cg_opts;
 
 typedef struct {
@@ -262,6 +269,8 @@ typedef struct {
     int32_t n_hist;       /* in: capacity of hist; out: entries written */
     double *hist;         /* host, optional: [n_hist][2] = (iteration, max Delta) */
     int32_t n_snap;       /* out: snapshots written to snap_buf */
+    int32_t precond_switch_it; /* out: iteration at which precond 2 fell back to M(G), -1 if it did not */
+    int32_t recoveries;   /* out: restarts after a lost Gram factorisation */
     double ms[4];         /* out: GPU time (HIP events on the stream) of the set-up (first orthonormalisation,
                              two H psi, Rayleigh-Ritz), the CG iterations, the checks (residuals and
                              Rayleigh-Ritz every check_every iterations) and the final Rayleigh-Ritz in H;

@@ -63,7 +63,8 @@ class pw_cg_opts(C.Structure):
                 ("precision", C.c_int32), ("check_every", C.c_int32), ("verbose", C.c_int32),
                 ("mixed_switch", C.c_double), ("stall_checks", C.c_int32), ("snap_buf", C.c_void_p),
                 ("snap_every", C.c_int32), ("snap_cap", C.c_int32), ("nconv", C.c_int32),
-                ("batch_launch", C.c_int32)]
+                ("batch_launch", C.c_int32), ("learned_stall", C.c_int32), ("recover", C.c_int32),
+                ("fault_check", C.c_int32)]
 
 
 class pw_lin_opts(C.Structure):
@@ -84,7 +85,8 @@ class pw_fft_cand(C.Structure):
 class pw_cg_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_hpsi", C.c_int64), ("max_resid", C.c_double),
                 ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double)),
-                ("n_snap", C.c_int32), ("ms", C.c_double * 4)]
+                ("n_snap", C.c_int32), ("precond_switch_it", C.c_int32), ("recoveries", C.c_int32),
+                ("ms", C.c_double * 4)]
 
 
 _lib = None
@@ -499,6 +501,7 @@ def folded_cg_solve(ctx, e_ref, psi, opts=None, hist_len=0, stream=None, raise_o
                                          _stream_ptr(stream))
     stats = dict(iters=st.iters, converged=bool(st.converged), n_hpsi=st.n_hpsi, max_resid=st.max_resid,
                  seconds=st.seconds, hist=hist[:st.n_hist].copy(), status=status, n_snap=st.n_snap,
+                 precond_switch_it=st.precond_switch_it, recoveries=st.recoveries,
                  ms_setup=st.ms[0], ms_iters=st.ms[1], ms_checks=st.ms[2], ms_final=st.ms[3])
     if status != PW_OK and not (status == PW_ENOCONV and not raise_on_noconv):
         _check(status)

@@ -172,7 +172,7 @@ void orthonormalize_c128(pw_ctx *ctx, int nb, void *psi, int64_t ld, void *ws, v
     double2 *S = (double2 *)small;
     double2 *T = S + (size_t)nb * nb;
     double2 *W = T + (size_t)nb * nb;     // chol_inv_work_bytes(nb)
-    zgemm_nt(nb, nb, npw, true, psi, ld, psi, ld, 1.0, nullptr, 0.0, S, nb, false, ctx->d_partial.p, st);
+    zgemm_nt(nb, nb, npw, true, psi, ld, psi, ld, 1.0, nullptr, 0.0, S, nb, false, ctx->d_partial.p, st, false, true);
     chol_inv(nb, S, nb, W, T, d_status, st);
     zgemm_nn_launch(nb, npw, nb, T, nb, psi, ld, 1.0, 0.0, ws, npw, st, false, ctx->rot_tune.get(nb), true);
     copy_block(nb, npw, ws, npw, psi, ld, st);

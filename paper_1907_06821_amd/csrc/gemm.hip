@@ -43,13 +43,16 @@ template <int WM, int WN, int BM, int BN, bool CONJA, int TAG>
 __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, int K, const double2 *__restrict__ A,
                                                                  int64_t lda, const double2 *__restrict__ B,
                                                                  int64_t ldb, int kchunk,
-                                                                 double2 *__restrict__ partial) {
+                                                                 double2 *__restrict__ partial, int herm) {
     constexpr int NT = WM * WN * 64;
     constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
     constexpr int LA = (TM * KT + NT - 1) / NT, LB = (TN * KT + NT - 1) / NT;   // loads per thread per stage
     __shared__ double2 As[TM][KT + 1];
     __shared__ double2 Bs[TN][KT + 1];
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN, s = blockIdx.z;
+    // herm (A = B): the result is Hermitian, so tiles wholly above the diagonal are left
+    // to the reduction, which takes them from their mirror images
+    if (herm && n0 > m0 + TM - 1) return;
     const int kbeg = s * kchunk;
     const int kend = min(K, kbeg + kchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -130,7 +133,9 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
 // out = alpha * rowscale[m] * sum_s partial[s][m][n] (+ beta * out); TRANS writes out[n][m].
 // A workgroup of 256 threads takes 64 consecutive elements: wave g sums the
 // splits s = g (mod 4) for each, then wave 0 adds the four sums in order (fixed
-// summation order, so the result does not depend on scheduling).
+// summation order, so the result does not depend on scheduling).  herm: only the
+// partials on and below the diagonal exist; an element above it is the conjugate
+// of its mirror.
 constexpr int kRedElems = 64, kRedGroups = 4;
 
 template <bool TRANS>
@@ -139,18 +144,22 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial(int M, 
                                                                          double alpha,
                                                                          const double *__restrict__ rowscale,
                                                                          double beta, double2 *__restrict__ out,
-                                                                         int64_t ldo) {
+                                                                         int64_t ldo, int herm) {
     __shared__ double2 sum[kRedGroups][kRedElems];
     const int e = threadIdx.x % kRedElems, g = threadIdx.x / kRedElems;
     const int64_t tot = (int64_t)M * N;
     const int64_t idx = (int64_t)blockIdx.x * kRedElems + e;
+    const int m_ = (int)(idx / N), n_ = (int)(idx % N);
+    const bool mirror = herm && n_ > m_;
+    const int64_t src = mirror ? (int64_t)n_ * N + m_ : idx;
     double re = 0, im = 0;
     if (idx < tot)
         for (int s = g; s < nsplit; s += kRedGroups) {
-            const double2 v = partial[(int64_t)s * tot + idx];
+            const double2 v = partial[(int64_t)s * tot + src];
             re += v.x;
             im += v.y;
         }
+    if (mirror) im = -im;
     sum[g][e] = make_double2(re, im);
     __syncthreads();
     if (g != 0 || idx >= tot) return;
@@ -311,24 +320,26 @@ size_t nt_partial_bytes(int M, int N, int K) {
 
 template <int WM, int WN, int BM, int BN>
 static void nt_go(dim3 grid, bool conja, bool proj, hipStream_t st, int M, int N, int K, const void *A, int64_t lda,
-                  const void *B, int64_t ldb, int kchunk, void *partial) {
+                  const void *B, int64_t ldb, int kchunk, void *partial, int herm) {
     const dim3 blk(WM * WN * 64);
     if (conja && proj)
         hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, true, 1>), grid, blk, 0, st, M, N, K, (const double2 *)A,
-                           lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
+                           lda, (const double2 *)B, ldb, kchunk, (double2 *)partial, herm);
     else if (conja)
         hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, true, 0>), grid, blk, 0, st, M, N, K, (const double2 *)A,
-                           lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
+                           lda, (const double2 *)B, ldb, kchunk, (double2 *)partial, herm);
     else
         hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, false, 0>), grid, blk, 0, st, M, N, K,
-                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial);
+                           (const double2 *)A, lda, (const double2 *)B, ldb, kchunk, (double2 *)partial, herm);
 }
 
 // C (M x N, ldc) = alpha * rowscale o (op(A) B^T) (+ beta C); trans: write C^T (N x M)
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
-              hipStream_t st, bool proj) {
+              hipStream_t st, bool proj, bool herm_in) {
     if (M <= 0 || N <= 0) return;
+    // a Gram matrix A^H A: half the tiles (alpha real, no row scale)
+    const int herm = (herm_in && conja && A == B && lda == ldb && M == N && !rowscale) ? 1 : 0;
     const int ns = nt_splits(M, N, K);
     int kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + KT - 1) / KT) * KT;
@@ -336,26 +347,26 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     const int tn = nt_tn(N), tm = nt_tm(M, N);
     dim3 grid((M + tm - 1) / tm, (N + tn - 1) / tn, nsplit);
     if (K <= 0) fill_zero(partial, (size_t)M * N * sizeof(double2), st);
-    else if (tn == 16 && tm == 128) nt_go<4, 1, 2, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tn == 16) nt_go<4, 1, 1, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tn == 32 && tm == 128) nt_go<4, 1, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tn == 32) nt_go<4, 1, 1, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tm == 48) nt_go<1, 3, 3, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tm == 128 && tn == 128) nt_go<4, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tm == 128) nt_go<4, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else if (tn == 128) nt_go<2, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
-    else nt_go<2, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial);
+    else if (tn == 16 && tm == 128) nt_go<4, 1, 2, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tn == 16) nt_go<4, 1, 1, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tn == 32 && tm == 128) nt_go<4, 1, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tn == 32) nt_go<4, 1, 1, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tm == 48) nt_go<1, 3, 3, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tm == 128 && tn == 128) nt_go<4, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tm == 128) nt_go<4, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tn == 128) nt_go<2, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else nt_go<2, 3, 2, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     PW_LAUNCH_CHECK();
     const int64_t tot = (int64_t)M * N;
     const int nblk = (int)((tot + kRedElems - 1) / kRedElems);
     const dim3 rblk(kRedElems * kRedGroups);
     if (trans)
         hipLaunchKernelGGL((reduce_partial<true>), dim3(nblk), rblk, 0, st, M, N, nsplit, (const double2 *)partial,
-                           alpha, rowscale, beta, (double2 *)C, ldc);
+                           alpha, rowscale, beta, (double2 *)C, ldc, herm);
     else
         hipLaunchKernelGGL((reduce_partial<false>), dim3(nblk), rblk, 0, st, M, N, nsplit, (const double2 *)partial,
-                           alpha, rowscale, beta, (double2 *)C, ldc);
+                           alpha, rowscale, beta, (double2 *)C, ldc, herm);
     PW_LAUNCH_CHECK();
 }
 

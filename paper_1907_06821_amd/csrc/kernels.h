@@ -14,9 +14,10 @@ template <typename T, int MODE> void launch_xy(pw_ctx *, int nb, void *cols, voi
 // gemm.hip (complex128)
 int nt_splits(int M, int N, int K);
 size_t nt_partial_bytes(int M, int N, int K);
+// herm: A == B (a Gram matrix A^H B): only the tiles on and below the diagonal are computed
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
-              hipStream_t, bool proj = false);
+              hipStream_t, bool proj = false, bool herm = false);
 // NN GEMM tile configurations: cfg < 0 picks by M, else one of kNnCfgs (autotuner)
 constexpr int kNnCfgs = 14;
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr);

@@ -103,6 +103,8 @@ struct FcgRun {
     int it = 0, stall = 0, nhist = 0, nsnap = 0;
     bool converged = false;
     double best = INFINITY;
+    int lstall = 0, switch_it = -1, recoveries = 0, nchecks = 0;
+    double lbest = INFINITY;
     pw_status result = PW_OK;
 
     FcgRun(pw_ctx *c, double e, int n, void *p, int64_t l, double *ev, double *rv, const pw_cg_opts &opt,
@@ -169,7 +171,9 @@ struct FcgRun {
     // S (nb x nb) = A^H B over the plane waves
     void gram(const void *A, const void *B, double alpha, double2 *S, bool trans) {
         ProfScope p(ctx, 6, st);
-        zgemm_nt(nb, nb, npw, true, A, L, B, L, alpha, nullptr, 0.0, S, nb, trans, ctx->d_partial.p, st);
+        // A == B: a Gram matrix, Hermitian, so half its tiles
+        zgemm_nt(nb, nb, npw, true, A, L, B, L, alpha, nullptr, 0.0, S, nb, trans, ctx->d_partial.p, st, false,
+                 A == B);
     }
     // (X, Y, AX) <- M . (X, Y, AX) in one batched launch (lower: M lower triangular)
     void rotate3(const double2 *M, bool lower = false) {
@@ -271,6 +275,30 @@ struct FcgRun {
             ++nsnap;
         }
     }
+    // After a lost Gram factorisation: back to the iterate of the last check (in psi;
+    // the start block before the first check), band `bad` replaced by a seeded random
+    // vector, directions cleared, then the set-up again (orthonormalisation, Y, AX,
+    // Rayleigh-Ritz in A).
+    void restart(int bad) {
+        ++recoveries;
+        if (o.verbose) fprintf(stderr, "[pw] it %6d  Gram factorisation lost at band %d: restart\n", it, bad);
+        std::vector<double2> v(npw);
+        uint64_t x = 0x9E3779B97F4A7C15ull * (uint64_t)(recoveries + 1) ^ (uint64_t)it;
+        auto unif = [&]() {       // splitmix64 to (0, 1)
+            x += 0x9E3779B97F4A7C15ull;
+            uint64_t z = x;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        };
+        for (int g = 0; g < npw; ++g) v[g] = make_double2(unif() - 0.5, unif() - 0.5);
+        const int b = std::min(std::max(bad, 0), nb - 1);
+        PW_HIP(hipMemcpyAsync((char *)psi + (size_t)b * ld * 16, v.data(), (size_t)npw * 16, hipMemcpyHostToDevice,
+                              st));
+        PW_HIP(hipStreamSynchronize(st));
+        setup();
+    }
     void check_device() {
         fold(X, Y, AX, false);
         a_rr(true);
@@ -285,7 +313,13 @@ struct FcgRun {
         PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
         PW_HIP(hipMemcpyAsync(h_status, d_status, sizeof h_status, hipMemcpyDeviceToHost, st));
         PW_HIP(hipStreamSynchronize(st));
+        ++nchecks;
+        if (o.fault_check > 0 && nchecks == o.fault_check) h_status[0] = nb / 2 + 1;   // forced by the host
         if (h_status[0]) {
+            if (o.recover && recoveries < 3) {
+                restart(h_status[0] - 1);
+                return it < o.maxit;
+            }
             set_error("Gram matrix lost positive definiteness (pivot %d) before iteration %d", h_status[0] - 1, it);
             result = PW_ENOTPD;
             return false;
@@ -308,6 +342,20 @@ struct FcgRun {
         if (mx <= o.tol) {
             converged = true;
             return false;
+        }
+        // the iterate of this check is the one a restart goes back to
+        if (o.recover) copy_block(nb, npw, X, L, psi, ld, st);
+        // the learned preconditioner gives way to the paper's M(G) once the best residual
+        // has not halved over learned_stall checks
+        if (pa.kind == 2 && o.learned_stall > 0) {
+            if (mx < 0.5 * lbest) {
+                lbest = mx;
+                lstall = 0;
+            } else if (++lstall >= o.learned_stall) {
+                pa.kind = 1;
+                switch_it = it;
+                if (o.verbose) fprintf(stderr, "[pw] it %6d  learned preconditioner stalled: M(G) from here\n", it);
+            }
         }
         // precision ladder: leave the low-precision operator below mixed_switch, or
         // once the best residual has not improved by 2x over stall_checks checks
@@ -366,6 +414,8 @@ struct FcgRun {
             stats->n_hpsi = n_hpsi;
             stats->n_hist = nhist;
             stats->n_snap = nsnap;
+            stats->precond_switch_it = switch_it;
+            stats->recoveries = recoveries;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         }
         return result;
@@ -454,6 +504,7 @@ namespace {
 struct SegGraph {
     int len = 0;
     bool low = false;
+    int kind = 0;          // preconditioner the segment was recorded with
     hipGraph_t g = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t hpsi = 0;
@@ -485,6 +536,7 @@ SegGraph record_segment(FcgRun &r, int len, hipStream_t cap) {
     SegGraph sg;
     sg.len = len;
     sg.low = r.use_mixed;
+    sg.kind = r.pa.kind;
     const hipStream_t keep = r.st;
     const int it0 = r.it;
     const int64_t h0 = r.n_hpsi;
@@ -532,7 +584,7 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
                 const int len = r.segment_length();
                 SegGraph *sg = nullptr;
                 for (SegGraph &c : b.segs)
-                    if (c.len == len && c.low == r.use_mixed) sg = &c;
+                    if (c.len == len && c.low == r.use_mixed && c.kind == r.pa.kind) sg = &c;
                 if (!sg) {
                     b.segs.push_back(record_segment(r, len, R.cap));
                     sg = &b.segs.back();
@@ -656,6 +708,9 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->snap_cap = 0;
     o->nconv = 0;
     o->batch_launch = 1;
+    o->learned_stall = 8;
+    o->recover = 1;
+    o->fault_check = 0;
 }
 
 pw_status pw_folded_cg_solve(pw_ctx *ctx, double e_ref, int32_t nb, void *psi, int64_t ld, double *eig,

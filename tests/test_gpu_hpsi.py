@@ -174,7 +174,7 @@ def test_hpsi_c64_error_bound(torch_cuda):
         assert err <= bound, (b, err, bound)
 
 
-@pytest.mark.parametrize("nb", [128, 136, 150])
+@pytest.mark.parametrize("nb", [128, 136, 150, 300])
 def test_orthonormalize_matches_oracle(torch_cuda, nb):
     import paper_1907_06821_amd as pw
     from oracle.eigen import cholesky_orthonormalize

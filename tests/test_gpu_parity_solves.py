@@ -90,7 +90,7 @@ def test_uneven_batch_converges_to_dense_eigenpairs(torch_cuda, precision):
     import paper_1907_06821_amd as pw
     sel = _separated_cubes(16)
     assert len(sel) == 16
-    nb, nconv = 24, 16
+    nb, nconv = 32, 16          # 16 buffer bands: with 8, some cubes creep near 1e-6 for thousands of steps
     probs = [p for p, _ in sel]
     ctxs = [_ctx(p, nb) for p in probs]
     psis = [torch.from_numpy(synth.start_vectors(4, nb, c.npw, seed=i)).to("cuda") for i, c in enumerate(ctxs)]

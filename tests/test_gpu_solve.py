@@ -103,3 +103,48 @@ def test_solve_buffer_bands(torch_cuda):
     assert np.max(np.abs(eig[near] - lam)) < 1e-8
     assert np.max(res[near]) <= 1e-9
     assert principal_cosines(u, vec[near]).min() > 1 - 1e-8
+
+
+def test_learned_preconditioner_falls_back_to_mg(torch_cuda):
+    """A network whose output saturates (last layer scaled up: K = M(G) e^{+-8} shell
+    by shell) stalls the solve; after learned_stall checks without the best residual
+    halving the solver continues with the paper's M(G) and still reaches the dense
+    nearest eigenpairs.  With learned_stall = 0 it never switches."""
+    import torch
+    import paper_1907_06821_amd as pw
+    prob = synth.small_nonlocal_problem(nbands=6, e_ref=0.8)
+    op = oracle_for(prob)
+    lam, _, _, _ = nearest_eigenpairs(op.dense(), prob.e_ref, 6)
+    ctx = gpu_context(prob, max_bands=6)
+    w = synth.mlp_init(3)
+    w[-65:-1] *= 1000.0                      # W3: f = 8 tanh(r / 8) pinned near +-8
+    pw.mlp_set(ctx, torch.from_numpy(w.astype(np.float32)).to("cuda"))
+    psi0 = synth.start_vectors(7, 6, op.npw)
+    eig, res, st, vec = _solve(ctx, prob, psi0, tol=1e-9, maxit=6000, check_every=10, precond=2, learned_stall=1)
+    assert st["converged"] and st["precond_switch_it"] >= 10, st
+    assert np.max(np.abs(eig - lam)) < 1e-8
+    _, _, st0, _ = _solve(ctx, prob, psi0, tol=1e-9, maxit=40, check_every=10, precond=2, learned_stall=0,
+                          raise_on_noconv=False)
+    assert st0["precond_switch_it"] == -1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_recovers_from_lost_gram_factorisation(torch_cuda, precision):
+    """The host marks the Gram factorisation of the second check as failed: the
+    solver goes back to the first check's iterate, replaces the failing band by a
+    random vector and still reaches the dense nearest eigenpairs; with recover = 0
+    the same forced failure returns PW_ENOTPD."""
+    import paper_1907_06821_amd as pw
+    prob = synth.small_nonlocal_problem(nbands=6, e_ref=0.8)
+    op = oracle_for(prob)
+    lam, u, _, _ = nearest_eigenpairs(op.dense(), prob.e_ref, 6)
+    ctx = pw.Context.from_problem(prob, max_bands=6, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    psi0 = synth.start_vectors(7, 6, op.npw)
+    eig, res, st, vec = _solve(ctx, prob, psi0, tol=1e-9, maxit=6000, check_every=10, fault_check=2,
+                               precision=precision)
+    assert st["converged"] and st["recoveries"] == 1, st
+    assert np.max(np.abs(eig - lam)) < 1e-8
+    assert principal_cosines(u, vec).min() > 1 - 1e-8
+    with pytest.raises(pw.PwError) as e:
+        _solve(ctx, prob, psi0, tol=1e-9, maxit=6000, check_every=10, fault_check=2, recover=0)
+    assert e.value.status == pw.PW_ENOTPD
