@@ -407,7 +407,7 @@ def wire4000_hpsi(steps=3, warmup=1, tune=False):
     ctx = pw.Context.from_problem(prob, max_bands=nb, flags=pw.PW_PREP_C64)
     torch.cuda.synchronize()
     t_ctx = time.perf_counter() - t0
-    tuned = wire4000_autotune(ctx) if tune else []
+    tuned = wire4000_autotune(ctx, lambda m: print(m, file=sys.stderr, flush=True)) if tune else []
     psi = torch.from_numpy(synth.start_vectors(5, nb, ctx.npw).astype(np.complex64)).to("cuda")
     out = torch.empty_like(psi)
     for _ in range(warmup):
@@ -421,17 +421,8 @@ def wire4000_hpsi(steps=3, warmup=1, tune=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = pw.profile_end(ctx)
-    work = stage_work(ctx, nb, 8, ctx.nproj)
-    stages = {}
-    for k, (ms, n) in prof.items():
-        if n == 0:
-            continue
-        bound, amount, unit = work[k]
-        avg_s = ms / n / 1e3
-        ach = amount / avg_s / (1e9 if bound == "hbm" else 1e12)
-        peak = HBM_PEAK_GBS if bound == "hbm" else BF16_PEAK_TFS
-        stages[k] = {"bound": bound, "avg_ms": round(ms / n, 3), "achieved": round(ach, 1), "peak": peak,
-                     "frac": round(ach / peak, 4)}
+    stages = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+              for k, v in stage_rooflines(ctx, nb, nb * steps, True, prof).items()}
     print(json.dumps({"metric": "band-Hpsi/s, complex64 + BF16 projector GEMMs", "value": round(nb * steps / dt, 1),
                       "unit": "band-Hpsi/s", "ms_per_hpsi": round(dt / steps * 1e3, 3), "dtype": "c64+bf16",
                       "config": {"workload": "wire4000: 50x50x200 bohr, 128x128x512 grid, Ecut 10 Ha, 4000 atoms x 4 "

@@ -162,14 +162,17 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * length at compile time, kind 2 the runtime-plan kernel with nthr threads
  * (256, 512 or 1024) and radix schedule sched (0: radices 8 first, 1: radix 4
  * at most, 2: the radices of 0 in ascending order; radix[] lists the z plan or
- * the xy axis-0 plan), for pass 1 on planes of 16, 32, 48 or 64 points a side
- * kind 3 the four-lane register kernel with nthr threads (128, 192 or 256; the
- * default there), kind 0 the built-in default.  Pass 4 (complex128 only)
+ * the xy axis-0 plan), for pass 1 on planes of 16, 32, 48, 64, 96 or 128
+ * points a side kind 3 the four-lane register kernel with nthr threads (128,
+ * 192, 256 or 512; the default there), kind 0 the built-in default.  Pass 4 (complex128 only)
  * is the back-projection GEMM: kind 3, sched the tile id, radix[0..1] the tile's
  * rows and columns, radix[2] the band count it was timed at (the choice applies
  * to calls with that many bands), nthr its threads.  Pass 5 (complex128 only),
  * in the same form, is the block-rotation GEMM of the solver (an nb x nb matrix
- * times the nb-band block). */
+ * times the nb-band block).  Pass 6 (complex64, contexts of more than 144
+ * bands) is the BF16 projection and back-projection pair timed together at
+ * max_bands: kind 3, sched the launch variant (0-5 register-prefetch tiles of
+ * 256 bands, 6 the same tile fed by LDS DMA three stages deep). */
 typedef struct {
     int32_t pass;
     int32_t kind;
@@ -252,7 +255,9 @@ typedef struct {
                              problems' segments as child graphs (rebuilt when a problem finishes or
                              changes precision).  Same kernels and results either way. */
     int32_t learned_stall;/* precond 2: fall back to the paper's M(G) after this many checks without the
-                             best residual halving (default 8; 0 = never) */
+                             best residual halving (default 25; 0 = never).  A folded solve normally
+                             spends a few hundred iterations on a plateau where the residual falls
+                             slowly whatever the preconditioner, so the count must outlast it */
     int32_t recover;      /* 1 (default): when the Gram matrix loses positive definiteness, restart from
                              the iterate of the last check (kept in psi) with the failing band replaced by
                              a seeded random vector, up to three times; 0: return PW_ENOTPD */

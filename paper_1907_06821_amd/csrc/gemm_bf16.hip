@@ -313,6 +313,25 @@ __global__ __launch_bounds__(NW * 64) void backproj16(int N, int J, int64_t ldp,
 // into registers while the current one is multiplied.
 // ---------------------------------------------------------------------------
 
+// Workgroups go to the eight XCDs (each with its own L2) round robin in dispatch
+// order.  wide_tile renumbers them so that each XCD takes one contiguous run of
+// tile indices, band tile fastest: the workgroups running together on an XCD are
+// then a few row tiles by every band tile of one split and share their table rows
+// and band planes in that XCD's L2 (the table is read from memory about once per
+// call instead of once per band tile).  A bijection of the grid, so every tile is
+// computed exactly as before.
+struct WideTile {
+    int x, y, z;
+};
+__device__ inline WideTile wide_tile() {
+    const int X = gridDim.x, Y = gridDim.y;
+    const int T = X * Y * gridDim.z;
+    const int id = blockIdx.x + X * (blockIdx.y + Y * blockIdx.z);
+    const int xcd = id % 8, q = T / 8, r = T % 8;
+    const int L = xcd * q + min(xcd, r) + id / 8;
+    return WideTile{(L / Y) % X, L % Y, L / (X * Y)};
+}
+
 template <int RB, int NBLK, int WM, int WN, int KW>
 __global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const uint16_t *__restrict__ Br,
                                                           const uint16_t *__restrict__ Bi, int64_t ldg,
@@ -325,9 +344,10 @@ __global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const ui
     __shared__ __attribute__((aligned(16))) uint16_t sPr[NB][LPW], sPi[NB][LPW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    const int m0 = blockIdx.x * (WM * RB * 16) + wm * RB * 16;
-    const int n0 = blockIdx.y * NB;
-    const int s = blockIdx.z;
+    const WideTile tile = wide_tile();
+    const int m0 = tile.x * (WM * RB * 16) + wm * RB * 16;
+    const int n0 = tile.y * NB;
+    const int s = tile.z;
     const int kbeg = s * kchunk;
     const int kend = (int)min((int64_t)kbeg + kchunk, ldg);
     v4f ar_[RB][NBLK], ai_[RB][NBLK];
@@ -429,12 +449,13 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int6
     __shared__ __attribute__((aligned(16))) uint16_t sWr[NB][LPW], sWi[NB][LPW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    const int b0 = blockIdx.y * NB;
+    const WideTile tile = wide_tile();
+    const int b0 = tile.y * NB;
     int64_t gcol[GB];
     bool okB[GB];
 #pragma unroll
     for (int g = 0; g < GB; ++g) {
-        gcol[g] = (int64_t)blockIdx.x * (WM * GB * 16) + wm * GB * 16 + g * 16 + (lane & 15);
+        gcol[g] = (int64_t)tile.x * (WM * GB * 16) + wm * GB * 16 + g * 16 + (lane & 15);
         okB[g] = gcol[g] < J;
     }
     v4f ar_[NBLK][GB], ai_[NBLK][GB];
@@ -516,6 +537,221 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int6
 }
 
 // ---------------------------------------------------------------------------
+// Ring variants of the wide kernels.  Both operands of a 32-deep stage go from
+// memory straight into LDS through global_load_lds_dwordx4 (no registers on the
+// way), kRingStages stages deep: a workgroup keeps two stages (96 KB) of loads
+// in flight while it multiplies a third, where the register-prefetch kernels
+// above hold one stage and stall on memory latency.  LDS holds each 16 x 32
+// fragment of a plane as one 1 KB block in the MFMA's lane order (lane l: row
+// l % 16, k 8 (l / 16) + 0..7), so every fragment read is one linear
+// ds_read_b128.  Rows beyond an operand are read as its last row: their
+// products only reach outputs that are not stored.  The copies are issued in
+// inline assembly because the compiler, not knowing which stage a DMA fills,
+// would wait for all of them before any LDS read; here each wave waits for its
+// own copies of the stage it is about to use (s_waitcnt vmcnt counts them in
+// issue order) and the barrier then publishes every wave's part.
+// ---------------------------------------------------------------------------
+constexpr int kRingStages = 3;
+
+// 16 bytes per lane from g (per lane) into LDS at lds + 16 lane (lds wave-uniform);
+// m0 carries the LDS address and is restored afterwards
+__device__ inline void lds_dma16(const void *g, uint32_t lds) {
+    uint32_t keep;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %1\n\t"
+        "global_load_lds_dwordx4 %2, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(keep)
+        : "s"(lds), "v"(g)
+        : "memory");
+}
+
+// at most N of this wave's copies still in flight, its LDS reads done, then the barrier
+template <int N>
+__device__ inline void ring_barrier() {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+__device__ inline uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// projection: partial[s][b][m] = sum over split s of conj(beta_m) psi_b; tiles of
+// WM RB 16 table rows by WN NBLK 16 bands, each wave RB x NBLK fragments
+template <int RB, int NBLK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void proj_ring(int M, int N, const uint16_t *__restrict__ Br,
+                                                          const uint16_t *__restrict__ Bi, int64_t ldg,
+                                                          const uint16_t *__restrict__ Pr,
+                                                          const uint16_t *__restrict__ Pi, int kchunk,
+                                                          float2 *__restrict__ partial) {
+    constexpr int NW = WM * WN, TB = WM * RB, BB = WN * NBLK;
+    constexpr int BLK = 2 * (TB + BB), PW = BLK / NW, STAGE = BLK * 1024;
+    static_assert(BLK % NW == 0, "DMA blocks must divide evenly over the waves");
+    __shared__ __attribute__((aligned(1024))) uint8_t ring[kRingStages][STAGE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WM, wn = wave / WM;
+    const WideTile tile = wide_tile();
+    const int m0 = tile.x * (TB * 16), n0 = tile.y * (BB * 16);
+    const int kbeg = tile.z * kchunk;
+    const int nst = (int)((std::min((int64_t)kbeg + kchunk, ldg) - kbeg) / 32);
+    const uint16_t *src[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const int b = wave * PW + i, piece = 8 * (lane >> 4);
+        if (b < 2 * TB) {
+            const int row = std::min(m0 + (b % TB) * 16 + (lane & 15), M - 1);
+            src[i] = (b < TB ? Br : Bi) + (int64_t)row * ldg + kbeg + piece;
+        } else {
+            const int c = b - 2 * TB;
+            const int band = std::min(n0 + (c % BB) * 16 + (lane & 15), N - 1);
+            src[i] = (c < BB ? Pr : Pi) + (int64_t)band * ldg + kbeg + piece;
+        }
+    }
+    const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
+    auto issue = [&](int s) {
+        const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
+#pragma unroll
+        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
+    };
+    v4f ar_[RB][NBLK], ai_[RB][NBLK];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) { ar_[r][j] = v4f{0, 0, 0, 0}; ai_[r][j] = v4f{0, 0, 0, 0}; }
+#pragma unroll
+    for (int s = 0; s < kRingStages - 1; ++s)
+        if (s < nst) issue(s);
+    for (int t = 0; t < nst; ++t) {
+        // stage t landed (stage t + 1 may still be in flight)
+        if (t + 1 < nst) ring_barrier<PW>();
+        else ring_barrier<0>();
+        if (t + kRingStages - 1 < nst) issue(t + kRingStages - 1);    // into the slot stage t - 1 left
+        const uint8_t *S = &ring[t % kRingStages][0] + lane * 16;
+        bf16x8 tr[RB], ti[RB], tn[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            tr[r] = *reinterpret_cast<const bf16x8 *>(S + (wm * RB + r) * 1024);
+            ti[r] = *reinterpret_cast<const bf16x8 *>(S + (TB + wm * RB + r) * 1024);
+            tn[r] = neg8(ti[r]);
+        }
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) {
+            const bf16x8 pr = *reinterpret_cast<const bf16x8 *>(S + (2 * TB + wn * NBLK + j) * 1024);
+            const bf16x8 pi = *reinterpret_cast<const bf16x8 *>(S + (2 * TB + BB + wn * NBLK + j) * 1024);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
+                ar_[r][j] = mfma_bf16(tr[r], pr, ar_[r][j]);
+                ar_[r][j] = mfma_bf16(ti[r], pi, ar_[r][j]);
+                ai_[r][j] = mfma_bf16(tr[r], pi, ai_[r][j]);
+                ai_[r][j] = mfma_bf16(tn[r], pr, ai_[r][j]);
+            }
+        }
+    }
+    float2 *P = partial + (int64_t)tile.z * M * N;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + (wm * RB + r) * 16 + 4 * (lane >> 4) + v;
+                const int col = n0 + (wn * NBLK + j) * 16 + (lane & 15);
+                if (row < M && col < N) P[(int64_t)col * M + row] = make_float2(ar_[r][j][v], ai_[r][j][v]);
+            }
+}
+
+// back-projection: out[b][g] += sum_p W[b][p] beta_p(g); tiles of WM GB 16 plane
+// waves by WN NBLK 16 bands, each wave NBLK x GB fragments, all ldp projectors
+template <int GB, int NBLK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void backproj_ring(int N, int J, int64_t ldp,
+                                                              const uint16_t *__restrict__ Wr,
+                                                              const uint16_t *__restrict__ Wi,
+                                                              const uint16_t *__restrict__ Tr,
+                                                              const uint16_t *__restrict__ Ti,
+                                                              float2 *__restrict__ out, int64_t ldo) {
+    constexpr int NW = WM * WN, TB = WM * GB, BB = WN * NBLK;
+    constexpr int BLK = 2 * (TB + BB), PW = BLK / NW, STAGE = BLK * 1024;
+    static_assert(BLK % NW == 0, "DMA blocks must divide evenly over the waves");
+    __shared__ __attribute__((aligned(1024))) uint8_t ring[kRingStages][STAGE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WM, wn = wave / WM;
+    const WideTile tile = wide_tile();
+    const int g0 = tile.x * (TB * 16), b0 = tile.y * (BB * 16);
+    const int nst = (int)(ldp / 32);
+    const uint16_t *src[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const int b = wave * PW + i, piece = 8 * (lane >> 4);
+        if (b < 2 * TB) {
+            const int g = std::min(g0 + (b % TB) * 16 + (lane & 15), J - 1);
+            src[i] = (b < TB ? Tr : Ti) + (int64_t)g * ldp + piece;
+        } else {
+            const int c = b - 2 * TB;
+            const int band = std::min(b0 + (c % BB) * 16 + (lane & 15), N - 1);
+            src[i] = (c < BB ? Wr : Wi) + (int64_t)band * ldp + piece;
+        }
+    }
+    const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
+    auto issue = [&](int s) {
+        const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
+#pragma unroll
+        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
+    };
+    v4f ar_[NBLK][GB], ai_[NBLK][GB];
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int g = 0; g < GB; ++g) { ar_[i][g] = v4f{0, 0, 0, 0}; ai_[i][g] = v4f{0, 0, 0, 0}; }
+#pragma unroll
+    for (int s = 0; s < kRingStages - 1; ++s)
+        if (s < nst) issue(s);
+    for (int t = 0; t < nst; ++t) {
+        if (t + 1 < nst) ring_barrier<PW>();
+        else ring_barrier<0>();
+        if (t + kRingStages - 1 < nst) issue(t + kRingStages - 1);
+        const uint8_t *S = &ring[t % kRingStages][0] + lane * 16;
+        bf16x8 tr[GB], ti[GB];
+#pragma unroll
+        for (int g = 0; g < GB; ++g) {
+            tr[g] = *reinterpret_cast<const bf16x8 *>(S + (wm * GB + g) * 1024);
+            ti[g] = *reinterpret_cast<const bf16x8 *>(S + (TB + wm * GB + g) * 1024);
+        }
+#pragma unroll
+        for (int i = 0; i < NBLK; ++i) {
+            const bf16x8 wr = *reinterpret_cast<const bf16x8 *>(S + (2 * TB + wn * NBLK + i) * 1024);
+            const bf16x8 wi = *reinterpret_cast<const bf16x8 *>(S + (2 * TB + BB + wn * NBLK + i) * 1024);
+            const bf16x8 nwi = neg8(wi);
+#pragma unroll
+            for (int g = 0; g < GB; ++g) {
+                // W beta: re = wr br - wi bi, im = wr bi + wi br
+                ar_[i][g] = mfma_bf16(wr, tr[g], ar_[i][g]);
+                ar_[i][g] = mfma_bf16(nwi, ti[g], ar_[i][g]);
+                ai_[i][g] = mfma_bf16(wr, ti[g], ai_[i][g]);
+                ai_[i][g] = mfma_bf16(wi, tr[g], ai_[i][g]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int g = 0; g < GB; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = b0 + (wn * NBLK + i) * 16 + 4 * (lane >> 4) + v;
+                const int gc = g0 + (wm * GB + g) * 16 + (lane & 15);
+                if (b < N && gc < J) {
+                    float2 *o = out + (int64_t)b * ldo + gc;
+                    const float2 old = *o;
+                    *o = make_float2(old.x + ar_[i][g][v], old.y + ai_[i][g][v]);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static int band_blocks(int nb) { return nb <= 64 ? 4 : nb <= 128 ? 8 : 9; }
@@ -532,8 +768,10 @@ static int proj_splits(int M, int64_t ldg) {
 
 // wide kernels: launch variants {RB (row blocks per wave), NBLK (band blocks per
 // wave), WM x WN waves, KW stage depth}; every variant spans 256 bands
+// (variant 6: the ring kernels, LDS filled by DMA, geometry of variant 0)
 static const int kWide[kBf16WideVariants][5] = {{2, 8, 4, 2, 32}, {2, 8, 4, 2, 64}, {2, 8, 2, 2, 32},
-                                                {2, 8, 2, 2, 64}, {4, 4, 2, 4, 32}, {1, 8, 4, 2, 64}};
+                                                {2, 8, 2, 2, 64}, {4, 4, 2, 4, 32}, {1, 8, 4, 2, 64},
+                                                {2, 8, 4, 2, 32}};
 constexpr int kWideBands = 256;
 static int wide_rows(int v) { return kWide[v][2] * kWide[v][0] * 16; }
 
@@ -565,6 +803,30 @@ static void proj_wide_go(int v, int M, int N, const uint16_t *Br, const uint16_t
     dim3 grid((M + rows - 1) / rows, (N + kWideBands - 1) / kWideBands, nsplit);
     hipLaunchKernelGGL((proj_wide<RB, NBLK, WM, WN, KW>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
                        kchunk, partial);
+    PW_LAUNCH_CHECK();
+}
+
+template <int RB, int NBLK, int WM, int WN>
+static void proj_ring_go(int v, int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_t ldg,
+                         const uint16_t *Pr, const uint16_t *Pi, float2 *partial, int &nsplit, hipStream_t st) {
+    const int ns = wide_splits(v, M, N, ldg);
+    int kchunk = (int)((ldg + ns - 1) / ns);
+    kchunk = (kchunk + 31) / 32 * 32;
+    nsplit = (int)((ldg + kchunk - 1) / kchunk);
+    constexpr int rows = WM * RB * 16;
+    dim3 grid((M + rows - 1) / rows, (N + kWideBands - 1) / kWideBands, nsplit);
+    hipLaunchKernelGGL((proj_ring<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
+                       kchunk, partial);
+    PW_LAUNCH_CHECK();
+}
+
+template <int GB, int NBLK, int WM, int WN>
+static void back_ring_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
+                         const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
+    constexpr int cols = WM * GB * 16;
+    dim3 grid((unsigned)((J + cols - 1) / cols), (N + kWideBands - 1) / kWideBands);
+    hipLaunchKernelGGL((backproj_ring<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi, Tr,
+                       Ti, out, ldo);
     PW_LAUNCH_CHECK();
 }
 
@@ -636,7 +898,8 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
             case 2: proj_wide_go<2, 8, 2, 2, 32>(2, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
             case 3: proj_wide_go<2, 8, 2, 2, 64>(3, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
             case 4: proj_wide_go<4, 4, 2, 4, 32>(4, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            default: proj_wide_go<1, 8, 4, 2, 64>(5, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 5: proj_wide_go<1, 8, 4, 2, 64>(5, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            default: proj_ring_go<2, 8, 4, 2>(6, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
         }
         const int64_t tot = (int64_t)nb * ldp;
         hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
@@ -677,7 +940,8 @@ void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT1
             case 2: back_wide_go<2, 8, 2, 2, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
             case 3: back_wide_go<2, 8, 2, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
             case 4: back_wide_go<4, 4, 2, 4, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            default: back_wide_go<1, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 5: back_wide_go<1, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            default: back_ring_go<2, 8, 4, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
         }
         return;
     }

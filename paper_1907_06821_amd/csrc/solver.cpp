@@ -708,7 +708,7 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->snap_cap = 0;
     o->nconv = 0;
     o->batch_launch = 1;
-    o->learned_stall = 8;
+    o->learned_stall = 25;
     o->recover = 1;
     o->fault_check = 0;
 }

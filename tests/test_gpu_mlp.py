@@ -122,11 +122,15 @@ def test_learned_preconditioner_solve_matches_dense(torch_cuda):
     assert st["converged"] and np.max(np.abs(eig - lam)) < 1e-8
 
 
-def test_trained_network_beats_its_base(torch_cuda):
-    """The committed network (trained on other energies and start vectors) against
-    the paper's M(G) preconditioner it scales, on the 256-atom wire: same
-    mixed-precision solve, same start; fewer iterations to max Delta <= 1e-6 and
-    the same eigenvalues."""
+def test_trained_network_against_its_base(torch_cuda):
+    """The committed network (trained on other energies and start vectors of the
+    256- and 2000-atom wires) against the paper's M(G) preconditioner it scales,
+    on the 256-atom wire: mixed-precision solves from five held-out starts (seeds
+    0-4; training used 11-14 and 21-22).  Every solve reaches max Delta <= 1e-6
+    with the same eigenvalues as its M(G) twin.  The network is no reliable gain
+    (over ten held-out starts its iteration count is 1.02 +- 0.17 times M(G)'s),
+    so the test bounds its cost: on average at most 15% more iterations; the
+    per-start ratios are printed."""
     import os
     import torch
     import paper_1907_06821_amd as pw
@@ -136,15 +140,19 @@ def test_trained_network_beats_its_base(torch_cuda):
     ctx = pw.Context.from_problem(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
     w = np.load(os.path.join(train_precond.DATA_DIR, train_precond.WEIGHTS + ".npy"))
     pw.mlp_set(ctx, torch.from_numpy(w).to("cuda"))
-    psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=0)).to("cuda")
-    out = {}
-    for pc in (1, 2):
-        psi = psi0.clone()
-        eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=2000, check_every=20, precision=1,
-                                          precond=pc, nconv=nconv, raise_on_noconv=False)
-        near = np.sort(eig[np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv]])
-        out[pc] = (st["iters"], st["converged"], near)
-        print(f"precond {pc}: {st['iters']} iterations, {st['seconds']:.2f} s")
-    assert out[1][1] and out[2][1]
-    assert out[2][0] < out[1][0]
-    assert np.max(np.abs(out[2][2] - out[1][2])) < 1e-8
+    its = {1: [], 2: []}
+    for seed in range(5):
+        psi0 = torch.from_numpy(synth.start_vectors(2, nb, ctx.npw, seed=seed)).to("cuda")
+        near = {}
+        for pc in (1, 2):
+            psi = psi0.clone()
+            eig, res, st = pw.folded_cg_solve(ctx, prob.e_ref, psi, tol=1e-6, maxit=2000, check_every=20,
+                                              precision=1, precond=pc, nconv=nconv, raise_on_noconv=False)
+            assert st["converged"], (seed, pc, st["max_resid"])
+            near[pc] = np.sort(eig[np.argsort(np.abs(eig - prob.e_ref), kind="stable")[:nconv]])
+            its[pc].append(st["iters"])
+        assert np.max(np.abs(near[2] - near[1])) < 1e-8, seed
+    ratio = np.array(its[2]) / np.array(its[1])
+    print(f"M(G) iterations {its[1]}, learned {its[2]}; learned / M(G) {ratio.round(3).tolist()}, "
+          f"mean {ratio.mean():.3f} +- {ratio.std(ddof=1):.3f}")
+    assert ratio.mean() <= 1.15
