@@ -391,7 +391,7 @@ def wire4000_autotune(ctx, log=None):
     return [r for r in recs if r["chosen"]]
 
 
-def wire4000_hpsi(steps=3, warmup=1, tune=False):
+def wire4000_hpsi(steps=3, warmup=1, tune=False, bf16_variant=None):
     """Complex64 + BF16 H psi on the 4000-atom wire (50 x 50 x 200 bohr, 128 x 128 x 512 grid,
     755,605 plane waves, 16,000 projectors) for 1024 bands in one call, from a complex64-only
     context (BF16 projector planes built 64 atoms at a time); `tune`: the launch variants the
@@ -408,6 +408,10 @@ def wire4000_hpsi(steps=3, warmup=1, tune=False):
     torch.cuda.synchronize()
     t_ctx = time.perf_counter() - t0
     tuned = wire4000_autotune(ctx, lambda m: print(m, file=sys.stderr, flush=True)) if tune else []
+    if bf16_variant is not None:
+        # the BF16 GEMM launch variant forced (counter runs of one variant)
+        pw.fft_choose(ctx, {"pass_": 6, "kind": 3, "sched": int(bf16_variant)}, dtype=pw.PW_C64)
+        tuned = [r for r in tuned if r["pass_"] != 6] + [{"pass_": 6, "kind": 3, "nthr": 0, "sched": int(bf16_variant)}]
     psi = torch.from_numpy(synth.start_vectors(5, nb, ctx.npw).astype(np.complex64)).to("cuda")
     out = torch.empty_like(psi)
     for _ in range(warmup):
@@ -493,7 +497,7 @@ def wire4000_step(steps, warmup, log=None):
     d = stages[dom]
     roofline = {"bound": d["bound"], "achieved": round(d["achieved"], 3), "peak": d["peak"], "unit": d["unit"],
                 "frac": round(d["frac"], 4), "kernel": dom, "work_per_launch": d["work_per_launch"],
-                "traffic": measured_traffic_wire4000(dom)}
+                "traffic": measured_traffic_wire4000(dom, next((r["sched"] for r in tuned if r["pass_"] == 6), None))}
     ideal = sum(v["work_per_launch"] * v["launches"] / (v["peak"] * (1e9 if v["bound"] == "hbm" else 1e12))
                 for v in stages.values())
     roofline["step_frac"] = round(ideal / it_s, 4)
@@ -537,10 +541,11 @@ def wire4000_step(steps, warmup, log=None):
     return line
 
 
-def measured_traffic_wire4000(stage):
+def measured_traffic_wire4000(stage, bf16_variant=None):
     """HBM bytes per launch of `stage` on the 4000-atom wire from the committed
     counter runs (FETCH_SIZE / WRITE_SIZE, copy-calibrated), if they were taken
-    on the current source of the kernel; else None."""
+    on the current source of the kernel (and, for the projector GEMMs, on the
+    BF16 launch variant in use); else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "wire4000_traffic.json")
     if not os.path.exists(path):
@@ -556,6 +561,8 @@ def measured_traffic_wire4000(stage):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != st["source_sha256"]:
             return None
+    if "bytes_by_variant" in st:
+        return st["bytes_by_variant"].get(str(bf16_variant))
     return st["bytes_per_launch"]
 
 
@@ -721,6 +728,10 @@ def main():
     ap.add_argument("--no-kinterp", action="store_true", help="skip the k-point interpolation leg")
     ap.add_argument("--wire4000-hpsi", action="store_true",
                     help="only: complex64 H psi throughput on the 4000-atom wire (1024 bands in one call)")
+    ap.add_argument("--wire256-only", action="store_true",
+                    help="only the wire256 legs (for kernel traces of those legs; not the benchmark line)")
+    ap.add_argument("--bf16-variant", type=int, default=None,
+                    help="with --wire4000-hpsi: force this BF16 GEMM launch variant (autotuner pass 6)")
     ap.add_argument("--tune", action="store_true",
                     help="with --wire4000-hpsi: the launch variants the folded-CG step autotunes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -732,7 +743,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.wire4000_hpsi:
-        wire4000_hpsi(steps=max(1, args.steps), warmup=max(1, args.warmup), tune=args.tune)
+        wire4000_hpsi(steps=max(1, args.steps), warmup=max(1, args.warmup), tune=args.tune,
+                      bf16_variant=args.bf16_variant)
         return
     if args.copy_probe:
         import torch
@@ -747,6 +759,9 @@ def main():
     import torch
     torch.cuda.set_device(0)
     log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    if args.wire256_only:
+        print(json.dumps({"wire256": wire256_legs(args, log)}))
+        return
     line = wire4000_step(args.steps, args.warmup, log=log)
     if not args.no_wire256:
         line["wire256"] = wire256_legs(args, log)

@@ -172,7 +172,7 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * times the nb-band block).  Pass 6 (complex64, contexts of more than 144
  * bands) is the BF16 projection and back-projection pair timed together at
  * max_bands: kind 3, sched the launch variant (0-5 register-prefetch tiles of
- * 256 bands, 6 the same tile fed by LDS DMA three stages deep). */
+ * 256 bands, 6-9 tiles fed by LDS DMA three stages deep). */
 typedef struct {
     int32_t pass;
     int32_t kind;
@@ -250,10 +250,18 @@ typedef struct {
     int32_t snap_cap;     /* capacity of snap_buf in snapshots */
     int32_t nconv;        /* only the nconv Ritz pairs nearest e_ref must reach tol (0 = all nb); the
                              other nb - nconv bands are buffer bands that widen the folded gap */
-    int32_t batch_launch; /* pw_batch_solve only: 1 (default) launches each problem's recorded segment
-                             graph in turn every check round; 0 launches one graph holding all running
-                             problems' segments as child graphs (rebuilt when a problem finishes or
-                             changes precision).  Same kernels and results either way. */
+    int32_t batch_launch; /* pw_batch_solve only: 2 (default) fuses the problems: every step of an
+                             iteration or check is one launch over all problems (one per group of equal
+                             FFT grids for the FFT passes), a device mask skipping finished problems,
+                             the round of check_every iterations and its check recorded once as a graph
+                             and replayed; it applies when every problem has FP64 H psi (precision 0),
+                             preconditioner 0 or 1, at most 136 bands, a stored FP64 projector table,
+                             default launch choices and no snapshots, else mode 1 runs.  1 launches each
+                             problem's recorded segment graph in turn every check round; 0 launches one
+                             graph holding all running problems' segments as child graphs (rebuilt when
+                             a problem finishes or changes precision).  Every mode runs each problem's
+                             own kernels, tiles and reduction order: results are bit for bit those of
+                             solving the problems one by one. */
     int32_t learned_stall;/* precond 2: fall back to the paper's M(G) after this many checks without the
                              best residual halving (default 25; 0 = never).  A folded solve normally
                              spends a few hundred iterations on a plateau where the residual falls
@@ -276,6 +284,7 @@ typedef struct {
     int32_t n_snap;       /* out: snapshots written to snap_buf */
     int32_t precond_switch_it; /* out: iteration at which precond 2 fell back to M(G), -1 if it did not */
     int32_t recoveries;   /* out: restarts after a lost Gram factorisation */
+    int32_t fused;        /* out (pw_batch_solve): 1 when the problem ran in the fused batch */
     double ms[4];         /* out: GPU time (HIP events on the stream) of the set-up (first orthonormalisation,
                              two H psi, Rayleigh-Ritz), the CG iterations, the checks (residuals and
                              Rayleigh-Ritz every check_every iterations) and the final Rayleigh-Ritz in H;

@@ -86,7 +86,7 @@ class pw_cg_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("n_hpsi", C.c_int64), ("max_resid", C.c_double),
                 ("seconds", C.c_double), ("n_hist", C.c_int32), ("hist", C.POINTER(C.c_double)),
                 ("n_snap", C.c_int32), ("precond_switch_it", C.c_int32), ("recoveries", C.c_int32),
-                ("ms", C.c_double * 4)]
+                ("fused", C.c_int32), ("ms", C.c_double * 4)]
 
 
 _lib = None
@@ -658,7 +658,8 @@ def batch_solve(ctxs, e_refs, psis, opts=None, hist_len=0, stream=None, raise_on
     rc = lib().pw_batch_solve(n, ctx_arr, e_arr.ctypes.data, nb, psi_arr, ld_arr.ctypes.data, eig_arr, res_arr,
                               C.byref(o), st_arr, status.ctypes.data, _stream_ptr(stream))
     stats = [dict(iters=s.iters, converged=bool(s.converged), n_hpsi=s.n_hpsi, max_resid=s.max_resid,
-                  seconds=s.seconds, hist=h[:s.n_hist].copy()) for s, h in zip(st_arr, hists)]
+                  seconds=s.seconds, hist=h[:s.n_hist].copy(), fused=bool(s.fused), recoveries=s.recoveries)
+             for s, h in zip(st_arr, hists)]
     if rc != PW_OK and not (rc == PW_ENOCONV and not raise_on_noconv):
         _check(rc)
     return eigs, ress, stats, status

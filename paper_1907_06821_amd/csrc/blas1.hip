@@ -51,12 +51,16 @@ __device__ inline void block_store(double (&acc)[NQ], double *partial, int nb, i
 }
 
 // out[q * nb + b] = sum_split partial[q][b][split]
-__global__ void finish_red(int nq, int nb, int nsplit, const double *__restrict__ partial, double *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq * nb) return;
+__device__ __forceinline__ void finish_body(int nsplit, const double *__restrict__ partial, double *__restrict__ out,
+                                            int i) {
     double s = 0;
     for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)i * nsplit + k];
     out[i] = s;
+}
+
+__global__ void finish_red(int nq, int nb, int nsplit, const double *__restrict__ partial, double *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq * nb) finish_body(nsplit, partial, out, i);
 }
 
 static void finish(int nq, int nb, const BandRed &r, double *out, hipStream_t st) {
@@ -64,16 +68,18 @@ static void finish(int nq, int nb, const BandRed &r, double *out, hipStream_t st
     PW_LAUNCH_CHECK();
 }
 
+// the plane waves of reduction workgroup `split` of band b (bodies below take
+// (b, split) so that single and batched kernels share them)
 #define BAND_LOOP(npw)                                                     \
-    const int b = blockIdx.y, split = blockIdx.x;                          \
     const int g0 = split * RCHUNK;                                         \
     const int g1 = min(npw, g0 + RCHUNK);                                  \
     for (int g = g0 + threadIdx.x; g < g1; g += RT)
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(RT) void k_mu_tband(int nb, int npw, const double2 *__restrict__ Y,
-                                                 const double2 *__restrict__ X, int64_t ld,
-                                                 const double *__restrict__ kin, double *partial, int nsplit) {
+__device__ __forceinline__ void mu_tband_body(int nb, int npw, const double2 *__restrict__ Y,
+                                              const double2 *__restrict__ X, int64_t ld,
+                                              const double *__restrict__ kin, double *partial, int nsplit, int b,
+                                              int split) {
     double acc[2] = {0, 0};
     BAND_LOOP(npw) {
         const double2 y = Y[(int64_t)b * ld + g], x = X[(int64_t)b * ld + g];
@@ -81,6 +87,12 @@ __global__ __launch_bounds__(RT) void k_mu_tband(int nb, int npw, const double2 
         acc[1] += kin[g] * (x.x * x.x + x.y * x.y);
     }
     block_store<2>(acc, partial, nb, nsplit, b, split);
+}
+
+__global__ __launch_bounds__(RT) void k_mu_tband(int nb, int npw, const double2 *__restrict__ Y,
+                                                 const double2 *__restrict__ X, int64_t ld,
+                                                 const double *__restrict__ kin, double *partial, int nsplit) {
+    mu_tband_body(nb, npw, Y, X, ld, kin, partial, nsplit, blockIdx.y, blockIdx.x);
 }
 
 void red_mu_tband(int nb, int npw, const void *Y, const void *X, int64_t ld, const double *kin, double *mu,
@@ -94,10 +106,10 @@ void red_mu_tband(int nb, int npw, const void *Y, const void *X, int64_t ld, con
 }
 
 // G = AX - mu X ; Z = K o G ; gz = Re<G, Z> ; gzo = Re<Gold, Z> ; Gold <- G
-__global__ __launch_bounds__(RT) void k_grad(int nb, int npw, const double2 *__restrict__ X,
-                                             const double2 *__restrict__ AX, double2 *__restrict__ Gold,
-                                             double2 *__restrict__ Z, int64_t ld, const double *__restrict__ mu,
-                                             PrecArgs pa, double *partial, int nsplit) {
+__device__ __forceinline__ void grad_body(int nb, int npw, const double2 *__restrict__ X,
+                                          const double2 *__restrict__ AX, double2 *__restrict__ Gold,
+                                          double2 *__restrict__ Z, int64_t ld, const double *__restrict__ mu,
+                                          const PrecArgs &pa, double *partial, int nsplit, int b, int split) {
     double acc[2] = {0, 0};
     BAND_LOOP(npw) {
         const int64_t i = (int64_t)b * ld + g;
@@ -114,6 +126,13 @@ __global__ __launch_bounds__(RT) void k_grad(int nb, int npw, const double2 *__r
     block_store<2>(acc, partial, nb, nsplit, b, split);
 }
 
+__global__ __launch_bounds__(RT) void k_grad(int nb, int npw, const double2 *__restrict__ X,
+                                             const double2 *__restrict__ AX, double2 *__restrict__ Gold,
+                                             double2 *__restrict__ Z, int64_t ld, const double *__restrict__ mu,
+                                             PrecArgs pa, double *partial, int nsplit) {
+    grad_body(nb, npw, X, AX, Gold, Z, ld, mu, pa, partial, nsplit, blockIdx.y, blockIdx.x);
+}
+
 void red_grad(int nb, int npw, const void *X, const void *AX, void *Gold, void *Z, int64_t ld, const double *mu,
               PrecArgs pa, double *gz, double *gzo, BandRed r, hipStream_t st) {
     hipLaunchKernelGGL(k_grad, dim3(r.nsplit, nb), dim3(RT), 0, st, nb, npw, (const double2 *)X,
@@ -123,14 +142,19 @@ void red_grad(int nb, int npw, const void *X, const void *AX, void *Gold, void *
     finish(2, nb, r, gz, st);
 }
 
-__global__ __launch_bounds__(RT) void k_gzold(int nb, int npw, const double2 *__restrict__ G, int64_t ld,
-                                              PrecArgs pa, double *partial, int nsplit) {
+__device__ __forceinline__ void gzold_body(int nb, int npw, const double2 *__restrict__ G, int64_t ld,
+                                           const PrecArgs &pa, double *partial, int nsplit, int b, int split) {
     double acc[1] = {0};
     BAND_LOOP(npw) {
         const double2 v = G[(int64_t)b * ld + g];
         acc[0] += prec_weight(pa, b, g) * (v.x * v.x + v.y * v.y);
     }
     block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+__global__ __launch_bounds__(RT) void k_gzold(int nb, int npw, const double2 *__restrict__ G, int64_t ld,
+                                              PrecArgs pa, double *partial, int nsplit) {
+    gzold_body(nb, npw, G, ld, pa, partial, nsplit, blockIdx.y, blockIdx.x);
 }
 
 void red_gzold(int nb, int npw, const void *G, int64_t ld, PrecArgs pa, double *gz_old, BandRed r, hipStream_t st) {
@@ -142,18 +166,23 @@ void red_gzold(int nb, int npw, const void *G, int64_t ld, PrecArgs pa, double *
 
 // P = -Z + beta P with Polak-Ribiere beta = max(0, (gz - gzo) / gz_old); the
 // first workgroup of each band also stores gz as the next gz_old.
-__global__ void k_pupdate(int nb, int npw, const double2 *__restrict__ Z, double2 *__restrict__ P, int64_t ld,
-                          const double *__restrict__ gz, const double *__restrict__ gzo, double *__restrict__ gz_old) {
-    const int b = blockIdx.y;
+__device__ __forceinline__ void pupdate_body(int npw, const double2 *__restrict__ Z, double2 *__restrict__ P,
+                                             int64_t ld, const double *__restrict__ gz,
+                                             const double *__restrict__ gzo, const double *__restrict__ gz_old, int b,
+                                             int g) {
     const double den = gz_old[b];
     double beta = den > 0.0 ? (gz[b] - gzo[b]) / den : 0.0;
     if (!(beta > 0.0)) beta = 0.0;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g < npw) {
         const int64_t i = (int64_t)b * ld + g;
         const double2 z = Z[i], p = P[i];
         P[i] = make_double2(-z.x + beta * p.x, -z.y + beta * p.y);
     }
+}
+
+__global__ void k_pupdate(int nb, int npw, const double2 *__restrict__ Z, double2 *__restrict__ P, int64_t ld,
+                          const double *__restrict__ gz, const double *__restrict__ gzo, double *__restrict__ gz_old) {
+    pupdate_body(npw, Z, P, ld, gz, gzo, gz_old, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void k_store_gzold(int nb, const double *gz, double *gz_old) {
@@ -171,9 +200,9 @@ void pupdate(int nb, int npw, const void *Z, void *P, int64_t ld, const double *
 }
 
 // <Y, YP> (re, im), ||YP||^2, ||P||^2
-__global__ __launch_bounds__(RT) void k_line(int nb, int npw, const double2 *__restrict__ Y,
-                                             const double2 *__restrict__ YP, const double2 *__restrict__ P,
-                                             int64_t ld, double *partial, int nsplit) {
+__device__ __forceinline__ void line_body(int nb, int npw, const double2 *__restrict__ Y,
+                                          const double2 *__restrict__ YP, const double2 *__restrict__ P, int64_t ld,
+                                          double *partial, int nsplit, int b, int split) {
     double acc[4] = {0, 0, 0, 0};
     BAND_LOOP(npw) {
         const int64_t i = (int64_t)b * ld + g;
@@ -184,6 +213,12 @@ __global__ __launch_bounds__(RT) void k_line(int nb, int npw, const double2 *__r
         acc[3] += p.x * p.x + p.y * p.y;
     }
     block_store<4>(acc, partial, nb, nsplit, b, split);
+}
+
+__global__ __launch_bounds__(RT) void k_line(int nb, int npw, const double2 *__restrict__ Y,
+                                             const double2 *__restrict__ YP, const double2 *__restrict__ P,
+                                             int64_t ld, double *partial, int nsplit) {
+    line_body(nb, npw, Y, YP, P, ld, partial, nsplit, blockIdx.y, blockIdx.x);
 }
 
 void red_line(int nb, int npw, const void *Y, const void *YP, const void *P, int64_t ld, double *out4, BandRed r,
@@ -198,10 +233,8 @@ void red_line(int nb, int npw, const void *Y, const void *YP, const void *P, int
 // psi): lowest eigenvector of [[a11, a12], [conj a12, a22]] in the basis
 // {psi, p/|p|}, computed without cancellation.  coef[b] = (alpha re, alpha im,
 // beta re, beta im) with psi' = alpha psi + beta p.
-__global__ void k_line_coef(int nb, const double *__restrict__ mu, const double *__restrict__ l4,
-                            double *__restrict__ coef) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
+__device__ __forceinline__ void line_coef_body(int nb, const double *__restrict__ mu, const double *__restrict__ l4,
+                                               double *__restrict__ coef, int b) {
     const double pn2 = l4[3 * nb + b];
     double ar = 1, ai = 0, br = 0, bi = 0;
     if (pn2 > 0.0) {
@@ -224,6 +257,12 @@ __global__ void k_line_coef(int nb, const double *__restrict__ mu, const double 
     coef[4 * b + 3] = bi;
 }
 
+__global__ void k_line_coef(int nb, const double *__restrict__ mu, const double *__restrict__ l4,
+                            double *__restrict__ coef) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) line_coef_body(nb, mu, l4, coef, b);
+}
+
 void line_coef(int nb, const double *mu, const double *l4, double *coef, hipStream_t st) {
     hipLaunchKernelGGL(k_line_coef, dim3((nb + 255) / 256), dim3(256), 0, st, nb, mu, l4, coef);
     PW_LAUNCH_CHECK();
@@ -233,11 +272,10 @@ __device__ inline double2 lin2(double2 a, double2 x, double2 b, double2 y) {
     return make_double2(a.x * x.x - a.y * x.y + b.x * y.x - b.y * y.y, a.x * x.y + a.y * x.x + b.x * y.y + b.y * y.x);
 }
 
-__global__ void k_combine3(int nb, int npw, double2 *__restrict__ X, double2 *__restrict__ Y, double2 *__restrict__ AX,
-                           const double2 *__restrict__ P, const double2 *__restrict__ YP,
-                           const double2 *__restrict__ AP, int64_t ld, const double *__restrict__ coef) {
-    const int b = blockIdx.y;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void combine3_body(int npw, double2 *__restrict__ X, double2 *__restrict__ Y,
+                                              double2 *__restrict__ AX, const double2 *__restrict__ P,
+                                              const double2 *__restrict__ YP, const double2 *__restrict__ AP,
+                                              int64_t ld, const double *__restrict__ coef, int b, int g) {
     if (g >= npw) return;
     const double2 al = make_double2(coef[4 * b], coef[4 * b + 1]);
     const double2 be = make_double2(coef[4 * b + 2], coef[4 * b + 3]);
@@ -245,6 +283,12 @@ __global__ void k_combine3(int nb, int npw, double2 *__restrict__ X, double2 *__
     X[i] = lin2(al, X[i], be, P[i]);
     Y[i] = lin2(al, Y[i], be, YP[i]);
     AX[i] = lin2(al, AX[i], be, AP[i]);
+}
+
+__global__ void k_combine3(int nb, int npw, double2 *__restrict__ X, double2 *__restrict__ Y, double2 *__restrict__ AX,
+                           const double2 *__restrict__ P, const double2 *__restrict__ YP,
+                           const double2 *__restrict__ AP, int64_t ld, const double *__restrict__ coef) {
+    combine3_body(npw, X, Y, AX, P, YP, AP, ld, coef, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 void combine3(int nb, int npw, void *X, void *Y, void *AX, const void *P, const void *YP, const void *AP,
@@ -256,9 +300,9 @@ void combine3(int nb, int npw, void *X, void *Y, void *AX, const void *P, const 
 }
 
 // res[b] = || Y_b - w_b X_b ||
-__global__ __launch_bounds__(RT) void k_resid(int nb, int npw, const double2 *__restrict__ Y,
-                                              const double2 *__restrict__ X, int64_t ld, const double *__restrict__ w,
-                                              double *partial, int nsplit) {
+__device__ __forceinline__ void resid_body(int nb, int npw, const double2 *__restrict__ Y,
+                                           const double2 *__restrict__ X, int64_t ld, const double *__restrict__ w,
+                                           double *partial, int nsplit, int b, int split) {
     double acc[1] = {0};
     BAND_LOOP(npw) {
         const int64_t i = (int64_t)b * ld + g;
@@ -268,6 +312,12 @@ __global__ __launch_bounds__(RT) void k_resid(int nb, int npw, const double2 *__
         acc[0] += rx * rx + ry * ry;
     }
     block_store<1>(acc, partial, nb, nsplit, b, split);
+}
+
+__global__ __launch_bounds__(RT) void k_resid(int nb, int npw, const double2 *__restrict__ Y,
+                                              const double2 *__restrict__ X, int64_t ld, const double *__restrict__ w,
+                                              double *partial, int nsplit) {
+    resid_body(nb, npw, Y, X, ld, w, partial, nsplit, blockIdx.y, blockIdx.x);
 }
 
 __global__ void k_sqrt(int n, double *x) {
@@ -287,6 +337,7 @@ void red_resid(int nb, int npw, const void *Y, const void *X, int64_t ld, const 
 
 __global__ __launch_bounds__(RT) void k_norm2(int nb, int npw, const double2 *__restrict__ X, int64_t ld,
                                               double *partial, int nsplit) {
+    const int b = blockIdx.y, split = blockIdx.x;
     double acc[1] = {0};
     BAND_LOOP(npw) {
         const double2 x = X[(int64_t)b * ld + g];
@@ -301,6 +352,172 @@ void band_norms(int nb, int npw, const void *X, int64_t ld, double *out, BandRed
     PW_LAUNCH_CHECK();
     finish(1, nb, r, out, st);
     hipLaunchKernelGGL(k_sqrt, dim3((nb + 255) / 256), dim3(256), 0, st, nb, out);
+    PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Batched band kernels: the problems of a batched folded-CG run (one BandProb
+// each, all with nb bands) in one launch, blockIdx.y = problem x nb + band (or the
+// problem alone); problems whose mask entry is 0 and workgroups beyond a problem's
+// own extent return at once.  They run the bodies of the kernels above with each
+// problem's arguments, so every problem's numbers are those of its own launches.
+// ---------------------------------------------------------------------------
+#define BATCH_BAND(nb)                                                     \
+    const int q = blockIdx.y / (nb), b = blockIdx.y % (nb);               \
+    if (!mask[q]) return;                                                  \
+    const BandProb &p = probs[q];
+
+__global__ __launch_bounds__(RT) void kb_mu_tband(const BandProb *__restrict__ probs, const int *__restrict__ mask,
+                                                  int nb) {
+    BATCH_BAND(nb)
+    if ((int)blockIdx.x >= p.nsplit) return;
+    mu_tband_body(nb, p.npw, p.blk[kBY], p.blk[kBX], p.ld, p.pa.kin, p.red, p.nsplit, b, blockIdx.x);
+}
+
+__global__ __launch_bounds__(RT) void kb_grad(const BandProb *__restrict__ probs, const int *__restrict__ mask,
+                                              int nb) {
+    BATCH_BAND(nb)
+    if ((int)blockIdx.x >= p.nsplit) return;
+    grad_body(nb, p.npw, p.blk[kBX], p.blk[kBAX], p.blk[kBG], p.blk[kBZ], p.ld, p.vec, p.pa, p.red, p.nsplit, b,
+              blockIdx.x);
+}
+
+__global__ __launch_bounds__(RT) void kb_gzold(const BandProb *__restrict__ probs, const int *__restrict__ mask,
+                                               int nb) {
+    BATCH_BAND(nb)
+    if ((int)blockIdx.x >= p.nsplit) return;
+    gzold_body(nb, p.npw, p.blk[kBG], p.ld, p.pa, p.red, p.nsplit, b, blockIdx.x);
+}
+
+__global__ __launch_bounds__(RT) void kb_line(const BandProb *__restrict__ probs, const int *__restrict__ mask,
+                                              int nb) {
+    BATCH_BAND(nb)
+    if ((int)blockIdx.x >= p.nsplit) return;
+    line_body(nb, p.npw, p.blk[kBY], p.blk[kBYP], p.blk[kBP], p.ld, p.red, p.nsplit, b, blockIdx.x);
+}
+
+__global__ __launch_bounds__(RT) void kb_resid(const BandProb *__restrict__ probs, const int *__restrict__ mask,
+                                               int nb, int iy, int ix) {
+    BATCH_BAND(nb)
+    if ((int)blockIdx.x >= p.nsplit) return;
+    resid_body(nb, p.npw, p.blk[iy], p.blk[ix], p.ld, p.vec + 13 * nb, p.red, p.nsplit, b, blockIdx.x);
+}
+
+__global__ void kb_pupdate(const BandProb *__restrict__ probs, const int *__restrict__ mask, int nb) {
+    BATCH_BAND(nb)
+    pupdate_body(p.npw, p.blk[kBZ], p.blk[kBP], p.ld, p.vec + 2 * nb, p.vec + 3 * nb, p.vec + 4 * nb, b,
+                 blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void kb_combine3(const BandProb *__restrict__ probs, const int *__restrict__ mask, int nb) {
+    BATCH_BAND(nb)
+    combine3_body(p.npw, p.blk[kBX], p.blk[kBY], p.blk[kBAX], p.blk[kBP], p.blk[kBYP], p.blk[kBAP], p.ld,
+                  p.vec + 9 * nb, b, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// blockIdx.y = problem: out = vec + off nb, nq quantities of nb bands
+__global__ void kb_finish(const BandProb *__restrict__ probs, const int *__restrict__ mask, int nb, int nq, int off) {
+    if (!mask[blockIdx.y]) return;
+    const BandProb &p = probs[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq * nb) finish_body(p.nsplit, p.red, p.vec + off * nb, i);
+}
+
+__global__ void kb_scalars(const BandProb *__restrict__ probs, const int *__restrict__ mask, int nb, int what) {
+    if (!mask[blockIdx.y]) return;
+    const BandProb &p = probs[blockIdx.y];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    if (what == 0) p.vec[4 * nb + b] = p.vec[2 * nb + b];                 // gz_old <- gz
+    else if (what == 1) line_coef_body(nb, p.vec, p.vec + 5 * nb, p.vec + 9 * nb, b);
+    else p.vec[14 * nb + b] = sqrt(p.vec[14 * nb + b]);                   // res <- sqrt(res)
+}
+
+// blk[dst[k]] <- blk[src[k]], k < n (blockIdx.z)
+__global__ void kb_copy(const BandProb *__restrict__ probs, const int *__restrict__ mask, int nb, int4 src, int4 dst) {
+    BATCH_BAND(nb)
+    const int k = blockIdx.z;
+    const int si = k == 0 ? src.x : k == 1 ? src.y : k == 2 ? src.z : src.w;
+    const int di = k == 0 ? dst.x : k == 1 ? dst.y : k == 2 ? dst.z : dst.w;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < p.npw) p.blk[di][(int64_t)b * p.ld + g] = p.blk[si][(int64_t)b * p.ld + g];
+}
+__global__ void kb_save(const BandProb *__restrict__ probs, const int *__restrict__ mask, int nb) {
+    BATCH_BAND(nb)
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < p.npw) p.psi[(int64_t)b * p.ldpsi + g] = p.blk[kBX][(int64_t)b * p.ld + g];
+}
+#undef BATCH_BAND
+
+__global__ void kb_gather(const BandProb *__restrict__ probs, int nb, double *__restrict__ out,
+                          int *__restrict__ sout) {
+    const BandProb &p = probs[blockIdx.x];
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) out[(int64_t)blockIdx.x * 2 * nb + i] = p.vec[13 * nb + i];
+    if (threadIdx.x < 8) sout[blockIdx.x * 8 + threadIdx.x] = p.status[threadIdx.x];
+}
+
+void band_batch_save(const BandProb *probs, const int *mask, int nprob, int nb, int maxnpw, hipStream_t st) {
+    hipLaunchKernelGGL(kb_save, dim3((maxnpw + 255) / 256, nprob * nb), dim3(256), 0, st, probs, mask, nb);
+    PW_LAUNCH_CHECK();
+}
+
+void band_batch_gather(const BandProb *probs, int nprob, int nb, double *out, int *sout, hipStream_t st) {
+    hipLaunchKernelGGL(kb_gather, dim3(nprob), dim3(256), 0, st, probs, nb, out, sout);
+    PW_LAUNCH_CHECK();
+}
+
+void band_batch(BandOp op, const BandProb *probs, const int *mask, int nprob, int nb, int maxsplit, int maxnpw,
+                hipStream_t st, int a0, int a1) {
+    const dim3 red(maxsplit, nprob * nb), vec((maxnpw + 255) / 256, nprob * nb);
+    const dim3 fin((4 * nb + 255) / 256, nprob), sc((nb + 255) / 256, nprob);
+    switch (op) {
+        case BandOp::MuTband:
+            hipLaunchKernelGGL(kb_mu_tband, red, dim3(RT), 0, st, probs, mask, nb);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_finish, fin, dim3(256), 0, st, probs, mask, nb, 2, 0);   // mu, tband
+            break;
+        case BandOp::Grad:
+            hipLaunchKernelGGL(kb_grad, red, dim3(RT), 0, st, probs, mask, nb);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_finish, fin, dim3(256), 0, st, probs, mask, nb, 2, 2);   // gz, gzo
+            break;
+        case BandOp::GzOld:
+            hipLaunchKernelGGL(kb_gzold, red, dim3(RT), 0, st, probs, mask, nb);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_finish, fin, dim3(256), 0, st, probs, mask, nb, 1, 4);   // gz_old
+            break;
+        case BandOp::PUpdate:
+            hipLaunchKernelGGL(kb_pupdate, vec, dim3(256), 0, st, probs, mask, nb);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_scalars, sc, dim3(256), 0, st, probs, mask, nb, 0);
+            break;
+        case BandOp::Line:
+            hipLaunchKernelGGL(kb_line, red, dim3(RT), 0, st, probs, mask, nb);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_finish, fin, dim3(256), 0, st, probs, mask, nb, 4, 5);   // line4
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_scalars, sc, dim3(256), 0, st, probs, mask, nb, 1);       // coef
+            break;
+        case BandOp::Combine3:
+            hipLaunchKernelGGL(kb_combine3, vec, dim3(256), 0, st, probs, mask, nb);
+            break;
+        case BandOp::Resid:   // res = ||blk[a0] - lam blk[a1]||
+            hipLaunchKernelGGL(kb_resid, red, dim3(RT), 0, st, probs, mask, nb, a0, a1);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_finish, fin, dim3(256), 0, st, probs, mask, nb, 1, 14);
+            PW_LAUNCH_CHECK();
+            hipLaunchKernelGGL(kb_scalars, sc, dim3(256), 0, st, probs, mask, nb, 2);
+            break;
+    }
+    PW_LAUNCH_CHECK();
+}
+
+void band_batch_copy(const BandProb *probs, const int *mask, int nprob, int nb, int maxnpw, int n, const int *src,
+                     const int *dst, hipStream_t st) {
+    PW_CHECK(n >= 1 && n <= 4, PW_EINVAL, "batched copy of 1..4 blocks");
+    int4 s4{src[0], n > 1 ? src[1] : 0, n > 2 ? src[2] : 0, n > 3 ? src[3] : 0};
+    int4 d4{dst[0], n > 1 ? dst[1] : 0, n > 2 ? dst[2] : 0, n > 3 ? dst[3] : 0};
+    hipLaunchKernelGGL(kb_copy, dim3((maxnpw + 255) / 256, nprob * nb, n), dim3(256), 0, st, probs, mask, nb, s4, d4);
     PW_LAUNCH_CHECK();
 }
 
@@ -360,6 +577,7 @@ __global__ __launch_bounds__(RT) void k_lin_mdiag(int nb, int npw, const double2
                                                   const double2 *__restrict__ U, double2 *__restrict__ Z, int64_t ld,
                                                   const double *__restrict__ kin, double e_ref, double de2,
                                                   double *partial, int nsplit) {
+    const int b = blockIdx.y, split = blockIdx.x;
     double acc[1] = {0};
     BAND_LOOP(npw) {
         const int64_t i = (int64_t)b * ld + g;
@@ -382,6 +600,7 @@ __global__ __launch_bounds__(RT) void k_lin_mdiag(int nb, int npw, const double2
 __global__ __launch_bounds__(RT) void k_lin_rz(int nb, int npw, const double2 *__restrict__ R,
                                                const double2 *__restrict__ Z, int64_t ld, double *partial,
                                                int nsplit) {
+    const int b = blockIdx.y, split = blockIdx.x;
     double acc[1] = {0};
     BAND_LOOP(npw) {
         const int64_t i = (int64_t)b * ld + g;
@@ -465,6 +684,7 @@ void lin_coef(int nrhs, int nev, const void *C, const void *D, const double *inv
 __global__ __launch_bounds__(RT) void k_lin_err(int nb, int npw, const double2 *__restrict__ Y, int64_t ldy,
                                                 const double2 *__restrict__ W, int64_t ldw, double *partial,
                                                 int nsplit) {
+    const int b = blockIdx.y, split = blockIdx.x;
     double acc[1] = {0};
     BAND_LOOP(npw) {
         const double2 y = Y[(int64_t)b * ldy + g], w = W[(int64_t)b * ldw + g];

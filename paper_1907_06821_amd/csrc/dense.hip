@@ -52,9 +52,9 @@ __device__ inline void tri_rc(int q, int &i, int &k) {
 // which turns the diagonal into sqrt(L_kk) as well.  Inverse in place by block
 // rows of 16 (nine barrier rounds at N = 136 instead of two per column).
 template <int NT>
-__global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
-                                                          double2 *__restrict__ T, int64_t ldt, int pivot_base,
-                                                          int *__restrict__ status) {
+__device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restrict__ S, int64_t lds,
+                                                  double2 *__restrict__ T, int64_t ldt, int pivot_base,
+                                                  int *__restrict__ status) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);
     __shared__ double sd[kLdsMaxN];
@@ -178,6 +178,22 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *
         const double2 v = c <= i ? L[tri(i, c)] : make_double2(0.0, 0.0);
         T[(int64_t)i * ldt + c] = make_double2(v.x, -v.y);
     }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void chol_inv_lds_kernel(int N, const double2 *__restrict__ S, int64_t lds,
+                                                          double2 *__restrict__ T, int64_t ldt, int pivot_base,
+                                                          int *__restrict__ status) {
+    chol_inv_lds_body<NT>(N, S, lds, T, ldt, pivot_base, status);
+}
+
+// one problem per workgroup (batched folded-CG runs); masked problems return at once
+template <int NT>
+__global__ __launch_bounds__(NT) void chol_inv_lds_jobs(const DenseJob *__restrict__ jobs,
+                                                        const int *__restrict__ mask) {
+    if (!mask[blockIdx.x]) return;
+    const DenseJob &j = jobs[blockIdx.x];
+    chol_inv_lds_body<NT>(j.N, j.A, j.lda, j.T, j.ldt, 0, j.status);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,10 +843,10 @@ __device__ void dc_block(int N, double *d, double *e, double *Zt, double *V, dou
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
-                                                            double2 *__restrict__ hv, double *__restrict__ zg,
-                                                            int *__restrict__ rank, double *__restrict__ lam, int key,
-                                                            double ref, int *__restrict__ info) {
+__device__ __forceinline__ void tridiag_ql_lds_body(int N, const double2 *__restrict__ Ain, int64_t lda,
+                                                    double2 *__restrict__ hv, double *__restrict__ zg,
+                                                    int *__restrict__ rank, double *__restrict__ lam, int key,
+                                                    double ref, int *__restrict__ info) {
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);     // packed lower triangle of A
     __shared__ double2 v[kLdsMaxN], w[kLdsMaxN];
@@ -923,6 +939,22 @@ __global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2
     // the triangle is dead: its LDS becomes the divide and conquer's scratch
     dc_block<NT>(N, d, e, zg, zg + (size_t)N * N, zg + 2 * (size_t)N * N, smem_raw, nullptr, nullptr, true, lam, rank,
                  key, ref, info);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void tridiag_ql_lds_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
+                                                            double2 *__restrict__ hv, double *__restrict__ zg,
+                                                            int *__restrict__ rank, double *__restrict__ lam, int key,
+                                                            double ref, int *__restrict__ info) {
+    tridiag_ql_lds_body<NT>(N, Ain, lda, hv, zg, rank, lam, key, ref, info);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void tridiag_ql_lds_jobs(const DenseJob *__restrict__ jobs,
+                                                          const int *__restrict__ mask) {
+    if (!mask[blockIdx.x]) return;
+    const DenseJob &j = jobs[blockIdx.x];
+    tridiag_ql_lds_body<NT>(j.N, j.A, j.lda, j.hv, j.zbuf, j.rank, j.lam, 0, 0.0, j.info);
 }
 
 // Same algorithm for N <= kEigMaxN.  Ag: N x N work copy of A (full Hermitian,
@@ -1027,10 +1059,9 @@ __global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const doub
 // LDS_V: all reflectors staged in LDS (N <= kLdsMaxN); otherwise read from
 // global memory one reflector ahead.
 template <int NW, int NMAX, bool LDS_V>
-__global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const double2 *__restrict__ hv,
-                                                                const double *__restrict__ zg,
-                                                                const int *__restrict__ rank,
-                                                                double2 *__restrict__ R) {
+__device__ __forceinline__ void backtransform_body(int N, const double2 *__restrict__ hv,
+                                                   const double *__restrict__ zg, const int *__restrict__ rank,
+                                                   double2 *__restrict__ R, int bx) {
     extern __shared__ unsigned char smem_raw[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int tau_off = N * (N - 1) / 2;
@@ -1042,7 +1073,7 @@ __global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const dou
         sv = s;
     }
     constexpr int Q = (NMAX + 63) / 64;
-    const int m = blockIdx.x * NW + wid;
+    const int m = bx * NW + wid;
     if (m >= N) return;
     double2 y[Q];
 #pragma unroll
@@ -1078,6 +1109,23 @@ __global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const dou
         const int r = lane + 64 * q;
         if (r < N) R[row + r] = y[q];
     }
+}
+
+template <int NW, int NMAX, bool LDS_V>
+__global__ __launch_bounds__(64 * NW) void backtransform_kernel(int N, const double2 *__restrict__ hv,
+                                                                const double *__restrict__ zg,
+                                                                const int *__restrict__ rank,
+                                                                double2 *__restrict__ R) {
+    backtransform_body<NW, NMAX, LDS_V>(N, hv, zg, rank, R, blockIdx.x);
+}
+
+template <int NW, int NMAX>
+__global__ __launch_bounds__(64 * NW) void backtransform_lds_jobs(const DenseJob *__restrict__ jobs,
+                                                                  const int *__restrict__ mask) {
+    if (!mask[blockIdx.y]) return;
+    const DenseJob &j = jobs[blockIdx.y];
+    if ((int)blockIdx.x * NW >= j.N) return;
+    backtransform_body<NW, NMAX, true>(j.N, j.hv, j.zbuf, j.rank, j.R, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1188,6 +1236,52 @@ void chol_inv(int N, const void *S_, int64_t lds, void *work, void *T_, int *sta
         zgemm_nn_launch(b, i0, i0, P, i0, T, N, 1.0, 0.0, PH, i0, st);                         // sums
         zgemm_nn_launch(b, i0, b, T + (size_t)i0 * N + i0, N, PH, i0, -1.0, 0.0, T + (size_t)i0 * N, N, st);
     }
+}
+
+// Batched small dense kernels (N <= kLdsMaxN, one workgroup per problem) for
+// batched folded-CG runs: the bodies of chol_inv's and dense_eigh's one-workgroup
+// path with each job's arguments (key 0).
+DenseJob dense_job(int N, const void *A, int64_t lda, void *work, double *lam, void *R, int *info, void *T,
+                   int *status) {
+    PW_CHECK(N >= 1 && N <= kLdsMaxN, PW_EUNSUPPORTED, "batched dense kernels need N <= %d", kLdsMaxN);
+    DenseJob j{};
+    j.N = N;
+    j.A = (const double2 *)A;
+    j.lda = lda;
+    j.T = (double2 *)T;
+    j.ldt = N;
+    j.status = status;
+    j.hv = (double2 *)work;
+    j.zbuf = (double *)(j.hv + ((size_t)N * (N - 1) / 2 + N));
+    j.rank = (int *)((char *)j.zbuf + (size_t)24 * N * N);
+    j.lam = lam;
+    j.R = (double2 *)R;
+    j.info = info;
+    return j;
+}
+
+void chol_inv_jobs(int N, const DenseJob *jobs, const int *mask, int njobs, hipStream_t st) {
+    PW_CHECK(N >= 1 && N <= kLdsMaxN, PW_EUNSUPPORTED, "batched Cholesky needs N <= %d", kLdsMaxN);
+    const size_t bytes = (size_t)N * (N + 1) / 2 * sizeof(double2);
+    static size_t attr_bytes = 64 * 1024;
+    lds_limit(reinterpret_cast<const void *>(chol_inv_lds_jobs<1024>), bytes, attr_bytes);
+    hipLaunchKernelGGL(chol_inv_lds_jobs<1024>, dim3(njobs), dim3(1024), bytes, st, jobs, mask);
+    PW_LAUNCH_CHECK();
+}
+
+void dense_eigh_jobs(int N, const DenseJob *jobs, const int *mask, int njobs, hipStream_t st) {
+    PW_CHECK(N >= 1 && N <= kLdsMaxN, PW_EUNSUPPORTED, "batched eigensolver needs N <= %d", kLdsMaxN);
+    const size_t dcb = dc_round(dc_lds_bytes(N, kEigNT / 64, true)) + dc_wave_bytes(N, kEigNT / 64);
+    const size_t b1 = std::max((size_t)N * (N + 1) / 2 * sizeof(double2), dcb);
+    static size_t attr1 = 64 * 1024, attr2 = 64 * 1024;
+    lds_limit(reinterpret_cast<const void *>(tridiag_ql_lds_jobs<kEigNT>), b1, attr1);
+    hipLaunchKernelGGL(tridiag_ql_lds_jobs<kEigNT>, dim3(njobs), dim3(kEigNT), b1, st, jobs, mask);
+    PW_LAUNCH_CHECK();
+    const size_t b2 = std::max<size_t>(1, (size_t)N * (N - 1) / 2 + N - 1) * sizeof(double2);
+    lds_limit(reinterpret_cast<const void *>(backtransform_lds_jobs<kBackNW, kLdsMaxN>), b2, attr2);
+    hipLaunchKernelGGL((backtransform_lds_jobs<kBackNW, kLdsMaxN>), dim3((N + kBackNW - 1) / kBackNW, njobs),
+                       dim3(64 * kBackNW), b2, st, jobs, mask);
+    PW_LAUNCH_CHECK();
 }
 
 size_t dense_eigh_work_bytes(int N) {

@@ -20,6 +20,8 @@
 #include <tuple>
 #include <mutex>
 #include <map>
+#include <deque>
+#include <memory>
 
 namespace pw {
 
@@ -44,6 +46,20 @@ struct XYArgs {
     const void *vz;           // [n2][n0][n1] potential, z-major (or null)
 };
 
+// one problem of a batched H psi (hpsi_batch below): its FFT arguments and blocks
+struct FftJob {
+    ZArgs z;
+    XYArgs xy;
+    int prob;                 // index into the problems' mask
+    const void *in;           // sphere block (z inverse input, kinetic term of the z forward pass)
+    int64_t ld;
+    void *cols;               // the problem's column grid
+    const double *kin;
+    double shift, scale;
+    void *out;
+    int64_t ldo;
+};
+
 template <typename T> __device__ inline void load_tw(cplx<T> *dst, const cplx<T> *src, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
@@ -52,13 +68,12 @@ template <typename T> __device__ inline void load_tw(cplx<T> *dst, const cplx<T>
 // z pass, inverse: sphere -> column grid
 // ---------------------------------------------------------------------------
 template <typename T, int NTHR, typename LZ>
-__global__ __launch_bounds__(NTHR) void zpass_inv(ZArgs a, const cplx<T> *__restrict__ psi, int64_t ld,
-                                                  cplx<T> *__restrict__ cols) {
+__device__ __forceinline__ void zinv_body(const ZArgs &a, const cplx<T> *__restrict__ psi, int64_t ld,
+                                          cplx<T> *__restrict__ cols, int cb, int b) {
     extern __shared__ unsigned char smem_raw[];
     const int n2 = LZ::N > 0 ? LZ::N : a.n2;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *buf = tw + n2;
-    const int cb = blockIdx.x, b = blockIdx.y;
     const int c0 = cb * a.cb;
     const int c1 = min(c0 + a.cb, a.ncols);
     const int nc = c1 - c0;
@@ -93,20 +108,37 @@ __global__ __launch_bounds__(NTHR) void zpass_inv(ZArgs a, const cplx<T> *__rest
     }
 }
 
+template <typename T, int NTHR, typename LZ>
+__global__ __launch_bounds__(NTHR) void zpass_inv(ZArgs a, const cplx<T> *__restrict__ psi, int64_t ld,
+                                                  cplx<T> *__restrict__ cols) {
+    zinv_body<T, NTHR, LZ>(a, psi, ld, cols, blockIdx.x, blockIdx.y);
+}
+
+// Batched launches over independent problems (one FftJob each, blockIdx.y = job x
+// nb + band; masked jobs and blocks beyond a job's extent return at once): the
+// bodies of the single-problem kernels with each job's arguments.
+template <typename T, int NTHR, typename LZ>
+__global__ __launch_bounds__(NTHR) void zpass_inv_jobs(const FftJob *__restrict__ jobs, const int *__restrict__ mask,
+                                                       int nb) {
+    const FftJob &j = jobs[blockIdx.y / nb];
+    if (!mask[j.prob] || (int)blockIdx.x * j.z.cb >= j.z.ncols) return;
+    zinv_body<T, NTHR, LZ>(j.z, reinterpret_cast<const cplx<T> *>(j.in), j.ld, reinterpret_cast<cplx<T> *>(j.cols),
+                           blockIdx.x, blockIdx.y % nb);
+}
+
 // ---------------------------------------------------------------------------
 // z pass, forward: column grid -> sphere, with (1/N) and the kinetic epilogue
 //   out[g] = scale * FFT(cols)[g] + (kin[g] - shift) * psi[g]   (kin may be null)
 // ---------------------------------------------------------------------------
 template <typename T, int NTHR, typename LZ>
-__global__ __launch_bounds__(NTHR) void zpass_fwd(ZArgs a, const cplx<T> *__restrict__ cols,
-                                                  const cplx<T> *__restrict__ psi, int64_t ld,
-                                                  const double *__restrict__ kin, double shift, double scale,
-                                                  cplx<T> *__restrict__ out, int64_t ldo) {
+__device__ __forceinline__ void zfwd_body(const ZArgs &a, const cplx<T> *__restrict__ cols,
+                                          const cplx<T> *__restrict__ psi, int64_t ld,
+                                          const double *__restrict__ kin, double shift, double scale,
+                                          cplx<T> *__restrict__ out, int64_t ldo, int cb, int b) {
     extern __shared__ unsigned char smem_raw[];
     const int n2 = LZ::N > 0 ? LZ::N : a.n2;
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *buf = tw + n2;
-    const int cb = blockIdx.x, b = blockIdx.y;
     const int c0 = cb * a.cb;
     const int c1 = min(c0 + a.cb, a.ncols);
     const int nc = c1 - c0;
@@ -155,20 +187,38 @@ __global__ __launch_bounds__(NTHR) void zpass_fwd(ZArgs a, const cplx<T> *__rest
     }
 }
 
+template <typename T, int NTHR, typename LZ>
+__global__ __launch_bounds__(NTHR) void zpass_fwd(ZArgs a, const cplx<T> *__restrict__ cols,
+                                                  const cplx<T> *__restrict__ psi, int64_t ld,
+                                                  const double *__restrict__ kin, double shift, double scale,
+                                                  cplx<T> *__restrict__ out, int64_t ldo) {
+    zfwd_body<T, NTHR, LZ>(a, cols, psi, ld, kin, shift, scale, out, ldo, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int NTHR, typename LZ>
+__global__ __launch_bounds__(NTHR) void zpass_fwd_jobs(const FftJob *__restrict__ jobs, const int *__restrict__ mask,
+                                                       int nb) {
+    const FftJob &j = jobs[blockIdx.y / nb];
+    if (!mask[j.prob] || (int)blockIdx.x * j.z.cb >= j.z.ncols) return;
+    zfwd_body<T, NTHR, LZ>(j.z, reinterpret_cast<const cplx<T> *>(j.cols), reinterpret_cast<const cplx<T> *>(j.in),
+                           j.ld, j.kin, j.shift, j.scale, reinterpret_cast<cplx<T> *>(j.out), j.ldo, blockIdx.x,
+                           blockIdx.y % nb);
+}
+
 // ---------------------------------------------------------------------------
 // xy pass.  MODE 0: columns -> plane -> x V -> columns (in place)
 //           MODE 1: columns -> plane -> grid out [b][x][y][z]
 //           MODE 2: grid in [b][x][y][z] -> plane -> columns
 // ---------------------------------------------------------------------------
 template <typename T, int NTHR, int MODE, typename L0, typename L1>
-__global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ cols, cplx<T> *__restrict__ grid) {
+__device__ __forceinline__ void xy_pass_body(const XYArgs &a, cplx<T> *__restrict__ cols, cplx<T> *__restrict__ grid,
+                                             int z, int b) {
     extern __shared__ unsigned char smem_raw[];
     const int n0 = L0::N > 0 ? L0::N : a.n0;
     const int n1 = L1::N > 0 ? L1::N : a.n1;
     cplx<T> *tw0 = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *tw1 = tw0 + n0;
     cplx<T> *pl = tw1 + n1;
-    const int z = blockIdx.x, b = blockIdx.y;
     const int rs = n1 + 1;
     const int npl = n0 * n1;
     load_tw<T>(tw0, reinterpret_cast<const cplx<T> *>(a.tw0), n0);
@@ -210,6 +260,19 @@ __global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ 
     L0::template fft<T, NTHR, L1::N>(pl, a.plan0, gx, tw0, -1);
     L1::template fft<T, NTHR, 0>(pl, a.plan1, gy, tw1, -1);
     for (int c = threadIdx.x; c < a.ncols; c += NTHR) crow[c] = pl[a.colpos[c]];
+}
+
+template <typename T, int NTHR, int MODE, typename L0, typename L1>
+__global__ __launch_bounds__(NTHR) void xy_pass(XYArgs a, cplx<T> *__restrict__ cols, cplx<T> *__restrict__ grid) {
+    xy_pass_body<T, NTHR, MODE, L0, L1>(a, cols, grid, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int NTHR, typename L0, typename L1>
+__global__ __launch_bounds__(NTHR) void xy_pass_jobs(const FftJob *__restrict__ jobs, const int *__restrict__ mask,
+                                                     int nb) {
+    const FftJob &j = jobs[blockIdx.y / nb];
+    if (!mask[j.prob]) return;
+    xy_pass_body<T, NTHR, 0, L0, L1>(j.xy, reinterpret_cast<cplx<T> *>(j.cols), nullptr, blockIdx.x, blockIdx.y % nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,12 +424,11 @@ template <typename T, int M, int S> __device__ inline void quad_b(cplx<T> *v, co
 }
 
 template <typename T, int M, int NTHR>
-__global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ cols) {
+__device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restrict__ cols, int z, int b) {
     constexpr int L = 4 * M, RS = L + 1, NQ = NTHR / 4;
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);   // [L]
     cplx<T> *pl = tw + L;                                   // [nrows][RS], touched x rows only
-    const int z = blockIdx.x, b = blockIdx.y;
     const int tid = threadIdx.x, q = tid & 3, quad = tid >> 2;
     const int rq = ((q & 1) << 1) | (q >> 1);
     const int nrows = a.nrows, rowlo = a.rowlo;
@@ -440,6 +502,19 @@ __global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ 
     }
     __syncthreads();
     for (int c = tid; c < a.ncols; c += NTHR) crow[c] = pl[a.colslot[c]];
+}
+
+template <typename T, int M, int NTHR>
+__global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ cols) {
+    xy_quad_body<T, M, NTHR>(a, cols, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int M, int NTHR>
+__global__ __launch_bounds__(NTHR) void xy_quad_jobs(const FftJob *__restrict__ jobs, const int *__restrict__ mask,
+                                                     int nb) {
+    const FftJob &j = jobs[blockIdx.y / nb];
+    if (!mask[j.prob]) return;
+    xy_quad_body<T, M, NTHR>(j.xy, reinterpret_cast<cplx<T> *>(j.cols), blockIdx.x, blockIdx.y % nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -690,6 +765,219 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
         default: PW_CHECK(false, PW_EUNSUPPORTED, "xy FFT does not fit the register budget");
     }
     PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex128 H psi over independent problems (contexts) with the same
+// band count: the three FFT passes once per group of equal grids and the two
+// projector GEMMs once for all problems, each problem's mask entry deciding at
+// run time whether its blocks are touched.  Every problem sees the kernels,
+// launch shapes and split-K chunking of its own pw_hpsi call (default launch
+// choices, all its bands in one FFT chunk), so its result is bit for bit that of
+// its own call.
+// ---------------------------------------------------------------------------
+struct HpsiGroup {
+    std::vector<FftJob> h;
+    DevBuf d;
+    pw_ctx *rep;              // a context of the group (grid, launch choices)
+    size_t quad_lds = 0;
+};
+struct HpsiBatch {
+    int nb = 0, nprob = 0;
+    std::deque<HpsiGroup> groups;
+    std::vector<NtJob> nt;
+    std::vector<NnJob> nn;
+    DevBuf d_nt, d_nn;
+    const int *mask = nullptr;
+    int nn_cfg = -1;
+};
+
+template <typename T, int NTHR, typename LZ>
+static void zinv_jobs_go(const HpsiGroup &g, int nb, size_t lds, const int *mask, hipStream_t s) {
+    allow_lds(zpass_inv_jobs<T, NTHR, LZ>, lds);
+    int ncb = 1;
+    for (const FftJob &j : g.h) ncb = std::max(ncb, (j.z.ncols + j.z.cb - 1) / j.z.cb);
+    hipLaunchKernelGGL((zpass_inv_jobs<T, NTHR, LZ>), dim3(ncb, (unsigned)(g.h.size() * nb)), dim3(NTHR), lds, s,
+                       g.d.as<FftJob>(), mask, nb);
+}
+template <typename T, int NTHR, typename LZ>
+static void zfwd_jobs_go(const HpsiGroup &g, int nb, size_t lds, const int *mask, hipStream_t s) {
+    allow_lds(zpass_fwd_jobs<T, NTHR, LZ>, lds);
+    int ncb = 1;
+    for (const FftJob &j : g.h) ncb = std::max(ncb, (j.z.ncols + j.z.cb - 1) / j.z.cb);
+    hipLaunchKernelGGL((zpass_fwd_jobs<T, NTHR, LZ>), dim3(ncb, (unsigned)(g.h.size() * nb)), dim3(NTHR), lds, s,
+                       g.d.as<FftJob>(), mask, nb);
+}
+template <typename T> struct ZJobsGo {
+    const HpsiGroup &g; int nb; size_t lds; const int *mask; hipStream_t s; bool fwd;
+    template <typename LZ, int NT> void operator()() {
+        if (fwd) zfwd_jobs_go<T, NT, LZ>(g, nb, lds, mask, s);
+        else zinv_jobs_go<T, NT, LZ>(g, nb, lds, mask, s);
+    }
+};
+template <typename T, int M, int NTHR>
+static void quad_jobs_go(const HpsiGroup &g, int nb, const int *mask, hipStream_t s) {
+    allow_lds(xy_quad_jobs<T, M, NTHR>, g.quad_lds);
+    hipLaunchKernelGGL((xy_quad_jobs<T, M, NTHR>), dim3(g.rep->cell.n[2], (unsigned)(g.h.size() * nb)), dim3(NTHR),
+                       g.quad_lds, s, g.d.as<FftJob>(), mask, nb);
+}
+template <typename T, typename L0, typename L1, int NTHR>
+static void xy_jobs_go(const HpsiGroup &g, int nb, size_t lds, const int *mask, hipStream_t s) {
+    allow_lds(xy_pass_jobs<T, NTHR, L0, L1>, lds);
+    hipLaunchKernelGGL((xy_pass_jobs<T, NTHR, L0, L1>), dim3(g.rep->cell.n[2], (unsigned)(g.h.size() * nb)),
+                       dim3(NTHR), lds, s, g.d.as<FftJob>(), mask, nb);
+}
+
+// the xy pass of pw_hpsi's default choice for this group's grid (complex128)
+static void xy_jobs(const HpsiGroup &g, int nb, const int *mask, hipStream_t s) {
+    using T = double;
+    const XYArgs &a = g.h[0].xy;
+    if (xy_has_quad(a.n0, a.n1) && g.quad_lds <= 160 * 1024) {
+        switch (a.n0) {
+            case 16: quad_jobs_go<T, 4, 256>(g, nb, mask, s); break;
+            case 32: quad_jobs_go<T, 8, 256>(g, nb, mask, s); break;
+            case 48: quad_jobs_go<T, 12, 256>(g, nb, mask, s); break;
+            case 64: quad_jobs_go<T, 16, 256>(g, nb, mask, s); break;
+            case 96: quad_jobs_go<T, 24, 256>(g, nb, mask, s); break;
+            default: quad_jobs_go<T, 32, 256>(g, nb, mask, s); break;
+        }
+        PW_LAUNCH_CHECK();
+        return;
+    }
+    const size_t lds = sizeof(cplx<T>) * (a.n0 + a.n1 + (size_t)a.n0 * (a.n1 + 1));
+    PW_CHECK(lds <= 160 * 1024, PW_EUNSUPPORTED, "xy plane %dx%d does not fit LDS", a.n0, a.n1);
+    if (a.n0 == a.n1) {
+#define PW_XYJCASE(L)                                                                       \
+    case L: {                                                                               \
+        constexpr int t = ct_threads<T>(L, L);                                              \
+        if constexpr (t > 0) {                                                              \
+            xy_jobs_go<T, CtLen<L>, CtLen<L>, t>(g, nb, lds, mask, s);                      \
+            PW_LAUNCH_CHECK();                                                              \
+            return;                                                                         \
+        }                                                                                   \
+        break;                                                                              \
+    }
+        switch (a.n0) {
+            PW_XYJCASE(16) PW_XYJCASE(32) PW_XYJCASE(40) PW_XYJCASE(48) PW_XYJCASE(64) PW_XYJCASE(96) PW_XYJCASE(128)
+            default: break;
+        }
+#undef PW_XYJCASE
+    }
+    int nthr = 0;
+    for (int t : {256, 512, 1024})
+        if (fft_fits<T>(a.plan1, a.n0, t) && fft_fits<T>(a.plan0, a.n1, t)) { nthr = t; break; }
+    switch (nthr) {
+        case 256: xy_jobs_go<T, RtLen, RtLen, 256>(g, nb, lds, mask, s); break;
+        case 512: xy_jobs_go<T, RtLen, RtLen, 512>(g, nb, lds, mask, s); break;
+        case 1024: xy_jobs_go<T, RtLen, RtLen, 1024>(g, nb, lds, mask, s); break;
+        default: PW_CHECK(false, PW_EUNSUPPORTED, "xy FFT does not fit the register budget");
+    }
+    PW_LAUNCH_CHECK();
+}
+
+static bool default_choices(pw_ctx *c) {
+    const FftTune &t = c->tune[0];
+    return t.zinv.kind == 0 && t.xy.kind == 0 && t.zfwd.kind == 0;
+}
+
+bool hpsi_batch_ok(int n, pw_ctx *const *ctx, int nb, std::string *why) {
+    for (int p = 0; p < n; ++p) {
+        pw_ctx *c = ctx[p];
+        const char *w = nullptr;
+        if (!c->d_beta64.p && c->nproj) w = "no stored complex128 projector table";
+        else if (!default_choices(c)) w = "autotuned FFT launch choices";
+        else if (c->cols_bands < nb || c->max_bands < nb) w = "bands beyond one FFT chunk";
+        else if (c->nn_tune.get(nb) >= 0 || c->rot_tune.get(nb) >= 0) w = "autotuned GEMM tiles";
+        if (w) {
+            if (why) *why = w;
+            return false;
+        }
+    }
+    return true;
+}
+
+HpsiBatch *hpsi_batch_create(int n, pw_ctx *const *ctx, int nb, void *const *in, const int64_t *ld,
+                             void *const *out, const int64_t *ldo, const double *shift, const int *mask) {
+    std::unique_ptr<HpsiBatch> B(new HpsiBatch);
+    B->nb = nb;
+    B->nprob = n;
+    B->mask = mask;
+    std::map<std::tuple<int, int, int>, int> gid;
+    for (int p = 0; p < n; ++p) {
+        pw_ctx *c = ctx[p];
+        const auto key = std::make_tuple(c->cell.n[0], c->cell.n[1], c->cell.n[2]);
+        auto it = gid.find(key);
+        if (it == gid.end()) {
+            it = gid.emplace(key, (int)B->groups.size()).first;
+            B->groups.emplace_back();
+            B->groups.back().rep = c;
+        }
+        HpsiGroup &g = B->groups[it->second];
+        FftJob j{};
+        j.z = zargs<double>(c, nb);
+        j.xy = xyargs<double>(c);
+        j.prob = p;
+        j.in = in[p];
+        j.ld = ld[p];
+        j.cols = c->d_cols.p;
+        j.kin = c->d_kin.as<double>();
+        j.shift = shift[p];
+        j.scale = 1.0 / ((double)c->cell.n[0] * c->cell.n[1] * c->cell.n[2]);
+        j.out = out[p];
+        j.ldo = ldo[p];
+        g.quad_lds = std::max(g.quad_lds, quad_lds<double>(j.xy));
+        g.h.push_back(j);
+        if (c->nproj) {
+            B->nt.push_back(nt_job(c->nproj, nb, c->basis.npw, true, c->d_beta64.p, c->basis.npw, in[p], ld[p], 1.0,
+                                   c->d_dproj.as<double>(), 0.0, c->d_proj.p, c->nproj, c->d_partial.p, false));
+            NnJob q{};
+            q.M = nb; q.J = c->basis.npw; q.K = c->nproj; q.nz = 1; q.lower = 0;
+            q.W = c->d_proj.as<double2>(); q.ldw = c->nproj;
+            q.X[0] = c->d_beta64.as<double2>(); q.Out[0] = (double2 *)out[p];
+            q.ldx = c->basis.npw; q.ldo = ldo[p]; q.alpha = 1.0; q.beta = 1.0;
+            B->nn.push_back(q);
+        } else {
+            // keep the job index equal to the problem index: an empty job the kernels skip
+            NtJob e{};
+            e.M = 0; e.N = 0; e.nsplit = 0;
+            B->nt.push_back(e);
+            NnJob q{};
+            B->nn.push_back(q);
+        }
+    }
+    for (HpsiGroup &g : B->groups) {
+        g.d.alloc(g.h.size() * sizeof(FftJob));
+        PW_HIP(hipMemcpy(g.d.p, g.h.data(), g.h.size() * sizeof(FftJob), hipMemcpyHostToDevice));
+    }
+    B->d_nt.alloc(B->nt.size() * sizeof(NtJob));
+    PW_HIP(hipMemcpy(B->d_nt.p, B->nt.data(), B->nt.size() * sizeof(NtJob), hipMemcpyHostToDevice));
+    B->d_nn.alloc(B->nn.size() * sizeof(NnJob));
+    PW_HIP(hipMemcpy(B->d_nn.p, B->nn.data(), B->nn.size() * sizeof(NnJob), hipMemcpyHostToDevice));
+    return B.release();
+}
+
+void hpsi_batch_destroy(HpsiBatch *b) { delete b; }
+
+void hpsi_batch_run(HpsiBatch *B, hipStream_t s) {
+    using T = double;
+    const int nb = B->nb;
+    for (const HpsiGroup &g : B->groups) {
+        const ZArgs &a = g.h[0].z;
+        const size_t lds = sizeof(cplx<T>) * (a.n2 + (size_t)a.cb * (a.n2 + 1));
+        const int nthr = pick_threads<T>(a.plan, a.cb);
+        ZJobsGo<T> inv{g, nb, lds, B->mask, s, false};
+        with_zlen<T>(a.n2, nthr, false, inv);
+        PW_LAUNCH_CHECK();
+        xy_jobs(g, nb, B->mask, s);
+        ZJobsGo<T> fwd{g, nb, lds, B->mask, s, true};
+        with_zlen<T>(a.n2, nthr, false, fwd);
+        PW_LAUNCH_CHECK();
+    }
+    bool any = false;
+    for (size_t q = 0; q < B->nt.size(); ++q) any = any || B->nt[q].M > 0;
+    if (!any) return;
+    zgemm_nt_jobs(B->nt, B->d_nt.as<NtJob>(), B->mask, true, true, true, s);
+    zgemm_nn_jobs_launch(B->nn, B->d_nn.as<NnJob>(), B->mask, -1, true, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,17 +39,17 @@ __device__ inline void cmfma(const double2 a, const double2 b, v4d &ar, v4d &ai)
 // op = conj when CONJA.  Waves WM x WN, each BM x BN blocks of 16 x 16.
 // ---------------------------------------------------------------------------
 // TAG only separates the projector launches from the block-algebra ones in profiles
-template <int WM, int WN, int BM, int BN, bool CONJA, int TAG>
-__global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, int K, const double2 *__restrict__ A,
-                                                                 int64_t lda, const double2 *__restrict__ B,
-                                                                 int64_t ldb, int kchunk,
-                                                                 double2 *__restrict__ partial, int herm) {
+// one tile (bm, bn) of split s; the batched kernel below runs the same body
+template <int WM, int WN, int BM, int BN, bool CONJA>
+__device__ __forceinline__ void nt_partial_tile(int M, int N, int K, const double2 *__restrict__ A, int64_t lda,
+                                                const double2 *__restrict__ B, int64_t ldb, int kchunk,
+                                                double2 *__restrict__ partial, int herm, int bm, int bn, int s) {
     constexpr int NT = WM * WN * 64;
     constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
     constexpr int LA = (TM * KT + NT - 1) / NT, LB = (TN * KT + NT - 1) / NT;   // loads per thread per stage
     __shared__ double2 As[TM][KT + 1];
     __shared__ double2 Bs[TN][KT + 1];
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN, s = blockIdx.z;
+    const int m0 = bm * TM, n0 = bn * TN;
     // herm (A = B): the result is Hermitian, so tiles wholly above the diagonal are left
     // to the reduction, which takes them from their mirror images
     if (herm && n0 > m0 + TM - 1) return;
@@ -130,6 +130,31 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
             }
 }
 
+template <int WM, int WN, int BM, int BN, bool CONJA, int TAG>
+__global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, int K, const double2 *__restrict__ A,
+                                                                 int64_t lda, const double2 *__restrict__ B,
+                                                                 int64_t ldb, int kchunk,
+                                                                 double2 *__restrict__ partial, int herm) {
+    nt_partial_tile<WM, WN, BM, BN, CONJA>(M, N, K, A, lda, B, ldb, kchunk, partial, herm, blockIdx.x, blockIdx.y,
+                                           blockIdx.z);
+}
+
+// Several independent problems in one launch (one job each, blockIdx.z = job x
+// maxsplit + split; jobs whose mask entry is 0 and tiles beyond a job's own
+// extent return at once).  Every tile runs the body of the single-problem kernel
+// with that job's arguments, so each job's result is bit for bit the same.
+template <int WM, int WN, int BM, int BN, bool CONJA, int TAG>
+__global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial_jobs(const NtJob *__restrict__ jobs,
+                                                                      const int *__restrict__ mask, int maxsplit) {
+    constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
+    const int q = blockIdx.z / maxsplit, s = blockIdx.z % maxsplit;
+    if (!mask[q]) return;
+    const NtJob &j = jobs[q];
+    if (s >= j.nsplit || (int)blockIdx.x * TM >= j.M || (int)blockIdx.y * TN >= j.N) return;
+    nt_partial_tile<WM, WN, BM, BN, CONJA>(j.M, j.N, j.K, j.A, j.lda, j.B, j.ldb, j.kchunk, j.partial, j.herm,
+                                           blockIdx.x, blockIdx.y, s);
+}
+
 // out = alpha * rowscale[m] * sum_s partial[s][m][n] (+ beta * out); TRANS writes out[n][m].
 // A workgroup of 256 threads takes 64 consecutive elements: wave g sums the
 // splits s = g (mod 4) for each, then wave 0 adds the four sums in order (fixed
@@ -139,16 +164,13 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
 constexpr int kRedElems = 64, kRedGroups = 4;
 
 template <bool TRANS>
-__global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial(int M, int N, int nsplit,
-                                                                         const double2 *__restrict__ partial,
-                                                                         double alpha,
-                                                                         const double *__restrict__ rowscale,
-                                                                         double beta, double2 *__restrict__ out,
-                                                                         int64_t ldo, int herm) {
+__device__ __forceinline__ void reduce_block(int M, int N, int nsplit, const double2 *__restrict__ partial,
+                                             double alpha, const double *__restrict__ rowscale, double beta,
+                                             double2 *__restrict__ out, int64_t ldo, int herm, int blk) {
     __shared__ double2 sum[kRedGroups][kRedElems];
     const int e = threadIdx.x % kRedElems, g = threadIdx.x / kRedElems;
     const int64_t tot = (int64_t)M * N;
-    const int64_t idx = (int64_t)blockIdx.x * kRedElems + e;
+    const int64_t idx = (int64_t)blk * kRedElems + e;
     const int m_ = (int)(idx / N), n_ = (int)(idx % N);
     const bool mirror = herm && n_ > m_;
     const int64_t src = mirror ? (int64_t)n_ * N + m_ : idx;
@@ -180,6 +202,25 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial(int M, 
     }
 }
 
+template <bool TRANS>
+__global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial(int M, int N, int nsplit,
+                                                                         const double2 *__restrict__ partial,
+                                                                         double alpha,
+                                                                         const double *__restrict__ rowscale,
+                                                                         double beta, double2 *__restrict__ out,
+                                                                         int64_t ldo, int herm) {
+    reduce_block<TRANS>(M, N, nsplit, partial, alpha, rowscale, beta, out, ldo, herm, blockIdx.x);
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(kRedElems * kRedGroups) void reduce_partial_jobs(const NtJob *__restrict__ jobs,
+                                                                              const int *__restrict__ mask) {
+    if (!mask[blockIdx.y]) return;
+    const NtJob &j = jobs[blockIdx.y];
+    if ((int64_t)blockIdx.x * kRedElems >= (int64_t)j.M * j.N) return;
+    reduce_block<TRANS>(j.M, j.N, j.nsplit, j.partial, j.alpha, j.rowscale, j.beta, j.C, j.ldc, j.herm, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // NN: Out_z[m][j] = alpha * sum_k W[m][k] X_z[k][j] + beta * Out_z[m][j]
 // for up to 4 (X_z, Out_z) pairs sharing W (blockIdx.z).  Waves WM x WJ, each
@@ -190,18 +231,16 @@ struct NNBatch {
     double2 *Out[4];
 };
 
-template <int WM, int WJ, int BM, int BJ, int TAG, int KD>
-__global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, int K, const double2 *__restrict__ W,
-                                                                int64_t ldw, NNBatch bt, int64_t ldx, double alpha,
-                                                                double beta, int64_t ldo, int lower) {
+template <int WM, int WJ, int BM, int BJ, int KD>
+__device__ __forceinline__ void nn_tile(int M, int J, int K, const double2 *__restrict__ W, int64_t ldw,
+                                        const double2 *__restrict__ X, double2 *__restrict__ Out, int64_t ldx,
+                                        double alpha, double beta, int64_t ldo, int lower, int bj, int bm) {
     constexpr int NT = WM * WJ * 64;
     constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
     constexpr int LW = (TM * KD + NT - 1) / NT, LX = (KD * TJ + NT - 1) / NT;
     __shared__ double2 Ws[TM][KD + 1];
     __shared__ double2 Xs[KD][TJ + 1];
-    const double2 *__restrict__ X = bt.X[blockIdx.z];
-    double2 *__restrict__ Out = bt.Out[blockIdx.z];
-    const int j0 = blockIdx.x * TJ, m0 = blockIdx.y * TM;
+    const int j0 = bj * TJ, m0 = bm * TM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wj = wave / WM;
     v4d accr[BM][BJ], acci[BM][BJ];
@@ -281,6 +320,27 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, in
             }
 }
 
+template <int WM, int WJ, int BM, int BJ, int TAG, int KD>
+__global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_kernel(int M, int J, int K, const double2 *__restrict__ W,
+                                                                int64_t ldw, NNBatch bt, int64_t ldx, double alpha,
+                                                                double beta, int64_t ldo, int lower) {
+    nn_tile<WM, WJ, BM, BJ, KD>(M, J, K, W, ldw, bt.X[blockIdx.z], bt.Out[blockIdx.z], ldx, alpha, beta, ldo, lower,
+                                blockIdx.x, blockIdx.y);
+}
+
+// several problems in one launch: blockIdx.z = job x 4 + block of the job
+template <int WM, int WJ, int BM, int BJ, int TAG, int KD>
+__global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_jobs(const NnJob *__restrict__ jobs,
+                                                             const int *__restrict__ mask) {
+    constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
+    const int q = blockIdx.z / 4, z = blockIdx.z % 4;
+    if (!mask[q]) return;
+    const NnJob &j = jobs[q];
+    if (z >= j.nz || (int)blockIdx.x * TJ >= j.J || (int)blockIdx.y * TM >= j.M) return;
+    nn_tile<WM, WJ, BM, BJ, KD>(j.M, j.J, j.K, j.W, j.ldw, j.X[z], j.Out[z], j.ldx, j.alpha, j.beta, j.ldo, j.lower,
+                                blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
@@ -302,10 +362,21 @@ static int nt_tm(int M, int N) {
 
 // K-splits: enough workgroups to cover the chip (~512) while keeping at least
 // four LDS stages per chunk and the partial sums under 64 MiB.
-int nt_splits(int M, int N, int K) {
+int nt_splits(int M, int N, int K, bool herm) {
     const int tn = nt_tn(N), tm = nt_tm(M, N);
-    const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
+    const int mt = (M + tm - 1) / tm, ntl = (N + tn - 1) / tn;
+    const int tiles = mt * ntl;
     int s = (512 + tiles - 1) / tiles;
+    if (herm) {
+        // a Gram matrix computes only the tiles that reach the diagonal: as many
+        // splits as fill the 256 compute units once (more would start a second,
+        // mostly idle round of workgroups)
+        int live = 0;
+        for (int i = 0; i < mt; ++i)
+            for (int j = 0; j < ntl; ++j) live += (j * tn <= i * tm + tm - 1) ? 1 : 0;
+        if (live * 2 <= 256) s = std::min(s, std::max(1, 256 / live));
+        else s = std::min(s, std::max(1, 512 / live));
+    }
     const int maxs = (K + 4 * KT - 1) / (4 * KT);
     if (s > maxs) s = maxs;
     const int64_t cap = (int64_t)(64 << 20) / ((int64_t)M * N * (int64_t)sizeof(double2));
@@ -340,7 +411,7 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     if (M <= 0 || N <= 0) return;
     // a Gram matrix A^H A: half the tiles (alpha real, no row scale)
     const int herm = (herm_in && conja && A == B && lda == ldb && M == N && !rowscale) ? 1 : 0;
-    const int ns = nt_splits(M, N, K);
+    const int ns = nt_splits(M, N, K, herm != 0);
     int kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + KT - 1) / KT) * KT;
     const int nsplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
@@ -367,6 +438,78 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     else
         hipLaunchKernelGGL((reduce_partial<false>), dim3(nblk), rblk, 0, st, M, N, nsplit, (const double2 *)partial,
                            alpha, rowscale, beta, (double2 *)C, ldc, herm);
+    PW_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches over independent problems (one job each): the tile shape and
+// split-K chunking of every job are those zgemm_nt / zgemm_nn_batch would pick for
+// it alone, so each job's result is bit for bit that of its own call.
+// ---------------------------------------------------------------------------
+NtJob nt_job(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb, double alpha,
+             const double *rowscale, double beta, void *C, int64_t ldc, void *partial, bool herm_in) {
+    PW_CHECK(M > 0 && N > 0 && K > 0, PW_EINVAL, "batched NT GEMM needs positive sizes");
+    NtJob j{};
+    j.M = M; j.N = N; j.K = K;
+    j.herm = (herm_in && conja && A == B && lda == ldb && M == N && !rowscale) ? 1 : 0;
+    const int ns = nt_splits(M, N, K, j.herm != 0);
+    j.kchunk = ((K + ns - 1) / ns + KT - 1) / KT * KT;
+    j.nsplit = (K + j.kchunk - 1) / j.kchunk;
+    j.A = (const double2 *)A; j.lda = lda;
+    j.B = (const double2 *)B; j.ldb = ldb;
+    j.alpha = alpha; j.beta = beta; j.rowscale = rowscale;
+    j.C = (double2 *)C; j.ldc = ldc;
+    j.partial = (double2 *)partial;
+    return j;
+}
+
+template <int WM, int WN, int BM, int BN>
+static void nt_jobs_go(dim3 grid, bool conja, bool proj, hipStream_t st, const NtJob *jobs, const int *mask,
+                       int maxsplit) {
+    const dim3 blk(WM * WN * 64);
+    if (conja && proj)
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 1>), grid, blk, 0, st, jobs, mask, maxsplit);
+    else if (conja)
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 0>), grid, blk, 0, st, jobs, mask, maxsplit);
+    else
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, false, 0>), grid, blk, 0, st, jobs, mask,
+                           maxsplit);
+}
+
+void zgemm_nt_jobs(const std::vector<NtJob> &h, const NtJob *d_jobs, const int *d_mask, bool conja, bool trans,
+                   bool proj, hipStream_t st) {
+    // jobs with M = 0 are placeholders (a problem without such a product): skipped
+    const NtJob *first = nullptr;
+    for (const NtJob &j : h)
+        if (j.M > 0 && !first) first = &j;
+    if (!first) return;
+    const int tn = nt_tn(first->N), tm = nt_tm(first->M, first->N);
+    int maxsplit = 1, mt = 1, ntl = 1;
+    int64_t maxel = 1;
+    for (const NtJob &j : h) {
+        if (j.M <= 0) continue;
+        PW_CHECK(nt_tn(j.N) == tn && nt_tm(j.M, j.N) == tm, PW_EINVAL, "batched NT jobs need one tile shape");
+        maxsplit = std::max(maxsplit, j.nsplit);
+        mt = std::max(mt, (j.M + tm - 1) / tm);
+        ntl = std::max(ntl, (j.N + tn - 1) / tn);
+        maxel = std::max(maxel, (int64_t)j.M * j.N);
+    }
+    dim3 grid(mt, ntl, (unsigned)(h.size() * maxsplit));
+    if (tn == 16 && tm == 128) nt_jobs_go<4, 1, 2, 1>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 16) nt_jobs_go<4, 1, 1, 1>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 32 && tm == 128) nt_jobs_go<4, 1, 2, 2>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 32) nt_jobs_go<4, 1, 1, 2>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 64) nt_jobs_go<2, 2, 2, 2>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tm == 48) nt_jobs_go<1, 3, 3, 3>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tm == 128 && tn == 128) nt_jobs_go<4, 2, 2, 4>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tm == 128) nt_jobs_go<4, 3, 2, 3>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 128) nt_jobs_go<2, 2, 2, 4>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    else nt_jobs_go<2, 3, 2, 3>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    PW_LAUNCH_CHECK();
+    const dim3 rgrid((unsigned)((maxel + kRedElems - 1) / kRedElems), (unsigned)h.size());
+    const dim3 rblk(kRedElems * kRedGroups);
+    if (trans) hipLaunchKernelGGL((reduce_partial_jobs<true>), rgrid, rblk, 0, st, d_jobs, d_mask);
+    else hipLaunchKernelGGL((reduce_partial_jobs<false>), rgrid, rblk, 0, st, d_jobs, d_mask);
     PW_LAUNCH_CHECK();
 }
 
@@ -400,6 +543,8 @@ static const int kNnCfg[kNnCfgs][5] = {{2, 2, 2, 2, 16}, {4, 1, 2, 4, 16}, {9, 1
                                        {3, 2, 3, 2, 8},  {8, 1, 1, 4, 8},  {3, 4, 3, 2, 8},  {3, 4, 3, 1, 8},
                                        {1, 4, 1, 1, 16}, {2, 2, 1, 1, 16}};
 
+int nn_default_cfg(int M) { return M <= 16 ? 12 : M <= 32 ? 13 : M <= 64 ? 0 : (M > 128 && M <= 144) ? 11 : 9; }
+
 void nn_cfg_shape(int id, int &tm, int &tj, int &nthr) {
     PW_CHECK(id >= 0 && id < kNnCfgs, PW_EINVAL, "NN tile %d unknown", id);
     const int *c = kNnCfg[id];
@@ -419,7 +564,7 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         bt.X[z] = (const double2 *)X[z];
         bt.Out[z] = (double2 *)Out[z];
     }
-    if (cfg < 0) cfg = M <= 16 ? 12 : M <= 32 ? 13 : M <= 64 ? 0 : (M > 128 && M <= 144) ? 11 : 9;
+    if (cfg < 0) cfg = nn_default_cfg(M);
     switch (cfg) {
         case 0: nn_go<2, 2, 2, 2>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
         case 1: nn_go<4, 1, 2, 4>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
@@ -435,6 +580,50 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
         case 11: nn_go<3, 4, 3, 1, 8>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
         case 12: nn_go<1, 4, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
         case 13: nn_go<2, 2, 1, 1>(nz, proj, st, M, J, K, W, ldw, bt, ldx, alpha, beta, ldo, lw); break;
+        default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
+    }
+    PW_LAUNCH_CHECK();
+}
+
+template <int WM, int WJ, int BM, int BJ, int KD = KT>
+static void nn_jobs_go(int njobs, int maxM, int maxJ, bool proj, hipStream_t st, const NnJob *jobs, const int *mask) {
+    constexpr int TM = WM * BM * 16, TJ = WJ * BJ * 16;
+    dim3 grid((maxJ + TJ - 1) / TJ, (maxM + TM - 1) / TM, 4 * njobs);
+    const dim3 blk(WM * WJ * 64);
+    if (proj) hipLaunchKernelGGL((zgemm_nn_jobs<WM, WJ, BM, BJ, 1, KD>), grid, blk, 0, st, jobs, mask);
+    else hipLaunchKernelGGL((zgemm_nn_jobs<WM, WJ, BM, BJ, 0, KD>), grid, blk, 0, st, jobs, mask);
+}
+
+void zgemm_nn_jobs_launch(const std::vector<NnJob> &h, const NnJob *d_jobs, const int *d_mask, int cfg, bool proj,
+                          hipStream_t st) {
+    // jobs with nz = 0 are placeholders: skipped
+    int maxM = 0, maxJ = 0, m0 = 0;
+    for (const NnJob &j : h) {
+        if (j.nz == 0) continue;
+        PW_CHECK(j.nz <= 4 && j.M > 0 && j.J > 0, PW_EINVAL, "bad batched NN job");
+        if (!maxM) m0 = j.M;
+        PW_CHECK(nn_default_cfg(j.M) == nn_default_cfg(m0), PW_EINVAL, "NN jobs differ in tile");
+        maxM = std::max(maxM, j.M);
+        maxJ = std::max(maxJ, j.J);
+    }
+    if (!maxM) return;
+    if (cfg < 0) cfg = nn_default_cfg(m0);
+    const int n = (int)h.size();
+    switch (cfg) {
+        case 0: nn_jobs_go<2, 2, 2, 2>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 1: nn_jobs_go<4, 1, 2, 4>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 2: nn_jobs_go<9, 1, 1, 4>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 3: nn_jobs_go<4, 2, 2, 2>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 4: nn_jobs_go<8, 1, 1, 4>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 5: nn_jobs_go<4, 1, 2, 2>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 6: nn_jobs_go<2, 4, 2, 2>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 7: nn_jobs_go<9, 1, 1, 4, 8>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 8: nn_jobs_go<3, 2, 3, 2, 8>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 9: nn_jobs_go<8, 1, 1, 4, 8>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 10: nn_jobs_go<3, 4, 3, 2, 8>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 11: nn_jobs_go<3, 4, 3, 1, 8>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 12: nn_jobs_go<1, 4, 1, 1>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
+        case 13: nn_jobs_go<2, 2, 1, 1>(n, maxM, maxJ, proj, st, d_jobs, d_mask); break;
         default: PW_CHECK(false, PW_EINVAL, "NN tile %d unknown", cfg);
     }
     PW_LAUNCH_CHECK();

@@ -768,10 +768,12 @@ static int proj_splits(int M, int64_t ldg) {
 
 // wide kernels: launch variants {RB (row blocks per wave), NBLK (band blocks per
 // wave), WM x WN waves, KW stage depth}; every variant spans 256 bands
-// (variant 6: the ring kernels, LDS filled by DMA, geometry of variant 0)
+// (variants 6-9: the ring kernels, LDS filled by DMA; 7 and 8 give each of four
+// waves 64 x 128 or 32 x 256 outputs, so every LDS fragment feeds more products)
 static const int kWide[kBf16WideVariants][5] = {{2, 8, 4, 2, 32}, {2, 8, 4, 2, 64}, {2, 8, 2, 2, 32},
                                                 {2, 8, 2, 2, 64}, {4, 4, 2, 4, 32}, {1, 8, 4, 2, 64},
-                                                {2, 8, 4, 2, 32}};
+                                                {2, 8, 4, 2, 32}, {4, 8, 2, 2, 32}, {2, 16, 4, 1, 32},
+                                                {4, 4, 2, 4, 32}};
 constexpr int kWideBands = 256;
 static int wide_rows(int v) { return kWide[v][2] * kWide[v][0] * 16; }
 
@@ -899,7 +901,10 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
             case 3: proj_wide_go<2, 8, 2, 2, 64>(3, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
             case 4: proj_wide_go<4, 4, 2, 4, 32>(4, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
             case 5: proj_wide_go<1, 8, 4, 2, 64>(5, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            default: proj_ring_go<2, 8, 4, 2>(6, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 6: proj_ring_go<2, 8, 4, 2>(6, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 7: proj_ring_go<4, 8, 2, 2>(7, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 8: proj_ring_go<2, 16, 4, 1>(8, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            default: proj_ring_go<4, 4, 2, 4>(9, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
         }
         const int64_t tot = (int64_t)nb * ldp;
         hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
@@ -941,7 +946,10 @@ void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT1
             case 3: back_wide_go<2, 8, 2, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
             case 4: back_wide_go<4, 4, 2, 4, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
             case 5: back_wide_go<1, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            default: back_ring_go<2, 8, 4, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 6: back_ring_go<2, 8, 4, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 7: back_ring_go<4, 8, 2, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 8: back_ring_go<2, 16, 4, 1>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            default: back_ring_go<4, 4, 2, 4>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
         }
         return;
     }

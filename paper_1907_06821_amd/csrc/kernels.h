@@ -12,7 +12,7 @@ void launch_zfwd(pw_ctx *, int nb, const void *cols, const void *psi, int64_t ld
 template <typename T, int MODE> void launch_xy(pw_ctx *, int nb, void *cols, void *grid, hipStream_t);
 
 // gemm.hip (complex128)
-int nt_splits(int M, int N, int K);
+int nt_splits(int M, int N, int K, bool herm = false);
 size_t nt_partial_bytes(int M, int N, int K);
 // herm: A == B (a Gram matrix A^H B): only the tiles on and below the diagonal are computed
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -29,6 +29,69 @@ void zgemm_nn_batch(int nz, int M, int J, int K, const void *W, int64_t ldw, con
                     double alpha, double beta, void *const *Out, int64_t ldo, hipStream_t, bool proj = false, int cfg = -1,
                     bool lower = false);
 
+// Batched launches over independent problems: one job per problem in a device
+// array, mask[q] = 0 skips job q (device-side, so a recorded launch stays valid as
+// problems finish).  Each job's tiles and split-K chunking are those of its own
+// single call, so its result is bit for bit the same.
+struct NtJob {                // C = alpha rowscale o (op(A) B^T) + beta C, split-K over K
+    int M, N, K, kchunk, nsplit, herm;
+    const double2 *A, *B;
+    int64_t lda, ldb;
+    double alpha, beta;
+    const double *rowscale;
+    double2 *C;
+    int64_t ldc;
+    double2 *partial;
+};
+struct NnJob {                // Out_z = alpha W X_z + beta Out_z, z < nz
+    int M, J, K, nz, lower;
+    const double2 *W;
+    int64_t ldw;
+    const double2 *X[4];
+    double2 *Out[4];
+    int64_t ldx, ldo;
+    double alpha, beta;
+};
+NtJob nt_job(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb, double alpha,
+             const double *rowscale, double beta, void *C, int64_t ldc, void *partial, bool herm);
+// jobs: host copy (tile shape, grid) and device copy; all with one tile shape
+void zgemm_nt_jobs(const std::vector<NtJob> &h, const NtJob *d_jobs, const int *d_mask, bool conja, bool trans,
+                   bool proj, hipStream_t);
+int nn_default_cfg(int M);
+void zgemm_nn_jobs_launch(const std::vector<NnJob> &h, const NnJob *d_jobs, const int *d_mask, int cfg, bool proj,
+                          hipStream_t);
+
+// Batched one-workgroup dense kernels (N <= 136) over problems (dense.hip)
+struct DenseJob {
+    int N;
+    const double2 *A;         // Gram (Cholesky) or the Hermitian matrix (eigensolver)
+    int64_t lda;
+    double2 *T;               // Cholesky: conj(L^-1), N x N
+    int64_t ldt;
+    int *status;              // Cholesky: first failing pivot + 1
+    double2 *hv;              // eigensolver work (dense_eigh's layout) and outputs
+    double *zbuf;
+    int *rank;
+    double *lam;
+    double2 *R;
+    int *info;
+};
+DenseJob dense_job(int N, const void *A, int64_t lda, void *work, double *lam, void *R, int *info, void *T,
+                   int *status);
+void chol_inv_jobs(int N, const DenseJob *jobs, const int *mask, int njobs, hipStream_t);
+void dense_eigh_jobs(int N, const DenseJob *jobs, const int *mask, int njobs, hipStream_t);
+
+// Batched complex128 (H - shift) psi over problems with the same band count (fft.hip):
+// in[p] -> out[p] for every problem p whose mask entry is set, bit for bit each
+// problem's own hpsi_any.  hpsi_batch_ok says whether the contexts allow it (stored
+// FP64 table, default launch choices, all bands in one FFT chunk).
+struct HpsiBatch;
+bool hpsi_batch_ok(int n, pw_ctx *const *ctx, int nb, std::string *why);
+HpsiBatch *hpsi_batch_create(int n, pw_ctx *const *ctx, int nb, void *const *in, const int64_t *ld,
+                             void *const *out, const int64_t *ldo, const double *shift, const int *mask);
+void hpsi_batch_run(HpsiBatch *, hipStream_t);
+void hpsi_batch_destroy(HpsiBatch *);
+
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
 size_t cnt_partial_bytes(int M, int N, int K);
 int64_t bf16_ld(int n);
@@ -37,7 +100,7 @@ void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, 
 void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
                          hipStream_t st);
 // variant: launch variant of the kernels for more than 144 bands (autotuner pass 6)
-constexpr int kBf16WideVariants = 7;
+constexpr int kBf16WideVariants = 10;
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
                int64_t ld, void *scratch, void *partial, hipStream_t st, int variant = 0);
 void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,
@@ -74,6 +137,33 @@ struct PrecArgs {
     const int32_t *shell;     // [npw]
     int nb;
 };
+
+// One problem of a batched folded-CG run (all problems with the same band count
+// nb): its solver blocks, its per-band vectors (mu, tband, gz, gzo, gz_old, line4
+// (4 nb), coef (4 nb), lam, res, nb each, in that order) and reduction scratch.
+enum { kBX = 0, kBY, kBAX, kBP, kBYP, kBAP, kBG, kBZ, kBT1, kBT2, kBT3, kBlocks };
+struct BandProb {
+    int npw, nsplit;
+    int64_t ld;
+    double2 *blk[kBlocks];
+    double *vec;
+    double *red;
+    PrecArgs pa;
+    double2 *psi;             // the caller's block (the iterate a restart goes back to)
+    int64_t ldpsi;
+    int *status;              // the solver's status ints (Cholesky pivot, eigensolver info)
+};
+enum class BandOp { MuTband, Grad, GzOld, PUpdate, Line, Combine3, Resid };
+// one batched launch (or two, for reductions) of a band-wise step of FcgRun over
+// every problem whose mask entry is set; Resid: res = ||blk[a0] - lam blk[a1]||
+void band_batch(BandOp op, const BandProb *probs, const int *mask, int nprob, int nb, int maxsplit, int maxnpw,
+                hipStream_t st, int a0 = 0, int a1 = 0);
+void band_batch_copy(const BandProb *probs, const int *mask, int nprob, int nb, int maxnpw, int n, const int *src,
+                     const int *dst, hipStream_t st);
+// psi <- X for every masked-in problem
+void band_batch_save(const BandProb *probs, const int *mask, int nprob, int nb, int maxnpw, hipStream_t st);
+// out[p] = (lam[0..nb), res[0..nb)), sout[p] = status[0..8) for every problem (masked-out ones too)
+void band_batch_gather(const BandProb *probs, int nprob, int nb, double *out, int *sout, hipStream_t st);
 
 struct BandRed {              // scratch for two-stage band reductions
     double *partial;          // [nq][nb][nsplit]

@@ -238,6 +238,23 @@ struct FcgRun {
         return m;
     }
 
+    // this solve as one problem of a fused batch (blocks fixed: swap_free)
+    BandProb band_prob() const {
+        BandProb b{};
+        b.npw = npw;
+        b.nsplit = br.nsplit;
+        b.ld = L;
+        void *const blk[kBlocks] = {X, Y, AX, P, YP, AP, G, Z, T1, T2, T3};
+        for (int i = 0; i < kBlocks; ++i) b.blk[i] = (double2 *)blk[i];
+        b.vec = mu;
+        b.red = br.partial;
+        b.pa = pa;
+        b.psi = (double2 *)psi;
+        b.ldpsi = ld;
+        b.status = d_status;
+        return b;
+    }
+
     void setup() {
         fill_zero(s->status.p, 256, st);
         copy_block(nb, npw, psi, ld, X, L, st);
@@ -313,11 +330,19 @@ struct FcgRun {
         PW_HIP(hipMemcpyAsync(h_res.data(), res, nb * 8, hipMemcpyDeviceToHost, st));
         PW_HIP(hipMemcpyAsync(h_status, d_status, sizeof h_status, hipMemcpyDeviceToHost, st));
         PW_HIP(hipStreamSynchronize(st));
+        return decide();
+    }
+    // the decisions of a check from h_lam, h_res and h_status; defer_save: the
+    // caller saves X to psi itself when this returns true with restarted unchanged
+    bool restarted = false;
+    bool decide(bool defer_save = false) {
+        restarted = false;
         ++nchecks;
         if (o.fault_check > 0 && nchecks == o.fault_check) h_status[0] = nb / 2 + 1;   // forced by the host
         if (h_status[0]) {
             if (o.recover && recoveries < 3) {
                 restart(h_status[0] - 1);
+                restarted = true;
                 return it < o.maxit;
             }
             set_error("Gram matrix lost positive definiteness (pivot %d) before iteration %d", h_status[0] - 1, it);
@@ -344,7 +369,7 @@ struct FcgRun {
             return false;
         }
         // the iterate of this check is the one a restart goes back to
-        if (o.recover) copy_block(nb, npw, X, L, psi, ld, st);
+        if (o.recover && !defer_save) copy_block(nb, npw, X, L, psi, ld, st);
         // the learned preconditioner gives way to the paper's M(G) once the best residual
         // has not halved over learned_stall checks
         if (pa.kind == 2 && o.learned_stall > 0) {
@@ -416,6 +441,7 @@ struct FcgRun {
             stats->n_snap = nsnap;
             stats->precond_switch_it = switch_it;
             stats->recoveries = recoveries;
+            stats->fused = 0;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         }
         return result;
@@ -561,10 +587,255 @@ SegGraph record_segment(FcgRun &r, int len, hipStream_t cap) {
 }
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fused batch (batch_launch = 2): every step of an iteration and of a check is
+// one launch (or one per group of equal FFT grids) over all problems, each
+// problem's kernels, tiles and split-K chunking being those of its own solve, so
+// each problem's numbers are bit for bit those of its own solve.  A device mask
+// says which problems still run: kernels of finished problems return at once,
+// so the recorded round (segment of iterations and the device part of a check)
+// is replayed unchanged while problems drop out.  FP64 H psi, preconditioners 0
+// and 1, at most 136 bands, default launch choices.
+// ---------------------------------------------------------------------------
+namespace {
+struct FusedJobs {
+    std::vector<NtJob> h;
+    DevBuf d;
+    void up() {
+        d.alloc(h.size() * sizeof(NtJob));
+        PW_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(NtJob), hipMemcpyHostToDevice));
+    }
+};
+struct FusedNn {
+    std::vector<NnJob> h;
+    DevBuf d;
+    void up() {
+        d.alloc(h.size() * sizeof(NnJob));
+        PW_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(NnJob), hipMemcpyHostToDevice));
+    }
+};
+struct FusedDense {
+    std::vector<DenseJob> h;
+    DevBuf d;
+    void up() {
+        d.alloc(h.size() * sizeof(DenseJob));
+        PW_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(DenseJob), hipMemcpyHostToDevice));
+    }
+};
+struct HpsiHandle {
+    HpsiBatch *b = nullptr;
+    ~HpsiHandle() { if (b) hpsi_batch_destroy(b); }
+};
+
+NnJob nn_job(int nb, int npw, const double2 *W, const std::vector<void *> &x, const std::vector<void *> &out,
+             int64_t L, double beta, bool lower) {
+    NnJob j{};
+    j.M = nb; j.J = npw; j.K = nb; j.nz = (int)x.size(); j.lower = lower ? 1 : 0;
+    j.W = W; j.ldw = nb;
+    for (size_t z = 0; z < x.size(); ++z) {
+        j.X[z] = (const double2 *)x[z];
+        j.Out[z] = (double2 *)out[z];
+    }
+    j.ldx = L; j.ldo = L; j.alpha = 1.0; j.beta = beta;
+    return j;
+}
+}  // namespace
+
+static bool fused_ok(int nprob, pw_ctx *const *ctxs, int nb, const pw_cg_opts &o, std::string *why) {
+    if (o.precision != 0) { *why = "mixed precision"; return false; }
+    if (o.precond != 0 && o.precond != 1) { *why = "learned preconditioner"; return false; }
+    if (nb > 136) { *why = "more than 136 bands"; return false; }
+    if (o.snap_every > 0 && o.snap_buf) { *why = "snapshots"; return false; }
+    return hpsi_batch_ok(nprob, ctxs, nb, why);
+}
+
+static void fused_solve(std::vector<FcgRun *> &runs, const pw_cg_opts &o, hipStream_t st) {
+    const int n = (int)runs.size(), nb = runs[0]->nb;
+    int maxsplit = 1, maxnpw = 1;
+    std::vector<BandProb> hp(n);
+    std::vector<pw_ctx *> ctx(n);
+    std::vector<double> shift(n);
+    std::vector<void *> X(n), Y(n), AX(n), P(n), YP(n), AP(n);
+    for (int p = 0; p < n; ++p) {
+        FcgRun &r = *runs[p];
+        hp[p] = r.band_prob();
+        ctx[p] = r.ctx;
+        shift[p] = r.E;
+        X[p] = r.X; Y[p] = r.Y; AX[p] = r.AX; P[p] = r.P; YP[p] = r.YP; AP[p] = r.AP;
+        maxsplit = std::max(maxsplit, r.br.nsplit);
+        maxnpw = std::max(maxnpw, r.npw);
+    }
+    DevBuf d_probs, d_mask, d_save, d_out, d_sout;
+    d_probs.alloc(n * sizeof(BandProb));
+    PW_HIP(hipMemcpy(d_probs.p, hp.data(), n * sizeof(BandProb), hipMemcpyHostToDevice));
+    std::vector<int> mask(n, 1), save(n, 0);
+    d_mask.alloc(n * sizeof(int));
+    d_save.alloc(n * sizeof(int));
+    PW_HIP(hipMemcpy(d_mask.p, mask.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    d_out.alloc((size_t)n * 2 * nb * sizeof(double));
+    d_sout.alloc((size_t)n * 8 * sizeof(int));
+    const int *dm = d_mask.as<int>();
+    const BandProb *dp = d_probs.as<BandProb>();
+    // H psi of the four fold inputs (internal leading dimension L = npw)
+    std::vector<int64_t> Ls(n);
+    for (int p = 0; p < n; ++p) Ls[p] = runs[p]->L;
+    HpsiHandle h_p, h_yp, h_x, h_y;
+    h_p.b = hpsi_batch_create(n, ctx.data(), nb, P.data(), Ls.data(), YP.data(), Ls.data(), shift.data(), dm);
+    h_yp.b = hpsi_batch_create(n, ctx.data(), nb, YP.data(), Ls.data(), AP.data(), Ls.data(), shift.data(), dm);
+    h_x.b = hpsi_batch_create(n, ctx.data(), nb, X.data(), Ls.data(), Y.data(), Ls.data(), shift.data(), dm);
+    h_y.b = hpsi_batch_create(n, ctx.data(), nb, Y.data(), Ls.data(), AX.data(), Ls.data(), shift.data(), dm);
+    // block products of an iteration and of a check
+    FusedJobs nt_xp, nt_xx, nt_yy, nt_xy;
+    FusedNn nn_px, nn_orth, nn_rr3, nn_pg, nn_x, nn_y;
+    FusedDense chol, eig;
+    for (int p = 0; p < n; ++p) {
+        FcgRun &r = *runs[p];
+        const int npw = r.npw;
+        const int64_t L = r.L;
+        void *part = r.ctx->d_partial.p;
+        nt_xp.h.push_back(nt_job(nb, nb, npw, true, r.X, L, r.P, L, -1.0, nullptr, 0.0, r.Wm, nb, part, false));
+        nt_xx.h.push_back(nt_job(nb, nb, npw, true, r.X, L, r.X, L, 1.0, nullptr, 0.0, r.Sm, nb, part, true));
+        nt_yy.h.push_back(nt_job(nb, nb, npw, true, r.Y, L, r.Y, L, 1.0, nullptr, 0.0, r.Sm, nb, part, true));
+        nt_xy.h.push_back(nt_job(nb, nb, npw, true, r.X, L, r.Y, L, 1.0, nullptr, 0.0, r.Sm, nb, part, false));
+        nn_px.h.push_back(nn_job(nb, npw, r.Wm, {r.X}, {r.P}, L, 1.0, false));
+        nn_orth.h.push_back(nn_job(nb, npw, r.Tm, {r.X, r.Y, r.AX}, {r.T1, r.T2, r.T3}, L, 0.0, true));
+        nn_rr3.h.push_back(nn_job(nb, npw, r.Rm, {r.X, r.Y, r.AX}, {r.T1, r.T2, r.T3}, L, 0.0, false));
+        nn_pg.h.push_back(nn_job(nb, npw, r.Rm, {r.P, r.G}, {r.T1, r.T2}, L, 0.0, false));
+        nn_x.h.push_back(nn_job(nb, npw, r.Rm, {r.X}, {r.T1}, L, 0.0, false));
+        nn_y.h.push_back(nn_job(nb, npw, r.Rm, {r.Y}, {r.T2}, L, 0.0, false));
+        chol.h.push_back(dense_job(nb, r.Sm, nb, r.Aw, nullptr, nullptr, nullptr, r.Tm, r.d_status));
+        eig.h.push_back(dense_job(nb, r.Sm, nb, r.Aw, r.lam, r.Rm, r.d_status + 4, nullptr, nullptr));
+    }
+    for (FusedJobs *j : {&nt_xp, &nt_xx, &nt_yy, &nt_xy}) j->up();
+    for (FusedNn *j : {&nn_px, &nn_orth, &nn_rr3, &nn_pg, &nn_x, &nn_y}) j->up();
+    chol.up();
+    eig.up();
+    const int c_xyax[3] = {kBT1, kBT2, kBT3}, d_xyax[3] = {kBX, kBY, kBAX};
+    const int c_pg[2] = {kBT1, kBT2}, d_pg[2] = {kBP, kBG};
+    auto band = [&](BandOp op, int a0 = 0, int a1 = 0) {
+        band_batch(op, dp, dm, n, nb, maxsplit, maxnpw, st, a0, a1);
+    };
+    auto iteration = [&]() {
+        band(BandOp::MuTband);
+        band(BandOp::Grad);
+        band(BandOp::PUpdate);
+        zgemm_nt_jobs(nt_xp.h, nt_xp.d.as<NtJob>(), dm, true, true, false, st);
+        zgemm_nn_jobs_launch(nn_px.h, nn_px.d.as<NnJob>(), dm, -1, false, st);
+        hpsi_batch_run(h_p.b, st);
+        hpsi_batch_run(h_yp.b, st);
+        band(BandOp::Line);
+        band(BandOp::Combine3);
+        zgemm_nt_jobs(nt_xx.h, nt_xx.d.as<NtJob>(), dm, true, false, false, st);
+        chol_inv_jobs(nb, chol.d.as<DenseJob>(), dm, n, st);
+        zgemm_nn_jobs_launch(nn_orth.h, nn_orth.d.as<NnJob>(), dm, -1, false, st);
+        band_batch_copy(dp, dm, n, nb, maxnpw, 3, c_xyax, d_xyax, st);
+    };
+    auto check_device = [&]() {
+        hpsi_batch_run(h_x.b, st);
+        hpsi_batch_run(h_y.b, st);
+        zgemm_nt_jobs(nt_yy.h, nt_yy.d.as<NtJob>(), dm, true, false, false, st);
+        dense_eigh_jobs(nb, eig.d.as<DenseJob>(), dm, n, st);
+        zgemm_nn_jobs_launch(nn_rr3.h, nn_rr3.d.as<NnJob>(), dm, -1, false, st);
+        band_batch_copy(dp, dm, n, nb, maxnpw, 3, c_xyax, d_xyax, st);
+        zgemm_nn_jobs_launch(nn_pg.h, nn_pg.d.as<NnJob>(), dm, -1, false, st);
+        band_batch_copy(dp, dm, n, nb, maxnpw, 2, c_pg, d_pg, st);
+        zgemm_nt_jobs(nt_xy.h, nt_xy.d.as<NtJob>(), dm, true, false, false, st);
+        dense_eigh_jobs(nb, eig.d.as<DenseJob>(), dm, n, st);
+        zgemm_nn_jobs_launch(nn_x.h, nn_x.d.as<NnJob>(), dm, -1, false, st);
+        zgemm_nn_jobs_launch(nn_y.h, nn_y.d.as<NnJob>(), dm, -1, false, st);
+        band(BandOp::Resid, kBT2, kBT1);
+        band(BandOp::MuTband);
+        band(BandOp::GzOld);
+        band_batch_gather(dp, n, nb, d_out.as<double>(), d_sout.as<int>(), st);
+    };
+    // one recorded round per segment length
+    struct Round {
+        int len;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Round> rounds;
+    struct Guard {
+        std::vector<Round> &r;
+        hipStream_t cap = nullptr;
+        ~Guard() {
+            for (Round &x : r) {
+                if (x.exec) (void)hipGraphExecDestroy(x.exec);
+                if (x.g) (void)hipGraphDestroy(x.g);
+            }
+            if (cap) (void)hipStreamDestroy(cap);
+        }
+    } guard{rounds};
+    PW_HIP(hipStreamCreateWithFlags(&guard.cap, hipStreamNonBlocking));
+    std::vector<double> out((size_t)n * 2 * nb);
+    std::vector<int> sout((size_t)n * 8);
+    for (;;) {
+        int len = 0;
+        for (int p = 0; p < n; ++p)
+            if (mask[p]) { len = runs[p]->segment_length(); break; }
+        if (!len) break;
+        Round *rd = nullptr;
+        for (Round &x : rounds)
+            if (x.len == len) rd = &x;
+        if (!rd) {
+            rounds.push_back(Round{len});
+            rd = &rounds.back();
+            const hipStream_t keep = st;
+            st = guard.cap;
+            PW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < len; ++k) iteration();
+                check_device();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                st = keep;
+                throw;
+            }
+            PW_HIP(hipStreamEndCapture(st, &rd->g));
+            st = keep;
+            PW_HIP(hipGraphInstantiate(&rd->exec, rd->g, nullptr, nullptr, 0));
+        }
+        PW_HIP(hipGraphLaunch(rd->exec, st));
+        PW_HIP(hipMemcpyAsync(out.data(), d_out.p, out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        PW_HIP(hipMemcpyAsync(sout.data(), d_sout.p, sout.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        PW_HIP(hipStreamSynchronize(st));
+        bool changed = false, any_save = false;
+        for (int p = 0; p < n; ++p) {
+            save[p] = 0;
+            if (!mask[p]) continue;
+            FcgRun &r = *runs[p];
+            r.it += len;
+            r.n_hpsi += (int64_t)2 * nb * len + 2 * nb;
+            std::copy(out.begin() + (size_t)p * 2 * nb, out.begin() + (size_t)p * 2 * nb + nb, r.h_lam.begin());
+            std::copy(out.begin() + (size_t)p * 2 * nb + nb, out.begin() + (size_t)(p + 1) * 2 * nb, r.h_res.begin());
+            for (int k = 0; k < 8; ++k) r.h_status[k] = sout[(size_t)p * 8 + k];
+            const bool more = r.decide(true);
+            if (!more) {
+                mask[p] = 0;
+                changed = true;
+            } else if (o.recover && !r.restarted) {
+                save[p] = 1;
+                any_save = true;
+            }
+        }
+        if (any_save) {
+            PW_HIP(hipMemcpyAsync(d_save.p, save.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+            band_batch_save(dp, d_save.as<int>(), n, nb, maxnpw, st);
+        }
+        if (changed) PW_HIP(hipMemcpyAsync(d_mask.p, mask.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        PW_HIP(hipStreamSynchronize(st));   // the host vectors outlive the copies
+    }
+}
+
 pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int nb, void *const *psi,
                       const int64_t *ld, double *const *eig, double *const *resid, const pw_cg_opts &o,
                       pw_cg_stats *stats, int32_t *status, hipStream_t st) {
+    std::string why;
+    const bool fused = o.batch_launch == 2 && fused_ok(nprob, ctxs, nb, o, &why);
     const bool each = o.batch_launch != 0;   // launch each problem's recorded segment, or one graph of them all
+    if (o.batch_launch == 2 && !fused && o.verbose) fprintf(stderr, "[pw] batch: not fused (%s)\n", why.c_str());
     BatchRes R;
     R.items.resize(nprob);
     PW_HIP(hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking));
@@ -575,7 +846,12 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
         b.run->swap_free = true;
         b.run->setup();
     }
-    for (;;) {
+    if (fused) {
+        std::vector<FcgRun *> runs;
+        for (BatchItem &b : R.items) runs.push_back(b.run.get());
+        fused_solve(runs, o, st);
+    }
+    for (; !fused;) {
         bool any = false, changed = false;
         for (BatchItem &b : R.items) {
             hipGraph_t want = nullptr;
@@ -635,6 +911,8 @@ pw_status batch_solve(int nprob, pw_ctx *const *ctxs, const double *e_ref, int n
         if (status) status[p] = r;
         if (r != PW_OK && (worst == PW_OK || worst == PW_ENOCONV)) worst = r;
     }
+    if (fused && stats)
+        for (int p = 0; p < nprob; ++p) stats[p].fused = 1;
     return worst;
 }
 
@@ -707,7 +985,7 @@ void pw_cg_opts_default(pw_cg_opts *o) {
     o->snap_every = 0;
     o->snap_cap = 0;
     o->nconv = 0;
-    o->batch_launch = 1;
+    o->batch_launch = 2;
     o->learned_stall = 25;
     o->recover = 1;
     o->fault_check = 0;
