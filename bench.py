@@ -21,14 +21,16 @@ over three seeded starts) with FP64 + Teter-Payne-Allan, FP64 + the paper's
 M(G), mixed with TPA, with M(G) and with the learned preconditioner; the folded
 linear equation with the eigenstate-augmented M' (8 and 32 boundary sources);
 ChebFD (degree 1500, a window of 64 states); wave-function interpolation
-between k-points.  cpu_baseline: the FP64 oracle's H psi on a bounded sample
-of the 4000-atom wire.
+between k-points.  batch64: 64 uneven cubes solved one by one and as one fused
+batch (bit for bit the same).  cpu_baseline: the FP64 oracle's H psi on a
+bounded sample of the 4000-atom wire.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
 --no-cpu --no-wire256 --wire256-steps N --no-solve --solve-legs a,b --no-linear
 --linear-maxit N --no-chebfd --chebfd-degree D --chebfd-steps S --chebfd-window N
---no-kinterp; --wire4000-hpsi (only the complex64 H psi of 1024 bands);
---copy-probe BYTES (HBM counter calibration).
+--no-kinterp --no-batch; profiling modes: --wire256-only, --wire4000-hpsi (only
+the complex64 H psi of 1024 bands; --tune, --bf16-variant V), --copy-probe BYTES
+(HBM counter calibration).
 """
 from __future__ import annotations
 
@@ -331,6 +333,52 @@ def chebfd_leg(ctx, prob, nb, eig_ref=None, n_window=64, degree=1500, steps=3, l
         out["roofline"] = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
                            "unit": "GB/s" if d["bound"] == "hbm" else "TFLOP/s", "frac": d["frac"], "kernel": dom}
         out["stages"] = stages
+    return out
+
+
+def batch_leg(n=64, nb=20, nconv=16, log=None):
+    """The uneven batch: 64 cubes of 8-14 bohr on 32^3-64^3 grids (16 wanted + 4
+    buffer bands, FP64 + M(G), max Delta <= 1e-6, at most 3000 steps, checks every
+    20), solved one by one and as one fused batch (every step one launch over all
+    problems, finished problems masked on the device); the batch must reproduce
+    every problem bit for bit."""
+    import numpy as np
+    import torch
+    import paper_1907_06821_amd as pw
+    from paper_1907_06821_amd import synth
+    probs = synth.batched_problems(n, seed=0)
+    ctxs = [pw.Context.from_problem(p, max_bands=nb) for p in probs]
+    starts = [torch.from_numpy(synth.start_vectors(4, nb, c.npw, seed=i)).to("cuda") for i, c in enumerate(ctxs)]
+    kw = dict(tol=1e-6, maxit=3000, check_every=20, precision=0, precond=1, nconv=nconv, raise_on_noconv=False)
+    for c, p, s_ in zip(ctxs, probs, starts):          # solver workspaces
+        pw.folded_cg_solve(c, p.e_ref, s_.clone(), **{**kw, "maxit": 20})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one = []
+    for c, p, s_ in zip(ctxs, probs, starts):
+        psi = s_.clone()
+        e, _, st = pw.folded_cg_solve(c, p.e_ref, psi, **kw)
+        one.append((e, st, psi))
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    psis = [s_.clone() for s_ in starts]
+    t0 = time.perf_counter()
+    eigs, _, sts, _ = pw.batch_solve(ctxs, [p.e_ref for p in probs], psis, **kw)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(eigs[i], one[i][0]) and torch.equal(psis[i], one[i][2]) for i in range(n))
+    out = {"workload": f"{n} cubes of 8-14 bohr on 32^3-64^3 grids, Ecut 8 Ha, npw "
+                       f"{min(c.npw for c in ctxs)}-{max(c.npw for c in ctxs)}, {nconv} wanted + {nb - nconv} buffer "
+                       "bands, FP64 + M(G), tol 1e-6, maxit 3000",
+           "one_by_one_s": round(t_one, 2), "fused_batch_s": round(t_batch, 2),
+           "speedup": round(t_one / t_batch, 2), "fused": all(s_["fused"] for s_ in sts),
+           "bit_identical": bool(same), "converged": int(sum(s_["converged"] for s_ in sts)),
+           "steps_total": int(sum(s_["iters"] for s_ in sts)), "steps_max": int(max(s_["iters"] for s_ in sts))}
+    if log:
+        log(f"batch of {n} cubes: one by one {t_one:.2f} s, fused {t_batch:.2f} s ({out['speedup']}x), "
+            f"bit-identical {same}")
+    for c in ctxs:
+        c.close()
     return out
 
 
@@ -726,6 +774,7 @@ def main():
     ap.add_argument("--chebfd-steps", type=int, default=3)
     ap.add_argument("--chebfd-window", type=int, default=64, help="eigenstates inside the ChebFD window")
     ap.add_argument("--no-kinterp", action="store_true", help="skip the k-point interpolation leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-cube batch leg")
     ap.add_argument("--wire4000-hpsi", action="store_true",
                     help="only: complex64 H psi throughput on the 4000-atom wire (1024 bands in one call)")
     ap.add_argument("--wire256-only", action="store_true",
@@ -765,6 +814,8 @@ def main():
     line = wire4000_step(args.steps, args.warmup, log=log)
     if not args.no_wire256:
         line["wire256"] = wire256_legs(args, log)
+    if not args.no_batch:
+        line["batch64"] = batch_leg(log=log)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_wire4000(log=log)
     else:

@@ -118,7 +118,12 @@ pw_status pw_basis_miller(const pw_cell *cell, int32_t *miller, int32_t npw);
  * energies, shells, V (z-major copy), projector tables per `flags`, and a
  * workspace for hpsi on up to `max_bands` bands.  All device memory is
  * allocated here (and by the first folded-CG solve); hot calls allocate
- * nothing.  Returns PW_EINVAL if the sphere does not fit the grid. */
+ * nothing.  Returns PW_EINVAL if the sphere does not fit the grid.
+ * A context is not safe for overlapping calls: its scratch (column grid,
+ * split-K partials, BF16 planes, solver workspace) serves every call on it, so
+ * calls on one context from several streams or threads race.  Calls on
+ * different contexts may overlap; the autotuner's process-wide result cache is
+ * guarded by a mutex. */
 pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t max_bands,
                         int32_t flags, void *stream, pw_ctx **out);
 pw_status pw_ctx_destroy(pw_ctx *ctx);

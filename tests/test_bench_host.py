@@ -1,56 +1,55 @@
-"""Host logic of the benchmark: the committed HBM counters are quoted only for
-the launch variant the autotuner picked and only while the GEMM source matches
-the hash recorded with them; --gpus above 1 is refused."""
+"""Host logic of the benchmark: the committed HBM counters of the 4000-atom
+wire are quoted only for the BF16 launch variant in use and only while the
+kernel source matches the hash recorded with them; --gpus above 1 is refused."""
+import hashlib
 import json
 import os
 import subprocess
 import sys
 
-import pytest
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
+REC = os.path.join(ROOT, "profiles", "wire4000_traffic.json")
+
 
 def _rec():
-    with open(os.path.join(ROOT, "profiles", "wire256_fp64_traffic.json")) as f:
+    with open(REC) as f:
         return json.load(f)
 
 
-def _source_matches(rec):
-    import hashlib
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest() == rec["source_sha256"]
+def _matches(st):
+    with open(os.path.join(ROOT, st["source"]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest() == st["source_sha256"]
 
 
-def test_traffic_follows_the_tuned_tile():
+def test_traffic_follows_the_bf16_variant():
     rec = _rec()
-    if not _source_matches(rec):                  # counters older than the GEMM source: never quoted
-        assert bench.measured_traffic("projection", False, 128, None) is None
+    st = rec["stages"]["projection"]
+    if not _matches(st):                          # counters older than the kernel source: never quoted
+        assert bench.measured_traffic_wire4000("projection", 6) is None
         return
-    by_cfg = rec["stages"]["back_projection"]["bytes_by_nn_cfg"]
-    for cfg, b in by_cfg.items():
-        assert bench.measured_traffic("back_projection", False, 128, int(cfg)) == b
-    assert bench.measured_traffic("back_projection", False, 128, 99) is None
-    assert bench.measured_traffic("projection", False, 128, None) == rec["stages"]["projection"]["bytes_per_launch"]
-    # counters were taken on the complex128 path at 128 bands only
-    assert bench.measured_traffic("projection", True, 128, None) is None
-    assert bench.measured_traffic("projection", False, 136, None) is None
-    assert bench.measured_traffic("xy_fft_v", False, 128, None) is None
+    for v, b in st["bytes_by_variant"].items():
+        assert bench.measured_traffic_wire4000("projection", int(v)) == b
+    assert bench.measured_traffic_wire4000("projection", 99) is None
+    assert bench.measured_traffic_wire4000("projection", None) is None
+    assert bench.measured_traffic_wire4000("block_gram", 6) is None          # no counter run for it
 
 
 def test_traffic_needs_the_recorded_source(tmp_path, monkeypatch):
     rec = _rec()
-    rec["source_sha256"] = "0" * 64
+    st = rec["stages"]["projection"]
+    st["source_sha256"] = "0" * 64
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "wire256_fp64_traffic.json").write_text(json.dumps(rec))
-    src = tmp_path / rec["source"]
+    (prof / "wire4000_traffic.json").write_text(json.dumps(rec))
+    src = tmp_path / st["source"]
     src.parent.mkdir(parents=True)
-    src.write_bytes(open(os.path.join(ROOT, rec["source"]), "rb").read())
+    src.write_bytes(open(os.path.join(ROOT, st["source"]), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("projection", False, 128, None) is None
+    v = next(iter(st["bytes_by_variant"]))
+    assert bench.measured_traffic_wire4000("projection", int(v)) is None
 
 
 def test_more_than_one_gpu_is_refused():
