@@ -287,7 +287,7 @@ def test_bf16_wide_variants_agree(torch_cuda):
     bound = 4 * 2.0 ** -8 * torch.linalg.vector_norm(nl, dim=1) + 1e-5 * torch.linalg.vector_norm(ref, dim=1)
     x32 = x.to(torch.complex64)
     recs = [r for r in pw.autotune(ctx, 64, dtype=pw.PW_C64, reps=1) if r["pass_"] == 6]
-    assert len(recs) == 7 and sum(r["chosen"] for r in recs) == 1
+    assert len(recs) == 10 and sum(r["chosen"] for r in recs) == 1
     for r in recs:
         pw.fft_choose(ctx, r, dtype=pw.PW_C64)
         got = pw.hpsi(ctx, x32, shift=prob.e_ref).to(torch.complex128)
