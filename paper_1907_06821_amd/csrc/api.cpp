@@ -246,9 +246,11 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
     upload(c->d_colstart, b.col_start, acct);
     std::vector<int32_t> zmap(b.npw), colpos(b.ncols), colslot(b.ncols);
     const int rowlo = ((b.n0min % n0) + n0) % n0;
+    const int qm = std::max(1, n1 / 4);      // the four-lane xy kernel's plane layout (square planes)
     for (int col = 0; col < b.ncols; ++col) {
         colpos[col] = b.col_i0[col] * (n1 + 1) + b.col_i1[col];
-        colslot[col] = ((b.col_i0[col] - rowlo + n0) % n0) * (n1 + 1) + b.col_i1[col];
+        const int i1 = b.col_i1[col];
+        colslot[col] = ((b.col_i0[col] - rowlo + n0) % n0) * quad_rs(qm) + i1 + (i1 / qm) * quad_pad(qm);
         for (int g = b.col_start[col]; g < b.col_start[col + 1]; ++g) {
             const int n2v = b.miller[3 * g + 2];
             zmap[g] = (col % c->cb) * (n2 + 1) + ((n2v % n2) + n2) % n2;

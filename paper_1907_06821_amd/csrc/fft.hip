@@ -41,7 +41,8 @@ struct XYArgs {
     int n0, n1, n2, ncols;
     int rowlo, nrows;         // x rows that hold columns: (rowlo + r) mod n0, r < nrows
     const int32_t *colpos;    // [ncols]: i0 * (n1 + 1) + i1 (padded plane index)
-    const int32_t *colslot;   // [ncols]: ((i0 - rowlo) mod n0) * (n1 + 1) + i1 (touched-rows plane)
+    const int32_t *colslot;   // [ncols]: place of (slot (i0 - rowlo) mod n0, column i1) in the
+                              // four-lane kernel's plane of touched rows (quad_rs, quad_pad)
     const void *tw0, *tw1;
     const void *vz;           // [n2][n0][n1] potential, z-major (or null)
 };
@@ -425,7 +426,7 @@ template <typename T, int M, int S> __device__ inline void quad_b(cplx<T> *v, co
 
 template <typename T, int M, int NTHR>
 __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restrict__ cols, int z, int b) {
-    constexpr int L = 4 * M, RS = L + 1, NQ = NTHR / 4;
+    constexpr int L = 4 * M, RS = quad_rs(M), PD = quad_pad(M), MB = M + PD, NQ = NTHR / 4;
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw = reinterpret_cast<cplx<T> *>(smem_raw);   // [L]
     cplx<T> *pl = tw + L;                                   // [nrows][RS], touched x rows only
@@ -456,10 +457,10 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
         cplx<T> *p = pl + f * RS;
         cplx<T> v[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = p[q + 4 * m];
+        for (int m = 0; m < M; ++m) v[m] = p[q + 4 * m + (4 * m / M) * PD];
         quad_a<T, M, 1>(v, tw, q);
 #pragma unroll
-        for (int k = 0; k < M; ++k) p[k + M * rq] = v[k];
+        for (int k = 0; k < M; ++k) p[k + MB * rq] = v[k];
     }
     __syncthreads();
     const T *vz = reinterpret_cast<const T *>(a.vz) + (int64_t)z * L * L;
@@ -467,6 +468,7 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
     // keeps it within 128 VGPRs (four waves per SIMD)
     constexpr bool VPF = sizeof(T) == 4;
     for (int y = quad; y < L; y += NQ) {                     // x inverse, V, x forward
+        const int yc = y + (y / M) * PD;
         T vv[M];
         if constexpr (VPF) {
 #pragma unroll
@@ -477,7 +479,7 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
         for (int m = 0; m < M; ++m) {
             int dx = q + 4 * m - rowlo;
             if (dx < 0) dx += L;
-            v[m] = dx < nrows ? pl[dx * RS + y] : cmake<T>(0, 0);
+            v[m] = dx < nrows ? pl[dx * RS + yc] : cmake<T>(0, 0);
         }
         quad_a<T, M, 1>(v, tw, q);
 #pragma unroll
@@ -487,7 +489,7 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
         for (int k = 0; k < M; ++k) {
             int dx = q + 4 * k - rowlo;
             if (dx < 0) dx += L;
-            if (dx < nrows) pl[dx * RS + y] = v[k];
+            if (dx < nrows) pl[dx * RS + yc] = v[k];
         }
     }
     __syncthreads();
@@ -495,10 +497,10 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
         cplx<T> *p = pl + f * RS;
         cplx<T> v[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) v[k] = p[k + M * rq];
+        for (int k = 0; k < M; ++k) v[k] = p[k + MB * rq];
         quad_b<T, M, -1>(v, tw, q);
 #pragma unroll
-        for (int k = 0; k < M; ++k) p[q + 4 * k] = v[k];
+        for (int k = 0; k < M; ++k) p[q + 4 * k + (4 * k / M) * PD] = v[k];
     }
     __syncthreads();
     for (int c = tid; c < a.ncols; c += NTHR) crow[c] = pl[a.colslot[c]];
@@ -682,7 +684,7 @@ static bool xy_has_quad(int n0, int n1) {
 
 // LDS of the four-lane kernel: twiddles and the touched rows of one plane
 template <typename T> static size_t quad_lds(const XYArgs &a) {
-    return sizeof(cplx<T>) * ((size_t)a.n0 + (size_t)a.nrows * (a.n1 + 1));
+    return sizeof(cplx<T>) * ((size_t)a.n0 + (size_t)a.nrows * quad_rs(std::max(1, a.n1 / 4)));
 }
 
 template <typename T, int M, int NTHR>

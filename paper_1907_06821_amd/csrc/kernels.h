@@ -11,6 +11,23 @@ void launch_zfwd(pw_ctx *, int nb, const void *cols, const void *psi, int64_t ld
                  double scale, void *out, int64_t ldo, hipStream_t);
 template <typename T, int MODE> void launch_xy(pw_ctx *, int nb, void *cols, void *grid, hipStream_t);
 
+// LDS plane of the four-lane xy kernel for planes of L = 4 m points a side: the
+// element of row slot r, column c sits at r quad_rs(m) + c + (c / m) quad_pad(m).
+// Its accesses (lane q of a quad at column q + 4 k, or at k + m q', or four lanes
+// on consecutive rows of one column) then fall into distinct banks among the 16
+// lanes that share an LDS cycle: rows are 4 mod 16 elements apart and each of the
+// four column blocks of m is shifted by one more element mod 16.
+constexpr int quad_pad(int m) {
+    int p = 1;
+    while ((m + p) % 16 != 1) ++p;
+    return p;
+}
+constexpr int quad_rs(int m) {
+    int r = 4 * m + 3 * quad_pad(m);
+    while (r % 16 != 4) ++r;
+    return r;
+}
+
 // gemm.hip (complex128)
 int nt_splits(int M, int N, int K, bool herm = false);
 size_t nt_partial_bytes(int M, int N, int K);
