@@ -752,6 +752,230 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_ring(int N, int J, int6
 }
 
 // ---------------------------------------------------------------------------
+// Pipelined ring variants.  Same tiles, LDS layout and DMA ring as above, but a
+// wave reads its LDS fragments one band step ahead of the matrix work that uses
+// them (the reads of step j + 1 are in flight while the products of step j
+// run), and the barrier that publishes stage t + 1 sits in front of the last
+// band step of stage t: the wave reads stage t + 1's first fragments, and the
+// DMA of stage t + 3 goes into the slot stage t leaves, while the last products
+// of stage t are still to be issued.  Every wave has read all of stage t before
+// that barrier (its LDS counter is drained there), so the slot is free; three
+// stages are then in flight at once.
+// ---------------------------------------------------------------------------
+#define PW_SCHED_READS(n) __builtin_amdgcn_sched_group_barrier(0x100, n, 0)
+#define PW_SCHED_MFMA(n) __builtin_amdgcn_sched_group_barrier(0x008, n, 0)
+
+template <int RB, int NBLK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void proj_pipe(int M, int N, const uint16_t *__restrict__ Br,
+                                                          const uint16_t *__restrict__ Bi, int64_t ldg,
+                                                          const uint16_t *__restrict__ Pr,
+                                                          const uint16_t *__restrict__ Pi, int kchunk,
+                                                          float2 *__restrict__ partial) {
+    constexpr int NW = WM * WN, TB = WM * RB, BB = WN * NBLK;
+    constexpr int BLK = 2 * (TB + BB), PW = BLK / NW, STAGE = BLK * 1024;
+    static_assert(BLK % NW == 0, "DMA blocks must divide evenly over the waves");
+    __shared__ __attribute__((aligned(1024))) uint8_t ring[kRingStages][STAGE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WM, wn = wave / WM;
+    const WideTile tile = wide_tile();
+    const int m0 = tile.x * (TB * 16), n0 = tile.y * (BB * 16);
+    const int kbeg = tile.z * kchunk;
+    const int nst = (int)((std::min((int64_t)kbeg + kchunk, ldg) - kbeg) / 32);
+    const uint16_t *src[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const int b = wave * PW + i, piece = 8 * (lane >> 4);
+        if (b < 2 * TB) {
+            const int row = std::min(m0 + (b % TB) * 16 + (lane & 15), M - 1);
+            src[i] = (b < TB ? Br : Bi) + (int64_t)row * ldg + kbeg + piece;
+        } else {
+            const int c = b - 2 * TB;
+            const int band = std::min(n0 + (c % BB) * 16 + (lane & 15), N - 1);
+            src[i] = (c < BB ? Pr : Pi) + (int64_t)band * ldg + kbeg + piece;
+        }
+    }
+    const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
+    auto issue = [&](int s) {
+        const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
+#pragma unroll
+        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
+    };
+    auto frag = [&](int s, int blk) {
+        return *reinterpret_cast<const bf16x8 *>(&ring[s % kRingStages][0] + blk * 1024 + lane * 16);
+    };
+    v4f ar_[RB][NBLK], ai_[RB][NBLK];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) { ar_[r][j] = v4f{0, 0, 0, 0}; ai_[r][j] = v4f{0, 0, 0, 0}; }
+    issue(0);
+    if (nst > 1) issue(1);
+    if (nst > 2) issue(2);
+    if (nst > 2) ring_barrier<2 * PW>();
+    else if (nst > 1) ring_barrier<PW>();
+    else ring_barrier<0>();
+    bf16x8 tr[RB], ti[RB], cr, ci;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) { tr[r] = frag(0, wm * RB + r); ti[r] = frag(0, TB + wm * RB + r); }
+    cr = frag(0, 2 * TB + wn * NBLK);
+    ci = frag(0, 2 * TB + BB + wn * NBLK);
+    for (int t = 0; t < nst; ++t) {
+        bf16x8 tn[RB], ntr[RB], nti[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) { tn[r] = neg8(ti[r]); ntr[r] = tr[r]; nti[r] = ti[r]; }
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j) {
+            bf16x8 nr = cr, ni = ci;
+            if (j + 1 < NBLK) {
+                nr = frag(t, 2 * TB + wn * NBLK + j + 1);
+                ni = frag(t, 2 * TB + BB + wn * NBLK + j + 1);
+                PW_SCHED_READS(2);
+            } else if (t + 1 < nst) {
+                // stage t read in full by every wave; stage t + 1 landed
+                if (t + 2 < nst) ring_barrier<PW>();
+                else ring_barrier<0>();
+                if (t + 3 < nst) issue(t + 3);
+#pragma unroll
+                for (int r = 0; r < RB; ++r) { ntr[r] = frag(t + 1, wm * RB + r); nti[r] = frag(t + 1, TB + wm * RB + r); }
+                nr = frag(t + 1, 2 * TB + wn * NBLK);
+                ni = frag(t + 1, 2 * TB + BB + wn * NBLK);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
+                ar_[r][j] = mfma_bf16(tr[r], cr, ar_[r][j]);
+                ar_[r][j] = mfma_bf16(ti[r], ci, ar_[r][j]);
+                ai_[r][j] = mfma_bf16(tr[r], ci, ai_[r][j]);
+                ai_[r][j] = mfma_bf16(tn[r], cr, ai_[r][j]);
+            }
+            if (j + 1 < NBLK) PW_SCHED_MFMA(4 * RB);
+            cr = nr;
+            ci = ni;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) { tr[r] = ntr[r]; ti[r] = nti[r]; }
+    }
+    float2 *P = partial + (int64_t)tile.z * M * N;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int j = 0; j < NBLK; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + (wm * RB + r) * 16 + 4 * (lane >> 4) + v;
+                const int col = n0 + (wn * NBLK + j) * 16 + (lane & 15);
+                if (row < M && col < N) P[(int64_t)col * M + row] = make_float2(ar_[r][j][v], ai_[r][j][v]);
+            }
+}
+
+template <int GB, int NBLK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void backproj_pipe(int N, int J, int64_t ldp,
+                                                              const uint16_t *__restrict__ Wr,
+                                                              const uint16_t *__restrict__ Wi,
+                                                              const uint16_t *__restrict__ Tr,
+                                                              const uint16_t *__restrict__ Ti,
+                                                              float2 *__restrict__ out, int64_t ldo) {
+    constexpr int NW = WM * WN, TB = WM * GB, BB = WN * NBLK;
+    constexpr int BLK = 2 * (TB + BB), PW = BLK / NW, STAGE = BLK * 1024;
+    static_assert(BLK % NW == 0, "DMA blocks must divide evenly over the waves");
+    __shared__ __attribute__((aligned(1024))) uint8_t ring[kRingStages][STAGE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WM, wn = wave / WM;
+    const WideTile tile = wide_tile();
+    const int g0 = tile.x * (TB * 16), b0 = tile.y * (BB * 16);
+    const int nst = (int)(ldp / 32);
+    const uint16_t *src[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const int b = wave * PW + i, piece = 8 * (lane >> 4);
+        if (b < 2 * TB) {
+            const int g = std::min(g0 + (b % TB) * 16 + (lane & 15), J - 1);
+            src[i] = (b < TB ? Tr : Ti) + (int64_t)g * ldp + piece;
+        } else {
+            const int c = b - 2 * TB;
+            const int band = std::min(b0 + (c % BB) * 16 + (lane & 15), N - 1);
+            src[i] = (c < BB ? Wr : Wi) + (int64_t)band * ldp + piece;
+        }
+    }
+    const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
+    auto issue = [&](int s) {
+        const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
+#pragma unroll
+        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
+    };
+    auto frag = [&](int s, int blk) {
+        return *reinterpret_cast<const bf16x8 *>(&ring[s % kRingStages][0] + blk * 1024 + lane * 16);
+    };
+    v4f ar_[NBLK][GB], ai_[NBLK][GB];
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int g = 0; g < GB; ++g) { ar_[i][g] = v4f{0, 0, 0, 0}; ai_[i][g] = v4f{0, 0, 0, 0}; }
+    issue(0);
+    if (nst > 1) issue(1);
+    if (nst > 2) issue(2);
+    if (nst > 2) ring_barrier<2 * PW>();
+    else if (nst > 1) ring_barrier<PW>();
+    else ring_barrier<0>();
+    bf16x8 tr[GB], ti[GB], cr, ci;
+#pragma unroll
+    for (int g = 0; g < GB; ++g) { tr[g] = frag(0, wm * GB + g); ti[g] = frag(0, TB + wm * GB + g); }
+    cr = frag(0, 2 * TB + wn * NBLK);
+    ci = frag(0, 2 * TB + BB + wn * NBLK);
+    for (int t = 0; t < nst; ++t) {
+        bf16x8 tn[GB], ntr[GB], nti[GB];
+#pragma unroll
+        for (int g = 0; g < GB; ++g) { tn[g] = neg8(ti[g]); ntr[g] = tr[g]; nti[g] = ti[g]; }
+#pragma unroll
+        for (int i = 0; i < NBLK; ++i) {
+            bf16x8 nr = cr, ni = ci;
+            if (i + 1 < NBLK) {
+                nr = frag(t, 2 * TB + wn * NBLK + i + 1);
+                ni = frag(t, 2 * TB + BB + wn * NBLK + i + 1);
+                PW_SCHED_READS(2);
+            } else if (t + 1 < nst) {
+                if (t + 2 < nst) ring_barrier<PW>();
+                else ring_barrier<0>();
+                if (t + 3 < nst) issue(t + 3);
+#pragma unroll
+                for (int g = 0; g < GB; ++g) { ntr[g] = frag(t + 1, wm * GB + g); nti[g] = frag(t + 1, TB + wm * GB + g); }
+                nr = frag(t + 1, 2 * TB + wn * NBLK);
+                ni = frag(t + 1, 2 * TB + BB + wn * NBLK);
+            }
+#pragma unroll
+            for (int g = 0; g < GB; ++g) {
+                // W beta: re = wr br - wi bi, im = wr bi + wi br
+                ar_[i][g] = mfma_bf16(cr, tr[g], ar_[i][g]);
+                ar_[i][g] = mfma_bf16(ci, tn[g], ar_[i][g]);
+                ai_[i][g] = mfma_bf16(cr, ti[g], ai_[i][g]);
+                ai_[i][g] = mfma_bf16(ci, tr[g], ai_[i][g]);
+            }
+            if (i + 1 < NBLK) PW_SCHED_MFMA(4 * GB);
+            cr = nr;
+            ci = ni;
+        }
+#pragma unroll
+        for (int g = 0; g < GB; ++g) { tr[g] = ntr[g]; ti[g] = nti[g]; }
+    }
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int g = 0; g < GB; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = b0 + (wn * NBLK + i) * 16 + 4 * (lane >> 4) + v;
+                const int gc = g0 + (wm * GB + g) * 16 + (lane & 15);
+                if (b < N && gc < J) {
+                    float2 *o = out + (int64_t)b * ldo + gc;
+                    const float2 old = *o;
+                    *o = make_float2(old.x + ar_[i][g][v], old.y + ai_[i][g][v]);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static int band_blocks(int nb) { return nb <= 64 ? 4 : nb <= 128 ? 8 : 9; }
@@ -773,7 +997,8 @@ static int proj_splits(int M, int64_t ldg) {
 static const int kWide[kBf16WideVariants][5] = {{2, 8, 4, 2, 32}, {2, 8, 4, 2, 64}, {2, 8, 2, 2, 32},
                                                 {2, 8, 2, 2, 64}, {4, 4, 2, 4, 32}, {1, 8, 4, 2, 64},
                                                 {2, 8, 4, 2, 32}, {4, 8, 2, 2, 32}, {2, 16, 4, 1, 32},
-                                                {4, 4, 2, 4, 32}};
+                                                {4, 4, 2, 4, 32}, {2, 8, 4, 2, 32}, {4, 8, 2, 2, 32},
+                                                {2, 16, 4, 1, 32}, {4, 4, 2, 4, 32}};
 constexpr int kWideBands = 256;
 static int wide_rows(int v) { return kWide[v][2] * kWide[v][0] * 16; }
 
@@ -808,7 +1033,7 @@ static void proj_wide_go(int v, int M, int N, const uint16_t *Br, const uint16_t
     PW_LAUNCH_CHECK();
 }
 
-template <int RB, int NBLK, int WM, int WN>
+template <int RB, int NBLK, int WM, int WN, bool PIPE = false>
 static void proj_ring_go(int v, int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_t ldg,
                          const uint16_t *Pr, const uint16_t *Pi, float2 *partial, int &nsplit, hipStream_t st) {
     const int ns = wide_splits(v, M, N, ldg);
@@ -817,18 +1042,26 @@ static void proj_ring_go(int v, int M, int N, const uint16_t *Br, const uint16_t
     nsplit = (int)((ldg + kchunk - 1) / kchunk);
     constexpr int rows = WM * RB * 16;
     dim3 grid((M + rows - 1) / rows, (N + kWideBands - 1) / kWideBands, nsplit);
-    hipLaunchKernelGGL((proj_ring<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
-                       kchunk, partial);
+    if (PIPE)
+        hipLaunchKernelGGL((proj_pipe<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
+                           kchunk, partial);
+    else
+        hipLaunchKernelGGL((proj_ring<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
+                           kchunk, partial);
     PW_LAUNCH_CHECK();
 }
 
-template <int GB, int NBLK, int WM, int WN>
+template <int GB, int NBLK, int WM, int WN, bool PIPE = false>
 static void back_ring_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
                          const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
     constexpr int cols = WM * GB * 16;
     dim3 grid((unsigned)((J + cols - 1) / cols), (N + kWideBands - 1) / kWideBands);
-    hipLaunchKernelGGL((backproj_ring<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi, Tr,
-                       Ti, out, ldo);
+    if (PIPE)
+        hipLaunchKernelGGL((backproj_pipe<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi,
+                           Tr, Ti, out, ldo);
+    else
+        hipLaunchKernelGGL((backproj_ring<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi,
+                           Tr, Ti, out, ldo);
     PW_LAUNCH_CHECK();
 }
 
@@ -904,7 +1137,11 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
             case 6: proj_ring_go<2, 8, 4, 2>(6, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
             case 7: proj_ring_go<4, 8, 2, 2>(7, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
             case 8: proj_ring_go<2, 16, 4, 1>(8, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            default: proj_ring_go<4, 4, 2, 4>(9, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 9: proj_ring_go<4, 4, 2, 4>(9, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 10: proj_ring_go<2, 8, 4, 2, true>(10, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 11: proj_ring_go<4, 8, 2, 2, true>(11, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 12: proj_ring_go<2, 16, 4, 1, true>(12, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            default: proj_ring_go<4, 4, 2, 4, true>(13, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
         }
         const int64_t tot = (int64_t)nb * ldp;
         hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
@@ -949,7 +1186,11 @@ void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT1
             case 6: back_ring_go<2, 8, 4, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
             case 7: back_ring_go<4, 8, 2, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
             case 8: back_ring_go<2, 16, 4, 1>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            default: back_ring_go<4, 4, 2, 4>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 9: back_ring_go<4, 4, 2, 4>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 10: back_ring_go<2, 8, 4, 2, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 11: back_ring_go<4, 8, 2, 2, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 12: back_ring_go<2, 16, 4, 1, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            default: back_ring_go<4, 4, 2, 4, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
         }
         return;
     }

@@ -117,7 +117,7 @@ void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, 
 void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
                          hipStream_t st);
 // variant: launch variant of the kernels for more than 144 bands (autotuner pass 6)
-constexpr int kBf16WideVariants = 10;
+constexpr int kBf16WideVariants = 14;
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
                int64_t ld, void *scratch, void *partial, hipStream_t st, int variant = 0);
 void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,

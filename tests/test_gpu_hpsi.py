@@ -287,9 +287,48 @@ def test_bf16_wide_variants_agree(torch_cuda):
     bound = 4 * 2.0 ** -8 * torch.linalg.vector_norm(nl, dim=1) + 1e-5 * torch.linalg.vector_norm(ref, dim=1)
     x32 = x.to(torch.complex64)
     recs = [r for r in pw.autotune(ctx, 64, dtype=pw.PW_C64, reps=1) if r["pass_"] == 6]
-    assert len(recs) == 10 and sum(r["chosen"] for r in recs) == 1
+    assert len(recs) == 14 and sum(r["chosen"] for r in recs) == 1
+    outs = {}
     for r in recs:
         pw.fft_choose(ctx, r, dtype=pw.PW_C64)
-        got = pw.hpsi(ctx, x32, shift=prob.e_ref).to(torch.complex128)
-        err = torch.linalg.vector_norm(got - ref, dim=1)
+        got = pw.hpsi(ctx, x32, shift=prob.e_ref)
+        outs[r["sched"]] = got
+        err = torch.linalg.vector_norm(got.to(torch.complex128) - ref, dim=1)
         assert bool(torch.all(err <= bound)), (r["sched"], float((err / bound).max()))
+    for v in range(10, 14):      # pipelined ring kernels: the same products in the same order
+        assert torch.equal(outs[v], outs[v - 4]), v
+
+
+@pytest.mark.parametrize("ecut,natom,tail", [(10.4, 3, 1), (9.0, 3, 2), (8.0, 20, 3)])
+def test_bf16_ring_short_splits(torch_cuda, ecut, natom, tail):
+    """The LDS-DMA ring kernels (launch variants 6-13) where a workgroup's K range
+    holds only one, two or three 32-deep stages (the last projection split; the
+    back-projection over 12 or 80 projectors, two or four stages): 160 bands,
+    every variant within the BF16 bound of complex128, the pipelined kernels
+    (10-13) bit for bit those of the same tile shape (6-9)."""
+    import torch
+    import paper_1907_06821_amd as pw
+    prob = synth.small_nonlocal_problem(grid=(24, 24, 30), ecut=ecut, natom=natom, nbands=160)
+    nb = 160
+    ctx = gpu_context(prob, max_bands=nb, flags=pw.PW_PREP_C128 | pw.PW_PREP_C64)
+    # the split of the projection's plane-wave range (128-row tiles, about 512
+    # workgroups, at least four stages a split): its last split holds `tail` stages
+    ldg = (ctx.npw + 63) // 64 * 64
+    ns = max(1, min(512, ldg // 128))
+    kchunk = ((ldg + ns - 1) // ns + 31) // 32 * 32
+    assert (ldg - (math.ceil(ldg / kchunk) - 1) * kchunk) // 32 == tail
+    loc = pw.Context.from_problem(dataclasses.replace(prob, pos=prob.pos[:0], depth=prob.depth[:0],
+                                                      dproj=prob.dproj[:0]), max_bands=nb, flags=pw.PW_PREP_C128)
+    x = to_dev(random_block(17, nb, ctx.npw))
+    ref = pw.hpsi(ctx, x, shift=prob.e_ref)
+    nl = ref - pw.hpsi(loc, x, shift=prob.e_ref)
+    bound = 4 * 2.0 ** -8 * torch.linalg.vector_norm(nl, dim=1) + 1e-5 * torch.linalg.vector_norm(ref, dim=1)
+    x32 = x.to(torch.complex64)
+    outs = {}
+    for v in range(6, 14):
+        pw.fft_choose(ctx, dict(pass_=6, kind=3, sched=v), dtype=pw.PW_C64)
+        outs[v] = pw.hpsi(ctx, x32, shift=prob.e_ref)
+        err = torch.linalg.vector_norm(outs[v].to(torch.complex128) - ref, dim=1)
+        assert bool(torch.all(err <= bound)), (v, float((err / bound).max()))
+    for v in range(10, 14):
+        assert torch.equal(outs[v], outs[v - 4]), v
