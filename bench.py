@@ -726,8 +726,10 @@ def stage_rooflines(ctx, nb, band_hpsi, mixed, prof):
     the profiled iterations; the xy pass also reads V once per launch) against
     HBM; the projector GEMMs do 8 nproj npw flops per band-H psi against the
     matrix peak of their precision (BF16 mixed, FP64 otherwise); the solver's FP64
-    block products do 8 npw nb^2 flops per product (three in block_rotate3)
-    against the FP64 peak.  avg_ms and work_per_launch are totals over launches."""
+    block products do 8 npw nb^2 flops per product (three in block_rotate3, whose
+    lower triangular matrix has nb (nb + 1) / 2 nonzero entries), a Hermitian Gram
+    matrix X^H X 4 npw nb (nb + 1) (the entries on and below the diagonal), against
+    the FP64 peak.  avg_ms and work_per_launch are totals over launches."""
     npw = ctx.npw
     n0, n1, n2 = ctx.grid
     per_band = stage_work(ctx, 1, 8 if mixed else 16, ctx.nproj)
@@ -741,7 +743,12 @@ def stage_rooflines(ctx, nb, band_hpsi, mixed, prof):
             # block_rotate3 rotates by the Cholesky inverse, lower triangular: nb (nb + 1) / 2 of its
             # entries are not zero, 3 blocks x 8 npw flops each
             bound, peak = "mfma", FP64_PEAK_TFS
-            total = (3 * 8.0 * npw * nb * (nb + 1) / 2 if k == "block_rotate3" else blk) * n
+            if k == "block_rotate3":
+                total = 3 * 8.0 * npw * nb * (nb + 1) / 2 * n
+            elif k == "block_gram_herm":
+                total = 4.0 * npw * nb * (nb + 1) * n
+            else:
+                total = blk * n
         else:
             bound, amount, _ = per_band[k]
             if k == "xy_fft_v":

@@ -176,8 +176,9 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * in the same form, is the block-rotation GEMM of the solver (an nb x nb matrix
  * times the nb-band block).  Pass 6 (complex64, contexts of more than 144
  * bands) is the BF16 projection and back-projection pair timed together at
- * max_bands: kind 3, sched the launch variant (0-5 register-prefetch tiles of
- * 256 bands, 6-9 tiles fed by LDS DMA three stages deep). */
+ * max_bands: kind 3, sched the launch variant 0-3 (four tile shapes of 256
+ * bands, fed by LDS DMA three stages deep from the 16-row panels such contexts
+ * keep their BF16 planes in). */
 typedef struct {
     int32_t pass;
     int32_t kind;
@@ -503,11 +504,13 @@ pw_status pw_mlp_train(int32_t nshell, int32_t nb, int32_t nsnap, const double *
  * (for generated rows: per chunk, the row generation counted with neither), and
  * the folded-CG solver's FP64 block products: 5 the rotation of X, Y and AX by
  * one nb x nb matrix (three products of 8 npw nb^2 flops in one launch), 6 the nb x nb
- * Gram-type products A^H B (8 npw nb^2 flops), 7 the other single rotations
- * nb x nb times nb x npw (8 npw nb^2 flops; the P update, the Ritz rotations).
+ * products A^H B of two different blocks (8 npw nb^2 flops), 7 the other single
+ * rotations nb x nb times nb x npw (8 npw nb^2 flops; the P update, the Ritz
+ * rotations), 8 the Hermitian Gram matrices X^H X (the tiles on and below the
+ * diagonal; 4 npw nb (nb + 1) flops determine the matrix).
  * Inside pw_folded_cg_solve only the CG iterations are recorded, not the set-up,
  * the checks or the final Rayleigh-Ritz. */
-#define PW_PROF_NKINDS 8
+#define PW_PROF_NKINDS 9
 pw_status pw_profile_begin(pw_ctx *ctx, int32_t max_records);
 pw_status pw_profile_end(pw_ctx *ctx, double *ms, int64_t *launches);
 

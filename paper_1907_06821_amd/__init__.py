@@ -33,8 +33,8 @@ EXPORTS = ("pw_basis_size", "pw_basis_miller", "pw_ctx_create", "pw_ctx_destroy"
            "pw_lin_opts_default", "pw_folded_linear_solve", "pw_cheb_filter", "pw_chebfd_step",
            "pw_spectral_bounds", "pw_kinterp", "pw_ctx_set_otf_atoms", "pw_dense_eigh_noalloc")
 PROF_KINDS = ("z_inverse", "xy_fft_v", "z_forward_kinetic", "projection", "back_projection", "block_rotate3",
-              "block_gram", "block_rotate")
-PW_PROF_NKINDS = 8
+              "block_gram", "block_rotate", "block_gram_herm")
+PW_PROF_NKINDS = 9
 
 
 class PwError(RuntimeError):

@@ -10,7 +10,7 @@ const char *last_error();
 void build_projectors(int npw, int natom, int nl, const int32_t *d_miller, const pw_cell &c, const double *d_pos,
                       double sigma, void *beta, hipStream_t st);
 void build_vz(int n0, int n1, int n2, const double *v, double *vz64, float *vz32, hipStream_t st);
-void beta_to_bf16(int rows, int npw, int64_t ldp, const void *src, void *re, void *im, hipStream_t st);
+void beta_to_bf16(int rows, int npw, int64_t ldp, const void *src, void *re, void *im, hipStream_t st, bool panel);
 void solver_destroy(Solver *s);
 
 void DevBuf::alloc(size_t b) {
@@ -67,7 +67,7 @@ size_t hpsi_partial_bytes(const pw_ctx *ctx) {
                 if (tail) b = std::max(b, nt_partial_bytes(tail * ctx->nl, n, npw));
             }
         }
-        if (ctx->nproj && c64) b = std::max(b, cnt_partial_bytes(ctx->nproj, n, npw));
+        if (ctx->nproj && c64) b = std::max(b, cnt_partial_bytes(ctx->nproj, n, npw, ctx->max_bands));
         if (c128) b = std::max(b, nt_partial_bytes(n, n, npw));
     }
     return b;
@@ -322,14 +322,18 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
         }
         if (flags & PW_PREP_C64) {
             c->ldb16 = ((b.npw + 63) / 64) * 64;
-            c->d_beta_bf16.alloc((size_t)2 * c->nproj * c->ldb16 * 2);
-            char *br = (char *)c->d_beta_bf16.p, *bi = br + (size_t)c->nproj * c->ldb16 * 2;
+            // contexts of more than 144 bands keep the planes in 16-row panels (rows padded to 16)
+            const bool panel = bf16_panels(max_bands);
+            const size_t prow = (size_t)bf16_rows(c->nproj, max_bands);
+            c->d_beta_bf16.alloc((size_t)2 * prow * c->ldb16 * 2);
+            char *br = (char *)c->d_beta_bf16.p, *bi = br + prow * c->ldb16 * 2;
+            if (prow > (size_t)c->nproj) fill_zero(c->d_beta_bf16.p, c->d_beta_bf16.bytes, st);
             const size_t tplane = (size_t)bf16_ld(b.npw) * bf16_ld(c->nproj) * 2;
             c->d_betaT_bf16.alloc(2 * tplane);
             char *tr = (char *)c->d_betaT_bf16.p, *ti = tr + tplane;
             if (c128) {
-                beta_to_bf16(c->nproj, b.npw, c->ldb16, c->d_beta64.p, br, bi, st);
-                beta_to_bf16_t(c->nproj, b.npw, c->d_beta64.p, tr, ti, st);
+                beta_to_bf16(c->nproj, b.npw, c->ldb16, c->d_beta64.p, br, bi, st, panel);
+                beta_to_bf16_t(c->nproj, b.npw, c->d_beta64.p, tr, ti, st, panel);
             } else {
                 // complex64 only: the FP64 rows are built and rounded 64 atoms at a time, so the FP64
                 // table (16 nproj npw bytes) never exists whole; the BF16 planes are the same bits
@@ -341,12 +345,13 @@ pw_status pw_ctx_create(const pw_cell *cell, const pw_potential *pot, int32_t ma
                     build_projectors(b.npw, na, c->nl, d_mil.as<int32_t>(), *cell, d_pos.as<double>() + 3 * a0,
                                      pot->sigma, chunk.p, st);
                     beta_to_bf16(rows, b.npw, c->ldb16, chunk.p, br + (size_t)p0 * c->ldb16 * 2,
-                                 bi + (size_t)p0 * c->ldb16 * 2, st);
-                    beta_to_bf16_t_rows(c->nproj, p0, rows, b.npw, chunk.p, tr, ti, st);
+                                 bi + (size_t)p0 * c->ldb16 * 2, st, panel);
+                    beta_to_bf16_t_rows(c->nproj, p0, rows, b.npw, chunk.p, tr, ti, st, panel);
                 }
                 PW_HIP(hipStreamSynchronize(st));     // the chunk buffer dies here
             }
             c->d_bf16_ws.alloc(bf16_scratch_bytes(c->nproj, b.npw, max_bands));
+            if (panel) fill_zero(c->d_bf16_ws.p, c->d_bf16_ws.bytes, st);   // padding rows of the last panel
             acct += c->d_beta_bf16.bytes + c->d_betaT_bf16.bytes + c->d_bf16_ws.bytes;
         }
         acct += c->d_beta64.bytes;

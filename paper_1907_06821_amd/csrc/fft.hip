@@ -519,6 +519,17 @@ __global__ __launch_bounds__(NTHR) void xy_quad_jobs(const FftJob *__restrict__ 
     xy_quad_body<T, M, NTHR>(j.xy, reinterpret_cast<cplx<T> *>(j.cols), blockIdx.x, blockIdx.y % nb);
 }
 
+// timing input of the autotuner: values in [-1, 1) from an integer hash of the index
+__global__ void k_fill_tune(float2 *__restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    p[i] = make_float2((float)(h & 0xffff) / 32768.0f - 1.0f, (float)(h >> 16) / 32768.0f - 1.0f);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -1225,14 +1236,18 @@ void autotune_fft(pw_ctx *ctx, int nb, int reps, std::vector<pw_fft_cand> &recs,
         PW_HIP(hipStreamSynchronize(s));
     }
     // complex64 BF16 projector GEMMs beyond 144 bands (pass 6): every launch variant of the
-    // projection and back-projection pair, timed on max_bands bands
+    // projection and back-projection pair, timed on max_bands bands of nonzero values (the
+    // matrix cores' power, and with it the clock, depends on the data)
     int bf16_best = -1;
     if (sizeof(T) == 4 && ctx->nproj > 0 && ctx->max_bands > 144 && ctx->d_beta_bf16.p) {
         const int nbw = ctx->max_bands, npw = ctx->basis.npw;
         DevBuf win, wout;
         win.alloc((size_t)nbw * npw * 8);
         wout.alloc((size_t)nbw * npw * 8);
-        fill_zero(win.p, (size_t)nbw * npw * 8, s);
+        const size_t nval = (size_t)nbw * npw;
+        hipLaunchKernelGGL(k_fill_tune, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, s,
+                           (float2 *)win.p, nval);
+        PW_LAUNCH_CHECK();
         fill_zero(wout.p, (size_t)nbw * npw * 8, s);
         const size_t first = recs.size();
         for (int v = 0; v < kBf16WideVariants; ++v) {

@@ -5,16 +5,20 @@
 //   back-projection out[b][G]  += sum_p projT[b][p] beta_p(G)
 //
 // Tables (built once per context, zero padded):
-//   beta   planes [nproj][ldg]   (ldg = npw rounded up to 64)   projection operand
-//   betaT  planes [ldg][ldp]     (ldp = nproj rounded up to 64) back-projection operand
-// so that every MFMA operand fragment (8 consecutive k of one row) is one
-// 16-byte load.  Per H psi the wave functions are rounded once to BF16 planes
-// [nb][ldg], and the projection's reduction writes D . C directly as BF16
-// planes [nb][ldp].  Up to 144 bands, workgroup tiles span all bands of the
-// call, so each table is read once per H psi; beyond that, wide tiles of 256
-// bands (each wave 32 table rows by 128 bands) read it once per 256 bands.  The
-// band operand of each tile is staged in LDS and shared by the waves, the table
-// fragments go straight from memory into registers.  Rounding is to nearest even.
+//   beta   planes nproj x ldg   (ldg = npw rounded up to 64)   projection operand
+//   betaT  planes ldg x ldp     (ldp = nproj rounded up to 64) back-projection operand
+// Per H psi the wave functions are rounded once to BF16 planes nb x ldg, and the
+// projection's reduction writes D . C directly as BF16 planes nb x ldp.
+//
+// Contexts of up to 144 bands keep every plane row-major, so that each MFMA
+// operand fragment (8 consecutive k of one row) is one 16-byte load; workgroup
+// tiles span all bands of the call, each table is read once per H psi, the band
+// operand is staged in LDS and the table fragments go straight into registers.
+// Contexts of more than 144 bands store every plane in 16-row panels
+// (bf16_panel_index): 16 rows by 32 k as one 1 KB fragment in the matrix cores'
+// lane order, a panel's fragments in k order.  Their kernels (the ring kernels
+// below) copy whole fragments from memory into LDS, tiles of 256 bands, so each
+// table is read once per 256 bands.  Rounding is to nearest even.
 #include "kernels.h"
 
 namespace pw {
@@ -58,22 +62,26 @@ constexpr int MAXNB = 144;      // largest band tile (9 blocks of 16)
 int64_t bf16_ld(int n) { return ((int64_t)n + 63) / 64 * 64; }
 
 // ---------------------------------------------------------------------------
-// complex64 rows -> BF16 planes [rows][ldp], zero beyond n
+// complex64 rows -> BF16 planes of rows x ldp (row-major or 16-row panels), zero
+// beyond n
 // ---------------------------------------------------------------------------
 __global__ void k_c64_to_planes(int rows, int n, const float2 *__restrict__ src, int64_t lds, int64_t ldp,
-                                uint16_t *__restrict__ re, uint16_t *__restrict__ im) {
+                                uint16_t *__restrict__ re, uint16_t *__restrict__ im, int panel) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (g >= ldp) return;
     const float2 v = g < n ? src[(int64_t)r * lds + g] : make_float2(0.f, 0.f);
-    re[(int64_t)r * ldp + g] = f2bf(v.x);
-    im[(int64_t)r * ldp + g] = f2bf(v.y);
+    const int64_t o = panel ? bf16_panel_index(r, g, ldp) : (int64_t)r * ldp + g;
+    re[o] = f2bf(v.x);
+    im[o] = f2bf(v.y);
 }
 
 // complex128 table rows [r_off, r_off + rows) ([rows][n]) -> columns of the transposed BF16 planes
-// [ldn][ldr]; columns from r_off + rows up to r_end are written as zeros (padding)
+// ldn x ldr (row-major or 16-row panels); columns from r_off + rows up to r_end are written as
+// zeros (padding)
 __global__ void k_c128_to_planes_t(int rows, int n, const double2 *__restrict__ src, int64_t ldr, int64_t ldn,
-                                   uint16_t *__restrict__ re, uint16_t *__restrict__ im, int r_off, int64_t r_end) {
+                                   uint16_t *__restrict__ re, uint16_t *__restrict__ im, int r_off, int64_t r_end,
+                                   int panel) {
     __shared__ double2 tile[32][33];
     const int r0 = r_off + blockIdx.y * 32, g0 = blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
@@ -86,26 +94,27 @@ __global__ void k_c128_to_planes_t(int rows, int n, const double2 *__restrict__ 
         const int g = g0 + y, r = r0 + tx;
         if (g < ldn && r < r_end) {
             const double2 v = tile[tx][y];
-            re[(int64_t)g * ldr + r] = f2bf((float)v.x);
-            im[(int64_t)g * ldr + r] = f2bf((float)v.y);
+            const int64_t o = panel ? bf16_panel_index(g, r, ldr) : (int64_t)g * ldr + r;
+            re[o] = f2bf((float)v.x);
+            im[o] = f2bf((float)v.y);
         }
     }
 }
 
-void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st) {
-    beta_to_bf16_t_rows(nproj, 0, nproj, npw, beta64, tr, ti, st);
+void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st, bool panel) {
+    beta_to_bf16_t_rows(nproj, 0, nproj, npw, beta64, tr, ti, st, panel);
 }
 
 // rows [p0, p0 + rows) of an nproj-row table (beta64 holds just those rows); the
 // chunk that ends the table also writes the zero columns up to the padded width
 void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
-                         hipStream_t st) {
+                         hipStream_t st, bool panel) {
     const int64_t ldr = bf16_ld(nproj), ldn = bf16_ld(npw);
     PW_CHECK(p0 % 32 == 0 && p0 + rows <= nproj, PW_EINVAL, "table chunk must start on a 32-row boundary");
     const int64_t r_end = p0 + rows == nproj ? ldr : p0 + rows;
     dim3 grid((unsigned)((ldn + 31) / 32), (unsigned)((r_end - p0 + 31) / 32));
     hipLaunchKernelGGL(k_c128_to_planes_t, grid, dim3(256), 0, st, rows, npw, (const double2 *)beta64, ldr, ldn,
-                       (uint16_t *)tr, (uint16_t *)ti, p0, r_end);
+                       (uint16_t *)tr, (uint16_t *)ti, p0, r_end, panel ? 1 : 0);
     PW_LAUNCH_CHECK();
 }
 
@@ -195,10 +204,11 @@ __global__ __launch_bounds__(NW * 64) void proj16_partial(int M, int N, const ui
         }
 }
 
-// W planes [b][ldp] = bf16(d[p] * sum_s partial[s][b][p]), zero for p >= M
+// W planes N x ldp (row-major or 16-row panels) = bf16(d[p] * sum_s partial[s][b][p]),
+// zero for p >= M
 __global__ void proj16_reduce(int M, int N, int nsplit, const float2 *__restrict__ partial,
                               const float *__restrict__ d, int64_t ldp, uint16_t *__restrict__ Wr,
-                              uint16_t *__restrict__ Wi) {
+                              uint16_t *__restrict__ Wi, int panel) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)N * ldp) return;
     const int n = (int)(idx / ldp), m = (int)(idx % ldp);
@@ -214,8 +224,9 @@ __global__ void proj16_reduce(int M, int N, int nsplit, const float2 *__restrict
         re = (float)(sr * sc);
         im = (float)(si * sc);
     }
-    Wr[idx] = f2bf(re);
-    Wi[idx] = f2bf(im);
+    const int64_t o = panel ? bf16_panel_index(n, m, ldp) : idx;
+    Wr[o] = f2bf(re);
+    Wi[o] = f2bf(im);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,18 +312,6 @@ __global__ __launch_bounds__(NW * 64) void backproj16(int N, int J, int64_t ldp,
         }
 }
 
-// ---------------------------------------------------------------------------
-// Wide band blocks (calls of more than MAXNB bands).  A workgroup of WM x WN waves
-// covers WM*RB*16 table rows (projection) or plane waves (back-projection) by
-// WN*NBLK*16 = 256 bands; each wave takes RB row blocks by NBLK band blocks, so a
-// band fragment read from LDS feeds RB complex products and a table fragment
-// (straight from memory into registers) NBLK of them.  The table is read once per
-// 256 bands (four times for 1024 bands, where 128-band chunks read it eight
-// times), and every LDS read feeds twice the matrix work of the narrow kernels.
-// KW-deep stages; the next stage's table fragments and band pieces are loaded
-// into registers while the current one is multiplied.
-// ---------------------------------------------------------------------------
-
 // Workgroups go to the eight XCDs (each with its own L2) round robin in dispatch
 // order.  wide_tile renumbers them so that each XCD takes one contiguous run of
 // tile indices, band tile fastest: the workgroups running together on an XCD are
@@ -332,224 +331,27 @@ __device__ inline WideTile wide_tile() {
     return WideTile{(L / Y) % X, L % Y, L / (X * Y)};
 }
 
-template <int RB, int NBLK, int WM, int WN, int KW>
-__global__ __launch_bounds__(WM * WN * 64) void proj_wide(int M, int N, const uint16_t *__restrict__ Br,
-                                                          const uint16_t *__restrict__ Bi, int64_t ldg,
-                                                          const uint16_t *__restrict__ Pr,
-                                                          const uint16_t *__restrict__ Pi, int kchunk,
-                                                          float2 *__restrict__ partial) {
-    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW, LPW = KW + 8, KSUB = KW / 32;
-    constexpr int PPT = NB * (KW / 8) / NT;              // 16-byte band pieces per thread and plane
-    static_assert(KW % 32 == 0 && NB * (KW / 8) % NT == 0, "band pieces must divide evenly over the threads");
-    __shared__ __attribute__((aligned(16))) uint16_t sPr[NB][LPW], sPi[NB][LPW];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
-    const WideTile tile = wide_tile();
-    const int m0 = tile.x * (WM * RB * 16) + wm * RB * 16;
-    const int n0 = tile.y * NB;
-    const int s = tile.z;
-    const int kbeg = s * kchunk;
-    const int kend = (int)min((int64_t)kbeg + kchunk, ldg);
-    v4f ar_[RB][NBLK], ai_[RB][NBLK];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int j = 0; j < NBLK; ++j) { ar_[r][j] = v4f{0, 0, 0, 0}; ai_[r][j] = v4f{0, 0, 0, 0}; }
-    int64_t rowA[RB];
-    bool okA[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        rowA[r] = m0 + r * 16 + (lane & 15);
-        okA[r] = rowA[r] < M;
-    }
-    bf16x8 fa_r[RB][KSUB], fa_i[RB][KSUB];
-    uint4 pr_n[PPT], pi_n[PPT];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int q = 0; q < KSUB; ++q) {
-                const int64_t off = rowA[r] * ldg + k0 + 32 * q + 8 * (lane >> 4);
-                fa_r[r][q] = okA[r] ? load8(Br + off) : zero8();
-                fa_i[r][q] = okA[r] ? load8(Bi + off) : zero8();
-            }
-#pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
-            const int band = n0 + r;
-            pr_n[t] = make_uint4(0, 0, 0, 0);
-            pi_n[t] = make_uint4(0, 0, 0, 0);
-            if (band < N) {
-                pr_n[t] = *reinterpret_cast<const uint4 *>(Pr + (int64_t)band * ldg + k0 + c8);
-                pi_n[t] = *reinterpret_cast<const uint4 *>(Pi + (int64_t)band * ldg + k0 + c8);
-            }
-        }
-    };
-    if (kbeg < kend) fetch(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += KW) {
-#pragma unroll
-        for (int t = 0; t < PPT; ++t) {
-            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
-            *reinterpret_cast<uint4 *>(&sPr[r][c8]) = pr_n[t];
-            *reinterpret_cast<uint4 *>(&sPi[r][c8]) = pi_n[t];
-        }
-        bf16x8 ca_r[RB][KSUB], ca_i[RB][KSUB], cn_i[RB][KSUB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int q = 0; q < KSUB; ++q) {
-                ca_r[r][q] = fa_r[r][q];
-                ca_i[r][q] = fa_i[r][q];
-                cn_i[r][q] = neg8(fa_i[r][q]);
-            }
-        __syncthreads();
-        if (k0 + KW < kend) fetch(k0 + KW);
-#pragma unroll
-        for (int q = 0; q < KSUB; ++q) {
-            const int kk = 32 * q + 8 * (lane >> 4);
-#pragma unroll
-            for (int j = 0; j < NBLK; ++j) {
-                const int row = wn * NBW + j * 16 + (lane & 15);
-                const bf16x8 pr = load8(&sPr[row][kk]), pi = load8(&sPi[row][kk]);
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
-                    ar_[r][j] = mfma_bf16(ca_r[r][q], pr, ar_[r][j]);
-                    ar_[r][j] = mfma_bf16(ca_i[r][q], pi, ar_[r][j]);
-                    ai_[r][j] = mfma_bf16(ca_r[r][q], pi, ai_[r][j]);
-                    ai_[r][j] = mfma_bf16(cn_i[r][q], pr, ai_[r][j]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    float2 *P = partial + (int64_t)s * M * N;
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int j = 0; j < NBLK; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = m0 + r * 16 + 4 * (lane >> 4) + v;
-                const int col = n0 + wn * NBW + j * 16 + (lane & 15);
-                if (row < M && col < N) P[(int64_t)col * M + row] = make_float2(ar_[r][j][v], ai_[r][j][v]);
-            }
-}
-
-template <int GB, int NBLK, int WM, int WN, int KW>
-__global__ __launch_bounds__(WM * WN * 64) void backproj_wide(int N, int J, int64_t ldp,
-                                                              const uint16_t *__restrict__ Wr,
-                                                              const uint16_t *__restrict__ Wi,
-                                                              const uint16_t *__restrict__ Tr,
-                                                              const uint16_t *__restrict__ Ti,
-                                                              float2 *__restrict__ out, int64_t ldo) {
-    constexpr int NT = WM * WN * 64, NBW = NBLK * 16, NB = WN * NBW, LPW = KW + 8, KSUB = KW / 32;
-    constexpr int WPT = NB * (KW / 8) / NT;              // 16-byte W pieces per thread and plane
-    static_assert(KW % 32 == 0 && NB * (KW / 8) % NT == 0, "W pieces must divide evenly over the threads");
-    __shared__ __attribute__((aligned(16))) uint16_t sWr[NB][LPW], sWi[NB][LPW];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
-    const WideTile tile = wide_tile();
-    const int b0 = tile.y * NB;
-    int64_t gcol[GB];
-    bool okB[GB];
-#pragma unroll
-    for (int g = 0; g < GB; ++g) {
-        gcol[g] = (int64_t)tile.x * (WM * GB * 16) + wm * GB * 16 + g * 16 + (lane & 15);
-        okB[g] = gcol[g] < J;
-    }
-    v4f ar_[NBLK][GB], ai_[NBLK][GB];
-#pragma unroll
-    for (int i = 0; i < NBLK; ++i)
-#pragma unroll
-        for (int g = 0; g < GB; ++g) { ar_[i][g] = v4f{0, 0, 0, 0}; ai_[i][g] = v4f{0, 0, 0, 0}; }
-    bf16x8 fb_r[GB][KSUB], fb_i[GB][KSUB];
-    uint4 wr_n[WPT], wi_n[WPT];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int g = 0; g < GB; ++g)
-#pragma unroll
-            for (int q = 0; q < KSUB; ++q) {
-                const int64_t off = gcol[g] * ldp + k0 + 32 * q + 8 * (lane >> 4);
-                fb_r[g][q] = okB[g] ? load8(Tr + off) : zero8();
-                fb_i[g][q] = okB[g] ? load8(Ti + off) : zero8();
-            }
-#pragma unroll
-        for (int t = 0; t < WPT; ++t) {
-            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
-            const int band = b0 + r;
-            wr_n[t] = make_uint4(0, 0, 0, 0);
-            wi_n[t] = make_uint4(0, 0, 0, 0);
-            if (band < N) {
-                wr_n[t] = *reinterpret_cast<const uint4 *>(Wr + (int64_t)band * ldp + k0 + c8);
-                wi_n[t] = *reinterpret_cast<const uint4 *>(Wi + (int64_t)band * ldp + k0 + c8);
-            }
-        }
-    };
-    fetch(0);
-    for (int k0 = 0; k0 < ldp; k0 += KW) {
-#pragma unroll
-        for (int t = 0; t < WPT; ++t) {
-            const int e = tid + t * NT, r = e / (KW / 8), c8 = (e % (KW / 8)) * 8;
-            *reinterpret_cast<uint4 *>(&sWr[r][c8]) = wr_n[t];
-            *reinterpret_cast<uint4 *>(&sWi[r][c8]) = wi_n[t];
-        }
-        bf16x8 cb_r[GB][KSUB], cb_i[GB][KSUB];
-#pragma unroll
-        for (int g = 0; g < GB; ++g)
-#pragma unroll
-            for (int q = 0; q < KSUB; ++q) { cb_r[g][q] = fb_r[g][q]; cb_i[g][q] = fb_i[g][q]; }
-        __syncthreads();
-        if (k0 + KW < ldp) fetch(k0 + KW);
-#pragma unroll
-        for (int q = 0; q < KSUB; ++q) {
-            const int kk = 32 * q + 8 * (lane >> 4);
-#pragma unroll
-            for (int i = 0; i < NBLK; ++i) {
-                const int row = wn * NBW + i * 16 + (lane & 15);
-                const bf16x8 wr = load8(&sWr[row][kk]), wi = load8(&sWi[row][kk]);
-                const bf16x8 nwi = neg8(wi);
-#pragma unroll
-                for (int g = 0; g < GB; ++g) {
-                    // W beta: re = wr br - wi bi, im = wr bi + wi br
-                    ar_[i][g] = mfma_bf16(wr, cb_r[g][q], ar_[i][g]);
-                    ar_[i][g] = mfma_bf16(nwi, cb_i[g][q], ar_[i][g]);
-                    ai_[i][g] = mfma_bf16(wr, cb_i[g][q], ai_[i][g]);
-                    ai_[i][g] = mfma_bf16(wi, cb_r[g][q], ai_[i][g]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < NBLK; ++i)
-#pragma unroll
-        for (int g = 0; g < GB; ++g)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = b0 + wn * NBW + i * 16 + 4 * (lane >> 4) + v;
-                if (b < N && okB[g]) {
-                    float2 *o = out + (int64_t)b * ldo + gcol[g];
-                    const float2 old = *o;
-                    *o = make_float2(old.x + ar_[i][g][v], old.y + ai_[i][g][v]);
-                }
-            }
-}
-
 // ---------------------------------------------------------------------------
-// Ring variants of the wide kernels.  Both operands of a 32-deep stage go from
-// memory straight into LDS through global_load_lds_dwordx4 (no registers on the
-// way), kRingStages stages deep: a workgroup keeps two stages (96 KB) of loads
-// in flight while it multiplies a third, where the register-prefetch kernels
-// above hold one stage and stall on memory latency.  LDS holds each 16 x 32
-// fragment of a plane as one 1 KB block in the MFMA's lane order (lane l: row
-// l % 16, k 8 (l / 16) + 0..7), so every fragment read is one linear
-// ds_read_b128.  Rows beyond an operand are read as its last row: their
-// products only reach outputs that are not stored.  The copies are issued in
-// inline assembly because the compiler, not knowing which stage a DMA fills,
-// would wait for all of them before any LDS read; here each wave waits for its
-// own copies of the stage it is about to use (s_waitcnt vmcnt counts them in
-// issue order) and the barrier then publishes every wave's part.
+// Wide band blocks (contexts of more than MAXNB bands, operands in 16-row
+// panels).  A workgroup of WM x WN waves covers WM*RB*16 table rows (projection)
+// or plane waves (back-projection) by WN*NBLK*16 = 256 bands; each wave takes RB
+// row blocks by NBLK band blocks, so a band fragment read from LDS feeds RB
+// complex products and a table fragment NBLK of them.  Both operands of a
+// 32-deep stage go from memory straight into LDS through
+// global_load_lds_dwordx4 (no registers on the way), kRingStages stages deep: a
+// workgroup keeps two stages (96 KB) of loads in flight while it multiplies a
+// third.  Each copy moves one whole 1 KB fragment of a panel, contiguous in
+// memory and already in the MFMA's lane order (lane l: row l % 16, k 8 (l / 16)
+// + 0..7), into one 1 KB block of LDS, so every fragment read is one linear
+// ds_read_b128; a workgroup streams a few dozen panels, each sequentially along
+// k.  (Row-major planes, where each copy gathers 64 bytes from each of 16 rows
+// 1.5 MB apart, ran the same copies at less than half the rate: every row is
+// its own stream and page.)  Row blocks beyond an operand are read as its last
+// block: their products only reach outputs that are not stored.  The copies
+// are issued in inline assembly because the compiler, not knowing which stage a
+// DMA fills, would wait for all of them before any LDS read; here each wave
+// waits for its own copies of the stage it is about to use (s_waitcnt vmcnt
+// counts them in issue order) and the barrier then publishes every wave's part.
 // ---------------------------------------------------------------------------
 constexpr int kRingStages = 3;
 
@@ -597,23 +399,24 @@ __global__ __launch_bounds__(WM * WN * 64) void proj_ring(int M, int N, const ui
     const int kbeg = tile.z * kchunk;
     const int nst = (int)((std::min((int64_t)kbeg + kchunk, ldg) - kbeg) / 32);
     const uint16_t *src[PW];
+    const int64_t kb0 = ((int64_t)(ldg >> 5) << 9), kfirst = (int64_t)(kbeg >> 5) << 9;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
-        const int b = wave * PW + i, piece = 8 * (lane >> 4);
+        const int b = wave * PW + i;
         if (b < 2 * TB) {
-            const int row = std::min(m0 + (b % TB) * 16 + (lane & 15), M - 1);
-            src[i] = (b < TB ? Br : Bi) + (int64_t)row * ldg + kbeg + piece;
+            const int rb = std::min(m0 / 16 + b % TB, (M - 1) >> 4);
+            src[i] = (b < TB ? Br : Bi) + rb * kb0 + kfirst + lane * 8;
         } else {
             const int c = b - 2 * TB;
-            const int band = std::min(n0 + (c % BB) * 16 + (lane & 15), N - 1);
-            src[i] = (c < BB ? Pr : Pi) + (int64_t)band * ldg + kbeg + piece;
+            const int nb = std::min(n0 / 16 + c % BB, (N - 1) >> 4);
+            src[i] = (c < BB ? Pr : Pi) + nb * kb0 + kfirst + lane * 8;
         }
     }
     const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
     auto issue = [&](int s) {
         const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
 #pragma unroll
-        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
+        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 512 * s, slot + (uint32_t)(i * 1024));
     };
     v4f ar_[RB][NBLK], ai_[RB][NBLK];
 #pragma unroll
@@ -683,23 +486,24 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_ring(int N, int J, int6
     const int g0 = tile.x * (TB * 16), b0 = tile.y * (BB * 16);
     const int nst = (int)(ldp / 32);
     const uint16_t *src[PW];
+    const int64_t kb0 = (int64_t)(ldp >> 5) << 9;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
-        const int b = wave * PW + i, piece = 8 * (lane >> 4);
+        const int b = wave * PW + i;
         if (b < 2 * TB) {
-            const int g = std::min(g0 + (b % TB) * 16 + (lane & 15), J - 1);
-            src[i] = (b < TB ? Tr : Ti) + (int64_t)g * ldp + piece;
+            const int gb = std::min(g0 / 16 + b % TB, (J - 1) >> 4);
+            src[i] = (b < TB ? Tr : Ti) + gb * kb0 + lane * 8;
         } else {
             const int c = b - 2 * TB;
-            const int band = std::min(b0 + (c % BB) * 16 + (lane & 15), N - 1);
-            src[i] = (c < BB ? Wr : Wi) + (int64_t)band * ldp + piece;
+            const int nb = std::min(b0 / 16 + c % BB, (N - 1) >> 4);
+            src[i] = (c < BB ? Wr : Wi) + nb * kb0 + lane * 8;
         }
     }
     const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
     auto issue = [&](int s) {
         const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
 #pragma unroll
-        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
+        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 512 * s, slot + (uint32_t)(i * 1024));
     };
     v4f ar_[NBLK][GB], ai_[NBLK][GB];
 #pragma unroll
@@ -752,234 +556,13 @@ __global__ __launch_bounds__(WM * WN * 64) void backproj_ring(int N, int J, int6
 }
 
 // ---------------------------------------------------------------------------
-// Pipelined ring variants.  Same tiles, LDS layout and DMA ring as above, but a
-// wave reads its LDS fragments one band step ahead of the matrix work that uses
-// them (the reads of step j + 1 are in flight while the products of step j
-// run), and the barrier that publishes stage t + 1 sits in front of the last
-// band step of stage t: the wave reads stage t + 1's first fragments, and the
-// DMA of stage t + 3 goes into the slot stage t leaves, while the last products
-// of stage t are still to be issued.  Every wave has read all of stage t before
-// that barrier (its LDS counter is drained there), so the slot is free; three
-// stages are then in flight at once.
-// ---------------------------------------------------------------------------
-#define PW_SCHED_READS(n) __builtin_amdgcn_sched_group_barrier(0x100, n, 0)
-#define PW_SCHED_MFMA(n) __builtin_amdgcn_sched_group_barrier(0x008, n, 0)
-
-template <int RB, int NBLK, int WM, int WN>
-__global__ __launch_bounds__(WM * WN * 64) void proj_pipe(int M, int N, const uint16_t *__restrict__ Br,
-                                                          const uint16_t *__restrict__ Bi, int64_t ldg,
-                                                          const uint16_t *__restrict__ Pr,
-                                                          const uint16_t *__restrict__ Pi, int kchunk,
-                                                          float2 *__restrict__ partial) {
-    constexpr int NW = WM * WN, TB = WM * RB, BB = WN * NBLK;
-    constexpr int BLK = 2 * (TB + BB), PW = BLK / NW, STAGE = BLK * 1024;
-    static_assert(BLK % NW == 0, "DMA blocks must divide evenly over the waves");
-    __shared__ __attribute__((aligned(1024))) uint8_t ring[kRingStages][STAGE];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = wave % WM, wn = wave / WM;
-    const WideTile tile = wide_tile();
-    const int m0 = tile.x * (TB * 16), n0 = tile.y * (BB * 16);
-    const int kbeg = tile.z * kchunk;
-    const int nst = (int)((std::min((int64_t)kbeg + kchunk, ldg) - kbeg) / 32);
-    const uint16_t *src[PW];
-#pragma unroll
-    for (int i = 0; i < PW; ++i) {
-        const int b = wave * PW + i, piece = 8 * (lane >> 4);
-        if (b < 2 * TB) {
-            const int row = std::min(m0 + (b % TB) * 16 + (lane & 15), M - 1);
-            src[i] = (b < TB ? Br : Bi) + (int64_t)row * ldg + kbeg + piece;
-        } else {
-            const int c = b - 2 * TB;
-            const int band = std::min(n0 + (c % BB) * 16 + (lane & 15), N - 1);
-            src[i] = (c < BB ? Pr : Pi) + (int64_t)band * ldg + kbeg + piece;
-        }
-    }
-    const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
-    auto issue = [&](int s) {
-        const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
-#pragma unroll
-        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
-    };
-    auto frag = [&](int s, int blk) {
-        return *reinterpret_cast<const bf16x8 *>(&ring[s % kRingStages][0] + blk * 1024 + lane * 16);
-    };
-    v4f ar_[RB][NBLK], ai_[RB][NBLK];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int j = 0; j < NBLK; ++j) { ar_[r][j] = v4f{0, 0, 0, 0}; ai_[r][j] = v4f{0, 0, 0, 0}; }
-    issue(0);
-    if (nst > 1) issue(1);
-    if (nst > 2) issue(2);
-    if (nst > 2) ring_barrier<2 * PW>();
-    else if (nst > 1) ring_barrier<PW>();
-    else ring_barrier<0>();
-    bf16x8 tr[RB], ti[RB], cr, ci;
-#pragma unroll
-    for (int r = 0; r < RB; ++r) { tr[r] = frag(0, wm * RB + r); ti[r] = frag(0, TB + wm * RB + r); }
-    cr = frag(0, 2 * TB + wn * NBLK);
-    ci = frag(0, 2 * TB + BB + wn * NBLK);
-    for (int t = 0; t < nst; ++t) {
-        bf16x8 tn[RB], ntr[RB], nti[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) { tn[r] = neg8(ti[r]); ntr[r] = tr[r]; nti[r] = ti[r]; }
-#pragma unroll
-        for (int j = 0; j < NBLK; ++j) {
-            bf16x8 nr = cr, ni = ci;
-            if (j + 1 < NBLK) {
-                nr = frag(t, 2 * TB + wn * NBLK + j + 1);
-                ni = frag(t, 2 * TB + BB + wn * NBLK + j + 1);
-                PW_SCHED_READS(2);
-            } else if (t + 1 < nst) {
-                // stage t read in full by every wave; stage t + 1 landed
-                if (t + 2 < nst) ring_barrier<PW>();
-                else ring_barrier<0>();
-                if (t + 3 < nst) issue(t + 3);
-#pragma unroll
-                for (int r = 0; r < RB; ++r) { ntr[r] = frag(t + 1, wm * RB + r); nti[r] = frag(t + 1, TB + wm * RB + r); }
-                nr = frag(t + 1, 2 * TB + wn * NBLK);
-                ni = frag(t + 1, 2 * TB + BB + wn * NBLK);
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                // conj(beta) psi: re = br pr + bi pi, im = br pi - bi pr
-                ar_[r][j] = mfma_bf16(tr[r], cr, ar_[r][j]);
-                ar_[r][j] = mfma_bf16(ti[r], ci, ar_[r][j]);
-                ai_[r][j] = mfma_bf16(tr[r], ci, ai_[r][j]);
-                ai_[r][j] = mfma_bf16(tn[r], cr, ai_[r][j]);
-            }
-            if (j + 1 < NBLK) PW_SCHED_MFMA(4 * RB);
-            cr = nr;
-            ci = ni;
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) { tr[r] = ntr[r]; ti[r] = nti[r]; }
-    }
-    float2 *P = partial + (int64_t)tile.z * M * N;
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int j = 0; j < NBLK; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = m0 + (wm * RB + r) * 16 + 4 * (lane >> 4) + v;
-                const int col = n0 + (wn * NBLK + j) * 16 + (lane & 15);
-                if (row < M && col < N) P[(int64_t)col * M + row] = make_float2(ar_[r][j][v], ai_[r][j][v]);
-            }
-}
-
-template <int GB, int NBLK, int WM, int WN>
-__global__ __launch_bounds__(WM * WN * 64) void backproj_pipe(int N, int J, int64_t ldp,
-                                                              const uint16_t *__restrict__ Wr,
-                                                              const uint16_t *__restrict__ Wi,
-                                                              const uint16_t *__restrict__ Tr,
-                                                              const uint16_t *__restrict__ Ti,
-                                                              float2 *__restrict__ out, int64_t ldo) {
-    constexpr int NW = WM * WN, TB = WM * GB, BB = WN * NBLK;
-    constexpr int BLK = 2 * (TB + BB), PW = BLK / NW, STAGE = BLK * 1024;
-    static_assert(BLK % NW == 0, "DMA blocks must divide evenly over the waves");
-    __shared__ __attribute__((aligned(1024))) uint8_t ring[kRingStages][STAGE];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = wave % WM, wn = wave / WM;
-    const WideTile tile = wide_tile();
-    const int g0 = tile.x * (TB * 16), b0 = tile.y * (BB * 16);
-    const int nst = (int)(ldp / 32);
-    const uint16_t *src[PW];
-#pragma unroll
-    for (int i = 0; i < PW; ++i) {
-        const int b = wave * PW + i, piece = 8 * (lane >> 4);
-        if (b < 2 * TB) {
-            const int g = std::min(g0 + (b % TB) * 16 + (lane & 15), J - 1);
-            src[i] = (b < TB ? Tr : Ti) + (int64_t)g * ldp + piece;
-        } else {
-            const int c = b - 2 * TB;
-            const int band = std::min(b0 + (c % BB) * 16 + (lane & 15), N - 1);
-            src[i] = (c < BB ? Wr : Wi) + (int64_t)band * ldp + piece;
-        }
-    }
-    const uint32_t base = __builtin_amdgcn_readfirstlane(lds_addr(&ring[0][0]));
-    auto issue = [&](int s) {
-        const uint32_t slot = base + (uint32_t)((s % kRingStages) * STAGE + wave * PW * 1024);
-#pragma unroll
-        for (int i = 0; i < PW; ++i) lds_dma16(src[i] + 32 * s, slot + (uint32_t)(i * 1024));
-    };
-    auto frag = [&](int s, int blk) {
-        return *reinterpret_cast<const bf16x8 *>(&ring[s % kRingStages][0] + blk * 1024 + lane * 16);
-    };
-    v4f ar_[NBLK][GB], ai_[NBLK][GB];
-#pragma unroll
-    for (int i = 0; i < NBLK; ++i)
-#pragma unroll
-        for (int g = 0; g < GB; ++g) { ar_[i][g] = v4f{0, 0, 0, 0}; ai_[i][g] = v4f{0, 0, 0, 0}; }
-    issue(0);
-    if (nst > 1) issue(1);
-    if (nst > 2) issue(2);
-    if (nst > 2) ring_barrier<2 * PW>();
-    else if (nst > 1) ring_barrier<PW>();
-    else ring_barrier<0>();
-    bf16x8 tr[GB], ti[GB], cr, ci;
-#pragma unroll
-    for (int g = 0; g < GB; ++g) { tr[g] = frag(0, wm * GB + g); ti[g] = frag(0, TB + wm * GB + g); }
-    cr = frag(0, 2 * TB + wn * NBLK);
-    ci = frag(0, 2 * TB + BB + wn * NBLK);
-    for (int t = 0; t < nst; ++t) {
-        bf16x8 tn[GB], ntr[GB], nti[GB];
-#pragma unroll
-        for (int g = 0; g < GB; ++g) { tn[g] = neg8(ti[g]); ntr[g] = tr[g]; nti[g] = ti[g]; }
-#pragma unroll
-        for (int i = 0; i < NBLK; ++i) {
-            bf16x8 nr = cr, ni = ci;
-            if (i + 1 < NBLK) {
-                nr = frag(t, 2 * TB + wn * NBLK + i + 1);
-                ni = frag(t, 2 * TB + BB + wn * NBLK + i + 1);
-                PW_SCHED_READS(2);
-            } else if (t + 1 < nst) {
-                if (t + 2 < nst) ring_barrier<PW>();
-                else ring_barrier<0>();
-                if (t + 3 < nst) issue(t + 3);
-#pragma unroll
-                for (int g = 0; g < GB; ++g) { ntr[g] = frag(t + 1, wm * GB + g); nti[g] = frag(t + 1, TB + wm * GB + g); }
-                nr = frag(t + 1, 2 * TB + wn * NBLK);
-                ni = frag(t + 1, 2 * TB + BB + wn * NBLK);
-            }
-#pragma unroll
-            for (int g = 0; g < GB; ++g) {
-                // W beta: re = wr br - wi bi, im = wr bi + wi br
-                ar_[i][g] = mfma_bf16(cr, tr[g], ar_[i][g]);
-                ar_[i][g] = mfma_bf16(ci, tn[g], ar_[i][g]);
-                ai_[i][g] = mfma_bf16(cr, ti[g], ai_[i][g]);
-                ai_[i][g] = mfma_bf16(ci, tr[g], ai_[i][g]);
-            }
-            if (i + 1 < NBLK) PW_SCHED_MFMA(4 * GB);
-            cr = nr;
-            ci = ni;
-        }
-#pragma unroll
-        for (int g = 0; g < GB; ++g) { tr[g] = ntr[g]; ti[g] = nti[g]; }
-    }
-#pragma unroll
-    for (int i = 0; i < NBLK; ++i)
-#pragma unroll
-        for (int g = 0; g < GB; ++g)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = b0 + (wn * NBLK + i) * 16 + 4 * (lane >> 4) + v;
-                const int gc = g0 + (wm * GB + g) * 16 + (lane & 15);
-                if (b < N && gc < J) {
-                    float2 *o = out + (int64_t)b * ldo + gc;
-                    const float2 old = *o;
-                    *o = make_float2(old.x + ar_[i][g][v], old.y + ai_[i][g][v]);
-                }
-            }
-}
-
-// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static int band_blocks(int nb) { return nb <= 64 ? 4 : nb <= 128 ? 8 : 9; }
 static int band_chunk(int nb) { return nb <= MAXNB ? nb : 128; }
+
+bool bf16_panels(int max_bands) { return max_bands > MAXNB; }
+int64_t bf16_rows(int rows, int max_bands) { return bf16_panels(max_bands) ? ((int64_t)rows + 15) / 16 * 16 : rows; }
 
 constexpr int kB16ProjNW = 4;   // waves (16 projectors each) per projection workgroup
 
@@ -991,27 +574,23 @@ static int proj_splits(int M, int64_t ldg) {
 }
 
 // wide kernels: launch variants {RB (row blocks per wave), NBLK (band blocks per
-// wave), WM x WN waves, KW stage depth}; every variant spans 256 bands
-// (variants 6-9: the ring kernels, LDS filled by DMA; 7 and 8 give each of four
-// waves 64 x 128 or 32 x 256 outputs, so every LDS fragment feeds more products)
-static const int kWide[kBf16WideVariants][5] = {{2, 8, 4, 2, 32}, {2, 8, 4, 2, 64}, {2, 8, 2, 2, 32},
-                                                {2, 8, 2, 2, 64}, {4, 4, 2, 4, 32}, {1, 8, 4, 2, 64},
-                                                {2, 8, 4, 2, 32}, {4, 8, 2, 2, 32}, {2, 16, 4, 1, 32},
-                                                {4, 4, 2, 4, 32}, {2, 8, 4, 2, 32}, {4, 8, 2, 2, 32},
-                                                {2, 16, 4, 1, 32}, {4, 4, 2, 4, 32}};
+// wave), WM x WN waves}; every variant spans 256 bands.  1 and 2 give each of
+// four waves 64 x 128 or 32 x 256 outputs, so every LDS fragment feeds more
+// products; 3 reads the fewest fragments per wave of the eight-wave tiles.
+static const int kWide[kBf16WideVariants][4] = {{2, 8, 4, 2}, {4, 8, 2, 2}, {2, 16, 4, 1}, {4, 4, 2, 4}};
 constexpr int kWideBands = 256;
 static int wide_rows(int v) { return kWide[v][2] * kWide[v][0] * 16; }
 
-// split-K of the wide projection: about 512 workgroups, at least four stages per split
+// split-K of the wide projection: about 512 workgroups, at least four 32-deep stages per split
 static int wide_splits(int v, int M, int N, int64_t ldg) {
     const int tiles = ((M + wide_rows(v) - 1) / wide_rows(v)) * ((N + kWideBands - 1) / kWideBands);
     const int s = (512 + tiles - 1) / tiles;
-    const int maxs = (int)std::max<int64_t>(1, ldg / (4 * kWide[v][4]));
+    const int maxs = (int)std::max<int64_t>(1, ldg / (4 * 32));
     return std::max(1, std::min(s, maxs));
 }
 
-size_t cnt_partial_bytes(int M, int N, int K) {
-    if (N > MAXNB) {
+size_t cnt_partial_bytes(int M, int N, int K, int max_bands) {
+    if (bf16_panels(max_bands)) {
         int s = 1;
         for (int v = 0; v < kBf16WideVariants; ++v) s = std::max(s, wide_splits(v, M, N, bf16_ld(K)));
         return (size_t)s * M * N * sizeof(float2);
@@ -1019,21 +598,7 @@ size_t cnt_partial_bytes(int M, int N, int K) {
     return (size_t)proj_splits(M, bf16_ld(K)) * M * band_chunk(N) * sizeof(float2);
 }
 
-template <int RB, int NBLK, int WM, int WN, int KW>
-static void proj_wide_go(int v, int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_t ldg,
-                         const uint16_t *Pr, const uint16_t *Pi, float2 *partial, int &nsplit, hipStream_t st) {
-    const int ns = wide_splits(v, M, N, ldg);
-    int kchunk = (int)((ldg + ns - 1) / ns);
-    kchunk = (kchunk + KW - 1) / KW * KW;
-    nsplit = (int)((ldg + kchunk - 1) / kchunk);
-    constexpr int rows = WM * RB * 16;
-    dim3 grid((M + rows - 1) / rows, (N + kWideBands - 1) / kWideBands, nsplit);
-    hipLaunchKernelGGL((proj_wide<RB, NBLK, WM, WN, KW>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
-                       kchunk, partial);
-    PW_LAUNCH_CHECK();
-}
-
-template <int RB, int NBLK, int WM, int WN, bool PIPE = false>
+template <int RB, int NBLK, int WM, int WN>
 static void proj_ring_go(int v, int M, int N, const uint16_t *Br, const uint16_t *Bi, int64_t ldg,
                          const uint16_t *Pr, const uint16_t *Pi, float2 *partial, int &nsplit, hipStream_t st) {
     const int ns = wide_splits(v, M, N, ldg);
@@ -1042,41 +607,23 @@ static void proj_ring_go(int v, int M, int N, const uint16_t *Br, const uint16_t
     nsplit = (int)((ldg + kchunk - 1) / kchunk);
     constexpr int rows = WM * RB * 16;
     dim3 grid((M + rows - 1) / rows, (N + kWideBands - 1) / kWideBands, nsplit);
-    if (PIPE)
-        hipLaunchKernelGGL((proj_pipe<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
-                           kchunk, partial);
-    else
-        hipLaunchKernelGGL((proj_ring<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
-                           kchunk, partial);
+    hipLaunchKernelGGL((proj_ring<RB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, Br, Bi, ldg, Pr, Pi,
+                       kchunk, partial);
     PW_LAUNCH_CHECK();
 }
 
-template <int GB, int NBLK, int WM, int WN, bool PIPE = false>
+template <int GB, int NBLK, int WM, int WN>
 static void back_ring_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
                          const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
     constexpr int cols = WM * GB * 16;
     dim3 grid((unsigned)((J + cols - 1) / cols), (N + kWideBands - 1) / kWideBands);
-    if (PIPE)
-        hipLaunchKernelGGL((backproj_pipe<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi,
-                           Tr, Ti, out, ldo);
-    else
-        hipLaunchKernelGGL((backproj_ring<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi,
-                           Tr, Ti, out, ldo);
-    PW_LAUNCH_CHECK();
-}
-
-template <int GB, int NBLK, int WM, int WN, int KW>
-static void back_wide_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_t *Wi, const uint16_t *Tr,
-                         const uint16_t *Ti, float2 *out, int64_t ldo, hipStream_t st) {
-    constexpr int cols = WM * GB * 16;
-    dim3 grid((unsigned)((J + cols - 1) / cols), (N + kWideBands - 1) / kWideBands);
-    hipLaunchKernelGGL((backproj_wide<GB, NBLK, WM, WN, KW>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi, Tr,
+    hipLaunchKernelGGL((backproj_ring<GB, NBLK, WM, WN>), grid, dim3(64 * WM * WN), 0, st, N, J, ldp, Wr, Wi, Tr,
                        Ti, out, ldo);
     PW_LAUNCH_CHECK();
 }
 
 size_t bf16_scratch_bytes(int nproj, int npw, int max_bands) {
-    return (size_t)2 * max_bands * (bf16_ld(npw) + bf16_ld(nproj)) * sizeof(uint16_t);
+    return (size_t)2 * bf16_rows(max_bands, max_bands) * (bf16_ld(npw) + bf16_ld(nproj)) * sizeof(uint16_t);
 }
 
 template <int NBLK>
@@ -1102,14 +649,16 @@ static void back_go(int N, int J, int64_t ldp, const uint16_t *Wr, const uint16_
     PW_LAUNCH_CHECK();
 }
 
-// Scratch (bf16_scratch_bytes): Pr, Pi [max_bands][ldg] then Wr, Wi [max_bands][ldp].
+// Scratch (bf16_scratch_bytes): Pr, Pi (rows x ldg) then Wr, Wi (rows x ldp), rows =
+// bf16_rows(max_bands), each plane row-major or in 16-row panels as the tables.
 struct Bf16Scratch {
     uint16_t *Pr, *Pi, *Wr, *Wi;
     Bf16Scratch(void *p, int max_bands, int64_t ldg, int64_t ldp) {
+        const int64_t rows = bf16_rows(max_bands, max_bands);
         Pr = (uint16_t *)p;
-        Pi = Pr + (int64_t)max_bands * ldg;
-        Wr = Pi + (int64_t)max_bands * ldg;
-        Wi = Wr + (int64_t)max_bands * ldp;
+        Pi = Pr + rows * ldg;
+        Wr = Pi + rows * ldg;
+        Wi = Wr + rows * ldp;
     }
 };
 
@@ -1117,35 +666,26 @@ struct Bf16Scratch {
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
                int64_t ld, void *scratch, void *partial, hipStream_t st, int variant) {
     const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
-    const uint16_t *Br = (const uint16_t *)beta16, *Bi = Br + (int64_t)nproj * ldg;
+    const bool panel = bf16_panels(max_bands);
+    const uint16_t *Br = (const uint16_t *)beta16, *Bi = Br + bf16_rows(nproj, max_bands) * ldg;
     Bf16Scratch S(scratch, max_bands, ldg, ldp);
     hipLaunchKernelGGL(k_c64_to_planes, dim3((unsigned)((ldg + 255) / 256), nb), dim3(256), 0, st, nb, npw,
-                       (const float2 *)psi, ld, ldg, S.Pr, S.Pi);
+                       (const float2 *)psi, ld, ldg, S.Pr, S.Pi, panel ? 1 : 0);
     PW_LAUNCH_CHECK();
-    if (nb > MAXNB) {
+    if (panel) {
         // every band in one launch of 256-band tiles, split over the plane waves
         PW_CHECK(variant >= 0 && variant < kBf16WideVariants, PW_EINVAL, "BF16 tile variant %d unknown", variant);
         int nsplit = 1;
         float2 *part = (float2 *)partial;
         switch (variant) {
-            case 0: proj_wide_go<2, 8, 4, 2, 32>(0, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 1: proj_wide_go<2, 8, 4, 2, 64>(1, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 2: proj_wide_go<2, 8, 2, 2, 32>(2, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 3: proj_wide_go<2, 8, 2, 2, 64>(3, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 4: proj_wide_go<4, 4, 2, 4, 32>(4, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 5: proj_wide_go<1, 8, 4, 2, 64>(5, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 6: proj_ring_go<2, 8, 4, 2>(6, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 7: proj_ring_go<4, 8, 2, 2>(7, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 8: proj_ring_go<2, 16, 4, 1>(8, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 9: proj_ring_go<4, 4, 2, 4>(9, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 10: proj_ring_go<2, 8, 4, 2, true>(10, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 11: proj_ring_go<4, 8, 2, 2, true>(11, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            case 12: proj_ring_go<2, 16, 4, 1, true>(12, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
-            default: proj_ring_go<4, 4, 2, 4, true>(13, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 0: proj_ring_go<2, 8, 4, 2>(0, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 1: proj_ring_go<4, 8, 2, 2>(1, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            case 2: proj_ring_go<2, 16, 4, 1>(2, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
+            default: proj_ring_go<4, 4, 2, 4>(3, nproj, nb, Br, Bi, ldg, S.Pr, S.Pi, part, nsplit, st); break;
         }
         const int64_t tot = (int64_t)nb * ldp;
         hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, nb, nsplit,
-                           (const float2 *)partial, d, ldp, S.Wr, S.Wi);
+                           (const float2 *)partial, d, ldp, S.Wr, S.Wi, 1);
         PW_LAUNCH_CHECK();
         return;
     }
@@ -1161,7 +701,7 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
         }
         const int64_t tot = (int64_t)n * ldp;
         hipLaunchKernelGGL(proj16_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nproj, n, nsplit,
-                           (const float2 *)part, d, ldp, S.Wr + (int64_t)b0 * ldp, S.Wi + (int64_t)b0 * ldp);
+                           (const float2 *)part, d, ldp, S.Wr + (int64_t)b0 * ldp, S.Wi + (int64_t)b0 * ldp, 0);
         PW_LAUNCH_CHECK();
     }
 }
@@ -1172,25 +712,15 @@ void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT1
     const int64_t ldg = bf16_ld(npw), ldp = bf16_ld(nproj);
     const uint16_t *Tr = (const uint16_t *)betaT16, *Ti = Tr + ldg * ldp;
     Bf16Scratch S(const_cast<void *>(scratch), max_bands, ldg, ldp);
-    if (nb > MAXNB) {
+    if (bf16_panels(max_bands)) {
         PW_CHECK(variant >= 0 && variant < kBf16WideVariants, PW_EINVAL, "BF16 tile variant %d unknown", variant);
         const uint16_t *Wr = S.Wr, *Wi = S.Wi;
         float2 *o = (float2 *)out;
         switch (variant) {
-            case 0: back_wide_go<2, 8, 4, 2, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 1: back_wide_go<2, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 2: back_wide_go<2, 8, 2, 2, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 3: back_wide_go<2, 8, 2, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 4: back_wide_go<4, 4, 2, 4, 32>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 5: back_wide_go<1, 8, 4, 2, 64>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 6: back_ring_go<2, 8, 4, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 7: back_ring_go<4, 8, 2, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 8: back_ring_go<2, 16, 4, 1>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 9: back_ring_go<4, 4, 2, 4>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 10: back_ring_go<2, 8, 4, 2, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 11: back_ring_go<4, 8, 2, 2, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            case 12: back_ring_go<2, 16, 4, 1, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
-            default: back_ring_go<4, 4, 2, 4, true>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 0: back_ring_go<2, 8, 4, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 1: back_ring_go<4, 8, 2, 2>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            case 2: back_ring_go<2, 16, 4, 1>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
+            default: back_ring_go<4, 4, 2, 4>(nb, npw, ldp, Wr, Wi, Tr, Ti, o, ldo, st); break;
         }
         return;
     }

@@ -110,14 +110,25 @@ void hpsi_batch_run(HpsiBatch *, hipStream_t);
 void hpsi_batch_destroy(HpsiBatch *);
 
 // gemm_bf16.hip (complex64 blocks, BF16 projector table, FP32 accumulation)
-size_t cnt_partial_bytes(int M, int N, int K);
+// BF16 planes of contexts of more than 144 bands (bf16_panels) are stored in
+// 16-row panels: rows 16 q .. 16 q + 15 of 32 consecutive k as one 1 KB fragment,
+// element (r, k) at lane r % 16 + 16 ((k % 32) / 8), position k % 8 (the matrix
+// cores' operand order), the fragments of a panel in k order; ld (the padded row
+// length, a multiple of 64) columns per row.  Rows are padded to a multiple of 16
+// (bf16_rows), and a panel of rows r0 .. starts at r0 ld for r0 a multiple of 16.
+__host__ __device__ inline int64_t bf16_panel_index(int64_t r, int64_t k, int64_t ld) {
+    return ((((r >> 4) * (ld >> 5) + (k >> 5)) << 6) + (r & 15) + (((k & 31) >> 3) << 4)) * 8 + (k & 7);
+}
+bool bf16_panels(int max_bands);
+int64_t bf16_rows(int rows, int max_bands);
+size_t cnt_partial_bytes(int M, int N, int K, int max_bands);
 int64_t bf16_ld(int n);
 size_t bf16_scratch_bytes(int nproj, int npw, int max_bands);
-void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st);
+void beta_to_bf16_t(int nproj, int npw, const void *beta64, void *tr, void *ti, hipStream_t st, bool panel);
 void beta_to_bf16_t_rows(int nproj, int p0, int rows, int npw, const void *beta64, void *tr, void *ti,
-                         hipStream_t st);
+                         hipStream_t st, bool panel);
 // variant: launch variant of the kernels for more than 144 bands (autotuner pass 6)
-constexpr int kBf16WideVariants = 14;
+constexpr int kBf16WideVariants = 4;
 void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, const float *d, const void *psi,
                int64_t ld, void *scratch, void *partial, hipStream_t st, int variant = 0);
 void backproj_bf16(int nproj, int nb, int npw, int max_bands, const void *betaT16, const void *scratch, void *out,

@@ -170,7 +170,7 @@ struct FcgRun {
     }
     // S (nb x nb) = A^H B over the plane waves
     void gram(const void *A, const void *B, double alpha, double2 *S, bool trans) {
-        ProfScope p(ctx, 6, st);
+        ProfScope p(ctx, A == B ? 8 : 6, st);
         // A == B: a Gram matrix, Hermitian, so half its tiles
         zgemm_nt(nb, nb, npw, true, A, L, B, L, alpha, nullptr, 0.0, S, nb, trans, ctx->d_partial.p, st, false,
                  A == B);

@@ -74,20 +74,23 @@ __device__ inline uint16_t to_bf16(float f) {
 }
 
 __global__ void k_to_bf16_planes(int rows, int npw, int64_t ldp, const double2 *__restrict__ src,
-                                 uint16_t *__restrict__ re, uint16_t *__restrict__ im) {
+                                 uint16_t *__restrict__ re, uint16_t *__restrict__ im, int panel) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (r >= rows) return;
     if (g < ldp) {
         const double2 v = g < npw ? src[(int64_t)r * npw + g] : make_double2(0.0, 0.0);
-        re[(int64_t)r * ldp + g] = to_bf16((float)v.x);
-        im[(int64_t)r * ldp + g] = to_bf16((float)v.y);
+        const int64_t o = panel ? bf16_panel_index(r, g, ldp) : (int64_t)r * ldp + g;
+        re[o] = to_bf16((float)v.x);
+        im[o] = to_bf16((float)v.y);
     }
 }
 
-void beta_to_bf16(int rows, int npw, int64_t ldp, const void *src, void *re, void *im, hipStream_t st) {
+// rows x npw complex128 -> BF16 planes of ldp columns, row-major or in 16-row panels
+// (re and im then start on a panel boundary)
+void beta_to_bf16(int rows, int npw, int64_t ldp, const void *src, void *re, void *im, hipStream_t st, bool panel) {
     hipLaunchKernelGGL(k_to_bf16_planes, dim3((unsigned)((ldp + 255) / 256), rows), dim3(256), 0, st, rows, npw, ldp,
-                       (const double2 *)src, (uint16_t *)re, (uint16_t *)im);
+                       (const double2 *)src, (uint16_t *)re, (uint16_t *)im, panel ? 1 : 0);
     PW_LAUNCH_CHECK();
 }
 
