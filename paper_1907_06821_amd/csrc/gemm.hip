@@ -139,6 +139,28 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
                                            blockIdx.z);
 }
 
+// A Gram matrix A^H A on a one-dimensional grid over the live tiles (on and below the
+// diagonal) of every split, live tile fastest.  Workgroups reach the eight XCDs round
+// robin in dispatch order, so each XCD gets an equal share of the live tiles; on the
+// (tile column, tile row, split) grid XCD x took tile column x, whose live tiles grow
+// with x (the last XCD eight times the first's at 1024 bands), and the whole launch
+// waited for it.  Each tile and split is the same computation as on that grid.
+template <int WM, int WN, int BM, int BN>
+__global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_herm(int M, int N, int K, const double2 *__restrict__ A,
+                                                              int64_t lda, int kchunk, double2 *__restrict__ partial,
+                                                              int live) {
+    constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
+    const int ntl = (N + TN - 1) / TN;
+    const int s = blockIdx.x / live;
+    int t = blockIdx.x % live, i = 0;
+    for (;; ++i) {
+        const int c = min(ntl, (i * TM + TM - 1) / TN + 1);   // live tiles of tile row i
+        if (t < c) break;
+        t -= c;
+    }
+    nt_partial_tile<WM, WN, BM, BN, true>(M, N, K, A, lda, A, lda, kchunk, partial, 1, i, t, s);
+}
+
 // Several independent problems in one launch (one job each, blockIdx.z = job x
 // maxsplit + split; jobs whose mask entry is 0 and tiles beyond a job's own
 // extent return at once).  Every tile runs the body of the single-problem kernel
@@ -346,10 +368,10 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_jobs(const NnJob *__res
 // ---------------------------------------------------------------------------
 // NT tiles: TN = 16 (N <= 16), 32 (N <= 32), 64 (N <= 64), 128 (N <= 128) or 144
 // (N <= 144, for 128 wanted bands plus buffer bands), else 128; TM = 128 rows of A
-// when A is tall (the projector table: B is then re-read half as often) or of a
-// square band-by-band product of up to 128 (Gram matrices: one tile); 48 for
-// square products of 129..144 (three waves of 3 x 3 blocks, 48 x 144 tiles), else
-// 64.  The narrow tiles serve a few right-hand sides against the whole table,
+// when A has at least 256 rows (the projector table or a chunk of its rows: B is
+// then re-read half as often) or for a square band-by-band product of up to 128
+// (Gram matrices: one tile); 48 for square products of 129..144 (three waves of
+// 3 x 3 blocks, 48 x 144 tiles), else 64.  The narrow tiles serve a few right-hand sides against the whole table,
 // where a 64-wide tile would spend most of its matrix-core work on padding.
 static int nt_tn(int N) {
     return N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128))));
@@ -357,11 +379,21 @@ static int nt_tn(int N) {
 static int nt_tm(int M, int N) {
     if (N <= 32) return M >= 512 ? 128 : 64;
     if (M == N && M > 128 && M <= 144) return 48;
-    return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
+    return ((M >= 256 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
+}
+
+// tiles of a Gram matrix's tile grid that reach the diagonal
+static int nt_live_tiles(int M, int N) {
+    const int tn = nt_tn(N), tm = nt_tm(M, N);
+    const int mt = (M + tm - 1) / tm, ntl = (N + tn - 1) / tn;
+    int live = 0;
+    for (int i = 0; i < mt; ++i) live += std::min(ntl, (i * tm + tm - 1) / tn + 1);
+    return live;
 }
 
 // K-splits: enough workgroups to cover the chip (~512) while keeping at least
-// four LDS stages per chunk and the partial sums under 64 MiB.
+// four LDS stages per chunk and the partial sums under 64 MiB (128 MiB for a Gram
+// matrix).
 int nt_splits(int M, int N, int K, bool herm) {
     const int tn = nt_tn(N), tm = nt_tm(M, N);
     const int mt = (M + tm - 1) / tm, ntl = (N + tn - 1) / tn;
@@ -369,31 +401,34 @@ int nt_splits(int M, int N, int K, bool herm) {
     int s = (512 + tiles - 1) / tiles;
     if (herm) {
         // a Gram matrix computes only the tiles that reach the diagonal: as many
-        // splits as fill the 256 compute units once (more would start a second,
-        // mostly idle round of workgroups)
-        int live = 0;
-        for (int i = 0; i < mt; ++i)
-            for (int j = 0; j < ntl; ++j) live += (j * tn <= i * tm + tm - 1) ? 1 : 0;
+        // splits as fill the 256 compute units once (a second workgroup on a unit
+        // halves the speed of both)
+        const int live = nt_live_tiles(M, N);
         if (live * 2 <= 256) s = std::min(s, std::max(1, 256 / live));
         else s = std::min(s, std::max(1, 512 / live));
     }
     const int maxs = (K + 4 * KT - 1) / (4 * KT);
     if (s > maxs) s = maxs;
-    const int64_t cap = (int64_t)(64 << 20) / ((int64_t)M * N * (int64_t)sizeof(double2));
+    const int64_t cap = ((int64_t)(herm ? 128 : 64) << 20) / ((int64_t)M * N * (int64_t)sizeof(double2));
     if (s > cap) s = (int)cap;
     if (s < 1) s = 1;
     return s;
 }
 
 size_t nt_partial_bytes(int M, int N, int K) {
-    return (size_t)nt_splits(M, N, K) * M * N * sizeof(double2);
+    const int s = std::max(nt_splits(M, N, K, false), M == N ? nt_splits(M, N, K, true) : 1);
+    return (size_t)s * M * N * sizeof(double2);
 }
 
 template <int WM, int WN, int BM, int BN>
 static void nt_go(dim3 grid, bool conja, bool proj, hipStream_t st, int M, int N, int K, const void *A, int64_t lda,
                   const void *B, int64_t ldb, int kchunk, void *partial, int herm) {
     const dim3 blk(WM * WN * 64);
-    if (conja && proj)
+    if (herm) {
+        const int live = nt_live_tiles(M, N);
+        hipLaunchKernelGGL((zgemm_nt_herm<WM, WN, BM, BN>), dim3((unsigned)(live * grid.z)), blk, 0, st, M, N, K,
+                           (const double2 *)A, lda, kchunk, (double2 *)partial, live);
+    } else if (conja && proj)
         hipLaunchKernelGGL((zgemm_nt_partial<WM, WN, BM, BN, true, 1>), grid, blk, 0, st, M, N, K, (const double2 *)A,
                            lda, (const double2 *)B, ldb, kchunk, (double2 *)partial, herm);
     else if (conja)
