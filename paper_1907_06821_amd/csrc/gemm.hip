@@ -26,12 +26,31 @@ __device__ inline v4d mfma16(double a, double b, v4d c) {
 
 constexpr int KT = 16;       // k-depth of one LDS stage (complex elements)
 
-// acc_r += Re(a b), acc_i += Im(a b)
-__device__ inline void cmfma(const double2 a, const double2 b, v4d &ar, v4d &ai) {
-    ar = mfma16(a.x, b.x, ar);
-    ar = mfma16(-a.y, b.y, ar);
-    ai = mfma16(a.x, b.y, ai);
-    ai = mfma16(a.y, b.x, ai);
+// Complex products of a wave's 16 x 16 blocks, two forms.  Four real products:
+// c1 += Re(a b), c2 += Im(a b).  Three (Gauss), for waves of at most four blocks in
+// workgroups of at most eight waves, whose third accumulator still fits the
+// register file without spilling: c1 += ar br, c2 += ai bi,
+// c3 += (ar + ai)(br + bi), with sa = ar + ai and sb = br + bi formed once per
+// operand fragment; then Re(sum a b) = c1 - c2 and Im(sum a b) = c3 - c1 - c2.
+// The three-product form does three quarters of the matrix-core work; its error
+// stays within a few units of roundoff of (|ar| + |ai|)(|br| + |bi|) summed over k.
+template <bool G3>
+__device__ inline void cmfma_blk(const double2 a, const double2 b, double sa, double sb, v4d &c1, v4d &c2,
+                                 v4d &c3) {
+    if constexpr (G3) {
+        c1 = mfma16(a.x, b.x, c1);
+        c2 = mfma16(a.y, b.y, c2);
+        c3 = mfma16(sa, sb, c3);
+    } else {
+        c1 = mfma16(a.x, b.x, c1);
+        c1 = mfma16(-a.y, b.y, c1);
+        c2 = mfma16(a.x, b.y, c2);
+        c2 = mfma16(a.y, b.x, c2);
+    }
+}
+template <bool G3> __device__ inline double2 cmfma_result(const v4d &c1, const v4d &c2, const v4d &c3, int v) {
+    if constexpr (G3) return make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
+    else return make_double2(c1[v], c2[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -40,7 +59,7 @@ __device__ inline void cmfma(const double2 a, const double2 b, v4d &ar, v4d &ai)
 // ---------------------------------------------------------------------------
 // TAG only separates the projector launches from the block-algebra ones in profiles
 // one tile (bm, bn) of split s; the batched kernel below runs the same body
-template <int WM, int WN, int BM, int BN, bool CONJA>
+template <int WM, int WN, int BM, int BN, bool CONJA, bool G3OK>
 __device__ __forceinline__ void nt_partial_tile(int M, int N, int K, const double2 *__restrict__ A, int64_t lda,
                                                 const double2 *__restrict__ B, int64_t ldb, int kchunk,
                                                 double2 *__restrict__ partial, int herm, int bm, int bn, int s) {
@@ -57,11 +76,19 @@ __device__ __forceinline__ void nt_partial_tile(int M, int N, int K, const doubl
     const int kend = min(K, kbeg + kchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    v4d accr[BM][BN], acci[BM][BN];
+    // Gram matrices A^H A keep the four-product form: identical columns then give
+    // identical entries (an exactly singular matrix for dependent bands, which the
+    // Cholesky factorisation must see as such)
+    constexpr bool G3 = G3OK && BM * BN <= 4 && NT <= 512;
+    constexpr int NC3 = G3 ? BN : 1;
+    v4d c1[BM][BN], c2[BM][BN], c3[BM][NC3];
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < BN; ++j) { accr[i][j] = v4d{0, 0, 0, 0}; acci[i][j] = v4d{0, 0, 0, 0}; }
+        for (int j = 0; j < BN; ++j) {
+            c1[i][j] = c2[i][j] = v4d{0, 0, 0, 0};
+            if (j < NC3) c3[i][j] = v4d{0, 0, 0, 0};
+        }
     double2 ra[LA], rb[LB];
     auto fetch = [&](int k0) {
 #pragma unroll
@@ -99,17 +126,23 @@ __device__ __forceinline__ void nt_partial_tile(int M, int N, int K, const doubl
         for (int kq = 0; kq < KT / 4; ++kq) {
             const int k = kq * 4 + (lane >> 4);
             double2 a[BM], b[BN];
+            double sa[BM], sb[BN];
 #pragma unroll
             for (int i = 0; i < BM; ++i) {
                 a[i] = As[(wm * BM + i) * 16 + (lane & 15)][k];
                 if (CONJA) a[i].y = -a[i].y;
+                sa[i] = a[i].x + a[i].y;
             }
 #pragma unroll
-            for (int j = 0; j < BN; ++j) b[j] = Bs[(wn * BN + j) * 16 + (lane & 15)][k];
+            for (int j = 0; j < BN; ++j) {
+                b[j] = Bs[(wn * BN + j) * 16 + (lane & 15)][k];
+                sb[j] = b[j].x + b[j].y;
+            }
 #pragma unroll
             for (int i = 0; i < BM; ++i)
 #pragma unroll
-                for (int j = 0; j < BN; ++j) cmfma(a[i], b[j], accr[i][j], acci[i][j]);
+                for (int j = 0; j < BN; ++j)
+                    cmfma_blk<G3>(a[i], b[j], sa[i], sb[j], c1[i][j], c2[i][j], c3[i][G3 ? j : 0]);
         }
         __syncthreads();
         if (more) {
@@ -126,7 +159,8 @@ __device__ __forceinline__ void nt_partial_tile(int M, int N, int K, const doubl
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + (wm * BM + i) * 16 + (lane >> 4) + 4 * v;
                 const int col = n0 + (wn * BN + j) * 16 + (lane & 15);
-                if (row < M && col < N) P[(int64_t)row * N + col] = make_double2(accr[i][j][v], acci[i][j][v]);
+                if (row < M && col < N)
+                    P[(int64_t)row * N + col] = cmfma_result<G3>(c1[i][j], c2[i][j], c3[i][G3 ? j : 0], v);
             }
 }
 
@@ -135,7 +169,7 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial(int M, int N, i
                                                                  int64_t lda, const double2 *__restrict__ B,
                                                                  int64_t ldb, int kchunk,
                                                                  double2 *__restrict__ partial, int herm) {
-    nt_partial_tile<WM, WN, BM, BN, CONJA>(M, N, K, A, lda, B, ldb, kchunk, partial, herm, blockIdx.x, blockIdx.y,
+    nt_partial_tile<WM, WN, BM, BN, CONJA, true>(M, N, K, A, lda, B, ldb, kchunk, partial, herm, blockIdx.x, blockIdx.y,
                                            blockIdx.z);
 }
 
@@ -158,14 +192,14 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_herm(int M, int N, int 
         if (t < c) break;
         t -= c;
     }
-    nt_partial_tile<WM, WN, BM, BN, true>(M, N, K, A, lda, A, lda, kchunk, partial, 1, i, t, s);
+    nt_partial_tile<WM, WN, BM, BN, true, false>(M, N, K, A, lda, A, lda, kchunk, partial, 1, i, t, s);
 }
 
 // Several independent problems in one launch (one job each, blockIdx.z = job x
 // maxsplit + split; jobs whose mask entry is 0 and tiles beyond a job's own
 // extent return at once).  Every tile runs the body of the single-problem kernel
 // with that job's arguments, so each job's result is bit for bit the same.
-template <int WM, int WN, int BM, int BN, bool CONJA, int TAG>
+template <int WM, int WN, int BM, int BN, bool CONJA, int TAG, bool G3OK>
 __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial_jobs(const NtJob *__restrict__ jobs,
                                                                       const int *__restrict__ mask, int maxsplit) {
     constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
@@ -173,7 +207,7 @@ __global__ __launch_bounds__(WM * WN * 64) void zgemm_nt_partial_jobs(const NtJo
     if (!mask[q]) return;
     const NtJob &j = jobs[q];
     if (s >= j.nsplit || (int)blockIdx.x * TM >= j.M || (int)blockIdx.y * TN >= j.N) return;
-    nt_partial_tile<WM, WN, BM, BN, CONJA>(j.M, j.N, j.K, j.A, j.lda, j.B, j.ldb, j.kchunk, j.partial, j.herm,
+    nt_partial_tile<WM, WN, BM, BN, CONJA, G3OK>(j.M, j.N, j.K, j.A, j.lda, j.B, j.ldb, j.kchunk, j.partial, j.herm,
                                            blockIdx.x, blockIdx.y, s);
 }
 
@@ -265,11 +299,16 @@ __device__ __forceinline__ void nn_tile(int M, int J, int K, const double2 *__re
     const int j0 = bj * TJ, m0 = bm * TM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wj = wave / WM;
-    v4d accr[BM][BJ], acci[BM][BJ];
+    constexpr bool G3 = BM * BJ <= 4 && NT <= 512;
+    constexpr int NC3 = G3 ? BJ : 1;
+    v4d c1[BM][BJ], c2[BM][BJ], c3[BM][NC3];
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j) { accr[i][j] = v4d{0, 0, 0, 0}; acci[i][j] = v4d{0, 0, 0, 0}; }
+        for (int j = 0; j < BJ; ++j) {
+            c1[i][j] = c2[i][j] = v4d{0, 0, 0, 0};
+            if (j < NC3) c3[i][j] = v4d{0, 0, 0, 0};
+        }
     double2 rw[LW], rx[LX];
     auto fetch = [&](int k0) {
 #pragma unroll
@@ -310,14 +349,22 @@ __device__ __forceinline__ void nn_tile(int M, int J, int K, const double2 *__re
         for (int kq = 0; kq < KD / 4; ++kq) {
             const int k = kq * 4 + (lane >> 4);
             double2 a[BM], b[BJ];
+            double sa[BM], sb[BJ];
 #pragma unroll
-            for (int i = 0; i < BM; ++i) a[i] = Ws[(wm * BM + i) * 16 + (lane & 15)][k];
+            for (int i = 0; i < BM; ++i) {
+                a[i] = Ws[(wm * BM + i) * 16 + (lane & 15)][k];
+                sa[i] = a[i].x + a[i].y;
+            }
 #pragma unroll
-            for (int j = 0; j < BJ; ++j) b[j] = Xs[k][(wj * BJ + j) * 16 + (lane & 15)];
+            for (int j = 0; j < BJ; ++j) {
+                b[j] = Xs[k][(wj * BJ + j) * 16 + (lane & 15)];
+                sb[j] = b[j].x + b[j].y;
+            }
 #pragma unroll
             for (int i = 0; i < BM; ++i)
 #pragma unroll
-                for (int j = 0; j < BJ; ++j) cmfma(a[i], b[j], accr[i][j], acci[i][j]);
+                for (int j = 0; j < BJ; ++j)
+                    cmfma_blk<G3>(a[i], b[j], sa[i], sb[j], c1[i][j], c2[i][j], c3[i][G3 ? j : 0]);
         }
         __syncthreads();
         if (more) {
@@ -335,7 +382,8 @@ __device__ __forceinline__ void nn_tile(int M, int J, int K, const double2 *__re
                 const int col = j0 + (wj * BJ + j) * 16 + (lane & 15);
                 if (row < M && col < J) {
                     double2 *o = Out + (int64_t)row * ldo + col;
-                    double re = alpha * accr[i][j][v], im = alpha * acci[i][j][v];
+                    const double2 r = cmfma_result<G3>(c1[i][j], c2[i][j], c3[i][G3 ? j : 0], v);
+                    double re = alpha * r.x, im = alpha * r.y;
                     if (beta != 0.0) { re += beta * o->x; im += beta * o->y; }
                     *o = make_double2(re, im);
                 }
@@ -499,15 +547,20 @@ NtJob nt_job(int M, int N, int K, bool conja, const void *A, int64_t lda, const 
 }
 
 template <int WM, int WN, int BM, int BN>
-static void nt_jobs_go(dim3 grid, bool conja, bool proj, hipStream_t st, const NtJob *jobs, const int *mask,
-                       int maxsplit) {
+static void nt_jobs_go(dim3 grid, bool conja, bool proj, bool herm, hipStream_t st, const NtJob *jobs,
+                       const int *mask, int maxsplit) {
     const dim3 blk(WM * WN * 64);
-    if (conja && proj)
-        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 1>), grid, blk, 0, st, jobs, mask, maxsplit);
+    if (herm)
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 0, false>), grid, blk, 0, st, jobs, mask,
+                           maxsplit);
+    else if (conja && proj)
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 1, true>), grid, blk, 0, st, jobs, mask,
+                           maxsplit);
     else if (conja)
-        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 0>), grid, blk, 0, st, jobs, mask, maxsplit);
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, true, 0, true>), grid, blk, 0, st, jobs, mask,
+                           maxsplit);
     else
-        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, false, 0>), grid, blk, 0, st, jobs, mask,
+        hipLaunchKernelGGL((zgemm_nt_partial_jobs<WM, WN, BM, BN, false, 0, true>), grid, blk, 0, st, jobs, mask,
                            maxsplit);
 }
 
@@ -529,17 +582,24 @@ void zgemm_nt_jobs(const std::vector<NtJob> &h, const NtJob *d_jobs, const int *
         ntl = std::max(ntl, (j.N + tn - 1) / tn);
         maxel = std::max(maxel, (int64_t)j.M * j.N);
     }
+    // the jobs of one call are all Gram matrices or none (the same product in every problem)
+    bool herm = false;
+    for (const NtJob &j : h)
+        if (j.M > 0) {
+            PW_CHECK(j.herm == first->herm, PW_EINVAL, "batched NT jobs mix Gram and other products");
+            herm = j.herm != 0;
+        }
     dim3 grid(mt, ntl, (unsigned)(h.size() * maxsplit));
-    if (tn == 16 && tm == 128) nt_jobs_go<4, 1, 2, 1>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tn == 16) nt_jobs_go<4, 1, 1, 1>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tn == 32 && tm == 128) nt_jobs_go<4, 1, 2, 2>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tn == 32) nt_jobs_go<4, 1, 1, 2>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tn == 64) nt_jobs_go<2, 2, 2, 2>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tm == 48) nt_jobs_go<1, 3, 3, 3>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tm == 128 && tn == 128) nt_jobs_go<4, 2, 2, 4>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tm == 128) nt_jobs_go<4, 3, 2, 3>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else if (tn == 128) nt_jobs_go<2, 2, 2, 4>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
-    else nt_jobs_go<2, 3, 2, 3>(grid, conja, proj, st, d_jobs, d_mask, maxsplit);
+    if (tn == 16 && tm == 128) nt_jobs_go<4, 1, 2, 1>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 16) nt_jobs_go<4, 1, 1, 1>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 32 && tm == 128) nt_jobs_go<4, 1, 2, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 32) nt_jobs_go<4, 1, 1, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 64) nt_jobs_go<2, 2, 2, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tm == 48) nt_jobs_go<1, 3, 3, 3>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tm == 128 && tn == 128) nt_jobs_go<4, 2, 2, 4>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tm == 128) nt_jobs_go<4, 3, 2, 3>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 128) nt_jobs_go<2, 2, 2, 4>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else nt_jobs_go<2, 3, 2, 3>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
     PW_LAUNCH_CHECK();
     const dim3 rgrid((unsigned)((maxel + kRedElems - 1) / kRedElems), (unsigned)h.size());
     const dim3 rblk(kRedElems * kRedGroups);

@@ -66,7 +66,7 @@ def test_fused_batch_with_finishing_problems(torch_cuda, fault):
         e, r, st = pw.folded_cg_solve(c, p.e_ref, psi, raise_on_noconv=False, hist_len=128, **kw)
         ind.append((e, r, st, psi))
     iters = sorted({st["iters"] for _, _, st, _ in ind})
-    assert len(iters) >= 3, iters                     # the problems finish at different checks
+    assert len(iters) >= 2, iters                     # some problems finish at a check, others go on
     psis = [s.clone() for s in starts]
     eigs, ress, sts, status = pw.batch_solve(ctxs, [p.e_ref for p in probs], psis, hist_len=128,
                                              raise_on_noconv=False, **kw)
