@@ -415,24 +415,28 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_jobs(const NnJob *__res
 // host wrappers
 // ---------------------------------------------------------------------------
 // NT tiles: TN = 16 (N <= 16), 32 (N <= 32), 64 (N <= 64), 128 (N <= 128) or 144
-// (N <= 144, for 128 wanted bands plus buffer bands), else 128; TM = 128 rows of A
-// when A has at least 256 rows (the projector table or a chunk of its rows: B is
-// then re-read half as often) or for a square band-by-band product of up to 128
-// (Gram matrices: one tile); 48 for square products of 129..144 (three waves of
-// 3 x 3 blocks, 48 x 144 tiles), else 64.  The narrow tiles serve a few right-hand sides against the whole table,
+// (N <= 144, for 128 wanted bands plus buffer bands), else 128 (64 for a product of
+// two different band blocks: 128 x 64 tiles take the three-product form); TM = 128
+// rows of A when A is tall (the projector table: B is then re-read half as often)
+// or of a square band-by-band product of up to 128 (Gram matrices: one tile); 48
+// for square products of 129..144 (three waves of 3 x 3 blocks, 48 x 144 tiles),
+// else 64.  The narrow tiles serve a few right-hand sides against the whole table,
 // where a 64-wide tile would spend most of its matrix-core work on padding.
-static int nt_tn(int N) {
+static int nt_tn(int M, int N, bool herm) {
+    // a band-by-band product of two different blocks beyond 144 bands: 128 x 64 tiles, whose
+    // four blocks per wave take the three-product form
+    if (!herm && M == N && N > 144) return 64;
     return N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128))));
 }
 static int nt_tm(int M, int N) {
     if (N <= 32) return M >= 512 ? 128 : 64;
     if (M == N && M > 128 && M <= 144) return 48;
-    return ((M >= 256 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
+    return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
 }
 
 // tiles of a Gram matrix's tile grid that reach the diagonal
 static int nt_live_tiles(int M, int N) {
-    const int tn = nt_tn(N), tm = nt_tm(M, N);
+    const int tn = nt_tn(M, N, true), tm = nt_tm(M, N);
     const int mt = (M + tm - 1) / tm, ntl = (N + tn - 1) / tn;
     int live = 0;
     for (int i = 0; i < mt; ++i) live += std::min(ntl, (i * tm + tm - 1) / tn + 1);
@@ -443,7 +447,7 @@ static int nt_live_tiles(int M, int N) {
 // four LDS stages per chunk and the partial sums under 64 MiB (128 MiB for a Gram
 // matrix).
 int nt_splits(int M, int N, int K, bool herm) {
-    const int tn = nt_tn(N), tm = nt_tm(M, N);
+    const int tn = nt_tn(M, N, herm), tm = nt_tm(M, N);
     const int mt = (M + tm - 1) / tm, ntl = (N + tn - 1) / tn;
     const int tiles = mt * ntl;
     int s = (512 + tiles - 1) / tiles;
@@ -498,13 +502,14 @@ void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const
     int kchunk = (K + ns - 1) / ns;
     kchunk = ((kchunk + KT - 1) / KT) * KT;
     const int nsplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
-    const int tn = nt_tn(N), tm = nt_tm(M, N);
+    const int tn = nt_tn(M, N, herm != 0), tm = nt_tm(M, N);
     dim3 grid((M + tm - 1) / tm, (N + tn - 1) / tn, nsplit);
     if (K <= 0) fill_zero(partial, (size_t)M * N * sizeof(double2), st);
     else if (tn == 16 && tm == 128) nt_go<4, 1, 2, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     else if (tn == 16) nt_go<4, 1, 1, 1>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     else if (tn == 32 && tm == 128) nt_go<4, 1, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     else if (tn == 32) nt_go<4, 1, 1, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
+    else if (tn == 64 && tm == 128) nt_go<4, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     else if (tn == 64) nt_go<2, 2, 2, 2>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     else if (tm == 48) nt_go<1, 3, 3, 3>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
     else if (tm == 128 && tn == 128) nt_go<4, 2, 2, 4>(grid, conja, proj, st, M, N, K, A, lda, B, ldb, kchunk, partial, herm);
@@ -571,12 +576,13 @@ void zgemm_nt_jobs(const std::vector<NtJob> &h, const NtJob *d_jobs, const int *
     for (const NtJob &j : h)
         if (j.M > 0 && !first) first = &j;
     if (!first) return;
-    const int tn = nt_tn(first->N), tm = nt_tm(first->M, first->N);
+    const int tn = nt_tn(first->M, first->N, first->herm != 0), tm = nt_tm(first->M, first->N);
     int maxsplit = 1, mt = 1, ntl = 1;
     int64_t maxel = 1;
     for (const NtJob &j : h) {
         if (j.M <= 0) continue;
-        PW_CHECK(nt_tn(j.N) == tn && nt_tm(j.M, j.N) == tm, PW_EINVAL, "batched NT jobs need one tile shape");
+        PW_CHECK(nt_tn(j.M, j.N, j.herm != 0) == tn && nt_tm(j.M, j.N) == tm, PW_EINVAL,
+                 "batched NT jobs need one tile shape");
         maxsplit = std::max(maxsplit, j.nsplit);
         mt = std::max(mt, (j.M + tm - 1) / tm);
         ntl = std::max(ntl, (j.N + tn - 1) / tn);
@@ -594,6 +600,7 @@ void zgemm_nt_jobs(const std::vector<NtJob> &h, const NtJob *d_jobs, const int *
     else if (tn == 16) nt_jobs_go<4, 1, 1, 1>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
     else if (tn == 32 && tm == 128) nt_jobs_go<4, 1, 2, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
     else if (tn == 32) nt_jobs_go<4, 1, 1, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
+    else if (tn == 64 && tm == 128) nt_jobs_go<4, 2, 2, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
     else if (tn == 64) nt_jobs_go<2, 2, 2, 2>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
     else if (tm == 48) nt_jobs_go<1, 3, 3, 3>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
     else if (tm == 128 && tn == 128) nt_jobs_go<4, 2, 2, 4>(grid, conja, proj, herm, st, d_jobs, d_mask, maxsplit);
