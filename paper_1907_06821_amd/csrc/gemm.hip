@@ -415,17 +415,18 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_jobs(const NnJob *__res
 // host wrappers
 // ---------------------------------------------------------------------------
 // NT tiles: TN = 16 (N <= 16), 32 (N <= 32), 64 (N <= 64), 128 (N <= 128) or 144
-// (N <= 144, for 128 wanted bands plus buffer bands), else 128 (64 for a product of
-// two different band blocks: 128 x 64 tiles take the three-product form); TM = 128
+// (N <= 144, for 128 wanted bands plus buffer bands), else 128 for a Gram matrix and
+// 64 for other products (their four blocks per wave take the three-product form); TM = 128
 // rows of A when A is tall (the projector table: B is then re-read half as often)
 // or of a square band-by-band product of up to 128 (Gram matrices: one tile); 48
 // for square products of 129..144 (three waves of 3 x 3 blocks, 48 x 144 tiles),
 // else 64.  The narrow tiles serve a few right-hand sides against the whole table,
 // where a 64-wide tile would spend most of its matrix-core work on padding.
 static int nt_tn(int M, int N, bool herm) {
-    // a band-by-band product of two different blocks beyond 144 bands: 128 x 64 tiles, whose
-    // four blocks per wave take the three-product form
-    if (!herm && M == N && N > 144) return 64;
+    // beyond 144 bands, products other than Gram matrices: tiles 64 columns wide, whose four
+    // blocks per wave take the three-product form
+    (void)M;
+    if (!herm && N > 144) return 64;
     return N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128))));
 }
 static int nt_tm(int M, int N) {
