@@ -108,6 +108,11 @@ template <typename T> struct Dft<T, 5> {
 // one Stockham stage on LDS data.
 // howmany transforms of length n; element e of transform f sits at
 // buf[((f + f0) % fmod) * ds + e * es].  Ns = product of earlier radices.
+// Consecutive threads take consecutive transforms at the same butterfly, so the
+// 16 lanes that share an LDS cycle touch 16 rows of odd stride ds (distinct banks
+// for the usual padded row lengths); with consecutive butterflies of one
+// transform per lane instead, a stage's strided writes hit the same banks (five
+// conflict cycles per LDS instruction on 512-point columns).
 // ---------------------------------------------------------------------------
 struct FftGeom {
     int n, howmany, es, ds, f0, fmod;
@@ -125,8 +130,8 @@ __device__ inline void fft_stage(cplx<T> *buf, const FftGeom &g, int Ns, const c
         const int idx = tid + it * NTHR;
         if (idx < total) {
             int f, j;
-            if (g.es == 1) { f = idx / nbf; j = idx - f * nbf; }
-            else { j = idx / g.howmany; f = idx - j * g.howmany; }
+            j = idx / g.howmany;
+            f = idx - j * g.howmany;
             int row = f + g.f0;
             if (row >= g.fmod) row -= g.fmod;
             const cplx<T> *src = buf + row * g.ds;
@@ -150,8 +155,8 @@ __device__ inline void fft_stage(cplx<T> *buf, const FftGeom &g, int Ns, const c
         const int idx = tid + it * NTHR;
         if (idx < total) {
             int f, j;
-            if (g.es == 1) { f = idx / nbf; j = idx - f * nbf; }
-            else { j = idx / g.howmany; f = idx - j * g.howmany; }
+            j = idx / g.howmany;
+            f = idx - j * g.howmany;
             int row = f + g.f0;
             if (row >= g.fmod) row -= g.fmod;
             cplx<T> *dst = buf + row * g.ds;
@@ -260,8 +265,8 @@ __device__ inline void ct_stage(cplx<T> *buf, const FftGeom &g, const cplx<T> *t
         const int idx = tid + it * NTHR;
         if (idx < total) {
             int f, j;
-            if (g.es == 1) { f = idx / nbf; j = idx - f * nbf; }
-            else { j = idx / howmany; f = idx - j * howmany; }
+            j = idx / howmany;
+            f = idx - j * howmany;
             int row = f + g.f0;
             if (row >= g.fmod) row -= g.fmod;
             const cplx<T> *src = buf + row * g.ds;
@@ -285,8 +290,8 @@ __device__ inline void ct_stage(cplx<T> *buf, const FftGeom &g, const cplx<T> *t
         const int idx = tid + it * NTHR;
         if (idx < total) {
             int f, j;
-            if (g.es == 1) { f = idx / nbf; j = idx - f * nbf; }
-            else { j = idx / howmany; f = idx - j * howmany; }
+            j = idx / howmany;
+            f = idx - j * howmany;
             int row = f + g.f0;
             if (row >= g.fmod) row -= g.fmod;
             cplx<T> *dst = buf + row * g.ds;
