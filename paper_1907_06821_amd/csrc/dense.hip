@@ -1055,6 +1055,144 @@ __global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const doub
                  reinterpret_cast<double *>(w), false, lam, rank, key, ref, info);
 }
 
+// ---------------------------------------------------------------------------
+// Householder reduction for kLdsMaxN < N <= kEigMaxN over the whole GPU: one
+// launch per stage of every step (the reflector of row k; w = tau A22 v with one
+// wave per row; the rank-two update A22 -= v w'^H + w' v^H, w' = w - (tau/2)
+// (w^H v) v, again one wave per row), so the trailing matrix's product and
+// update stream through every CU instead of one workgroup.  The same reflectors
+// as the one-workgroup kernel above, stored in the same places (hv); d, e, v, w
+// and the step's scalars live in the part of the work region that the matrix
+// copy leaves free.  The divide and conquer then runs in one workgroup
+// (dc_global_kernel).
+// ---------------------------------------------------------------------------
+constexpr int kHhWaves = 8;          // rows (waves) per workgroup of the row kernels
+
+struct HhScratch {
+    double2 *v, *w, *sc;             // sc[0] tau, sc[1] scale of the reflector
+    double *d, *e;
+};
+
+__global__ __launch_bounds__(256) void hh_symmetrize(int N, const double2 *__restrict__ Ain, int64_t lda,
+                                                     double2 *__restrict__ Ag) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < N; j += 256) {
+        const double2 a = Ain[(int64_t)i * lda + j], b = Ain[(int64_t)j * lda + i];
+        Ag[(int64_t)i * N + j] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+    }
+}
+
+// reflector of row k (A[k][i] = conj(A[i][k])) and its vector v (v[k + 1] = 1)
+__global__ __launch_bounds__(256) void hh_reflector(int N, int k, const double2 *__restrict__ Ag,
+                                                    double2 *__restrict__ hv, HhScratch s) {
+    __shared__ double part[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const double2 *rowk = Ag + (int64_t)k * N;
+    double s2 = 0.0;
+    for (int i = k + 2 + tid; i < N; i += 256) {
+        const double2 a = rowk[i];
+        s2 += a.x * a.x + a.y * a.y;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) part[wid] = s2;
+    __syncthreads();
+    __shared__ double2 tsc[2];
+    if (tid == 0) {
+        double2 tau, scl;
+        double beta;
+        householder(zconj(rowk[k + 1]), (part[0] + part[1]) + (part[2] + part[3]), tau, beta, scl);
+        s.d[k] = rowk[k].x;
+        s.e[k] = beta;
+        s.sc[0] = tau;
+        s.sc[1] = scl;
+        hv[N * (N - 1) / 2 + k] = tau;
+        tsc[0] = tau;
+        tsc[1] = scl;
+    }
+    __syncthreads();
+    const double2 tau = tsc[0], scl = tsc[1];
+    if (tau.x == 0.0 && tau.y == 0.0) return;
+    const int off = refl_off(k, N);
+    for (int i = k + 1 + tid; i < N; i += 256) {
+        const double2 x = i == k + 1 ? make_double2(1.0, 0.0) : zmul(zconj(rowk[i]), scl);
+        s.v[i] = x;
+        hv[off + (i - k - 1)] = x;
+    }
+}
+
+// w[i] = tau sum_j A[i][j] v[j], rows i > k, one wave per row
+__global__ __launch_bounds__(64 * kHhWaves) void hh_matvec(int N, int k, const double2 *__restrict__ Ag,
+                                                           HhScratch s) {
+    const double2 tau = s.sc[0];
+    if (tau.x == 0.0 && tau.y == 0.0) return;
+    const int lane = threadIdx.x & 63;
+    const int i = k + 1 + blockIdx.x * kHhWaves + (threadIdx.x >> 6);
+    if (i >= N) return;
+    const double2 *row = Ag + (int64_t)i * N;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = k + 1 + lane; j < N; j += 64) acc = zfma(row[j], s.v[j], acc);
+    acc = wave_sum2(acc);
+    if (lane == 0) s.w[i] = zmul(tau, acc);
+}
+
+// A22 -= v w'^H + w' v^H with w' = w + a2 v, a2 = -(tau / 2) (w^H v); every
+// workgroup forms w^H v itself (a few thousand products)
+__global__ __launch_bounds__(64 * kHhWaves) void hh_update(int N, int k, double2 *__restrict__ Ag, HhScratch s) {
+    const double2 tau = s.sc[0];
+    if (tau.x == 0.0 && tau.y == 0.0) return;
+    __shared__ double2 part[kHhWaves];
+    __shared__ double2 a2s;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double2 t = make_double2(0.0, 0.0);
+    for (int i = k + 1 + tid; i < N; i += 64 * kHhWaves) t = zfma(zconj(s.w[i]), s.v[i], t);
+    t = wave_sum2(t);
+    if (lane == 0) part[wid] = t;
+    __syncthreads();
+    if (tid == 0) {
+        double2 tt = make_double2(0.0, 0.0);
+        for (int q = 0; q < kHhWaves; ++q) tt = make_double2(tt.x + part[q].x, tt.y + part[q].y);
+        const double2 h = zmul(tau, tt);
+        a2s = make_double2(-0.5 * h.x, -0.5 * h.y);
+    }
+    __syncthreads();
+    const double2 a2 = a2s;
+    const int i = k + 1 + blockIdx.x * kHhWaves + wid;
+    if (i >= N) return;
+    double2 *row = Ag + (int64_t)i * N;
+    const double2 vi = s.v[i], wi = zfma(a2, vi, s.w[i]);
+    for (int j = k + 1 + lane; j < N; j += 64) {
+        const double2 vj = s.v[j], wj = zfma(a2, vj, s.w[j]);
+        const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
+        double2 a = row[j];
+        a.x -= t1.x + t2.x;
+        a.y = i == j ? 0.0 : a.y - (t1.y + t2.y);
+        row[j] = a;
+    }
+}
+
+// divide and conquer of the tridiagonal (d, e) left by the reduction, one workgroup;
+// the reduced matrix's storage becomes Z, the product's temporary and V
+template <int NT>
+__global__ __launch_bounds__(NT) void dc_global_kernel(int N, double2 *__restrict__ Ag, HhScratch s,
+                                                       int *__restrict__ rank, double *__restrict__ lam, int key,
+                                                       double ref, int *__restrict__ info) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double2 v[kEigMaxN], w[kEigMaxN];
+    __shared__ double d[kEigMaxN], e[kEigMaxN];
+    for (int i = threadIdx.x; i < N - 1; i += NT) {
+        d[i] = s.d[i];
+        e[i] = s.e[i];
+    }
+    if (threadIdx.x == 0) {
+        d[N - 1] = Ag[(int64_t)(N - 1) * N + (N - 1)].x;
+        e[N - 1] = 0.0;
+    }
+    __syncthreads();
+    double *Zt = reinterpret_cast<double *>(Ag);
+    dc_block<NT>(N, d, e, Zt, Zt + 2 * (size_t)N * N, Zt + (size_t)N * N, smem_raw, reinterpret_cast<double *>(v),
+                 reinterpret_cast<double *>(w), false, lam, rank, key, ref, info);
+}
+
 // Back-transformation, one wave per eigenvector, NW waves per workgroup.
 // LDS_V: all reflectors staged in LDS (N <= kLdsMaxN); otherwise read from
 // global memory one reflector ahead.
@@ -1312,9 +1450,29 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
                            dim3(64 * kBackNW), b2, st, N, (const double2 *)hv, (const double *)zbuf,
                            (const int *)rank, (double2 *)R);
     } else {
-        lds_limit(reinterpret_cast<const void *>(tridiag_ql_global_kernel<kEigNT>), dcb, attr3);
-        hipLaunchKernelGGL(tridiag_ql_global_kernel<kEigNT>, dim3(1), dim3(kEigNT), dcb, st, N, (const double2 *)A,
-                           lda, zbuf, hv, rank, lam, key, ref, info);
+        // the reduction over the whole GPU (the matrix copy in the first 16 N^2 bytes of
+        // zbuf, d, e, v, w and the step's scalars in the next 8 N^2), then the divide and
+        // conquer in one workgroup
+        double2 *Ag = (double2 *)zbuf;
+        char *free8 = (char *)zbuf + (size_t)16 * N * N;
+        HhScratch s;
+        s.v = (double2 *)free8;
+        s.w = s.v + N;
+        s.sc = s.w + N;
+        s.d = (double *)(s.sc + 4);
+        s.e = s.d + N;
+        hipLaunchKernelGGL(hh_symmetrize, dim3(N), dim3(256), 0, st, N, (const double2 *)A, lda, Ag);
+        PW_LAUNCH_CHECK();
+        for (int k = 0; k + 1 < N; ++k) {
+            const int nblk = (N - 1 - k + kHhWaves - 1) / kHhWaves;
+            hipLaunchKernelGGL(hh_reflector, dim3(1), dim3(256), 0, st, N, k, (const double2 *)Ag, hv, s);
+            hipLaunchKernelGGL(hh_matvec, dim3(nblk), dim3(64 * kHhWaves), 0, st, N, k, (const double2 *)Ag, s);
+            hipLaunchKernelGGL(hh_update, dim3(nblk), dim3(64 * kHhWaves), 0, st, N, k, Ag, s);
+        }
+        PW_LAUNCH_CHECK();
+        lds_limit(reinterpret_cast<const void *>(dc_global_kernel<kEigNT>), dcb, attr3);
+        hipLaunchKernelGGL(dc_global_kernel<kEigNT>, dim3(1), dim3(kEigNT), dcb, st, N, Ag, s, rank, lam, key, ref,
+                           info);
         PW_LAUNCH_CHECK();
         hipLaunchKernelGGL((backtransform_kernel<kBackNW, kEigMaxN, false>), dim3((N + kBackNW - 1) / kBackNW),
                            dim3(64 * kBackNW), 0, st, N, (const double2 *)hv, (const double *)zbuf, (const int *)rank,

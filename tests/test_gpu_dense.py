@@ -14,7 +14,7 @@ def _herm(n, seed, spread=1.0):
     return (q * w) @ q.conj().T, w
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 128, 136, 137, 160])
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 128, 136, 137, 160, 300, 1024])
 def test_dense_eigh_random(torch_cuda, n):
     import torch
     import paper_1907_06821_amd as pw
