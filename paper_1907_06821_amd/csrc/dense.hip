@@ -218,9 +218,9 @@ __global__ __launch_bounds__(NT) void chol_inv_lds_jobs(const DenseJob *__restri
 //
 // tridiag_ql_lds_kernel (N <= kLdsMaxN): A as a packed lower triangle in LDS,
 // whose space then holds the divide and conquer's scratch; Z, V and the
-// product's temporary in global work memory.  tridiag_ql_global_kernel
-// (N <= kEigMaxN): full A in global memory (rows coalesced), Z and the rest over
-// the dead A.
+// product's temporary in global work memory.  kLdsMaxN < N <= kEigMaxN: the same
+// steps as launches over the whole GPU (hh_* and dc_*_kernel below), full A in
+// global memory, Z and the rest over the dead A.
 // ---------------------------------------------------------------------------
 constexpr int kQlMaxIter = 60;
 constexpr int kEigNT = 512;
@@ -563,10 +563,12 @@ __device__ inline double secular_root(int i, int K, const double *d, const doubl
     return tau;
 }
 
-// merge the solved blocks [a, b) and [b, c) (whole workgroup)
+// merge of the solved blocks [a, b) and [b, c), first part (whole workgroup): order,
+// deflation (its rotations applied to Z), secular roots, the merged eigenvalues in
+// t.lamv and the kept block's eigenvectors V (K x K, row i for root i)
 template <int NT>
-__device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V, double *Ztmp,
-                         const DcLds &t) {
+__device__ void dc_merge_roots(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V,
+                               const DcLds &t) {
     const int tid = threadIdx.x % NT;
     const int n = c - a;
     const double rho = fabs(beta), sg = beta >= 0.0 ? 1.0 : -1.0;
@@ -690,6 +692,14 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
         for (int j = 0; j < K; ++j) V[(int64_t)i * K + j] *= inv;
     }
     dc_sync<NT>();
+}
+
+// second part: the block's new eigenvector columns and eigenvalues
+template <int NT>
+__device__ void dc_merge_update(int N, int a, int c, double *d, double *Zt, const double *V, double *Ztmp,
+                                const DcLds &t) {
+    const int tid = threadIdx.x % NT;
+    const int n = c - a, K = t.ctl[0];
     // new columns in ascending order: deflated ones copied, kept ones (Z_kept V^T):
     // k chunks of Z_kept (rows of the block) and V staged in LDS, each thread
     // accumulating 4 x 4 tiles of the product
@@ -753,6 +763,13 @@ __device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, dou
     }
     for (int j = tid; j < n; j += NT) d[a + j] = t.lamv[j];
     dc_sync<NT>();
+}
+
+template <int NT>
+__device__ void dc_merge(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V, double *Ztmp,
+                         const DcLds &t) {
+    dc_merge_roots<NT>(N, a, b, c, beta, d, Zt, V, t);
+    dc_merge_update<NT>(N, a, c, d, Zt, V, Ztmp, t);
 }
 
 // Eigen-decomposition of the tridiagonal (d, e) into d (eigenvalues) and Zt
@@ -957,120 +974,22 @@ __global__ __launch_bounds__(NT) void tridiag_ql_lds_jobs(const DenseJob *__rest
     tridiag_ql_lds_body<NT>(j.N, j.A, j.lda, j.hv, j.zbuf, j.rank, j.lam, 0, 0.0, j.info);
 }
 
-// Same algorithm for N <= kEigMaxN.  Ag: N x N work copy of A (full Hermitian,
-// rows coalesced); Z overwrites it once the reduction is done (zg == Ag).
-template <int NT>
-__global__ __launch_bounds__(NT) void tridiag_ql_global_kernel(int N, const double2 *__restrict__ Ain, int64_t lda,
-                                                               double2 *__restrict__ Ag, double2 *__restrict__ hv,
-                                                               int *__restrict__ rank, double *__restrict__ lam,
-                                                               int key, double ref, int *__restrict__ info) {
-    extern __shared__ unsigned char smem_raw[];            // the divide and conquer's scratch
-    __shared__ double2 v[kEigMaxN], w[kEigMaxN];
-    __shared__ double d[kEigMaxN], e[kEigMaxN];
-    __shared__ double2 sc[3][2];
-    constexpr int NW = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int tau_off = N * (N - 1) / 2;
-    for (int i = wid; i < N; i += NW)
-        for (int j = lane; j < N; j += 64) {
-            const double2 a = Ain[(int64_t)i * lda + j], b = Ain[(int64_t)j * lda + i];
-            Ag[(int64_t)i * N + j] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
-        }
-    __syncthreads();
-    for (int k = 0; k + 1 < N; ++k) {
-        const int par = k & 1, m = N - 1 - k;
-        const double2 *rowk = Ag + (int64_t)k * N;          // A[k][i] = conj(A[i][k])
-        if (wid == 0) {
-            double s2 = 0.0;
-            for (int i = k + 2 + lane; i < N; i += 64) {
-                const double2 a = rowk[i];
-                s2 += a.x * a.x + a.y * a.y;
-            }
-            s2 = wave_sum(s2);
-            if (lane == 0) {
-                double2 tau, scl;
-                double beta;
-                householder(zconj(rowk[k + 1]), s2, tau, beta, scl);
-                d[k] = rowk[k].x;
-                e[k] = beta;
-                sc[0][par] = tau;
-                sc[1][par] = scl;
-                hv[tau_off + k] = tau;
-            }
-        }
-        __syncthreads();
-        const double2 tau = sc[0][par], scl = sc[1][par];
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
-        const int off = refl_off(k, N);
-        for (int i = k + 1 + tid; i < N; i += NT) {
-            const double2 x = i == k + 1 ? make_double2(1.0, 0.0) : zmul(zconj(rowk[i]), scl);
-            v[i] = x;
-            hv[off + (i - k - 1)] = x;
-        }
-        __syncthreads();
-        for (int r = wid; r < m; r += NW) {                 // w = tau A22 v, one wave per row
-            const int i = k + 1 + r;
-            const double2 *row = Ag + (int64_t)i * N;
-            double2 acc = make_double2(0.0, 0.0);
-            for (int j = k + 1 + lane; j < N; j += 64) acc = zfma(row[j], v[j], acc);
-            acc = wave_sum2(acc);
-            if (lane == 0) w[i] = zmul(tau, acc);
-        }
-        __syncthreads();
-        if (wid == 0) {
-            double2 t = make_double2(0.0, 0.0);
-            for (int i = k + 1 + lane; i < N; i += 64) t = zfma(zconj(w[i]), v[i], t);
-            t = wave_sum2(t);
-            if (lane == 0) {
-                const double2 h = zmul(tau, t);
-                sc[2][par] = make_double2(-0.5 * h.x, -0.5 * h.y);
-            }
-        }
-        __syncthreads();
-        const double2 a2 = sc[2][par];
-        for (int r = wid; r < m; r += NW) {
-            const int i = k + 1 + r;
-            double2 *row = Ag + (int64_t)i * N;
-            const double2 vi = v[i], wi = zfma(a2, vi, w[i]);
-            for (int j = k + 1 + lane; j < N; j += 64) {
-                const double2 vj = v[j], wj = zfma(a2, vj, w[j]);
-                const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
-                double2 a = row[j];
-                a.x -= t1.x + t2.x;
-                a.y = i == j ? 0.0 : a.y - (t1.y + t2.y);
-                row[j] = a;
-            }
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        d[N - 1] = Ag[(int64_t)(N - 1) * N + (N - 1)].x;
-        e[N - 1] = 0.0;
-    }
-    __syncthreads();
-    // A is dead: its storage holds Z and the product's temporary, V follows it;
-    // the reflector staging v, w (2048 doubles each) holds the product chunks
-    double *Zt = reinterpret_cast<double *>(Ag);
-    dc_block<NT>(N, d, e, Zt, Zt + 2 * (size_t)N * N, Zt + (size_t)N * N, smem_raw, reinterpret_cast<double *>(v),
-                 reinterpret_cast<double *>(w), false, lam, rank, key, ref, info);
-}
-
 // ---------------------------------------------------------------------------
 // Householder reduction for kLdsMaxN < N <= kEigMaxN over the whole GPU: one
 // launch per stage of every step (the reflector of row k; w = tau A22 v with one
 // wave per row; the rank-two update A22 -= v w'^H + w' v^H, w' = w - (tau/2)
 // (w^H v) v, again one wave per row), so the trailing matrix's product and
 // update stream through every CU instead of one workgroup.  The same reflectors
-// as the one-workgroup kernel above, stored in the same places (hv); d, e, v, w
-// and the step's scalars live in the part of the work region that the matrix
-// copy leaves free.  The divide and conquer then runs in one workgroup
-// (dc_global_kernel).
+// as the one-workgroup kernel above, stored in the same places (hv); Ag is the
+// N x N work copy of A (full Hermitian, rows coalesced), whose storage Z takes
+// once the reduction is done; v, w and the step's scalars live in the part of the
+// work region that V takes later, d and e in the divide and conquer's DcGlobal.
 // ---------------------------------------------------------------------------
 constexpr int kHhWaves = 8;          // rows (waves) per workgroup of the row kernels
 
 struct HhScratch {
     double2 *v, *w, *sc;             // sc[0] tau, sc[1] scale of the reflector
-    double *d, *e;
+    double *d, *e;                   // the tridiagonal
 };
 
 __global__ __launch_bounds__(256) void hh_symmetrize(int N, const double2 *__restrict__ Ain, int64_t lda,
@@ -1170,27 +1089,208 @@ __global__ __launch_bounds__(64 * kHhWaves) void hh_update(int N, int k, double2
     }
 }
 
-// divide and conquer of the tridiagonal (d, e) left by the reduction, one workgroup;
-// the reduced matrix's storage becomes Z, the product's temporary and V
+// ---------------------------------------------------------------------------
+// Divide and conquer for kLdsMaxN < N <= kEigMaxN over the whole GPU: the tears,
+// leaves and merges of dc_block, in launches.  The tears; Z = I; the leaves (one
+// wave each, its d, e and rotation lists in LDS); then per level of merges one
+// workgroup per merge for the order, deflation, secular roots and V (its scratch
+// in LDS), a tiled product Z_kept V^T over all of the level's merges, and the copy
+// of the new columns back into Z; last the eigenvalue order.  The product sums
+// over the kept columns in the same order as dc_merge_update, so both give the
+// same bits.  d, e, beta and what a merge hands on to the product (per row of the
+// merge: the order, the deflation flags and the kept positions; per merge, at its
+// first row: the kept count) stay in global memory.
+// ---------------------------------------------------------------------------
+struct DcGlobal {
+    double *d, *e, *beta;
+    int *perm, *flag, *kept, *kcount;
+    int *ctl;                        // [0] largest QL iteration count, [1] a leaf failed
+};
+// bytes of DcGlobal for N rows (after 256-byte alignment)
+__host__ __device__ constexpr size_t dc_global_bytes(int N) { return (size_t)40 * N + 64; }
+
+// eigensolver work bytes: reflectors and taus, then 3 N^2 doubles (Z, V, the
+// product's temporary; or the N x N complex copy of A followed by V), the ranks,
+// then (256-byte aligned) the divide and conquer's DcGlobal
+constexpr size_t eigh_work_bytes(int N) {
+    return ((size_t)N * (N - 1) / 2 + N) * sizeof(double2) + (size_t)24 * N * N + (size_t)4 * N + 256 +
+           dc_global_bytes(N) + 256;
+}
+
+constexpr int kDcLeafWaves = 4;      // leaves (waves) per workgroup
+constexpr int kDcTile = 64;          // rows and columns of a product tile
+constexpr int kDcKc = 16;            // kept columns per staged chunk of the product
+
+// merge m of the level whose merges are `span` leaves wide: rows [a, c), split at b
+__device__ inline double dc_level_merge(int N, int span, int m, const DcGlobal &g, int &a, int &b, int &c) {
+    const int P = dc_leaves(N), k = m * span;
+    a = (int)((int64_t)k * N / P);
+    b = (int)((int64_t)(k + span / 2) * N / P);
+    c = (int)((int64_t)(k + span) * N / P);
+    return g.beta[k + span / 2];
+}
+
+__global__ void dc_tear_kernel(int N, const double2 *__restrict__ Ag, DcGlobal g) {
+    if (threadIdx.x != 0) return;
+    g.d[N - 1] = Ag[(int64_t)(N - 1) * N + (N - 1)].x;
+    g.e[N - 1] = 0.0;
+    const int P = dc_leaves(N);
+    for (int i = 1; i < P; ++i) {
+        const int bb = (int)((int64_t)i * N / P);
+        const double be = g.e[bb - 1];
+        g.beta[i] = be;
+        g.d[bb - 1] -= fabs(be);
+        g.d[bb] -= fabs(be);
+        g.e[bb - 1] = 0.0;
+    }
+    g.ctl[0] = 0;
+    g.ctl[1] = 0;
+}
+
+__global__ __launch_bounds__(256) void dc_identity_kernel(int N, double *__restrict__ Zt) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < (int64_t)N * N) Zt[q] = (q / N == q % N) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(64 * kDcLeafWaves) void dc_leaf_kernel(int N, double *__restrict__ Zt, DcGlobal g) {
+    __shared__ double sd[kDcLeafWaves][kDcLeaf], se[kDcLeafWaves][kDcLeaf];
+    __shared__ double scs[kDcLeafWaves][kDcLeaf], ssn[kDcLeafWaves][kDcLeaf];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int P = dc_leaves(N), leaf = blockIdx.x * kDcLeafWaves + wid;
+    if (leaf >= P) return;
+    const int a = (int)((int64_t)leaf * N / P), n = (int)((int64_t)(leaf + 1) * N / P) - a;
+    double *d = sd[wid], *e = se[wid];
+    if (lane < n) {
+        d[lane] = g.d[a + lane];
+        e[lane] = g.e[a + lane];
+    }
+    dc_sync<64>();
+    int l = 0, iter = 0, maxiter = 0;
+    bool fail = false;
+    for (;;) {
+        int nrot;
+        const int ms = ql_sweep(n, d, e, scs[wid], ssn[wid], l, iter, maxiter, fail, lane, nrot);
+        if (ms < 0) break;
+        if (lane < n && nrot > 0) ql_apply(Zt + (int64_t)a * N + a, N, lane, ms, nrot, scs[wid], ssn[wid]);
+        __builtin_amdgcn_wave_barrier();
+    }
+    dc_sync<64>();
+    if (lane < n) g.d[a + lane] = d[lane];
+    if (lane == 0) {
+        atomicMax(&g.ctl[0], maxiter);
+        if (fail) atomicMax(&g.ctl[1], 1);
+    }
+}
+
+// one workgroup per merge of the level; V of merge [a, c) at V + a N
 template <int NT>
-__global__ __launch_bounds__(NT) void dc_global_kernel(int N, double2 *__restrict__ Ag, HhScratch s,
-                                                       int *__restrict__ rank, double *__restrict__ lam, int key,
-                                                       double ref, int *__restrict__ info) {
+__global__ __launch_bounds__(NT) void dc_roots_kernel(int N, int span, double *__restrict__ Zt, double *__restrict__ V,
+                                                      DcGlobal g) {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double2 v[kEigMaxN], w[kEigMaxN];
-    __shared__ double d[kEigMaxN], e[kEigMaxN];
-    for (int i = threadIdx.x; i < N - 1; i += NT) {
-        d[i] = s.d[i];
-        e[i] = s.e[i];
+    int a, b, c;
+    const double be = dc_level_merge(N, span, blockIdx.x, g, a, b, c);
+    if (be == 0.0) return;
+    const int n = c - a;
+    double *no_chunks = reinterpret_cast<double *>(smem_raw);   // non-null: the product runs elsewhere
+    const DcLds t = dc_carve(smem_raw, n, NT / 64, no_chunks, no_chunks);
+    dc_merge_roots<NT>(N, a, b, c, be, g.d, Zt, V + (int64_t)a * N, t);
+    const int K = t.ctl[0];
+    for (int j = threadIdx.x; j < n; j += NT) {
+        g.perm[a + j] = t.perm[j];
+        g.flag[a + j] = t.flag[j];
+        g.d[a + j] = t.lamv[j];
     }
-    if (threadIdx.x == 0) {
-        d[N - 1] = Ag[(int64_t)(N - 1) * N + (N - 1)].x;
-        e[N - 1] = 0.0;
+    for (int i = threadIdx.x; i < K; i += NT) g.kept[a + i] = t.kept[i];
+    if (threadIdx.x == 0) g.kcount[a] = K;
+}
+
+// new columns of every merge of the level into its temporary (Ztmp + a N, column j
+// at j n): deflated ones copied, kept ones Z_kept V^T in 64 x 64 tiles, 4 x 4 per
+// thread, over kDcKc-deep chunks of the kept columns staged in LDS
+__global__ __launch_bounds__(256) void dc_product_kernel(int N, int span, int tiles, const double *__restrict__ Zt,
+                                                         const double *__restrict__ V, double *__restrict__ Ztmp,
+                                                         DcGlobal g) {
+    __shared__ double zs[kDcKc][kDcTile], vs[kDcKc][kDcTile];
+    int a, b, c;
+    if (dc_level_merge(N, span, blockIdx.y, g, a, b, c) == 0.0) return;
+    const int n = c - a;
+    const int r0 = (blockIdx.x % tiles) * kDcTile, c0 = (blockIdx.x / tiles) * kDcTile;
+    if (r0 >= n || c0 >= n) return;
+    const int tid = threadIdx.x, K = g.kcount[a];
+    const int *perm = g.perm + a, *flag = g.flag + a, *kept = g.kept + a;
+    double *Zm = Ztmp + (int64_t)a * N;
+    const double *Vm = V + (int64_t)a * N;
+    for (int e = tid; e < kDcTile * kDcTile; e += 256) {
+        const int tc = c0 + e / kDcTile, r = r0 + e % kDcTile;
+        if (tc < n && r < n && flag[tc] > 0) Zm[(int64_t)tc * n + r] = Zt[(int64_t)perm[tc] * N + a + r];
     }
-    __syncthreads();
-    double *Zt = reinterpret_cast<double *>(Ag);
-    dc_block<NT>(N, d, e, Zt, Zt + 2 * (size_t)N * N, Zt + (size_t)N * N, smem_raw, reinterpret_cast<double *>(v),
-                 reinterpret_cast<double *>(w), false, lam, rank, key, ref, info);
+    if (c0 >= K) return;
+    const int tr = (tid & 15) * 4, tq = (tid >> 4) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int j0 = 0; j0 < K; j0 += kDcKc) {
+        const int kc = min(kDcKc, K - j0);
+        __syncthreads();
+        for (int e = tid; e < kDcKc * kDcTile; e += 256) {
+            const int jj = e / kDcTile, x = e % kDcTile;           // Z: rows contiguous
+            zs[jj][x] = jj < kc && r0 + x < n ? Zt[(int64_t)perm[kept[j0 + jj]] * N + a + r0 + x] : 0.0;
+            const int cy = e / kDcKc, ji = e % kDcKc;              // V: kept index contiguous
+            vs[ji][cy] = ji < kc && c0 + cy < K ? Vm[(int64_t)(c0 + cy) * K + j0 + ji] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < kc; ++jj) {
+            double zr[4], vr[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) zr[x] = zs[jj][tr + x];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) vr[y] = vs[jj][tq + y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = fma(zr[x], vr[y], acc[x][y]);
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int r = r0 + tr + x, cc = c0 + tq + y;
+            if (r < n && cc < K) Zm[(int64_t)kept[cc] * n + r] = acc[x][y];
+        }
+}
+
+// the level's new columns back into Z (block x: column x of each merge)
+__global__ __launch_bounds__(256) void dc_write_kernel(int N, int span, double *__restrict__ Zt,
+                                                       const double *__restrict__ Ztmp, DcGlobal g) {
+    int a, b, c;
+    if (dc_level_merge(N, span, blockIdx.y, g, a, b, c) == 0.0) return;
+    const int n = c - a, col = blockIdx.x;
+    if (col >= n) return;
+    const double *src = Ztmp + (int64_t)a * N + (int64_t)col * n;
+    double *dst = Zt + (int64_t)(a + col) * N + a;
+    for (int r = threadIdx.x; r < n; r += 256) dst[r] = src[r];
+}
+
+// eigenvalues ordered by key (ties by value, then index) into lam, ranks, info
+__global__ __launch_bounds__(256) void dc_order_kernel(int N, DcGlobal g, int *__restrict__ rank,
+                                                       double *__restrict__ lam, int key, double ref,
+                                                       int *__restrict__ info) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0 && info) info[0] = g.ctl[1] ? -1 : g.ctl[0];
+    if (i >= N) return;
+    const double li = g.d[i];
+    const double ki = key ? fabs(li - ref) : li;
+    int rk = 0;
+    for (int j = 0; j < N; ++j) {
+        const double lj = g.d[j];
+        const double kj = key ? fabs(lj - ref) : lj;
+        if (kj < ki || (kj == ki && (lj < li || (lj == li && j < i)))) ++rk;
+    }
+    lam[rk] = li;
+    rank[i] = rk;
 }
 
 // Back-transformation, one wave per eigenvector, NW waves per workgroup.
@@ -1422,11 +1522,7 @@ void dense_eigh_jobs(int N, const DenseJob *jobs, const int *mask, int njobs, hi
     PW_LAUNCH_CHECK();
 }
 
-size_t dense_eigh_work_bytes(int N) {
-    // reflectors and taus, then 3 N^2 doubles (Z, V, the product's temporary; or the
-    // N x N complex copy of A followed by V), then the ranks
-    return ((size_t)N * (N - 1) / 2 + N) * sizeof(double2) + (size_t)24 * N * N + (size_t)4 * N + 256;
-}
+size_t dense_eigh_work_bytes(int N) { return eigh_work_bytes(N); }
 
 void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void *R, int key, double ref, int *info,
                 hipStream_t st) {
@@ -1451,16 +1547,25 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
                            (const int *)rank, (double2 *)R);
     } else {
         // the reduction over the whole GPU (the matrix copy in the first 16 N^2 bytes of
-        // zbuf, d, e, v, w and the step's scalars in the next 8 N^2), then the divide and
-        // conquer in one workgroup
+        // zbuf; v, w and the step's scalars in the next 8 N^2, which V takes later),
+        // then the divide and conquer (d, e and the merges' hand-over after the ranks)
         double2 *Ag = (double2 *)zbuf;
-        char *free8 = (char *)zbuf + (size_t)16 * N * N;
+        char *ext = (char *)(((uintptr_t)(rank + N) + 255) & ~(uintptr_t)255);
+        DcGlobal g;
+        g.d = (double *)ext;
+        g.e = g.d + N;
+        g.beta = g.e + N;
+        g.perm = (int *)(g.beta + N);
+        g.flag = g.perm + N;
+        g.kept = g.flag + N;
+        g.kcount = g.kept + N;
+        g.ctl = g.kcount + N;
         HhScratch s;
-        s.v = (double2 *)free8;
+        s.v = (double2 *)((char *)zbuf + (size_t)16 * N * N);
         s.w = s.v + N;
         s.sc = s.w + N;
-        s.d = (double *)(s.sc + 4);
-        s.e = s.d + N;
+        s.d = g.d;
+        s.e = g.e;
         hipLaunchKernelGGL(hh_symmetrize, dim3(N), dim3(256), 0, st, N, (const double2 *)A, lda, Ag);
         PW_LAUNCH_CHECK();
         for (int k = 0; k + 1 < N; ++k) {
@@ -1470,9 +1575,28 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
             hipLaunchKernelGGL(hh_update, dim3(nblk), dim3(64 * kHhWaves), 0, st, N, k, Ag, s);
         }
         PW_LAUNCH_CHECK();
-        lds_limit(reinterpret_cast<const void *>(dc_global_kernel<kEigNT>), dcb, attr3);
-        hipLaunchKernelGGL(dc_global_kernel<kEigNT>, dim3(1), dim3(kEigNT), dcb, st, N, Ag, s, rank, lam, key, ref,
-                           info);
+        double *Zt = (double *)zbuf, *Ztmp = Zt + (size_t)N * N, *V = Zt + 2 * (size_t)N * N;
+        hipLaunchKernelGGL(dc_tear_kernel, dim3(1), dim3(64), 0, st, N, (const double2 *)Ag, g);
+        hipLaunchKernelGGL(dc_identity_kernel, dim3((unsigned)(((int64_t)N * N + 255) / 256)), dim3(256), 0, st, N,
+                           Zt);
+        const int P = dc_leaves(N);
+        hipLaunchKernelGGL(dc_leaf_kernel, dim3((P + kDcLeafWaves - 1) / kDcLeafWaves), dim3(64 * kDcLeafWaves), 0,
+                           st, N, Zt, g);
+        PW_LAUNCH_CHECK();
+        for (int span = 2; span <= P; span *= 2) {
+            const int nm = P / span;
+            const int nmax = (int)(((int64_t)span * N + P - 1) / P) + 1;   // no merge of the level is larger
+            const size_t lb = dc_lds_bytes(nmax, kEigNT / 64, false);
+            lds_limit(reinterpret_cast<const void *>(dc_roots_kernel<kEigNT>), lb, attr3);
+            hipLaunchKernelGGL(dc_roots_kernel<kEigNT>, dim3(nm), dim3(kEigNT), lb, st, N, span, Zt, V, g);
+            const int tiles = (nmax + kDcTile - 1) / kDcTile;
+            hipLaunchKernelGGL(dc_product_kernel, dim3(tiles * tiles, nm), dim3(256), 0, st, N, span, tiles,
+                               (const double *)Zt, (const double *)V, Ztmp, g);
+            hipLaunchKernelGGL(dc_write_kernel, dim3(nmax, nm), dim3(256), 0, st, N, span, Zt, (const double *)Ztmp,
+                               g);
+            PW_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(dc_order_kernel, dim3((N + 255) / 256), dim3(256), 0, st, N, g, rank, lam, key, ref, info);
         PW_LAUNCH_CHECK();
         hipLaunchKernelGGL((backtransform_kernel<kBackNW, kEigMaxN, false>), dim3((N + kBackNW - 1) / kBackNW),
                            dim3(64 * kBackNW), 0, st, N, (const double2 *)hv, (const double *)zbuf, (const int *)rank,
@@ -1491,9 +1615,7 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
 // 256 bytes for the QL iteration count.
 // ---------------------------------------------------------------------------
 constexpr int kNoAllocMaxN = 512;
-constexpr size_t kNoAllocWork = (((size_t)kNoAllocMaxN * (kNoAllocMaxN - 1) / 2 + kNoAllocMaxN) * sizeof(double2) +
-                                 (size_t)24 * kNoAllocMaxN * kNoAllocMaxN + (size_t)4 * kNoAllocMaxN + 256 + 255) /
-                                256 * 256;
+constexpr size_t kNoAllocWork = (eigh_work_bytes(kNoAllocMaxN) + 255) / 256 * 256;
 constexpr size_t kScratchBytes = kNoAllocWork + 256;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
