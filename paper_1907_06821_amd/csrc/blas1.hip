@@ -12,6 +12,12 @@ constexpr int RCHUNK = RT * 8;   // plane waves per reduction workgroup
 
 int band_splits(int npw) { return (npw + RCHUNK - 1) / RCHUNK; }
 
+// kVec plane waves per thread, strided by the workgroup so that each load stays
+// coalesced, loads issued ahead of the stores
+constexpr int kVec = 4;
+inline dim3 vec_grid(int npw, int nb) { return dim3((unsigned)((npw + 256 * kVec - 1) / (256 * kVec)), nb); }
+
+
 __device__ inline double tpa_k(double x) {
     // Teter-Payne-Allan kinetic preconditioner
     const double num = 27.0 + x * (18.0 + x * (12.0 + 8.0 * x));
@@ -111,17 +117,36 @@ __device__ __forceinline__ void grad_body(int nb, int npw, const double2 *__rest
                                           double2 *__restrict__ Z, int64_t ld, const double *__restrict__ mu,
                                           const PrecArgs &pa, double *partial, int nsplit, int b, int split) {
     double acc[2] = {0, 0};
-    BAND_LOOP(npw) {
-        const int64_t i = (int64_t)b * ld + g;
-        const double m = mu[b];
-        const double2 x = X[i], ax = AX[i], go = Gold[i];
-        const double2 gr = make_double2(ax.x - m * x.x, ax.y - m * x.y);
-        const double w = prec_weight(pa, b, g);
-        const double2 z = make_double2(w * gr.x, w * gr.y);
-        acc[0] += gr.x * z.x + gr.y * z.y;
-        acc[1] += go.x * z.x + go.y * z.y;
-        Gold[i] = gr;
-        Z[i] = z;
+    const int g0 = split * RCHUNK, g1 = min(npw, g0 + RCHUNK);
+    const double m = mu[b];
+    // four plane waves per pass, their loads ahead of the arithmetic (the sums keep
+    // the order of one plane wave at a time)
+    for (int gb = g0 + threadIdx.x; gb < g1; gb += RT * 4) {
+        double2 x[4], ax[4], go[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int g = gb + RT * j;
+            if (g < g1) {
+                const int64_t i = (int64_t)b * ld + g;
+                x[j] = X[i];
+                ax[j] = AX[i];
+                go[j] = Gold[i];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int g = gb + RT * j;
+            if (g < g1) {
+                const int64_t i = (int64_t)b * ld + g;
+                const double2 gr = make_double2(ax[j].x - m * x[j].x, ax[j].y - m * x[j].y);
+                const double w = prec_weight(pa, b, g);
+                const double2 z = make_double2(w * gr.x, w * gr.y);
+                acc[0] += gr.x * z.x + gr.y * z.y;
+                acc[1] += go[j].x * z.x + go[j].y * z.y;
+                Gold[i] = gr;
+                Z[i] = z;
+            }
+        }
     }
     block_store<2>(acc, partial, nb, nsplit, b, split);
 }
@@ -180,9 +205,12 @@ __device__ __forceinline__ void pupdate_body(int npw, const double2 *__restrict_
     }
 }
 
-__global__ void k_pupdate(int nb, int npw, const double2 *__restrict__ Z, double2 *__restrict__ P, int64_t ld,
-                          const double *__restrict__ gz, const double *__restrict__ gzo, double *__restrict__ gz_old) {
-    pupdate_body(npw, Z, P, ld, gz, gzo, gz_old, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(256) void k_pupdate(int nb, int npw, const double2 *__restrict__ Z,
+                                                 double2 *__restrict__ P, int64_t ld, const double *__restrict__ gz,
+                                                 const double *__restrict__ gzo, double *__restrict__ gz_old) {
+    const int g0 = blockIdx.x * 256 * kVec + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) pupdate_body(npw, Z, P, ld, gz, gzo, gz_old, blockIdx.y, g0 + 256 * j);
 }
 
 __global__ void k_store_gzold(int nb, const double *gz, double *gz_old) {
@@ -192,7 +220,7 @@ __global__ void k_store_gzold(int nb, const double *gz, double *gz_old) {
 
 void pupdate(int nb, int npw, const void *Z, void *P, int64_t ld, const double *gz, const double *gzo,
              double *gz_old, hipStream_t st) {
-    hipLaunchKernelGGL(k_pupdate, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (const double2 *)Z,
+    hipLaunchKernelGGL(k_pupdate, vec_grid(npw, nb), dim3(256), 0, st, nb, npw, (const double2 *)Z,
                        (double2 *)P, ld, gz, gzo, gz_old);
     PW_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_store_gzold, dim3((nb + 255) / 256), dim3(256), 0, st, nb, gz, gz_old);
@@ -285,15 +313,18 @@ __device__ __forceinline__ void combine3_body(int npw, double2 *__restrict__ X, 
     AX[i] = lin2(al, AX[i], be, AP[i]);
 }
 
-__global__ void k_combine3(int nb, int npw, double2 *__restrict__ X, double2 *__restrict__ Y, double2 *__restrict__ AX,
-                           const double2 *__restrict__ P, const double2 *__restrict__ YP,
-                           const double2 *__restrict__ AP, int64_t ld, const double *__restrict__ coef) {
-    combine3_body(npw, X, Y, AX, P, YP, AP, ld, coef, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(256) void k_combine3(int nb, int npw, double2 *__restrict__ X, double2 *__restrict__ Y,
+                                                  double2 *__restrict__ AX, const double2 *__restrict__ P,
+                                                  const double2 *__restrict__ YP, const double2 *__restrict__ AP,
+                                                  int64_t ld, const double *__restrict__ coef) {
+    const int g0 = blockIdx.x * 256 * kVec + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) combine3_body(npw, X, Y, AX, P, YP, AP, ld, coef, blockIdx.y, g0 + 256 * j);
 }
 
 void combine3(int nb, int npw, void *X, void *Y, void *AX, const void *P, const void *YP, const void *AP,
               int64_t ld, const double *coef, hipStream_t st) {
-    hipLaunchKernelGGL(k_combine3, dim3((npw + 255) / 256, nb), dim3(256), 0, st, nb, npw, (double2 *)X,
+    hipLaunchKernelGGL(k_combine3, vec_grid(npw, nb), dim3(256), 0, st, nb, npw, (double2 *)X,
                        (double2 *)Y, (double2 *)AX, (const double2 *)P, (const double2 *)YP, (const double2 *)AP,
                        ld, coef);
     PW_LAUNCH_CHECK();
@@ -853,34 +884,45 @@ void fill_zero(void *p, size_t bytes, hipStream_t st) {
 }
 
 template <typename S, typename D>
-__global__ void k_convert(int npw, const S *__restrict__ src, int64_t lds, D *__restrict__ dst, int64_t ldd) {
+__global__ __launch_bounds__(256) void k_convert(int npw, const S *__restrict__ src, int64_t lds, D *__restrict__ dst,
+                                                 int64_t ldd) {
     const int b = blockIdx.y;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= npw) return;
-    const S v = src[(int64_t)b * lds + g];
-    D o;
-    o.x = v.x;
-    o.y = v.y;
-    dst[(int64_t)b * ldd + g] = o;
+    const int g0 = blockIdx.x * 256 * kVec + threadIdx.x;
+    S v[kVec];
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        const int g = g0 + 256 * j;
+        if (g < npw) v[j] = src[(int64_t)b * lds + g];
+    }
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        const int g = g0 + 256 * j;
+        if (g < npw) {
+            D o;
+            o.x = v[j].x;
+            o.y = v[j].y;
+            dst[(int64_t)b * ldd + g] = o;
+        }
+    }
 }
 
 void copy_block(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t st) {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_convert<double2, double2>), dim3((npw + 255) / 256, nb), dim3(256), 0, st, npw,
+    hipLaunchKernelGGL((k_convert<double2, double2>), vec_grid(npw, nb), dim3(256), 0, st, npw,
                        (const double2 *)src, lds, (double2 *)dst, ldd);
     PW_LAUNCH_CHECK();
 }
 
 void c64_to_c128(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t st) {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_convert<float2, double2>), dim3((npw + 255) / 256, nb), dim3(256), 0, st, npw,
+    hipLaunchKernelGGL((k_convert<float2, double2>), vec_grid(npw, nb), dim3(256), 0, st, npw,
                        (const float2 *)src, lds, (double2 *)dst, ldd);
     PW_LAUNCH_CHECK();
 }
 
 void c128_to_c64(int nb, int npw, const void *src, int64_t lds, void *dst, int64_t ldd, hipStream_t st) {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_convert<double2, float2>), dim3((npw + 255) / 256, nb), dim3(256), 0, st, npw,
+    hipLaunchKernelGGL((k_convert<double2, float2>), vec_grid(npw, nb), dim3(256), 0, st, npw,
                        (const double2 *)src, lds, (float2 *)dst, ldd);
     PW_LAUNCH_CHECK();
 }

@@ -62,18 +62,49 @@ constexpr int MAXNB = 144;      // largest band tile (9 blocks of 16)
 int64_t bf16_ld(int n) { return ((int64_t)n + 63) / 64 * 64; }
 
 // ---------------------------------------------------------------------------
-// complex64 rows -> BF16 planes of rows x ldp (row-major or 16-row panels), zero
-// beyond n
+// complex64 rows -> row-major BF16 planes of rows x ldp, zero beyond n
 // ---------------------------------------------------------------------------
 __global__ void k_c64_to_planes(int rows, int n, const float2 *__restrict__ src, int64_t lds, int64_t ldp,
-                                uint16_t *__restrict__ re, uint16_t *__restrict__ im, int panel) {
+                                uint16_t *__restrict__ re, uint16_t *__restrict__ im) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (g >= ldp) return;
     const float2 v = g < n ? src[(int64_t)r * lds + g] : make_float2(0.f, 0.f);
-    const int64_t o = panel ? bf16_panel_index(r, g, ldp) : (int64_t)r * ldp + g;
+    const int64_t o = (int64_t)r * ldp + g;
     re[o] = f2bf(v.x);
     im[o] = f2bf(v.y);
+}
+
+// complex64 rows -> BF16 planes in 16-row panels: a workgroup takes 16 rows x 256
+// columns, converts them through LDS (row reads coalesced) and writes its eight 1 KB
+// panel blocks per plane as whole 16-byte runs (consecutive threads, consecutive
+// runs); zero beyond n, rows beyond `rows` left alone
+__global__ __launch_bounds__(256) void k_c64_to_panels(int rows, int n, const float2 *__restrict__ src, int64_t lds,
+                                                       int64_t ldp, uint16_t *__restrict__ re,
+                                                       uint16_t *__restrict__ im) {
+    __shared__ uint4 tre[16][32], tim[16][32];            // [row][run of 8 columns]
+    uint16_t *lre = reinterpret_cast<uint16_t *>(&tre[0][0]), *lim = reinterpret_cast<uint16_t *>(&tim[0][0]);
+    const int t = threadIdx.x, r0 = blockIdx.y * 16;
+    const int64_t k0 = (int64_t)blockIdx.x * 256, k = k0 + t;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        const int r = r0 + i;
+        const float2 v = r < rows && k < n ? src[(int64_t)r * lds + k] : make_float2(0.f, 0.f);
+        lre[i * 256 + t] = f2bf(v.x);
+        lim[i * 256 + t] = f2bf(v.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int id = t + 256 * h, q = id & 63;
+        const int i = q & 15, run = (id >> 6) * 4 + (q >> 4);   // panel block id >> 6, run q within it
+        const int r = r0 + i;
+        const int64_t kk = k0 + run * 8;
+        if (r >= rows || kk >= ldp) continue;
+        const int64_t o = bf16_panel_index(r, kk, ldp);
+        *reinterpret_cast<uint4 *>(re + o) = tre[i][run];
+        *reinterpret_cast<uint4 *>(im + o) = tim[i][run];
+    }
 }
 
 // complex128 table rows [r_off, r_off + rows) ([rows][n]) -> columns of the transposed BF16 planes
@@ -669,8 +700,12 @@ void proj_bf16(int nproj, int nb, int npw, int max_bands, const void *beta16, co
     const bool panel = bf16_panels(max_bands);
     const uint16_t *Br = (const uint16_t *)beta16, *Bi = Br + bf16_rows(nproj, max_bands) * ldg;
     Bf16Scratch S(scratch, max_bands, ldg, ldp);
-    hipLaunchKernelGGL(k_c64_to_planes, dim3((unsigned)((ldg + 255) / 256), nb), dim3(256), 0, st, nb, npw,
-                       (const float2 *)psi, ld, ldg, S.Pr, S.Pi, panel ? 1 : 0);
+    if (panel)
+        hipLaunchKernelGGL(k_c64_to_panels, dim3((unsigned)((ldg + 255) / 256), (nb + 15) / 16), dim3(256), 0, st, nb,
+                           npw, (const float2 *)psi, ld, ldg, S.Pr, S.Pi);
+    else
+        hipLaunchKernelGGL(k_c64_to_planes, dim3((unsigned)((ldg + 255) / 256), nb), dim3(256), 0, st, nb, npw,
+                           (const float2 *)psi, ld, ldg, S.Pr, S.Pi);
     PW_LAUNCH_CHECK();
     if (panel) {
         // every band in one launch of 256-band tiles, split over the plane waves
