@@ -444,15 +444,32 @@ static int nt_live_tiles(int M, int N) {
     return live;
 }
 
-// K-splits: enough workgroups to cover the chip (~512) while keeping at least
-// four LDS stages per chunk and the partial sums under 64 MiB (128 MiB for a Gram
-// matrix).
+// K-splits: enough workgroups to cover the chip (~512, two per compute unit) while
+// keeping at least four LDS stages per chunk and the partial sums under 64 MiB
+// (128 MiB for a Gram matrix).  Other than for a Gram matrix the count is the one
+// with the least time per split in rounds of 512 workgroups: a split count just
+// past a whole round leaves a short last round (96 tiles x 6 splits = 576
+// workgroups ran at about half the speed of 96 x 5).
 int nt_splits(int M, int N, int K, bool herm) {
     const int tn = nt_tn(M, N, herm), tm = nt_tm(M, N);
     const int mt = (M + tm - 1) / tm, ntl = (N + tn - 1) / tn;
     const int tiles = mt * ntl;
     int s = (512 + tiles - 1) / tiles;
-    if (herm) {
+    if (!herm) {
+        const int64_t cap = ((int64_t)64 << 20) / ((int64_t)M * N * (int64_t)sizeof(double2));
+        const int hi = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)s, (K + 4 * KT - 1) / (4 * KT), cap}));
+        int best = 1;
+        double bcost = 2.0;
+        for (int c = 1; c <= hi; ++c) {
+            const double cost = (double)(((int64_t)tiles * c + 511) / 512) / c;
+            if (cost < bcost * (1.0 - 1e-9)) {
+                bcost = cost;
+                best = c;
+            }
+        }
+        return best;
+    }
+    {
         // a Gram matrix computes only the tiles that reach the diagonal: as many
         // splits as fill the 256 compute units once (a second workgroup on a unit
         // halves the speed of both)
