@@ -432,7 +432,7 @@ static int nt_tn(int M, int N, bool herm) {
 static int nt_tm(int M, int N) {
     if (N <= 32) return M >= 512 ? 128 : 64;
     if (M == N && M > 128 && M <= 144) return 48;
-    return ((M >= 512 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
+    return ((M >= 256 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
 }
 
 // tiles of a Gram matrix's tile grid that reach the diagonal
