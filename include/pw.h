@@ -169,7 +169,9 @@ pw_status pw_orthonormalize(pw_ctx *ctx, int32_t nb, void *psi, int64_t ld, void
  * at most, 2: the radices of 0 in ascending order; radix[] lists the z plan or
  * the xy axis-0 plan), for pass 1 on planes of 16, 32, 48, 64, 96 or 128
  * points a side kind 3 the four-lane register kernel with nthr threads (128,
- * 192, 256 or 512; the default there), kind 0 the built-in default.  Pass 4 (complex128 only)
+ * 192, 256 or 512; the default there; sched 1, complex128 planes of at most 64
+ * points only: V(r) loaded ahead of the x transforms), kind 0 the built-in
+ * default.  Pass 4 (complex128 only)
  * is the back-projection GEMM: kind 3, sched the tile id, radix[0..1] the tile's
  * rows and columns, radix[2] the band count it was timed at (the choice applies
  * to calls with that many bands), nthr its threads.  Pass 5 (complex128 only),

@@ -87,6 +87,7 @@ FftPlan make_plan_sched(int n, int sched);
 struct FftChoice {
     int kind = 0;
     int nthr = 0;
+    bool vpf = false;       // four-lane xy kernel, complex128: V(r) loaded ahead
     FftPlan p0{}, p1{};
 };
 // back-projection GEMM tile per band count (complex128); -1: chosen by band count

@@ -424,7 +424,7 @@ template <typename T, int M, int S> __device__ inline void quad_b(cplx<T> *v, co
     reg_dft<T, M, S>(v);
 }
 
-template <typename T, int M, int NTHR>
+template <typename T, int M, int NTHR, bool VPF = sizeof(T) == 4>
 __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restrict__ cols, int z, int b) {
     constexpr int L = 4 * M, RS = quad_rs(M), PD = quad_pad(M), MB = M + PD, NQ = NTHR / 4;
     extern __shared__ unsigned char smem_raw[];
@@ -464,9 +464,8 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
     }
     __syncthreads();
     const T *vz = reinterpret_cast<const T *>(a.vz) + (int64_t)z * L * L;
-    // complex64 loads V(r) ahead of the x transforms; complex128 at its use, which
-    // keeps it within 128 VGPRs (four waves per SIMD)
-    constexpr bool VPF = sizeof(T) == 4;
+    // V(r) loaded ahead of the x transforms (VPF; always for complex64), or at its
+    // use (fewer VGPRs: complex128 on 64-point planes 182 against 208 at 256 threads)
     for (int y = quad; y < L; y += NQ) {                     // x inverse, V, x forward
         const int yc = y + (y / M) * PD;
         T vv[M];
@@ -506,9 +505,9 @@ __device__ __forceinline__ void xy_quad_body(const XYArgs &a, cplx<T> *__restric
     for (int c = tid; c < a.ncols; c += NTHR) crow[c] = pl[a.colslot[c]];
 }
 
-template <typename T, int M, int NTHR>
+template <typename T, int M, int NTHR, bool VPF>
 __global__ __launch_bounds__(NTHR) void xy_quad(XYArgs a, cplx<T> *__restrict__ cols) {
-    xy_quad_body<T, M, NTHR>(a, cols, blockIdx.x, blockIdx.y);
+    xy_quad_body<T, M, NTHR, VPF>(a, cols, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, int M, int NTHR>
@@ -698,22 +697,38 @@ template <typename T> static size_t quad_lds(const XYArgs &a) {
     return sizeof(cplx<T>) * ((size_t)a.n0 + (size_t)a.nrows * quad_rs(std::max(1, a.n1 / 4)));
 }
 
-template <typename T, int M, int NTHR>
+template <typename T, int M, int NTHR, bool VPF>
 static void quad_go(const XYArgs &a, int nb, hipStream_t s, void *cols) {
     const size_t lds = quad_lds<T>(a);
-    allow_lds(xy_quad<T, M, NTHR>, lds);
-    hipLaunchKernelGGL((xy_quad<T, M, NTHR>), dim3(a.n2, nb), dim3(NTHR), lds, s, a,
+    allow_lds(xy_quad<T, M, NTHR, VPF>, lds);
+    hipLaunchKernelGGL((xy_quad<T, M, NTHR, VPF>), dim3(a.n2, nb), dim3(NTHR), lds, s, a,
                        reinterpret_cast<cplx<T> *>(cols));
 }
 
-template <typename T, int NTHR> static void quad_len(const XYArgs &a, int nb, hipStream_t s, void *cols) {
+// vpf: complex128 with V(r) loaded ahead (planes of at most 64 points; complex64
+// always loads it ahead)
+template <typename T, int NTHR>
+static void quad_len(const XYArgs &a, int nb, hipStream_t s, void *cols, bool vpf) {
+    constexpr bool D = sizeof(T) == 8;
+    if (D && vpf) {
+        if constexpr (D) {
+            switch (a.n0) {
+                case 16: quad_go<T, 4, NTHR, true>(a, nb, s, cols); return;
+                case 32: quad_go<T, 8, NTHR, true>(a, nb, s, cols); return;
+                case 48: quad_go<T, 12, NTHR, true>(a, nb, s, cols); return;
+                case 64: quad_go<T, 16, NTHR, true>(a, nb, s, cols); return;
+                default: PW_CHECK(false, PW_EUNSUPPORTED, "no V-prefetch xy kernel for %d x %d", a.n0, a.n1);
+            }
+        }
+        return;
+    }
     switch (a.n0) {
-        case 16: quad_go<T, 4, NTHR>(a, nb, s, cols); break;
-        case 32: quad_go<T, 8, NTHR>(a, nb, s, cols); break;
-        case 48: quad_go<T, 12, NTHR>(a, nb, s, cols); break;
-        case 64: quad_go<T, 16, NTHR>(a, nb, s, cols); break;
-        case 96: quad_go<T, 24, NTHR>(a, nb, s, cols); break;
-        case 128: quad_go<T, 32, NTHR>(a, nb, s, cols); break;
+        case 16: quad_go<T, 4, NTHR, !D>(a, nb, s, cols); break;
+        case 32: quad_go<T, 8, NTHR, !D>(a, nb, s, cols); break;
+        case 48: quad_go<T, 12, NTHR, !D>(a, nb, s, cols); break;
+        case 64: quad_go<T, 16, NTHR, !D>(a, nb, s, cols); break;
+        case 96: quad_go<T, 24, NTHR, !D>(a, nb, s, cols); break;
+        case 128: quad_go<T, 32, NTHR, !D>(a, nb, s, cols); break;
         default: PW_CHECK(false, PW_EUNSUPPORTED, "no four-lane xy kernel for %d x %d", a.n0, a.n1);
     }
 }
@@ -733,11 +748,12 @@ void launch_xy(pw_ctx *ctx, int nb, void *cols, void *grid, hipStream_t s) {
     if (MODE == 0 && (c.kind == 3 || (c.kind == 0 && xy_has_quad(a.n0, a.n1) && quad_lds<T>(a) <= 160 * 1024))) {
         PW_CHECK(xy_has_quad(a.n0, a.n1), PW_EUNSUPPORTED, "no four-lane xy kernel for %d x %d", a.n0, a.n1);
         const int nthr = c.kind == 3 ? c.nthr : (sizeof(T) == 8 || a.n0 > 64 ? 256 : 192);
+        const bool vpf = c.kind == 3 && c.vpf;
         switch (nthr) {
-            case 128: quad_len<T, 128>(a, nb, s, cols); break;
-            case 192: quad_len<T, 192>(a, nb, s, cols); break;
-            case 256: quad_len<T, 256>(a, nb, s, cols); break;
-            case 512: quad_len<T, 512>(a, nb, s, cols); break;
+            case 128: quad_len<T, 128>(a, nb, s, cols, vpf); break;
+            case 192: quad_len<T, 192>(a, nb, s, cols, vpf); break;
+            case 256: quad_len<T, 256>(a, nb, s, cols, vpf); break;
+            case 512: quad_len<T, 512>(a, nb, s, cols, vpf); break;
             default: PW_CHECK(false, PW_EUNSUPPORTED, "four-lane xy kernel with %d threads", nthr);
         }
         PW_LAUNCH_CHECK();
@@ -1027,6 +1043,9 @@ template <typename T> static bool choice_from(pw_ctx *ctx, const pw_fft_cand &r,
     if (r.kind == 1) return r.pass == 1 ? (n0 == n1 && xy_has_ct<T>(n0)) : z_has_ct(n2);
     if (r.kind == 3) {
         c.nthr = r.nthr;
+        // sched 1: complex128 with V(r) loaded ahead, on planes of at most 64 points
+        c.vpf = r.sched == 1;
+        if (r.sched != 0 && !(r.sched == 1 && sizeof(T) == 8 && n0 <= 64)) return false;
         // (512 threads would spill the complex128 96- and 128-point kernels: not offered)
         return r.pass == 1 && xy_has_quad(n0, n1) && quad_lds<T>(xyargs<T>(ctx)) <= 160 * 1024 &&
                (c.nthr == 128 || c.nthr == 192 || c.nthr == 256 || (c.nthr == 512 && (sizeof(T) == 4 || n0 <= 64)));
@@ -1050,13 +1069,15 @@ template <typename T> static std::vector<pw_fft_cand> candidates(pw_ctx *ctx, in
     FftChoice c;
     r.kind = 1;
     if (choice_from<T>(ctx, r, c)) out.push_back(r);
-    for (int t : {128, 192, 256, 512}) {
-        r = pw_fft_cand{};
-        r.pass = pass;
-        r.kind = 3;
-        r.nthr = t;
-        if (choice_from<T>(ctx, r, c)) out.push_back(r);
-    }
+    for (int vpf = 0; vpf < 2; ++vpf)
+        for (int t : {128, 192, 256, 512}) {
+            r = pw_fft_cand{};
+            r.pass = pass;
+            r.kind = 3;
+            r.nthr = t;
+            r.sched = vpf;
+            if (choice_from<T>(ctx, r, c)) out.push_back(r);
+        }
     std::vector<FftChoice> seen;
     for (int sched = 0; sched < 3; ++sched) {
         for (int t : {256, 512, 1024}) {

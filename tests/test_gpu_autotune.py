@@ -35,8 +35,10 @@ def test_every_fft_candidate_matches_oracle(torch_cuda, which):
     for dtype, tol_ref, tol_var in ((pw.PW_C128, 1e-12, 1e-12), (pw.PW_C64, 2e-3, 3e-6)):
         recs = pw.autotune(ctx, nb, dtype=dtype, reps=2)
         if which in ("cube48", "tiny"):
-            # four-lane kernel at 128, 192, 256 and 512 threads
-            assert sum(r["pass_"] == 1 and r["kind"] == 3 for r in recs) == 4
+            # four-lane kernel at 128, 192, 256 and 512 threads; complex128 also with V(r)
+            # loaded ahead (sched 1)
+            n4 = 8 if dtype == pw.PW_C128 else 4
+            assert sum(r["pass_"] == 1 and r["kind"] == 3 for r in recs) == n4
         for p in range(3):
             mine = [r for r in recs if r["pass_"] == p]
             assert len(mine) >= 2
