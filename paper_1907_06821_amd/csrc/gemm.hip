@@ -425,14 +425,16 @@ __global__ __launch_bounds__(WM * WJ * 64) void zgemm_nn_jobs(const NnJob *__res
 static int nt_tn(int M, int N, bool herm) {
     // beyond 144 bands, products other than Gram matrices: tiles 64 columns wide, whose four
     // blocks per wave take the three-product form
-    (void)M;
     if (!herm && N > 144) return 64;
+    // square products of at most 128 bands (the block algebra of up to 128 bands): 64 x 64
+    // tiles, whose four blocks per wave take the three-product form outside Gram matrices
+    if (M == N && N > 64 && N <= 128) return 64;
     return N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128))));
 }
 static int nt_tm(int M, int N) {
     if (N <= 32) return M >= 512 ? 128 : 64;
     if (M == N && M > 128 && M <= 144) return 48;
-    return ((M >= 256 && N > 64) || (M == N && M > 64 && M <= 128)) ? 128 : 64;
+    return (M >= 256 && N > 64) ? 128 : 64;
 }
 
 // tiles of a Gram matrix's tile grid that reach the diagonal
