@@ -81,6 +81,31 @@ def test_dense_eigh_key_orders_by_distance(torch_cuda):
     assert np.max(np.abs(np.sort(w) - w_ref)) < 1e-13
 
 
+@pytest.mark.parametrize("n, split", [(128, 64), (300, 150), (1024, 512)])
+def test_dense_eigh_decoupled_blocks(torch_cuda, n, split):
+    """Degenerate tridiagonals: a block-diagonal matrix, whose reduction leaves an exact
+    zero off-diagonal at the block boundary, where a tear of the divide and conquer
+    falls (the merge across it has nothing to do), and a diagonal matrix with repeated
+    entries (every off-diagonal zero, no merge at all).  One-workgroup path at 128,
+    the launches over the GPU beyond 136."""
+    import torch
+    import paper_1907_06821_amd as pw
+    a1, _ = _herm(split, n + 1)
+    a2, _ = _herm(n - split, n + 2)
+    a = np.zeros((n, n), complex)
+    a[:split, :split] = a1
+    a[split:, split:] = a2 + 0.25 * np.eye(n - split)
+    rng = np.random.default_rng(n)
+    d = np.repeat(rng.uniform(-1, 1, n // 4), 4)[:n]
+    for m in (a, np.diag(d).astype(complex)):
+        w, r, _ = pw.dense_eigh(torch.from_numpy(m).to("cuda"), key=0)
+        w = w.cpu().numpy()
+        v = r.cpu().numpy().T
+        assert np.max(np.abs(w - np.linalg.eigvalsh(m))) < 1e-13 * max(1, n)
+        assert np.max(np.abs(m @ v - v * w[None, :])) < 1e-11
+        assert np.max(np.abs(v.conj().T @ v - np.eye(n))) < 1e-12
+
+
 @pytest.mark.parametrize("n", [1, 5, 64, 128, 136, 137, 200, 256, 300, 1024])
 def test_dense_chol_inv(torch_cuda, n):
     import torch
