@@ -563,12 +563,11 @@ __device__ inline double secular_root(int i, int K, const double *d, const doubl
     return tau;
 }
 
-// merge of the solved blocks [a, b) and [b, c), first part (whole workgroup): order,
-// deflation (its rotations applied to Z), secular roots, the merged eigenvalues in
-// t.lamv and the kept block's eigenvectors V (K x K, row i for root i)
+// merge of the solved blocks [a, b) and [b, c), first part (whole workgroup): order and
+// deflation (its rotations applied to Z); the kept poles and weights in t.kd, t.kz, their
+// count in t.ctl[0], rho |z|^2 in t.dbl[0]
 template <int NT>
-__device__ void dc_merge_roots(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V,
-                               const DcLds &t) {
+__device__ void dc_merge_deflate(int N, int a, int b, int c, double beta, double *d, double *Zt, const DcLds &t) {
     const int tid = threadIdx.x % NT;
     const int n = c - a;
     const double rho = fabs(beta), sg = beta >= 0.0 ? 1.0 : -1.0;
@@ -639,8 +638,7 @@ __device__ void dc_merge_roots(int N, int a, int b, int c, double beta, double *
         t.dbl[0] = rhon;
     }
     dc_sync<NT>();
-    const int K = t.ctl[0], nrot = t.ctl[1];
-    const double rhon = t.dbl[0];
+    const int nrot = t.ctl[1];
     // the deflation's rotations act on the block's eigenvector columns, row by row
     for (int r = a + tid; r < c; r += NT)
         for (int q = 0; q < nrot; ++q) {
@@ -650,6 +648,18 @@ __device__ void dc_merge_roots(int N, int a, int b, int c, double beta, double *
             *zp = t.rc[q] * x - t.rs[q] * y;
             *zq = t.rs[q] * x + t.rc[q] * y;
         }
+    dc_sync<NT>();
+}
+
+// second part: secular roots, the merged eigenvalues in t.lamv and the kept block's
+// eigenvectors V (K x K, row i for root i)
+template <int NT>
+__device__ void dc_merge_roots(int N, int a, int b, int c, double beta, double *d, double *Zt, double *V,
+                               const DcLds &t) {
+    dc_merge_deflate<NT>(N, a, b, c, beta, d, Zt, t);
+    const int tid = threadIdx.x % NT;
+    const int n = c - a, K = t.ctl[0];
+    const double rhon = t.dbl[0];
     // roots of the secular equation, four lanes each; flag of a kept position = -(root + 1)
     {
         constexpr int G = 4;
@@ -1093,21 +1103,24 @@ __global__ __launch_bounds__(64 * kHhWaves) void hh_update(int N, int k, double2
 // Divide and conquer for kLdsMaxN < N <= kEigMaxN over the whole GPU: the tears,
 // leaves and merges of dc_block, in launches.  The tears; Z = I; the leaves (one
 // wave each, its d, e and rotation lists in LDS); then per level of merges one
-// workgroup per merge for the order, deflation, secular roots and V (its scratch
-// in LDS), a tiled product Z_kept V^T over all of the level's merges, and the copy
-// of the new columns back into Z; last the eigenvalue order.  The product sums
-// over the kept columns in the same order as dc_merge_update, so both give the
-// same bits.  d, e, beta and what a merge hands on to the product (per row of the
-// merge: the order, the deflation flags and the kept positions; per merge, at its
-// first row: the kept count) stay in global memory.
+// workgroup per merge for the order and deflation (its scratch in LDS), the secular
+// roots, the recomputed z and the rows of V each over all of the level's merges, a
+// tiled product Z_kept V^T, and the copy of the new columns back into Z; last the
+// eigenvalue order.  The product sums over the kept columns in the same order as
+// dc_merge_update.  d, e, beta and what the launches of a merge hand on (per row of
+// the merge: the order, the deflation flags, the ordered D; per root: the kept
+// position, pole, weight, root and recomputed z; per merge, at its first row: the
+// kept count and rho |z|^2) stay in global memory.
 // ---------------------------------------------------------------------------
 struct DcGlobal {
     double *d, *e, *beta;
-    int *perm, *flag, *kept, *kcount;
+    double *sd, *kd, *kz, *tau, *zh; // per row of a merge: ordered D; per root: kept pole, weight, root, z
+    double *rho;                     // per merge (at its first row): rho |z|^2
+    int *perm, *flag, *kept, *kcount, *org;
     int *ctl;                        // [0] largest QL iteration count, [1] a leaf failed
 };
 // bytes of DcGlobal for N rows (after 256-byte alignment)
-__host__ __device__ constexpr size_t dc_global_bytes(int N) { return (size_t)40 * N + 64; }
+__host__ __device__ constexpr size_t dc_global_bytes(int N) { return (size_t)92 * N + 64; }
 
 // eigensolver work bytes: reflectors and taus, then 3 N^2 doubles (Z, V, the
 // product's temporary; or the N x N complex copy of A followed by V), the ranks,
@@ -1182,10 +1195,11 @@ __global__ __launch_bounds__(64 * kDcLeafWaves) void dc_leaf_kernel(int N, doubl
     }
 }
 
-// one workgroup per merge of the level; V of merge [a, c) at V + a N
+// one workgroup per merge of the level: order, deflation and its rotations of Z; hands
+// on the order, the deflation flags, the ordered D, the kept positions, poles and
+// weights, their count and rho |z|^2
 template <int NT>
-__global__ __launch_bounds__(NT) void dc_roots_kernel(int N, int span, double *__restrict__ Zt, double *__restrict__ V,
-                                                      DcGlobal g) {
+__global__ __launch_bounds__(NT) void dc_deflate_kernel(int N, int span, double *__restrict__ Zt, DcGlobal g) {
     extern __shared__ unsigned char smem_raw[];
     int a, b, c;
     const double be = dc_level_merge(N, span, blockIdx.x, g, a, b, c);
@@ -1193,15 +1207,111 @@ __global__ __launch_bounds__(NT) void dc_roots_kernel(int N, int span, double *_
     const int n = c - a;
     double *no_chunks = reinterpret_cast<double *>(smem_raw);   // non-null: the product runs elsewhere
     const DcLds t = dc_carve(smem_raw, n, NT / 64, no_chunks, no_chunks);
-    dc_merge_roots<NT>(N, a, b, c, be, g.d, Zt, V + (int64_t)a * N, t);
+    dc_merge_deflate<NT>(N, a, b, c, be, g.d, Zt, t);
     const int K = t.ctl[0];
     for (int j = threadIdx.x; j < n; j += NT) {
         g.perm[a + j] = t.perm[j];
         g.flag[a + j] = t.flag[j];
-        g.d[a + j] = t.lamv[j];
+        g.sd[a + j] = t.sD[j];
     }
-    for (int i = threadIdx.x; i < K; i += NT) g.kept[a + i] = t.kept[i];
-    if (threadIdx.x == 0) g.kcount[a] = K;
+    for (int i = threadIdx.x; i < K; i += NT) {
+        g.kept[a + i] = t.kept[i];
+        g.kd[a + i] = t.kd[i];
+        g.kz[a + i] = t.kz[i];
+    }
+    if (threadIdx.x == 0) {
+        g.kcount[a] = K;
+        g.rho[a] = t.dbl[0];
+    }
+}
+
+// secular roots of every merge of the level over the whole GPU: kDcRootLanes lanes per
+// root, the merge's poles and weights staged in LDS (a workgroup of the one-workgroup
+// merge solves its roots in turn, its waves waiting for their slowest root each time)
+constexpr int kDcRootLanes = 16;
+constexpr int kDcRootsPerBlock = 256 / kDcRootLanes;
+__global__ __launch_bounds__(256) void dc_secular_kernel(int N, int span, DcGlobal g) {
+    __shared__ double sd[kEigMaxN], sz[kEigMaxN];
+    int a, b, c;
+    if (dc_level_merge(N, span, blockIdx.y, g, a, b, c) == 0.0) return;
+    const int K = g.kcount[a], i0 = blockIdx.x * kDcRootsPerBlock;
+    if (i0 >= K) return;
+    for (int j = threadIdx.x; j < K; j += 256) {
+        sd[j] = g.kd[a + j];
+        sz[j] = g.kz[a + j];
+    }
+    __syncthreads();
+    const int sub = threadIdx.x % kDcRootLanes, i = i0 + threadIdx.x / kDcRootLanes;
+    if (i < K) {
+        int o;
+        const double tv = secular_root<kDcRootLanes>(i, K, sd, sz, g.rho[a], sub, &o);
+        if (sub == 0) {
+            g.tau[a + i] = tv;
+            g.org[a + i] = o;
+        }
+    }
+}
+
+// z recomputed from the roots (one thread per kept pole) and the merged eigenvalues
+// into d: roots at the kept positions, the deflated positions keep their D
+__global__ __launch_bounds__(256) void dc_zh_kernel(int N, int span, DcGlobal g) {
+    __shared__ double sd[kEigMaxN], st[kEigMaxN];
+    __shared__ int so[kEigMaxN];
+    int a, b, c;
+    if (dc_level_merge(N, span, blockIdx.y, g, a, b, c) == 0.0) return;
+    const int n = c - a, K = g.kcount[a], x = blockIdx.x * 256 + threadIdx.x;
+    if ((int)blockIdx.x * 256 >= n) return;
+    for (int j = threadIdx.x; j < K; j += 256) {
+        sd[j] = g.kd[a + j];
+        st[j] = g.tau[a + j];
+        so[j] = g.org[a + j];
+    }
+    __syncthreads();
+    if (x < K) {
+        double w = 1.0;
+        for (int i = 0; i < K; ++i) {
+            const double xi = (sd[so[i]] - sd[x]) + st[i];
+            w *= i == x ? xi : xi * rcp64(sd[i] - sd[x]);
+        }
+        g.zh[a + x] = copysign(sqrt(fmax(w, 0.0) / g.rho[a]), g.kz[a + x]);
+        g.d[a + g.kept[a + x]] = sd[so[x]] + st[x];
+    }
+    if (x < n && g.flag[a + x] > 0) g.d[a + x] = g.sd[a + x];
+}
+
+// V of every merge of the level (at V + a N, row i for root i): one wave per row,
+// V[i][j] = zh_j / (d_j - x_i), normalised
+constexpr int kDcVWaves = 4;
+__global__ __launch_bounds__(64 * kDcVWaves) void dc_vmat_kernel(int N, int span, double *__restrict__ V, DcGlobal g) {
+    __shared__ double sd[kEigMaxN], sz[kEigMaxN];
+    int a, b, c;
+    if (dc_level_merge(N, span, blockIdx.y, g, a, b, c) == 0.0) return;
+    const int K = g.kcount[a], i0 = blockIdx.x * kDcVWaves;
+    if (i0 >= K) return;
+    for (int j = threadIdx.x; j < K; j += 64 * kDcVWaves) {
+        sd[j] = g.kd[a + j];
+        sz[j] = g.zh[a + j];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, i = i0 + (threadIdx.x >> 6);
+    if (i >= K) return;
+    const double ti = g.tau[a + i], dorg = sd[g.org[a + i]];
+    constexpr int J = kEigMaxN / 64;
+    double v[J];
+    double nrm = 0.0;
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int j = lane + 64 * q;
+        v[q] = j < K ? sz[j] * rcp64((sd[j] - dorg) - ti) : 0.0;
+        nrm += v[q] * v[q];
+    }
+    const double inv = 1.0 / sqrt(wave_sum(nrm));
+    double *row = V + (int64_t)a * N + (int64_t)i * K;
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int j = lane + 64 * q;
+        if (j < K) row[j] = v[q] * inv;
+    }
 }
 
 // new columns of every merge of the level into its temporary (Ztmp + a N, column j
@@ -1555,11 +1665,18 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
         g.d = (double *)ext;
         g.e = g.d + N;
         g.beta = g.e + N;
-        g.perm = (int *)(g.beta + N);
+        g.sd = g.beta + N;
+        g.kd = g.sd + N;
+        g.kz = g.kd + N;
+        g.tau = g.kz + N;
+        g.zh = g.tau + N;
+        g.rho = g.zh + N;
+        g.perm = (int *)(g.rho + N);
         g.flag = g.perm + N;
         g.kept = g.flag + N;
         g.kcount = g.kept + N;
-        g.ctl = g.kcount + N;
+        g.org = g.kcount + N;
+        g.ctl = g.org + N;
         HhScratch s;
         s.v = (double2 *)((char *)zbuf + (size_t)16 * N * N);
         s.w = s.v + N;
@@ -1587,8 +1704,13 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
             const int nm = P / span;
             const int nmax = (int)(((int64_t)span * N + P - 1) / P) + 1;   // no merge of the level is larger
             const size_t lb = dc_lds_bytes(nmax, kEigNT / 64, false);
-            lds_limit(reinterpret_cast<const void *>(dc_roots_kernel<kEigNT>), lb, attr3);
-            hipLaunchKernelGGL(dc_roots_kernel<kEigNT>, dim3(nm), dim3(kEigNT), lb, st, N, span, Zt, V, g);
+            lds_limit(reinterpret_cast<const void *>(dc_deflate_kernel<kEigNT>), lb, attr3);
+            hipLaunchKernelGGL(dc_deflate_kernel<kEigNT>, dim3(nm), dim3(kEigNT), lb, st, N, span, Zt, g);
+            hipLaunchKernelGGL(dc_secular_kernel, dim3((nmax + kDcRootsPerBlock - 1) / kDcRootsPerBlock, nm),
+                               dim3(256), 0, st, N, span, g);
+            hipLaunchKernelGGL(dc_zh_kernel, dim3((nmax + 255) / 256, nm), dim3(256), 0, st, N, span, g);
+            hipLaunchKernelGGL(dc_vmat_kernel, dim3((nmax + kDcVWaves - 1) / kDcVWaves, nm), dim3(64 * kDcVWaves), 0,
+                               st, N, span, V, g);
             const int tiles = (nmax + kDcTile - 1) / kDcTile;
             hipLaunchKernelGGL(dc_product_kernel, dim3(tiles * tiles, nm), dim3(256), 0, st, N, span, tiles,
                                (const double *)Zt, (const double *)V, Ztmp, g);
