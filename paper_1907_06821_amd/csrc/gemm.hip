@@ -429,6 +429,8 @@ static int nt_tn(int M, int N, bool herm) {
     // square products of at most 128 bands (the block algebra of up to 128 bands): 64 x 64
     // tiles, whose four blocks per wave take the three-product form outside Gram matrices
     if (M == N && N > 64 && N <= 128) return 64;
+    // tall products of 128 bands (the projection of 128 bands onto 512 or more projectors)
+    if (!herm && M >= 512 && N == 128) return 64;
     return N <= 16 ? 16 : (N <= 32 ? 32 : (N <= 64 ? 64 : (N <= 128 ? 128 : (N <= 144 ? 144 : 128))));
 }
 static int nt_tm(int M, int N) {
