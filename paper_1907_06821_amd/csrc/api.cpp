@@ -120,15 +120,23 @@ static void hpsi_c128(pw_ctx *ctx, int nb, const void *psi, int64_t ld, void *ou
     if (ctx->nproj && ctx->beta_otf) {
         nonlocal_otf(ctx, nb, psi, ld, out, ldo, st);
     } else if (ctx->nproj) {
-        // projT[b][p] = D_p <beta_p | psi_b>, then out += projT . beta
+        // projT[b][p] = D_p <beta_p | psi_b>, then out += projT . beta; band counts just past
+        // 128 as the first 128 bands (tiles of the three-product form) and the rest
+        const int nb1 = proj_band_split(nb);
+        double2 *proj = ctx->d_proj.as<double2>();
         {
             ProfScope p(ctx, 3, st);
-            zgemm_nt(ctx->nproj, nb, npw, true, ctx->d_beta64.p, npw, psi, ld, 1.0, ctx->d_dproj.as<double>(), 0.0,
-                     ctx->d_proj.p, ctx->nproj, true, ctx->d_partial.p, st, true);
+            for (int b0 = 0; b0 < nb; b0 += nb1)
+                zgemm_nt(ctx->nproj, std::min(nb1, nb - b0), npw, true, ctx->d_beta64.p, npw,
+                         (const double2 *)psi + (size_t)b0 * ld, ld, 1.0, ctx->d_dproj.as<double>(), 0.0,
+                         proj + (size_t)b0 * ctx->nproj, ctx->nproj, true, ctx->d_partial.p, st, true);
         }
         ProfScope p(ctx, 4, st);
-        zgemm_nn_launch(nb, npw, ctx->nproj, ctx->d_proj.p, ctx->nproj, ctx->d_beta64.p, npw, 1.0, 1.0, out, ldo, st,
-                        true, ctx->nn_tune.get(nb));
+        for (int b0 = 0; b0 < nb; b0 += nb1) {
+            const int n = std::min(nb1, nb - b0);
+            zgemm_nn_launch(n, npw, ctx->nproj, proj + (size_t)b0 * ctx->nproj, ctx->nproj, ctx->d_beta64.p, npw, 1.0,
+                            1.0, (double2 *)out + (size_t)b0 * ldo, ldo, st, true, ctx->nn_tune.get(n));
+        }
     }
 }
 

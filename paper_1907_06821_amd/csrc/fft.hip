@@ -814,9 +814,10 @@ struct HpsiGroup {
 struct HpsiBatch {
     int nb = 0, nprob = 0;
     std::deque<HpsiGroup> groups;
-    std::vector<NtJob> nt;
-    std::vector<NnJob> nn;
-    DevBuf d_nt, d_nn;
+    // projector GEMM jobs, one per problem, per launch of proj_band_split's band ranges
+    std::vector<std::vector<NtJob>> nt;
+    std::vector<std::vector<NnJob>> nn;
+    std::deque<DevBuf> d_nt, d_nn;
     const int *mask = nullptr;
     int nn_cfg = -1;
 };
@@ -932,6 +933,9 @@ HpsiBatch *hpsi_batch_create(int n, pw_ctx *const *ctx, int nb, void *const *in,
     B->nprob = n;
     B->mask = mask;
     std::map<std::tuple<int, int, int>, int> gid;
+    const int nb1 = proj_band_split(nb), nlaunch = (nb + nb1 - 1) / nb1;
+    B->nt.resize(nlaunch);
+    B->nn.resize(nlaunch);
     for (int p = 0; p < n; ++p) {
         pw_ctx *c = ctx[p];
         const auto key = std::make_tuple(c->cell.n[0], c->cell.n[1], c->cell.n[2]);
@@ -956,32 +960,41 @@ HpsiBatch *hpsi_batch_create(int n, pw_ctx *const *ctx, int nb, void *const *in,
         j.ldo = ldo[p];
         g.quad_lds = std::max(g.quad_lds, quad_lds<double>(j.xy));
         g.h.push_back(j);
-        if (c->nproj) {
-            B->nt.push_back(nt_job(c->nproj, nb, c->basis.npw, true, c->d_beta64.p, c->basis.npw, in[p], ld[p], 1.0,
-                                   c->d_dproj.as<double>(), 0.0, c->d_proj.p, c->nproj, c->d_partial.p, false));
-            NnJob q{};
-            q.M = nb; q.J = c->basis.npw; q.K = c->nproj; q.nz = 1; q.lower = 0;
-            q.W = c->d_proj.as<double2>(); q.ldw = c->nproj;
-            q.X[0] = c->d_beta64.as<double2>(); q.Out[0] = (double2 *)out[p];
-            q.ldx = c->basis.npw; q.ldo = ldo[p]; q.alpha = 1.0; q.beta = 1.0;
-            B->nn.push_back(q);
-        } else {
-            // keep the job index equal to the problem index: an empty job the kernels skip
-            NtJob e{};
-            e.M = 0; e.N = 0; e.nsplit = 0;
-            B->nt.push_back(e);
-            NnJob q{};
-            B->nn.push_back(q);
+        for (int l = 0; l < nlaunch; ++l) {
+            const int b0 = l * nb1, nbl = std::min(nb1, nb - b0);
+            if (c->nproj) {
+                double2 *proj = c->d_proj.as<double2>() + (size_t)b0 * c->nproj;
+                B->nt[l].push_back(nt_job(c->nproj, nbl, c->basis.npw, true, c->d_beta64.p, c->basis.npw,
+                                          (const double2 *)in[p] + (size_t)b0 * ld[p], ld[p], 1.0,
+                                          c->d_dproj.as<double>(), 0.0, proj, c->nproj, c->d_partial.p, false));
+                NnJob q{};
+                q.M = nbl; q.J = c->basis.npw; q.K = c->nproj; q.nz = 1; q.lower = 0;
+                q.W = proj; q.ldw = c->nproj;
+                q.X[0] = c->d_beta64.as<double2>(); q.Out[0] = (double2 *)out[p] + (size_t)b0 * ldo[p];
+                q.ldx = c->basis.npw; q.ldo = ldo[p]; q.alpha = 1.0; q.beta = 1.0;
+                B->nn[l].push_back(q);
+            } else {
+                // keep the job index equal to the problem index: an empty job the kernels skip
+                NtJob e{};
+                e.M = 0; e.N = 0; e.nsplit = 0;
+                B->nt[l].push_back(e);
+                NnJob q{};
+                B->nn[l].push_back(q);
+            }
         }
     }
     for (HpsiGroup &g : B->groups) {
         g.d.alloc(g.h.size() * sizeof(FftJob));
         PW_HIP(hipMemcpy(g.d.p, g.h.data(), g.h.size() * sizeof(FftJob), hipMemcpyHostToDevice));
     }
-    B->d_nt.alloc(B->nt.size() * sizeof(NtJob));
-    PW_HIP(hipMemcpy(B->d_nt.p, B->nt.data(), B->nt.size() * sizeof(NtJob), hipMemcpyHostToDevice));
-    B->d_nn.alloc(B->nn.size() * sizeof(NnJob));
-    PW_HIP(hipMemcpy(B->d_nn.p, B->nn.data(), B->nn.size() * sizeof(NnJob), hipMemcpyHostToDevice));
+    for (int l = 0; l < nlaunch; ++l) {
+        B->d_nt.emplace_back();
+        B->d_nt.back().alloc(B->nt[l].size() * sizeof(NtJob));
+        PW_HIP(hipMemcpy(B->d_nt.back().p, B->nt[l].data(), B->nt[l].size() * sizeof(NtJob), hipMemcpyHostToDevice));
+        B->d_nn.emplace_back();
+        B->d_nn.back().alloc(B->nn[l].size() * sizeof(NnJob));
+        PW_HIP(hipMemcpy(B->d_nn.back().p, B->nn[l].data(), B->nn[l].size() * sizeof(NnJob), hipMemcpyHostToDevice));
+    }
     return B.release();
 }
 
@@ -1003,10 +1016,12 @@ void hpsi_batch_run(HpsiBatch *B, hipStream_t s) {
         PW_LAUNCH_CHECK();
     }
     bool any = false;
-    for (size_t q = 0; q < B->nt.size(); ++q) any = any || B->nt[q].M > 0;
+    for (size_t q = 0; q < B->nt[0].size(); ++q) any = any || B->nt[0][q].M > 0;
     if (!any) return;
-    zgemm_nt_jobs(B->nt, B->d_nt.as<NtJob>(), B->mask, true, true, true, s);
-    zgemm_nn_jobs_launch(B->nn, B->d_nn.as<NnJob>(), B->mask, -1, true, s);
+    for (size_t l = 0; l < B->nt.size(); ++l)
+        zgemm_nt_jobs(B->nt[l], B->d_nt[l].as<NtJob>(), B->mask, true, true, true, s);
+    for (size_t l = 0; l < B->nn.size(); ++l)
+        zgemm_nn_jobs_launch(B->nn[l], B->d_nn[l].as<NnJob>(), B->mask, -1, true, s);
 }
 
 // ---------------------------------------------------------------------------

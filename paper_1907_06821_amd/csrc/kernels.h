@@ -31,6 +31,9 @@ constexpr int quad_rs(int m) {
 // gemm.hip (complex128)
 int nt_splits(int M, int N, int K, bool herm = false);
 size_t nt_partial_bytes(int M, int N, int K);
+// bands per projector GEMM launch of the stored-table FP64 H psi: 129-144 bands go as
+// the first 128 (tiles of the three-product form) and the rest, others in one launch
+inline int proj_band_split(int nb) { return nb > 128 && nb <= 144 ? 128 : nb; }
 // herm: A == B (a Gram matrix A^H B): only the tiles on and below the diagonal are computed
 void zgemm_nt(int M, int N, int K, bool conja, const void *A, int64_t lda, const void *B, int64_t ldb,
               double alpha, const double *rowscale, double beta, void *C, int64_t ldc, bool trans, void *partial,
