@@ -911,13 +911,23 @@ static bool default_choices(pw_ctx *c) {
 }
 
 bool hpsi_batch_ok(int n, pw_ctx *const *ctx, int nb, std::string *why) {
+    // the projection of every problem in one launch per band range: one NT tile shape
+    // (it follows the projector count)
+    const int nb1 = proj_band_split(nb);
+    int tile0 = -1, tile1 = -1;
     for (int p = 0; p < n; ++p) {
         pw_ctx *c = ctx[p];
         const char *w = nullptr;
+        const int t0 = c->nproj ? nt_tile_id(c->nproj, nb1, false) : -1;
+        const int t1 = c->nproj && nb > nb1 ? nt_tile_id(c->nproj, nb - nb1, false) : -1;
         if (!c->d_beta64.p && c->nproj) w = "no stored complex128 projector table";
         else if (!default_choices(c)) w = "autotuned FFT launch choices";
         else if (c->cols_bands < nb || c->max_bands < nb) w = "bands beyond one FFT chunk";
         else if (c->nn_tune.get(nb) >= 0 || c->rot_tune.get(nb) >= 0) w = "autotuned GEMM tiles";
+        else if ((t0 >= 0 && tile0 >= 0 && t0 != tile0) || (t1 >= 0 && tile1 >= 0 && t1 != tile1))
+            w = "projector counts that take different GEMM tiles";
+        if (t0 >= 0) tile0 = t0;
+        if (t1 >= 0) tile1 = t1;
         if (w) {
             if (why) *why = w;
             return false;

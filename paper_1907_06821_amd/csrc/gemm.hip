@@ -439,6 +439,9 @@ static int nt_tm(int M, int N) {
     return (M >= 256 && N > 64) ? 128 : 64;
 }
 
+// tile shape of an NT product (batched NT jobs of one launch must share it)
+int nt_tile_id(int M, int N, bool herm) { return nt_tm(M, N) * 1024 + nt_tn(M, N, herm); }
+
 // tiles of a Gram matrix's tile grid that reach the diagonal
 static int nt_live_tiles(int M, int N) {
     const int tn = nt_tn(M, N, true), tm = nt_tm(M, N);

@@ -31,6 +31,7 @@ constexpr int quad_rs(int m) {
 // gemm.hip (complex128)
 int nt_splits(int M, int N, int K, bool herm = false);
 size_t nt_partial_bytes(int M, int N, int K);
+int nt_tile_id(int M, int N, bool herm);
 // bands per projector GEMM launch of the stored-table FP64 H psi: 129-144 bands go as
 // the first 128 (tiles of the three-product form) and the rest, others in one launch
 inline int proj_band_split(int nb) { return nb > 128 && nb <= 144 ? 128 : nb; }

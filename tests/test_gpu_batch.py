@@ -47,6 +47,37 @@ def test_batch_equals_individual_solves(torch_cuda, precision, launch):
     _compare(ind, eigs, ress, sts, status, psis)     # several replays of the recorded rounds
 
 
+@pytest.mark.parametrize("cells", ["one", "uneven"])
+def test_fused_batch_equals_individual_solves_at_136_bands(torch_cuda, cells):
+    """128 wanted + 8 buffer bands: the FP64 projector GEMMs of 129-144 bands run as the
+    first 128 bands and the rest, in the fused batch's job lists as in a single solve, so
+    the fused batch stays bit for bit each problem's own solve ("one": three starts on one
+    cell).  Cells whose projector counts take different GEMM tiles ("uneven") cannot share
+    one projection launch: the batch falls back to its recorded rounds, still bit for bit."""
+    import torch
+    import paper_1907_06821_amd as pw
+    probs = synth.batched_problems(3, seed=2)
+    if cells == "one":
+        probs = [probs[0]] * 3
+    nb, nconv = 136, 128
+    ctxs = [pw.Context.from_problem(p, max_bands=nb) for p in probs]
+    assert all(c.npw >= nb and c.nproj > 0 for c in ctxs)
+    starts = [torch.from_numpy(synth.start_vectors(4, nb, c.npw, seed=i)).to("cuda") for i, c in enumerate(ctxs)]
+    kw = dict(tol=1e-9, maxit=40, check_every=20, precision=0, precond=1, nconv=nconv)
+    ind = []
+    for c, p, s in zip(ctxs, probs, starts):
+        psi = s.clone()
+        e, r, st = pw.folded_cg_solve(c, p.e_ref, psi, raise_on_noconv=False, hist_len=16, **kw)
+        ind.append((e, r, st, psi))
+    psis = [s.clone() for s in starts]
+    eigs, ress, sts, status = pw.batch_solve(ctxs, [p.e_ref for p in probs], psis, hist_len=16,
+                                             raise_on_noconv=False, batch_launch=2, **kw)
+    if cells == "one":
+        assert all(s_["fused"] for s_ in sts)
+    print("projector counts", [c.nproj for c in ctxs], "fused", [s_["fused"] for s_ in sts])
+    _compare(ind, eigs, ress, sts, status, psis, min_hist=2)
+
+
 @pytest.mark.parametrize("fault", [0, 2])
 def test_fused_batch_with_finishing_problems(torch_cuda, fault):
     """Problems of the fused batch that converge at different checks drop out
