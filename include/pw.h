@@ -267,7 +267,10 @@ typedef struct {
                              the round of check_every iterations and its check recorded once as a graph
                              and replayed; it applies when every problem has FP64 H psi (precision 0),
                              preconditioner 0 or 1, at most 136 bands, a stored FP64 projector table,
-                             default launch choices and no snapshots, else mode 1 runs.  1 launches each
+                             projector counts whose projection takes one GEMM tile shape (the row
+                             tile follows the count: 64 rows below 256 projectors, 128 from there
+                             at more than 64 bands), default launch choices and no snapshots, else
+                             mode 1 runs.  1 launches each
                              problem's recorded segment graph in turn every check round; 0 launches one
                              graph holding all running problems' segments as child graphs (rebuilt when
                              a problem finishes or changes precision).  Every mode runs each problem's

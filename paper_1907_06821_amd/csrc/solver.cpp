@@ -595,7 +595,8 @@ SegGraph record_segment(FcgRun &r, int len, hipStream_t cap) {
 // says which problems still run: kernels of finished problems return at once,
 // so the recorded round (segment of iterations and the device part of a check)
 // is replayed unchanged while problems drop out.  FP64 H psi, preconditioners 0
-// and 1, at most 136 bands, default launch choices.
+// and 1, at most 136 bands, default launch choices, projector counts whose
+// projection takes one GEMM tile shape.
 // ---------------------------------------------------------------------------
 namespace {
 struct FusedJobs {
