@@ -224,9 +224,10 @@ pw_status pw_ctx_fft_choose(pw_ctx *ctx, pw_dtype dtype, const pw_fft_cand *cand
  *   pivot that is not positive.  Synchronises.
  * Both are the Rayleigh-Ritz and Gram/Cholesky steps of the solver. */
 /* pw_dense_eigh: n <= 1024.  n <= 136 in one workgroup (A as a packed triangle in
- * LDS); larger n as launches over the whole GPU (three per Householder step, then
- * per level of merges one workgroup per merge for the secular roots and a tiled
- * product over all of the level's merges). */
+ * LDS); larger n as launches over the whole GPU (two per Householder step, then
+ * per level of merges one workgroup per merge for the order and deflation, and
+ * the secular roots, eigenvector weights and a tiled product each over all of the
+ * level's merges). */
 pw_status pw_dense_eigh(int32_t n, const void *A, int64_t lda, double *w, void *R, int32_t key, double ref,
                         int32_t *sweeps, void *stream);
 pw_status pw_dense_chol_inv(int32_t n, const void *S, int64_t lds, void *T, void *stream);

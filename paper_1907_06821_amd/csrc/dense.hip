@@ -985,21 +985,28 @@ __global__ __launch_bounds__(NT) void tridiag_ql_lds_jobs(const DenseJob *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Householder reduction for kLdsMaxN < N <= kEigMaxN over the whole GPU: one
-// launch per stage of every step (the reflector of row k; w = tau A22 v with one
-// wave per row; the rank-two update A22 -= v w'^H + w' v^H, w' = w - (tau/2)
-// (w^H v) v, again one wave per row), so the trailing matrix's product and
-// update stream through every CU instead of one workgroup.  The same reflectors
-// as the one-workgroup kernel above, stored in the same places (hv); Ag is the
-// N x N work copy of A (full Hermitian, rows coalesced), whose storage Z takes
-// once the reduction is done; v, w and the step's scalars live in the part of the
-// work region that V takes later, d and e in the divide and conquer's DcGlobal.
+// Householder reduction for kLdsMaxN < N <= kEigMaxN over the whole GPU, two
+// launches per step.  Step k's rank-two update A22 -= v w'^H + w' v^H (w' = w -
+// (tau/2)(w^H v) v, w = tau A22 v) is applied to row k + 1 by one workgroup, which
+// then forms reflector k + 1 from that row (hh_rowstep); a second launch applies it
+// to the rows below, one wave per row, and forms w of step k + 1 from each updated
+// row in the same pass (hh_fused), so the trailing matrix streams through every CU
+// once per step.  The same reflectors as the one-workgroup kernel above, stored in
+// the same places (hv); Ag is the N x N work copy of A (full Hermitian, rows
+// coalesced), whose storage Z takes once the reduction is done; v, w and the
+// step's scalars (two of each, by step parity) live in the part of the work
+// region that V takes later, d and e in the divide and conquer's DcGlobal.
 // ---------------------------------------------------------------------------
 constexpr int kHhWaves = 8;          // rows (waves) per workgroup of the row kernels
 
 struct HhScratch {
-    double2 *v, *w, *sc;             // sc[0] tau, sc[1] scale of the reflector
+    double2 *v, *w, *sc;             // step 0's v, w and scalars (sc[0] tau)
     double *d, *e;                   // the tridiagonal
+};
+// per step parity: v, w (N each) and the scalars tau, a2 = -(tau/2) w^H v
+struct HhBufs {
+    double2 *v[2], *w[2], *sc[2];
+    double *d, *e;
 };
 
 __global__ __launch_bounds__(256) void hh_symmetrize(int N, const double2 *__restrict__ Ain, int64_t lda,
@@ -1008,44 +1015,6 @@ __global__ __launch_bounds__(256) void hh_symmetrize(int N, const double2 *__res
     for (int j = threadIdx.x; j < N; j += 256) {
         const double2 a = Ain[(int64_t)i * lda + j], b = Ain[(int64_t)j * lda + i];
         Ag[(int64_t)i * N + j] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
-    }
-}
-
-// reflector of row k (A[k][i] = conj(A[i][k])) and its vector v (v[k + 1] = 1)
-__global__ __launch_bounds__(256) void hh_reflector(int N, int k, const double2 *__restrict__ Ag,
-                                                    double2 *__restrict__ hv, HhScratch s) {
-    __shared__ double part[4];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const double2 *rowk = Ag + (int64_t)k * N;
-    double s2 = 0.0;
-    for (int i = k + 2 + tid; i < N; i += 256) {
-        const double2 a = rowk[i];
-        s2 += a.x * a.x + a.y * a.y;
-    }
-    s2 = wave_sum(s2);
-    if (lane == 0) part[wid] = s2;
-    __syncthreads();
-    __shared__ double2 tsc[2];
-    if (tid == 0) {
-        double2 tau, scl;
-        double beta;
-        householder(zconj(rowk[k + 1]), (part[0] + part[1]) + (part[2] + part[3]), tau, beta, scl);
-        s.d[k] = rowk[k].x;
-        s.e[k] = beta;
-        s.sc[0] = tau;
-        s.sc[1] = scl;
-        hv[N * (N - 1) / 2 + k] = tau;
-        tsc[0] = tau;
-        tsc[1] = scl;
-    }
-    __syncthreads();
-    const double2 tau = tsc[0], scl = tsc[1];
-    if (tau.x == 0.0 && tau.y == 0.0) return;
-    const int off = refl_off(k, N);
-    for (int i = k + 1 + tid; i < N; i += 256) {
-        const double2 x = i == k + 1 ? make_double2(1.0, 0.0) : zmul(zconj(rowk[i]), scl);
-        s.v[i] = x;
-        hv[off + (i - k - 1)] = x;
     }
 }
 
@@ -1064,39 +1033,127 @@ __global__ __launch_bounds__(64 * kHhWaves) void hh_matvec(int N, int k, const d
     if (lane == 0) s.w[i] = zmul(tau, acc);
 }
 
-// A22 -= v w'^H + w' v^H with w' = w + a2 v, a2 = -(tau / 2) (w^H v); every
-// workgroup forms w^H v itself (a few thousand products)
-__global__ __launch_bounds__(64 * kHhWaves) void hh_update(int N, int k, double2 *__restrict__ Ag, HhScratch s) {
-    const double2 tau = s.sc[0];
-    if (tau.x == 0.0 && tau.y == 0.0) return;
-    __shared__ double2 part[kHhWaves];
-    __shared__ double2 a2s;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    double2 t = make_double2(0.0, 0.0);
-    for (int i = k + 1 + tid; i < N; i += 64 * kHhWaves) t = zfma(zconj(s.w[i]), s.v[i], t);
-    t = wave_sum2(t);
-    if (lane == 0) part[wid] = t;
+// row r = k + 1: step k's update (k >= 0, its tau nonzero; a2 of step k formed here
+// and kept in sck[1]), then, if r < N - 1, reflector r from the updated row
+// (A[r][i] = conj(A[i][r]); v[r + 1] = 1) into vr, scr[0], hv, d[r] and e[r]
+constexpr int kHhRowT = 256;
+__global__ __launch_bounds__(kHhRowT) void hh_rowstep(int N, int k, double2 *__restrict__ Ag, double2 *__restrict__ hv,
+                                                      const double2 *__restrict__ vk, const double2 *__restrict__ wk,
+                                                      double2 *__restrict__ sck, double2 *__restrict__ vr,
+                                                      double2 *__restrict__ scr, double *__restrict__ d,
+                                                      double *__restrict__ e) {
+    __shared__ double2 red[kHhRowT / 64];
+    __shared__ double sred[kHhRowT / 64];
+    __shared__ double2 bc[4];                 // a2, tau, scale, A[r][r + 1]
+    __shared__ double dg;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, r = k + 1;
+    const double2 tauk = k >= 0 ? sck[0] : make_double2(0.0, 0.0);
+    const bool upd = !(tauk.x == 0.0 && tauk.y == 0.0);
+    double2 a2 = make_double2(0.0, 0.0);
+    if (upd) {
+        double2 t = make_double2(0.0, 0.0);
+        for (int i = r + tid; i < N; i += kHhRowT) t = zfma(zconj(wk[i]), vk[i], t);
+        t = wave_sum2(t);
+        if (lane == 0) red[wid] = t;
+        __syncthreads();
+        if (tid == 0) {
+            double2 tt = make_double2(0.0, 0.0);
+            for (int q = 0; q < kHhRowT / 64; ++q) tt = make_double2(tt.x + red[q].x, tt.y + red[q].y);
+            const double2 h = zmul(tauk, tt);
+            bc[0] = make_double2(-0.5 * h.x, -0.5 * h.y);
+            sck[1] = bc[0];
+        }
+        __syncthreads();
+        a2 = bc[0];
+    }
+    double2 *row = Ag + (int64_t)r * N;
+    constexpr int RJ = kEigMaxN / kHhRowT;
+    double2 a[RJ];
+    double s2 = 0.0;
+    const double2 vi = upd ? vk[r] : make_double2(0.0, 0.0);
+    const double2 wi = upd ? zfma(a2, vi, wk[r]) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < RJ; ++q) {
+        const int j = r + tid + q * kHhRowT;
+        a[q] = make_double2(0.0, 0.0);
+        if (j < N) {
+            double2 x = row[j];
+            if (upd) {
+                const double2 vj = vk[j], wj = zfma(a2, vj, wk[j]);
+                const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
+                x.x -= t1.x + t2.x;
+                x.y = j == r ? 0.0 : x.y - (t1.y + t2.y);
+                row[j] = x;
+            }
+            a[q] = x;
+            if (j == r) dg = x.x;
+            if (j == r + 1) bc[3] = x;
+            if (j >= r + 2) s2 += x.x * x.x + x.y * x.y;
+        }
+    }
+    if (r >= N - 1) return;
+    s2 = wave_sum(s2);
+    if (lane == 0) sred[wid] = s2;
     __syncthreads();
     if (tid == 0) {
-        double2 tt = make_double2(0.0, 0.0);
-        for (int q = 0; q < kHhWaves; ++q) tt = make_double2(tt.x + part[q].x, tt.y + part[q].y);
-        const double2 h = zmul(tau, tt);
-        a2s = make_double2(-0.5 * h.x, -0.5 * h.y);
+        double ss = 0.0;
+        for (int q = 0; q < kHhRowT / 64; ++q) ss += sred[q];
+        double2 tau, scl;
+        double beta;
+        householder(zconj(bc[3]), ss, tau, beta, scl);
+        d[r] = dg;
+        e[r] = beta;
+        scr[0] = tau;
+        hv[N * (N - 1) / 2 + r] = tau;
+        bc[1] = tau;
+        bc[2] = scl;
     }
     __syncthreads();
-    const double2 a2 = a2s;
-    const int i = k + 1 + blockIdx.x * kHhWaves + wid;
-    if (i >= N) return;
-    double2 *row = Ag + (int64_t)i * N;
-    const double2 vi = s.v[i], wi = zfma(a2, vi, s.w[i]);
-    for (int j = k + 1 + lane; j < N; j += 64) {
-        const double2 vj = s.v[j], wj = zfma(a2, vj, s.w[j]);
-        const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
-        double2 a = row[j];
-        a.x -= t1.x + t2.x;
-        a.y = i == j ? 0.0 : a.y - (t1.y + t2.y);
-        row[j] = a;
+    const double2 tau = bc[1], scl = bc[2];
+    if (tau.x == 0.0 && tau.y == 0.0) return;
+    const int off = refl_off(r, N);
+#pragma unroll
+    for (int q = 0; q < RJ; ++q) {
+        const int j = r + tid + q * kHhRowT;
+        if (j >= r + 1 && j < N) {
+            const double2 x = j == r + 1 ? make_double2(1.0, 0.0) : zmul(zconj(a[q]), scl);
+            vr[j] = x;
+            hv[off + (j - r - 1)] = x;
+        }
     }
+}
+
+// rows i > k + 1: step k's update (if its tau is nonzero), then w of step k + 1,
+// tau_r sum_{j > k + 1} A'[i][j] vr[j], from the updated row (one wave per row)
+__global__ __launch_bounds__(64 * kHhWaves) void hh_fused(int N, int k, double2 *__restrict__ Ag,
+                                                          const double2 *__restrict__ vk,
+                                                          const double2 *__restrict__ wk,
+                                                          const double2 *__restrict__ sck,
+                                                          const double2 *__restrict__ vr, double2 *__restrict__ wr,
+                                                          const double2 *__restrict__ scr) {
+    const double2 tauk = sck[0], taur = scr[0];
+    const bool upd = !(tauk.x == 0.0 && tauk.y == 0.0);
+    const int lane = threadIdx.x & 63;
+    const int i = k + 2 + blockIdx.x * kHhWaves + (threadIdx.x >> 6);
+    if (i >= N) return;
+    const double2 a2 = upd ? sck[1] : make_double2(0.0, 0.0);
+    double2 *row = Ag + (int64_t)i * N;
+    const double2 vi = upd ? vk[i] : make_double2(0.0, 0.0);
+    const double2 wi = upd ? zfma(a2, vi, wk[i]) : make_double2(0.0, 0.0);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = k + 1 + lane; j < N; j += 64) {
+        double2 x = row[j];
+        if (upd) {
+            const double2 vj = vk[j], wj = zfma(a2, vj, wk[j]);
+            const double2 t1 = zmulc(vi, wj), t2 = zmulc(wi, vj);
+            x.x -= t1.x + t2.x;
+            x.y = i == j ? 0.0 : x.y - (t1.y + t2.y);
+            row[j] = x;
+        }
+        if (j >= k + 2) acc = zfma(x, vr[j], acc);
+    }
+    acc = wave_sum2(acc);
+    if (lane == 0) wr[i] = zmul(taur, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1677,19 +1734,38 @@ void dense_eigh(int N, const void *A, int64_t lda, void *work, double *lam, void
         g.kcount = g.kept + N;
         g.org = g.kcount + N;
         g.ctl = g.org + N;
-        HhScratch s;
-        s.v = (double2 *)((char *)zbuf + (size_t)16 * N * N);
-        s.w = s.v + N;
-        s.sc = s.w + N;
-        s.d = g.d;
-        s.e = g.e;
+        HhBufs hb;
+        hb.v[0] = (double2 *)((char *)zbuf + (size_t)16 * N * N);
+        hb.v[1] = hb.v[0] + N;
+        hb.w[0] = hb.v[1] + N;
+        hb.w[1] = hb.w[0] + N;
+        hb.sc[0] = hb.w[1] + N;
+        hb.sc[1] = hb.sc[0] + 2;
+        hb.d = g.d;
+        hb.e = g.e;
         hipLaunchKernelGGL(hh_symmetrize, dim3(N), dim3(256), 0, st, N, (const double2 *)A, lda, Ag);
+        // reflector 0, w of step 0; then per step k: row k + 1 and reflector k + 1, the rows
+        // below with w of step k + 1; last, row N - 1 with the update of step N - 2
+        hipLaunchKernelGGL(hh_rowstep, dim3(1), dim3(kHhRowT), 0, st, N, -1, Ag, hv, (const double2 *)hb.v[1],
+                           (const double2 *)hb.w[1], hb.sc[1], hb.v[0], hb.sc[0], hb.d, hb.e);
+        HhScratch s0;
+        s0.v = hb.v[0];
+        s0.w = hb.w[0];
+        s0.sc = hb.sc[0];
+        s0.d = hb.d;
+        s0.e = hb.e;
+        hipLaunchKernelGGL(hh_matvec, dim3((N - 1 + kHhWaves - 1) / kHhWaves), dim3(64 * kHhWaves), 0, st, N, 0,
+                           (const double2 *)Ag, s0);
         PW_LAUNCH_CHECK();
         for (int k = 0; k + 1 < N; ++k) {
-            const int nblk = (N - 1 - k + kHhWaves - 1) / kHhWaves;
-            hipLaunchKernelGGL(hh_reflector, dim3(1), dim3(256), 0, st, N, k, (const double2 *)Ag, hv, s);
-            hipLaunchKernelGGL(hh_matvec, dim3(nblk), dim3(64 * kHhWaves), 0, st, N, k, (const double2 *)Ag, s);
-            hipLaunchKernelGGL(hh_update, dim3(nblk), dim3(64 * kHhWaves), 0, st, N, k, Ag, s);
+            const int p = k & 1, q = p ^ 1;
+            hipLaunchKernelGGL(hh_rowstep, dim3(1), dim3(kHhRowT), 0, st, N, k, Ag, hv, (const double2 *)hb.v[p],
+                               (const double2 *)hb.w[p], hb.sc[p], hb.v[q], hb.sc[q], hb.d, hb.e);
+            if (k + 2 < N)
+                hipLaunchKernelGGL(hh_fused, dim3((N - k - 2 + kHhWaves - 1) / kHhWaves), dim3(64 * kHhWaves), 0, st,
+                                   N, k, Ag, (const double2 *)hb.v[p], (const double2 *)hb.w[p],
+                                   (const double2 *)hb.sc[p], (const double2 *)hb.v[q], hb.w[q],
+                                   (const double2 *)hb.sc[q]);
         }
         PW_LAUNCH_CHECK();
         double *Zt = (double *)zbuf, *Ztmp = Zt + (size_t)N * N, *V = Zt + 2 * (size_t)N * N;
