@@ -32,6 +32,11 @@ __device__ inline double2 zfma(double2 a, double2 b, double2 c) {   // a b + c
 // ---------------------------------------------------------------------------
 __device__ inline int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
+// v_mfma_f64_16x16x4f64 (wave64): lane l holds A[l % 16][k = l / 16] and
+// B[k = l / 16][l % 16]; item v of D at lane l is D[l / 16 + 4 v][l % 16]
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ inline v4d mfma_f64(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
 // largest matrix whose packed triangle (N (N + 1) / 2 complex128) fits in LDS
 constexpr int kLdsMaxN = 136;
 
@@ -101,13 +106,15 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
     // above already holding X,
     //   X_II = inv(L_II)                         (one thread per column of the block)
     //   X_Ic = -X_II sum_{k = c}^{r0 - 1} L[r0 + ., k] X[k][c]   for every column c < r0
-    // the sums run one output per lane (16 lanes per column, one per row of the block)
-    // and the multiplication by X_II exchanges the column's 16 sums by shuffles.  The
-    // results wait in registers until every read of the block row is done.
+    // both products on the FP64 matrix cores, one wave per 16-column tile of X_I.
+    // (waves 1, 2, ...; wave 0 meanwhile forms X_II): the sums as (L_I. rows, 4-deep k
+    // steps) x (X rows, zero above the diagonal), then -X_II times them, whose B
+    // operand for k step v is item v of the sums' own accumulator.  The results wait
+    // in registers until every read of the block row is done.
     {
-        constexpr int BS = 16, CPT = 2;              // columns per 16-lane group
-        static_assert(CPT * NT / BS >= (kLdsMaxN - 1) / BS * BS, "columns left of the last block row");
-        const int r = tid % BS, grp = tid / BS;
+        constexpr int BS = 16;
+        static_assert((NT / 64 - 1) * BS >= kLdsMaxN, "a wave per 16-column tile left of the last block row");
+        const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
         for (int r0 = 0; r0 < N; r0 += BS) {
             const int nr = min(BS, N - r0);
             if (tid < BS) {                          // column tid of inv(L_II), forward substitution
@@ -131,40 +138,40 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
 #pragma unroll
                 for (int i = 0; i < BS; ++i) dinv[i][c] = col[i];
             }
-            __syncthreads();
-            double2 xo[CPT];
-#pragma unroll
-            for (int h = 0; h < CPT; ++h) {
-                const int c = grp + h * (NT / BS);   // the same for the group's 16 lanes
-                double2 sacc = make_double2(0.0, 0.0);
-                if (c < r0 && r < nr) {
-                    // four partial sums keep several LDS reads in flight
-                    const int base = tri(r0 + r, 0);
-                    double2 s4[4] = {sacc, sacc, sacc, sacc};
-                    int k = c;
-                    for (; k + 3 < r0; k += 4) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) s4[u] = zfma(L[base + k + u], L[tri(k + u, c)], s4[u]);
-                    }
-                    for (; k < r0; ++k) s4[0] = zfma(L[base + k], L[tri(k, c)], s4[0]);
-                    sacc = make_double2((s4[0].x + s4[1].x) + (s4[2].x + s4[3].x),
-                                        (s4[0].y + s4[1].y) + (s4[2].y + s4[3].y));
+            // waves 1, 2, ...: the sums of their column tiles while wave 0 inverts the block
+            const int c0 = (wave - 1) * BS;          // this wave's column tile
+            const bool act = wave > 0 && c0 < r0;    // the same for the whole wave
+            v4d x1 = {0.0, 0.0, 0.0, 0.0}, x2 = x1, s1 = x1, s2 = x1;
+            if (act) {
+                const int ar = r0 + lr, bc = c0 + lr;
+                for (int k4 = c0; k4 < r0; k4 += 4) {
+                    const int k = k4 + lk;
+                    const double2 a = lr < nr ? L[tri(ar, k)] : make_double2(0.0, 0.0);
+                    const double2 b = bc <= k ? L[tri(k, bc)] : make_double2(0.0, 0.0);
+                    s1 = mfma_f64(a.x, b.x, s1);
+                    s1 = mfma_f64(-a.y, b.y, s1);
+                    s2 = mfma_f64(a.x, b.y, s2);
+                    s2 = mfma_f64(a.y, b.x, s2);
                 }
-                double2 x = make_double2(0.0, 0.0);
-                if (c < r0) {
+            }
+            __syncthreads();                         // inv(L_II) in dinv
+            if (act) {
 #pragma unroll
-                    for (int q = 0; q < BS; ++q) {
-                        const double2 sq = make_double2(__shfl(sacc.x, q, BS), __shfl(sacc.y, q, BS));
-                        if (q <= r && r < nr) x = zfma(dinv[r][q], sq, x);
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const double2 a = dinv[lr][4 * v + lk];
+                    x1 = mfma_f64(a.x, s1[v], x1);
+                    x1 = mfma_f64(-a.y, s2[v], x1);
+                    x2 = mfma_f64(a.x, s2[v], x2);
+                    x2 = mfma_f64(a.y, s1[v], x2);
                 }
-                xo[h] = make_double2(-x.x, -x.y);
             }
             __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int h = 0; h < CPT; ++h) {
-                const int c = grp + h * (NT / BS);
-                if (c < r0 && r < nr) L[tri(r0 + r, c)] = xo[h];
+                for (int v = 0; v < 4; ++v) {
+                    const int r = lk + 4 * v;
+                    if (r < nr) L[tri(r0 + r, c0 + lr)] = make_double2(-x1[v], -x2[v]);
+                }
             }
             for (int e = tid; e < nr * nr; e += NT) {
                 const int i = e / nr, c = e % nr;
