@@ -64,6 +64,7 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
     double2 *L = reinterpret_cast<double2 *>(smem_raw);
     __shared__ double sd[kLdsMaxN];
     __shared__ double2 dinv[16][17];
+    __shared__ double rdp[16];                           // 1 / d_j of the panel's columns
     const int tid = threadIdx.x;
     for (int q = tid; q < N * (N + 1) / 2; q += NT) {   // every load in flight at once
         int i, k;
@@ -72,23 +73,68 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
     }
     __syncthreads();
     constexpr int G = NT / 128;
-    const int sub = tid % G;
-    for (int j = 0; j < N; ++j) {
-        const double d = L[tri(j, j)].x;                 // the same value in every thread
-        if (!(d > 0.0) || !isfinite(d)) {
-            if (tid == 0 && status[0] == 0) status[0] = pivot_base + j + 1;   // the first failure is kept
-            return;
+    constexpr int PB = 16;                               // panel width
+    const int sub = tid % G, lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+    for (int p0 = 0; p0 < N; p0 += PB) {
+        const int pe = min(p0 + PB, N);
+        // the panel's columns one by one, each step updating only the panel's columns
+        for (int j = p0; j < pe; ++j) {
+            const double d = L[tri(j, j)].x;             // the same value in every thread
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (tid == 0 && status[0] == 0) status[0] = pivot_base + j + 1;   // the first failure is kept
+                return;
+            }
+            const double rd = 1.0 / d;
+            if (tid == 0) rdp[j - p0] = rd;
+            // a row per group of G threads, the group's lanes striding over the row's panel columns
+            for (int i = j + 1 + tid / G; i < N; i += NT / G) {
+                const double2 lij = L[tri(i, j)];
+                const double2 s_ = make_double2(lij.x * rd, lij.y * rd);
+                const int base = tri(i, 0), ke = min(i, pe - 1);
+                for (int k = j + 1 + sub; k <= ke; k += G) {
+                    const double2 u = zmulc(s_, L[tri(k, j)]);
+                    const double2 w = L[base + k];
+                    L[base + k] = make_double2(w.x - u.x, w.y - u.y);
+                }
+            }
+            __syncthreads();
         }
-        const double rd = 1.0 / d;
-        // a row per group of G threads, the group's lanes striding over the row's columns
-        for (int i = j + 1 + tid / G; i < N; i += NT / G) {
-            const double2 lij = L[tri(i, j)];
-            const double2 s_ = make_double2(lij.x * rd, lij.y * rd);
-            const int base = tri(i, 0);
-            for (int k = j + 1 + sub; k <= i; k += G) {
-                const double2 u = zmulc(s_, L[tri(k, j)]);
-                const double2 w = L[base + k];
-                L[base + k] = make_double2(w.x - u.x, w.y - u.y);
+        // the rest of the rank-PB update, L[i][k] -= sum_j (L[i][j] / d_j) conj(L[k][j]) for
+        // i >= k >= pe, on the FP64 matrix cores: one wave per 16 x 16 tile of the lower
+        // triangle, four 4-deep steps over the panel's columns
+        const int nt = (N - pe + 15) / 16;
+        for (int t = wave; t < nt * (nt + 1) / 2; t += NT / 64) {
+            int ti = 0;
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            const int tk = t - ti * (ti + 1) / 2;
+            const int ia = pe + 16 * ti + lr, kb = pe + 16 * tk + lr;
+            v4d c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1;
+#pragma unroll
+            for (int k4 = 0; k4 < PB; k4 += 4) {
+                const int j = p0 + k4 + lk;
+                double2 a = make_double2(0.0, 0.0), b = a;
+                if (j < pe) {
+                    if (ia < N) {
+                        const double2 x = L[tri(ia, j)];
+                        a = make_double2(x.x * rdp[j - p0], x.y * rdp[j - p0]);
+                    }
+                    if (kb < N) {
+                        const double2 y = L[tri(kb, j)];
+                        b = make_double2(y.x, -y.y);
+                    }
+                }
+                c1 = mfma_f64(a.x, b.x, c1);
+                c1 = mfma_f64(-a.y, b.y, c1);
+                c2 = mfma_f64(a.x, b.y, c2);
+                c2 = mfma_f64(a.y, b.x, c2);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = pe + 16 * ti + lk + 4 * v, k = pe + 16 * tk + lr;
+                if (i < N && k <= i) {
+                    const double2 w = L[tri(i, k)];
+                    L[tri(i, k)] = make_double2(w.x - c1[v], w.y - c2[v]);
+                }
             }
         }
         __syncthreads();
@@ -114,7 +160,6 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
     {
         constexpr int BS = 16;
         static_assert((NT / 64 - 1) * BS >= kLdsMaxN, "a wave per 16-column tile left of the last block row");
-        const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
         for (int r0 = 0; r0 < N; r0 += BS) {
             const int nr = min(BS, N - r0);
             if (tid < BS) {                          // column tid of inv(L_II), forward substitution
