@@ -63,7 +63,6 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
     extern __shared__ unsigned char smem_raw[];
     double2 *L = reinterpret_cast<double2 *>(smem_raw);
     __shared__ double sd[kLdsMaxN];
-    __shared__ double2 dinv[16][17];
     __shared__ double rdp[16];                           // 1 / d_j of the panel's columns
     const int tid = threadIdx.x;
     for (int q = tid; q < N * (N + 1) / 2; q += NT) {   // every load in flight at once
@@ -148,24 +147,25 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
         L[q] = make_double2(L[q].x * f, L[q].y * f);
     }
     __syncthreads();
-    // in-place inverse X = L^{-1} by block rows of BS: for block row I, with rows
-    // above already holding X,
-    //   X_II = inv(L_II)                         (one thread per column of the block)
+    // in-place inverse X = L^{-1} by block rows of BS.  First every diagonal block
+    // X_II = inv(L_II) at once, in place (16 threads per block, one per column,
+    // forward substitution): no later step reads L_II.  Then for block row I, with the
+    // rows above already holding X,
     //   X_Ic = -X_II sum_{k = c}^{r0 - 1} L[r0 + ., k] X[k][c]   for every column c < r0
-    // both products on the FP64 matrix cores, one wave per 16-column tile of X_I.
-    // (waves 1, 2, ...; wave 0 meanwhile forms X_II): the sums as (L_I. rows, 4-deep k
-    // steps) x (X rows, zero above the diagonal), then -X_II times them, whose B
-    // operand for k step v is item v of the sums' own accumulator.  The results wait
-    // in registers until every read of the block row is done.
+    // both products on the FP64 matrix cores, one wave per 16-column tile of X_I.: the
+    // sums as (L_I. rows, 4-deep k steps) x (X rows, zero above the diagonal), then
+    // -X_II times them, whose B operand for k step v is item v of the sums' own
+    // accumulator.  The results wait in registers until every read of the block row
+    // is done.
     {
         constexpr int BS = 16;
-        static_assert((NT / 64 - 1) * BS >= kLdsMaxN, "a wave per 16-column tile left of the last block row");
-        for (int r0 = 0; r0 < N; r0 += BS) {
-            const int nr = min(BS, N - r0);
-            if (tid < BS) {                          // column tid of inv(L_II), forward substitution
-                const int c = tid;                   // unrolled: the block's loads issue ahead of the sums
-                double2 col[BS];
-#pragma unroll
+        static_assert(NT / 64 * BS >= kLdsMaxN, "a wave per 16-column tile left of the last block row");
+        static_assert(NT / BS * BS >= kLdsMaxN, "16 threads per diagonal block");
+        {
+            const int r0 = (tid / BS) * BS, c = tid % BS, nr = min(BS, N - r0);
+            double2 col[BS];
+            if (r0 < N) {                            // column c of inv(L_II), unrolled so that the
+#pragma unroll                                       // block's loads issue ahead of the sums
                 for (int i = 0; i < BS; ++i) {
                     double2 acc = make_double2(i == c ? 1.0 : 0.0, 0.0);
                     if (i < nr) {
@@ -180,14 +180,22 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
                     }
                     col[i] = i < c ? make_double2(0.0, 0.0) : acc;
                 }
-#pragma unroll
-                for (int i = 0; i < BS; ++i) dinv[i][c] = col[i];
             }
-            // waves 1, 2, ...: the sums of their column tiles while wave 0 inverts the block
-            const int c0 = (wave - 1) * BS;          // this wave's column tile
-            const bool act = wave > 0 && c0 < r0;    // the same for the whole wave
-            v4d x1 = {0.0, 0.0, 0.0, 0.0}, x2 = x1, s1 = x1, s2 = x1;
+            __syncthreads();
+            if (r0 < N && c < nr) {
+#pragma unroll
+                for (int i = 0; i < BS; ++i)
+                    if (i >= c && i < nr) L[tri(r0 + i, r0 + c)] = col[i];
+            }
+            __syncthreads();
+        }
+        for (int r0 = BS; r0 < N; r0 += BS) {
+            const int nr = min(BS, N - r0);
+            const int c0 = wave * BS;                // this wave's column tile
+            const bool act = c0 < r0;                // the same for the whole wave
+            v4d x1 = {0.0, 0.0, 0.0, 0.0}, x2 = x1;
             if (act) {
+                v4d s1 = x1, s2 = x1;
                 const int ar = r0 + lr, bc = c0 + lr;
                 for (int k4 = c0; k4 < r0; k4 += 4) {
                     const int k = k4 + lk;
@@ -198,12 +206,10 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
                     s2 = mfma_f64(a.x, b.y, s2);
                     s2 = mfma_f64(a.y, b.x, s2);
                 }
-            }
-            __syncthreads();                         // inv(L_II) in dinv
-            if (act) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const double2 a = dinv[lr][4 * v + lk];
+                    const int q = 4 * v + lk;        // X_II[lr][q], zero above the diagonal
+                    const double2 a = q <= lr && lr < nr ? L[tri(r0 + lr, r0 + q)] : make_double2(0.0, 0.0);
                     x1 = mfma_f64(a.x, s1[v], x1);
                     x1 = mfma_f64(-a.y, s2[v], x1);
                     x2 = mfma_f64(a.x, s2[v], x2);
@@ -217,10 +223,6 @@ __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restri
                     const int r = lk + 4 * v;
                     if (r < nr) L[tri(r0 + r, c0 + lr)] = make_double2(-x1[v], -x2[v]);
                 }
-            }
-            for (int e = tid; e < nr * nr; e += NT) {
-                const int i = e / nr, c = e % nr;
-                if (c <= i) L[tri(r0 + i, r0 + c)] = dinv[i][c];
             }
             __syncthreads();
         }
