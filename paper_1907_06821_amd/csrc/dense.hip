@@ -50,12 +50,14 @@ __device__ inline void tri_rc(int q, int &i, int &k) {
 }
 
 // N <= kLdsMaxN.  The packed lower triangle lives in LDS.  Factorisation: right-
-// looking without square roots during the sweep: step j subtracts
-// L_ij conj(L_kj) / L_jj from the trailing triangle (rows i > j, columns j < k <= i)
-// and leaves column j unscaled, so one barrier per column suffices (column j is
-// read, never written, in step j).  Then every column k is divided by sqrt(L_kk),
-// which turns the diagonal into sqrt(L_kk) as well.  Inverse in place by block
-// rows of 16 (nine barrier rounds at N = 136 instead of two per column).
+// looking without square roots during the sweep, by panels of 16 columns: step j
+// subtracts L_ij conj(L_kj) / L_jj (rows i > j) from the panel's later columns only
+// and leaves column j unscaled, one barrier per column (column j is read, never
+// written, in step j); after the panel, the rest of its rank-16 update (columns k
+// past the panel) runs on the FP64 matrix cores.  Then every column k is divided by
+// sqrt(L_kk), which turns the diagonal into sqrt(L_kk) as well.  Inverse in place:
+// the diagonal blocks of 16 first, all at once, then the block rows below on the
+// matrix cores (see the inverse below).
 template <int NT>
 __device__ __forceinline__ void chol_inv_lds_body(int N, const double2 *__restrict__ S, int64_t lds,
                                                   double2 *__restrict__ T, int64_t ldt, int pivot_base,
